@@ -1,0 +1,275 @@
+"""Plain FP64 CPU oracle for one RI qsGW iteration.
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import or call this module.  The product
+path (the HIP library and its binding) never routes through it, and this
+module shares no code with that path.
+
+Everything here is real (the paper considers real orbitals, section
+"Theoretical background"), FP64, Hartree atomic units, closed shell.  The
+code follows the paper's equations in the paper's order and notation:
+
+  * LCAO and the AO->MO transform, Eqs. (3) and (16), with the RI
+    factorisation (mu nu|lambda tau) ~ sum_P B^P_{mu nu} B^P_{lambda tau}
+    (section "Self-consistent field", the paragraph on the RI approximation).
+  * Casida equation, Eqs. (12)-(14), closed-shell singlet block, solved in its
+    Hermitian form M = (A-B)^{1/2} (A+B) (A-B)^{1/2}.
+  * Residues w^s_{mn}, Eq. (18).
+  * GW self-energy Sigma_{mn}(omega), Eq. (17); qsGW potential, Eq. (19).
+  * Hamiltonian Eq. (6) with Hartree Eq. (7), density Eq. (9), exchange
+    Eq. (10); eigenproblem Eq. (4) with S = I.
+
+Readings of passages that are silent or ambiguous (each one is listed with
+its reason in the design notes of the repository):
+
+  * Eqs. (13)-(14) are read with "+" signs (standard direct RPA):
+    A = Delta + (ia|jb), B = (ia|bj) per spin pair.  With the printed "-"
+    A+B is indefinite for a positive semidefinite Coulomb kernel.
+  * Closed shell: the spin sums of Eqs. (12)-(18) give the singlet block
+    A = Delta + 2K, B = 2K and w = sqrt(2) sum_ia (mn|ia)(X+Y)_ia; triplet
+    excitations have zero residue.
+  * Normalisation X^T X - Y^T Y = 1, so X+Y = (A-B)^{1/2} Z Omega^{-1/2}.
+  * Eq. (19) takes the real part: V_mn = 1/2 Re[Sigma_mn(eps_m) + Sigma_mn(eps_n)]
+    with eta kept finite.
+  * The one-body part of Eq. (6), T + V_ext, is a synthetic matrix h built so
+    that the starting (eps0, C0) is an exact Hartree-Fock fixed point.
+  * No mixing by default; convergence when max_m |eps_m' - eps_m| < tol.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+
+# ---------------------------------------------------------------- O1 ------
+def mo_transform(B_ao: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Eq. (16) with RI: B^P_{mn} = sum_{mu nu} C_{mu m} B^P_{mu nu} C_{nu n}.
+
+    B_ao is [P][mu][nu]; C is [mu][m] (column m = MO m, Eq. (3)).
+    Returns B_mo as [P][m][n].
+    """
+    return np.matmul(np.matmul(C.T[None, :, :], B_ao), C[None, :, :])
+
+
+def eri_mo(B_mo: np.ndarray) -> np.ndarray:
+    """(mn|pq) = sum_P B^P_{mn} B^P_{pq}, the RI form of Eq. (15).  Small cases only."""
+    n = B_mo.shape[1]
+    flat = B_mo.reshape(B_mo.shape[0], n * n)
+    return (flat.T @ flat).reshape(n, n, n, n)
+
+
+# ---------------------------------------------------------------- O2 ------
+def transition_energies(eps: np.ndarray, nocc: int) -> np.ndarray:
+    """Delta_t = eps_a - eps_i for t = i * n_v + (a - n_occ)."""
+    return (eps[None, nocc:] - eps[:nocc, None]).reshape(-1)
+
+
+def casida_AB(B_mo: np.ndarray, eps: np.ndarray, nocc: int):
+    """Eqs. (13)-(14), closed-shell singlet block, "+" sign reading.
+
+    K_{ia,jb} = (ia|jb) = sum_P B^P_{ia} B^P_{jb}; (ia|bj) = (ia|jb) for
+    real orbitals.  A = diag(Delta) + 2K, B = 2K (the factor 2 is the sum
+    over the spin sigma' of the partner pair).
+    """
+    naux = B_mo.shape[0]
+    Bia = B_mo[:, :nocc, nocc:].reshape(naux, -1)
+    K = Bia.T @ Bia
+    delta = transition_energies(eps, nocc)
+    A = np.diag(delta) + 2.0 * K
+    B = 2.0 * K
+    return A, B
+
+
+def rpa_hermitian(B_mo: np.ndarray, eps: np.ndarray, nocc: int):
+    """M = (A-B)^{1/2} (A+B) (A-B)^{1/2} with A-B = diag(Delta) for real orbitals.
+
+    Returns (M, sqrt_delta).
+    """
+    A, B = casida_AB(B_mo, eps, nocc)
+    delta = transition_energies(eps, nocc)
+    sqrt_delta = np.sqrt(delta)
+    M = sqrt_delta[:, None] * (A + B) * sqrt_delta[None, :]
+    return M, sqrt_delta
+
+
+# ---------------------------------------------------------------- O3 ------
+def rpa_solve(M: np.ndarray, sqrt_delta: np.ndarray):
+    """Solve M Z = Z Omega^2; (X+Y)^s = (A-B)^{1/2} Z^s / sqrt(Omega_s).
+
+    Returns (Omega ascending, XpY[t][s]).
+    """
+    lam, Z = scipy.linalg.eigh(M)
+    if lam[0] <= 0.0:
+        raise ValueError("RPA instability: non-positive Omega^2")
+    Omega = np.sqrt(lam)
+    XpY = sqrt_delta[:, None] * Z / np.sqrt(Omega)[None, :]
+    return Omega, XpY
+
+
+# ---------------------------------------------------------------- O4 ------
+def residues(B_mo: np.ndarray, XpY: np.ndarray, nocc: int) -> np.ndarray:
+    """Eq. (18): w^s_{mn} = sum_{ia sigma'} (mn|ia sigma') (X+Y)^s_{ia sigma'}.
+
+    With RI and the singlet spin sum, w^s_{mn} = sqrt(2) sum_P B^P_{mn} rho_{P s},
+    rho_{P s} = sum_{ia} B^P_{ia} (X+Y)^s_{ia}.  Returns w as [m][n][s].
+    """
+    naux, n, _ = B_mo.shape
+    Bia = B_mo[:, :nocc, nocc:].reshape(naux, -1)
+    rho = Bia @ XpY
+    w = np.sqrt(2.0) * (B_mo.reshape(naux, n * n).T @ rho)
+    return w.reshape(n, n, -1)
+
+
+# ---------------------------------------------------------------- O5 ------
+def _pole_denominators(omega: float, eps: np.ndarray, Omega: np.ndarray,
+                       nocc: int, eta: float) -> np.ndarray:
+    """Denominators of Eq. (17) as a [k][s] complex array at one frequency.
+
+    occupied k = i:  omega - eps_i + Omega_s - i eta
+    virtual  k = a:  omega - eps_a - Omega_s + i eta
+    """
+    d = np.empty((eps.size, Omega.size), dtype=np.complex128)
+    d[:nocc] = (omega - eps[:nocc, None] + Omega[None, :]) - 1j * eta
+    d[nocc:] = (omega - eps[nocc:, None] - Omega[None, :]) + 1j * eta
+    return d
+
+
+def sigma_element(w: np.ndarray, eps: np.ndarray, Omega: np.ndarray, nocc: int,
+                  eta: float, m: int, n: int, omegas) -> np.ndarray:
+    """Eq. (17): <m|Sigma_c^GW(omega)|n> for each omega in ``omegas`` (complex)."""
+    num = w[m] * w[n]  # [k][s]
+    out = np.empty(len(omegas), dtype=np.complex128)
+    for j, om in enumerate(omegas):
+        out[j] = np.sum(num / _pole_denominators(om, eps, Omega, nocc, eta))
+    return out
+
+
+def sigma_row(w: np.ndarray, eps: np.ndarray, Omega: np.ndarray, nocc: int,
+              eta: float, m: int, omega: float) -> np.ndarray:
+    """Eq. (17) for row m at one frequency: Sigma_{mn}(omega) for all n (complex)."""
+    inv_d = 1.0 / _pole_denominators(omega, eps, Omega, nocc, eta)
+    return np.tensordot(w, w[m] * inv_d, axes=([1, 2], [0, 1]))
+
+
+# ---------------------------------------------------------------- O6 ------
+def sigma_qs(w: np.ndarray, eps: np.ndarray, Omega: np.ndarray, nocc: int,
+             eta: float) -> np.ndarray:
+    """Eq. (19), real part: V_mn = 1/2 Re[Sigma_mn(eps_m) + Sigma_mn(eps_n)].
+
+    Sigma is complex symmetric in (m, n) for real orbitals, so the second
+    term is the transpose of the first: with G_mn = Re Sigma_mn(eps_m),
+    V = (G + G^T) / 2.
+    """
+    n = eps.size
+    G = np.empty((n, n))
+    for m in range(n):
+        # w is real, so Re sum_ks w_mks w_nks / d_ks = sum_ks w_mks w_nks Re(1/d_ks)
+        g = (1.0 / _pole_denominators(eps[m], eps, Omega, nocc, eta)).real
+        G[m] = np.tensordot(w, w[m] * g, axes=([1, 2], [0, 1]))
+    return 0.5 * (G + G.T)
+
+
+# ---------------------------------------------------------------- O7 ------
+def density(C: np.ndarray, nocc: int) -> np.ndarray:
+    """Eq. (9) per spin, closed shell: D = sum_{i occ} C_{mu i} C_{nu i}."""
+    Cocc = C[:, :nocc]
+    return Cocc @ Cocc.T
+
+
+def hartree(B_ao: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Eq. (7) with RI: J = sum_P B^P (B^P . sum_sigma D^sigma), sum_sigma D^sigma = 2D."""
+    c = np.einsum("plt,lt->p", B_ao, 2.0 * D)
+    return np.einsum("p,pmn->mn", c, B_ao)
+
+
+def exchange(B_ao: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Eq. (10) with RI: K_{mu nu} = sum_{lt} D_{lt} (mu lambda|tau nu) = sum_P (B^P D B^P)_{mu nu}."""
+    return np.einsum("pml,lt,ptn->mn", B_ao, D, B_ao, optimize=True)
+
+
+def hf_core(B_ao: np.ndarray, C0: np.ndarray, eps0: np.ndarray, nocc: int) -> np.ndarray:
+    """One-body matrix h that makes (eps0, C0) a Hartree-Fock fixed point:
+    h = C0 diag(eps0) C0^T - (J - K)[D0]."""
+    D0 = density(C0, nocc)
+    return (C0 * eps0[None, :]) @ C0.T - hartree(B_ao, D0) + exchange(B_ao, D0)
+
+
+def fock(h: np.ndarray, B_ao: np.ndarray, C: np.ndarray, nocc: int,
+         V: np.ndarray) -> np.ndarray:
+    """Eq. (6): H = h + J - K + Sigma_c, with Sigma_c in the AO basis = C V C^T."""
+    D = density(C, nocc)
+    return h + hartree(B_ao, D) - exchange(B_ao, D) + C @ V @ C.T
+
+
+def diagonalize(F: np.ndarray):
+    """Eq. (4) with S = I.  Returns (eps ascending, C) with each column's
+    largest-magnitude entry made positive (a fixed sign convention)."""
+    e, C = scipy.linalg.eigh(F)
+    idx = np.argmax(np.abs(C), axis=0)
+    sgn = np.sign(C[idx, np.arange(C.shape[1])])
+    sgn[sgn == 0] = 1.0
+    return e, C * sgn[None, :]
+
+
+# ---------------------------------------------------------------- O1-O8 ---
+def qsgw_step(B_ao, h, C, eps, nocc, eta):
+    """One qsGW iteration from (eps, C).  Returns a dict of every intermediate."""
+    B_mo = mo_transform(B_ao, C)
+    M, sqrt_delta = rpa_hermitian(B_mo, eps, nocc)
+    Omega, XpY = rpa_solve(M, sqrt_delta)
+    w = residues(B_mo, XpY, nocc)
+    V = sigma_qs(w, eps, Omega, nocc, eta)
+    F = fock(h, B_ao, C, nocc, V)
+    eps_new, C_new = diagonalize(F)
+    return dict(B_mo=B_mo, M=M, sqrt_delta=sqrt_delta, Omega=Omega, XpY=XpY,
+                w=w, V=V, F=F, eps=eps_new, C=C_new)
+
+
+def qsgw_iterate(B_ao, h, C0, eps0, nocc, eta, tol, max_iter, mix=1.0,
+                 keep=("eps", "Omega")):
+    """Repeat the qsGW step until max|eps' - eps| < tol or max_iter.
+
+    With mix < 1 the AO-basis correlation potential is mixed linearly with the
+    previous one: Sigma_ao <- mix * Sigma_ao + (1 - mix) * Sigma_ao_prev.
+    Returns (eps, C, history) where history[j] holds the ``keep`` entries and
+    max|d eps| of iteration j + 1.
+    """
+    C, eps = C0.copy(), eps0.copy()
+    hist = []
+    Vao_prev = None
+    for _ in range(max_iter):
+        B_mo = mo_transform(B_ao, C)
+        M, sqrt_delta = rpa_hermitian(B_mo, eps, nocc)
+        Omega, XpY = rpa_solve(M, sqrt_delta)
+        w = residues(B_mo, XpY, nocc)
+        V = sigma_qs(w, eps, Omega, nocc, eta)
+        Vao = C @ V @ C.T
+        if Vao_prev is not None and mix != 1.0:
+            Vao = mix * Vao + (1.0 - mix) * Vao_prev
+        Vao_prev = Vao
+        D = density(C, nocc)
+        F = h + hartree(B_ao, D) - exchange(B_ao, D) + Vao
+        eps_new, C_new = diagonalize(F)
+        d = float(np.max(np.abs(eps_new - eps)))
+        rec = {"max_deps": d}
+        loc = dict(B_mo=B_mo, M=M, Omega=Omega, XpY=XpY, w=w, V=V, Vao=Vao,
+                   F=F, eps=eps_new, C=C_new)
+        for k in keep:
+            rec[k] = loc[k]
+        hist.append(rec)
+        C, eps = C_new, eps_new
+        if d < tol:
+            break
+    return eps, C, hist
+
+
+# ------------------------------------------------- per-state features -----
+def exchange_diagonal_mo(B_mo: np.ndarray, nocc: int) -> np.ndarray:
+    """Sigma_x,mm = -sum_{i occ} (mi|im) = -sum_i sum_P (B^P_{mi})^2."""
+    return -np.einsum("pmi,pmi->m", B_mo[:, :, :nocc], B_mo[:, :, :nocc])
+
+
+def sigma_diag_derivative(w, eps, Omega, nocc, eta, m, omega) -> complex:
+    """d Sigma_mm / d omega of Eq. (17): -sum_{k s} w_mks^2 / d_ks^2."""
+    d = _pole_denominators(omega, eps, Omega, nocc, eta)
+    return complex(-np.sum(w[m] ** 2 / d ** 2))

@@ -1,0 +1,310 @@
+"""Pins of the FP64 oracle to the paper's equations (CPU only).
+
+Each test compares the oracle with a route that does not go through the
+oracle's code: closed forms, brute-force diagonalisation, the spin-orbital
+form of the equations, the Dyson equation, frequency integration, the MP2
+self-energy, four-index integrals, invariances.  The mutation tests at the end
+plant mistakes in a copy of an oracle step and check that a pin catches them.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import pins
+from qsgw_inputs import cfg1_omega_grid, make_config, make_problem
+
+
+def tiny(nbf=6, naux=14, nocc=2, seed=3, coupling=1.0):
+    return make_problem(nbf, naux, nocc, naux, 0.9, seed, coupling=coupling)
+
+
+def chain(p, eps=None, C=None):
+    eps = p.eps0 if eps is None else eps
+    C = p.C0 if C is None else C
+    B_mo = O.mo_transform(p.B_ao, C)
+    M, sq = O.rpa_hermitian(B_mo, eps, p.nocc)
+    Om, XpY = O.rpa_solve(M, sq)
+    w = O.residues(B_mo, XpY, p.nocc)
+    return B_mo, M, sq, Om, XpY, w
+
+
+# --------------------------------------------------------------- P1 ------
+@pytest.mark.parametrize("b,B00,B11", [(0.3, 0.7, -0.2), (1.1, 0.0, 0.4), (0.05, -0.3, 0.9)])
+def test_p1_one_transition_closed_form(b, B00, B11):
+    eps = np.array([-0.8, 0.45])
+    eta = 1e-3
+    B_ao = np.array([[[B00, b], [b, B11]]])
+    C = np.eye(2)
+    B_mo = O.mo_transform(B_ao, C)
+    M, sq = O.rpa_hermitian(B_mo, eps, 1)
+    Om, XpY = O.rpa_solve(M, sq)
+    w = O.residues(B_mo, XpY, 1)
+    grid = np.linspace(-2, 2, 41)
+    Om_ref, w_ref, sig_ref = pins.one_transition_closed_form(eps[0], eps[1], b, B00, B11, eta, grid)
+    assert abs(Om[0] - Om_ref) <= 1e-15 * Om_ref
+    # w is fixed up to the sign of the Casida eigenvector
+    s = np.sign(w[0, 1, 0] / w_ref[0, 1])
+    np.testing.assert_allclose(s * w[:, :, 0], w_ref, rtol=1e-14, atol=1e-16)
+    for m in range(2):
+        sig = O.sigma_element(w, eps, Om, 1, eta, m, m, grid)
+        np.testing.assert_allclose(sig, sig_ref[m], rtol=1e-13, atol=1e-16)
+    # qsGW potential, Eq. (19), from the closed-form residues
+    V = O.sigma_qs(w, eps, Om, 1, eta)
+    G = np.zeros((2, 2))
+    for m in range(2):
+        for n in range(2):
+            x0 = eps[m] - eps[0] + Om_ref
+            x1 = eps[m] - eps[1] - Om_ref
+            G[m, n] = (w_ref[m, 0] * w_ref[n, 0] * x0 / (x0 ** 2 + eta ** 2)
+                       + w_ref[m, 1] * w_ref[n, 1] * x1 / (x1 ** 2 + eta ** 2))
+    np.testing.assert_allclose(V, 0.5 * (G + G.T), rtol=1e-13, atol=1e-16)
+
+
+# --------------------------------------------------------------- P2 ------
+@pytest.mark.parametrize("seed", [1, 2])
+def test_p2_nonhermitian_casida(seed):
+    p = tiny(seed=seed)
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    Om_b, XpY_b = pins.casida_nonhermitian(B_mo, p.eps0, p.nocc)
+    np.testing.assert_allclose(Om, Om_b, rtol=1e-12)
+    for s in range(Om.size):
+        sgn = np.sign(XpY[:, s] @ XpY_b[:, s])
+        np.testing.assert_allclose(XpY[:, s], sgn * XpY_b[:, s], rtol=1e-9, atol=1e-11)
+
+
+# --------------------------------------------------------------- P3 ------
+def test_p3_spin_orbital_equations():
+    p = tiny(nbf=5, naux=9, nocc=2, seed=7)
+    eta = 1e-2
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    grid = np.array([-1.3, 0.2, 0.9, 2.5])
+    Om_so, sig_so = pins.spin_orbital_gw(B_mo, p.eps0, p.nocc, eta, grid, 1, 3)
+    # singlets are the spin-adapted Omega, triplets are Delta (A = Delta, B = 0)
+    delta = O.transition_energies(p.eps0, p.nocc)
+    expect = np.sort(np.concatenate([Om, delta]))
+    np.testing.assert_allclose(Om_so, expect, rtol=1e-12)
+    sig = O.sigma_element(w, p.eps0, Om, p.nocc, eta, 1, 3, grid)
+    np.testing.assert_allclose(sig, sig_so, rtol=1e-11, atol=1e-14)
+
+
+# --------------------------------------------------------------- P4 ------
+@pytest.mark.parametrize("nu", [0.0, 0.37, 2.0, 11.0])
+def test_p4_dyson_screened_interaction(nu):
+    p = tiny(nbf=7, naux=12, nocc=3, seed=11)
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    Wd = pins.screened_dyson(B_mo, p.eps0, p.nocc, nu)
+    Ws = pins.screened_spectral(w, Om, nu)
+    np.testing.assert_allclose(Ws, Wd, rtol=1e-10, atol=1e-13 * np.abs(Wd).max())
+
+
+# --------------------------------------------------------------- P5 ------
+@pytest.mark.parametrize("m,n,xi", [(1, 1, 0.3), (1, 3, 0.3), (0, 4, 1.5), (5, 2, 0.05)])
+def test_p5_frequency_integration_of_iGW(m, n, xi):
+    p = tiny(seed=3)
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    mu = 0.5 * (p.eps0[p.nocc - 1] + p.eps0[p.nocc])
+    z = mu + 1j * xi
+    ref = O.sigma_element(w, p.eps0, Om, p.nocc, 0.0, m, n, [z])[0]
+    q = pins.sigma_frequency_integral(B_mo, p.eps0, p.nocc, z, m, n, npts=400)
+    assert abs(q - ref) < 1e-9 * max(1.0, abs(ref))
+
+
+# --------------------------------------------------------------- P6 ------
+def test_p6_weak_coupling_is_mp2_direct():
+    p = tiny(nbf=5, naux=10, nocc=2, seed=5)
+    eta = 0.05
+    om = 0.37
+    diffs, sigs = [], []
+    for lam in (0.01, 0.02):
+        B = p.B_ao * lam
+        B_mo = O.mo_transform(B, p.C0)
+        M, sq = O.rpa_hermitian(B_mo, p.eps0, p.nocc)
+        Om, XpY = O.rpa_solve(M, sq)
+        w = O.residues(B_mo, XpY, p.nocc)
+        gw = O.sigma_element(w, p.eps0, Om, p.nocc, eta, 1, 2, [om])[0]
+        mp2 = pins.sigma_mp2_direct(B_mo, p.eps0, p.nocc, eta, om, 1, 2)
+        diffs.append(abs(gw - mp2))
+        sigs.append(abs(gw))
+    # Sigma ~ lambda^4, Sigma^GW - Sigma^MP2,direct ~ lambda^6
+    assert 14.0 < sigs[1] / sigs[0] < 18.0
+    assert 54.0 < diffs[1] / diffs[0] < 74.0
+
+
+# --------------------------------------------------------------- P7 ------
+def test_p7_sum_rules():
+    p = tiny(nbf=8, naux=16, nocc=3, seed=9)
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    A, B = O.casida_AB(B_mo, p.eps0, p.nocc)
+    delta = O.transition_energies(p.eps0, p.nocc)
+    np.testing.assert_allclose((XpY * Om[None, :]) @ XpY.T, np.diag(delta), atol=1e-11)
+    np.testing.assert_allclose((XpY / Om[None, :]) @ XpY.T, np.linalg.inv(A + B), atol=1e-11)
+    assert abs(np.sum(Om ** 2) - np.trace(M)) < 1e-10 * np.trace(M)
+    np.testing.assert_allclose(A - B, np.diag(delta), atol=1e-13)
+
+
+# --------------------------------------------------------------- P8 ------
+def test_p8_invariances():
+    p = tiny(nbf=7, naux=12, nocc=3, seed=13)
+    eta = 1e-2
+    h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+    ref = O.qsgw_step(p.B_ao, h, p.C0, p.eps0, p.nocc, eta)
+    rng = np.random.default_rng(99)
+    # auxiliary rotation
+    Oa, _ = np.linalg.qr(rng.standard_normal((p.naux, p.naux)))
+    Brot = np.einsum("pq,qmn->pmn", Oa, p.B_ao)
+    r1 = O.qsgw_step(Brot, O.hf_core(Brot, p.C0, p.eps0, p.nocc), p.C0, p.eps0, p.nocc, eta)
+    np.testing.assert_allclose(r1["eps"], ref["eps"], atol=1e-11)
+    np.testing.assert_allclose(r1["Omega"], ref["Omega"], rtol=1e-11)
+    np.testing.assert_allclose(r1["V"], ref["V"], atol=1e-11)
+    # AO rotation
+    R, _ = np.linalg.qr(rng.standard_normal((p.nbf, p.nbf)))
+    B2 = np.einsum("am,pab,bn->pmn", R, p.B_ao, R)
+    C2 = R.T @ p.C0
+    h2 = R.T @ h @ R
+    r2 = O.qsgw_step(B2, h2, C2, p.eps0, p.nocc, eta)
+    np.testing.assert_allclose(r2["eps"], ref["eps"], atol=1e-11)
+    np.testing.assert_allclose(r2["V"], ref["V"], atol=1e-11)
+    np.testing.assert_allclose(R @ r2["F"] @ R.T, ref["F"], atol=1e-11)
+    # MO sign flips
+    sg = np.array([1, -1, -1, 1, -1, 1, -1.0])
+    r3 = O.qsgw_step(p.B_ao, h, p.C0 * sg[None, :], p.eps0, p.nocc, eta)
+    np.testing.assert_allclose(r3["eps"], ref["eps"], atol=1e-11)
+    np.testing.assert_allclose(r3["V"], ref["V"] * np.outer(sg, sg), atol=1e-11)
+
+
+# --------------------------------------------------------------- P9 ------
+def test_p9_ri_hartree_exchange_four_index():
+    p = tiny(nbf=6, naux=10, nocc=2, seed=17)
+    D = O.density(p.C0, p.nocc)
+    J4, K4 = pins.jk_four_index(p.B_ao, D)
+    np.testing.assert_allclose(O.hartree(p.B_ao, D), J4, atol=1e-12)
+    np.testing.assert_allclose(O.exchange(p.B_ao, D), K4, atol=1e-12)
+
+
+# --------------------------------------------------------------- P10 -----
+def test_p10_hf_fixed_point():
+    p = make_config("cfg1")
+    h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+    F = O.fock(h, p.B_ao, p.C0, p.nocc, np.zeros((p.nbf, p.nbf)))
+    e, C = O.diagonalize(F)
+    np.testing.assert_allclose(e, p.eps0, atol=1e-12)
+    np.testing.assert_allclose(np.abs(C.T @ p.C0), np.eye(p.nbf), atol=1e-9)
+    np.testing.assert_allclose(F, F.T, atol=0)
+
+
+# ------------------------------------------------ iteration properties ---
+def test_sigma_real_symmetric_and_cfg1_grid():
+    p = make_config("cfg1")
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    assert Om.size == 95
+    V = O.sigma_qs(w, p.eps0, Om, p.nocc, 1e-3)
+    np.testing.assert_array_equal(V, V.T)
+    grid = cfg1_omega_grid()
+    assert grid.size == 201 and grid[0] == -2.0 and abs(grid[-1] - 2.0) < 1e-15
+    homo = p.nocc - 1
+    sig = O.sigma_element(w, p.eps0, Om, p.nocc, 1e-3, homo, homo, grid)
+    # Sigma(omega) at the grid equals the row form at each omega
+    row = O.sigma_row(w, p.eps0, Om, p.nocc, 1e-3, homo, grid[37])
+    assert abs(row[homo] - sig[37]) < 1e-12 * abs(sig[37])
+    # Sigma(conj z) = conj Sigma(z) with eta -> 0 (real residues)
+    z = 0.1 + 0.4j
+    a = O.sigma_element(w, p.eps0, Om, p.nocc, 0.0, homo, homo + 1, [z, np.conj(z)])
+    assert abs(a[1] - np.conj(a[0])) < 1e-14 * abs(a[0])
+
+
+def test_iterate_records_and_mixing():
+    p = tiny(nbf=8, naux=16, nocc=3, seed=21, coupling=0.1)
+    h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+    eps, C, hist = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, 1e-2, 1e-10, 40)
+    assert hist[-1]["max_deps"] < 1e-10
+    np.testing.assert_allclose(C.T @ C, np.eye(p.nbf), atol=1e-12)
+    # at the fixed point, one more step returns the same energies
+    st = O.qsgw_step(p.B_ao, h, C, eps, p.nocc, 1e-2)
+    np.testing.assert_allclose(st["eps"], eps, atol=1e-9)
+    # linear mixing reaches the same fixed point
+    eps2, _, _ = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, 1e-2, 1e-11, 200, mix=0.6)
+    np.testing.assert_allclose(eps2, eps, atol=1e-9)
+
+
+# ------------------------------------------------------------- mutations --
+_residues = O.residues
+
+
+def _mutant_residues_no_sqrt2(B_mo, XpY, nocc):
+    return _residues(B_mo, XpY, nocc) / np.sqrt(2.0)
+
+
+def _mutant_rpa_minus_sign(B_mo, eps, nocc):
+    A, B = O.casida_AB(B_mo, eps, nocc)
+    delta = O.transition_energies(eps, nocc)
+    K = (A - np.diag(delta)) / 2.0
+    sq = np.sqrt(delta)
+    # A + B with a single factor 2 (spin sum dropped)
+    return sq[:, None] * (np.diag(delta) + 2.0 * K) * sq[None, :], sq
+
+
+def _mutant_residues_transposed(B_mo, XpY, nocc):
+    naux, n, _ = B_mo.shape
+    Bai = B_mo[:, nocc:, :nocc].transpose(0, 2, 1).reshape(naux, -1)
+    rho = Bai @ XpY[::-1]
+    return (np.sqrt(2.0) * (B_mo.reshape(naux, n * n).T @ rho)).reshape(n, n, -1)
+
+
+@pytest.mark.parametrize("target,mutant", [
+    ("residues", _mutant_residues_no_sqrt2),
+    ("rpa_hermitian", _mutant_rpa_minus_sign),
+    ("residues", _mutant_residues_transposed),
+])
+def test_pins_catch_planted_mistakes(monkeypatch, target, mutant):
+    """A plausible mistake planted in the oracle makes the Dyson pin fail."""
+    monkeypatch.setattr(O, target, mutant)
+    p = tiny(nbf=7, naux=12, nocc=3, seed=11)
+    B_mo = O.mo_transform(p.B_ao, p.C0)
+    M, sq = O.rpa_hermitian(B_mo, p.eps0, p.nocc)
+    Om, XpY = O.rpa_solve(M, sq)
+    w = O.residues(B_mo, XpY, p.nocc)
+    Wd = pins.screened_dyson(B_mo, p.eps0, p.nocc, 0.37)
+    Ws = pins.screened_spectral(w, Om, 0.37)
+    assert not np.allclose(Ws, Wd, rtol=1e-6, atol=1e-10)
+
+
+def test_mutant_sigma_sign_caught_by_closed_form(monkeypatch):
+    """Swapping the occupied/virtual pole signs of Eq. (17) fails P1."""
+    import oracle.qsgw_oracle as OM
+    orig = OM._pole_denominators
+
+    def swapped(omega, eps, Omega, nocc, eta):
+        d = orig(omega, eps, Omega, nocc, eta)
+        return d.conj()
+
+    monkeypatch.setattr(OM, "_pole_denominators", swapped)
+    eps = np.array([-0.8, 0.45])
+    B_mo = np.array([[[0.7, 0.3], [0.3, -0.2]]])
+    M, sq = O.rpa_hermitian(B_mo, eps, 1)
+    Om, XpY = O.rpa_solve(M, sq)
+    w = O.residues(B_mo, XpY, 1)
+    grid = np.array([0.1])
+    _, _, sig_ref = pins.one_transition_closed_form(eps[0], eps[1], 0.3, 0.7, -0.2, 1e-3, grid)
+    sig = O.sigma_element(w, eps, Om, 1, 1e-3, 0, 0, grid)
+    assert not np.allclose(sig, sig_ref[0], rtol=1e-8)
+
+
+# ------------------------------------------------------------ generator ---
+def test_generator_determinism_and_structure():
+    a = make_problem(10, 30, 3, 15, 0.9, 42)
+    b = make_problem(10, 30, 3, 15, 0.9, 42)
+    np.testing.assert_array_equal(a.B_ao, b.B_ao)
+    np.testing.assert_array_equal(a.eps0, b.eps0)
+    np.testing.assert_array_equal(a.B_ao, a.B_ao.transpose(0, 2, 1))
+    np.testing.assert_allclose(a.C0.T @ a.C0, np.eye(10), atol=1e-13)
+    assert np.all(np.diff(a.eps0) > 0)
+    assert a.eps0[2] < -0.3 + 1e-12 and a.eps0[3] > 0.05 - 1e-12
+    c = make_problem(10, 30, 3, 15, 0.9, 43)
+    assert not np.array_equal(a.B_ao, c.B_ao)
+
+
+def test_generator_coupling_scale():
+    # mean diagonal (mu mu|mu mu) = 0.5 * coupling Ha in expectation
+    p = make_problem(60, 240, 8, 120, 0.99, 0, coupling=1.0)
+    diag = np.einsum("pmm,pmm->m", p.B_ao, p.B_ao)
+    assert 0.3 < diag.mean() < 0.7
