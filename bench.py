@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of one RI qsGW iteration on one MI355X.
+
+A step is one qsGW iteration of the plain FP64 path through the C-ABI
+(qsgw_iterate, max_iter = 1) from the same starting orbitals: AO->MO
+transform, Casida build, rocSOLVER eigensolve of the Casida matrix, residues,
+qsGW self-energy matrix, Fock build, rocSOLVER eigensolve of the Fock matrix.
+The eigensolves are timed apart from the hot path.  The reported value is the
+sustained algorithmic FLOP rate of the hot path (all stages except the two
+eigensolves), from HIP events recorded inside the library on its stream;
+ms_per_step is the wall time of the whole iteration including eigensolves.
+
+    python bench.py [--steps K] [--warmup W] [--config cfg2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "qsGW iteration time & sustained TFLOP/s vs FP64 plain path at ≤1 meV QP error"
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_name(p, eta):
+    return (f"plain FP64 qsGW iteration, N_basis={p.nbf}, N_aux={p.naux}, n_occ={p.nocc}, "
+            f"{p.ntr} transitions, eta={eta} Ha, synthetic RI tensor rank {p.meta['rank']} "
+            f"decay {p.meta['decay']}, seed {p.meta['seed']}")
+
+
+def cpu_baseline(p, eta, hot_flops):
+    """Time the FP64 oracle on a bounded sample of the same iteration and scale it.
+
+    Sample: 1/8 of the auxiliary functions for the AO->MO transform, the
+    Casida build and the Fock build; 1/40 of the excitations for the residues
+    and the qsGW matrix (random X+Y of the right shape: the timing does not
+    depend on the values).  Each stage time is scaled by its work ratio.
+    """
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    ps = max(1, p.naux // 8)
+    ss = max(1, p.ntr // 40)
+    rng = np.random.default_rng(7)
+    t = {}
+    B = p.B_ao[:ps]
+    t0 = time.perf_counter()
+    Bmo = O.mo_transform(B, p.C0)
+    t["mo_transform"] = (time.perf_counter() - t0) * (p.naux / ps)
+    t0 = time.perf_counter()
+    O.rpa_hermitian(Bmo, p.eps0, p.nocc)
+    t["rpa_build"] = (time.perf_counter() - t0) * (p.naux / ps)
+    XpY = rng.standard_normal((p.ntr, ss))
+    Om = np.sort(rng.uniform(0.5, 50.0, ss))
+    t0 = time.perf_counter()
+    w = O.residues(Bmo, XpY, p.nocc)
+    t["residues"] = (time.perf_counter() - t0) * (p.naux / ps) * (p.ntr / ss)
+    t0 = time.perf_counter()
+    V = O.sigma_qs(w, p.eps0, Om, p.nocc, eta)
+    t["sigma"] = (time.perf_counter() - t0) * (p.ntr / ss)
+    t0 = time.perf_counter()
+    O.fock(np.zeros((p.nbf, p.nbf)), B, p.C0, p.nocc, V)
+    t["fock"] = (time.perf_counter() - t0) * (p.naux / ps)
+    est = sum(t.values())
+    return dict(value=hot_flops / est / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
+                sample=(f"oracle stages on 1/8 of the auxiliary functions (AO->MO, Casida build, "
+                        f"Fock) and 1/40 of the excitations (residues, qsGW matrix), scaled by "
+                        f"work ratio to the full iteration; est. hot-path s/iteration = {est:.2f}"),
+                stage_s=t)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the qsGW iteration here runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2210_17093_amd.qsgw as q
+    from qsgw_inputs import CONFIGS, make_config
+
+    cfg = CONFIGS[args.config]
+    eta = cfg["eta"]
+    log(f"[bench] generating {args.config} inputs")
+    p = make_config(args.config)
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(p.B_ao).to(dev)
+    C0 = torch.from_numpy(p.C0).to(dev)
+    e0 = torch.from_numpy(p.eps0).to(dev)
+    C = torch.empty_like(C0)
+    e = torch.empty_like(e0)
+    ctx = q.Context()
+    h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
+    torch.cuda.synchronize()
+
+    def step():
+        C.copy_(C0)
+        e.copy_(e0)
+        return q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1)
+
+    for i in range(args.warmup):
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rc, rep, _ = step()
+        reps.append(rep)
+        log(f"[bench] step {i + 1}/{args.steps}: hot "
+            f"{sum(v for k, v in rep['ms'].items() if not k.startswith('eig')):.2f} ms, "
+            f"eig_rpa {rep['ms']['eig_rpa']:.1f} ms, eig_fock {rep['ms']['eig_fock']:.1f} ms")
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+
+    hot_ms = float(np.mean([sum(v for k, v in r["ms"].items() if not k.startswith("eig"))
+                            for r in reps]))
+    hot_flops = reps[0]["hot_flops"]
+    value = hot_flops / (hot_ms * 1e-3) / 1e12
+    kern_ms = {k: float(np.mean([r["kernel_ms"][k] for r in reps])) for k in reps[0]["kernel_ms"]}
+    launches = reps[0]["kernel_launches"]
+    dom = max(kern_ms, key=kern_ms.get)
+    per_launch_ms = kern_ms[dom] / max(1, launches[dom])
+    flops_per_launch = reps[0]["kernel_flops"][dom] / max(1, launches[dom])
+    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload_name(p, eta), "precision": "fp64-plain"},
+        "hot_path_ms": round(hot_ms, 3),
+        "eig_rpa_ms": round(float(np.mean([r["ms"]["eig_rpa"] for r in reps])), 3),
+        "eig_fock_ms": round(float(np.mean([r["ms"]["eig_fock"] for r in reps])), 3),
+        "stage_ms": {k: round(float(np.mean([r["ms"][k] for r in reps])), 3) for k in reps[0]["ms"]},
+        "kernel_ms": {k: round(v, 3) for k, v in kern_ms.items()},
+        "hot_flops": hot_flops,
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": flops_per_launch, "ms_per_launch": round(per_launch_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(p, eta, hot_flops)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * libqsgw -- one RI quasiparticle self-consistent GW (qsGW) iteration on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of "GPU acceleration of many-body perturbation theory
+ * methods in MOLGW with OpenACC" (arXiv 2210.17093), section "Theoretical
+ * background", with the two-electron integrals in resolution-of-identity
+ * (RI) form (mu nu|lambda tau) = sum_P B^P_{mu nu} B^P_{lambda tau}:
+ *
+ *   LCAO, Eq. (3)            phi_m = sum_mu C_{mu m} phi_mu
+ *   AO->MO, Eq. (16)         B^P_{mn} = sum_{mu nu} C_{mu m} B^P_{mu nu} C_{nu n}
+ *   Casida, Eqs. (12)-(14)   closed-shell singlet, A = Delta + 2K, B = 2K,
+ *                            K_{ia,jb} = sum_P B^P_{ia} B^P_{jb}, solved as
+ *                            M = (A-B)^{1/2}(A+B)(A-B)^{1/2} = Delta^2 + 4 sqrt(Delta) K sqrt(Delta)
+ *   residues, Eq. (18)       w^s_{mn} = sqrt(2) sum_P B^P_{mn} sum_{ia} B^P_{ia} (X+Y)^s_{ia}
+ *   self-energy, Eq. (17)    Sigma_{mn}(omega) = sum_{i s} w^s_{mi} w^s_{ni} / (omega - eps_i + Omega_s - i eta)
+ *                                              + sum_{a s} w^s_{ma} w^s_{na} / (omega - eps_a - Omega_s + i eta)
+ *   qsGW potential, Eq. (19) V_{mn} = 1/2 Re[Sigma_{mn}(eps_m) + Sigma_{mn}(eps_n)]
+ *   Hamiltonian, Eq. (6)     F = h + J - K + C V C^T, with J, K of Eqs. (7), (9), (10)
+ *   eigenproblem, Eq. (4)    F C' = C' eps' (S = I: orthonormal synthetic AO basis)
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer, FP64, row-major, contiguous,
+ *     allocated and owned by the caller.  The library never frees a caller
+ *     pointer and keeps none past the call.
+ *   - Sizes are int64_t; element offsets are computed in 64-bit.
+ *   - n_occ occupied orbitals are the lowest ones (aufbau); n_v = nbf - nocc;
+ *     transitions are t = i * n_v + (a - nocc) for 0 <= i < nocc <= a < nbf;
+ *     ntr = nocc * n_v.
+ *   - Work is queued on the context's HIP stream and is asynchronous unless
+ *     stated otherwise.  The context owns its workspace (grown on demand with
+ *     hipMalloc, released by qsgw_ctx_destroy).
+ *   - Return value: QSGW_OK, QSGW_NOT_CONVERGED (results valid), or a
+ *     negative error; qsgw_last_error() returns a message for the context.
+ *   - One context per host thread.  Calls on one context must not overlap.
+ */
+#ifndef QSGW_H
+#define QSGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSGW_VERSION 1
+
+/* Status codes. */
+#define QSGW_OK 0
+#define QSGW_NOT_CONVERGED 1
+#define QSGW_ERR_INVALID_ARG (-1)
+#define QSGW_ERR_NONFINITE (-2)
+#define QSGW_ERR_HIP (-3)
+#define QSGW_ERR_SOLVER (-4)
+#define QSGW_ERR_ALLOC (-5)
+#define QSGW_ERR_UNSUPPORTED (-6)
+
+/* Arithmetic of the contractions (MO transform, RPA build, residues). */
+#define QSGW_PREC_FP64 0
+#define QSGW_PREC_FP32 1       /* not in this version: QSGW_ERR_UNSUPPORTED */
+#define QSGW_PREC_SPLIT_BF16 2 /* not in this version: QSGW_ERR_UNSUPPORTED */
+
+/* qsgw_sigma modes. */
+#define QSGW_SIGMA_QS_MATRIX 0
+#define QSGW_SIGMA_DIAG_GRID 1
+
+/* Fock update modes of qsgw_iterate. */
+#define QSGW_FOCK_FULL_JK 0 /* F = h + J[D] - K[D] + Vc, D from the current orbitals */
+
+#define QSGW_REPORT_MAX_ITERS 64
+
+typedef struct qsgw_ctx qsgw_ctx;
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL
+ * means the null stream of the current device).  The context also creates a
+ * rocBLAS handle on that stream for the dense eigensolver. */
+int qsgw_ctx_create(qsgw_ctx** ctx, void* hip_stream);
+int qsgw_ctx_destroy(qsgw_ctx* ctx);
+/* Last error message of this context ("" if none).  Owned by the context. */
+const char* qsgw_last_error(const qsgw_ctx* ctx);
+/* Returns QSGW_VERSION. */
+int qsgw_version(void);
+/* Host timing of the last call's stages, milliseconds (HIP events on the
+ * context stream); fills up to n entries in the order
+ * {mo_transform, rpa_build, eig_rpa, residues, sigma, fock, eig_fock}. */
+int qsgw_last_stage_ms(const qsgw_ctx* ctx, double* ms, int n);
+
+/*
+ * AO->MO transform of the RI tensor, Eq. (16):
+ *   B_mo[P][m][n] = sum_{mu,nu} C[mu][m] B_ao[P][mu][nu] C[nu][n].
+ * B_ao: [naux][nbf][nbf], symmetric in its last two indices.
+ * C:    [nbf][nbf], column m holds MO m.
+ * B_mo: [naux][nbf][nbf] out; written exactly symmetric in (m, n).
+ * Errors: nbf < 1, naux < 1, NULL pointers, precision other than FP64.
+ */
+int qsgw_mo_transform(qsgw_ctx* ctx, int64_t nbf, int64_t naux, const double* B_ao,
+                      const double* C, double* B_mo, int precision);
+
+/*
+ * Hermitian Casida matrix, Eqs. (12)-(14), closed-shell singlet:
+ *   sqrt_delta[t] = sqrt(eps[a] - eps[i]),
+ *   M[t][u] = delta_tu Delta_t^2 + 4 sqrt_delta[t] (sum_P B_mo[P][i][a] B_mo[P][j][b]) sqrt_delta[u]
+ * for t = (i, a), u = (j, b).  M is [ntr][ntr], written exactly symmetric.
+ * B_mo: [naux][nbf][nbf]; eps: [nbf] ascending (eps[a] > eps[i] required).
+ * Errors: 0 < nocc < nbf violated; precision other than FP64.
+ */
+int qsgw_rpa_build(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                   const double* eps, double* M, double* sqrt_delta, int precision);
+
+/*
+ * Dense symmetric eigensolve of the Casida matrix (rocSOLVER dsyevd), kept
+ * apart from the hot path: M Z = Z Omega^2.
+ * M_to_Z: [ntr][ntr] in; on return holds Z column-major, i.e. row s of the
+ *         row-major view is the eigenvector of Omega[s].
+ * Omega:  [ntr] out, ascending, Omega_s = sqrt of the eigenvalue.
+ * Errors: QSGW_ERR_SOLVER if dsyevd fails or an eigenvalue is <= 0 (RPA
+ * instability).  Synchronizes the context stream.
+ */
+int qsgw_rpa_solve(qsgw_ctx* ctx, int64_t ntr, double* M_to_Z, double* Omega);
+
+/*
+ * Screened-interaction residues, Eq. (18), for excitations
+ * s in [s_begin, s_begin + s_count):
+ *   (X+Y)[t][s] = sqrt_delta[t] Z[s][t] / sqrt(Omega[s])
+ *   rho[P][s]   = sum_t B_mo[P][i_t][a_t] (X+Y)[t][s]
+ *   w[m][n][s - s_begin] = sqrt(2) sum_P B_mo[P][m][n] rho[P][s]
+ * Z: [ntr][ntr] as returned by qsgw_rpa_solve; Omega: [ntr].
+ * w: [nbf][nbf][s_count] out, written exactly symmetric in (m, n).
+ * Errors: s range outside [0, ntr); precision other than FP64.
+ */
+int qsgw_residues(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                  const double* sqrt_delta, const double* Z, const double* Omega,
+                  int64_t s_begin, int64_t s_count, double* w, int precision);
+
+/*
+ * GW self-energy from residues of ns excitations, Eq. (17).
+ * w:     [nbf][nbf][ns] as written by qsgw_residues;
+ * Omega: [ns], the excitation energies of those ns columns.
+ * mode QSGW_SIGMA_QS_MATRIX, Eq. (19):
+ *   out[m][n] (+)= 1/2 (G[m][n] + G[n][m]),
+ *   G[m][n] = sum_{k,s} w[m][k][s] w[n][k][s] Re 1/(eps_m - eps_k +- (Omega_s - i eta))
+ *   ("+" for occupied k, "-" for empty k).  omega, nomega, states, nstates unused.
+ * mode QSGW_SIGMA_DIAG_GRID, Eq. (17) with m = n:
+ *   out[j][l] (+)= Sigma_{mm}(omega[l]), m = states[j], complex128 stored as
+ *   interleaved (re, im) pairs: out is [nstates][nomega][2].
+ *   omega: [nomega] device; states: [nstates] device int64.
+ * accumulate = 1 adds into out (for streamed excitation blocks), 0 overwrites.
+ * Errors: eta <= 0; states out of range (checked on the host only for nstates
+ * <= 0; device indexes are clamped-checked and flagged as INVALID_ARG).
+ */
+int qsgw_sigma(qsgw_ctx* ctx, int mode, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
+               const double* eps, const double* Omega, double eta, const double* omega,
+               int64_t nomega, const int64_t* states, int64_t nstates, double* out, int accumulate);
+
+/*
+ * One-body matrix that makes (eps0, C0) a Hartree-Fock fixed point of
+ * Eq. (6) with Sigma_c = 0:  h = C0 diag(eps0) C0^T - J[D0] + K[D0],
+ * D0 = C0[:, :nocc] C0[:, :nocc]^T (Eq. (9)), J and K from Eqs. (7), (10).
+ * h: [nbf][nbf] out.  Used to build synthetic problems.
+ */
+int qsgw_hf_core(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_ao,
+                 const double* C0, const double* eps0, double* h);
+
+/* Problem, state, options and report of qsgw_iterate. */
+typedef struct {
+  int64_t nbf;
+  int64_t naux;
+  int64_t nocc;
+  const double* B_ao; /* device [naux][nbf][nbf], symmetric in (mu, nu) */
+  const double* h;    /* device [nbf][nbf], one-body part T + V_ext of Eq. (6) */
+} qsgw_problem;
+
+typedef struct {
+  double* eps;       /* device [nbf], in/out: orbital energies, ascending */
+  double* C;         /* device [nbf][nbf], in/out: MO coefficients, orthonormal columns */
+  double* Vc;        /* device [nbf][nbf] or NULL, out: last AO-basis potential C V C^T;
+                        read back as the previous potential when mix != 1 and iteration > 0 */
+  int64_t iteration; /* in/out: iterations done so far (0 at the start) */
+} qsgw_state;
+
+typedef struct {
+  int precision;    /* QSGW_PREC_FP64 */
+  double eta;       /* > 0, Ha */
+  double tol;       /* converged when max_m |eps'_m - eps_m| < tol */
+  int64_t max_iter; /* iterations in this call, >= 1 */
+  double mix;       /* Vc <- mix Vc + (1 - mix) Vc_prev, in (0, 1]; 1 = no mixing */
+  int fock_mode;    /* QSGW_FOCK_FULL_JK */
+  int64_t s_block;  /* excitations per streamed residue block; 0 = automatic */
+} qsgw_options;
+
+typedef struct {
+  int64_t iterations; /* iterations done in this call */
+  int converged;      /* 1 if the last iteration met tol */
+  double max_deps[QSGW_REPORT_MAX_ITERS]; /* max |d eps| of each iteration of this call */
+  double ms_stage[7];      /* summed over the call: mo_transform, rpa_build, eig_rpa,
+                              residues, sigma, fock, eig_fock */
+  double hot_flops;        /* algorithmic FLOPs of one iteration's hot path */
+  double ms_kernel[8];     /* summed over the call, per kernel: AO->MO half 1, AO->MO half 2,
+                              Casida gather+product, residue rho, residue w, qsGW matrix
+                              product, qsGW reduce, Fock build */
+  double kernel_flops[8];  /* algorithmic FLOPs of one iteration, same kernel order */
+  int64_t kernel_launches[8]; /* launches of each kernel in the call */
+} qsgw_report;
+
+/*
+ * qsGW iterations, all on the device: per iteration Eq. (16) -> Casida
+ * (eigensolve apart) -> Eq. (18) -> Eqs. (17), (19) -> Eq. (6) in the basis
+ * of the current orbitals -> eigensolve of Eq. (4) -> C' = C U.
+ * Updates st->eps, st->C (and st->Vc) in place; stops after max_iter or when
+ * converged.  Synchronizes once per iteration to read max|d eps|.
+ * Returns QSGW_OK if converged, QSGW_NOT_CONVERGED otherwise.
+ */
+int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const qsgw_options* opt,
+                 qsgw_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSGW_H */

@@ -1,0 +1,229 @@
+// FP64 matrix-core GEMM for gfx950 (CDNA4), the contraction engine of every
+// dense step of the qsGW iteration (AO->MO transform, Casida build, residues,
+// qsGW self-energy matrix, Fock exchange).
+//
+//   C[b][m][n] = sum_{k in split z} A_b(m, k) * B_b(n, k)
+//
+// A and B are "operands": functors that return element (r, k) of a logical
+// R x K matrix of batch b, with a compile-time flag telling whether k or r is
+// the unit-stride direction (so global loads are coalesced either way).  The
+// epilogue is a functor that receives each finished element.
+//
+// Tiling: BM x BN block tile, BK = 16, 256 threads = 4 wave64 in a 2 x 2
+// arrangement; each wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16
+// accumulators updated by v_mfma_f64_16x16x4_f64.  Both operands are staged
+// k-major in LDS ([k][r], row pitch BR+1 doubles so the transposing stores
+// of k-contiguous operands hit distinct banks), double buffered with one
+// barrier per k-tile, and the next k-tile is prefetched into registers while
+// the current one feeds the matrix cores.
+//
+// MFMA f64 16x16x4 lane layout (wave64):
+//   A fragment: lane l holds A[l % 16][l / 16]      (16 rows x 4 k)
+//   B fragment: lane l holds B[l / 16][l % 16]      (4 k x 16 cols)
+//   D:          lane l, element j holds D[4 (l / 16) + j][l % 16]
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qsgw {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Element (r, k) at p[b*sb + r*sr + k*sk]; rows >= `rows` or k >= K read 0.
+template <bool KC>
+struct Strided {
+  static constexpr bool kContig = KC;
+  const double* p;
+  int64_t sr, sk, sb;
+  int64_t rows;
+  __device__ __forceinline__ double get(int64_t b, int64_t r, int64_t k) const {
+    return r < rows ? p[b * sb + r * sr + k * sk] : 0.0;
+  }
+};
+
+// Hardware dispatches consecutive workgroup ids round-robin over the 8 XCDs
+// (each with its own L2).  Renumber so that each XCD walks a contiguous range
+// of logical tiles: neighbouring tiles share operand panels in one L2.
+__device__ __forceinline__ int64_t xcd_logical_id(int64_t bid, int64_t nwg) {
+  constexpr int64_t NXCD = 8;
+  if (nwg < NXCD) return bid;
+  const int64_t xcd = bid % NXCD, local = bid / NXCD;
+  const int64_t q = nwg / NXCD, r = nwg % NXCD;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+struct TileCoord {
+  int64_t tm, tn;
+};
+
+// Grouped ordering: GROUP_M row tiles sweep all column tiles before the next
+// group starts, bounding the live A and B panels.
+__device__ __forceinline__ TileCoord grouped_tile(int64_t id, int64_t tiles_m, int64_t tiles_n) {
+  constexpr int64_t GROUP_M = 8;
+  const int64_t per_group = GROUP_M * tiles_n;
+  const int64_t g = id / per_group;
+  const int64_t first_m = g * GROUP_M;
+  const int64_t gsz = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
+  const int64_t in = id - g * per_group;
+  return {first_m + in % gsz, in / gsz};
+}
+
+// Upper-triangular tile pairs tm <= tn, numbered column by column:
+// id = tn (tn + 1) / 2 + tm.
+__device__ __forceinline__ TileCoord tri_tile(int64_t id) {
+  int64_t tn = (int64_t)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+  while (tn * (tn + 1) / 2 > id) --tn;
+  while ((tn + 1) * (tn + 2) / 2 <= id) ++tn;
+  return {id - tn * (tn + 1) / 2, tn};
+}
+
+// Tile filter hook: returns false for tiles whose outputs are all unneeded.
+struct AllTiles {
+  __device__ __forceinline__ bool operator()(int64_t, int64_t, int64_t, int64_t) const { return true; }
+};
+
+// TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
+// epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
+template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
+                                                       int64_t K, int64_t kchunk, int64_t tiles_m,
+                                                       int64_t tiles_n, FILT filt) {
+  constexpr int BK = 16;
+  constexpr int LDA = BM + 1;
+  constexpr int LDB = BN + 1;
+  constexpr int EA = BM * BK / 256;
+  constexpr int EB = BN * BK / 256;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert(BM % 32 == 0 && BN % 32 == 0, "tile must split into 2x2 waves of 16x16 MFMA tiles");
+  static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+
+  __shared__ double As[2][BK * LDA];
+  __shared__ double Bs[2][BK * LDB];
+
+  const int64_t nwg = (int64_t)gridDim.x;
+  const int64_t id = xcd_logical_id((int64_t)blockIdx.x, nwg);
+  TileCoord tc = TRI ? tri_tile(id) : grouped_tile(id, tiles_m, tiles_n);
+  const int64_t batch = blockIdx.y;
+  const int64_t split = blockIdx.z;
+  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  if (m0 >= M || n0 >= N) return;
+  if (!filt(m0, m0 + BM < M ? m0 + BM : M, n0, n0 + BN < N ? n0 + BN : N)) return;
+  const int64_t kb0 = split * kchunk;
+  const int64_t kb1 = (kb0 + kchunk) < K ? (kb0 + kchunk) : K;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * WM;
+  const int wn = (wave & 1) * WN;
+
+  f64x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[EA], rb[EB];
+
+  auto gload = [&](int64_t kbase) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = e * 256 + tid;
+      const int kk = OA::kContig ? (idx % BK) : (idx / BM);
+      const int r = OA::kContig ? (idx / BK) : (idx % BM);
+      const int64_t k = kbase + kk;
+      ra[e] = (k < kb1) ? A.get(batch, m0 + r, k) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = e * 256 + tid;
+      const int kk = OB::kContig ? (idx % BK) : (idx / BN);
+      const int r = OB::kContig ? (idx / BK) : (idx % BN);
+      const int64_t k = kbase + kk;
+      rb[e] = (k < kb1) ? B.get(batch, n0 + r, k) : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = e * 256 + tid;
+      const int kk = OA::kContig ? (idx % BK) : (idx / BM);
+      const int r = OA::kContig ? (idx / BK) : (idx % BM);
+      As[buf][kk * LDA + r] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = e * 256 + tid;
+      const int kk = OB::kContig ? (idx % BK) : (idx / BN);
+      const int r = OB::kContig ? (idx / BK) : (idx % BN);
+      Bs[buf][kk * LDB + r] = rb[e];
+    }
+  };
+
+  const int64_t nk = kb1 > kb0 ? (kb1 - kb0 + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kb0);
+    sstore(0);
+    __syncthreads();
+  }
+  for (int64_t it = 0; it < nk; ++it) {
+    const int cur = (int)(it & 1);
+    if (it + 1 < nk) gload(kb0 + (it + 1) * BK);
+    const double* as = As[cur];
+    const double* bs = Bs[cur];
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int krow = ks * 4 + (lane >> 4);
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = as[krow * LDA + wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = bs[krow * LDB + wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t m = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+        const int64_t n = n0 + wn + j * 16 + (lane & 15);
+        if (m < M && n < N) {
+          if (TRI) {
+            if (m <= n) epi(batch, split, m, n, acc[i][j][q], m != n);
+          } else {
+            epi(batch, split, m, n, acc[i][j][q], false);
+          }
+        }
+      }
+}
+
+// ---------------------------------------------------------------- epilogues
+// C[b or z][m][n] = alpha * v  (mirror writes (n, m) too)
+struct EpiStore {
+  double* c;
+  int64_t ldc;
+  int64_t sb;       // stride per batch index
+  int64_t sz;       // stride per split index (partial sums)
+  double alpha;
+  __device__ __forceinline__ void operator()(int64_t b, int64_t z, int64_t m, int64_t n, double v,
+                                             bool mirror) const {
+    double* cb = c + b * sb + z * sz;
+    const double x = alpha * v;
+    cb[m * ldc + n] = x;
+    if (mirror) cb[n * ldc + m] = x;
+  }
+};
+
+}  // namespace qsgw

@@ -1,0 +1,243 @@
+// Plain kernels of the qsGW iteration (see kernels.hpp for the contracts).
+#include "kernels.hpp"
+
+#include <math.h>
+
+namespace qsgw {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+}  // namespace
+
+__global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, double* delta,
+                              double* sqrt_delta, int* bad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nocc * nv) return;
+  const int64_t i = t / nv;
+  const int64_t a = nocc + (t - i * nv);
+  const double d = eps[a] - eps[i];
+  if (!(d > 0.0) || !finite(d)) atomicOr(bad, 1);
+  delta[t] = d;
+  sqrt_delta[t] = sqrt(d > 0.0 ? d : 0.0);
+}
+
+__global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_t naux,
+                             int64_t nbf, int64_t nocc, double* bt) {
+  const int64_t nv = nbf - nocc;
+  const int64_t ntr = nocc * nv;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= naux * ntr) return;
+  const int64_t P = idx / ntr;
+  const int64_t t = idx - P * ntr;
+  const int64_t i = t / nv;
+  const int64_t a = nocc + (t - i * nv);
+  bt[idx] = bmo[(P * nbf + i) * nbf + a] * sqrt_delta[t];
+}
+
+__global__ void k_omega_from_eigs(const double* lam, int64_t n, double* Omega, int* bad) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double l = lam[s];
+  if (!(l > 0.0) || !finite(l)) atomicOr(bad, 1);
+  Omega[s] = sqrt(l > 0.0 ? l : 0.0);
+}
+
+__global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* out,
+                             int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t m = idx / n;
+  const int64_t c = idx - m * n;
+  const int64_t nn = n * n;
+  double a = 0.0, b = 0.0;
+  for (int64_t z = 0; z < nz; ++z) {
+    a += part[z * nn + m * n + c];
+    b += part[z * nn + c * n + m];
+  }
+  // a + b and b + a round identically, so out stays exactly symmetric.
+  const double v = 0.5 * (a + b);
+  out[idx] = accumulate ? out[idx] + v : v;
+}
+
+__global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc,
+                            double* c) {
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= naux) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < nocc; ++i) s += bmo[(P * nbf + i) * nbf + i];
+  c[P] = s;
+}
+
+__global__ void k_hartree_mo(const double* bmo, const double* c, int64_t naux, int64_t nn,
+                             double* J) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  double s = 0.0;
+  for (int64_t P = 0; P < naux; ++P) s += c[P] * bmo[P * nn + idx];
+  J[idx] = 2.0 * s;
+}
+
+__global__ void k_fock_assemble(const double* hmo, const double* J, const double* Kpart,
+                                int64_t nz, const double* V, int64_t n, double* F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t m = idx / n;
+  const int64_t c = idx - m * n;
+  const int64_t nn = n * n;
+  double k = 0.0;
+  for (int64_t z = 0; z < nz; ++z) k += Kpart[z * nn + idx];
+  const double h = 0.5 * (hmo[m * n + c] + hmo[c * n + m]);
+  F[idx] = h + J[idx] - k + V[idx];
+}
+
+__global__ void k_hf_core_mo(const double* eps, const double* J, const double* Kpart, int64_t nz,
+                             int64_t n, double* X) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t m = idx / n;
+  const int64_t c = idx - m * n;
+  const int64_t nn = n * n;
+  double k = 0.0;
+  for (int64_t z = 0; z < nz; ++z) k += Kpart[z * nn + idx];
+  X[idx] = (m == c ? eps[m] : 0.0) - J[idx] + k;
+}
+
+__global__ void k_symmetrize(const double* a, int64_t n, double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t m = idx / n;
+  const int64_t c = idx - m * n;
+  out[idx] = 0.5 * (a[m * n + c] + a[c * n + m]);
+}
+
+__global__ void k_axpby(const double* a, const double* b, double alpha, double beta, int64_t len,
+                        double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= len) return;
+  out[idx] = alpha * a[idx] + beta * b[idx];
+}
+
+__global__ void k_fix_column_signs(double* C, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double best = -1.0, val = 1.0;
+  for (int64_t r = 0; r < n; ++r) {
+    const double x = C[r * n + j];
+    if (fabs(x) > best) {
+      best = fabs(x);
+      val = x;
+    }
+  }
+  if (val < 0.0)
+    for (int64_t r = 0; r < n; ++r) C[r * n + j] = -C[r * n + j];
+}
+
+__global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, double* out) {
+  __shared__ double red[4];
+  double m = 0.0;
+  bool nonfinite = false;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = fabs(a[i] - b[i]);
+    if (!finite(d)) nonfinite = true;
+    m = fmax(m, d);
+  }
+  if (nonfinite) m = INFINITY;
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    *out = r;
+  }
+}
+
+__global__ void k_check_finite(const double* x, int64_t len, int* bad) {
+  bool ok = true;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    ok = ok && finite(x[i]);
+  if (!ok) atomicOr(bad, 1);
+}
+
+// One workgroup per (state, block of OT frequencies).  Threads stride over the
+// (k, s) pairs of w[m][k][s] (unit stride in s), accumulate OT complex pole
+// sums in registers, then reduce in a fixed order (wave shuffles, then the 4
+// waves in index order): the result is deterministic.
+__global__ void k_sigma_diag_grid(const double* w, const double* eps, const double* Omega,
+                                  int64_t nbf, int64_t nocc, int64_t ns, double eta,
+                                  const double* omega, int64_t nomega, const int64_t* states,
+                                  int64_t nstates, double* out, int accumulate, int* bad) {
+  constexpr int OT = 8;
+  __shared__ double red[4][2 * OT];
+  const int64_t j = blockIdx.x;
+  const int64_t l0 = (int64_t)blockIdx.y * OT;
+  if (j >= nstates) return;
+  const int64_t m = states[j];
+  if (m < 0 || m >= nbf) {
+    if (threadIdx.x == 0) atomicOr(bad, 1);
+    return;
+  }
+  double om[OT];
+#pragma unroll
+  for (int q = 0; q < OT; ++q) om[q] = (l0 + q < nomega) ? omega[l0 + q] : 0.0;
+  double re[OT], im[OT];
+#pragma unroll
+  for (int q = 0; q < OT; ++q) re[q] = im[q] = 0.0;
+  const double eta2 = eta * eta;
+  const int64_t npair = nbf * ns;
+  const double* wm = w + m * npair;
+  for (int64_t p = threadIdx.x; p < npair; p += blockDim.x) {
+    const int64_t k = p / ns;
+    const int64_t s = p - k * ns;
+    const double x = wm[p];
+    const double w2 = x * x;
+    const bool occ = k < nocc;
+    const double shift = occ ? (Omega[s] - eps[k]) : (-Omega[s] - eps[k]);
+    const double sg = occ ? eta : -eta;
+#pragma unroll
+    for (int q = 0; q < OT; ++q) {
+      const double d = om[q] + shift;
+      const double inv = w2 / (d * d + eta2);
+      re[q] += d * inv;
+      im[q] += sg * inv;
+    }
+  }
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < OT; ++q) {
+    const double a = wave_sum(re[q]);
+    const double b = wave_sum(im[q]);
+    if ((threadIdx.x & 63) == 0) {
+      red[wv][2 * q] = a;
+      red[wv][2 * q + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * OT) {
+    const int q = threadIdx.x >> 1;
+    double v = 0.0;
+    for (int u = 0; u < (int)(blockDim.x >> 6); ++u) v += red[u][threadIdx.x];
+    const int64_t l = l0 + q;
+    if (l < nomega) {
+      double* o = out + (j * nomega + l) * 2 + (threadIdx.x & 1);
+      *o = accumulate ? *o + v : v;
+    }
+  }
+}
+
+}  // namespace qsgw

@@ -1,0 +1,144 @@
+// Element-wise, gather, reduction and pole-sum kernels of the qsGW iteration,
+// plus the operand/epilogue functors that specialise the FP64 GEMM engine to
+// each contraction.  All offsets are 64-bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gemm_f64.hpp"
+
+namespace qsgw {
+
+// ------------------------------------------------------------ operands ----
+// Fock exchange in the MO basis, K_mn = sum_P sum_{i<nocc} B^P_{im} B^P_{in}:
+// element (r = m, k = (P, i)) at B_mo[P][i][m]; m is unit-stride.
+struct OccRowsOp {
+  static constexpr bool kContig = false;
+  const double* bmo;
+  int64_t nbf, nocc;
+  __device__ __forceinline__ double get(int64_t, int64_t r, int64_t k) const {
+    if (r >= nbf) return 0.0;
+    const int64_t P = k / nocc;
+    const int64_t i = k - P * nocc;
+    return bmo[(P * nbf + i) * nbf + r];
+  }
+};
+
+// Pole-weighted residues for the qsGW matrix, Eqs. (17) and (19):
+// element (r = m, k = (kst, s)) = w[m][kst][s] * Re 1/(eps_m - eps_kst +- (Omega_s - i eta))
+//   = w * x / (x^2 + eta^2),  x = eps_m - eps_kst + Omega_s (occupied kst)
+//                             x = eps_m - eps_kst - Omega_s (empty kst)
+struct PoleScaledResidueOp {
+  static constexpr bool kContig = true;
+  const double* w;
+  const double* eps;
+  const double* Omega;
+  int64_t nbf, nocc, ns;
+  double eta;
+  __device__ __forceinline__ double get(int64_t, int64_t r, int64_t k) const {
+    if (r >= nbf) return 0.0;
+    const int64_t kst = k / ns;
+    const int64_t s = k - kst * ns;
+    const double om = Omega[s];
+    const double x = eps[r] - eps[kst] + (kst < nocc ? om : -om);
+    return w[r * nbf * ns + k] * (x / (x * x + eta * eta));
+  }
+};
+
+// ----------------------------------------------------------- epilogues ----
+// Casida matrix: M[t][u] = 4 v + delta_tu Delta_t^2, with v = sum_P Bt Bt
+// where Bt = B_ia sqrt(Delta) already carries the (A-B)^{1/2} factors.
+struct EpiCasida {
+  double* Mout;
+  const double* delta;
+  int64_t ntr;
+  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t m, int64_t n, double v,
+                                             bool mirror) const {
+    double x = 4.0 * v;
+    if (m == n) x += delta[m] * delta[m];
+    Mout[m * ntr + n] = x;
+    if (mirror) Mout[n * ntr + m] = x;
+  }
+};
+
+// rho'[P][s] = sqrt(2 / Omega_s) v: the (X+Y) normalisation Omega^{-1/2} and
+// the singlet spin factor sqrt(2) of Eq. (18) applied once per column.
+struct EpiRho {
+  double* rho;
+  const double* Omega;  // already offset to the block's first excitation
+  int64_t ld;
+  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t m, int64_t n, double v,
+                                             bool) const {
+    rho[m * ld + n] = v * sqrt(2.0 / Omega[n]);
+  }
+};
+
+// w[m][k][s] from the GEMM row r = m * nbf + k; written for m <= k and
+// mirrored to (k, m), so w is exactly symmetric in (m, k).
+struct EpiResidue {
+  double* w;
+  int64_t nbf, ns;
+  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
+                                             bool) const {
+    const int64_t m = r / nbf;
+    const int64_t k = r - m * nbf;
+    if (m > k) return;
+    w[r * ns + s] = v;
+    if (m != k) w[(k * nbf + m) * ns + s] = v;
+  }
+};
+
+// Row tiles of the residue GEMM that hold at least one pair m <= k.
+struct UpperPairRows {
+  int64_t nbf;
+  __device__ __forceinline__ bool operator()(int64_t r0, int64_t r1, int64_t, int64_t) const {
+    for (int64_t m = r0 / nbf; m * nbf < r1; ++m) {
+      const int64_t lo = m * (nbf + 1) > r0 ? m * (nbf + 1) : r0;
+      const int64_t hi = (m + 1) * nbf < r1 ? (m + 1) * nbf : r1;
+      if (lo < hi) return true;
+    }
+    return false;
+  }
+};
+
+// ------------------------------------------------------ plain kernels ----
+
+// Delta_t = eps_a - eps_i, sqrt_delta_t, and Bt[P][t] = B_mo[P][i][a] sqrt(Delta_t).
+__global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, double* delta,
+                              double* sqrt_delta, int* bad);
+__global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_t naux,
+                             int64_t nbf, int64_t nocc, double* bt);
+// Omega = sqrt(lambda); flags lambda <= 0 or non-finite.
+__global__ void k_omega_from_eigs(const double* lam, int64_t n, double* Omega, int* bad);
+// out[m][n] (+)= 1/2 (sum_z part[z][m][n] + sum_z part[z][n][m])
+__global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* out, int accumulate);
+// c_P = sum_{i<nocc} B_mo[P][i][i]
+__global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc, double* c);
+// J_mn = 2 sum_P c_P B_mo[P][m][n]
+__global__ void k_hartree_mo(const double* bmo, const double* c, int64_t naux, int64_t nn,
+                             double* J);
+// F[m][n] = sym(hmo)[m][n] + J[m][n] - sum_z Kpart[z][m][n] + V[m][n]
+__global__ void k_fock_assemble(const double* hmo, const double* J, const double* Kpart, int64_t nz,
+                                const double* V, int64_t n, double* F);
+// X = diag(eps) - J + sum_z Kpart   (HF core in the MO basis)
+__global__ void k_hf_core_mo(const double* eps, const double* J, const double* Kpart, int64_t nz,
+                             int64_t n, double* X);
+// out = 1/2 (a + a^T)
+__global__ void k_symmetrize(const double* a, int64_t n, double* out);
+// out = alpha * a + beta * b (elementwise)
+__global__ void k_axpby(const double* a, const double* b, double alpha, double beta, int64_t len,
+                        double* out);
+// Sign convention of eigenvector columns: the largest-|.| entry is positive.
+__global__ void k_fix_column_signs(double* C, int64_t n);
+// max_m |a_m - b_m| (one workgroup), and a finiteness flag.
+__global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, double* out);
+// Non-finite scan: flags any NaN/Inf in x[0..len).
+__global__ void k_check_finite(const double* x, int64_t len, int* bad);
+// Diagonal pole sum Sigma_mm(omega_l), Eq. (17), complex128 interleaved.
+__global__ void k_sigma_diag_grid(const double* w, const double* eps, const double* Omega,
+                                  int64_t nbf, int64_t nocc, int64_t ns, double eta,
+                                  const double* omega, int64_t nomega, const int64_t* states,
+                                  int64_t nstates, double* out, int accumulate, int* bad);
+
+}  // namespace qsgw

@@ -1,0 +1,841 @@
+// C-ABI of libqsgw: context, workspace, stage drivers and the qsGW iteration.
+// Every numerical step runs in the kernels of this library (FP64 matrix-core
+// GEMMs of gemm_f64.hpp and the plain kernels of kernels.hip); the dense
+// symmetric eigensolves go to rocSOLVER and are timed apart.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qsgw.h"
+#include "gemm_f64.hpp"
+#include "kernels.hpp"
+
+using namespace qsgw;
+
+namespace {
+
+enum Slot {
+  W_T = 0,    // AO->MO half transform B_ao C            [naux][nbf][nbf]
+  W_BMO,      // MO tensor (iterate / hf_core)            [naux][nbf][nbf]
+  W_BT,       // B_ia sqrt(Delta)                         [naux][ntr]
+  W_DELTA,    // Delta_t                                  [ntr]
+  W_SQD,      // sqrt(Delta_t)                            [ntr]
+  W_M,        // Casida matrix, then eigenvectors         [ntr][ntr]
+  W_OMEGA,    // Omega                                    [ntr]
+  W_RHO,      // rho' of one excitation block             [naux][sb]
+  W_W,        // residues of one excitation block         [nbf][nbf][sb]
+  W_PART,     // split-K partial sums                     [nz][nbf][nbf]
+  W_V,        // qsGW potential, MO basis                 [nbf][nbf]
+  W_HMO,      // C^T h C                                  [nbf][nbf]
+  W_J,        // Hartree, MO basis                        [nbf][nbf]
+  W_CP,       // occupied traces c_P                      [naux]
+  W_F,        // Fock, then its eigenvectors              [nbf][nbf]
+  W_TMP,      // scratch                                  [nbf][nbf]
+  W_TMP2,     // scratch                                  [nbf][nbf]
+  W_EPSN,     // new energies                             [nbf]
+  W_CNEW,     // new coefficients                         [nbf][nbf]
+  W_EIGE,     // dsyevd off-diagonal workspace            [max(ntr, nbf)]
+  W_SCAL,     // device scalars                           [8]
+  W_FLAGS,    // device int flags                         [8]
+  W_NSLOTS
+};
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qsgw_ctx {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  rocblas_handle blas = nullptr;
+  std::string err;
+  Buffer ws[W_NSLOTS];
+  std::vector<hipEvent_t> events;
+  double stage_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  // events bracketing each stage of the last single-stage call
+  int last_stage = -1;
+};
+
+namespace {
+
+constexpr int kStageMo = 0, kStageRpa = 1, kStageEigRpa = 2, kStageRes = 3, kStageSigma = 4,
+              kStageFock = 5, kStageEigFock = 6;
+
+int fail(qsgw_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, QSGW_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                       \
+  } while (0)
+
+#define CHECK(x)                \
+  do {                          \
+    int r_ = (x);               \
+    if (r_ < 0) return r_;      \
+  } while (0)
+
+template <class T>
+int ws_get(qsgw_ctx* c, int slot, size_t count, T** out) {
+  const size_t bytes = count * sizeof(T) > 0 ? count * sizeof(T) : 8;
+  Buffer& b = c->ws[slot];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, QSGW_ERR_ALLOC, "workspace allocation of %zu bytes failed (slot %d)", bytes,
+                  slot);
+    }
+    b.p = p;
+    b.bytes = bytes;
+  }
+  *out = static_cast<T*>(b.p);
+  return QSGW_OK;
+}
+
+inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+int launch_check(qsgw_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, QSGW_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return QSGW_OK;
+}
+
+// K-split plan: chunks of a multiple of 16, no empty split.
+struct SplitPlan {
+  int64_t kchunk, nz;
+};
+inline SplitPlan split_plan(int64_t K, int64_t want) {
+  if (want <= 1 || K <= 16) return {K, 1};
+  int64_t kchunk = (K + want - 1) / want;
+  kchunk = ((kchunk + 15) / 16) * 16;
+  return {kchunk, (K + kchunk - 1) / kchunk};
+}
+
+// Launch the FP64 GEMM engine.  TRI requires M == N.  `sp` is the K-split plan
+// (partial-sum buffers must hold sp.nz slices).
+template <int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
+int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
+         int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
+  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  const int64_t ntiles = TRI ? tm * (tm + 1) / 2 : tm * tn;
+  const int64_t kchunk = sp.nz > 1 ? sp.kchunk : K;
+  const int64_t splits = sp.nz > 1 ? sp.nz : 1;
+  if (ntiles <= 0 || batch <= 0 || K <= 0) return QSGW_OK;
+  if (batch > 65535 || splits > 65535 || ntiles > 0x7fffffffLL)
+    return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
+  dim3 grid((unsigned)ntiles, (unsigned)batch, (unsigned)splits);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT>), grid, dim3(256), 0,
+                     c->stream, a, b, e, M, N, K, kchunk, tm, tn, f);
+  return launch_check(c, what);
+}
+
+// Split count that gives roughly `target` workgroups for a tiny output.
+inline int64_t splits_for(int64_t tiles, int64_t K, int64_t target = 2048) {
+  int64_t s = (target + tiles - 1) / tiles;
+  const int64_t maxs = (K + 255) / 256;  // keep >= 256 k per split
+  if (s > maxs) s = maxs;
+  return s < 1 ? 1 : s;
+}
+
+// qsGW matrix: 64 x 64 tiles of the nbf x nbf output, K = nbf * ns.
+inline SplitPlan sigma_split(int64_t nbf, int64_t ns) {
+  const int64_t t = (nbf + 63) / 64;
+  return split_plan(nbf * ns, splits_for(t * t, nbf * ns));
+}
+
+// MO exchange: upper 64 x 64 tiles, K = naux * nocc.
+inline SplitPlan exchange_split(int64_t nbf, int64_t naux, int64_t nocc) {
+  const int64_t t = (nbf + 63) / 64;
+  return split_plan(naux * nocc, splits_for(t * (t + 1) / 2, naux * nocc));
+}
+
+int record(qsgw_ctx* c, size_t idx) {
+  while (c->events.size() <= idx) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  HIP_TRY(c, hipEventRecord(c->events[idx], c->stream));
+  return QSGW_OK;
+}
+
+double elapsed(qsgw_ctx* c, size_t a, size_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, c->events[a], c->events[b]) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.0;
+  }
+  return (double)ms;
+}
+
+// Timed spans on the context stream: each span is a pair of events; `id`
+// names a stage (0..6) or a kernel (kKernelBase + 0..7).
+constexpr int kKernelBase = 100;
+constexpr int kKMo1 = kKernelBase + 0, kKMo2 = kKernelBase + 1, kKCasida = kKernelBase + 2,
+              kKRho = kKernelBase + 3, kKW = kKernelBase + 4, kKSigma = kKernelBase + 5,
+              kKSigmaRed = kKernelBase + 6, kKFock = kKernelBase + 7;
+
+struct Spans {
+  qsgw_ctx* c = nullptr;
+  size_t next = 0;
+  struct Span {
+    int id;
+    size_t e0, e1;
+  };
+  std::vector<Span> v;
+  std::vector<size_t> open_stack;
+  int open(int id) {
+    if (!c) return QSGW_OK;
+    v.push_back({id, next, 0});
+    open_stack.push_back(v.size() - 1);
+    return record(c, next++);
+  }
+  int close() {
+    if (!c) return QSGW_OK;
+    v[open_stack.back()].e1 = next;
+    open_stack.pop_back();
+    return record(c, next++);
+  }
+};
+
+#define SPAN_OPEN(sp, id)              \
+  do {                                 \
+    if (sp) CHECK((sp)->open(id));     \
+  } while (0)
+#define SPAN_CLOSE(sp)                 \
+  do {                                 \
+    if (sp) CHECK((sp)->close());      \
+  } while (0)
+
+// ------------------------------------------------------------- stages ----
+
+// Eq. (16): T = B_ao C (one GEMM over all P), B_mo[P] = C^T T[P] (batched
+// over P, upper tiles only, mirrored).
+int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
+                       const double* C, double* T, double* B_mo, Spans* sp = nullptr) {
+  const int64_t nn = nbf * nbf;
+  {
+    Strided<true> A{B_ao, nbf, 1, 0, naux * nbf};
+    Strided<false> B{C, 1, nbf, 0, nbf};
+    EpiStore E{T, nbf, 0, 0, 1.0};
+    SPAN_OPEN(sp, kKMo1);
+    CHECK((gemm<128, 64, false>(c, "mo_transform/1", A, B, E, naux * nbf, nbf, nbf, 1)));
+    SPAN_CLOSE(sp);
+  }
+  {
+    Strided<false> A{C, 1, nbf, 0, nbf};
+    Strided<false> B{T, 1, nbf, nn, nbf};
+    EpiStore E{B_mo, nbf, nn, 0, 1.0};
+    SPAN_OPEN(sp, kKMo2);
+    CHECK((gemm<64, 64, true>(c, "mo_transform/2", A, B, E, nbf, nbf, nbf, naux)));
+    SPAN_CLOSE(sp);
+  }
+  return QSGW_OK;
+}
+
+// Eqs. (12)-(14): Delta, sqrt(Delta), Bt = B_ia sqrt(Delta), M = Delta^2 + 4 Bt^T Bt.
+int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                    const double* eps, double* M, double* sqrt_delta, double* delta, double* Bt,
+                    int* flags, Spans* sp = nullptr) {
+  const int64_t nv = nbf - nocc, ntr = nocc * nv;
+  SPAN_OPEN(sp, kKCasida);
+  hipLaunchKernelGGL(k_transitions, dim3(blocks_for(ntr)), dim3(256), 0, c->stream, eps, nocc, nv,
+                     delta, sqrt_delta, flags);
+  CHECK(launch_check(c, "k_transitions"));
+  hipLaunchKernelGGL(k_gather_bia, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, B_mo,
+                     sqrt_delta, naux, nbf, nocc, Bt);
+  CHECK(launch_check(c, "k_gather_bia"));
+  Strided<false> A{Bt, 1, ntr, 0, ntr};
+  EpiCasida E{M, delta, ntr};
+  CHECK((gemm<128, 128, true>(c, "rpa_build", A, A, E, ntr, ntr, naux, 1)));
+  SPAN_CLOSE(sp);
+  return QSGW_OK;
+}
+
+int read_flag(qsgw_ctx* c, int* dflag, int* out) {
+  HIP_TRY(c, hipMemcpyAsync(out, dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return QSGW_OK;
+}
+
+// rocSOLVER dsyevd, eigenvectors in place (column-major).
+int syevd(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what) {
+  if (n > 0x7fffffffLL) return fail(c, QSGW_ERR_UNSUPPORTED, "%s: n too large for rocSOLVER", what);
+  double* E = nullptr;
+  CHECK(ws_get(c, W_EIGE, (size_t)n, &E));
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  rocblas_status st = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_upper,
+                                       (rocblas_int)n, A, (rocblas_int)n, evals, E,
+                                       (rocblas_int*)(flags + 1));
+  if (st != rocblas_status_success)
+    return fail(c, QSGW_ERR_SOLVER, "%s: rocsolver_dsyevd status %d", what, (int)st);
+  int info = 0;
+  CHECK(read_flag(c, flags + 1, &info));
+  if (info != 0) return fail(c, QSGW_ERR_SOLVER, "%s: dsyevd info = %d", what, info);
+  return QSGW_OK;
+}
+
+int stage_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M, double* Omega) {
+  CHECK(syevd(c, ntr, M, Omega, "rpa_solve"));
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_omega_from_eigs, dim3(blocks_for(ntr)), dim3(256), 0, c->stream, Omega, ntr,
+                     Omega, flags);
+  CHECK(launch_check(c, "k_omega_from_eigs"));
+  int bad = 0;
+  CHECK(read_flag(c, flags, &bad));
+  if (bad) return fail(c, QSGW_ERR_SOLVER, "RPA instability: a Casida eigenvalue Omega^2 <= 0");
+  return QSGW_OK;
+}
+
+// Eq. (18) for excitations [s0, s0 + ns): rho' = sqrt(2/Omega) Bt Z^T, w = B_mo^T rho'.
+int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
+                   const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
+                   double* rho, double* w, Spans* sp = nullptr) {
+  {
+    Strided<true> A{Bt, ntr, 1, 0, naux};
+    Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
+    EpiRho E{rho, Omega + s0, ns};
+    SPAN_OPEN(sp, kKRho);
+    CHECK((gemm<128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1)));
+    SPAN_CLOSE(sp);
+  }
+  {
+    const int64_t nn = nbf * nbf;
+    Strided<false> A{B_mo, 1, nn, 0, nn};
+    Strided<false> B{rho, 1, ns, 0, ns};
+    EpiResidue E{w, nbf, ns};
+    SPAN_OPEN(sp, kKW);
+    CHECK((gemm<128, 128, false>(c, "residues/w", A, B, E, nn, ns, naux, 1, SplitPlan{0, 1},
+                                 UpperPairRows{nbf})));
+    SPAN_CLOSE(sp);
+  }
+  return QSGW_OK;
+}
+
+// Eq. (19) contribution of one excitation block: V (+)= 1/2 (G + G^T).
+int stage_sigma_qs(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
+                   const double* eps, const double* Omega, double eta, double* V, int accumulate,
+                   Spans* spn = nullptr) {
+  const SplitPlan sp = sigma_split(nbf, ns);
+  double* part = nullptr;
+  CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nbf * nbf), &part));
+  PoleScaledResidueOp A{w, eps, Omega, nbf, nocc, ns, eta};
+  Strided<true> B{w, nbf * ns, 1, 0, nbf};
+  EpiStore E{part, nbf, 0, nbf * nbf, 1.0};
+  SPAN_OPEN(spn, kKSigma);
+  CHECK((gemm<64, 64, false>(c, "sigma_qs", A, B, E, nbf, nbf, nbf * ns, 1, sp)));
+  SPAN_CLOSE(spn);
+  SPAN_OPEN(spn, kKSigmaRed);
+  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nbf * nbf)), dim3(256), 0, c->stream, part,
+                     sp.nz, nbf, V, accumulate);
+  CHECK(launch_check(c, "k_reduce_sym"));
+  SPAN_CLOSE(spn);
+  return QSGW_OK;
+}
+
+// Hartree and exchange in the MO basis of the orbitals that produced B_mo:
+// J = 2 sum_P c_P B^P, c_P = sum_i B^P_ii;  K = sum_P B^P_{:,occ} (B^P_{:,occ})^T.
+// Leaves J in W_J and the K partial sums in W_PART; returns their count.
+int stage_jk_mo(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                double** J, double** Kpart, int64_t* nz) {
+  const int64_t nn = nbf * nbf;
+  double* cp = nullptr;
+  CHECK(ws_get(c, W_CP, (size_t)naux, &cp));
+  CHECK(ws_get(c, W_J, (size_t)nn, J));
+  hipLaunchKernelGGL(k_occ_trace, dim3(blocks_for(naux)), dim3(256), 0, c->stream, B_mo, naux, nbf,
+                     nocc, cp);
+  CHECK(launch_check(c, "k_occ_trace"));
+  hipLaunchKernelGGL(k_hartree_mo, dim3(blocks_for(nn)), dim3(256), 0, c->stream, B_mo, cp, naux,
+                     nn, *J);
+  CHECK(launch_check(c, "k_hartree_mo"));
+  const SplitPlan sp = exchange_split(nbf, naux, nocc);
+  CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nn), Kpart));
+  OccRowsOp A{B_mo, nbf, nocc};
+  EpiStore E{*Kpart, nbf, 0, nn, 1.0};
+  CHECK((gemm<64, 64, true>(c, "exchange_mo", A, A, E, nbf, nbf, naux * nocc, 1, sp)));
+  *nz = sp.nz;
+  return QSGW_OK;
+}
+
+// out = X^T Y X for square n x n matrices (row-major):  tmp = Y X, out = X^T tmp.
+int congruence_t(qsgw_ctx* c, int64_t n, const double* X, const double* Y, double* tmp,
+                 double* out) {
+  {
+    Strided<true> A{Y, n, 1, 0, n};
+    Strided<false> B{X, 1, n, 0, n};
+    EpiStore E{tmp, n, 0, 0, 1.0};
+    CHECK((gemm<64, 64, false>(c, "congruence/1", A, B, E, n, n, n, 1)));
+  }
+  {
+    Strided<false> A{X, 1, n, 0, n};
+    Strided<false> B{tmp, 1, n, 0, n};
+    EpiStore E{out, n, 0, 0, 1.0};
+    CHECK((gemm<64, 64, false>(c, "congruence/2", A, B, E, n, n, n, 1)));
+  }
+  return QSGW_OK;
+}
+
+// out = X Y X^T:  tmp = X Y, out = tmp X^T.
+int congruence(qsgw_ctx* c, int64_t n, const double* X, const double* Y, double* tmp,
+               double* out) {
+  {
+    Strided<true> A{X, n, 1, 0, n};
+    Strided<false> B{Y, 1, n, 0, n};
+    EpiStore E{tmp, n, 0, 0, 1.0};
+    CHECK((gemm<64, 64, false>(c, "congruence/3", A, B, E, n, n, n, 1)));
+  }
+  {
+    Strided<true> A{tmp, n, 1, 0, n};
+    Strided<true> B{X, n, 1, 0, n};
+    EpiStore E{out, n, 0, 0, 1.0};
+    CHECK((gemm<64, 64, false>(c, "congruence/4", A, B, E, n, n, n, 1)));
+  }
+  return QSGW_OK;
+}
+
+int check_common(qsgw_ctx* c, int64_t nbf, int64_t naux) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  if (nbf < 1 || naux < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need nbf >= 1 and naux >= 1");
+  if (nbf > 46340) return fail(c, QSGW_ERR_INVALID_ARG, "nbf too large");
+  return QSGW_OK;
+}
+
+int check_prec(qsgw_ctx* c, int precision) {
+  if (precision == QSGW_PREC_FP64) return QSGW_OK;
+  if (precision == QSGW_PREC_FP32 || precision == QSGW_PREC_SPLIT_BF16)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "precision %d is not available in this version",
+                precision);
+  return fail(c, QSGW_ERR_INVALID_ARG, "unknown precision %d", precision);
+}
+
+int single_begin(qsgw_ctx* c, int stage) {
+  c->last_stage = stage;
+  return record(c, 0);
+}
+int single_end(qsgw_ctx* c) { return record(c, 1); }
+
+}  // namespace
+
+// ================================================================ C-ABI ====
+extern "C" {
+
+int qsgw_version(void) { return QSGW_VERSION; }
+
+int qsgw_ctx_create(qsgw_ctx** out, void* hip_stream) {
+  if (!out) return QSGW_ERR_INVALID_ARG;
+  *out = nullptr;
+  qsgw_ctx* c = new (std::nothrow) qsgw_ctx();
+  if (!c) return QSGW_ERR_ALLOC;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return QSGW_ERR_HIP;
+  }
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    delete c;
+    return QSGW_ERR_SOLVER;
+  }
+  if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success) {
+    rocblas_destroy_handle(c->blas);
+    delete c;
+    return QSGW_ERR_SOLVER;
+  }
+  *out = c;
+  return QSGW_OK;
+}
+
+int qsgw_ctx_destroy(qsgw_ctx* c) {
+  if (!c) return QSGW_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->ws)
+    if (b.p) (void)hipFree(b.p);
+  for (auto e : c->events) (void)hipEventDestroy(e);
+  if (c->blas) rocblas_destroy_handle(c->blas);
+  delete c;
+  return QSGW_OK;
+}
+
+const char* qsgw_last_error(const qsgw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int qsgw_last_stage_ms(const qsgw_ctx* c0, double* ms, int n) {
+  qsgw_ctx* c = const_cast<qsgw_ctx*>(c0);
+  if (!c || !ms || n < 0) return QSGW_ERR_INVALID_ARG;
+  if (c->last_stage >= 0 && c->events.size() >= 2) {
+    HIP_TRY(c, hipEventSynchronize(c->events[1]));
+    for (int i = 0; i < 7; ++i) c->stage_ms[i] = 0.0;
+    c->stage_ms[c->last_stage] = elapsed(c, 0, 1);
+  }
+  for (int i = 0; i < n && i < 7; ++i) ms[i] = c->stage_ms[i];
+  return QSGW_OK;
+}
+
+int qsgw_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao, const double* C,
+                      double* B_mo, int precision) {
+  CHECK(check_common(c, nbf, naux));
+  CHECK(check_prec(c, precision));
+  if (!B_ao || !C || !B_mo) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  double* T = nullptr;
+  CHECK(ws_get(c, W_T, (size_t)(naux * nbf * nbf), &T));
+  CHECK(single_begin(c, kStageMo));
+  CHECK(stage_mo_transform(c, nbf, naux, B_ao, C, T, B_mo));
+  return single_end(c);
+}
+
+int qsgw_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                   const double* eps, double* M, double* sqrt_delta, int precision) {
+  CHECK(check_common(c, nbf, naux));
+  CHECK(check_prec(c, precision));
+  if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
+  if (!B_mo || !eps || !M || !sqrt_delta) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  const int64_t ntr = nocc * (nbf - nocc);
+  double *delta = nullptr, *Bt = nullptr;
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_DELTA, (size_t)ntr, &delta));
+  CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+  CHECK(single_begin(c, kStageRpa));
+  CHECK(stage_rpa_build(c, nbf, naux, nocc, B_mo, eps, M, sqrt_delta, delta, Bt, flags));
+  CHECK(single_end(c));
+  int bad = 0;
+  CHECK(read_flag(c, flags, &bad));
+  if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "eps[a] - eps[i] must be > 0 for every transition");
+  return QSGW_OK;
+}
+
+int qsgw_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M_to_Z, double* Omega) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  if (ntr < 1 || !M_to_Z || !Omega) return fail(c, QSGW_ERR_INVALID_ARG, "bad arguments");
+  CHECK(single_begin(c, kStageEigRpa));
+  CHECK(stage_rpa_solve(c, ntr, M_to_Z, Omega));
+  return single_end(c);
+}
+
+int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                  const double* sqrt_delta, const double* Z, const double* Omega, int64_t s_begin,
+                  int64_t s_count, double* w, int precision) {
+  CHECK(check_common(c, nbf, naux));
+  CHECK(check_prec(c, precision));
+  if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
+  const int64_t ntr = nocc * (nbf - nocc);
+  if (s_begin < 0 || s_count < 1 || s_begin + s_count > ntr)
+    return fail(c, QSGW_ERR_INVALID_ARG, "excitation range [%lld, %lld) outside [0, %lld)",
+                (long long)s_begin, (long long)(s_begin + s_count), (long long)ntr);
+  if (!B_mo || !sqrt_delta || !Z || !Omega || !w)
+    return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  double *Bt = nullptr, *rho = nullptr;
+  CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
+  CHECK(ws_get(c, W_RHO, (size_t)(naux * s_count), &rho));
+  CHECK(single_begin(c, kStageRes));
+  hipLaunchKernelGGL(k_gather_bia, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, B_mo,
+                     sqrt_delta, naux, nbf, nocc, Bt);
+  CHECK(launch_check(c, "k_gather_bia"));
+  CHECK(stage_residues(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s_begin, s_count, rho, w));
+  return single_end(c);
+}
+
+int qsgw_sigma(qsgw_ctx* c, int mode, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
+               const double* eps, const double* Omega, double eta, const double* omega,
+               int64_t nomega, const int64_t* states, int64_t nstates, double* out,
+               int accumulate) {
+  CHECK(check_common(c, nbf, 1));
+  if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
+  if (ns < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need ns >= 1");
+  if (!(eta > 0.0) || !isfinite(eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need finite eta > 0");
+  if (!w || !eps || !Omega || !out) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  if (mode == QSGW_SIGMA_QS_MATRIX) {
+    CHECK(single_begin(c, kStageSigma));
+    CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega, eta, out, accumulate ? 1 : 0));
+    return single_end(c);
+  }
+  if (mode != QSGW_SIGMA_DIAG_GRID) return fail(c, QSGW_ERR_INVALID_ARG, "unknown mode %d", mode);
+  if (nomega < 1 || nstates < 1 || !omega || !states)
+    return fail(c, QSGW_ERR_INVALID_ARG, "diagonal grid needs nomega, nstates >= 1");
+  if (nstates > 0x7fffffffLL || (nomega + 7) / 8 > 65535)
+    return fail(c, QSGW_ERR_INVALID_ARG, "grid too large");
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+  CHECK(single_begin(c, kStageSigma));
+  hipLaunchKernelGGL(k_sigma_diag_grid, dim3((unsigned)nstates, (unsigned)((nomega + 7) / 8)),
+                     dim3(256), 0, c->stream, w, eps, Omega, nbf, nocc, ns, eta, omega, nomega,
+                     states, nstates, out, accumulate ? 1 : 0, flags);
+  CHECK(launch_check(c, "k_sigma_diag_grid"));
+  CHECK(single_end(c));
+  int bad = 0;
+  CHECK(read_flag(c, flags, &bad));
+  if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "a state index is outside [0, nbf)");
+  return QSGW_OK;
+}
+
+int qsgw_hf_core(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_ao,
+                 const double* C0, const double* eps0, double* h) {
+  CHECK(check_common(c, nbf, naux));
+  if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
+  if (!B_ao || !C0 || !eps0 || !h) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  const int64_t nn = nbf * nbf;
+  double *T = nullptr, *Bmo = nullptr, *X = nullptr, *tmp = nullptr, *tmp2 = nullptr;
+  CHECK(ws_get(c, W_T, (size_t)(naux * nn), &T));
+  CHECK(ws_get(c, W_BMO, (size_t)(naux * nn), &Bmo));
+  CHECK(ws_get(c, W_TMP, (size_t)nn, &X));
+  CHECK(ws_get(c, W_TMP2, (size_t)nn, &tmp));
+  CHECK(ws_get(c, W_HMO, (size_t)nn, &tmp2));
+  CHECK(stage_mo_transform(c, nbf, naux, B_ao, C0, T, Bmo));
+  double *J = nullptr, *Kpart = nullptr;
+  int64_t nz = 0;
+  CHECK(stage_jk_mo(c, nbf, naux, nocc, Bmo, &J, &Kpart, &nz));
+  hipLaunchKernelGGL(k_hf_core_mo, dim3(blocks_for(nn)), dim3(256), 0, c->stream, eps0, J, Kpart,
+                     nz, nbf, X);
+  CHECK(launch_check(c, "k_hf_core_mo"));
+  CHECK(congruence(c, nbf, C0, X, tmp, tmp2));
+  hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(nn)), dim3(256), 0, c->stream, tmp2, nbf, h);
+  return launch_check(c, "k_symmetrize");
+}
+
+int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_options* o,
+                 qsgw_report* rep) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  if (!p || !st || !o) return fail(c, QSGW_ERR_INVALID_ARG, "null argument struct");
+  const int64_t nbf = p->nbf, naux = p->naux, nocc = p->nocc;
+  CHECK(check_common(c, nbf, naux));
+  CHECK(check_prec(c, o->precision));
+  if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
+  if (!p->B_ao || !p->h || !st->eps || !st->C)
+    return fail(c, QSGW_ERR_INVALID_ARG, "null problem/state pointer");
+  if (!(o->eta > 0.0) || !isfinite(o->eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need eta > 0");
+  if (o->max_iter < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need max_iter >= 1");
+  if (!(o->mix > 0.0 && o->mix <= 1.0)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < mix <= 1");
+  if (o->mix != 1.0 && !st->Vc)
+    return fail(c, QSGW_ERR_INVALID_ARG, "mixing needs a Vc buffer in the state");
+  if (o->fock_mode != QSGW_FOCK_FULL_JK)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "fock_mode %d is not available", o->fock_mode);
+  if (o->s_block < 0) return fail(c, QSGW_ERR_INVALID_ARG, "need s_block >= 0");
+
+  const int64_t nv = nbf - nocc, ntr = nocc * nv, nn = nbf * nbf;
+  int64_t sb = o->s_block;
+  if (sb == 0) {
+    // stream residues in blocks of at most ~8 GiB of w
+    const int64_t cap = (int64_t)((8ull << 30) / (sizeof(double) * (uint64_t)nn));
+    sb = ntr < cap ? ntr : (cap < 64 ? 64 : cap);
+  }
+  if (sb > ntr) sb = ntr;
+
+  double *T, *Bmo, *Bt, *delta, *sqd, *M, *Omega, *rho, *w, *V, *hmo, *F, *tmp, *tmp2, *epsn, *Cn,
+      *scal;
+  int* flags;
+  CHECK(ws_get(c, W_T, (size_t)(naux * nn), &T));
+  CHECK(ws_get(c, W_BMO, (size_t)(naux * nn), &Bmo));
+  CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
+  CHECK(ws_get(c, W_DELTA, (size_t)ntr, &delta));
+  CHECK(ws_get(c, W_SQD, (size_t)ntr, &sqd));
+  CHECK(ws_get(c, W_M, (size_t)(ntr * ntr), &M));
+  CHECK(ws_get(c, W_OMEGA, (size_t)ntr, &Omega));
+  CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
+  CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
+  CHECK(ws_get(c, W_V, (size_t)nn, &V));
+  CHECK(ws_get(c, W_HMO, (size_t)nn, &hmo));
+  CHECK(ws_get(c, W_F, (size_t)nn, &F));
+  CHECK(ws_get(c, W_TMP, (size_t)nn, &tmp));
+  CHECK(ws_get(c, W_TMP2, (size_t)nn, &tmp2));
+  CHECK(ws_get(c, W_EPSN, (size_t)nbf, &epsn));
+  CHECK(ws_get(c, W_CNEW, (size_t)nn, &Cn));
+  CHECK(ws_get(c, W_SCAL, 8, &scal));
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  // The partial-sum slot is sized by its largest user before any pointer into it is taken.
+  {
+    double* part = nullptr;
+    int64_t nz = exchange_split(nbf, naux, nocc).nz;
+    for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
+      const int64_t z = sigma_split(nbf, (ntr - s0) < sb ? (ntr - s0) : sb).nz;
+      nz = z > nz ? z : nz;
+    }
+    CHECK(ws_get(c, W_PART, (size_t)(nz * nn), &part));
+    double* dummy = nullptr;
+    CHECK(ws_get(c, W_J, (size_t)nn, &dummy));
+    CHECK(ws_get(c, W_CP, (size_t)naux, &dummy));
+    CHECK(ws_get(c, W_EIGE, (size_t)(ntr > nbf ? ntr : nbf), &dummy));
+  }
+
+  // Finite inputs (one pass over each input array).
+  HIP_TRY(c, hipMemsetAsync(flags, 0, 8 * sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_check_finite, dim3(2048), dim3(256), 0, c->stream, p->B_ao, naux * nn, flags);
+  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, p->h, nn, flags);
+  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, st->C, nn, flags);
+  hipLaunchKernelGGL(k_check_finite, dim3(1), dim3(256), 0, c->stream, st->eps, nbf, flags);
+  CHECK(launch_check(c, "k_check_finite"));
+  {
+    int bad = 0;
+    CHECK(read_flag(c, flags, &bad));
+    if (bad) return fail(c, QSGW_ERR_NONFINITE, "non-finite value in B_ao, h, C or eps");
+  }
+
+  qsgw_report local;
+  memset(&local, 0, sizeof(local));
+  {
+    const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
+    local.hot_flops = 4.0 * b * b * b * a            // Eq. (16)
+                      + t * (t + 1.0) * a            // Casida build (symmetric)
+                      + 2.0 * a * t * t              // rho
+                      + b * (b + 1.0) * a * t        // residues (symmetric in m, k)
+                      + 2.0 * b * b * b * t          // qsGW matrix
+                      + b * (b + 1.0) * a * oc       // exchange (symmetric)
+                      + 2.0 * a * b * b              // Hartree
+                      + 8.0 * b * b * b;             // C^T h C, C V C^T, C U
+  }
+  {
+    const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
+    local.kernel_flops[kKMo1 - kKernelBase] = 2.0 * b * b * b * a;
+    local.kernel_flops[kKMo2 - kKernelBase] = 2.0 * b * b * b * a;
+    local.kernel_flops[kKCasida - kKernelBase] = t * (t + 1.0) * a;
+    local.kernel_flops[kKRho - kKernelBase] = 2.0 * a * t * t;
+    local.kernel_flops[kKW - kKernelBase] = b * (b + 1.0) * a * t;
+    local.kernel_flops[kKSigma - kKernelBase] = 2.0 * b * b * b * t;
+    local.kernel_flops[kKSigmaRed - kKernelBase] = 0.0;
+    local.kernel_flops[kKFock - kKernelBase] = b * (b + 1.0) * a * oc + 2.0 * a * b * b + 8.0 * b * b * b;
+  }
+  int status = QSGW_NOT_CONVERGED;
+  for (int64_t it = 0; it < o->max_iter; ++it) {
+    const double* eps = st->eps;
+    const double* C = st->C;
+    Spans sp;
+    sp.c = c;
+    CHECK(sp.open(kStageMo));
+    CHECK(stage_mo_transform(c, nbf, naux, p->B_ao, C, T, Bmo, &sp));
+    CHECK(sp.close());
+    HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+    CHECK(sp.open(kStageRpa));
+    CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, M, sqd, delta, Bt, flags, &sp));
+    CHECK(sp.close());
+    {
+      int bad = 0;
+      CHECK(read_flag(c, flags, &bad));
+      if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "orbital energies are not in aufbau order");
+    }
+    CHECK(sp.open(kStageEigRpa));
+    CHECK(stage_rpa_solve(c, ntr, M, Omega));
+    CHECK(sp.close());
+    for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
+      const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
+      CHECK(sp.open(kStageRes));
+      CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp));
+      CHECK(sp.close());
+      CHECK(sp.open(kStageSigma));
+      CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp));
+      CHECK(sp.close());
+    }
+    CHECK(sp.open(kStageFock));
+    CHECK(sp.open(kKFock));
+    // correlation potential in the AO basis (output and mixing)
+    if (st->Vc) {
+      CHECK(congruence(c, nbf, C, V, tmp, tmp2));
+      if (o->mix != 1.0 && st->iteration > 0) {
+        hipLaunchKernelGGL(k_axpby, dim3(blocks_for(nn)), dim3(256), 0, c->stream, tmp2, st->Vc,
+                           o->mix, 1.0 - o->mix, nn, tmp2);
+        CHECK(launch_check(c, "k_axpby"));
+        hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(nn)), dim3(256), 0, c->stream, tmp2, nbf,
+                           st->Vc);
+        CHECK(launch_check(c, "k_symmetrize"));
+        // back to the MO basis of the current orbitals for the Fock build
+        CHECK(congruence_t(c, nbf, C, st->Vc, tmp, tmp2));
+        hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(nn)), dim3(256), 0, c->stream, tmp2, nbf,
+                           V);
+        CHECK(launch_check(c, "k_symmetrize"));
+      } else {
+        hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(nn)), dim3(256), 0, c->stream, tmp2, nbf,
+                           st->Vc);
+        CHECK(launch_check(c, "k_symmetrize"));
+      }
+    }
+    // Eq. (6) in the MO basis of the current orbitals: C^T h C + J - K + V
+    CHECK(congruence_t(c, nbf, C, p->h, tmp, hmo));
+    double *J = nullptr, *Kpart = nullptr;
+    int64_t nz = 0;
+    CHECK(stage_jk_mo(c, nbf, naux, nocc, Bmo, &J, &Kpart, &nz));
+    hipLaunchKernelGGL(k_fock_assemble, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hmo, J, Kpart,
+                       nz, V, nbf, F);
+    CHECK(launch_check(c, "k_fock_assemble"));
+    CHECK(sp.close());
+    CHECK(sp.close());
+    CHECK(sp.open(kStageEigFock));
+    CHECK(syevd(c, nbf, F, epsn, "eig_fock"));
+    CHECK(sp.close());
+    // C' = C U (U column-major in F), sign convention, max |d eps|
+    {
+      Strided<true> A{C, nbf, 1, 0, nbf};
+      Strided<true> B{F, nbf, 1, 0, nbf};
+      EpiStore E{Cn, nbf, 0, 0, 1.0};
+      CHECK((gemm<64, 64, false>(c, "rotate_orbitals", A, B, E, nbf, nbf, nbf, 1)));
+    }
+    hipLaunchKernelGGL(k_fix_column_signs, dim3(blocks_for(nbf)), dim3(256), 0, c->stream, Cn, nbf);
+    hipLaunchKernelGGL(k_max_abs_diff, dim3(1), dim3(256), 0, c->stream, epsn, st->eps, nbf, scal);
+    CHECK(launch_check(c, "k_max_abs_diff"));
+    HIP_TRY(c, hipMemcpyAsync(st->eps, epsn, nbf * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st->C, Cn, nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    double dmax = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&dmax, scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+
+    for (const auto& span : sp.v) {
+      const double ms = elapsed(c, span.e0, span.e1);
+      if (span.id >= kKernelBase) {
+        local.ms_kernel[span.id - kKernelBase] += ms;
+        local.kernel_launches[span.id - kKernelBase] += 1;
+      } else {
+        local.ms_stage[span.id] += ms;
+      }
+    }
+
+    if (local.iterations < QSGW_REPORT_MAX_ITERS) local.max_deps[local.iterations] = dmax;
+    local.iterations++;
+    st->iteration++;
+    if (!isfinite(dmax)) {
+      if (rep) *rep = local;
+      return fail(c, QSGW_ERR_NONFINITE, "non-finite orbital energies after iteration %lld",
+                  (long long)st->iteration);
+    }
+    if (dmax < o->tol) {
+      status = QSGW_OK;
+      local.converged = 1;
+      break;
+    }
+  }
+  for (int i = 0; i < 7; ++i) c->stage_ms[i] = local.ms_stage[i];
+  c->last_stage = -1;
+  if (rep) *rep = local;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+"""ctypes binding of libqsgw (include/qsgw.h).
+
+Argument marshalling only: every function checks that its torch tensors are
+HIP-device, float64 (int64 for state lists), contiguous and of the expected
+shape, then passes raw device pointers and the context's stream to the C-ABI
+entry point of the same name.  No arithmetic of the method happens here.  If
+the compiled library is missing the import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsgw.so")
+
+OK = 0
+NOT_CONVERGED = 1
+ERR_INVALID_ARG = -1
+ERR_NONFINITE = -2
+ERR_HIP = -3
+ERR_SOLVER = -4
+ERR_ALLOC = -5
+ERR_UNSUPPORTED = -6
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_SPLIT_BF16 = 2
+
+SIGMA_QS_MATRIX = 0
+SIGMA_DIAG_GRID = 1
+
+FOCK_FULL_JK = 0
+REPORT_MAX_ITERS = 64
+STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "eig_fock")
+
+EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
+           "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
+           "qsgw_residues", "qsgw_sigma", "qsgw_hf_core", "qsgw_iterate")
+
+
+class QsgwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libqsgw error {code}: {msg}")
+        self.code = code
+
+
+class Problem(ct.Structure):
+    _fields_ = [("nbf", ct.c_int64), ("naux", ct.c_int64), ("nocc", ct.c_int64),
+                ("B_ao", ct.c_void_p), ("h", ct.c_void_p)]
+
+
+class State(ct.Structure):
+    _fields_ = [("eps", ct.c_void_p), ("C", ct.c_void_p), ("Vc", ct.c_void_p),
+                ("iteration", ct.c_int64)]
+
+
+class Options(ct.Structure):
+    _fields_ = [("precision", ct.c_int), ("eta", ct.c_double), ("tol", ct.c_double),
+                ("max_iter", ct.c_int64), ("mix", ct.c_double), ("fock_mode", ct.c_int),
+                ("s_block", ct.c_int64)]
+
+
+KERNELS = ("mo_transform_1", "mo_transform_2", "casida", "residue_rho", "residue_w",
+           "sigma_qs_gemm", "sigma_qs_reduce", "fock")
+
+
+class Report(ct.Structure):
+    _fields_ = [("iterations", ct.c_int64), ("converged", ct.c_int),
+                ("max_deps", ct.c_double * REPORT_MAX_ITERS), ("ms_stage", ct.c_double * 7),
+                ("hot_flops", ct.c_double), ("ms_kernel", ct.c_double * 8),
+                ("kernel_flops", ct.c_double * 8), ("kernel_launches", ct.c_int64 * 8)]
+
+    def as_dict(self):
+        n = min(self.iterations, REPORT_MAX_ITERS)
+        return dict(iterations=int(self.iterations), converged=bool(self.converged),
+                    max_deps=[self.max_deps[i] for i in range(n)],
+                    ms=dict(zip(STAGES, list(self.ms_stage))), hot_flops=self.hot_flops,
+                    kernel_ms=dict(zip(KERNELS, list(self.ms_kernel))),
+                    kernel_flops=dict(zip(KERNELS, list(self.kernel_flops))),
+                    kernel_launches=dict(zip(KERNELS, [int(x) for x in self.kernel_launches])))
+
+
+def load_library(path: str = LIB_PATH) -> ct.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2210_17093_amd.build`")
+    lib = ct.CDLL(path)
+    P, I64, D, I = ct.c_void_p, ct.c_int64, ct.c_double, ct.c_int
+    sig = {
+        "qsgw_version": ([], I),
+        "qsgw_ctx_create": ([ct.POINTER(P), P], I),
+        "qsgw_ctx_destroy": ([P], I),
+        "qsgw_last_error": ([P], ct.c_char_p),
+        "qsgw_last_stage_ms": ([P, ct.POINTER(D), I], I),
+        "qsgw_mo_transform": ([P, I64, I64, P, P, P, I], I),
+        "qsgw_rpa_build": ([P, I64, I64, I64, P, P, P, P, I], I),
+        "qsgw_rpa_solve": ([P, I64, P, P], I),
+        "qsgw_residues": ([P, I64, I64, I64, P, P, P, P, I64, I64, P, I], I),
+        "qsgw_sigma": ([P, I, I64, I64, I64, P, P, P, D, P, I64, P, I64, P, I], I),
+        "qsgw_hf_core": ([P, I64, I64, I64, P, P, P, P], I),
+        "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
+                          ct.POINTER(Report)], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = load_library()
+
+
+def lib() -> ct.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _ptr(t: torch.Tensor, shape, dtype=torch.float64, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ct.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libqsgw context bound to a torch HIP stream (the current one by default)."""
+
+    def __init__(self, stream: torch.cuda.Stream | None = None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ct.c_void_p()
+        rc = lib().qsgw_ctx_create(ct.byref(h), ct.c_void_p(self.stream.cuda_stream))
+        if rc != OK:
+            raise QsgwError(rc, "qsgw_ctx_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qsgw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def check(self, rc, allow=(OK,)):
+        if rc in allow:
+            return rc
+        msg = lib().qsgw_last_error(self.handle)
+        raise QsgwError(rc, msg.decode() if msg else "")
+
+    def last_stage_ms(self):
+        buf = (ct.c_double * 7)()
+        self.check(lib().qsgw_last_stage_ms(self.handle, buf, 7))
+        return dict(zip(STAGES, list(buf)))
+
+
+def qsgw_version() -> int:
+    return lib().qsgw_version()
+
+
+def qsgw_mo_transform(ctx: Context, B_ao, C, B_mo=None, precision=PREC_FP64):
+    naux, nbf, _ = B_ao.shape
+    if B_mo is None:
+        B_mo = torch.empty_like(B_ao)
+    ctx.check(lib().qsgw_mo_transform(ctx.handle, nbf, naux, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
+                                      _ptr(C, (nbf, nbf), name="C"),
+                                      _ptr(B_mo, (naux, nbf, nbf), name="B_mo"), precision))
+    return B_mo
+
+
+def qsgw_rpa_build(ctx: Context, B_mo, eps, nocc, M=None, sqrt_delta=None, precision=PREC_FP64):
+    naux, nbf, _ = B_mo.shape
+    ntr = nocc * (nbf - nocc)
+    if M is None:
+        M = torch.empty((ntr, ntr), dtype=torch.float64, device=B_mo.device)
+    if sqrt_delta is None:
+        sqrt_delta = torch.empty(ntr, dtype=torch.float64, device=B_mo.device)
+    ctx.check(lib().qsgw_rpa_build(ctx.handle, nbf, naux, nocc,
+                                   _ptr(B_mo, (naux, nbf, nbf), name="B_mo"),
+                                   _ptr(eps, (nbf,), name="eps"), _ptr(M, (ntr, ntr), name="M"),
+                                   _ptr(sqrt_delta, (ntr,), name="sqrt_delta"), precision))
+    return M, sqrt_delta
+
+
+def qsgw_rpa_solve(ctx: Context, M_to_Z, Omega=None):
+    ntr = M_to_Z.shape[0]
+    if Omega is None:
+        Omega = torch.empty(ntr, dtype=torch.float64, device=M_to_Z.device)
+    ctx.check(lib().qsgw_rpa_solve(ctx.handle, ntr, _ptr(M_to_Z, (ntr, ntr), name="M"),
+                                   _ptr(Omega, (ntr,), name="Omega")))
+    return M_to_Z, Omega
+
+
+def qsgw_residues(ctx: Context, B_mo, sqrt_delta, Z, Omega, nocc, s_begin=0, s_count=None,
+                  w=None, precision=PREC_FP64):
+    naux, nbf, _ = B_mo.shape
+    ntr = nocc * (nbf - nocc)
+    if s_count is None:
+        s_count = ntr - s_begin
+    if w is None:
+        w = torch.empty((nbf, nbf, s_count), dtype=torch.float64, device=B_mo.device)
+    ctx.check(lib().qsgw_residues(ctx.handle, nbf, naux, nocc,
+                                  _ptr(B_mo, (naux, nbf, nbf), name="B_mo"),
+                                  _ptr(sqrt_delta, (ntr,), name="sqrt_delta"),
+                                  _ptr(Z, (ntr, ntr), name="Z"), _ptr(Omega, (ntr,), name="Omega"),
+                                  s_begin, s_count, _ptr(w, (nbf, nbf, s_count), name="w"),
+                                  precision))
+    return w
+
+
+def qsgw_sigma_qs(ctx: Context, w, eps, Omega_block, nocc, eta, out=None, accumulate=False):
+    nbf, _, ns = w.shape
+    if out is None:
+        out = torch.empty((nbf, nbf), dtype=torch.float64, device=w.device)
+    ctx.check(lib().qsgw_sigma(ctx.handle, SIGMA_QS_MATRIX, nbf, nocc, ns,
+                               _ptr(w, (nbf, nbf, ns), name="w"), _ptr(eps, (nbf,), name="eps"),
+                               _ptr(Omega_block, (ns,), name="Omega"), float(eta), None, 0, None, 0,
+                               _ptr(out, (nbf, nbf), name="out"), int(bool(accumulate))))
+    return out
+
+
+def qsgw_sigma_diag(ctx: Context, w, eps, Omega_block, nocc, eta, omega, states, out=None,
+                    accumulate=False):
+    """Returns complex128 [nstates][nomega] (a view of the interleaved float64 buffer)."""
+    nbf, _, ns = w.shape
+    nomega, nstates = omega.shape[0], states.shape[0]
+    if out is None:
+        out = torch.empty((nstates, nomega, 2), dtype=torch.float64, device=w.device)
+    ctx.check(lib().qsgw_sigma(ctx.handle, SIGMA_DIAG_GRID, nbf, nocc, ns,
+                               _ptr(w, (nbf, nbf, ns), name="w"), _ptr(eps, (nbf,), name="eps"),
+                               _ptr(Omega_block, (ns,), name="Omega"), float(eta),
+                               _ptr(omega, (nomega,), name="omega"), nomega,
+                               _ptr(states, (nstates,), torch.int64, name="states"), nstates,
+                               _ptr(out, (nstates, nomega, 2), name="out"), int(bool(accumulate))))
+    return torch.view_as_complex(out)
+
+
+def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
+    naux, nbf, _ = B_ao.shape
+    if h is None:
+        h = torch.empty((nbf, nbf), dtype=torch.float64, device=B_ao.device)
+    ctx.check(lib().qsgw_hf_core(ctx.handle, nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
+                                 _ptr(C0, (nbf, nbf), name="C0"), _ptr(eps0, (nbf,), name="eps0"),
+                                 _ptr(h, (nbf, nbf), name="h")))
+    return h
+
+
+def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
+                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64):
+    """Runs qsGW iterations in place on (eps, C).  Returns (status, report dict, iteration)."""
+    naux, nbf, _ = B_ao.shape
+    prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
+                   _ptr(h, (nbf, nbf), name="h"))
+    st = State(_ptr(eps, (nbf,), name="eps"), _ptr(C, (nbf, nbf), name="C"),
+               _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration)
+    opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
+                  int(s_block))
+    rep = Report()
+    rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
+                                      ct.byref(rep)), allow=(OK, NOT_CONVERGED))
+    return rc, rep.as_dict(), int(st.iteration)
