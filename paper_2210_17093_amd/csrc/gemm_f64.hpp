@@ -20,7 +20,8 @@
 // MFMA f64 16x16x4 lane layout (wave64):
 //   A fragment: lane l holds A[l % 16][l / 16]      (16 rows x 4 k)
 //   B fragment: lane l holds B[l / 16][l % 16]      (4 k x 16 cols)
-//   D:          lane l, element j holds D[4 (l / 16) + j][l % 16]
+//   D:          lane l, element q holds D[4 q + l / 16][l % 16]  (rows interleaved
+//               across the four lane groups; measured on gfx950)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(OA A, OB B, EPI epi, int6
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t m = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+        const int64_t m = m0 + wm + i * 16 + 4 * q + (lane >> 4);
         const int64_t n = n0 + wn + j * 16 + (lane & 15);
         if (m < M && n < N) {
           if (TRI) {
