@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter "
+                         "calibration: 1 GiB read + 1 GiB written per copy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -98,6 +101,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 8, "copies": 4}), flush=True)
+        return
     import paper_2210_17093_amd.qsgw as q
     from qsgw_inputs import CONFIGS, make_config
 

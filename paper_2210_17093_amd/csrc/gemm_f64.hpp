@@ -32,9 +32,13 @@ namespace qsgw {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Element (r, k) at p[b*sb + r*sr + k*sk]; rows >= `rows` or k >= K read 0.
+// Strided operands take the branch-free tile loader of the kernel: one base
+// pointer per thread, a uniform stride between the thread's elements, and on
+// edge tiles loads from a clamped (always valid) address followed by a select.
 template <bool KC>
 struct Strided {
   static constexpr bool kContig = KC;
+  static constexpr bool kStrided = true;
   const double* p;
   int64_t sr, sk, sb;
   int64_t rows;
@@ -42,6 +46,66 @@ struct Strided {
     return r < rows ? p[b * sb + r * sr + k * sk] : 0.0;
   }
 };
+
+// Operands without the fast path (index arithmetic per element) leave
+// kStrided false.
+template <class OP, class = void>
+struct is_strided_op {
+  static constexpr bool value = false;
+};
+template <class OP>
+struct is_strided_op<OP, decltype((void)OP::kStrided, void())> {
+  static constexpr bool value = OP::kStrided;
+};
+
+// Load this thread's E = BR*BK/256 elements of a BR x BK operand tile
+// (rows r0.., k = kbase..) into v[].  Element e of thread tid sits at
+//   k-contiguous operand:  r = e*(256/BK) + tid/BK,  kk = tid % BK
+//   r-contiguous operand:  r = tid % BR,             kk = e*(256/BR) + tid/BR
+// so consecutive lanes read consecutive addresses either way.
+template <int BR, int BK, class OP>
+__device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
+                                          int64_t kend, int tid, double* v) {
+  constexpr int E = BR * BK / 256;
+  if constexpr (is_strided_op<OP>::value) {
+    static_assert(256 % BK == 0 && 256 % BR == 0, "tile shape must divide the block");
+    // Uniform part (scalar registers): the tile origin and the element step.
+    // Per-thread part: one 32-bit byte offset shared by all E elements.
+    const int rl = OP::kContig ? (tid / BK) : (tid % BR);
+    const int kl = OP::kContig ? (tid % BK) : (tid / BR);
+    const int64_t estride = OP::kContig ? (int64_t)(256 / BK) * op.sr : (int64_t)(256 / BR) * op.sk;
+    const double* origin = op.p + b * op.sb + r0 * op.sr + kbase * op.sk;
+    const uint32_t toff = (uint32_t)(((int64_t)rl * op.sr + (int64_t)kl * op.sk) * 8);
+    const bool full = (r0 + BR <= op.rows) && (kbase + BK <= kend);
+    if (full) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const char* sb = reinterpret_cast<const char*>(origin + e * estride);
+        v[e] = *reinterpret_cast<const double*>(sb + toff);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = OP::kContig ? rl + e * (256 / BK) : rl;
+        const int k = OP::kContig ? kl : kl + e * (256 / BR);
+        const bool ok = (r0 + r < op.rows) && (kbase + k < kend);
+        // masked elements read the tile origin, which is always a valid element
+        const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : origin);
+        const double x = *reinterpret_cast<const double*>(sb + (ok ? toff : 0u));
+        v[e] = ok ? x : 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = e * 256 + tid;
+      const int kk = OP::kContig ? (idx % BK) : (idx / BR);
+      const int r = OP::kContig ? (idx / BK) : (idx % BR);
+      const int64_t k = kbase + kk;
+      v[e] = (k < kend) ? op.get(b, r0 + r, k) : 0.0;
+    }
+  }
+}
 
 // Hardware dispatches consecutive workgroup ids round-robin over the 8 XCDs
 // (each with its own L2).  Renumber so that each XCD walks a contiguous range
@@ -87,7 +151,7 @@ struct AllTiles {
 // TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
 // epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
 template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
                                                        int64_t K, int64_t kchunk, int64_t tiles_m,
                                                        int64_t tiles_n, FILT filt) {
   constexpr int BK = 16;
@@ -100,8 +164,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(OA A, OB B, EPI epi, int6
   static_assert(BM % 32 == 0 && BN % 32 == 0, "tile must split into 2x2 waves of 16x16 MFMA tiles");
   static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
 
-  __shared__ double As[2][BK * LDA];
-  __shared__ double Bs[2][BK * LDB];
+  // One LDS block: the double-buffered operand tiles during the K loop, then
+  // the staging area of the epilogue (WM rows of the C tile at a time).
+  constexpr int LDC = BN + 1;
+  constexpr int SMEM = 2 * BK * (LDA + LDB);
+  static_assert(WM * LDC <= SMEM, "epilogue staging must fit in the operand buffers");
+  __shared__ double smem[SMEM];
+  double (*As)[BK * LDA] = reinterpret_cast<double (*)[BK * LDA]>(smem);
+  double (*Bs)[BK * LDB] = reinterpret_cast<double (*)[BK * LDB]>(smem + 2 * BK * LDA);
 
   const int64_t nwg = (int64_t)gridDim.x;
   const int64_t id = xcd_logical_id((int64_t)blockIdx.x, nwg);
@@ -129,22 +199,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(OA A, OB B, EPI epi, int6
   double ra[EA], rb[EB];
 
   auto gload = [&](int64_t kbase) {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = e * 256 + tid;
-      const int kk = OA::kContig ? (idx % BK) : (idx / BM);
-      const int r = OA::kContig ? (idx / BK) : (idx % BM);
-      const int64_t k = kbase + kk;
-      ra[e] = (k < kb1) ? A.get(batch, m0 + r, k) : 0.0;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int idx = e * 256 + tid;
-      const int kk = OB::kContig ? (idx % BK) : (idx / BN);
-      const int r = OB::kContig ? (idx / BK) : (idx % BN);
-      const int64_t k = kbase + kk;
-      rb[e] = (k < kb1) ? B.get(batch, n0 + r, k) : 0.0;
-    }
+    load_tile<BM, BK>(A, batch, m0, kbase, kb1, tid, ra);
+    load_tile<BN, BK>(B, batch, n0, kbase, kb1, tid, rb);
   };
   auto sstore = [&](int buf) {
 #pragma unroll
@@ -192,22 +248,41 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(OA A, OB B, EPI epi, int6
     __syncthreads();
   }
 
+  // Epilogue through LDS, one wave-row (WM rows of the tile) per pass: the
+  // two waves owning those rows store their accumulators straight from the
+  // matrix-core registers, then all 256 threads apply the epilogue row by row
+  // (consecutive threads on consecutive columns).  Keeping the arithmetic out
+  // of the accumulator registers stops the compiler from copying all of them
+  // to VGPRs at once, which would halve the occupancy of the K loop.
+  if (nk > 0) __syncthreads();  // operand buffers are free once every wave is done
+  double* Cs = smem;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int pass = 0; pass < 2; ++pass) {
+    if ((wave >> 1) == pass) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t m = m0 + wm + i * 16 + 4 * q + (lane >> 4);
-        const int64_t n = n0 + wn + j * 16 + (lane & 15);
-        if (m < M && n < N) {
-          if (TRI) {
-            if (m <= n) epi(batch, split, m, n, acc[i][j][q], m != n);
-          } else {
-            epi(batch, split, m, n, acc[i][j][q], false);
-          }
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            Cs[(i * 16 + 4 * q + (lane >> 4)) * LDC + wn + j * 16 + (lane & 15)] = acc[i][j][q];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < WM * BN; idx += 256) {
+      const int row = idx / BN, col = idx - (idx / BN) * BN;
+      const int64_t m = m0 + pass * WM + row;
+      const int64_t n = n0 + col;
+      if (m < M && n < N) {
+        const double v = Cs[row * LDC + col];
+        if (TRI) {
+          if (m <= n) epi(batch, split, m, n, v, m != n);
+        } else {
+          epi(batch, split, m, n, v, false);
         }
       }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- epilogues

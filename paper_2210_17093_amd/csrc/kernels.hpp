@@ -38,7 +38,8 @@ struct PoleScaledResidueOp {
   double eta;
   __device__ __forceinline__ double get(int64_t, int64_t r, int64_t k) const {
     if (r >= nbf) return 0.0;
-    const int64_t kst = k / ns;
+    // k < nbf * ns < 2^32 (checked by the caller): 32-bit division
+    const int64_t kst = (int64_t)((uint32_t)k / (uint32_t)ns);
     const int64_t s = k - kst * ns;
     const double om = Omega[s];
     const double x = eps[r] - eps[kst] + (kst < nocc ? om : -om);
@@ -86,6 +87,37 @@ struct EpiResidue {
     if (m > k) return;
     w[r * ns + s] = v;
     if (m != k) w[(k * nbf + m) * ns + s] = v;
+  }
+};
+
+// As EpiResidue, and also the pole-weighted copy used by the qsGW matrix,
+// Eqs. (17) and (19): wh[m][k][s] = w[m][k][s] * Re 1/(eps_m - eps_k +- (Omega_s - i eta))
+// = w x / (x^2 + eta^2), x = eps_m - eps_k + Omega_s (occupied k) or
+// eps_m - eps_k - Omega_s (empty k); the mirrored entry (k, m) gets its own weight.
+struct EpiResidueWeighted {
+  double* w;
+  double* wh;
+  const double* eps;
+  const double* Omega;  // the block's excitations
+  int64_t nbf, nocc, ns;
+  double eta;
+  __device__ __forceinline__ double weight(int64_t a, int64_t b, double om) const {
+    const double x = eps[a] - eps[b] + (b < nocc ? om : -om);
+    return x / (x * x + eta * eta);
+  }
+  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
+                                             bool) const {
+    const int64_t m = r / nbf;
+    const int64_t k = r - m * nbf;
+    if (m > k) return;
+    const double om = Omega[s];
+    w[r * ns + s] = v;
+    wh[r * ns + s] = v * weight(m, k, om);
+    if (m != k) {
+      const int64_t r2 = k * nbf + m;
+      w[r2 * ns + s] = v;
+      wh[r2 * ns + s] = v * weight(k, m, om);
+    }
   }
 };
 

@@ -32,6 +32,7 @@ enum Slot {
   W_OMEGA,    // Omega                                    [ntr]
   W_RHO,      // rho' of one excitation block             [naux][sb]
   W_W,        // residues of one excitation block         [nbf][nbf][sb]
+  W_WH,       // pole-weighted residues of the block      [nbf][nbf][sb]
   W_PART,     // split-K partial sums                     [nz][nbf][nbf]
   W_V,        // qsGW potential, MO basis                 [nbf][nbf]
   W_HMO,      // C^T h C                                  [nbf][nbf]
@@ -322,7 +323,8 @@ int stage_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M, double* Omega) {
 // Eq. (18) for excitations [s0, s0 + ns): rho' = sqrt(2/Omega) Bt Z^T, w = B_mo^T rho'.
 int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
                    const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
-                   double* rho, double* w, Spans* sp = nullptr) {
+                   double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
+                   const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0) {
   {
     Strided<true> A{Bt, ntr, 1, 0, naux};
     Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
@@ -335,10 +337,16 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
     const int64_t nn = nbf * nbf;
     Strided<false> A{B_mo, 1, nn, 0, nn};
     Strided<false> B{rho, 1, ns, 0, ns};
-    EpiResidue E{w, nbf, ns};
     SPAN_OPEN(sp, kKW);
-    CHECK((gemm<128, 128, false>(c, "residues/w", A, B, E, nn, ns, naux, 1, SplitPlan{0, 1},
-                                 UpperPairRows{nbf})));
+    if (wh) {
+      EpiResidueWeighted E{w, wh, eps, Omega + s0, nbf, nocc, ns, eta};
+      CHECK((gemm<128, 128, false>(c, "residues/w+wh", A, B, E, nn, ns, naux, 1, SplitPlan{0, 1},
+                                   UpperPairRows{nbf})));
+    } else {
+      EpiResidue E{w, nbf, ns};
+      CHECK((gemm<128, 128, false>(c, "residues/w", A, B, E, nn, ns, naux, 1, SplitPlan{0, 1},
+                                   UpperPairRows{nbf})));
+    }
     SPAN_CLOSE(sp);
   }
   return QSGW_OK;
@@ -347,15 +355,23 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
 // Eq. (19) contribution of one excitation block: V (+)= 1/2 (G + G^T).
 int stage_sigma_qs(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
                    const double* eps, const double* Omega, double eta, double* V, int accumulate,
-                   Spans* spn = nullptr) {
+                   Spans* spn = nullptr, const double* wh = nullptr) {
   const SplitPlan sp = sigma_split(nbf, ns);
+  if (nbf * ns >= (int64_t)1 << 32)
+    return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^32");
   double* part = nullptr;
   CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nbf * nbf), &part));
-  PoleScaledResidueOp A{w, eps, Omega, nbf, nocc, ns, eta};
   Strided<true> B{w, nbf * ns, 1, 0, nbf};
   EpiStore E{part, nbf, 0, nbf * nbf, 1.0};
   SPAN_OPEN(spn, kKSigma);
-  CHECK((gemm<64, 64, false>(c, "sigma_qs", A, B, E, nbf, nbf, nbf * ns, 1, sp)));
+  if (wh) {
+    // pole weights already applied by the residue epilogue
+    Strided<true> A{wh, nbf * ns, 1, 0, nbf};
+    CHECK((gemm<64, 64, false>(c, "sigma_qs", A, B, E, nbf, nbf, nbf * ns, 1, sp)));
+  } else {
+    PoleScaledResidueOp A{w, eps, Omega, nbf, nocc, ns, eta};
+    CHECK((gemm<64, 64, false>(c, "sigma_qs", A, B, E, nbf, nbf, nbf * ns, 1, sp)));
+  }
   SPAN_CLOSE(spn);
   SPAN_OPEN(spn, kKSigmaRed);
   hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nbf * nbf)), dim3(256), 0, c->stream, part,
@@ -648,6 +664,7 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   if (sb == 0) {
     // stream residues in blocks of at most ~8 GiB of w
     const int64_t cap = (int64_t)((8ull << 30) / (sizeof(double) * (uint64_t)nn));
+    // (two block buffers, w and the pole-weighted copy)
     sb = ntr < cap ? ntr : (cap < 64 ? 64 : cap);
   }
   if (sb > ntr) sb = ntr;
@@ -664,6 +681,8 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   CHECK(ws_get(c, W_OMEGA, (size_t)ntr, &Omega));
   CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
   CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
+  double* wh = nullptr;
+  CHECK(ws_get(c, W_WH, (size_t)(nn * sb), &wh));
   CHECK(ws_get(c, W_V, (size_t)nn, &V));
   CHECK(ws_get(c, W_HMO, (size_t)nn, &hmo));
   CHECK(ws_get(c, W_F, (size_t)nn, &F));
@@ -749,10 +768,12 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
       const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
       CHECK(sp.open(kStageRes));
-      CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp));
+      CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps, nocc,
+                           o->eta));
       CHECK(sp.close());
       CHECK(sp.open(kStageSigma));
-      CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp));
+      CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
+                           wh));
       CHECK(sp.close());
     }
     CHECK(sp.open(kStageFock));
