@@ -58,6 +58,40 @@ struct is_strided_op<OP, decltype((void)OP::kStrided, void())> {
   static constexpr bool value = OP::kStrided;
 };
 
+// Rows that are pairs (m, k) of a symmetric N x N index, blocked in 2-D:
+// row tile t covers the PM x PK block (blocks[t] = mb << 16 | kb) of pairs
+// m = PM mb + i / PK, k = PK kb + i % PK, i = 0..PM*PK-1.  Element (row, kk)
+// sits at p[b*sb + kk*sk + m*N + k].  Only blocks holding some m <= k are
+// listed, so a symmetric product in (m, k) runs about half the pair space.
+template <int PM, int PK>
+struct PairRows {
+  static constexpr bool kContig = false;
+  static constexpr bool kPairRows = true;
+  static constexpr int kPM = PM, kPK = PK;
+  const double* p;
+  int64_t sk, sb;
+  int64_t n;              // N, the range of m and k
+  const int32_t* blocks;  // one entry per row tile
+};
+
+template <class OP, class = void>
+struct is_pair_rows_op {
+  static constexpr bool value = false;
+};
+template <class OP>
+struct is_pair_rows_op<OP, decltype((void)OP::kPairRows, void())> {
+  static constexpr bool value = OP::kPairRows;
+};
+
+// Pair (m, k) of row i of pair-row tile t (blocks as in PairRows).
+template <int PM, int PK>
+__device__ __forceinline__ void pair_of(const int32_t* blocks, int64_t t, int i, int64_t& m,
+                                        int64_t& k) {
+  const int32_t bk = blocks[t];
+  m = (int64_t)(bk >> 16) * PM + i / PK;
+  k = (int64_t)(bk & 0xffff) * PK + i % PK;
+}
+
 // Load this thread's E = BR*BK/256 elements of a BR x BK operand tile
 // (rows r0.., k = kbase..) into v[].  Element e of thread tid sits at
 //   k-contiguous operand:  r = e*(256/BK) + tid/BK,  kk = tid % BK
@@ -67,7 +101,26 @@ template <int BR, int BK, class OP>
 __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
                                           int64_t kend, int tid, double* v) {
   constexpr int E = BR * BK / 256;
-  if constexpr (is_strided_op<OP>::value) {
+  if constexpr (is_pair_rows_op<OP>::value) {
+    static_assert(OP::kPM * OP::kPK == BR && 256 % BR == 0, "pair block must fill the row tile");
+    // rows are unit-stride within a block row: thread owns one row i = tid % BR
+    const int i = tid % BR;
+    const int kl = tid / BR;
+    int64_t m, k;
+    pair_of<OP::kPM, OP::kPK>(op.blocks, r0 / BR, i, m, k);
+    const bool rok = (m < op.n) && (k < op.n);
+    const uint32_t toff = rok ? (uint32_t)((m * op.n + k) * 8) : 0u;
+    const int64_t estride = (int64_t)(256 / BR) * op.sk;
+    const double* origin = op.p + b * op.sb + (kbase + kl) * op.sk;
+    const bool kfull = kbase + BK <= kend;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool ok = rok && (kfull || kbase + kl + e * (256 / BR) < kend);
+      const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : op.p);
+      const double x = *reinterpret_cast<const double*>(sb + (ok ? toff : 0u));
+      v[e] = ok ? x : 0.0;
+    }
+  } else if constexpr (is_strided_op<OP>::value) {
     static_assert(256 % BK == 0 && 256 % BR == 0, "tile shape must divide the block");
     // Uniform part (scalar registers): the tile origin and the element step.
     // Per-thread part: one 32-bit byte offset shared by all E elements.
@@ -143,10 +196,15 @@ __device__ __forceinline__ TileCoord tri_tile(int64_t id) {
   return {id - tn * (tn + 1) / 2, tn};
 }
 
-// Tile filter hook: returns false for tiles whose outputs are all unneeded.
+// Row-tile map: the launch enumerates `tiles_m` row tiles, and the map turns
+// that index into the row tile actually computed.  The identity covers the
+// whole output; a table skips row tiles whose outputs are all unneeded
+// without leaving idle workgroups in the launch (idle workgroups would also
+// unbalance the per-XCD work, as each XCD owns a contiguous range).
 struct AllTiles {
-  __device__ __forceinline__ bool operator()(int64_t, int64_t, int64_t, int64_t) const { return true; }
+  __device__ __forceinline__ int64_t operator()(int64_t t) const { return t; }
 };
+
 
 // TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
 // epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
@@ -178,9 +236,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   TileCoord tc = TRI ? tri_tile(id) : grouped_tile(id, tiles_m, tiles_n);
   const int64_t batch = blockIdx.y;
   const int64_t split = blockIdx.z;
-  const int64_t m0 = tc.tm * BM, n0 = tc.tn * BN;
+  const int64_t m0 = (TRI ? tc.tm : filt(tc.tm)) * BM, n0 = tc.tn * BN;
   if (m0 >= M || n0 >= N) return;
-  if (!filt(m0, m0 + BM < M ? m0 + BM : M, n0, n0 + BN < N ? n0 + BN : N)) return;
   const int64_t kb0 = split * kchunk;
   const int64_t kb1 = (kb0 + kchunk) < K ? (kb0 + kchunk) : K;
 

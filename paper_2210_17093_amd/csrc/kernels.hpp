@@ -75,30 +75,19 @@ struct EpiRho {
   }
 };
 
-// w[m][k][s] from the GEMM row r = m * nbf + k; written for m <= k and
-// mirrored to (k, m), so w is exactly symmetric in (m, k).
-struct EpiResidue {
+// Residues from the pair-blocked product (rows = pair tiles of PairRows<8, 16>):
+// w[m][k][s] for m <= k, mirrored to (k, m), so w is exactly symmetric in
+// (m, k).  With wh != nullptr also the pole-weighted copy used by the qsGW
+// matrix, Eqs. (17) and (19):
+//   wh[m][k][s] = w[m][k][s] Re 1/(eps_m - eps_k +- (Omega_s - i eta)) = w x / (x^2 + eta^2),
+//   x = eps_m - eps_k + Omega_s (occupied k) or eps_m - eps_k - Omega_s (empty k);
+// the mirrored entry (k, m) gets its own weight.
+struct EpiPairResidue {
   double* w;
-  int64_t nbf, ns;
-  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
-                                             bool) const {
-    const int64_t m = r / nbf;
-    const int64_t k = r - m * nbf;
-    if (m > k) return;
-    w[r * ns + s] = v;
-    if (m != k) w[(k * nbf + m) * ns + s] = v;
-  }
-};
-
-// As EpiResidue, and also the pole-weighted copy used by the qsGW matrix,
-// Eqs. (17) and (19): wh[m][k][s] = w[m][k][s] * Re 1/(eps_m - eps_k +- (Omega_s - i eta))
-// = w x / (x^2 + eta^2), x = eps_m - eps_k + Omega_s (occupied k) or
-// eps_m - eps_k - Omega_s (empty k); the mirrored entry (k, m) gets its own weight.
-struct EpiResidueWeighted {
-  double* w;
-  double* wh;
+  double* wh;             // nullptr: residues only
+  const int32_t* blocks;
   const double* eps;
-  const double* Omega;  // the block's excitations
+  const double* Omega;    // the block's excitations
   int64_t nbf, nocc, ns;
   double eta;
   __device__ __forceinline__ double weight(int64_t a, int64_t b, double om) const {
@@ -107,30 +96,17 @@ struct EpiResidueWeighted {
   }
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
                                              bool) const {
-    const int64_t m = r / nbf;
-    const int64_t k = r - m * nbf;
-    if (m > k) return;
-    const double om = Omega[s];
-    w[r * ns + s] = v;
-    wh[r * ns + s] = v * weight(m, k, om);
-    if (m != k) {
-      const int64_t r2 = k * nbf + m;
-      w[r2 * ns + s] = v;
-      wh[r2 * ns + s] = v * weight(k, m, om);
+    int64_t m, k;
+    pair_of<8, 16>(blocks, r >> 7, (int)(r & 127), m, k);
+    if (m >= nbf || k >= nbf || m > k) return;
+    const int64_t r1 = m * nbf + k, r2 = k * nbf + m;
+    w[r1 * ns + s] = v;
+    if (m != k) w[r2 * ns + s] = v;
+    if (wh) {
+      const double om = Omega[s];
+      wh[r1 * ns + s] = v * weight(m, k, om);
+      if (m != k) wh[r2 * ns + s] = v * weight(k, m, om);
     }
-  }
-};
-
-// Row tiles of the residue GEMM that hold at least one pair m <= k.
-struct UpperPairRows {
-  int64_t nbf;
-  __device__ __forceinline__ bool operator()(int64_t r0, int64_t r1, int64_t, int64_t) const {
-    for (int64_t m = r0 / nbf; m * nbf < r1; ++m) {
-      const int64_t lo = m * (nbf + 1) > r0 ? m * (nbf + 1) : r0;
-      const int64_t hi = (m + 1) * nbf < r1 ? (m + 1) * nbf : r1;
-      if (lo < hi) return true;
-    }
-    return false;
   }
 };
 

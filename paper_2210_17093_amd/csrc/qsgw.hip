@@ -46,6 +46,7 @@ enum Slot {
   W_EIGE,     // dsyevd off-diagonal workspace            [max(ntr, nbf)]
   W_SCAL,     // device scalars                           [8]
   W_FLAGS,    // device int flags                         [8]
+  W_ROWTAB,   // residue pair blocks holding some m <= k  [blocks]
   W_NSLOTS
 };
 
@@ -67,6 +68,8 @@ struct qsgw_ctx {
   double stage_ms[7] = {0, 0, 0, 0, 0, 0, 0};
   // events bracketing each stage of the last single-stage call
   int last_stage = -1;
+  // cached residue pair-block table
+  int64_t rowtab_nbf = -1, rowtab_n = 0;
 };
 
 namespace {
@@ -146,7 +149,8 @@ inline SplitPlan split_plan(int64_t K, int64_t want) {
 template <int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
 int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
          int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
-  const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  const int64_t tm = (M + BM - 1) / BM;
+  const int64_t tn = (N + BN - 1) / BN;
   const int64_t ntiles = TRI ? tm * (tm + 1) / 2 : tm * tn;
   const int64_t kchunk = sp.nz > 1 ? sp.kchunk : K;
   const int64_t splits = sp.nz > 1 ? sp.nz : 1;
@@ -236,6 +240,30 @@ struct Spans {
   do {                                 \
     if (sp) CHECK((sp)->close());      \
   } while (0)
+
+// Pair blocks (8 values of m x 16 values of k) of the residue product that
+// hold at least one pair m <= k, encoded mb << 16 | kb, in row-major block
+// order.  Built on the host once per nbf and kept on the device.
+int pair_blocks(qsgw_ctx* c, int64_t nbf, const int32_t** tab, int64_t* n) {
+  if (c->rowtab_nbf != nbf) {
+    const int64_t nmb = (nbf + 7) / 8, nkb = (nbf + 15) / 16;
+    if (nmb > 0x7fff || nkb > 0xffff) return fail(c, QSGW_ERR_INVALID_ARG, "nbf too large");
+    std::vector<int32_t> keep;
+    for (int64_t mb = 0; mb < nmb; ++mb)
+      for (int64_t kb = 0; kb < nkb; ++kb)
+        if (8 * mb <= 16 * kb + 15) keep.push_back((int32_t)((mb << 16) | kb));
+    int32_t* d = nullptr;
+    CHECK(ws_get(c, W_ROWTAB, keep.size(), &d));
+    // work already queued may still read the previous table
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(d, keep.data(), keep.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->rowtab_nbf = nbf;
+    c->rowtab_n = (int64_t)keep.size();
+  }
+  *tab = static_cast<const int32_t*>(c->ws[W_ROWTAB].p);
+  *n = c->rowtab_n;
+  return QSGW_OK;
+}
 
 // ------------------------------------------------------------- stages ----
 
@@ -335,18 +363,14 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
   }
   {
     const int64_t nn = nbf * nbf;
-    Strided<false> A{B_mo, 1, nn, 0, nn};
+    const int32_t* blocks = nullptr;
+    int64_t nblk = 0;
+    CHECK(pair_blocks(c, nbf, &blocks, &nblk));
+    PairRows<8, 16> A{B_mo, nn, 0, nbf, blocks};
     Strided<false> B{rho, 1, ns, 0, ns};
+    EpiPairResidue E{w, wh, blocks, eps, Omega + s0, nbf, nocc, ns, eta};
     SPAN_OPEN(sp, kKW);
-    if (wh) {
-      EpiResidueWeighted E{w, wh, eps, Omega + s0, nbf, nocc, ns, eta};
-      CHECK((gemm<128, 128, false>(c, "residues/w+wh", A, B, E, nn, ns, naux, 1, SplitPlan{0, 1},
-                                   UpperPairRows{nbf})));
-    } else {
-      EpiResidue E{w, nbf, ns};
-      CHECK((gemm<128, 128, false>(c, "residues/w", A, B, E, nn, ns, naux, 1, SplitPlan{0, 1},
-                                   UpperPairRows{nbf})));
-    }
+    CHECK((gemm<128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
     SPAN_CLOSE(sp);
   }
   return QSGW_OK;

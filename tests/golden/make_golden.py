@@ -8,6 +8,9 @@ trajectory is stored here and the GPU tests compare against the file.
     python tests/golden/make_golden.py cfg2            # writes cfg2_oracle.json
     python tests/golden/make_golden.py cfg2 --perturb  # also records how a
                                                        # 1e-11 Ha start shift grows
+    python tests/golden/make_golden.py cfg2 --spread   # also records the distance to
+                                                       # the oracle run on P-permuted
+                                                       # inputs (pure rounding spread)
 """
 from __future__ import annotations
 
@@ -35,7 +38,7 @@ def input_fingerprint(p):
                 C_sum=float(p.C0.sum()), eps_sum=float(p.eps0.sum()))
 
 
-def run(name, perturb):
+def run(name, perturb, spread):
     c = CONFIGS[name]
     p = make_config(name)
     t0 = time.time()
@@ -56,6 +59,19 @@ def run(name, perturb):
         out["iterations"].append(rec)
         print(f"iteration {j + 1}: max|deps| = {r['max_deps']:.3e}", flush=True)
     out["oracle_seconds"] = time.time() - t0
+    if spread:
+        # Exact symmetry of the method: a permutation of the auxiliary index P.
+        # Every P-contraction sums in a different order, so the two oracle
+        # trajectories differ only by FP64 rounding: their distance is the
+        # intrinsic rounding spread of this workload, iteration by iteration.
+        perm = np.random.default_rng(123).permutation(p.naux)
+        Bp = np.ascontiguousarray(p.B_ao[perm])
+        hp = O.hf_core(Bp, p.C0, p.eps0, p.nocc)
+        _, _, hist3 = O.qsgw_iterate(Bp, hp, p.C0, p.eps0, p.nocc, c["eta"], 0.0, c["max_iter"],
+                                     keep=("eps",))
+        out["reorder_spread"] = [float(np.max(np.abs(a["eps"] - b["eps"])))
+                                 for a, b in zip(hist, hist3)]
+        print("rounding spread", out["reorder_spread"], flush=True)
     if perturb:
         _, _, hist2 = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0 + 1e-11, p.nocc, c["eta"],
                                      0.0, c["max_iter"], keep=("eps",))
@@ -69,4 +85,5 @@ def run(name, perturb):
 
 
 if __name__ == "__main__":
-    run(sys.argv[1] if len(sys.argv) > 1 else "cfg2", "--perturb" in sys.argv)
+    run(sys.argv[1] if len(sys.argv) > 1 else "cfg2", "--perturb" in sys.argv,
+        "--spread" in sys.argv)
