@@ -29,6 +29,14 @@ METRIC = "qsGW iteration time & sustained TFLOP/s vs FP64 plain path at ≤1 meV
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel at the cfg2 workload, from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes scaled by the plain-copy calibration
+# (profiles/residue_w_cfg2_hbm_counters.md).  Only valid for the kernel build
+# the counters were taken on: set an entry to None whenever that kernel changes.
+MEASURED_TRAFFIC_BYTES = {
+    ("cfg2", "residue_w"): 49.78e9,
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -91,6 +99,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="for rocprofv3 --pmc passes only: run the hot-path entry points once "
+                         "each (MO transform, Casida build, residues with the pole-weighted copy, "
+                         "qsGW matrix) with Z = I and Omega = Delta in place of the eigensolve, "
+                         "which is not run under counter collection; prints no timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter "
                          "calibration: 1 GiB read + 1 GiB written per copy)")
@@ -111,6 +124,26 @@ def main():
         return
     import paper_2210_17093_amd.qsgw as q
     from qsgw_inputs import CONFIGS, make_config
+
+    if args.counter_probe:
+        cfg = CONFIGS[args.config]
+        p = make_config(args.config)
+        dev = torch.device("cuda:0")
+        B = torch.from_numpy(p.B_ao).to(dev)
+        C0 = torch.from_numpy(p.C0).to(dev)
+        e0 = torch.from_numpy(p.eps0).to(dev)
+        with q.Context() as ctx:
+            B_mo = q.qsgw_mo_transform(ctx, B, C0)
+            M, sq = q.qsgw_rpa_build(ctx, B_mo, e0, p.nocc)
+            # an orthogonal eigenvector matrix and positive energies of the right shape
+            Z = torch.eye(p.ntr, dtype=torch.float64, device=dev)
+            Om = (sq * sq).contiguous()
+            w, wh = q.qsgw_residues(ctx, B_mo, sq, Z, Om, p.nocc, weighted=True, eps=e0,
+                                    eta=cfg["eta"])
+            q.qsgw_sigma_qs(ctx, w, e0, Om, p.nocc, cfg["eta"], wh=wh)
+            torch.cuda.synchronize()
+        print(json.dumps({"counter_probe": args.config}), flush=True)
+        return
 
     cfg = CONFIGS[args.config]
     eta = cfg["eta"]
@@ -178,7 +211,8 @@ def main():
         "hot_flops": hot_flops,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": MEASURED_TRAFFIC_BYTES.get((args.config, dom)),
                      "flops_per_launch": flops_per_launch, "ms_per_launch": round(per_launch_ms, 4)},
     }
     if not args.no_cpu_baseline:

@@ -126,15 +126,25 @@ int qsgw_rpa_solve(qsgw_ctx* ctx, int64_t ntr, double* M_to_Z, double* Omega);
  *   w[m][n][s - s_begin] = sqrt(2) sum_P B_mo[P][m][n] rho[P][s]
  * Z: [ntr][ntr] as returned by qsgw_rpa_solve; Omega: [ntr].
  * w: [nbf][nbf][s_count] out, written exactly symmetric in (m, n).
- * Errors: s range outside [0, ntr); precision other than FP64.
+ * wh: NULL, or [nbf][nbf][s_count] out: the pole-weighted copy used by the
+ *   qsGW matrix of qsgw_sigma,
+ *   wh[m][n][s] = w[m][n][s] Re 1/(eps_m - eps_n +- (Omega_s - i eta))
+ *   ("+" for occupied n, "-" for empty n); then eps ([nbf]) and eta > 0 are
+ *   required, otherwise they are ignored.
+ * Errors: s range outside [0, ntr); precision other than FP64; wh without
+ * eps or with eta <= 0.
  */
 int qsgw_residues(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                   const double* sqrt_delta, const double* Z, const double* Omega,
-                  int64_t s_begin, int64_t s_count, double* w, int precision);
+                  int64_t s_begin, int64_t s_count, double* w, double* wh, const double* eps,
+                  double eta, int precision);
 
 /*
  * GW self-energy from residues of ns excitations, Eq. (17).
  * w:     [nbf][nbf][ns] as written by qsgw_residues;
+ * wh:    NULL, or the pole-weighted copy written by qsgw_residues with the
+ *        same eps, Omega and eta (QS_MATRIX mode only; saves recomputing the
+ *        weights); ignored by DIAG_GRID;
  * Omega: [ns], the excitation energies of those ns columns.
  * mode QSGW_SIGMA_QS_MATRIX, Eq. (19):
  *   out[m][n] (+)= 1/2 (G[m][n] + G[n][m]),
@@ -149,8 +159,9 @@ int qsgw_residues(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const 
  * <= 0; device indexes are clamped-checked and flagged as INVALID_ARG).
  */
 int qsgw_sigma(qsgw_ctx* ctx, int mode, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
-               const double* eps, const double* Omega, double eta, const double* omega,
-               int64_t nomega, const int64_t* states, int64_t nstates, double* out, int accumulate);
+               const double* wh, const double* eps, const double* Omega, double eta,
+               const double* omega, int64_t nomega, const int64_t* states, int64_t nstates,
+               double* out, int accumulate);
 
 /*
  * One-body matrix that makes (eps0, C0) a Hartree-Fock fixed point of

@@ -9,13 +9,13 @@
 // the unit-stride direction (so global loads are coalesced either way).  The
 // epilogue is a functor that receives each finished element.
 //
-// Tiling: BM x BN block tile, BK = 16, 256 threads = 4 wave64 in a 2 x 2
+// Tiling: BM x BN block tile, BK = 16 by default, 256 threads = 4 wave64 in a 2 x 2
 // arrangement; each wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16
-// accumulators updated by v_mfma_f64_16x16x4_f64.  Both operands are staged
-// k-major in LDS ([k][r], row pitch BR+1 doubles so the transposing stores
-// of k-contiguous operands hit distinct banks), double buffered with one
-// barrier per k-tile, and the next k-tile is prefetched into registers while
-// the current one feeds the matrix cores.
+// accumulators updated by v_mfma_f64_16x16x4_f64.  Operands are staged in
+// LDS in their global orientation ([r][k] for k-contiguous, [k][r] for
+// r-contiguous, odd pitches), double buffered with one barrier per k-tile,
+// and the next k-tile is prefetched into registers while the current one
+// feeds the matrix cores.
 //
 // MFMA f64 16x16x4 lane layout (wave64):
 //   A fragment: lane l holds A[l % 16][l / 16]      (16 rows x 4 k)
@@ -121,7 +121,8 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
       v[e] = ok ? x : 0.0;
     }
   } else if constexpr (is_strided_op<OP>::value) {
-    static_assert(256 % BK == 0 && 256 % BR == 0, "tile shape must divide the block");
+    static_assert(OP::kContig ? (256 % BK == 0) : (256 % BR == 0),
+                  "tile shape must divide the block");
     // Uniform part (scalar registers): the tile origin and the element step.
     // Per-thread part: one 32-bit byte offset shared by all E elements.
     const int rl = OP::kContig ? (tid / BK) : (tid % BR);
@@ -208,13 +209,19 @@ struct AllTiles {
 
 // TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
 // epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
-template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles>
+template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles,
+          int BK = 16>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
                                                        int64_t K, int64_t kchunk, int64_t tiles_m,
-                                                       int64_t tiles_n, FILT filt) {
-  constexpr int BK = 16;
-  constexpr int LDA = BM + 1;
-  constexpr int LDB = BN + 1;
+                                                       int64_t tiles_n, int64_t nbatch, FILT filt) {
+  static_assert(BK % 4 == 0, "BK is a multiple of the MFMA depth");
+  // LDS layout per operand: a k-contiguous operand is kept [r][k] (pitch BK+1)
+  // so global rows land in LDS rows without a transpose; an r-contiguous one
+  // is kept [k][r] (pitch BR+1).  Both pitches are odd, which keeps the 16
+  // lanes of an MFMA fragment read on distinct banks.
+  constexpr bool AK = OA::kContig, BKC = OB::kContig;
+  constexpr int SZA = AK ? BM * (BK + 1) : BK * (BM + 1);
+  constexpr int SZB = BKC ? BN * (BK + 1) : BK * (BN + 1);
   constexpr int EA = BM * BK / 256;
   constexpr int EB = BN * BK / 256;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -225,17 +232,26 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   // One LDS block: the double-buffered operand tiles during the K loop, then
   // the staging area of the epilogue (WM rows of the C tile at a time).
   constexpr int LDC = BN + 1;
-  constexpr int SMEM = 2 * BK * (LDA + LDB);
+  constexpr int SMEM = 2 * (SZA + SZB);
   static_assert(WM * LDC <= SMEM, "epilogue staging must fit in the operand buffers");
   __shared__ double smem[SMEM];
-  double (*As)[BK * LDA] = reinterpret_cast<double (*)[BK * LDA]>(smem);
-  double (*Bs)[BK * LDB] = reinterpret_cast<double (*)[BK * LDB]>(smem + 2 * BK * LDA);
+  double (*As)[SZA] = reinterpret_cast<double (*)[SZA]>(smem);
+  double (*Bs)[SZB] = reinterpret_cast<double (*)[SZB]>(smem + 2 * SZA);
+  // element (r, k) of the staged tiles
+  auto a_at = [](int r, int k) { return AK ? r * (BK + 1) + k : k * (BM + 1) + r; };
+  auto b_at = [](int r, int k) { return BKC ? r * (BK + 1) + k : k * (BN + 1) + r; };
 
-  const int64_t nwg = (int64_t)gridDim.x;
-  const int64_t id = xcd_logical_id((int64_t)blockIdx.x, nwg);
+  // The launch is one-dimensional over (split, batch, tile), tile fastest.
+  // Workgroups go to the XCDs round-robin by this linear id; renumbering
+  // gives each XCD a contiguous logical range, so the tiles that share one
+  // K chunk (or one batch entry) share one L2.
+  const int64_t ntiles = TRI ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+  const int64_t lid = xcd_logical_id((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int64_t id = lid % ntiles;
+  const int64_t rest = lid / ntiles;
+  const int64_t batch = rest % nbatch;
+  const int64_t split = rest / nbatch;
   TileCoord tc = TRI ? tri_tile(id) : grouped_tile(id, tiles_m, tiles_n);
-  const int64_t batch = blockIdx.y;
-  const int64_t split = blockIdx.z;
   const int64_t m0 = (TRI ? tc.tm : filt(tc.tm)) * BM, n0 = tc.tn * BN;
   if (m0 >= M || n0 >= N) return;
   const int64_t kb0 = split * kchunk;
@@ -265,14 +281,14 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
       const int idx = e * 256 + tid;
       const int kk = OA::kContig ? (idx % BK) : (idx / BM);
       const int r = OA::kContig ? (idx / BK) : (idx % BM);
-      As[buf][kk * LDA + r] = ra[e];
+      As[buf][a_at(r, kk)] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = e * 256 + tid;
       const int kk = OB::kContig ? (idx % BK) : (idx / BN);
       const int r = OB::kContig ? (idx / BK) : (idx % BN);
-      Bs[buf][kk * LDB + r] = rb[e];
+      Bs[buf][b_at(r, kk)] = rb[e];
     }
   };
 
@@ -292,9 +308,9 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
       const int krow = ks * 4 + (lane >> 4);
       double a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = as[krow * LDA + wm + i * 16 + (lane & 15)];
+      for (int i = 0; i < TM; ++i) a[i] = as[a_at(wm + i * 16 + (lane & 15), krow)];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = bs[krow * LDB + wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < TN; ++j) b[j] = bs[b_at(wn + j * 16 + (lane & 15), krow)];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll

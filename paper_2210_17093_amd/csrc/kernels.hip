@@ -73,6 +73,16 @@ __global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* 
   out[idx] = accumulate ? out[idx] + v : v;
 }
 
+__global__ void k_rho_reduce(const double* part, int64_t nz, int64_t rows, int64_t ns,
+                             const double* Omega, double* rho) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t len = rows * ns;
+  if (idx >= len) return;
+  double v = 0.0;
+  for (int64_t z = 0; z < nz; ++z) v += part[z * len + idx];
+  rho[idx] = v * sqrt(2.0 / Omega[idx % ns]);
+}
+
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc,
                             double* c) {
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -121,6 +121,9 @@ __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_
 __global__ void k_omega_from_eigs(const double* lam, int64_t n, double* Omega, int* bad);
 // out[m][n] (+)= 1/2 (sum_z part[z][m][n] + sum_z part[z][n][m])
 __global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* out, int accumulate);
+// rho'[P][s] = sqrt(2 / Omega_s) sum_z part[z][P][s]  (split-K reduce of the rho product)
+__global__ void k_rho_reduce(const double* part, int64_t nz, int64_t rows, int64_t ns,
+                             const double* Omega, double* rho);
 // c_P = sum_{i<nocc} B_mo[P][i][i]
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc, double* c);
 // J_mn = 2 sum_P c_P B_mo[P][m][n]

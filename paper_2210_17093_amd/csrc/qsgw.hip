@@ -47,6 +47,7 @@ enum Slot {
   W_SCAL,     // device scalars                           [8]
   W_FLAGS,    // device int flags                         [8]
   W_ROWTAB,   // residue pair blocks holding some m <= k  [blocks]
+  W_RHOPART,  // split-K partial sums of rho              [nz][naux][sb]
   W_NSLOTS
 };
 
@@ -155,11 +156,10 @@ int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N,
   const int64_t kchunk = sp.nz > 1 ? sp.kchunk : K;
   const int64_t splits = sp.nz > 1 ? sp.nz : 1;
   if (ntiles <= 0 || batch <= 0 || K <= 0) return QSGW_OK;
-  if (batch > 65535 || splits > 65535 || ntiles > 0x7fffffffLL)
-    return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
-  dim3 grid((unsigned)ntiles, (unsigned)batch, (unsigned)splits);
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT>), grid, dim3(256), 0,
-                     c->stream, a, b, e, M, N, K, kchunk, tm, tn, f);
+  const int64_t total = ntiles * batch * splits;
+  if (total > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT>), dim3((unsigned)total),
+                     dim3(256), 0, c->stream, a, b, e, M, N, K, kchunk, tm, tn, batch, f);
   return launch_check(c, what);
 }
 
@@ -174,7 +174,15 @@ inline int64_t splits_for(int64_t tiles, int64_t K, int64_t target = 2048) {
 // qsGW matrix: 64 x 64 tiles of the nbf x nbf output, K = nbf * ns.
 inline SplitPlan sigma_split(int64_t nbf, int64_t ns) {
   const int64_t t = (nbf + 63) / 64;
-  return split_plan(nbf * ns, splits_for(t * t, nbf * ns));
+  return split_plan(nbf * ns, splits_for(t * t, nbf * ns, 4096));
+}
+
+// rho product: 128 x 128 tiles of the naux x ns output, K = ntr; split only
+// when the tiles alone leave the chip under-filled.
+inline SplitPlan rho_split(int64_t naux, int64_t ns, int64_t ntr) {
+  const int64_t tiles = ((naux + 127) / 128) * ((ns + 127) / 128);
+  if (tiles >= 2048) return {ntr, 1};
+  return split_plan(ntr, splits_for(tiles, ntr, 2048));
 }
 
 // MO exchange: upper 64 x 64 tiles, K = naux * nocc.
@@ -356,9 +364,20 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
   {
     Strided<true> A{Bt, ntr, 1, 0, naux};
     Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
-    EpiRho E{rho, Omega + s0, ns};
+    const SplitPlan spl = rho_split(naux, ns, ntr);
     SPAN_OPEN(sp, kKRho);
-    CHECK((gemm<128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1)));
+    if (spl.nz > 1) {
+      double* part = nullptr;
+      CHECK(ws_get(c, W_RHOPART, (size_t)(spl.nz * naux * ns), &part));
+      EpiStore E{part, ns, 0, naux * ns, 1.0};
+      CHECK((gemm<128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1, spl)));
+      hipLaunchKernelGGL(k_rho_reduce, dim3(blocks_for(naux * ns)), dim3(256), 0, c->stream, part,
+                         spl.nz, naux, ns, Omega + s0, rho);
+      CHECK(launch_check(c, "k_rho_reduce"));
+    } else {
+      EpiRho E{rho, Omega + s0, ns};
+      CHECK((gemm<128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1)));
+    }
     SPAN_CLOSE(sp);
   }
   {
@@ -585,7 +604,8 @@ int qsgw_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M_to_Z, double* Omega) {
 
 int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                   const double* sqrt_delta, const double* Z, const double* Omega, int64_t s_begin,
-                  int64_t s_count, double* w, int precision) {
+                  int64_t s_count, double* w, double* wh, const double* eps, double eta,
+                  int precision) {
   CHECK(check_common(c, nbf, naux));
   CHECK(check_prec(c, precision));
   if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
@@ -595,6 +615,8 @@ int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const do
                 (long long)s_begin, (long long)(s_begin + s_count), (long long)ntr);
   if (!B_mo || !sqrt_delta || !Z || !Omega || !w)
     return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  if (wh && (!eps || !(eta > 0.0) || !isfinite(eta)))
+    return fail(c, QSGW_ERR_INVALID_ARG, "the pole-weighted copy needs eps and a finite eta > 0");
   double *Bt = nullptr, *rho = nullptr;
   CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
   CHECK(ws_get(c, W_RHO, (size_t)(naux * s_count), &rho));
@@ -602,14 +624,15 @@ int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const do
   hipLaunchKernelGGL(k_gather_bia, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, B_mo,
                      sqrt_delta, naux, nbf, nocc, Bt);
   CHECK(launch_check(c, "k_gather_bia"));
-  CHECK(stage_residues(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s_begin, s_count, rho, w));
+  CHECK(stage_residues(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s_begin, s_count, rho, w, nullptr,
+                       wh, eps, nocc, eta));
   return single_end(c);
 }
 
 int qsgw_sigma(qsgw_ctx* c, int mode, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
-               const double* eps, const double* Omega, double eta, const double* omega,
-               int64_t nomega, const int64_t* states, int64_t nstates, double* out,
-               int accumulate) {
+               const double* wh, const double* eps, const double* Omega, double eta,
+               const double* omega, int64_t nomega, const int64_t* states, int64_t nstates,
+               double* out, int accumulate) {
   CHECK(check_common(c, nbf, 1));
   if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
   if (ns < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need ns >= 1");
@@ -617,7 +640,8 @@ int qsgw_sigma(qsgw_ctx* c, int mode, int64_t nbf, int64_t nocc, int64_t ns, con
   if (!w || !eps || !Omega || !out) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
   if (mode == QSGW_SIGMA_QS_MATRIX) {
     CHECK(single_begin(c, kStageSigma));
-    CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega, eta, out, accumulate ? 1 : 0));
+    CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega, eta, out, accumulate ? 1 : 0, nullptr,
+                         wh));
     return single_end(c);
   }
   if (mode != QSGW_SIGMA_DIAG_GRID) return fail(c, QSGW_ERR_INVALID_ARG, "unknown mode %d", mode);

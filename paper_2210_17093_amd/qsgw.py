@@ -97,8 +97,8 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_mo_transform": ([P, I64, I64, P, P, P, I], I),
         "qsgw_rpa_build": ([P, I64, I64, I64, P, P, P, P, I], I),
         "qsgw_rpa_solve": ([P, I64, P, P], I),
-        "qsgw_residues": ([P, I64, I64, I64, P, P, P, P, I64, I64, P, I], I),
-        "qsgw_sigma": ([P, I, I64, I64, I64, P, P, P, D, P, I64, P, I64, P, I], I),
+        "qsgw_residues": ([P, I64, I64, I64, P, P, P, P, I64, I64, P, P, P, D, I], I),
+        "qsgw_sigma": ([P, I, I64, I64, I64, P, P, P, P, D, P, I64, P, I64, P, I], I),
         "qsgw_hf_core": ([P, I64, I64, I64, P, P, P, P], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
@@ -212,28 +212,38 @@ def qsgw_rpa_solve(ctx: Context, M_to_Z, Omega=None):
 
 
 def qsgw_residues(ctx: Context, B_mo, sqrt_delta, Z, Omega, nocc, s_begin=0, s_count=None,
-                  w=None, precision=PREC_FP64):
+                  w=None, precision=PREC_FP64, weighted=False, eps=None, eta=0.0):
+    """Residues w of excitations [s_begin, s_begin + s_count).  With weighted=True
+    also returns the pole-weighted copy wh (needs eps and eta): (w, wh)."""
     naux, nbf, _ = B_mo.shape
     ntr = nocc * (nbf - nocc)
     if s_count is None:
         s_count = ntr - s_begin
     if w is None:
         w = torch.empty((nbf, nbf, s_count), dtype=torch.float64, device=B_mo.device)
+    wh = None
+    if weighted:
+        wh = torch.empty((nbf, nbf, s_count), dtype=torch.float64, device=B_mo.device)
     ctx.check(lib().qsgw_residues(ctx.handle, nbf, naux, nocc,
                                   _ptr(B_mo, (naux, nbf, nbf), name="B_mo"),
                                   _ptr(sqrt_delta, (ntr,), name="sqrt_delta"),
                                   _ptr(Z, (ntr, ntr), name="Z"), _ptr(Omega, (ntr,), name="Omega"),
                                   s_begin, s_count, _ptr(w, (nbf, nbf, s_count), name="w"),
-                                  precision))
-    return w
+                                  _ptr(wh, (nbf, nbf, s_count), name="wh") if weighted else None,
+                                  _ptr(eps, (nbf,), name="eps") if weighted else None,
+                                  float(eta), precision))
+    return (w, wh) if weighted else w
 
 
-def qsgw_sigma_qs(ctx: Context, w, eps, Omega_block, nocc, eta, out=None, accumulate=False):
+def qsgw_sigma_qs(ctx: Context, w, eps, Omega_block, nocc, eta, out=None, accumulate=False,
+                  wh=None):
     nbf, _, ns = w.shape
     if out is None:
         out = torch.empty((nbf, nbf), dtype=torch.float64, device=w.device)
     ctx.check(lib().qsgw_sigma(ctx.handle, SIGMA_QS_MATRIX, nbf, nocc, ns,
-                               _ptr(w, (nbf, nbf, ns), name="w"), _ptr(eps, (nbf,), name="eps"),
+                               _ptr(w, (nbf, nbf, ns), name="w"),
+                               _ptr(wh, (nbf, nbf, ns), name="wh") if wh is not None else None,
+                               _ptr(eps, (nbf,), name="eps"),
                                _ptr(Omega_block, (ns,), name="Omega"), float(eta), None, 0, None, 0,
                                _ptr(out, (nbf, nbf), name="out"), int(bool(accumulate))))
     return out
@@ -247,7 +257,8 @@ def qsgw_sigma_diag(ctx: Context, w, eps, Omega_block, nocc, eta, omega, states,
     if out is None:
         out = torch.empty((nstates, nomega, 2), dtype=torch.float64, device=w.device)
     ctx.check(lib().qsgw_sigma(ctx.handle, SIGMA_DIAG_GRID, nbf, nocc, ns,
-                               _ptr(w, (nbf, nbf, ns), name="w"), _ptr(eps, (nbf,), name="eps"),
+                               _ptr(w, (nbf, nbf, ns), name="w"), None,
+                               _ptr(eps, (nbf,), name="eps"),
                                _ptr(Omega_block, (ns,), name="Omega"), float(eta),
                                _ptr(omega, (nomega,), name="omega"), nomega,
                                _ptr(states, (nstates,), torch.int64, name="states"), nstates,

@@ -168,6 +168,18 @@ def test_sigma_qs_matrix(q, ctx, shape, eta):
     np.testing.assert_array_equal(V, V.T)
     bound = 1e-12 * _sigma_bound(w, p.eps0, Om, nocc, eta) + 1e-300
     assert np.all(np.abs(V - V_ref) <= bound)
+    # the pole-weighted copy from the residue step gives the same matrix
+    dB = dev(B_mo)
+    M, sq = q.qsgw_rpa_build(ctx, dB, de, nocc)
+    Z, Omg = q.qsgw_rpa_solve(ctx, M)
+    wg, whg = q.qsgw_residues(ctx, dB, sq, Z, Omg, nocc, weighted=True, eps=de, eta=eta)
+    V2 = host(q.qsgw_sigma_qs(ctx, wg, de, Omg, nocc, eta, wh=whg))
+    V3 = host(q.qsgw_sigma_qs(ctx, wg, de, Omg, nocc, eta))
+    np.testing.assert_array_equal(V2, V2.T)
+    # same residues, weights applied in the residue epilogue vs while loading
+    assert np.all(np.abs(V2 - V3) <= 2 * bound)
+    # residues from the GPU eigenvectors: upstream rounding, relative to |V|
+    assert np.max(np.abs(V2 - V_ref)) <= 1e-9 * np.abs(V_ref).max()
     # two streamed blocks accumulate to the same matrix
     ntr = Om.size
     if ntr >= 2:
