@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of one RI qsGW iteration on one MI355X.
 
-A step is one qsGW iteration of the plain FP64 path through the C-ABI
-(qsgw_iterate, max_iter = 1) from the same starting orbitals: AO->MO
-transform, Casida build, rocSOLVER eigensolve of the Casida matrix, residues,
-qsGW self-energy matrix, Fock build, rocSOLVER eigensolve of the Fock matrix.
-The eigensolves are timed apart from the hot path.  The reported value is the
-sustained algorithmic FLOP rate of the hot path (all stages except the two
-eigensolves), from HIP events recorded inside the library on its stream;
-ms_per_step is the wall time of the whole iteration including eigensolves.
+A step is one qsGW iteration through the C-ABI (qsgw_iterate, max_iter = 1)
+from the same starting orbitals, run twice per step: the plain FP64 path and
+the FP32 matrix-core variant (MO transform, Casida build and residue products
+in FP32 with FP64 outputs; eigensolves, sqrt(Delta), the self-energy product
+and the Fock update in FP64).  Each run does the AO->MO transform, Casida
+build, rocSOLVER eigensolve of the Casida matrix, residues, qsGW self-energy
+matrix, Fock build and rocSOLVER eigensolve of the Fock matrix.
 
-    python bench.py [--steps K] [--warmup W] [--config cfg2] [--no-cpu-baseline]
+The eigensolves are timed apart from the hot path.  `value` is the sustained
+algorithmic FLOP rate (FP64-equivalent FLOPs of SURVEY-style counting) of the
+hot path of the fastest variant whose per-state quasiparticle energies stay
+within 1 meV of the FP64 step from the same start, from HIP events recorded
+inside the library on its stream; ms_per_step is the wall time of one step
+(both variants, eigensolves included).
+
+    python bench.py [--steps K] [--warmup W] [--config cfg2] [--precision both|fp64|fp32]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -27,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "qsGW iteration time & sustained TFLOP/s vs FP64 plain path at ≤1 meV QP error"
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+HARTREE_MEV = 27211.386
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of a kernel at the cfg2 workload, from the rocprofv3
@@ -34,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/residue_w_cfg2_hbm_counters.md).  Only valid for the kernel build
 # the counters were taken on: set an entry to None whenever that kernel changes.
 MEASURED_TRAFFIC_BYTES = {
-    ("cfg2", "residue_w"): 49.78e9,
+    ("cfg2", "fp64", "residue_w"): 49.78e9,
 }
 
 
@@ -99,6 +108,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both",
+                    help="both: time the FP64 plain step and the FP32 matrix-core step from the "
+                         "same start and report their per-state QP difference")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc passes only: run the hot-path entry points once "
                          "each (MO transform, Casida build, residues with the pole-weighted copy, "
@@ -159,36 +171,64 @@ def main():
     h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
     torch.cuda.synchronize()
 
-    def step():
+    def step(prec):
         C.copy_(C0)
         e.copy_(e0)
-        return q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1)
+        return q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1, precision=prec)
 
+    variants = {"fp64": q.PREC_FP64, "fp32": q.PREC_FP32}
+    if args.precision != "both":
+        variants = {args.precision: variants[args.precision]}
     for i in range(args.warmup):
         log(f"[bench] warmup {i + 1}/{args.warmup}")
-        step()
+        for v in variants.values():
+            step(v)
     torch.cuda.synchronize()
-    reps = []
+    reps = {k: [] for k in variants}
+    eps_out = {}
     t0 = time.perf_counter()
     for i in range(args.steps):
-        rc, rep, _ = step()
-        reps.append(rep)
-        log(f"[bench] step {i + 1}/{args.steps}: hot "
-            f"{sum(v for k, v in rep['ms'].items() if not k.startswith('eig')):.2f} ms, "
-            f"eig_rpa {rep['ms']['eig_rpa']:.1f} ms, eig_fock {rep['ms']['eig_fock']:.1f} ms")
+        for name, v in variants.items():
+            rc, rep, _ = step(v)
+            reps[name].append(rep)
+            eps_out[name] = e.cpu().numpy()
+            log(f"[bench] step {i + 1}/{args.steps} {name}: hot "
+                f"{sum(x for k, x in rep['ms'].items() if not k.startswith('eig')):.2f} ms, "
+                f"eig_rpa {rep['ms']['eig_rpa']:.1f} ms, eig_fock {rep['ms']['eig_fock']:.1f} ms")
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
 
-    hot_ms = float(np.mean([sum(v for k, v in r["ms"].items() if not k.startswith("eig"))
-                            for r in reps]))
-    hot_flops = reps[0]["hot_flops"]
-    value = hot_flops / (hot_ms * 1e-3) / 1e12
-    kern_ms = {k: float(np.mean([r["kernel_ms"][k] for r in reps])) for k in reps[0]["kernel_ms"]}
-    launches = reps[0]["kernel_launches"]
-    dom = max(kern_ms, key=kern_ms.get)
-    per_launch_ms = kern_ms[dom] / max(1, launches[dom])
-    flops_per_launch = reps[0]["kernel_flops"][dom] / max(1, launches[dom])
-    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    def summary(rs, peak):
+        hot_ms = float(np.mean([sum(v for k, v in r["ms"].items() if not k.startswith("eig"))
+                                for r in rs]))
+        kern_ms = {k: float(np.mean([r["kernel_ms"][k] for r in rs])) for k in rs[0]["kernel_ms"]}
+        dom = max(kern_ms, key=kern_ms.get)
+        launches = rs[0]["kernel_launches"][dom]
+        per_launch_ms = kern_ms[dom] / max(1, launches)
+        flops_per_launch = rs[0]["kernel_flops"][dom] / max(1, launches)
+        achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+        return dict(hot_ms=hot_ms, kern_ms=kern_ms, dom=dom, per_launch_ms=per_launch_ms,
+                    flops_per_launch=flops_per_launch, achieved=achieved, peak=peak,
+                    eig_rpa=float(np.mean([r["ms"]["eig_rpa"] for r in rs])),
+                    eig_fock=float(np.mean([r["ms"]["eig_fock"] for r in rs])),
+                    stage_ms={k: float(np.mean([r["ms"][k] for r in rs])) for k in rs[0]["ms"]})
+
+    peaks = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS}
+    sums = {k: summary(reps[k], peaks[k]) for k in reps}
+    hot_flops = next(iter(reps.values()))[0]["hot_flops"]
+    qp = None
+    if "fp64" in eps_out and "fp32" in eps_out:
+        err = np.abs(eps_out["fp32"] - eps_out["fp64"]) * HARTREE_MEV
+        qp = dict(max_meV=float(err.max()), median_meV=float(np.median(err)),
+                  states_over_1meV=int((err > 1.0).sum()), states=int(err.size))
+    # headline: the fastest variant whose per-state QP error against FP64 is <= 1 meV
+    pick = "fp64"
+    if "fp32" in sums and (qp is None and args.precision == "fp32" or qp and qp["max_meV"] <= 1.0):
+        pick = "fp32"
+    if args.precision == "fp32" and "fp64" not in sums:
+        pick = "fp32"
+    S = sums[pick]
+    value = hot_flops / (S["hot_ms"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -200,21 +240,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if pick == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": workload_name(p, eta), "precision": "fp64-plain"},
-        "hot_path_ms": round(hot_ms, 3),
-        "eig_rpa_ms": round(float(np.mean([r["ms"]["eig_rpa"] for r in reps])), 3),
-        "eig_fock_ms": round(float(np.mean([r["ms"]["eig_fock"] for r in reps])), 3),
-        "stage_ms": {k: round(float(np.mean([r["ms"][k] for r in reps])), 3) for k in reps[0]["ms"]},
-        "kernel_ms": {k: round(v, 3) for k, v in kern_ms.items()},
+        "config": {"workload": workload_name(p, eta), "precision": pick},
+        "hot_path_ms": round(S["hot_ms"], 3),
+        "eig_rpa_ms": round(S["eig_rpa"], 3),
+        "eig_fock_ms": round(S["eig_fock"], 3),
+        "stage_ms": {k: round(v, 3) for k, v in S["stage_ms"].items()},
+        "kernel_ms": {k: round(v, 3) for k, v in S["kern_ms"].items()},
         "hot_flops": hot_flops,
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": MEASURED_TRAFFIC_BYTES.get((args.config, dom)),
-                     "flops_per_launch": flops_per_launch, "ms_per_launch": round(per_launch_ms, 4)},
+        "roofline": {"bound": "mfma", "kernel": S["dom"], "achieved": round(S["achieved"], 3),
+                     "peak": S["peak"], "unit": "TFLOP/s", "frac": round(S["achieved"] / S["peak"], 4),
+                     "traffic": MEASURED_TRAFFIC_BYTES.get((args.config, pick, S["dom"])),
+                     "flops_per_launch": S["flops_per_launch"],
+                     "ms_per_launch": round(S["per_launch_ms"], 4)},
+        "variants": {k: {"hot_path_ms": round(v["hot_ms"], 3),
+                         "sustained_tflops": round(hot_flops / (v["hot_ms"] * 1e-3) / 1e12, 3),
+                         "dominant_kernel": v["dom"], "dominant_frac": round(v["achieved"] / v["peak"], 4)}
+                     for k, v in sums.items()},
     }
+    if qp is not None:
+        out["qp_error_fp32_vs_fp64"] = qp
+        out["speedup_fp32_vs_fp64"] = round(sums["fp64"]["hot_ms"] / sums["fp32"]["hot_ms"], 3)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, eta, hot_flops)

@@ -30,6 +30,33 @@
 namespace qsgw {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core instruction per compute type.  Both take the same 16 x 4 / 4 x 16
+// operand fragments (lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]) and
+// produce a 16 x 16 tile as four values per lane; `row` gives the tile row of
+// value q of lane l (column l % 16).
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  __device__ __forceinline__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ __forceinline__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // f64 16x16x4 on gfx950: rows interleaved across the four lane groups
+  __device__ __forceinline__ static int row(int lane, int q) { return 4 * q + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  __device__ __forceinline__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ __forceinline__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
 
 // Element (r, k) at p[b*sb + r*sr + k*sk]; rows >= `rows` or k >= K read 0.
 // Strided operands take the branch-free tile loader of the kernel: one base
@@ -210,7 +237,7 @@ struct AllTiles {
 // TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
 // epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
 template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles,
-          int BK = 16>
+          int BK = 16, class T = double>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
                                                        int64_t K, int64_t kchunk, int64_t tiles_m,
                                                        int64_t tiles_n, int64_t nbatch, FILT filt) {
@@ -229,14 +256,17 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   static_assert(BM % 32 == 0 && BN % 32 == 0, "tile must split into 2x2 waves of 16x16 MFMA tiles");
   static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
 
-  // One LDS block: the double-buffered operand tiles during the K loop, then
-  // the staging area of the epilogue (WM rows of the C tile at a time).
+  // One LDS block: the double-buffered operand tiles (compute type T) during
+  // the K loop, then the FP64 staging area of the epilogue (WM rows of the C
+  // tile at a time).
   constexpr int LDC = BN + 1;
-  constexpr int SMEM = 2 * (SZA + SZB);
-  static_assert(WM * LDC <= SMEM, "epilogue staging must fit in the operand buffers");
-  __shared__ double smem[SMEM];
-  double (*As)[SZA] = reinterpret_cast<double (*)[SZA]>(smem);
-  double (*Bs)[SZB] = reinterpret_cast<double (*)[SZB]>(smem + 2 * SZA);
+  constexpr size_t OPER_BYTES = 2 * (size_t)(SZA + SZB) * sizeof(T);
+  constexpr size_t STAGE_BYTES = (size_t)WM * LDC * sizeof(double);
+  constexpr size_t SMEM_BYTES = OPER_BYTES > STAGE_BYTES ? OPER_BYTES : STAGE_BYTES;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  T (*As)[SZA] = reinterpret_cast<T (*)[SZA]>(smem);
+  T (*Bs)[SZB] = reinterpret_cast<T (*)[SZB]>(smem + 2 * (size_t)SZA * sizeof(T));
+  typedef Mfma<T> MM;
   // element (r, k) of the staged tiles
   auto a_at = [](int r, int k) { return AK ? r * (BK + 1) + k : k * (BM + 1) + r; };
   auto b_at = [](int r, int k) { return BKC ? r * (BK + 1) + k : k * (BN + 1) + r; };
@@ -263,11 +293,11 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   const int wm = (wave >> 1) * WM;
   const int wn = (wave & 1) * WN;
 
-  f64x4 acc[TM][TN];
+  typename MM::acc_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = MM::zero();
 
   double ra[EA], rb[EB];
 
@@ -281,14 +311,14 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
       const int idx = e * 256 + tid;
       const int kk = OA::kContig ? (idx % BK) : (idx / BM);
       const int r = OA::kContig ? (idx / BK) : (idx % BM);
-      As[buf][a_at(r, kk)] = ra[e];
+      As[buf][a_at(r, kk)] = (T)ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = e * 256 + tid;
       const int kk = OB::kContig ? (idx % BK) : (idx / BN);
       const int r = OB::kContig ? (idx / BK) : (idx % BN);
-      Bs[buf][b_at(r, kk)] = rb[e];
+      Bs[buf][b_at(r, kk)] = (T)rb[e];
     }
   };
 
@@ -301,12 +331,12 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   for (int64_t it = 0; it < nk; ++it) {
     const int cur = (int)(it & 1);
     if (it + 1 < nk) gload(kb0 + (it + 1) * BK);
-    const double* as = As[cur];
-    const double* bs = Bs[cur];
+    const T* as = As[cur];
+    const T* bs = Bs[cur];
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int krow = ks * 4 + (lane >> 4);
-      double a[TM], b[TN];
+      T a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) a[i] = as[a_at(wm + i * 16 + (lane & 15), krow)];
 #pragma unroll
@@ -315,7 +345,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
     }
     if (it + 1 < nk) sstore(cur ^ 1);
     __syncthreads();
@@ -328,7 +358,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   // of the accumulator registers stops the compiler from copying all of them
   // to VGPRs at once, which would halve the occupancy of the K loop.
   if (nk > 0) __syncthreads();  // operand buffers are free once every wave is done
-  double* Cs = smem;
+  double* Cs = reinterpret_cast<double*>(smem);
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
     if ((wave >> 1) == pass) {
@@ -338,7 +368,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
         for (int j = 0; j < TN; ++j)
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            Cs[(i * 16 + 4 * q + (lane >> 4)) * LDC + wn + j * 16 + (lane & 15)] = acc[i][j][q];
+            Cs[(i * 16 + MM::row(lane, q)) * LDC + wn + j * 16 + (lane & 15)] = (double)acc[i][j][q];
     }
     __syncthreads();
     for (int idx = tid; idx < WM * BN; idx += 256) {

@@ -147,9 +147,9 @@ inline SplitPlan split_plan(int64_t K, int64_t want) {
 
 // Launch the FP64 GEMM engine.  TRI requires M == N.  `sp` is the K-split plan
 // (partial-sum buffers must hold sp.nz slices).
-template <int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
-int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
-         int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
+template <class T, int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
+int gemm_t(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
+           int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
   const int64_t tm = (M + BM - 1) / BM;
   const int64_t tn = (N + BN - 1) / BN;
   const int64_t ntiles = TRI ? tm * (tm + 1) / 2 : tm * tn;
@@ -158,10 +158,21 @@ int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N,
   if (ntiles <= 0 || batch <= 0 || K <= 0) return QSGW_OK;
   const int64_t total = ntiles * batch * splits;
   if (total > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT>), dim3((unsigned)total),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT, 16, T>), dim3((unsigned)total),
                      dim3(256), 0, c->stream, a, b, e, M, N, K, kchunk, tm, tn, batch, f);
   return launch_check(c, what);
 }
+
+// FP64 products.
+template <int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
+int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
+         int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
+  return gemm_t<double, BM, BN, TRI>(c, what, a, b, e, M, N, K, batch, sp, f);
+}
+
+// Longest K run one FP32-accumulating workgroup covers before its partial
+// sum is handed to the FP64 split-K reduction.
+constexpr int64_t kFp32MaxK = 4096;
 
 // Split count that gives roughly `target` workgroups for a tiny output.
 inline int64_t splits_for(int64_t tiles, int64_t K, int64_t target = 2048) {
@@ -179,10 +190,12 @@ inline SplitPlan sigma_split(int64_t nbf, int64_t ns) {
 
 // rho product: 128 x 128 tiles of the naux x ns output, K = ntr; split only
 // when the tiles alone leave the chip under-filled.
-inline SplitPlan rho_split(int64_t naux, int64_t ns, int64_t ntr) {
+inline SplitPlan rho_split(int64_t naux, int64_t ns, int64_t ntr, int64_t maxk) {
   const int64_t tiles = ((naux + 127) / 128) * ((ns + 127) / 128);
-  if (tiles >= 2048) return {ntr, 1};
-  return split_plan(ntr, splits_for(tiles, ntr, 2048));
+  int64_t want = tiles >= 2048 ? 1 : splits_for(tiles, ntr, 2048);
+  const int64_t need = (ntr + maxk - 1) / maxk;  // keep each split's K <= maxk
+  if (want < need) want = need;
+  return split_plan(ntr, want);
 }
 
 // MO exchange: upper 64 x 64 tiles, K = naux * nocc.
@@ -276,16 +289,17 @@ int pair_blocks(qsgw_ctx* c, int64_t nbf, const int32_t** tab, int64_t* n) {
 // ------------------------------------------------------------- stages ----
 
 // Eq. (16): T = B_ao C (one GEMM over all P), B_mo[P] = C^T T[P] (batched
-// over P, upper tiles only, mirrored).
-int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
-                       const double* C, double* T, double* B_mo, Spans* sp = nullptr) {
+// over P, upper tiles only, mirrored).  CT is the matrix-core type.
+template <class CT>
+int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
+                         const double* C, double* T, double* B_mo, Spans* sp) {
   const int64_t nn = nbf * nbf;
   {
     Strided<true> A{B_ao, nbf, 1, 0, naux * nbf};
     Strided<false> B{C, 1, nbf, 0, nbf};
     EpiStore E{T, nbf, 0, 0, 1.0};
     SPAN_OPEN(sp, kKMo1);
-    CHECK((gemm<128, 64, false>(c, "mo_transform/1", A, B, E, naux * nbf, nbf, nbf, 1)));
+    CHECK((gemm_t<CT, 128, 64, false>(c, "mo_transform/1", A, B, E, naux * nbf, nbf, nbf, 1)));
     SPAN_CLOSE(sp);
   }
   {
@@ -293,16 +307,24 @@ int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_a
     Strided<false> B{T, 1, nbf, nn, nbf};
     EpiStore E{B_mo, nbf, nn, 0, 1.0};
     SPAN_OPEN(sp, kKMo2);
-    CHECK((gemm<64, 64, true>(c, "mo_transform/2", A, B, E, nbf, nbf, nbf, naux)));
+    CHECK((gemm_t<CT, 64, 64, true>(c, "mo_transform/2", A, B, E, nbf, nbf, nbf, naux)));
     SPAN_CLOSE(sp);
   }
   return QSGW_OK;
 }
 
+int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
+                       const double* C, double* T, double* B_mo, Spans* sp = nullptr,
+                       int prec = QSGW_PREC_FP64) {
+  if (prec == QSGW_PREC_FP32) return stage_mo_transform_t<float>(c, nbf, naux, B_ao, C, T, B_mo, sp);
+  return stage_mo_transform_t<double>(c, nbf, naux, B_ao, C, T, B_mo, sp);
+}
+
 // Eqs. (12)-(14): Delta, sqrt(Delta), Bt = B_ia sqrt(Delta), M = Delta^2 + 4 Bt^T Bt.
+// Delta and sqrt(Delta) are always FP64; the product runs on the type of prec.
 int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                     const double* eps, double* M, double* sqrt_delta, double* delta, double* Bt,
-                    int* flags, Spans* sp = nullptr) {
+                    int* flags, Spans* sp = nullptr, int prec = QSGW_PREC_FP64) {
   const int64_t nv = nbf - nocc, ntr = nocc * nv;
   SPAN_OPEN(sp, kKCasida);
   hipLaunchKernelGGL(k_transitions, dim3(blocks_for(ntr)), dim3(256), 0, c->stream, eps, nocc, nv,
@@ -313,7 +335,10 @@ int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const 
   CHECK(launch_check(c, "k_gather_bia"));
   Strided<false> A{Bt, 1, ntr, 0, ntr};
   EpiCasida E{M, delta, ntr};
-  CHECK((gemm<128, 128, true>(c, "rpa_build", A, A, E, ntr, ntr, naux, 1)));
+  if (prec == QSGW_PREC_FP32)
+    CHECK((gemm_t<float, 128, 128, true>(c, "rpa_build", A, A, E, ntr, ntr, naux, 1)));
+  else
+    CHECK((gemm<128, 128, true>(c, "rpa_build", A, A, E, ntr, ntr, naux, 1)));
   SPAN_CLOSE(sp);
   return QSGW_OK;
 }
@@ -357,26 +382,28 @@ int stage_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M, double* Omega) {
 }
 
 // Eq. (18) for excitations [s0, s0 + ns): rho' = sqrt(2/Omega) Bt Z^T, w = B_mo^T rho'.
-int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
-                   const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
-                   double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
-                   const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0) {
+template <class CT>
+int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
+                     const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
+                     double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
+                     double eta) {
   {
     Strided<true> A{Bt, ntr, 1, 0, naux};
     Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
-    const SplitPlan spl = rho_split(naux, ns, ntr);
+    const int64_t maxk = sizeof(CT) == sizeof(float) ? kFp32MaxK : ntr;
+    const SplitPlan spl = rho_split(naux, ns, ntr, maxk);
     SPAN_OPEN(sp, kKRho);
     if (spl.nz > 1) {
       double* part = nullptr;
       CHECK(ws_get(c, W_RHOPART, (size_t)(spl.nz * naux * ns), &part));
       EpiStore E{part, ns, 0, naux * ns, 1.0};
-      CHECK((gemm<128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1, spl)));
+      CHECK((gemm_t<CT, 128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1, spl)));
       hipLaunchKernelGGL(k_rho_reduce, dim3(blocks_for(naux * ns)), dim3(256), 0, c->stream, part,
                          spl.nz, naux, ns, Omega + s0, rho);
       CHECK(launch_check(c, "k_rho_reduce"));
     } else {
       EpiRho E{rho, Omega + s0, ns};
-      CHECK((gemm<128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1)));
+      CHECK((gemm_t<CT, 128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1)));
     }
     SPAN_CLOSE(sp);
   }
@@ -389,10 +416,22 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
     Strided<false> B{rho, 1, ns, 0, ns};
     EpiPairResidue E{w, wh, blocks, eps, Omega + s0, nbf, nocc, ns, eta};
     SPAN_OPEN(sp, kKW);
-    CHECK((gemm<128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
+    CHECK((gemm_t<CT, 128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
     SPAN_CLOSE(sp);
   }
   return QSGW_OK;
+}
+
+int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
+                   const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
+                   double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
+                   const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
+                   int prec = QSGW_PREC_FP64) {
+  if (prec == QSGW_PREC_FP32)
+    return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
+                                   eps, nocc, eta);
+  return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
+                                  eps, nocc, eta);
 }
 
 // Eq. (19) contribution of one excitation block: V (+)= 1/2 (G + G^T).
@@ -492,8 +531,8 @@ int check_common(qsgw_ctx* c, int64_t nbf, int64_t naux) {
 }
 
 int check_prec(qsgw_ctx* c, int precision) {
-  if (precision == QSGW_PREC_FP64) return QSGW_OK;
-  if (precision == QSGW_PREC_FP32 || precision == QSGW_PREC_SPLIT_BF16)
+  if (precision == QSGW_PREC_FP64 || precision == QSGW_PREC_FP32) return QSGW_OK;
+  if (precision == QSGW_PREC_SPLIT_BF16)
     return fail(c, QSGW_ERR_UNSUPPORTED, "precision %d is not available in this version",
                 precision);
   return fail(c, QSGW_ERR_INVALID_ARG, "unknown precision %d", precision);
@@ -568,7 +607,7 @@ int qsgw_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao
   double* T = nullptr;
   CHECK(ws_get(c, W_T, (size_t)(naux * nbf * nbf), &T));
   CHECK(single_begin(c, kStageMo));
-  CHECK(stage_mo_transform(c, nbf, naux, B_ao, C, T, B_mo));
+  CHECK(stage_mo_transform(c, nbf, naux, B_ao, C, T, B_mo, nullptr, precision));
   return single_end(c);
 }
 
@@ -586,7 +625,8 @@ int qsgw_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const d
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
   HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
   CHECK(single_begin(c, kStageRpa));
-  CHECK(stage_rpa_build(c, nbf, naux, nocc, B_mo, eps, M, sqrt_delta, delta, Bt, flags));
+  CHECK(stage_rpa_build(c, nbf, naux, nocc, B_mo, eps, M, sqrt_delta, delta, Bt, flags, nullptr,
+                        precision));
   CHECK(single_end(c));
   int bad = 0;
   CHECK(read_flag(c, flags, &bad));
@@ -625,7 +665,7 @@ int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const do
                      sqrt_delta, naux, nbf, nocc, Bt);
   CHECK(launch_check(c, "k_gather_bia"));
   CHECK(stage_residues(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s_begin, s_count, rho, w, nullptr,
-                       wh, eps, nocc, eta));
+                       wh, eps, nocc, eta, precision));
   return single_end(c);
 }
 
@@ -799,11 +839,12 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     Spans sp;
     sp.c = c;
     CHECK(sp.open(kStageMo));
-    CHECK(stage_mo_transform(c, nbf, naux, p->B_ao, C, T, Bmo, &sp));
+    CHECK(stage_mo_transform(c, nbf, naux, p->B_ao, C, T, Bmo, &sp, o->precision));
     CHECK(sp.close());
     HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
     CHECK(sp.open(kStageRpa));
-    CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, M, sqd, delta, Bt, flags, &sp));
+    CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, M, sqd, delta, Bt, flags, &sp,
+                          o->precision));
     CHECK(sp.close());
     {
       int bad = 0;
@@ -817,7 +858,7 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
       CHECK(sp.open(kStageRes));
       CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps, nocc,
-                           o->eta));
+                           o->eta, o->precision));
       CHECK(sp.close());
       CHECK(sp.open(kStageSigma));
       CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,

@@ -317,7 +317,7 @@ def test_error_paths(q, ctx):
     p = problem(10, 12, 3)
     dB, dC, de = dev(p.B_ao), dev(p.C0), dev(p.eps0)
     with pytest.raises(q.QsgwError) as e:
-        q.qsgw_mo_transform(ctx, dB, dC, precision=q.PREC_FP32)
+        q.qsgw_mo_transform(ctx, dB, dC, precision=q.PREC_SPLIT_BF16)
     assert e.value.code == q.ERR_UNSUPPORTED
     B_mo = q.qsgw_mo_transform(ctx, dB, dC)
     with pytest.raises(q.QsgwError) as e:
@@ -344,3 +344,47 @@ def test_error_paths(q, ctx):
     rc, rep, it = q.qsgw_iterate(ctx, dB, h, 3, de.clone(), dC.clone(), 1e-3, tol=0.0,
                                  max_iter=1)
     assert rc == q.NOT_CONVERGED and not rep["converged"]
+
+
+# ------------------------------------------- FP32 matrix-core variant -----
+# The FP32 path rounds every operand of the MO transform, Casida and residue
+# products to FP32 and accumulates in FP32 over at most 4096 terms (longer K
+# is split and reduced in FP64).  Bounds are relative: unit roundoff 2^-24
+# times the length of each contraction, on sums of absolute terms.
+FP32_QP_TOL = 1e-3 / 27.211386  # 1 meV in Ha
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 2), (37, 53, 9), (130, 260, 17)])
+def test_fp32_products(q, ctx, shape):
+    nbf, naux, nocc = shape
+    log("fp32 products", shape)
+    p = problem(*shape)
+    u = 2.0 ** -24
+    ref = O.mo_transform(p.B_ao, p.C0)
+    got = host(q.qsgw_mo_transform(ctx, dev(p.B_ao), dev(p.C0), precision=q.PREC_FP32))
+    absb = O.mo_transform(np.abs(p.B_ao), np.abs(p.C0))
+    assert np.all(np.abs(got - ref) <= 4 * nbf * u * absb + 1e-300)
+    np.testing.assert_array_equal(got, got.transpose(0, 2, 1))
+    M_ref, sq_ref = O.rpa_hermitian(ref, p.eps0, nocc)
+    M, sq = q.qsgw_rpa_build(ctx, dev(ref), dev(p.eps0), nocc, precision=q.PREC_FP32)
+    Mh = host(M)
+    Bt = np.abs(ref[:, :nocc, nocc:].reshape(naux, -1)) * sq_ref[None, :]
+    assert np.all(np.abs(Mh - M_ref) <= 4 * (2 * naux * u) * (Bt.T @ Bt) + 1e-12 * np.abs(M_ref).max())
+    np.testing.assert_array_equal(Mh, Mh.T)
+
+
+@pytest.mark.parametrize("shape", [(24, 96, 5), (70, 200, 11)])
+def test_fp32_iteration_qp_error(q, ctx, shape):
+    """One iteration in FP32 against the FP64 oracle: per-state QP error <= 1 meV."""
+    log("fp32 iteration", shape)
+    p = make_config("cfg1") if shape == (24, 96, 5) else problem(*shape)
+    eta = 1e-3
+    h_ref = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+    st = O.qsgw_step(p.B_ao, h_ref, p.C0, p.eps0, p.nocc, eta)
+    dB, h, dC, de = _gpu_start(q, ctx, p)
+    rc, rep, it = q.qsgw_iterate(ctx, dB, h, p.nocc, de, dC, eta, tol=0.0, max_iter=1,
+                                 precision=q.PREC_FP32)
+    err = np.abs(host(de) - st["eps"])
+    log(f"  FP32 per-state QP error: max {err.max() * 27211.386:.4f} meV, "
+        f"median {np.median(err) * 27211.386:.5f} meV")
+    assert err.max() <= FP32_QP_TOL
