@@ -57,7 +57,7 @@ extern "C" {
 
 /* Arithmetic of the contractions (MO transform, RPA build, residues). */
 #define QSGW_PREC_FP64 0
-#define QSGW_PREC_FP32 1       /* not in this version: QSGW_ERR_UNSUPPORTED */
+#define QSGW_PREC_FP32 1       /* FP32 matrix-core products, FP64 accumulation across K chunks */
 #define QSGW_PREC_SPLIT_BF16 2 /* not in this version: QSGW_ERR_UNSUPPORTED */
 
 /* qsgw_sigma modes. */
@@ -197,7 +197,12 @@ typedef struct {
   double mix;       /* Vc <- mix Vc + (1 - mix) Vc_prev, in (0, 1]; 1 = no mixing */
   int fock_mode;    /* QSGW_FOCK_FULL_JK */
   int64_t s_block;  /* excitations per streamed residue block; 0 = automatic */
+  int64_t flags;    /* QSGW_OPT_* bits */
 } qsgw_options;
+
+/* qsgw_options.flags, qsgw_iterate_batched only: run the kernel segments
+ * between eigensolves from hipGraphs captured on the first iteration. */
+#define QSGW_OPT_GRAPH 1
 
 typedef struct {
   int64_t iterations; /* iterations done in this call */
@@ -223,6 +228,38 @@ typedef struct {
  */
 int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const qsgw_options* opt,
                  qsgw_report* rep);
+
+/*
+ * Batched qsGW iterations for nmol independent molecules of different sizes
+ * (hundreds of small molecules per call).
+ * probs, states: host arrays of nmol entries whose pointers are device
+ * pointers as in qsgw_iterate (states[i].Vc is not used); reports: host array
+ * of nmol entries or NULL.  The arrays are read during the call only.
+ * Every stage runs as one launch over all molecules: grouped matrix-core
+ * GEMMs (a job table with one entry per molecule, each workgroup finding its
+ * molecule by binary search) and segment kernels for the element-wise steps.
+ * Each molecule's arithmetic is that of qsgw_iterate (same tile shapes, K
+ * splits and epilogues).  The Casida and Fock eigensolves are rocSOLVER
+ * strided-batched dsyevd calls, one per size bucket: each matrix is stored
+ * padded to its bucket size with zero coupling and a diagonal above its
+ * Gershgorin bound, so its own eigenpairs come first.  With QSGW_OPT_GRAPH
+ * the kernel segments between eigensolves are captured into hipGraphs on the
+ * first iteration and replayed on every iteration (this needs a context
+ * created on a stream other than the legacy default stream).
+ * Every molecule runs opt->max_iter iterations (opt->mix must be 1 and
+ * opt->s_block 0; precision FP64 or FP32); a report's converged field says
+ * whether some iteration met tol, max_deps holds every iteration's
+ * max |d eps|.  Times are whole-batch figures, the same in every report:
+ * ms_stage[2] and ms_stage[6] the Casida and Fock eigensolves, ms_stage[0]
+ * every other step; ms_kernel and kernel_launches per kernel group when the
+ * segments run eagerly (zero with QSGW_OPT_GRAPH).  hot_flops and
+ * kernel_flops are the molecule's own algorithmic FLOPs per iteration.
+ * Synchronizes once per iteration.
+ * Returns QSGW_OK if every molecule met tol, QSGW_NOT_CONVERGED otherwise;
+ * an error names the first failing molecule.
+ */
+int qsgw_iterate_batched(qsgw_ctx* ctx, int64_t nmol, const qsgw_problem* probs,
+                         qsgw_state* states, const qsgw_options* opt, qsgw_report* reports);
 
 #ifdef __cplusplus
 }

@@ -188,6 +188,22 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
   }
 }
 
+// Host check: the tile loaders address a thread's elements with one 32-bit
+// byte offset from a uniform origin; it must fit for the operand's strides
+// (BR rows x BK k per tile, 256 threads).
+template <class OP>
+inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16) {
+  if constexpr (is_pair_rows_op<OP>::value) {
+    return (uint64_t)op.n * (uint64_t)op.n * 8u < (1ull << 32);
+  } else if constexpr (is_strided_op<OP>::value) {
+    const uint64_t rl = OP::kContig ? 256 / BK - 1 : BR - 1;
+    const uint64_t kl = OP::kContig ? BK - 1 : 256 / BR - 1;
+    return (rl * (uint64_t)op.sr + kl * (uint64_t)op.sk) * 8u < (1ull << 32);
+  } else {
+    return true;
+  }
+}
+
 // Hardware dispatches consecutive workgroup ids round-robin over the 8 XCDs
 // (each with its own L2).  Renumber so that each XCD walks a contiguous range
 // of logical tiles: neighbouring tiles share operand panels in one L2.
@@ -236,11 +252,11 @@ struct AllTiles {
 
 // TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
 // epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
-template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles,
-          int BK = 16, class T = double>
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
-                                                       int64_t K, int64_t kchunk, int64_t tiles_m,
-                                                       int64_t tiles_n, int64_t nbatch, FILT filt) {
+template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT, int BK, class T>
+__device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& epi, int64_t M,
+                                          int64_t N, int64_t K, int64_t kchunk, int64_t tiles_m,
+                                          int64_t tiles_n, int64_t nbatch, const FILT& filt,
+                                          int64_t lid) {
   static_assert(BK % 4 == 0, "BK is a multiple of the MFMA depth");
   // LDS layout per operand: a k-contiguous operand is kept [r][k] (pitch BK+1)
   // so global rows land in LDS rows without a transpose; an r-contiguous one
@@ -276,7 +292,6 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
   // gives each XCD a contiguous logical range, so the tiles that share one
   // K chunk (or one batch entry) share one L2.
   const int64_t ntiles = TRI ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
-  const int64_t lid = xcd_logical_id((int64_t)blockIdx.x, (int64_t)gridDim.x);
   const int64_t id = lid % ntiles;
   const int64_t rest = lid / ntiles;
   const int64_t batch = rest % nbatch;
@@ -386,6 +401,48 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, i
     }
     __syncthreads();
   }
+}
+
+// Single problem: the launch is one-dimensional over (split, batch, tile).
+template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT = AllTiles,
+          int BK = 16, class T = double>
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(OA A, OB B, EPI epi, int64_t M, int64_t N,
+                                                       int64_t K, int64_t kchunk, int64_t tiles_m,
+                                                       int64_t tiles_n, int64_t nbatch, FILT filt) {
+  const int64_t lid = xcd_logical_id((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  gemm_body<BM, BN, OA, OB, EPI, TRI, FILT, BK, T>(A, B, epi, M, N, K, kchunk, tiles_m, tiles_n,
+                                                   nbatch, filt, lid);
+}
+
+// One job of a grouped launch: a whole problem of the single-problem kernel
+// (its own operands, epilogue, sizes, split plan), owning the workgroups
+// [wg_begin, wg_begin + tiles * nbatch * nsplit) of the launch.
+template <class OA, class OB, class EPI>
+struct GemmJob {
+  OA a;
+  OB b;
+  EPI e;
+  int64_t M, N, K, kchunk, tiles_m, tiles_n, nbatch;
+  int64_t wg_begin;
+};
+
+// Grouped launch: many independent problems of different sizes (one per
+// molecule of a batch) in one dispatch.  Each workgroup finds its job by
+// binary search over the jobs' first workgroup ids, then runs the same tile
+// body as the single-problem kernel.
+template <int BM, int BN, class OA, class OB, class EPI, bool TRI, int BK = 16, class T = double>
+__global__ __launch_bounds__(256, 2) void gemm_grouped_kernel(const GemmJob<OA, OB, EPI>* jobs,
+                                                              int64_t njobs) {
+  const int64_t g = xcd_logical_id((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  int64_t lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg_begin <= g) lo = mid; else hi = mid - 1;
+  }
+  const GemmJob<OA, OB, EPI>& j = jobs[lo];
+  gemm_body<BM, BN, OA, OB, EPI, TRI, AllTiles, BK, T>(j.a, j.b, j.e, j.M, j.N, j.K, j.kchunk,
+                                                       j.tiles_m, j.tiles_n, j.nbatch, AllTiles(),
+                                                       g - j.wg_begin);
 }
 
 // ---------------------------------------------------------------- epilogues

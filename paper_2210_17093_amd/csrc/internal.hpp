@@ -1,0 +1,322 @@
+// Host-side machinery shared by the single-problem and batched drivers of
+// libqsgw: the context, its workspace, error handling, GEMM launchers and
+// K-split plans, stage timers, the pair-block table of the residue product
+// and the dense eigensolver wrapper.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qsgw.h"
+#include "gemm_f64.hpp"
+#include "kernels.hpp"
+
+using namespace qsgw;
+
+namespace {
+
+enum Slot {
+  W_T = 0,    // AO->MO half transform B_ao C            [naux][nbf][nbf]
+  W_BMO,      // MO tensor (iterate / hf_core)            [naux][nbf][nbf]
+  W_BT,       // B_ia sqrt(Delta)                         [naux][ntr]
+  W_DELTA,    // Delta_t                                  [ntr]
+  W_SQD,      // sqrt(Delta_t)                            [ntr]
+  W_M,        // Casida matrix, then eigenvectors         [ntr][ntr]
+  W_OMEGA,    // Omega                                    [ntr]
+  W_RHO,      // rho' of one excitation block             [naux][sb]
+  W_W,        // residues of one excitation block         [nbf][nbf][sb]
+  W_WH,       // pole-weighted residues of the block      [nbf][nbf][sb]
+  W_PART,     // split-K partial sums                     [nz][nbf][nbf]
+  W_V,        // qsGW potential, MO basis                 [nbf][nbf]
+  W_HMO,      // C^T h C                                  [nbf][nbf]
+  W_J,        // Hartree, MO basis                        [nbf][nbf]
+  W_CP,       // occupied traces c_P                      [naux]
+  W_F,        // Fock, then its eigenvectors              [nbf][nbf]
+  W_TMP,      // scratch                                  [nbf][nbf]
+  W_TMP2,     // scratch                                  [nbf][nbf]
+  W_EPSN,     // new energies                             [nbf]
+  W_CNEW,     // new coefficients                         [nbf][nbf]
+  W_EIGE,     // dsyevd off-diagonal workspace            [max(ntr, nbf)]
+  W_SCAL,     // device scalars                           [8]
+  W_FLAGS,    // device int flags                         [8]
+  W_ROWTAB,   // residue pair blocks holding some m <= k  [blocks]
+  W_RHOPART,  // split-K partial sums of rho              [nz][naux][sb]
+  W_BATCH_F64,   // batched iteration: every molecule's arrays
+  W_BATCH_I32,   // batched iteration: pair tables, flags, solver info
+  W_BATCH_PRE,   // batched iteration: segment prefix sums, split counts
+  W_BATCH_JOBS,  // batched iteration: grouped GEMM job tables
+  W_BATCH_MOLS,  // batched iteration: molecule descriptors
+  W_NSLOTS
+};
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qsgw_ctx {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  rocblas_handle blas = nullptr;
+  std::string err;
+  Buffer ws[W_NSLOTS];
+  std::vector<hipEvent_t> events;
+  double stage_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  // events bracketing each stage of the last single-stage call
+  int last_stage = -1;
+  // cached residue pair-block table
+  int64_t rowtab_nbf = -1, rowtab_n = 0;
+};
+
+namespace {
+
+constexpr int kStageMo = 0, kStageRpa = 1, kStageEigRpa = 2, kStageRes = 3, kStageSigma = 4,
+              kStageFock = 5, kStageEigFock = 6;
+
+int fail(qsgw_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, QSGW_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                       \
+  } while (0)
+
+#define CHECK(x)                \
+  do {                          \
+    int r_ = (x);               \
+    if (r_ < 0) return r_;      \
+  } while (0)
+
+template <class T>
+int ws_get(qsgw_ctx* c, int slot, size_t count, T** out) {
+  const size_t bytes = count * sizeof(T) > 0 ? count * sizeof(T) : 8;
+  Buffer& b = c->ws[slot];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, QSGW_ERR_ALLOC, "workspace allocation of %zu bytes failed (slot %d)", bytes,
+                  slot);
+    }
+    b.p = p;
+    b.bytes = bytes;
+  }
+  *out = static_cast<T*>(b.p);
+  return QSGW_OK;
+}
+
+inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+int launch_check(qsgw_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, QSGW_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return QSGW_OK;
+}
+
+// K-split plan: chunks of a multiple of 16, no empty split.
+struct SplitPlan {
+  int64_t kchunk, nz;
+};
+inline SplitPlan split_plan(int64_t K, int64_t want) {
+  if (want <= 1 || K <= 16) return {K, 1};
+  int64_t kchunk = (K + want - 1) / want;
+  kchunk = ((kchunk + 15) / 16) * 16;
+  return {kchunk, (K + kchunk - 1) / kchunk};
+}
+
+// Launch the FP64 GEMM engine.  TRI requires M == N.  `sp` is the K-split plan
+// (partial-sum buffers must hold sp.nz slices).
+template <class T, int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
+int gemm_t(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
+           int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
+  const int64_t tm = (M + BM - 1) / BM;
+  const int64_t tn = (N + BN - 1) / BN;
+  const int64_t ntiles = TRI ? tm * (tm + 1) / 2 : tm * tn;
+  const int64_t kchunk = sp.nz > 1 ? sp.kchunk : K;
+  const int64_t splits = sp.nz > 1 ? sp.nz : 1;
+  if (ntiles <= 0 || batch <= 0 || K <= 0) return QSGW_OK;
+  const int64_t total = ntiles * batch * splits;
+  if (total > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
+  if (!loader_offsets_fit(a, BM) || !loader_offsets_fit(b, BN))
+    return fail(c, QSGW_ERR_UNSUPPORTED, "%s: operand strides too large for the tile loader", what);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT, 16, T>), dim3((unsigned)total),
+                     dim3(256), 0, c->stream, a, b, e, M, N, K, kchunk, tm, tn, batch, f);
+  return launch_check(c, what);
+}
+
+// FP64 products.
+template <int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
+int gemm(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
+         int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
+  return gemm_t<double, BM, BN, TRI>(c, what, a, b, e, M, N, K, batch, sp, f);
+}
+
+// Longest K run one FP32-accumulating workgroup covers before its partial
+// sum is handed to the FP64 split-K reduction.
+constexpr int64_t kFp32MaxK = 4096;
+
+// Split count that gives roughly `target` workgroups for a tiny output.
+inline int64_t splits_for(int64_t tiles, int64_t K, int64_t target = 2048) {
+  int64_t s = (target + tiles - 1) / tiles;
+  const int64_t maxs = (K + 255) / 256;  // keep >= 256 k per split
+  if (s > maxs) s = maxs;
+  return s < 1 ? 1 : s;
+}
+
+// qsGW matrix: 64 x 64 tiles of the nbf x nbf output, K = nbf * ns.
+inline SplitPlan sigma_split(int64_t nbf, int64_t ns) {
+  const int64_t t = (nbf + 63) / 64;
+  return split_plan(nbf * ns, splits_for(t * t, nbf * ns, 4096));
+}
+
+// rho product: 128 x 128 tiles of the naux x ns output, K = ntr; split only
+// when the tiles alone leave the chip under-filled.
+inline SplitPlan rho_split(int64_t naux, int64_t ns, int64_t ntr, int64_t maxk) {
+  const int64_t tiles = ((naux + 127) / 128) * ((ns + 127) / 128);
+  int64_t want = tiles >= 2048 ? 1 : splits_for(tiles, ntr, 2048);
+  const int64_t need = (ntr + maxk - 1) / maxk;  // keep each split's K <= maxk
+  if (want < need) want = need;
+  return split_plan(ntr, want);
+}
+
+// MO exchange: upper 64 x 64 tiles, K = naux * nocc.
+inline SplitPlan exchange_split(int64_t nbf, int64_t naux, int64_t nocc) {
+  const int64_t t = (nbf + 63) / 64;
+  return split_plan(naux * nocc, splits_for(t * (t + 1) / 2, naux * nocc));
+}
+
+int record(qsgw_ctx* c, size_t idx) {
+  while (c->events.size() <= idx) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  HIP_TRY(c, hipEventRecord(c->events[idx], c->stream));
+  return QSGW_OK;
+}
+
+double elapsed(qsgw_ctx* c, size_t a, size_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, c->events[a], c->events[b]) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.0;
+  }
+  return (double)ms;
+}
+
+// Timed spans on the context stream: each span is a pair of events; `id`
+// names a stage (0..6) or a kernel (kKernelBase + 0..7).
+constexpr int kKernelBase = 100;
+constexpr int kKMo1 = kKernelBase + 0, kKMo2 = kKernelBase + 1, kKCasida = kKernelBase + 2,
+              kKRho = kKernelBase + 3, kKW = kKernelBase + 4, kKSigma = kKernelBase + 5,
+              kKSigmaRed = kKernelBase + 6, kKFock = kKernelBase + 7;
+
+struct Spans {
+  qsgw_ctx* c = nullptr;
+  size_t next = 0;
+  struct Span {
+    int id;
+    size_t e0, e1;
+  };
+  std::vector<Span> v;
+  std::vector<size_t> open_stack;
+  int open(int id) {
+    if (!c) return QSGW_OK;
+    v.push_back({id, next, 0});
+    open_stack.push_back(v.size() - 1);
+    return record(c, next++);
+  }
+  int close() {
+    if (!c) return QSGW_OK;
+    v[open_stack.back()].e1 = next;
+    open_stack.pop_back();
+    return record(c, next++);
+  }
+};
+
+#define SPAN_OPEN(sp, id)              \
+  do {                                 \
+    if (sp) CHECK((sp)->open(id));     \
+  } while (0)
+#define SPAN_CLOSE(sp)                 \
+  do {                                 \
+    if (sp) CHECK((sp)->close());      \
+  } while (0)
+
+// Pair blocks (8 values of m x 16 values of k) of the residue product that
+// hold at least one pair m <= k, encoded mb << 16 | kb, in row-major block
+// order.  Built on the host once per nbf and kept on the device.
+int pair_blocks(qsgw_ctx* c, int64_t nbf, const int32_t** tab, int64_t* n) {
+  if (c->rowtab_nbf != nbf) {
+    const int64_t nmb = (nbf + 7) / 8, nkb = (nbf + 15) / 16;
+    if (nmb > 0x7fff || nkb > 0xffff) return fail(c, QSGW_ERR_INVALID_ARG, "nbf too large");
+    std::vector<int32_t> keep;
+    for (int64_t mb = 0; mb < nmb; ++mb)
+      for (int64_t kb = 0; kb < nkb; ++kb)
+        if (8 * mb <= 16 * kb + 15) keep.push_back((int32_t)((mb << 16) | kb));
+    int32_t* d = nullptr;
+    CHECK(ws_get(c, W_ROWTAB, keep.size(), &d));
+    // work already queued may still read the previous table
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(d, keep.data(), keep.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->rowtab_nbf = nbf;
+    c->rowtab_n = (int64_t)keep.size();
+  }
+  *tab = static_cast<const int32_t*>(c->ws[W_ROWTAB].p);
+  *n = c->rowtab_n;
+  return QSGW_OK;
+}
+
+int read_flag(qsgw_ctx* c, int* dflag, int* out) {
+  HIP_TRY(c, hipMemcpyAsync(out, dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return QSGW_OK;
+}
+
+// rocSOLVER dsyevd, eigenvectors in place (column-major).
+int syevd(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what) {
+  if (n > 0x7fffffffLL) return fail(c, QSGW_ERR_UNSUPPORTED, "%s: n too large for rocSOLVER", what);
+  double* E = nullptr;
+  CHECK(ws_get(c, W_EIGE, (size_t)n, &E));
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  rocblas_status st = rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_upper,
+                                       (rocblas_int)n, A, (rocblas_int)n, evals, E,
+                                       (rocblas_int*)(flags + 1));
+  if (st != rocblas_status_success)
+    return fail(c, QSGW_ERR_SOLVER, "%s: rocsolver_dsyevd status %d", what, (int)st);
+  int info = 0;
+  CHECK(read_flag(c, flags + 1, &info));
+  if (info != 0) return fail(c, QSGW_ERR_SOLVER, "%s: dsyevd info = %d", what, info);
+  return QSGW_OK;
+}
+
+
+}  // namespace

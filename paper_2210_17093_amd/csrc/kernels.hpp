@@ -53,13 +53,13 @@ struct PoleScaledResidueOp {
 struct EpiCasida {
   double* Mout;
   const double* delta;
-  int64_t ntr;
+  int64_t ld;  // row pitch of Mout (ntr, or a padded order)
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t m, int64_t n, double v,
                                              bool mirror) const {
     double x = 4.0 * v;
     if (m == n) x += delta[m] * delta[m];
-    Mout[m * ntr + n] = x;
-    if (mirror) Mout[n * ntr + m] = x;
+    Mout[m * ld + n] = x;
+    if (mirror) Mout[n * ld + m] = x;
   }
 };
 

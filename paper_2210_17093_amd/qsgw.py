@@ -33,12 +33,14 @@ SIGMA_QS_MATRIX = 0
 SIGMA_DIAG_GRID = 1
 
 FOCK_FULL_JK = 0
+OPT_GRAPH = 1
 REPORT_MAX_ITERS = 64
 STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "eig_fock")
 
 EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
-           "qsgw_residues", "qsgw_sigma", "qsgw_hf_core", "qsgw_iterate")
+           "qsgw_residues", "qsgw_sigma", "qsgw_hf_core", "qsgw_iterate",
+           "qsgw_iterate_batched")
 
 
 class QsgwError(RuntimeError):
@@ -60,7 +62,7 @@ class State(ct.Structure):
 class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("eta", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int64), ("mix", ct.c_double), ("fock_mode", ct.c_int),
-                ("s_block", ct.c_int64)]
+                ("s_block", ct.c_int64), ("flags", ct.c_int64)]
 
 
 KERNELS = ("mo_transform_1", "mo_transform_2", "casida", "residue_rho", "residue_w",
@@ -102,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_hf_core": ([P, I64, I64, I64, P, P, P, P], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
+        "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
+                                  ct.POINTER(Options), ct.POINTER(Report)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -285,8 +289,34 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
     st = State(_ptr(eps, (nbf,), name="eps"), _ptr(C, (nbf, nbf), name="C"),
                _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration)
     opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
-                  int(s_block))
+                  int(s_block), 0)
     rep = Report()
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))
     return rc, rep.as_dict(), int(st.iteration)
+
+
+def qsgw_iterate_batched(ctx: Context, mols, eta, tol=1e-6, max_iter=1, graph=False,
+                         precision=PREC_FP64):
+    """Batched qsGW iterations in place.  `mols` is a sequence of dicts with
+    device tensors B_ao [naux][nbf][nbf], h, eps, C and the int nocc.
+    Returns (status, list of report dicts)."""
+    n = len(mols)
+    if n < 1:
+        raise ValueError("need at least one molecule")
+    probs = (Problem * n)()
+    states = (State * n)()
+    for i, m in enumerate(mols):
+        naux, nbf, _ = m["B_ao"].shape
+        probs[i] = Problem(nbf, naux, int(m["nocc"]), _ptr(m["B_ao"], (naux, nbf, nbf), name="B_ao"),
+                           _ptr(m["h"], (nbf, nbf), name="h"))
+        states[i] = State(_ptr(m["eps"], (nbf,), name="eps"), _ptr(m["C"], (nbf, nbf), name="C"),
+                          None, int(m.get("iteration", 0)))
+    opt = Options(precision, float(eta), float(tol), int(max_iter), 1.0, FOCK_FULL_JK, 0,
+                  OPT_GRAPH if graph else 0)
+    reps = (Report * n)()
+    rc = ctx.check(lib().qsgw_iterate_batched(ctx.handle, n, probs, states, ct.byref(opt), reps),
+                   allow=(OK, NOT_CONVERGED))
+    for i, m in enumerate(mols):
+        m["iteration"] = int(states[i].iteration)
+    return rc, [r.as_dict() for r in reps]

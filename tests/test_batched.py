@@ -1,0 +1,191 @@
+"""Batched qsGW iterations (many uneven molecules per launch) through the C-ABI.
+
+Every molecule of a batch must reproduce what the single-instance entry point
+computes for it alone: the grouped GEMMs run the same tile bodies, split plans
+and epilogues, so the two paths differ only inside the eigensolver (a padded
+bucket matrix instead of the bare one).  The first iteration is also checked
+against the FP64 oracle at the 1e-8 Ha QP gate, and the hipGraph replay of
+the kernel segments against the eager launches of the same batch.
+"""
+import numpy as np
+import pytest
+
+from qsgw_inputs import batch_shapes, make_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ETA = 1e-3
+# Batched and single-instance runs differ only by the rounding of two
+# different (padded vs bare) eigensolves; near-pole terms of Eq. (19)
+# amplify that (weights up to 1/(2 eta), slopes up to 1/eta^2), so the two
+# are held to the same 1e-8 Ha gate as any FP64 evaluation of the method.
+QP_TOL = 1e-8      # Ha
+
+
+def shapes():
+    """Uneven molecules: tiny edge cases, the distribution's extremes and a
+    few draws from it (N_b in [20, 120], N_aux = 4 N_b, n_occ = N_b / 6)."""
+    out = [dict(nbf=7, naux=28, nocc=1, rank=14, decay=0.99, seed=501),
+           dict(nbf=20, naux=80, nocc=3, rank=40, decay=0.99, seed=502),
+           dict(nbf=120, naux=480, nocc=20, rank=240, decay=0.99, seed=503),
+           dict(nbf=33, naux=70, nocc=6, rank=60, decay=0.99, seed=504)]
+    out += batch_shapes(nmol=6, seed=11, base_seed=600)
+    return out
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2210_17093_amd.qsgw as q
+    stream = torch.cuda.Stream()
+    ctx = q.Context(stream)
+    dev = torch.device("cuda:0")
+    probs = []
+    with torch.cuda.stream(stream):
+        for s in shapes():
+            p = make_problem(s["nbf"], s["naux"], s["nocc"], s["rank"], s["decay"], s["seed"])
+            B = torch.from_numpy(p.B_ao).to(dev)
+            C0 = torch.from_numpy(p.C0.copy()).to(dev)
+            e0 = torch.from_numpy(p.eps0.copy()).to(dev)
+            h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
+            probs.append(dict(p=p, B=B, C0=C0, e0=e0, h=h))
+    stream.synchronize()
+    yield q, ctx, stream, probs
+    ctx.close()
+
+
+def fresh(probs):
+    return [dict(B_ao=x["B"], h=x["h"], nocc=x["p"].nocc, eps=x["e0"].clone(), C=x["C0"].clone())
+            for x in probs]
+
+
+def single(q, ctx, stream, x, iters, precision=0):
+    e = x["e0"].clone()
+    C = x["C0"].clone()
+    hist = []
+    it = 0
+    with torch.cuda.stream(stream):
+        for _ in range(iters):
+            rc, rep, it = q.qsgw_iterate(ctx, x["B"], x["h"], x["p"].nocc, e, C, ETA, tol=0.0,
+                                         max_iter=1, iteration=it, precision=precision)
+            hist.append(rep["max_deps"][0])
+    stream.synchronize()
+    return e.cpu().numpy(), C.cpu().numpy(), hist
+
+
+def run_batch(q, ctx, stream, probs, iters, graph=False, precision=0):
+    mols = fresh(probs)
+    with torch.cuda.stream(stream):
+        rc, reps = q.qsgw_iterate_batched(ctx, mols, ETA, tol=0.0, max_iter=iters, graph=graph,
+                                          precision=precision)
+    stream.synchronize()
+    return rc, reps, mols
+
+
+def test_batched_one_iteration_matches_single_and_oracle(env):
+    q, ctx, stream, probs = env
+    print("batched: one iteration, %d molecules" % len(probs), flush=True)
+    rc, reps, mols = run_batch(q, ctx, stream, probs, 1)
+    assert rc == q.NOT_CONVERGED  # tol = 0 is never met
+    for x, m, r in zip(probs, mols, reps):
+        e1, C1, hist = single(q, ctx, stream, x, 1)
+        eb = m["eps"].cpu().numpy()
+        Cb = m["C"].cpu().numpy()
+        nbf = x["p"].nbf
+        assert m["iteration"] == 1 and r["iterations"] == 1
+        err = np.max(np.abs(eb - e1))
+        print(f"nbf={nbf}: max|eps batched - single| = {err:.2e}", flush=True)
+        assert err <= QP_TOL, (nbf, err)
+        assert abs(r["max_deps"][0] - hist[0]) <= QP_TOL
+        # orbitals: same sign convention, equal up to eigenvector rounding
+        # (backward error of the two eigensolves ~1e-13 Ha over the smallest gap)
+        gap = np.min(np.diff(e1))
+        assert np.max(np.abs(Cb - C1)) <= 1e-9 / max(gap, 1e-6), nbf
+        # orthonormal columns
+        assert np.max(np.abs(Cb.T @ Cb - np.eye(nbf))) <= 1e-12
+
+
+def test_batched_first_iteration_against_oracle(env):
+    import oracle as O
+    q, ctx, stream, probs = env
+    small = [x for x in probs if x["p"].nbf <= 40]
+    assert len(small) >= 3
+    rc, reps, mols = run_batch(q, ctx, stream, small, 1)
+    for x, m in zip(small, mols):
+        p = x["p"]
+        print(f"batched vs oracle: nbf={p.nbf} naux={p.naux} nocc={p.nocc}", flush=True)
+        h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+        eps, C, hist = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, ETA, 0.0, 1)
+        err = np.max(np.abs(m["eps"].cpu().numpy() - eps))
+        assert err <= QP_TOL, (p.nbf, err)
+
+
+def test_batched_three_iterations_match_single(env):
+    q, ctx, stream, probs = env
+    rc, reps, mols = run_batch(q, ctx, stream, probs, 3)
+    for x, m, r in zip(probs, mols, reps):
+        e3, C3, hist = single(q, ctx, stream, x, 3)
+        err = np.max(np.abs(m["eps"].cpu().numpy() - e3))
+        print(f"batched 3 iterations nbf={x['p'].nbf}: max|eps - single| = {err:.2e}", flush=True)
+        assert err <= QP_TOL, (x["p"].nbf, err)
+        assert r["iterations"] == 3 and m["iteration"] == 3
+        np.testing.assert_allclose(r["max_deps"], hist, rtol=0, atol=QP_TOL)
+
+
+def test_graph_replays_match_eager(env):
+    """Kernel segments captured once and replayed on every iteration give the
+    eager batch's results on each of several calls."""
+    q, ctx, stream, probs = env
+    _, reps0, eager = run_batch(q, ctx, stream, probs, 3)
+    for call in range(2):
+        _, reps1, g = run_batch(q, ctx, stream, probs, 3, graph=True)
+        torch.cuda.synchronize()
+        for a, b, ra, rb in zip(eager, g, reps0, reps1):
+            assert torch.equal(a["eps"], b["eps"]) or \
+                float((a["eps"] - b["eps"]).abs().max()) <= 1e-12, call
+            assert float((a["C"] - b["C"]).abs().max()) <= 1e-10, call
+            np.testing.assert_allclose(ra["max_deps"], rb["max_deps"], rtol=0, atol=1e-12)
+
+
+def test_batched_fp32_matches_single_fp32(env):
+    q, ctx, stream, probs = env
+    rc, reps, mols = run_batch(q, ctx, stream, probs, 1, precision=q.PREC_FP32)
+    for x, m in zip(probs, mols):
+        e1, _, _ = single(q, ctx, stream, x, 1, precision=q.PREC_FP32)
+        err = np.max(np.abs(m["eps"].cpu().numpy() - e1))
+        print(f"FP32 nbf={x['p'].nbf}: max|eps batched - single| = {err:.2e}", flush=True)
+        assert err <= QP_TOL, (x["p"].nbf, err)
+
+
+def test_single_molecule_batch(env):
+    q, ctx, stream, probs = env
+    x = probs[1]
+    rc, reps, mols = run_batch(q, ctx, stream, [x], 2)
+    e2, _, _ = single(q, ctx, stream, x, 2)
+    assert np.max(np.abs(mols[0]["eps"].cpu().numpy() - e2)) <= QP_TOL
+
+
+def test_batched_rejects_unsupported_options(env):
+    q, ctx, stream, probs = env
+    mols = fresh(probs[:2])
+    import ctypes as ct
+    n = 2
+    P = (q.Problem * n)()
+    S = (q.State * n)()
+    for i, m in enumerate(mols):
+        naux, nbf, _ = m["B_ao"].shape
+        P[i] = q.Problem(nbf, naux, m["nocc"], m["B_ao"].data_ptr(), m["h"].data_ptr())
+        S[i] = q.State(m["eps"].data_ptr(), m["C"].data_ptr(), None, 0)
+    opt = q.Options(0, ETA, 0.0, 1, 0.5, 0, 0, 0)  # mix != 1
+    rc = q.lib().qsgw_iterate_batched(ctx.handle, n, P, S, ct.byref(opt), None)
+    assert rc == q.ERR_UNSUPPORTED
+    opt = q.Options(0, ETA, 0.0, 0, 1.0, 0, 0, 0)  # max_iter 0
+    assert q.lib().qsgw_iterate_batched(ctx.handle, n, P, S, ct.byref(opt), None) == \
+        q.ERR_INVALID_ARG
+    P[1] = q.Problem(10, 40, 10, mols[1]["B_ao"].data_ptr(), mols[1]["h"].data_ptr())  # nocc = nbf
+    opt = q.Options(0, ETA, 0.0, 1, 1.0, 0, 0, 0)
+    assert q.lib().qsgw_iterate_batched(ctx.handle, n, P, S, ct.byref(opt), None) == \
+        q.ERR_INVALID_ARG
+    assert b"molecule 1" in q.lib().qsgw_last_error(ctx.handle)
