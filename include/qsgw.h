@@ -63,6 +63,7 @@ extern "C" {
 /* qsgw_sigma modes. */
 #define QSGW_SIGMA_QS_MATRIX 0
 #define QSGW_SIGMA_DIAG_GRID 1
+#define QSGW_SIGMA_DIAG_SELF 2
 
 /* Fock update modes of qsgw_iterate. */
 #define QSGW_FOCK_FULL_JK 0 /* F = h + J[D] - K[D] + Vc, D from the current orbitals */
@@ -154,6 +155,10 @@ int qsgw_residues(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const 
  *   out[j][l] (+)= Sigma_{mm}(omega[l]), m = states[j], complex128 stored as
  *   interleaved (re, im) pairs: out is [nstates][nomega][2].
  *   omega: [nomega] device; states: [nstates] device int64.
+ * mode QSGW_SIGMA_DIAG_SELF, Eq. (17) with m = n at each state's own energy:
+ *   out[j][0..2] (+)= Re Sigma_mm(eps_m), Im Sigma_mm(eps_m) and
+ *   Re dSigma_mm/domega at omega = eps_m, m = states[j]; out is [nstates][3].
+ *   states: [nstates] device int64; omega, nomega unused.
  * accumulate = 1 adds into out (for streamed excitation blocks), 0 overwrites.
  * Errors: eta <= 0; states out of range (checked on the host only for nstates
  * <= 0; device indexes are clamped-checked and flagged as INVALID_ARG).
@@ -187,6 +192,10 @@ typedef struct {
   double* Vc;        /* device [nbf][nbf] or NULL, out: last AO-basis potential C V C^T;
                         read back as the previous potential when mix != 1 and iteration > 0 */
   int64_t iteration; /* in/out: iterations done so far (0 at the start) */
+  double* diag;      /* device [nbf][4] or NULL, out: for the first iteration of the call, per
+                        state m at the iteration's input energies, Eq. (17) with m = n:
+                        Re Sigma_mm(eps_m), Im Sigma_mm(eps_m), Re dSigma_mm/domega(eps_m),
+                        and the exchange diagonal Sigma_x,mm = -sum_{i occ, P} (B^P_mi)^2 */
 } qsgw_state;
 
 typedef struct {
@@ -233,8 +242,8 @@ int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const 
  * Batched qsGW iterations for nmol independent molecules of different sizes
  * (hundreds of small molecules per call).
  * probs, states: host arrays of nmol entries whose pointers are device
- * pointers as in qsgw_iterate (states[i].Vc is not used); reports: host array
- * of nmol entries or NULL.  The arrays are read during the call only.
+ * pointers as in qsgw_iterate; reports: host array of nmol entries or NULL.
+ * The arrays are read during the call only.
  * Every stage runs as one launch over all molecules: grouped matrix-core
  * GEMMs (a job table with one entry per molecule, each workgroup finding its
  * molecule by binary search) and segment kernels for the element-wise steps.
@@ -246,8 +255,11 @@ int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const 
  * the kernel segments between eigensolves are captured into hipGraphs on the
  * first iteration and replayed on every iteration (this needs a context
  * created on a stream other than the legacy default stream).
- * Every molecule runs opt->max_iter iterations (opt->mix must be 1 and
- * opt->s_block 0; precision FP64 or FP32); a report's converged field says
+ * Every molecule runs opt->max_iter iterations (opt->s_block must be 0 and
+ * precision FP64 or FP32; with opt->mix != 1 every state needs a Vc buffer,
+ * mixed as in qsgw_iterate from the molecule's own iteration count; the
+ * diag outputs of a state are written during the call's first iteration);
+ * a report's converged field says
  * whether some iteration met tol, max_deps holds every iteration's
  * max |d eps|.  Times are whole-batch figures, the same in every report:
  * ms_stage[2] and ms_stage[6] the Casida and Fock eigensolves, ms_stage[0]

@@ -32,10 +32,14 @@ struct Mol {
   double* eps;  // state
   double* C;    // state
   double *T, *Bmo, *Bt, *delta, *sqd, *M, *Mev, *rho, *rhopart, *w, *wh, *part, *V, *hmo, *J,
-      *tmp, *F, *Fev, *Cn, *cp;
+      *tmp, *tmp2, *F, *Fev, *Cn, *cp;
+  double* Vc;     // state: AO-basis potential, or null
+  double* diag;   // state: per-state diagonal outputs [nbf][4], or null
+  int64_t* itc;   // iterations done (device copy of the state's counter)
   int64_t rho_nz;
   const int32_t* pblocks;
   int64_t npblocks;
+  double eta;
   double* deps;  // this molecule's max |d eps| slot
   double* pad;   // [0] Casida padding diagonal, [1] Fock padding diagonal
   int* flag;
@@ -210,6 +214,56 @@ __global__ void kb_commit(const Mol* mols, const int64_t* pre, int64_t nmol, int
   SEG_PROLOGUE(total)
   m.C[li] = m.Cn[li];
   if (li < m.nbf) m.eps[li] = m.Fev[li];
+  if (li == 0) *m.itc += 1;
+}
+
+// Potential mixing in the AO basis (molecules with a Vc buffer), after
+// tmp2 = C V C^T:
+//   kb_mix_a: tmp = mix tmp2 + (1 - mix) Vc   (mixing: mix != 1 and an earlier iteration)
+//             tmp = tmp2                      (otherwise)
+//   kb_mix_b: Vc = 1/2 (tmp + tmp^T)
+//   kb_mix_c: V = 1/2 (tmp2 + tmp2^T) with tmp2 = C^T Vc C   (mixing only)
+__device__ __forceinline__ bool mixing(const Mol& m, double mix) {
+  return mix != 1.0 && *m.itc > 0;
+}
+
+__global__ void kb_mix_a(const Mol* mols, const int64_t* pre, int64_t nmol, int64_t total,
+                         double mix) {
+  SEG_PROLOGUE(total)
+  if (!m.Vc) return;
+  m.tmp[li] = mixing(m, mix) ? mix * m.tmp2[li] + (1.0 - mix) * m.Vc[li] : m.tmp2[li];
+}
+
+__global__ void kb_mix_b(const Mol* mols, const int64_t* pre, int64_t nmol, int64_t total) {
+  SEG_PROLOGUE(total)
+  if (!m.Vc) return;
+  const int64_t n = m.nbf, r = li / n, c = li - (li / n) * n;
+  m.Vc[li] = 0.5 * (m.tmp[r * n + c] + m.tmp[c * n + r]);
+}
+
+__global__ void kb_mix_c(const Mol* mols, const int64_t* pre, int64_t nmol, int64_t total,
+                         double mix) {
+  SEG_PROLOGUE(total)
+  if (!m.Vc || !mixing(m, mix)) return;
+  const int64_t n = m.nbf, r = li / n, c = li - (li / n) * n;
+  m.V[li] = 0.5 * (m.tmp2[r * n + c] + m.tmp2[c * n + r]);
+}
+
+// Per-state diagonal outputs (one workgroup per state of every molecule with
+// a diag buffer): Eq. (17) at omega = eps_m and its derivative from the
+// residues of all excitations, and the exchange diagonal.
+__global__ void kb_diag(const Mol* mols, const int64_t* pre, int64_t nmol) {
+  const int64_t idx = blockIdx.x;
+  const int64_t mi = seg_find(pre, nmol, idx);
+  const Mol& m = mols[mi];
+  const int64_t st = idx - pre[mi];
+  if (!m.diag || st >= m.nbf) return;
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  diag_self_partial(m.w + st * m.nbf * m.ntr, m.eps, m.Mev, st, m.nbf, m.nocc, m.ntr, m.eta, r);
+  r[3] = exchange_diag_partial(m.Bmo, m.naux, m.nbf, m.nocc, st);
+  block_sum<4>(r);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) m.diag[st * 4 + q] = r[q];
 }
 
 // ------------------------------------------------------------- host side --
@@ -231,6 +285,7 @@ struct Plan {
   int64_t* exc_nz = nullptr;   // device, per molecule
   std::vector<Bucket> bM, bF;
   double* deps = nullptr;      // device [nmol]
+  double mix = 1.0;
 };
 
 template <int BM, int BN, class J>
@@ -297,6 +352,13 @@ struct Jobs {
   const JobK* exc; int64_t exc_wg;
   const JobTT* rot; int64_t rot_wg;   // C' = C U
   int64_t n;
+  // potential of molecules with a Vc buffer (nv of them): tmp2 = C V C^T,
+  // and with mixing (nmix of them) tmp2 = C^T Vc C
+  const JobTF* cg3; int64_t cg3_wg;   // tmp = C V
+  const JobTT* cg4; int64_t cg4_wg;   // tmp2 = tmp C^T
+  const JobTF* ct1; int64_t ct1_wg;   // tmp = Vc C
+  const JobFF* ct2; int64_t ct2_wg;   // tmp2 = C^T tmp
+  int64_t nv, nmix;
 };
 
 template <class CT>
@@ -335,6 +397,11 @@ int segment_b(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   SPAN_OPEN(sp, kKW);
   CHECK((launch_grouped<128, 128, false, CT>(c, "batched residues", J.w, J.n, J.w_wg)));
   SPAN_CLOSE(sp);
+  return launch_check(c, "batched segment B1");
+}
+
+int segment_b2(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
+  const int64_t nmol = (int64_t)P.mols.size();
   SPAN_OPEN(sp, kKSigma);
   CHECK((launch_grouped<64, 64, false, double>(c, "batched sigma", J.sig, J.n, J.sig_wg)));
   SPAN_CLOSE(sp);
@@ -343,6 +410,20 @@ int segment_b(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
                      P.dpre[S_NN], nmol, P.total[S_NN], P.sig_nz, 0);
   SPAN_CLOSE(sp);
   SPAN_OPEN(sp, kKFock);
+  if (J.nv > 0) {
+    CHECK((launch_grouped<64, 64, false, double>(c, "batched C V", J.cg3, J.nv, J.cg3_wg)));
+    CHECK((launch_grouped<64, 64, false, double>(c, "batched C V C^T", J.cg4, J.nv, J.cg4_wg)));
+    hipLaunchKernelGGL(kb_mix_a, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream, P.dmols,
+                       P.dpre[S_NN], nmol, P.total[S_NN], P.mix);
+    hipLaunchKernelGGL(kb_mix_b, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream, P.dmols,
+                       P.dpre[S_NN], nmol, P.total[S_NN]);
+    if (J.nmix > 0) {
+      CHECK((launch_grouped<64, 64, false, double>(c, "batched Vc C", J.ct1, J.nmix, J.ct1_wg)));
+      CHECK((launch_grouped<64, 64, false, double>(c, "batched C^T Vc C", J.ct2, J.nmix, J.ct2_wg)));
+      hipLaunchKernelGGL(kb_mix_c, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream,
+                         P.dmols, P.dpre[S_NN], nmol, P.total[S_NN], P.mix);
+    }
+  }
   CHECK((launch_grouped<64, 64, false, double>(c, "batched hC", J.hc1, J.n, J.hc1_wg)));
   CHECK((launch_grouped<64, 64, false, double>(c, "batched C^T hC", J.hc2, J.n, J.hc2_wg)));
   hipLaunchKernelGGL(kb_occ_trace, dim3(blocks_for(P.total[S_NAUX])), dim3(256), 0, c->stream,
@@ -356,7 +437,7 @@ int segment_b(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   hipLaunchKernelGGL(kb_gershgorin, dim3((unsigned)nmol), dim3(256), 0, c->stream, P.dmols, 1);
   hipLaunchKernelGGL(kb_pad, dim3(blocks_for(P.total[S_NBF2])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NBF2], nmol, P.total[S_NBF2], 1);
-  return launch_check(c, "batched segment B");
+  return launch_check(c, "batched segment B2");
 }
 
 int segment_c(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
@@ -384,7 +465,7 @@ int eig_buckets(qsgw_ctx* c, std::vector<Bucket>& bs) {
 }
 
 struct Graphs {
-  hipGraphExec_t x[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t x[4] = {nullptr, nullptr, nullptr, nullptr};
   ~Graphs() {
     for (auto g : x)
       if (g) (void)hipGraphExecDestroy(g);
@@ -404,8 +485,9 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     return fail(c, QSGW_ERR_UNSUPPORTED, "precision %d is not available", o->precision);
   if (!(o->eta > 0.0) || !isfinite(o->eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need eta > 0");
   if (o->max_iter < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need max_iter >= 1");
-  if (o->mix != 1.0 || o->s_block != 0)
-    return fail(c, QSGW_ERR_UNSUPPORTED, "the batched iteration runs unmixed, unblocked");
+  if (!(o->mix > 0.0 && o->mix <= 1.0)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < mix <= 1");
+  if (o->s_block != 0)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "the batched iteration keeps every excitation resident");
   if (o->fock_mode != QSGW_FOCK_FULL_JK)
     return fail(c, QSGW_ERR_UNSUPPORTED, "fock_mode %d is not available", o->fock_mode);
   const bool fp32 = o->precision == QSGW_PREC_FP32;
@@ -428,6 +510,10 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
                   (long long)i);
     if (!p.B_ao || !p.h || !states[i].eps || !states[i].C)
       return fail(c, QSGW_ERR_INVALID_ARG, "molecule %lld: null pointer", (long long)i);
+    if (o->mix != 1.0 && !states[i].Vc)
+      return fail(c, QSGW_ERR_INVALID_ARG, "molecule %lld: mixing needs a Vc buffer", (long long)i);
+    if (states[i].iteration < 0)
+      return fail(c, QSGW_ERR_INVALID_ARG, "molecule %lld: negative iteration count", (long long)i);
     m.nv = m.nbf - m.nocc;
     m.ntr = m.nocc * m.nv;
     m.nn = m.nbf * m.nbf;
@@ -437,6 +523,9 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     m.h = p.h;
     m.eps = states[i].eps;
     m.C = states[i].C;
+    m.Vc = states[i].Vc;
+    m.diag = states[i].diag;
+    m.eta = o->eta;
     bucketM[m.nbM].push_back(i);
     bucketF[m.nbF].push_back(i);
     const SplitPlan rs = rho_split(m.naux, m.ntr, m.ntr, fp32 ? kFp32MaxK : m.ntr);
@@ -445,7 +534,7 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     exc_nz[i] = exchange_split(m.nbf, m.naux, m.nocc).nz;
     const int64_t pnz = std::max(sig_nz[i], exc_nz[i]);
     nd += 2 * m.naux * m.nn + m.naux * m.ntr * (2 + m.rho_nz) + 2 * m.ntr + 2 * m.nn * m.ntr +
-          pnz * m.nn + 6 * m.nn + m.naux + 64;
+          pnz * m.nn + 7 * m.nn + m.naux + 64;
     const int64_t nmb = (m.nbf + 7) / 8, nkb = (m.nbf + 15) / 16;
     for (int64_t mb = 0; mb < nmb; ++mb)
       for (int64_t kb = 0; kb < nkb; ++kb)
@@ -487,6 +576,7 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     m.hmo = take(m.nn);
     m.J = take(m.nn);
     m.tmp = take(m.nn);
+    m.tmp2 = take(m.nn);
     m.Cn = take(m.nn);
     m.cp = take(m.naux);
     m.deps = P.deps + i;
@@ -540,7 +630,7 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     P.total[s] = acc;
   }
   int64_t* dpre = nullptr;
-  CHECK(ws_get(c, W_BATCH_PRE, (size_t)(S_COUNT * nmol + 2 * nmol), &dpre));
+  CHECK(ws_get(c, W_BATCH_PRE, (size_t)(S_COUNT * nmol + 3 * nmol), &dpre));
   HIP_TRY(c, hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                             c->stream));
   for (int s = 0; s < S_COUNT; ++s) P.dpre[s] = dpre + s * nmol;
@@ -550,6 +640,14 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(P.exc_nz, exc_nz.data(), nmol * sizeof(int64_t), hipMemcpyHostToDevice,
                             c->stream));
+  std::vector<int64_t> itc0(nmol);
+  for (int64_t i = 0; i < nmol; ++i) {
+    itc0[i] = states[i].iteration;
+    P.mols[i].itc = P.exc_nz + nmol + i;
+  }
+  HIP_TRY(c, hipMemcpyAsync(P.exc_nz + nmol, itc0.data(), nmol * sizeof(int64_t),
+                            hipMemcpyHostToDevice, c->stream));
+  P.mix = o->mix;
 
   // ------------------------------------------------------------- jobs --
   std::vector<JobTF> mo1, hc1;
@@ -558,6 +656,9 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   std::vector<JobTT> rho, sig, rot;
   std::vector<JobW> wj;
   std::vector<JobK> exc;
+  std::vector<JobTF> cg3, ct1;
+  std::vector<JobTT> cg4;
+  std::vector<JobFF> ct2;
   for (int64_t i = 0; i < nmol; ++i) {
     const Mol& m = P.mols[i];
     const int64_t nbf = m.nbf, naux = m.naux, ntr = m.ntr, nn = m.nn;
@@ -587,10 +688,24 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
                       exchange_split(nbf, naux, m.nocc), true));
     rot.push_back(job(Strided<true>{m.C, nbf, 1, 0, nbf}, Strided<true>{m.F, m.nbF, 1, 0, nbf},
                       EpiStore{m.Cn, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
+    if (m.Vc) {
+      // the congruences of the single-instance path: C V C^T, then C^T Vc C
+      cg3.push_back(job(Strided<true>{m.C, nbf, 1, 0, nbf}, Strided<false>{m.V, 1, nbf, 0, nbf},
+                        EpiStore{m.tmp, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
+      cg4.push_back(job(Strided<true>{m.tmp, nbf, 1, 0, nbf}, Strided<true>{m.C, nbf, 1, 0, nbf},
+                        EpiStore{m.tmp2, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
+      if (o->mix != 1.0) {
+        ct1.push_back(job(Strided<true>{m.Vc, nbf, 1, 0, nbf}, Strided<false>{m.C, 1, nbf, 0, nbf},
+                          EpiStore{m.tmp, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
+        ct2.push_back(job(Strided<false>{m.C, 1, nbf, 0, nbf}, Strided<false>{m.tmp, 1, nbf, 0, nbf},
+                          EpiStore{m.tmp2, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
+      }
+    }
   }
   const size_t jbytes = job_bytes<JobTF>(nmol) * 2 + job_bytes<JobFF>(nmol) * 2 +
                         job_bytes<JobCas>(nmol) + job_bytes<JobTT>(nmol) * 3 +
-                        job_bytes<JobW>(nmol) + job_bytes<JobK>(nmol) + 4096;
+                        job_bytes<JobW>(nmol) + job_bytes<JobK>(nmol) + job_bytes<JobTF>(nmol) * 2 +
+                        job_bytes<JobTT>(nmol) + job_bytes<JobFF>(nmol) + 4096;
   char* jb = nullptr;
   CHECK(ws_get(c, W_BATCH_JOBS, jbytes, &jb));
   char* cursor = jb;
@@ -606,6 +721,12 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   CHECK((upload_jobs<64, 64>(c, hc2, cursor, &J.hc2, &J.hc2_wg)));
   CHECK((upload_jobs<64, 64>(c, exc, cursor, &J.exc, &J.exc_wg)));
   CHECK((upload_jobs<64, 64>(c, rot, cursor, &J.rot, &J.rot_wg)));
+  CHECK((upload_jobs<64, 64>(c, cg3, cursor, &J.cg3, &J.cg3_wg)));
+  CHECK((upload_jobs<64, 64>(c, cg4, cursor, &J.cg4, &J.cg4_wg)));
+  CHECK((upload_jobs<64, 64>(c, ct1, cursor, &J.ct1, &J.ct1_wg)));
+  CHECK((upload_jobs<64, 64>(c, ct2, cursor, &J.ct2, &J.ct2_wg)));
+  J.nv = (int64_t)cg3.size();
+  J.nmix = (int64_t)ct1.size();
   Mol* dm = nullptr;
   CHECK(ws_get(c, W_BATCH_MOLS, (size_t)nmol, &dm));
   HIP_TRY(c, hipMemcpyAsync(dm, P.mols.data(), nmol * sizeof(Mol), hipMemcpyHostToDevice, c->stream));
@@ -625,20 +746,27 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   double ms_hot = 0.0, ms_eigM = 0.0, ms_eigF = 0.0;
   double ms_kernel[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // kernel segments: A (MO transform, Casida build), B1 (rho, residues),
+  // B2 (qsGW matrix, Fock build), C (rotation, update); the Casida eigensolve
+  // follows A, the Fock eigensolve B2; the per-state diagonal outputs run
+  // between B1 and B2 on the first iteration only
   auto seg = [&](int k, Spans* ks) -> int {
     if (k == 0) return fp32 ? segment_a<float>(c, P, J, ks) : segment_a<double>(c, P, J, ks);
     if (k == 1) return fp32 ? segment_b<float>(c, P, J, ks) : segment_b<double>(c, P, J, ks);
+    if (k == 2) return segment_b2(c, P, J, ks);
     return segment_c(c, P, J, ks);
   };
-  const int seg_stage[3] = {kStageMo, kStageRes, kStageFock};
+  bool any_diag = false;
+  for (int64_t i = 0; i < nmol; ++i) any_diag = any_diag || P.mols[i].diag != nullptr;
+  const int seg_stage[4] = {kStageMo, kStageRes, kStageSigma, kStageFock};
   int status = QSGW_OK;
   for (int64_t it = 0; it < o->max_iter; ++it) {
-    // stage spans: the three kernel segments and the two eigensolves; kernel
-    // spans inside the segments when they run eagerly
+    // stage spans: the kernel segments and the two eigensolves; kernel spans
+    // inside the segments when they run eagerly
     Spans sp;
     sp.c = c;
     Spans* ks = graph ? nullptr : &sp;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       if (graph && !gx.x[k]) {
         // capture the segment once (nothing runs during capture), then replay
         hipGraph_t g = nullptr;
@@ -664,7 +792,12 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
         CHECK(seg(k, ks));
       }
       CHECK(sp.close());
-      if (k < 2) {
+      if (k == 1 && it == 0 && any_diag) {
+        hipLaunchKernelGGL(kb_diag, dim3((unsigned)P.total[S_NBF]), dim3(256), 0, c->stream, P.dmols,
+                           P.dpre[S_NBF], nmol);
+        CHECK(launch_check(c, "kb_diag"));
+      }
+      if (k == 0 || k == 2) {
         CHECK(sp.open(k == 0 ? kStageEigRpa : kStageEigFock));
         CHECK(eig_buckets(c, k == 0 ? P.bM : P.bF));
         CHECK(sp.close());

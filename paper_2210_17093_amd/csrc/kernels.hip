@@ -250,4 +250,31 @@ __global__ void k_sigma_diag_grid(const double* w, const double* eps, const doub
   }
 }
 
+__global__ void k_sigma_diag_self(const double* w, const double* eps, const double* Omega,
+                                  int64_t nbf, int64_t nocc, int64_t ns, double eta,
+                                  const int64_t* states, int64_t nstates, double* out, int64_t ld,
+                                  int accumulate, int* bad) {
+  const int64_t j = blockIdx.x;
+  if (j >= nstates) return;
+  const int64_t m = states ? states[j] : j;
+  if (m < 0 || m >= nbf) {
+    if (threadIdx.x == 0) atomicOr(bad, 1);
+    return;
+  }
+  double r[3] = {0.0, 0.0, 0.0};
+  diag_self_partial(w + m * nbf * ns, eps, Omega, m, nbf, nocc, ns, eta, r);
+  block_sum<3>(r);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) out[j * ld + q] = accumulate ? out[j * ld + q] + r[q] : r[q];
+}
+
+__global__ void k_exchange_diag(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc,
+                                double* out, int64_t ld) {
+  const int64_t m = blockIdx.x;
+  if (m >= nbf) return;
+  double v[1] = {exchange_diag_partial(bmo, naux, nbf, nocc, m)};
+  block_sum<1>(v);
+  if (threadIdx.x == 0) out[m * ld] = v[0];
+}
+
 }  // namespace qsgw

@@ -113,6 +113,82 @@ struct EpiPairResidue {
 // ------------------------------------------------------ plain kernels ----
 
 // Delta_t = eps_a - eps_i, sqrt_delta_t, and Bt[P][t] = B_mo[P][i][a] sqrt(Delta_t).
+// ------------------------------------------------ per-state diagonal -----
+// This thread's share of Eq. (17) with m = n at omega = eps_m, and of its
+// frequency derivative, from row m of the residues (w[m][k][s], ns columns):
+//   r[0] += sum w^2 x / (x^2 + eta^2)                      Re Sigma_mm(eps_m)
+//   r[1] += sum (+-eta) w^2 / (x^2 + eta^2)                Im Sigma_mm(eps_m)
+//   r[2] += -sum w^2 (x^2 - eta^2) / (x^2 + eta^2)^2       Re dSigma_mm/domega
+// with x = eps_m - eps_k + Omega_s, +eta (occupied k) or x = eps_m - eps_k -
+// Omega_s, -eta (empty k).  k runs outer, s is strided by the block size, so
+// a wave reads consecutive addresses.
+__device__ __forceinline__ void diag_self_partial(const double* wrow, const double* eps,
+                                                  const double* Omega, int64_t m, int64_t nbf,
+                                                  int64_t nocc, int64_t ns, double eta,
+                                                  double r[3]) {
+  const double em = eps[m], eta2 = eta * eta;
+  for (int64_t k = 0; k < nbf; ++k) {
+    const bool occ = k < nocc;
+    const double base = em - eps[k];
+    const double* wk = wrow + k * ns;
+    for (int64_t s = threadIdx.x; s < ns; s += blockDim.x) {
+      const double x = occ ? base + Omega[s] : base - Omega[s];
+      const double w2 = wk[s] * wk[s];
+      const double den = x * x + eta2;
+      const double inv = 1.0 / den;
+      r[0] += w2 * x * inv;
+      r[1] += (occ ? eta : -eta) * w2 * inv;
+      r[2] -= w2 * (x * x - eta2) * inv * inv;
+    }
+  }
+}
+
+// Sum of N values over the block (blockDim.x a multiple of 64, <= 1024), in a
+// fixed order (wave shuffles, then waves in index order); valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_sum(double v[N]) {
+  __shared__ double red[16][N];
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < N; ++q) red[threadIdx.x >> 6][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int q = 0; q < N; ++q) {
+      double t = 0.0;
+      for (int u = 0; u < (int)(blockDim.x >> 6); ++u) t += red[u][q];
+      v[q] = t;
+    }
+}
+
+// One workgroup per listed state: out[j * ld + 0..2] (+)= the three sums of
+// diag_self_partial for m = states[j] (m = j when states is null).
+__global__ void k_sigma_diag_self(const double* w, const double* eps, const double* Omega,
+                                  int64_t nbf, int64_t nocc, int64_t ns, double eta,
+                                  const int64_t* states, int64_t nstates, double* out, int64_t ld,
+                                  int accumulate, int* bad);
+
+// Exchange diagonal in the MO basis, one workgroup per state m:
+// out[m * ld] = -sum_{P, i < nocc} (B^P_mi)^2.
+__global__ void k_exchange_diag(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc,
+                                double* out, int64_t ld);
+
+// Exchange diagonal share of this thread for state m (P, i strided by the block).
+__device__ __forceinline__ double exchange_diag_partial(const double* bmo, int64_t naux,
+                                                        int64_t nbf, int64_t nocc, int64_t m) {
+  double acc = 0.0;
+  const int64_t n = naux * nocc;
+  for (int64_t q = threadIdx.x; q < n; q += blockDim.x) {
+    const int64_t P = q / nocc, i = q - P * nocc;
+    const double b = bmo[(P * nbf + m) * nbf + i];
+    acc -= b * b;
+  }
+  return acc;
+}
+
 __global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, double* delta,
                               double* sqrt_delta, int* bad);
 __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_t naux,

@@ -380,6 +380,23 @@ int qsgw_sigma(qsgw_ctx* c, int mode, int64_t nbf, int64_t nocc, int64_t ns, con
                          wh));
     return single_end(c);
   }
+  if (mode == QSGW_SIGMA_DIAG_SELF) {
+    if (nstates < 1 || !states) return fail(c, QSGW_ERR_INVALID_ARG, "need nstates >= 1 and states");
+    if (nstates > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "too many states");
+    int* flags = nullptr;
+    CHECK(ws_get(c, W_FLAGS, 8, &flags));
+    HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+    CHECK(single_begin(c, kStageSigma));
+    hipLaunchKernelGGL(k_sigma_diag_self, dim3((unsigned)nstates), dim3(256), 0, c->stream, w, eps,
+                       Omega, nbf, nocc, ns, eta, states, nstates, out, (int64_t)3,
+                       accumulate ? 1 : 0, flags);
+    CHECK(launch_check(c, "k_sigma_diag_self"));
+    CHECK(single_end(c));
+    int bad = 0;
+    CHECK(read_flag(c, flags, &bad));
+    if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "a state index is outside [0, nbf)");
+    return QSGW_OK;
+  }
   if (mode != QSGW_SIGMA_DIAG_GRID) return fail(c, QSGW_ERR_INVALID_ARG, "unknown mode %d", mode);
   if (nomega < 1 || nstates < 1 || !omega || !states)
     return fail(c, QSGW_ERR_INVALID_ARG, "diagonal grid needs nomega, nstates >= 1");
@@ -560,6 +577,17 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
                            wh));
       CHECK(sp.close());
+      if (it == 0 && st->diag) {
+        hipLaunchKernelGGL(k_sigma_diag_self, dim3((unsigned)nbf), dim3(256), 0, c->stream, w, eps,
+                           Omega + s0, nbf, nocc, ns, o->eta, (const int64_t*)nullptr, nbf,
+                           st->diag, (int64_t)4, s0 > 0 ? 1 : 0, flags + 3);
+        CHECK(launch_check(c, "k_sigma_diag_self"));
+      }
+    }
+    if (it == 0 && st->diag) {
+      hipLaunchKernelGGL(k_exchange_diag, dim3((unsigned)nbf), dim3(256), 0, c->stream, Bmo, naux,
+                         nbf, nocc, st->diag + 3, (int64_t)4);
+      CHECK(launch_check(c, "k_exchange_diag"));
     }
     CHECK(sp.open(kStageFock));
     CHECK(sp.open(kKFock));

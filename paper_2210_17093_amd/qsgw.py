@@ -31,6 +31,7 @@ PREC_SPLIT_BF16 = 2
 
 SIGMA_QS_MATRIX = 0
 SIGMA_DIAG_GRID = 1
+SIGMA_DIAG_SELF = 2
 
 FOCK_FULL_JK = 0
 OPT_GRAPH = 1
@@ -56,7 +57,7 @@ class Problem(ct.Structure):
 
 class State(ct.Structure):
     _fields_ = [("eps", ct.c_void_p), ("C", ct.c_void_p), ("Vc", ct.c_void_p),
-                ("iteration", ct.c_int64)]
+                ("iteration", ct.c_int64), ("diag", ct.c_void_p)]
 
 
 class Options(ct.Structure):
@@ -270,6 +271,23 @@ def qsgw_sigma_diag(ctx: Context, w, eps, Omega_block, nocc, eta, omega, states,
     return torch.view_as_complex(out)
 
 
+def qsgw_sigma_diag_self(ctx: Context, w, eps, Omega_block, nocc, eta, states, out=None,
+                         accumulate=False):
+    """Per-state Eq. (17) at omega = eps_m: float64 [nstates][3] holding
+    Re Sigma_mm(eps_m), Im Sigma_mm(eps_m), Re dSigma_mm/domega(eps_m)."""
+    nbf, _, ns = w.shape
+    nstates = states.shape[0]
+    if out is None:
+        out = torch.empty((nstates, 3), dtype=torch.float64, device=w.device)
+    ctx.check(lib().qsgw_sigma(ctx.handle, SIGMA_DIAG_SELF, nbf, nocc, ns,
+                               _ptr(w, (nbf, nbf, ns), name="w"), None,
+                               _ptr(eps, (nbf,), name="eps"),
+                               _ptr(Omega_block, (ns,), name="Omega"), float(eta), None, 0,
+                               _ptr(states, (nstates,), torch.int64, name="states"), nstates,
+                               _ptr(out, (nstates, 3), name="out"), int(bool(accumulate))))
+    return out
+
+
 def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
     naux, nbf, _ = B_ao.shape
     if h is None:
@@ -281,13 +299,14 @@ def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
 
 
 def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
-                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64):
+                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None):
     """Runs qsGW iterations in place on (eps, C).  Returns (status, report dict, iteration)."""
     naux, nbf, _ = B_ao.shape
     prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
                    _ptr(h, (nbf, nbf), name="h"))
     st = State(_ptr(eps, (nbf,), name="eps"), _ptr(C, (nbf, nbf), name="C"),
-               _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration)
+               _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration,
+               _ptr(diag, (nbf, 4), name="diag") if diag is not None else None)
     opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
                   int(s_block), 0)
     rep = Report()
@@ -297,10 +316,11 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
 
 
 def qsgw_iterate_batched(ctx: Context, mols, eta, tol=1e-6, max_iter=1, graph=False,
-                         precision=PREC_FP64):
+                         precision=PREC_FP64, mix=1.0):
     """Batched qsGW iterations in place.  `mols` is a sequence of dicts with
-    device tensors B_ao [naux][nbf][nbf], h, eps, C and the int nocc.
-    Returns (status, list of report dicts)."""
+    device tensors B_ao [naux][nbf][nbf], h, eps, C, the int nocc, and
+    optionally Vc [nbf][nbf] (required when mix != 1), diag [nbf][4] and
+    iteration.  Returns (status, list of report dicts)."""
     n = len(mols)
     if n < 1:
         raise ValueError("need at least one molecule")
@@ -310,9 +330,12 @@ def qsgw_iterate_batched(ctx: Context, mols, eta, tol=1e-6, max_iter=1, graph=Fa
         naux, nbf, _ = m["B_ao"].shape
         probs[i] = Problem(nbf, naux, int(m["nocc"]), _ptr(m["B_ao"], (naux, nbf, nbf), name="B_ao"),
                            _ptr(m["h"], (nbf, nbf), name="h"))
+        Vc, diag = m.get("Vc"), m.get("diag")
         states[i] = State(_ptr(m["eps"], (nbf,), name="eps"), _ptr(m["C"], (nbf, nbf), name="C"),
-                          None, int(m.get("iteration", 0)))
-    opt = Options(precision, float(eta), float(tol), int(max_iter), 1.0, FOCK_FULL_JK, 0,
+                          _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None,
+                          int(m.get("iteration", 0)),
+                          _ptr(diag, (nbf, 4), name="diag") if diag is not None else None)
+    opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK, 0,
                   OPT_GRAPH if graph else 0)
     reps = (Report * n)()
     rc = ctx.check(lib().qsgw_iterate_batched(ctx.handle, n, probs, states, ct.byref(opt), reps),

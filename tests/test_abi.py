@@ -68,6 +68,6 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the C structs: sizes follow the header's field order."""
     import paper_2210_17093_amd.qsgw as q
     assert ctypes.sizeof(q.Problem) == 5 * 8
-    assert ctypes.sizeof(q.State) == 4 * 8
+    assert ctypes.sizeof(q.State) == 5 * 8
     assert ctypes.sizeof(q.Options) == 8 * 8
     assert ctypes.sizeof(q.Report) == 8 + 8 + 64 * 8 + 7 * 8 + 8 + 3 * 8 * 8

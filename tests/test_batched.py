@@ -178,7 +178,10 @@ def test_batched_rejects_unsupported_options(env):
         naux, nbf, _ = m["B_ao"].shape
         P[i] = q.Problem(nbf, naux, m["nocc"], m["B_ao"].data_ptr(), m["h"].data_ptr())
         S[i] = q.State(m["eps"].data_ptr(), m["C"].data_ptr(), None, 0)
-    opt = q.Options(0, ETA, 0.0, 1, 0.5, 0, 0, 0)  # mix != 1
+    opt = q.Options(0, ETA, 0.0, 1, 0.5, 0, 0, 0)  # mix != 1 without Vc buffers
+    rc = q.lib().qsgw_iterate_batched(ctx.handle, n, P, S, ct.byref(opt), None)
+    assert rc == q.ERR_INVALID_ARG
+    opt = q.Options(0, ETA, 0.0, 1, 1.0, 0, 64, 0)  # streamed excitation blocks
     rc = q.lib().qsgw_iterate_batched(ctx.handle, n, P, S, ct.byref(opt), None)
     assert rc == q.ERR_UNSUPPORTED
     opt = q.Options(0, ETA, 0.0, 0, 1.0, 0, 0, 0)  # max_iter 0
@@ -189,3 +192,111 @@ def test_batched_rejects_unsupported_options(env):
     assert q.lib().qsgw_iterate_batched(ctx.handle, n, P, S, ct.byref(opt), None) == \
         q.ERR_INVALID_ARG
     assert b"molecule 1" in q.lib().qsgw_last_error(ctx.handle)
+
+
+def test_batched_mixing_matches_single(env):
+    """Linear mixing of the AO-basis potential (mix = 0.5) over three
+    iterations: batched against single instance, including the potential."""
+    q, ctx, stream, probs = env
+    sub = probs[:5]
+    mols = fresh(sub)
+    for m in mols:
+        nbf = m["eps"].shape[0]
+        m["Vc"] = torch.zeros((nbf, nbf), dtype=torch.float64, device=m["eps"].device)
+    with torch.cuda.stream(stream):
+        rc, reps = q.qsgw_iterate_batched(ctx, mols, ETA, tol=0.0, max_iter=3, mix=0.5)
+    stream.synchronize()
+    for x, m in zip(sub, mols):
+        nbf = x["p"].nbf
+        e = x["e0"].clone()
+        C = x["C0"].clone()
+        Vc = torch.zeros((nbf, nbf), dtype=torch.float64, device=e.device)
+        it = 0
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                _, _, it = q.qsgw_iterate(ctx, x["B"], x["h"], x["p"].nocc, e, C, ETA, tol=0.0,
+                                          max_iter=1, mix=0.5, Vc=Vc, iteration=it)
+        stream.synchronize()
+        err = float((m["eps"] - e).abs().max())
+        verr = float((m["Vc"] - Vc).abs().max())
+        print(f"mixing nbf={nbf}: eps {err:.2e}, Vc {verr:.2e}", flush=True)
+        assert err <= QP_TOL and verr <= 1e-7, (nbf, err, verr)
+        assert torch.equal(m["Vc"], m["Vc"].T)
+
+
+def test_batched_diag_outputs_against_single_and_oracle(env):
+    """Per-state Eq. (17) at omega = eps_m, its derivative and the exchange
+    diagonal from the first iteration: batched vs single vs oracle."""
+    import oracle as O
+    q, ctx, stream, probs = env
+    sub = [x for x in probs if x["p"].nbf <= 40][:3]
+    mols = fresh(sub)
+    for m in mols:
+        nbf = m["eps"].shape[0]
+        m["diag"] = torch.full((nbf, 4), float("nan"), dtype=torch.float64, device=m["eps"].device)
+    with torch.cuda.stream(stream):
+        q.qsgw_iterate_batched(ctx, mols, ETA, tol=0.0, max_iter=2, graph=True)
+    stream.synchronize()
+    for x, m in zip(sub, mols):
+        p = x["p"]
+        d = torch.empty((p.nbf, 4), dtype=torch.float64, device=x["e0"].device)
+        e = x["e0"].clone()
+        C = x["C0"].clone()
+        with torch.cuda.stream(stream):
+            q.qsgw_iterate(ctx, x["B"], x["h"], p.nocc, e, C, ETA, tol=0.0, max_iter=1, diag=d)
+        stream.synchronize()
+        db = m["diag"].cpu().numpy()
+        ds = d.cpu().numpy()
+        # oracle at the iteration-1 inputs (eps0, C0)
+        B_mo = O.mo_transform(p.B_ao, p.C0)
+        M, sq = O.rpa_hermitian(B_mo, p.eps0, p.nocc)
+        Om, XpY = O.rpa_solve(M, sq)
+        w = O.residues(B_mo, XpY, p.nocc)
+        ref = np.empty((p.nbf, 4))
+        for mm in range(p.nbf):
+            sig = O.sigma_element(w, p.eps0, Om, p.nocc, ETA, mm, mm, [p.eps0[mm]])[0]
+            der = O.sigma_diag_derivative(w, p.eps0, Om, p.nocc, ETA, mm, p.eps0[mm])
+            ref[mm] = [sig.real, sig.imag, der.real, 0.0]
+        ref[:, 3] = O.exchange_diagonal_mo(B_mo, p.nocc)
+        scale = np.abs(ref).max(axis=0)
+        print(f"diag nbf={p.nbf}: scales {scale}", flush=True)
+        assert np.all(np.isfinite(db))
+        # batched and single share every kernel of the first iteration up to
+        # the eigensolve of the Casida matrix
+        np.testing.assert_allclose(db, ds, rtol=0, atol=1e-9 * scale.max())
+        for col in range(4):
+            assert np.max(np.abs(db[:, col] - ref[:, col])) <= 1e-8 * max(scale[col], 1.0), col
+
+
+def test_sigma_diag_self_mode_against_oracle():
+    """qsgw_sigma in DIAG_SELF mode on the small single-instance workload,
+    streamed over two excitation blocks (accumulate)."""
+    import oracle as O
+    from qsgw_inputs import make_config
+    import paper_2210_17093_amd.qsgw as q
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    p = make_config("cfg1")
+    dev = torch.device("cuda:0")
+    B_mo = O.mo_transform(p.B_ao, p.C0)
+    M, sq = O.rpa_hermitian(B_mo, p.eps0, p.nocc)
+    Om, XpY = O.rpa_solve(M, sq)
+    w = O.residues(B_mo, XpY, p.nocc)
+    states = np.array([0, p.nocc - 1, p.nocc, p.nbf - 1], dtype=np.int64)
+    with q.Context() as ctx:
+        wt = torch.from_numpy(np.ascontiguousarray(w)).to(dev)
+        e = torch.from_numpy(p.eps0).to(dev)
+        O_t = torch.from_numpy(Om).to(dev)
+        st = torch.from_numpy(states).to(dev)
+        half = p.ntr // 2
+        w1 = wt[:, :, :half].contiguous()
+        w2 = wt[:, :, half:].contiguous()
+        out = q.qsgw_sigma_diag_self(ctx, w1, e, O_t[:half].contiguous(), p.nocc, 1e-3, st)
+        out = q.qsgw_sigma_diag_self(ctx, w2, e, O_t[half:].contiguous(), p.nocc, 1e-3, st,
+                                     out=out, accumulate=True)
+        got = out.cpu().numpy()
+    for j, mm in enumerate(states):
+        sig = O.sigma_element(w, p.eps0, Om, p.nocc, 1e-3, mm, mm, [p.eps0[mm]])[0]
+        der = O.sigma_diag_derivative(w, p.eps0, Om, p.nocc, 1e-3, mm, p.eps0[mm])
+        ref = np.array([sig.real, sig.imag, der.real])
+        np.testing.assert_allclose(got[j], ref, rtol=1e-11, atol=1e-13)
