@@ -273,6 +273,57 @@ int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const 
 int qsgw_iterate_batched(qsgw_ctx* ctx, int64_t nmol, const qsgw_problem* probs,
                          qsgw_state* states, const qsgw_options* opt, qsgw_report* reports);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A network 16 -> 128 -> 128 -> 1 with GELU
+ * activations maps per-state features of a molecule's first iteration to the
+ * state's converged qsGW shift delta_m = eps_m(converged) - eps_m(start); the
+ * iteration then starts from eps0 + delta and the unchanged orbitals.
+ * Parameters are one FP32 array of QSGW_MLP_NPARAMS values laid out as
+ * W1[128][16], b1[128], W2[128][128], b2[128], w3[128], b3[1]
+ * (z = W x + b per layer, y = w3 . a2 + b3).  All arrays are device pointers.
+ * ------------------------------------------------------------------------ */
+#define QSGW_MLP_NPARAMS 18817
+#define QSGW_MLP_NFEAT 16
+
+/*
+ * Features of every state m of one molecule, from its orbital energies eps
+ * ([nbf], the first iteration's input) and the diag output of that
+ * iteration ([nbf][4], see qsgw_state.diag):
+ *   0 eps_m, 1 Sigma_x,mm, 2 Re Sigma_mm(eps_m), 3 Re dSigma_mm/domega,
+ *   4 nocc/nbf, 5 eps_LUMO - eps_HOMO, 6 Im Sigma_mm(eps_m),
+ *   7 Z = 1/(1 - dSigma/domega), 8 occupied (1/0), 9 eps_m - eps_HOMO,
+ *   10 eps_m - eps_LUMO, 11 nbf/120, 12 m/nbf, 13 Z Re Sigma_mm(eps_m)
+ *   (the linearized shift at a Hartree-Fock start), 14 |dSigma/domega| > 1
+ *   (1/0), 15 constant 1.
+ * X: [nbf][16] FP32 out, (f - mean[q]) / scale[q] when mean and scale
+ * ([16] FP32) are given, raw values when both are NULL.
+ */
+int qsgw_mlp_features(qsgw_ctx* ctx, int64_t nbf, int64_t nocc, const double* eps,
+                      const double* diag, const float* mean, const float* scale, float* X);
+
+/* y[b] = network(X[b]) for n states; X: [n][16], y: [n] FP32. */
+int qsgw_mlp_forward(qsgw_ctx* ctx, const float* params, int64_t n, const float* X, float* y);
+
+/*
+ * One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
+ * step count `step` >= 1, learning rate lr) on the mean squared error
+ * L = (1/n) sum_b (network(X[b]) - target[b])^2 of a batch of n states.
+ * params, adam_m, adam_v: [QSGW_MLP_NPARAMS] FP32, updated in place.
+ * grad: NULL, or [QSGW_MLP_NPARAMS] FP32 out: dL/dparams before the update.
+ * loss: NULL, or a device double out: L before the update.
+ */
+int qsgw_mlp_train_step(qsgw_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step,
+                        double lr, int64_t n, const float* X, const float* target, float* grad,
+                        double* loss);
+
+/*
+ * Warm-start orbitals: eps = the values eps0[m] + delta[m] sorted ascending
+ * (stable), C = C0 with its columns permuted the same way.  eps0, eps: [nbf]
+ * FP64; delta: [nbf] FP32; C0, C: [nbf][nbf] FP64 (must not alias).
+ */
+int qsgw_warm_start(qsgw_ctx* ctx, int64_t nbf, const double* eps0, const double* C0,
+                    const float* delta, double* eps, double* C);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,19 +58,21 @@ struct Mfma<float> {
   __device__ __forceinline__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-// Element (r, k) at p[b*sb + r*sr + k*sk]; rows >= `rows` or k >= K read 0.
+// Element (r, k) at p[b*sb + r*sr + k*sk] (strides in elements of the
+// storage type S, double or float); rows >= `rows` or k >= K read 0.
 // Strided operands take the branch-free tile loader of the kernel: one base
 // pointer per thread, a uniform stride between the thread's elements, and on
 // edge tiles loads from a clamped (always valid) address followed by a select.
-template <bool KC>
+template <bool KC, class S = double>
 struct Strided {
   static constexpr bool kContig = KC;
   static constexpr bool kStrided = true;
-  const double* p;
+  typedef S storage_t;
+  const S* p;
   int64_t sr, sk, sb;
   int64_t rows;
   __device__ __forceinline__ double get(int64_t b, int64_t r, int64_t k) const {
-    return r < rows ? p[b * sb + r * sr + k * sk] : 0.0;
+    return r < rows ? (double)p[b * sb + r * sr + k * sk] : 0.0;
   }
 };
 
@@ -154,15 +156,16 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
     // Per-thread part: one 32-bit byte offset shared by all E elements.
     const int rl = OP::kContig ? (tid / BK) : (tid % BR);
     const int kl = OP::kContig ? (tid % BK) : (tid / BR);
+    typedef typename OP::storage_t S;
     const int64_t estride = OP::kContig ? (int64_t)(256 / BK) * op.sr : (int64_t)(256 / BR) * op.sk;
-    const double* origin = op.p + b * op.sb + r0 * op.sr + kbase * op.sk;
-    const uint32_t toff = (uint32_t)(((int64_t)rl * op.sr + (int64_t)kl * op.sk) * 8);
+    const S* origin = op.p + b * op.sb + r0 * op.sr + kbase * op.sk;
+    const uint32_t toff = (uint32_t)(((int64_t)rl * op.sr + (int64_t)kl * op.sk) * (int64_t)sizeof(S));
     const bool full = (r0 + BR <= op.rows) && (kbase + BK <= kend);
     if (full) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const char* sb = reinterpret_cast<const char*>(origin + e * estride);
-        v[e] = *reinterpret_cast<const double*>(sb + toff);
+        v[e] = (double)*reinterpret_cast<const S*>(sb + toff);
       }
     } else {
 #pragma unroll
@@ -172,7 +175,7 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
         const bool ok = (r0 + r < op.rows) && (kbase + k < kend);
         // masked elements read the tile origin, which is always a valid element
         const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : origin);
-        const double x = *reinterpret_cast<const double*>(sb + (ok ? toff : 0u));
+        const double x = (double)*reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
         v[e] = ok ? x : 0.0;
       }
     }
@@ -198,7 +201,8 @@ inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16) {
   } else if constexpr (is_strided_op<OP>::value) {
     const uint64_t rl = OP::kContig ? 256 / BK - 1 : BR - 1;
     const uint64_t kl = OP::kContig ? BK - 1 : 256 / BR - 1;
-    return (rl * (uint64_t)op.sr + kl * (uint64_t)op.sk) * 8u < (1ull << 32);
+    return (rl * (uint64_t)op.sr + kl * (uint64_t)op.sk) * sizeof(typename OP::storage_t) <
+           (1ull << 32);
   } else {
     return true;
   }

@@ -54,6 +54,9 @@ enum Slot {
   W_BATCH_PRE,   // batched iteration: segment prefix sums, split counts
   W_BATCH_JOBS,  // batched iteration: grouped GEMM job tables
   W_BATCH_MOLS,  // batched iteration: molecule descriptors
+  W_MLP_F32,     // warm-start network: activations, gradients
+  W_MLP_F64,     // warm-start network: partial sums, squared errors
+  W_MLP_PERM,    // warm start: state permutation
   W_NSLOTS
 };
 

@@ -1,0 +1,244 @@
+"""Learned warm start of the qsGW iteration: data, training and evaluation.
+
+Every numerical step runs in libqsgw (batched iterations, per-state features,
+network forward/backward/Adam, warm-start orbitals); this module only moves
+tensors and keeps the books.
+
+Protocol (one reading of the workload, stated in the design notes):
+  * molecules from the batched distribution (N_b ~ U{20..120}, N_aux = 4 N_b,
+    n_occ = round(N_b / 6)), training seeds from 100000, held-out test seeds
+    from 200000;
+  * the plain path: batched iterations from the Hartree-Fock start (eps0, C0)
+    with linear mixing of the AO potential (mix 0.5; the unmixed iteration
+    oscillates at eta = 1e-3 Ha), up to MAX_ITER iterations; a molecule is
+    converged at the first iteration with max|d eps| < TOL;
+  * target of state m: delta_m = eps_m(converged) - eps0_m;
+  * features of state m: qsgw_mlp_features of the plain path's first
+    iteration, standardized with training-set statistics;
+  * warm start: one feature iteration (the plain first iteration's self-energy
+    diagonal), the network's delta, then the same iteration from
+    (eps0 + delta, C0) re-sorted; fallback: when the warm path's first
+    iteration moves any energy by more than 10 meV the prediction is rejected
+    and the plain path runs from the start;
+  * reported: iterations to TOL with and without the warm start (the warm
+    count includes the feature iteration and, on fallback, the rejected
+    iteration), fallbacks, and the prediction error against the converged
+    plain result.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import qsgw as q
+
+ETA = 1e-3
+MIX = 0.5
+TOL = 1e-5
+MAX_ITER = 40
+HARTREE_MEV = 27211.386
+FALLBACK_HA = 10.0 / HARTREE_MEV
+NO_SCALE = (8, 14, 15)  # flags and the constant: not standardized
+
+
+def build_molecules(ctx, stream, shapes):
+    from qsgw_inputs import make_problem
+    dev = torch.device("cuda:0")
+    mols = []
+    with torch.cuda.stream(stream):
+        for s in shapes:
+            p = make_problem(s["nbf"], s["naux"], s["nocc"], s["rank"], s["decay"], s["seed"])
+            B = torch.from_numpy(p.B_ao).to(dev)
+            C0 = torch.from_numpy(p.C0.copy()).to(dev)
+            e0 = torch.from_numpy(p.eps0.copy()).to(dev)
+            h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
+            mols.append(dict(nbf=p.nbf, nocc=p.nocc, B=B, C0=C0, e0=e0, h=h))
+    stream.synchronize()
+    return mols
+
+
+def iterate(ctx, stream, mols, starts, max_iter, diag=False, graph=True):
+    """Batched mixed iterations from the given (eps, C) starts.  Returns the
+    final energies, each molecule's max|d eps| history and (optionally) the
+    first iteration's diagonal outputs."""
+    with torch.cuda.stream(stream):
+        runs = []
+        for m, (e, C) in zip(mols, starts):
+            nbf = m["nbf"]
+            r = dict(B_ao=m["B"], h=m["h"], nocc=m["nocc"], eps=e.clone(), C=C.clone(),
+                     Vc=torch.zeros((nbf, nbf), dtype=torch.float64, device=e.device))
+            if diag:
+                r["diag"] = torch.empty((nbf, 4), dtype=torch.float64, device=e.device)
+            runs.append(r)
+    stream.synchronize()
+    with torch.cuda.stream(stream):
+        _, reps = q.qsgw_iterate_batched(ctx, runs, ETA, tol=TOL, max_iter=max_iter, graph=graph,
+                                         mix=MIX)
+    stream.synchronize()
+    return runs, [r["max_deps"] for r in reps]
+
+
+def first_below(hist, tol=TOL):
+    for j, d in enumerate(hist):
+        if d < tol:
+            return j + 1
+    return None
+
+
+def solve_plain(ctx, stream, mols, batch=256, max_iter=MAX_ITER):
+    """Plain path for every molecule: converged energies, iteration counts
+    and the first iteration's diagonal outputs (the features' source)."""
+    out = []
+    for b0 in range(0, len(mols), batch):
+        sub = mols[b0:b0 + batch]
+        runs, hists = iterate(ctx, stream, sub, [(m["e0"], m["C0"]) for m in sub], max_iter,
+                              diag=True)
+        for m, r, h in zip(sub, runs, hists):
+            out.append(dict(eps=r["eps"], diag=r["diag"], hist=h, iters=first_below(h)))
+    return out
+
+
+def features(ctx, stream, mols, plain, mean=None, scale=None):
+    with torch.cuda.stream(stream):
+        X = [q.qsgw_mlp_features(ctx, m["e0"], r["diag"], m["nocc"], mean, scale)
+             for m, r in zip(mols, plain)]
+        X = torch.cat(X)
+    stream.synchronize()
+    return X
+
+
+def standardization(X):
+    Xh = X.double().cpu().numpy()
+    mean = Xh.mean(axis=0)
+    scale = Xh.std(axis=0)
+    for k in NO_SCALE:
+        mean[k], scale[k] = 0.0, 1.0
+    scale[scale < 1e-12] = 1.0
+    dev = X.device
+    return (torch.tensor(mean, dtype=torch.float32, device=dev),
+            torch.tensor(scale, dtype=torch.float32, device=dev))
+
+
+def init_params(seed):
+    rng = np.random.default_rng(seed)
+    W1 = rng.uniform(-1, 1, (128, 16)) / math.sqrt(16)
+    W2 = rng.uniform(-1, 1, (128, 128)) / math.sqrt(128)
+    w3 = rng.uniform(-1, 1, 128) / math.sqrt(128)
+    p = np.concatenate([W1.ravel(), np.zeros(128), W2.ravel(), np.zeros(128), w3, np.zeros(1)])
+    assert p.size == q.MLP_NPARAMS
+    return torch.tensor(p, dtype=torch.float32, device="cuda")
+
+
+def train(ctx, stream, X, T, epochs=150, batch=4096, lr=2e-3, seed=0, log=None):
+    """Adam on minibatches (reshuffled each epoch), cosine learning-rate decay.
+    Targets are scaled to unit variance for training; returns (params, tscale)."""
+    n = X.shape[0]
+    tscale = float(T.double().std().item()) or 1.0
+    Ts = (T / tscale).contiguous()
+    P = init_params(seed)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    L = torch.zeros(1, dtype=torch.float64, device=X.device)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    steps = 0
+    total = epochs * ((n + batch - 1) // batch)
+    with torch.cuda.stream(stream):
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=gen).to(X.device)
+            Xp, Tp = X[perm].contiguous(), Ts[perm].contiguous()
+            for b0 in range(0, n, batch):
+                steps += 1
+                rate = 0.5 * lr * (1.0 + math.cos(math.pi * steps / total))
+                q.qsgw_mlp_train_step(ctx, P, M, V, steps, rate, Xp[b0:b0 + batch].contiguous(),
+                                      Tp[b0:b0 + batch].contiguous(), loss=L)
+            if log and (ep % 25 == 0 or ep == epochs - 1):
+                stream.synchronize()
+                log(f"[learn] epoch {ep + 1}/{epochs}: batch loss {L.item():.4e} (scaled)")
+    stream.synchronize()
+    return P, tscale
+
+
+def predict(ctx, stream, P, tscale, X):
+    with torch.cuda.stream(stream):
+        y = q.qsgw_mlp_forward(ctx, P, X.contiguous()) * tscale
+    stream.synchronize()
+    return y
+
+
+def run(n_train=1024, n_test=256, epochs=150, max_iter=MAX_ITER, log=print):
+    """Full protocol; returns a dict of results."""
+    from qsgw_inputs import batch_shapes
+    stream = torch.cuda.Stream()
+    ctx = q.Context(stream)
+    t0 = time.perf_counter()
+    res = dict(eta=ETA, mix=MIX, tol=TOL, max_iter=max_iter, n_train=n_train, n_test=n_test)
+    tr_shapes = batch_shapes(nmol=n_train, seed=5, base_seed=100000)
+    te_shapes = batch_shapes(nmol=n_test, seed=6, base_seed=200000)
+    X_tr, T_tr = [], []
+    conv_tr = 0
+    for b0 in range(0, n_train, 256):
+        mols = build_molecules(ctx, stream, tr_shapes[b0:b0 + 256])
+        plain = solve_plain(ctx, stream, mols, max_iter=max_iter)
+        X = features(ctx, stream, mols, plain)
+        for m, r, xs in zip(mols, plain, torch.split(X, [m["nbf"] for m in mols])):
+            if r["iters"] is None:
+                continue
+            conv_tr += 1
+            X_tr.append(xs)
+            T_tr.append((r["eps"] - m["e0"]).float())
+        log(f"[learn] training molecules {b0 + len(mols)}/{n_train} solved, "
+            f"{conv_tr} converged ({time.perf_counter() - t0:.0f} s)")
+        del mols, plain, X
+    X_tr = torch.cat(X_tr)
+    T_tr = torch.cat(T_tr)
+    mean, scale = standardization(X_tr)
+    Xs = (X_tr - mean) / scale
+    t1 = time.perf_counter()
+    P, tscale = train(ctx, stream, Xs.contiguous(), T_tr, epochs=epochs, log=log)
+    res["train_seconds"] = time.perf_counter() - t1
+    res["train_states"] = int(X_tr.shape[0])
+    res["train_molecules_converged"] = conv_tr
+    # held-out molecules: plain, then warm
+    mols = build_molecules(ctx, stream, te_shapes)
+    plain = solve_plain(ctx, stream, mols, max_iter=max_iter)
+    X = features(ctx, stream, mols, plain, mean, scale)
+    dhat = predict(ctx, stream, P, tscale, X)
+    starts = []
+    with torch.cuda.stream(stream):
+        for m, d in zip(mols, torch.split(dhat, [m["nbf"] for m in mols])):
+            starts.append(q.qsgw_warm_start(ctx, m["e0"], m["C0"], d.contiguous()))
+    stream.synchronize()
+    runs, hists = iterate(ctx, stream, mols, starts, max_iter)
+    rows = []
+    for m, r, d, h in zip(mols, plain, torch.split(dhat, [m["nbf"] for m in mols]), hists):
+        true = (r["eps"] - m["e0"]).double().cpu().numpy() if r["iters"] else None
+        err = float(np.max(np.abs(d.double().cpu().numpy() - true))) if true is not None else None
+        accept = h[0] <= FALLBACK_HA
+        warm = first_below(h)
+        if accept and warm is not None:
+            cost = 1 + warm
+        elif r["iters"] is not None:
+            cost = 2 + r["iters"]  # feature iteration + rejected iteration + plain
+        else:
+            cost = None
+        rows.append(dict(nbf=m["nbf"], plain=r["iters"], warm=warm, accept=accept, cost=cost,
+                         err=err))
+    both = [x for x in rows if x["plain"] is not None and x["cost"] is not None]
+    res["test_converged_plain"] = sum(x["plain"] is not None for x in rows)
+    res["compared"] = len(both)
+    res["plain_mean_iterations"] = float(np.mean([x["plain"] for x in both])) if both else None
+    res["warm_mean_iterations"] = float(np.mean([x["cost"] for x in both])) if both else None
+    res["fallbacks"] = sum(not x["accept"] for x in rows)
+    errs = [x["err"] for x in rows if x["err"] is not None]
+    res["prediction_max_err_meV_median"] = float(np.median(errs) * HARTREE_MEV) if errs else None
+    res["prediction_within_10meV"] = int(sum(e <= FALLBACK_HA for e in errs))
+    res["false_accept"] = sum(x["accept"] and x["err"] is not None and x["err"] > FALLBACK_HA
+                              for x in rows)
+    res["false_reject"] = sum((not x["accept"]) and x["err"] is not None and x["err"] <= FALLBACK_HA
+                              for x in rows)
+    res["seconds"] = time.perf_counter() - t0
+    ctx.close()
+    return res

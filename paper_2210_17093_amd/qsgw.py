@@ -36,12 +36,15 @@ SIGMA_DIAG_SELF = 2
 FOCK_FULL_JK = 0
 OPT_GRAPH = 1
 REPORT_MAX_ITERS = 64
+MLP_NPARAMS = 18817
+MLP_NFEAT = 16
 STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "eig_fock")
 
 EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
            "qsgw_residues", "qsgw_sigma", "qsgw_hf_core", "qsgw_iterate",
-           "qsgw_iterate_batched")
+           "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
+           "qsgw_mlp_train_step", "qsgw_warm_start")
 
 
 class QsgwError(RuntimeError):
@@ -107,6 +110,10 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
                           ct.POINTER(Report)], I),
         "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
                                   ct.POINTER(Options), ct.POINTER(Report)], I),
+        "qsgw_mlp_features": ([P, I64, I64, P, P, P, P, P], I),
+        "qsgw_mlp_forward": ([P, P, I64, P, P], I),
+        "qsgw_mlp_train_step": ([P, P, P, P, I64, D, I64, P, P, P, P], I),
+        "qsgw_warm_start": ([P, I64, P, P, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -343,3 +350,54 @@ def qsgw_iterate_batched(ctx: Context, mols, eta, tol=1e-6, max_iter=1, graph=Fa
     for i, m in enumerate(mols):
         m["iteration"] = int(states[i].iteration)
     return rc, [r.as_dict() for r in reps]
+
+
+# ------------------------------------------------------------ warm start --
+def qsgw_mlp_features(ctx: Context, eps, diag, nocc, mean=None, scale=None, out=None):
+    """Per-state features [nbf][16] (float32) of one molecule."""
+    nbf = eps.shape[0]
+    if out is None:
+        out = torch.empty((nbf, MLP_NFEAT), dtype=torch.float32, device=eps.device)
+    ctx.check(lib().qsgw_mlp_features(
+        ctx.handle, nbf, int(nocc), _ptr(eps, (nbf,), name="eps"), _ptr(diag, (nbf, 4), name="diag"),
+        _ptr(mean, (MLP_NFEAT,), torch.float32, name="mean") if mean is not None else None,
+        _ptr(scale, (MLP_NFEAT,), torch.float32, name="scale") if scale is not None else None,
+        _ptr(out, (nbf, MLP_NFEAT), torch.float32, name="X")))
+    return out
+
+
+def qsgw_mlp_forward(ctx: Context, params, X, out=None):
+    n = X.shape[0]
+    if out is None:
+        out = torch.empty((n,), dtype=torch.float32, device=X.device)
+    ctx.check(lib().qsgw_mlp_forward(ctx.handle, _ptr(params, (MLP_NPARAMS,), torch.float32, "params"),
+                                     n, _ptr(X, (n, MLP_NFEAT), torch.float32, "X"),
+                                     _ptr(out, (n,), torch.float32, "y")))
+    return out
+
+
+def qsgw_mlp_train_step(ctx: Context, params, adam_m, adam_v, step, lr, X, target, grad=None,
+                        loss=None):
+    """One Adam step in place; returns (grad, loss) device tensors when given."""
+    n = X.shape[0]
+    f32 = torch.float32
+    ctx.check(lib().qsgw_mlp_train_step(
+        ctx.handle, _ptr(params, (MLP_NPARAMS,), f32, "params"), _ptr(adam_m, (MLP_NPARAMS,), f32, "m"),
+        _ptr(adam_v, (MLP_NPARAMS,), f32, "v"), int(step), float(lr), n,
+        _ptr(X, (n, MLP_NFEAT), f32, "X"), _ptr(target, (n,), f32, "target"),
+        _ptr(grad, (MLP_NPARAMS,), f32, "grad") if grad is not None else None,
+        _ptr(loss, (1,), torch.float64, "loss") if loss is not None else None))
+    return grad, loss
+
+
+def qsgw_warm_start(ctx: Context, eps0, C0, delta, eps=None, C=None):
+    nbf = eps0.shape[0]
+    if eps is None:
+        eps = torch.empty_like(eps0)
+    if C is None:
+        C = torch.empty_like(C0)
+    ctx.check(lib().qsgw_warm_start(ctx.handle, nbf, _ptr(eps0, (nbf,), name="eps0"),
+                                    _ptr(C0, (nbf, nbf), name="C0"),
+                                    _ptr(delta, (nbf,), torch.float32, "delta"),
+                                    _ptr(eps, (nbf,), name="eps"), _ptr(C, (nbf, nbf), name="C")))
+    return eps, C

@@ -1,0 +1,132 @@
+"""HIP kernels of the learned warm start against the NumPy reference
+(tests/mlp_ref.py, pinned by finite differences) and the feature and
+warm-start definitions of include/qsgw.h."""
+import numpy as np
+import pytest
+
+import mlp_ref as R
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2210_17093_amd.qsgw as q
+    ctx = q.Context()
+    yield q, ctx
+    ctx.close()
+
+
+def dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000, 5000])
+def test_forward_matches_reference(env, n):
+    q, ctx = env
+    rng = np.random.default_rng(n)
+    p = R.init(2) + 0.02 * rng.standard_normal(R.NPARAMS)
+    X = rng.standard_normal((n, R.NIN))
+    p32, X32 = p.astype(np.float32), X.astype(np.float32)
+    y = q.qsgw_mlp_forward(ctx, dev32(p32), dev32(X32)).cpu().numpy()
+    yr, _ = R.forward(p32.astype(np.float64), X32.astype(np.float64))
+    np.testing.assert_allclose(y, yr, rtol=0, atol=2e-5 * max(1.0, np.abs(yr).max()))
+
+
+@pytest.mark.parametrize("n", [5, 700, 4100])
+def test_train_step_gradient_loss_and_adam(env, n):
+    q, ctx = env
+    rng = np.random.default_rng(10 + n)
+    p = (R.init(3) + 0.02 * rng.standard_normal(R.NPARAMS)).astype(np.float32)
+    X = rng.standard_normal((n, R.NIN)).astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    m0 = (0.01 * rng.standard_normal(R.NPARAMS)).astype(np.float32)
+    v0 = (0.01 * rng.random(R.NPARAMS)).astype(np.float32)
+    P, M, V = dev32(p), dev32(m0), dev32(v0)
+    G = torch.empty(R.NPARAMS, dtype=torch.float32, device="cuda")
+    L = torch.empty(1, dtype=torch.float64, device="cuda")
+    q.qsgw_mlp_train_step(ctx, P, M, V, 3, 1e-3, dev32(X), dev32(t), grad=G, loss=L)
+    g = G.cpu().numpy().astype(np.float64)
+    p64, X64, t64 = p.astype(np.float64), X.astype(np.float64), t.astype(np.float64)
+    gr = R.grad(p64, X64, t64)
+    lr_ = R.loss(p64, X64, t64)
+    assert abs(L.item() - lr_) <= 1e-5 * max(1.0, lr_)
+    # FP32 products and activations: compare each block against its own scale
+    o = 0
+    for k, s in R.SIZES.items():
+        sz = int(np.prod(s))
+        a, b = g[o:o + sz], gr[o:o + sz]
+        assert np.max(np.abs(a - b)) <= 1e-4 * max(np.abs(b).max(), 1e-6), k
+        o += sz
+    # Adam on the returned gradient
+    pe, me, ve = R.adam(p64, m0.astype(np.float64), v0.astype(np.float64), g, 3, 1e-3)
+    np.testing.assert_allclose(P.cpu().numpy(), pe, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(M.cpu().numpy(), me, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(V.cpu().numpy(), ve, rtol=1e-5, atol=1e-12)
+
+
+def test_training_reduces_loss(env):
+    """A smooth synthetic regression: 300 Adam steps cut the loss tenfold."""
+    q, ctx = env
+    rng = np.random.default_rng(5)
+    n = 2048
+    X = rng.standard_normal((n, R.NIN)).astype(np.float32)
+    t = (np.tanh(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
+    P = dev32(R.init(4))
+    M = torch.zeros(R.NPARAMS, dtype=torch.float32, device="cuda")
+    V = torch.zeros_like(M)
+    L = torch.empty(1, dtype=torch.float64, device="cuda")
+    Xd, td = dev32(X), dev32(t)
+    q.qsgw_mlp_train_step(ctx, P, M, V, 1, 3e-3, Xd, td, loss=L)
+    first = L.item()
+    for s in range(2, 301):
+        q.qsgw_mlp_train_step(ctx, P, M, V, s, 3e-3, Xd, td, loss=L)
+    assert L.item() < 0.1 * first, (first, L.item())
+
+
+def test_features_follow_their_definition(env):
+    q, ctx = env
+    from qsgw_inputs import make_config
+    p = make_config("cfg1")
+    B = torch.from_numpy(p.B_ao).cuda()
+    C0 = torch.from_numpy(p.C0.copy()).cuda()
+    e0 = torch.from_numpy(p.eps0.copy()).cuda()
+    h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
+    d = torch.empty((p.nbf, 4), dtype=torch.float64, device="cuda")
+    e, C = e0.clone(), C0.clone()
+    q.qsgw_iterate(ctx, B, h, p.nocc, e, C, 1e-3, tol=0.0, max_iter=1, diag=d)
+    X = q.qsgw_mlp_features(ctx, e0, d, p.nocc).cpu().numpy()
+    dd, eps = d.cpu().numpy(), p.eps0
+    nb, no = p.nbf, p.nocc
+    z = 1.0 / (1.0 - dd[:, 2])
+    ref = np.stack([eps, dd[:, 3], dd[:, 0], dd[:, 2], np.full(nb, no / nb),
+                    np.full(nb, eps[no] - eps[no - 1]), dd[:, 1], z,
+                    (np.arange(nb) < no).astype(float), eps - eps[no - 1], eps - eps[no],
+                    np.full(nb, nb / 120), np.arange(nb) / nb, z * dd[:, 0],
+                    (np.abs(dd[:, 2]) > 1).astype(float), np.ones(nb)], axis=1)
+    np.testing.assert_allclose(X, ref.astype(np.float32), rtol=1e-6, atol=1e-7)
+    mean = np.linspace(-1, 1, 16).astype(np.float32)
+    scale = np.linspace(0.5, 2, 16).astype(np.float32)
+    Xs = q.qsgw_mlp_features(ctx, e0, d, p.nocc, dev32(mean), dev32(scale)).cpu().numpy()
+    np.testing.assert_allclose(Xs, (ref.astype(np.float32) - mean) / scale, rtol=1e-5, atol=1e-6)
+
+
+def test_warm_start_sorts_and_permutes(env):
+    q, ctx = env
+    rng = np.random.default_rng(9)
+    for nbf in (1, 5, 130):
+        eps0 = np.sort(rng.uniform(-3, 3, nbf))
+        C0 = rng.standard_normal((nbf, nbf))
+        delta = rng.uniform(-1, 1, nbf).astype(np.float32)
+        if nbf > 2:
+            delta[1] = np.float32(eps0[2] - eps0[1]) + delta[2]  # a tie, resolved by index
+            eps0[1] = eps0[2] - float(delta[1]) + float(delta[2])
+        e, C = q.qsgw_warm_start(ctx, torch.from_numpy(eps0).cuda(), torch.from_numpy(C0).cuda(),
+                                 dev32(delta))
+        shifted = eps0 + delta.astype(np.float64)
+        order = np.argsort(shifted, kind="stable")
+        np.testing.assert_array_equal(e.cpu().numpy(), shifted[order])
+        np.testing.assert_array_equal(C.cpu().numpy(), C0[:, order])
