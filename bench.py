@@ -60,6 +60,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def tuned_tiles(workload):
+    """Tile table the autotuner (paper_2210_17093_amd/tune.py) chose for this
+    workload, or None (library defaults)."""
+    path = os.path.join(ROOT, "paper_2210_17093_amd", "tiles.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(workload, {}).get("spec")
+
+
 def workload_name(p, eta):
     return (f"plain FP64 qsGW iteration, N_basis={p.nbf}, N_aux={p.naux}, n_occ={p.nocc}, "
             f"{p.ntr} transitions, eta={eta} Ha, synthetic RI tensor rank {p.meta['rank']} "
@@ -149,6 +159,8 @@ def bench_batched(args, q, torch):
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
     ctx = q.Context(stream)
+    tiles = tuned_tiles("cfg4")
+    ctx.set_tiles(tiles)
     probs = []
     with torch.cuda.stream(stream):
         for s in shapes:
@@ -234,7 +246,8 @@ def bench_batched(args, q, torch):
         "config": {"workload": (f"{len(probs)} synthetic molecules, N_basis uniform in [20, 120], "
                                 f"N_aux = 4 N_basis, n_occ = round(N_basis/6), {iters} qsGW "
                                 f"iterations each, eta = {eta} Ha, kernel segments from hipGraphs"),
-                   "precision": pick},
+                   "precision": pick, "tiles": ctx.get_tiles(),
+                   "tiles_from": "tune.py" if tiles else "defaults"},
         "hot_path_ms": round(r0["ms"]["mo_transform"], 3),
         "eig_rpa_ms": round(r0["ms"]["eig_rpa"], 3),
         "eig_fock_ms": round(r0["ms"]["eig_fock"], 3),
@@ -362,6 +375,8 @@ def main():
     C = torch.empty_like(C0)
     e = torch.empty_like(e0)
     ctx = q.Context()
+    tiles = tuned_tiles(args.config)
+    ctx.set_tiles(tiles)
     h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
     torch.cuda.synchronize()
 
@@ -436,7 +451,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if pick == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": workload_name(p, eta), "precision": pick},
+        "config": {"workload": workload_name(p, eta), "precision": pick,
+                   "tiles": ctx.get_tiles(), "tiles_from": "tune.py" if tiles else "defaults"},
         "hot_path_ms": round(S["hot_ms"], 3),
         "eig_rpa_ms": round(S["eig_rpa"], 3),
         "eig_fock_ms": round(S["eig_fock"], 3),

@@ -212,6 +212,12 @@ typedef struct {
 /* qsgw_options.flags, qsgw_iterate_batched only: run the kernel segments
  * between eigensolves from hipGraphs captured on the first iteration. */
 #define QSGW_OPT_GRAPH 1
+/* qsgw_options.flags, qsgw_iterate with a reduced precision only: after the
+ * reduced-precision iterations stop (converged or max_iter), run one more
+ * iteration in FP64 from where they stopped (refinement pass).  The report
+ * counts it: its last max_deps entry is the FP64 iteration's, and converged
+ * and the return code are that iteration's. */
+#define QSGW_OPT_REFINE 2
 
 typedef struct {
   int64_t iterations; /* iterations done in this call */
@@ -272,6 +278,21 @@ int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const 
  */
 int qsgw_iterate_batched(qsgw_ctx* ctx, int64_t nmol, const qsgw_problem* probs,
                          qsgw_state* states, const qsgw_options* opt, qsgw_report* reports);
+
+/*
+ * Tile table of the context (written by the autotuner, tune.py).  spec is a
+ * comma-separated list of key=value: mo1, rho, sigma take 64x64, 128x64 or
+ * 128x128; mo2, casida, exchange (symmetric products) 64x64 or 128x128;
+ * sigma_target, rho_target, exchange_target (integers in [64, 2^20]) are the
+ * workgroup counts a K-split aims for when a product has few output tiles.
+ * Keys not given keep their defaults (mo1=128x64, mo2=64x64,
+ * casida=128x128, rho=128x128, sigma=64x64, exchange=64x64, 4096, 2048,
+ * 2048); NULL or "" restores all defaults.  Every later product and
+ * iteration on the context uses the table (results change only by rounding
+ * order).  qsgw_get_tiles writes the current table in the same format.
+ */
+int qsgw_set_tiles(qsgw_ctx* ctx, const char* spec);
+int qsgw_get_tiles(qsgw_ctx* ctx, char* buf, int64_t size);
 
 /* ------------------------------------------------------------------------
  * Learned warm start.  A network 16 -> 128 -> 128 -> 1 with GELU

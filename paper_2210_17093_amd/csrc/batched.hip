@@ -288,11 +288,12 @@ struct Plan {
   double mix = 1.0;
 };
 
-template <int BM, int BN, class J>
-int upload_jobs(qsgw_ctx* c, std::vector<J>& jobs, char*& cursor, const J** out, int64_t* nwg) {
+template <class J>
+int upload_jobs(qsgw_ctx* c, std::vector<J>& jobs, int bm, int bn, char*& cursor, const J** out,
+                int64_t* nwg) {
   int64_t wg = 0;
   for (auto& j : jobs) {
-    if (!loader_offsets_fit(j.a, BM) || !loader_offsets_fit(j.b, BN))
+    if (!loader_offsets_fit(j.a, bm) || !loader_offsets_fit(j.b, bn))
       return fail(c, QSGW_ERR_UNSUPPORTED, "batched: operand strides too large for the tile loader");
     j.wg_begin = wg;
     const int64_t tiles = j.tiles_n > 0 ? j.tiles_m * j.tiles_n : j.tiles_m * (j.tiles_m + 1) / 2;
@@ -331,6 +332,24 @@ int launch_grouped(qsgw_ctx* c, const char* what, const GemmJob<OA, OB, EPI>* jo
   return launch_check(c, what);
 }
 
+// Grouped launch with the tile shape chosen at run time.
+template <bool TRI, class CT, class OA, class OB, class EPI>
+int launch_shape(qsgw_ctx* c, int shape, const char* what, const GemmJob<OA, OB, EPI>* jobs,
+                 int64_t njobs, int64_t nwg) {
+  switch (shape) {
+    case SH_64x64:
+      return launch_grouped<64, 64, TRI, CT>(c, what, jobs, njobs, nwg);
+    case SH_128x128:
+      return launch_grouped<128, 128, TRI, CT>(c, what, jobs, njobs, nwg);
+    default:
+      if constexpr (TRI) {
+        return fail(c, QSGW_ERR_INVALID_ARG, "%s: symmetric products take square tiles", what);
+      } else {
+        return launch_grouped<128, 64, false, CT>(c, what, jobs, njobs, nwg);
+      }
+  }
+}
+
 // The kernel body handles a symmetric job through tiles_n = 0: the grouped
 // kernel is instantiated with TRI and reads tiles_m only.
 typedef GemmJob<Strided<true>, Strided<false>, EpiStore> JobTF;
@@ -366,17 +385,18 @@ int segment_a(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   const int64_t nmol = (int64_t)P.mols.size();
   hipLaunchKernelGGL(kb_zero_flags, dim3(blocks_for(nmol)), dim3(256), 0, c->stream, P.dmols, nmol);
   SPAN_OPEN(sp, kKMo1);
-  CHECK((launch_grouped<128, 64, false, CT>(c, "batched mo/1", J.mo1, J.n, J.mo1_wg)));
+  CHECK((launch_shape<false, CT>(c, c->tiles.shape[TU_MO1], "batched mo/1", J.mo1, J.n, J.mo1_wg)));
   SPAN_CLOSE(sp);
   SPAN_OPEN(sp, kKMo2);
-  CHECK((launch_grouped<64, 64, true, CT>(c, "batched mo/2", J.mo2, J.n, J.mo2_wg)));
+  CHECK((launch_shape<true, CT>(c, c->tiles.shape[TU_MO2], "batched mo/2", J.mo2, J.n, J.mo2_wg)));
   SPAN_CLOSE(sp);
   SPAN_OPEN(sp, kKCasida);
   hipLaunchKernelGGL(kb_transitions, dim3(blocks_for(P.total[S_NTR])), dim3(256), 0, c->stream,
                      P.dmols, P.dpre[S_NTR], nmol, P.total[S_NTR]);
   hipLaunchKernelGGL(kb_gather_bia, dim3(blocks_for(P.total[S_NAUXNTR])), dim3(256), 0, c->stream,
                      P.dmols, P.dpre[S_NAUXNTR], nmol, P.total[S_NAUXNTR]);
-  CHECK((launch_grouped<128, 128, true, CT>(c, "batched casida", J.cas, J.n, J.cas_wg)));
+  CHECK((launch_shape<true, CT>(c, c->tiles.shape[TU_CASIDA], "batched casida", J.cas, J.n,
+                                J.cas_wg)));
   SPAN_CLOSE(sp);
   hipLaunchKernelGGL(kb_gershgorin, dim3((unsigned)nmol), dim3(256), 0, c->stream, P.dmols, 0);
   hipLaunchKernelGGL(kb_pad, dim3(blocks_for(P.total[S_NBM2])), dim3(256), 0, c->stream, P.dmols,
@@ -390,7 +410,7 @@ int segment_b(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   SPAN_OPEN(sp, kKRho);
   hipLaunchKernelGGL(kb_omega, dim3(blocks_for(P.total[S_NTR])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NTR], nmol, P.total[S_NTR]);
-  CHECK((launch_grouped<128, 128, false, CT>(c, "batched rho", J.rho, J.n, J.rho_wg)));
+  CHECK((launch_shape<false, CT>(c, c->tiles.shape[TU_RHO], "batched rho", J.rho, J.n, J.rho_wg)));
   hipLaunchKernelGGL(kb_rho_reduce, dim3(blocks_for(P.total[S_NAUXNTR])), dim3(256), 0, c->stream,
                      P.dmols, P.dpre[S_NAUXNTR], nmol, P.total[S_NAUXNTR]);
   SPAN_CLOSE(sp);
@@ -403,7 +423,8 @@ int segment_b(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
 int segment_b2(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   const int64_t nmol = (int64_t)P.mols.size();
   SPAN_OPEN(sp, kKSigma);
-  CHECK((launch_grouped<64, 64, false, double>(c, "batched sigma", J.sig, J.n, J.sig_wg)));
+  CHECK((launch_shape<false, double>(c, c->tiles.shape[TU_SIGMA], "batched sigma", J.sig, J.n,
+                                     J.sig_wg)));
   SPAN_CLOSE(sp);
   SPAN_OPEN(sp, kKSigmaRed);
   hipLaunchKernelGGL(kb_reduce_nn, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream, P.dmols,
@@ -430,7 +451,8 @@ int segment_b2(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
                      P.dmols, P.dpre[S_NAUX], nmol, P.total[S_NAUX]);
   hipLaunchKernelGGL(kb_hartree, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NN], nmol, P.total[S_NN]);
-  CHECK((launch_grouped<64, 64, true, double>(c, "batched exchange", J.exc, J.n, J.exc_wg)));
+  CHECK((launch_shape<true, double>(c, c->tiles.shape[TU_EXCHANGE], "batched exchange", J.exc, J.n,
+                                    J.exc_wg)));
   hipLaunchKernelGGL(kb_reduce_nn, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NN], nmol, P.total[S_NN], P.exc_nz, 1);
   SPAN_CLOSE(sp);
@@ -528,10 +550,10 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     m.eta = o->eta;
     bucketM[m.nbM].push_back(i);
     bucketF[m.nbF].push_back(i);
-    const SplitPlan rs = rho_split(m.naux, m.ntr, m.ntr, fp32 ? kFp32MaxK : m.ntr);
+    const SplitPlan rs = rho_split(c->tiles, m.naux, m.ntr, m.ntr, fp32 ? kFp32MaxK : m.ntr);
     m.rho_nz = rs.nz;
-    sig_nz[i] = sigma_split(m.nbf, m.ntr).nz;
-    exc_nz[i] = exchange_split(m.nbf, m.naux, m.nocc).nz;
+    sig_nz[i] = sigma_split(c->tiles, m.nbf, m.ntr).nz;
+    exc_nz[i] = exchange_split(c->tiles, m.nbf, m.naux, m.nocc).nz;
     const int64_t pnz = std::max(sig_nz[i], exc_nz[i]);
     nd += 2 * m.naux * m.nn + m.naux * m.ntr * (2 + m.rho_nz) + 2 * m.ntr + 2 * m.nn * m.ntr +
           pnz * m.nn + 7 * m.nn + m.naux + 64;
@@ -659,33 +681,39 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   std::vector<JobTF> cg3, ct1;
   std::vector<JobTT> cg4;
   std::vector<JobFF> ct2;
+  const Tiles& tl = c->tiles;
+  auto bm = [&](int t) { return shape_m(tl.shape[t]); };
+  auto bn = [&](int t) { return shape_n(tl.shape[t]); };
   for (int64_t i = 0; i < nmol; ++i) {
     const Mol& m = P.mols[i];
     const int64_t nbf = m.nbf, naux = m.naux, ntr = m.ntr, nn = m.nn;
     const SplitPlan one{0, 1};
     mo1.push_back(job(Strided<true>{m.B_ao, nbf, 1, 0, naux * nbf}, Strided<false>{m.C, 1, nbf, 0, nbf},
-                      EpiStore{m.T, nbf, 0, 0, 1.0}, naux * nbf, nbf, nbf, 1, 128, 64, one, false));
-    mo2.push_back(job(Strided<false>{m.C, 1, nbf, 0, nbf}, Strided<false>{m.T, 1, nbf, nn, nbf},
-                      EpiStore{m.Bmo, nbf, nn, 0, 1.0}, nbf, nbf, nbf, naux, 64, 64, one, true));
-    cas.push_back(job(Strided<false>{m.Bt, 1, ntr, 0, ntr}, Strided<false>{m.Bt, 1, ntr, 0, ntr},
-                      EpiCasida{m.M, m.delta, m.nbM}, ntr, ntr, naux, 1, 128, 128, one, true));
-    const SplitPlan rs = rho_split(naux, ntr, ntr, fp32 ? kFp32MaxK : ntr);
-    rho.push_back(job(Strided<true>{m.Bt, ntr, 1, 0, naux}, Strided<true>{m.M, m.nbM, 1, 0, ntr},
-                      EpiStore{m.rhopart, ntr, 0, naux * ntr, 1.0}, naux, ntr, ntr, 1, 128, 128, rs,
+                      EpiStore{m.T, nbf, 0, 0, 1.0}, naux * nbf, nbf, nbf, 1, bm(TU_MO1), bn(TU_MO1), one,
                       false));
+    mo2.push_back(job(Strided<false>{m.C, 1, nbf, 0, nbf}, Strided<false>{m.T, 1, nbf, nn, nbf},
+                      EpiStore{m.Bmo, nbf, nn, 0, 1.0}, nbf, nbf, nbf, naux, bm(TU_MO2), bn(TU_MO2), one,
+                      true));
+    cas.push_back(job(Strided<false>{m.Bt, 1, ntr, 0, ntr}, Strided<false>{m.Bt, 1, ntr, 0, ntr},
+                      EpiCasida{m.M, m.delta, m.nbM}, ntr, ntr, naux, 1, bm(TU_CASIDA), bn(TU_CASIDA), one,
+                      true));
+    const SplitPlan rs = rho_split(tl, naux, ntr, ntr, fp32 ? kFp32MaxK : ntr);
+    rho.push_back(job(Strided<true>{m.Bt, ntr, 1, 0, naux}, Strided<true>{m.M, m.nbM, 1, 0, ntr},
+                      EpiStore{m.rhopart, ntr, 0, naux * ntr, 1.0}, naux, ntr, ntr, 1, bm(TU_RHO),
+                      bn(TU_RHO), rs, false));
     wj.push_back(job(PairRows<8, 16>{m.Bmo, nn, 0, nbf, m.pblocks}, Strided<false>{m.rho, 1, ntr, 0, ntr},
                      EpiPairResidue{m.w, m.wh, m.pblocks, m.eps, m.Mev, nbf, m.nocc, ntr, o->eta},
                      m.npblocks * 128, ntr, naux, 1, 128, 128, one, false));
     sig.push_back(job(Strided<true>{m.wh, nbf * ntr, 1, 0, nbf}, Strided<true>{m.w, nbf * ntr, 1, 0, nbf},
-                      EpiStore{m.part, nbf, 0, nn, 1.0}, nbf, nbf, nbf * ntr, 1, 64, 64,
-                      sigma_split(nbf, ntr), false));
+                      EpiStore{m.part, nbf, 0, nn, 1.0}, nbf, nbf, nbf * ntr, 1, bm(TU_SIGMA),
+                      bn(TU_SIGMA), sigma_split(tl, nbf, ntr), false));
     hc1.push_back(job(Strided<true>{m.h, nbf, 1, 0, nbf}, Strided<false>{m.C, 1, nbf, 0, nbf},
                       EpiStore{m.tmp, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
     hc2.push_back(job(Strided<false>{m.C, 1, nbf, 0, nbf}, Strided<false>{m.tmp, 1, nbf, 0, nbf},
                       EpiStore{m.hmo, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
     exc.push_back(job(OccRowsOp{m.Bmo, nbf, m.nocc}, OccRowsOp{m.Bmo, nbf, m.nocc},
-                      EpiStore{m.part, nbf, 0, nn, 1.0}, nbf, nbf, naux * m.nocc, 1, 64, 64,
-                      exchange_split(nbf, naux, m.nocc), true));
+                      EpiStore{m.part, nbf, 0, nn, 1.0}, nbf, nbf, naux * m.nocc, 1, bm(TU_EXCHANGE),
+                      bn(TU_EXCHANGE), exchange_split(tl, nbf, naux, m.nocc), true));
     rot.push_back(job(Strided<true>{m.C, nbf, 1, 0, nbf}, Strided<true>{m.F, m.nbF, 1, 0, nbf},
                       EpiStore{m.Cn, nbf, 0, 0, 1.0}, nbf, nbf, nbf, 1, 64, 64, one, false));
     if (m.Vc) {
@@ -711,20 +739,20 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   char* cursor = jb;
   Jobs J;
   J.n = nmol;
-  CHECK((upload_jobs<128, 64>(c, mo1, cursor, &J.mo1, &J.mo1_wg)));
-  CHECK((upload_jobs<64, 64>(c, mo2, cursor, &J.mo2, &J.mo2_wg)));
-  CHECK((upload_jobs<128, 128>(c, cas, cursor, &J.cas, &J.cas_wg)));
-  CHECK((upload_jobs<128, 128>(c, rho, cursor, &J.rho, &J.rho_wg)));
-  CHECK((upload_jobs<128, 128>(c, wj, cursor, &J.w, &J.w_wg)));
-  CHECK((upload_jobs<64, 64>(c, sig, cursor, &J.sig, &J.sig_wg)));
-  CHECK((upload_jobs<64, 64>(c, hc1, cursor, &J.hc1, &J.hc1_wg)));
-  CHECK((upload_jobs<64, 64>(c, hc2, cursor, &J.hc2, &J.hc2_wg)));
-  CHECK((upload_jobs<64, 64>(c, exc, cursor, &J.exc, &J.exc_wg)));
-  CHECK((upload_jobs<64, 64>(c, rot, cursor, &J.rot, &J.rot_wg)));
-  CHECK((upload_jobs<64, 64>(c, cg3, cursor, &J.cg3, &J.cg3_wg)));
-  CHECK((upload_jobs<64, 64>(c, cg4, cursor, &J.cg4, &J.cg4_wg)));
-  CHECK((upload_jobs<64, 64>(c, ct1, cursor, &J.ct1, &J.ct1_wg)));
-  CHECK((upload_jobs<64, 64>(c, ct2, cursor, &J.ct2, &J.ct2_wg)));
+  CHECK(upload_jobs(c, mo1, bm(TU_MO1), bn(TU_MO1), cursor, &J.mo1, &J.mo1_wg));
+  CHECK(upload_jobs(c, mo2, bm(TU_MO2), bn(TU_MO2), cursor, &J.mo2, &J.mo2_wg));
+  CHECK(upload_jobs(c, cas, bm(TU_CASIDA), bn(TU_CASIDA), cursor, &J.cas, &J.cas_wg));
+  CHECK(upload_jobs(c, rho, bm(TU_RHO), bn(TU_RHO), cursor, &J.rho, &J.rho_wg));
+  CHECK(upload_jobs(c, wj, 128, 128, cursor, &J.w, &J.w_wg));
+  CHECK(upload_jobs(c, sig, bm(TU_SIGMA), bn(TU_SIGMA), cursor, &J.sig, &J.sig_wg));
+  CHECK(upload_jobs(c, hc1, 64, 64, cursor, &J.hc1, &J.hc1_wg));
+  CHECK(upload_jobs(c, hc2, 64, 64, cursor, &J.hc2, &J.hc2_wg));
+  CHECK(upload_jobs(c, exc, bm(TU_EXCHANGE), bn(TU_EXCHANGE), cursor, &J.exc, &J.exc_wg));
+  CHECK(upload_jobs(c, rot, 64, 64, cursor, &J.rot, &J.rot_wg));
+  CHECK(upload_jobs(c, cg3, 64, 64, cursor, &J.cg3, &J.cg3_wg));
+  CHECK(upload_jobs(c, cg4, 64, 64, cursor, &J.cg4, &J.cg4_wg));
+  CHECK(upload_jobs(c, ct1, 64, 64, cursor, &J.ct1, &J.ct1_wg));
+  CHECK(upload_jobs(c, ct2, 64, 64, cursor, &J.ct2, &J.ct2_wg));
   J.nv = (int64_t)cg3.size();
   J.nmix = (int64_t)ct1.size();
   Mol* dm = nullptr;

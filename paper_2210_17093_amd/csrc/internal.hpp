@@ -65,6 +65,18 @@ struct Buffer {
   size_t bytes = 0;
 };
 
+// Tile shapes of the tunable products (qsgw_set_tiles).  Symmetric (upper
+// tile) products take square shapes only.
+enum Shape { SH_64x64 = 0, SH_128x64 = 1, SH_128x128 = 2, SH_COUNT };
+enum Tunable { TU_MO1 = 0, TU_MO2, TU_CASIDA, TU_RHO, TU_SIGMA, TU_EXCHANGE, TU_COUNT };
+struct Tiles {
+  int shape[TU_COUNT] = {SH_128x64, SH_64x64, SH_128x128, SH_128x128, SH_64x64, SH_64x64};
+  // workgroups a K-split aims for when the output tiles alone are few
+  int64_t sigma_target = 4096, rho_target = 2048, exchange_target = 2048;
+};
+inline int shape_m(int s) { return s == SH_64x64 ? 64 : 128; }
+inline int shape_n(int s) { return s == SH_128x128 ? 128 : 64; }
+
 }  // namespace
 
 struct qsgw_ctx {
@@ -80,6 +92,7 @@ struct qsgw_ctx {
   int last_stage = -1;
   // cached residue pair-block table
   int64_t rowtab_nbf = -1, rowtab_n = 0;
+  Tiles tiles;
 };
 
 namespace {
@@ -193,26 +206,48 @@ inline int64_t splits_for(int64_t tiles, int64_t K, int64_t target = 2048) {
   return s < 1 ? 1 : s;
 }
 
-// qsGW matrix: 64 x 64 tiles of the nbf x nbf output, K = nbf * ns.
-inline SplitPlan sigma_split(int64_t nbf, int64_t ns) {
-  const int64_t t = (nbf + 63) / 64;
-  return split_plan(nbf * ns, splits_for(t * t, nbf * ns, 4096));
+inline int64_t tiles_of(int shape, int64_t M, int64_t N) {
+  return ((M + shape_m(shape) - 1) / shape_m(shape)) * ((N + shape_n(shape) - 1) / shape_n(shape));
 }
 
-// rho product: 128 x 128 tiles of the naux x ns output, K = ntr; split only
-// when the tiles alone leave the chip under-filled.
-inline SplitPlan rho_split(int64_t naux, int64_t ns, int64_t ntr, int64_t maxk) {
-  const int64_t tiles = ((naux + 127) / 128) * ((ns + 127) / 128);
-  int64_t want = tiles >= 2048 ? 1 : splits_for(tiles, ntr, 2048);
+// qsGW matrix: tiles of the nbf x nbf output, K = nbf * ns.
+inline SplitPlan sigma_split(const Tiles& tl, int64_t nbf, int64_t ns) {
+  const int64_t t = tiles_of(tl.shape[TU_SIGMA], nbf, nbf);
+  return split_plan(nbf * ns, splits_for(t, nbf * ns, tl.sigma_target));
+}
+
+// rho product: tiles of the naux x ns output, K = ntr; split only when the
+// tiles alone leave the chip under-filled.
+inline SplitPlan rho_split(const Tiles& tl, int64_t naux, int64_t ns, int64_t ntr, int64_t maxk) {
+  const int64_t tiles = tiles_of(tl.shape[TU_RHO], naux, ns);
+  int64_t want = tiles >= tl.rho_target ? 1 : splits_for(tiles, ntr, tl.rho_target);
   const int64_t need = (ntr + maxk - 1) / maxk;  // keep each split's K <= maxk
   if (want < need) want = need;
   return split_plan(ntr, want);
 }
 
-// MO exchange: upper 64 x 64 tiles, K = naux * nocc.
-inline SplitPlan exchange_split(int64_t nbf, int64_t naux, int64_t nocc) {
-  const int64_t t = (nbf + 63) / 64;
-  return split_plan(naux * nocc, splits_for(t * (t + 1) / 2, naux * nocc));
+// MO exchange: upper square tiles, K = naux * nocc.
+inline SplitPlan exchange_split(const Tiles& tl, int64_t nbf, int64_t naux, int64_t nocc) {
+  const int64_t t = (nbf + shape_m(tl.shape[TU_EXCHANGE]) - 1) / shape_m(tl.shape[TU_EXCHANGE]);
+  return split_plan(naux * nocc, splits_for(t * (t + 1) / 2, naux * nocc, tl.exchange_target));
+}
+
+// GEMM with the tile shape chosen at run time.
+template <class T, bool TRI, class OA, class OB, class EPI>
+int gemm_shape(qsgw_ctx* c, int shape, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N,
+               int64_t K, int64_t batch, SplitPlan sp = {0, 1}) {
+  switch (shape) {
+    case SH_64x64:
+      return gemm_t<T, 64, 64, TRI>(c, what, a, b, e, M, N, K, batch, sp);
+    case SH_128x128:
+      return gemm_t<T, 128, 128, TRI>(c, what, a, b, e, M, N, K, batch, sp);
+    default:
+      if constexpr (TRI) {
+        return fail(c, QSGW_ERR_INVALID_ARG, "%s: symmetric products take square tiles", what);
+      } else {
+        return gemm_t<T, 128, 64, false>(c, what, a, b, e, M, N, K, batch, sp);
+      }
+  }
 }
 
 int record(qsgw_ctx* c, size_t idx) {

@@ -19,7 +19,8 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
     Strided<false> B{C, 1, nbf, 0, nbf};
     EpiStore E{T, nbf, 0, 0, 1.0};
     SPAN_OPEN(sp, kKMo1);
-    CHECK((gemm_t<CT, 128, 64, false>(c, "mo_transform/1", A, B, E, naux * nbf, nbf, nbf, 1)));
+    CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_MO1], "mo_transform/1", A, B, E, naux * nbf,
+                                 nbf, nbf, 1)));
     SPAN_CLOSE(sp);
   }
   {
@@ -27,7 +28,8 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
     Strided<false> B{T, 1, nbf, nn, nbf};
     EpiStore E{B_mo, nbf, nn, 0, 1.0};
     SPAN_OPEN(sp, kKMo2);
-    CHECK((gemm_t<CT, 64, 64, true>(c, "mo_transform/2", A, B, E, nbf, nbf, nbf, naux)));
+    CHECK((gemm_shape<CT, true>(c, c->tiles.shape[TU_MO2], "mo_transform/2", A, B, E, nbf, nbf, nbf,
+                                naux)));
     SPAN_CLOSE(sp);
   }
   return QSGW_OK;
@@ -56,9 +58,11 @@ int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const 
   Strided<false> A{Bt, 1, ntr, 0, ntr};
   EpiCasida E{M, delta, ntr};
   if (prec == QSGW_PREC_FP32)
-    CHECK((gemm_t<float, 128, 128, true>(c, "rpa_build", A, A, E, ntr, ntr, naux, 1)));
+    CHECK((gemm_shape<float, true>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr, ntr,
+                                   naux, 1)));
   else
-    CHECK((gemm<128, 128, true>(c, "rpa_build", A, A, E, ntr, ntr, naux, 1)));
+    CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr, ntr,
+                                    naux, 1)));
   SPAN_CLOSE(sp);
   return QSGW_OK;
 }
@@ -87,19 +91,21 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     Strided<true> A{Bt, ntr, 1, 0, naux};
     Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
     const int64_t maxk = sizeof(CT) == sizeof(float) ? kFp32MaxK : ntr;
-    const SplitPlan spl = rho_split(naux, ns, ntr, maxk);
+    const SplitPlan spl = rho_split(c->tiles, naux, ns, ntr, maxk);
     SPAN_OPEN(sp, kKRho);
     if (spl.nz > 1) {
       double* part = nullptr;
       CHECK(ws_get(c, W_RHOPART, (size_t)(spl.nz * naux * ns), &part));
       EpiStore E{part, ns, 0, naux * ns, 1.0};
-      CHECK((gemm_t<CT, 128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1, spl)));
+      CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns, ntr,
+                                   1, spl)));
       hipLaunchKernelGGL(k_rho_reduce, dim3(blocks_for(naux * ns)), dim3(256), 0, c->stream, part,
                          spl.nz, naux, ns, Omega + s0, rho);
       CHECK(launch_check(c, "k_rho_reduce"));
     } else {
       EpiRho E{rho, Omega + s0, ns};
-      CHECK((gemm_t<CT, 128, 128, false>(c, "residues/rho", A, B, E, naux, ns, ntr, 1)));
+      CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns, ntr,
+                                   1)));
     }
     SPAN_CLOSE(sp);
   }
@@ -134,7 +140,7 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
 int stage_sigma_qs(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
                    const double* eps, const double* Omega, double eta, double* V, int accumulate,
                    Spans* spn = nullptr, const double* wh = nullptr) {
-  const SplitPlan sp = sigma_split(nbf, ns);
+  const SplitPlan sp = sigma_split(c->tiles, nbf, ns);
   if (nbf * ns >= (int64_t)1 << 32)
     return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^32");
   double* part = nullptr;
@@ -145,10 +151,12 @@ int stage_sigma_qs(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const dou
   if (wh) {
     // pole weights already applied by the residue epilogue
     Strided<true> A{wh, nbf * ns, 1, 0, nbf};
-    CHECK((gemm<64, 64, false>(c, "sigma_qs", A, B, E, nbf, nbf, nbf * ns, 1, sp)));
+    CHECK((gemm_shape<double, false>(c, c->tiles.shape[TU_SIGMA], "sigma_qs", A, B, E, nbf, nbf,
+                                     nbf * ns, 1, sp)));
   } else {
     PoleScaledResidueOp A{w, eps, Omega, nbf, nocc, ns, eta};
-    CHECK((gemm<64, 64, false>(c, "sigma_qs", A, B, E, nbf, nbf, nbf * ns, 1, sp)));
+    CHECK((gemm_shape<double, false>(c, c->tiles.shape[TU_SIGMA], "sigma_qs", A, B, E, nbf, nbf,
+                                     nbf * ns, 1, sp)));
   }
   SPAN_CLOSE(spn);
   SPAN_OPEN(spn, kKSigmaRed);
@@ -174,11 +182,12 @@ int stage_jk_mo(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const doub
   hipLaunchKernelGGL(k_hartree_mo, dim3(blocks_for(nn)), dim3(256), 0, c->stream, B_mo, cp, naux,
                      nn, *J);
   CHECK(launch_check(c, "k_hartree_mo"));
-  const SplitPlan sp = exchange_split(nbf, naux, nocc);
+  const SplitPlan sp = exchange_split(c->tiles, nbf, naux, nocc);
   CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nn), Kpart));
   OccRowsOp A{B_mo, nbf, nocc};
   EpiStore E{*Kpart, nbf, 0, nn, 1.0};
-  CHECK((gemm<64, 64, true>(c, "exchange_mo", A, A, E, nbf, nbf, naux * nocc, 1, sp)));
+  CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_EXCHANGE], "exchange_mo", A, A, E, nbf, nbf,
+                                  naux * nocc, 1, sp)));
   *nz = sp.nz;
   return QSGW_OK;
 }
@@ -441,7 +450,11 @@ int qsgw_hf_core(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const dou
   return launch_check(c, "k_symmetrize");
 }
 
-int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_options* o,
+}  // extern "C"
+
+namespace {
+
+int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_options* o,
                  qsgw_report* rep) {
   if (!c) return QSGW_ERR_INVALID_ARG;
   if (!p || !st || !o) return fail(c, QSGW_ERR_INVALID_ARG, "null argument struct");
@@ -496,9 +509,9 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   // The partial-sum slot is sized by its largest user before any pointer into it is taken.
   {
     double* part = nullptr;
-    int64_t nz = exchange_split(nbf, naux, nocc).nz;
+    int64_t nz = exchange_split(c->tiles, nbf, naux, nocc).nz;
     for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
-      const int64_t z = sigma_split(nbf, (ntr - s0) < sb ? (ntr - s0) : sb).nz;
+      const int64_t z = sigma_split(c->tiles, nbf, (ntr - s0) < sb ? (ntr - s0) : sb).nz;
       nz = z > nz ? z : nz;
     }
     CHECK(ws_get(c, W_PART, (size_t)(nz * nn), &part));
@@ -670,6 +683,113 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   c->last_stage = -1;
   if (rep) *rep = local;
   return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_options* o,
+                 qsgw_report* rep) {
+  const bool refine = o && (o->flags & QSGW_OPT_REFINE) && o->precision != QSGW_PREC_FP64;
+  if (!refine) return iterate_impl(c, p, st, o, rep);
+  // reduced-precision iterations, then one FP64 iteration from where they stopped
+  qsgw_report r1, r2;
+  memset(&r1, 0, sizeof(r1));
+  memset(&r2, 0, sizeof(r2));
+  const int rc1 = iterate_impl(c, p, st, o, &r1);
+  if (rc1 < 0) {
+    if (rep) *rep = r1;
+    return rc1;
+  }
+  qsgw_options o2 = *o;
+  o2.precision = QSGW_PREC_FP64;
+  o2.max_iter = 1;
+  o2.flags &= ~(int64_t)QSGW_OPT_REFINE;
+  double* diag = st->diag;  // diagonal outputs belong to the call's first iteration
+  st->diag = nullptr;
+  const int rc2 = iterate_impl(c, p, st, &o2, &r2);
+  st->diag = diag;
+  if (rep) {
+    qsgw_report r = r1;
+    if (r.iterations < QSGW_REPORT_MAX_ITERS) r.max_deps[r.iterations] = r2.max_deps[0];
+    r.iterations += r2.iterations;
+    r.converged = r2.converged;
+    for (int k = 0; k < 7; ++k) r.ms_stage[k] += r2.ms_stage[k];
+    for (int k = 0; k < 8; ++k) {
+      r.ms_kernel[k] += r2.ms_kernel[k];
+      r.kernel_launches[k] += r2.kernel_launches[k];
+    }
+    *rep = r;
+  }
+  return rc2;
+}
+
+int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  Tiles t;  // defaults
+  if (spec && *spec) {
+    static const char* names[TU_COUNT] = {"mo1", "mo2", "casida", "rho", "sigma", "exchange"};
+    static const bool square[TU_COUNT] = {false, true, true, false, false, true};
+    std::string all(spec);
+    size_t pos = 0;
+    while (pos <= all.size()) {
+      size_t end = all.find(',', pos);
+      if (end == std::string::npos) end = all.size();
+      const std::string item = all.substr(pos, end - pos);
+      pos = end + 1;
+      if (item.empty()) continue;
+      const size_t eq = item.find('=');
+      if (eq == std::string::npos) return fail(c, QSGW_ERR_INVALID_ARG, "tiles: no '=' in '%s'", item.c_str());
+      const std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+      bool done = false;
+      for (int k = 0; k < TU_COUNT && !done; ++k) {
+        if (key != names[k]) continue;
+        int sh = -1;
+        if (val == "64x64") sh = SH_64x64;
+        else if (val == "128x64") sh = SH_128x64;
+        else if (val == "128x128") sh = SH_128x128;
+        if (sh < 0 || (square[k] && sh == SH_128x64))
+          return fail(c, QSGW_ERR_INVALID_ARG, "tiles: shape '%s' not available for %s", val.c_str(),
+                      key.c_str());
+        t.shape[k] = sh;
+        done = true;
+      }
+      if (done) continue;
+      int64_t* target = key == "sigma_target" ? &t.sigma_target
+                        : key == "rho_target" ? &t.rho_target
+                        : key == "exchange_target" ? &t.exchange_target
+                                                    : nullptr;
+      if (!target) return fail(c, QSGW_ERR_INVALID_ARG, "tiles: unknown key '%s'", key.c_str());
+      char* e = nullptr;
+      const long long v = strtoll(val.c_str(), &e, 10);
+      if (!e || *e || v < 64 || v > (1 << 20))
+        return fail(c, QSGW_ERR_INVALID_ARG, "tiles: %s needs an integer in [64, 2^20]", key.c_str());
+      *target = v;
+    }
+  }
+  // work queued with the previous table may still run; the table only affects launches
+  c->tiles = t;
+  return QSGW_OK;
+}
+
+int qsgw_get_tiles(qsgw_ctx* c, char* buf, int64_t size) {
+  if (!c || !buf || size < 1) return QSGW_ERR_INVALID_ARG;
+  static const char* names[TU_COUNT] = {"mo1", "mo2", "casida", "rho", "sigma", "exchange"};
+  static const char* shapes[SH_COUNT] = {"64x64", "128x64", "128x128"};
+  std::string out;
+  for (int k = 0; k < TU_COUNT; ++k) {
+    out += names[k];
+    out += "=";
+    out += shapes[c->tiles.shape[k]];
+    out += ",";
+  }
+  out += "sigma_target=" + std::to_string(c->tiles.sigma_target);
+  out += ",rho_target=" + std::to_string(c->tiles.rho_target);
+  out += ",exchange_target=" + std::to_string(c->tiles.exchange_target);
+  if ((int64_t)out.size() + 1 > size) return fail(c, QSGW_ERR_INVALID_ARG, "buffer too small");
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return QSGW_OK;
 }
 
 }  // extern "C"

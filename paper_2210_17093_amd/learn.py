@@ -218,12 +218,11 @@ def run(n_train=1024, n_test=256, epochs=150, max_iter=MAX_ITER, log=print):
         err = float(np.max(np.abs(d.double().cpu().numpy() - true))) if true is not None else None
         accept = h[0] <= FALLBACK_HA
         warm = first_below(h)
-        if accept and warm is not None:
-            cost = 1 + warm
-        elif r["iters"] is not None:
-            cost = 2 + r["iters"]  # feature iteration + rejected iteration + plain
+        if accept:
+            cost = 1 + warm if warm is not None else None  # feature iteration + warm path
         else:
-            cost = None
+            # feature iteration + rejected iteration + the plain path
+            cost = 2 + r["iters"] if r["iters"] is not None else None
         rows.append(dict(nbf=m["nbf"], plain=r["iters"], warm=warm, accept=accept, cost=cost,
                          err=err))
     both = [x for x in rows if x["plain"] is not None and x["cost"] is not None]
@@ -232,6 +231,7 @@ def run(n_train=1024, n_test=256, epochs=150, max_iter=MAX_ITER, log=print):
     res["plain_mean_iterations"] = float(np.mean([x["plain"] for x in both])) if both else None
     res["warm_mean_iterations"] = float(np.mean([x["cost"] for x in both])) if both else None
     res["fallbacks"] = sum(not x["accept"] for x in rows)
+    res["warm_not_converged"] = sum(x["accept"] and x["warm"] is None for x in rows)
     errs = [x["err"] for x in rows if x["err"] is not None]
     res["prediction_max_err_meV_median"] = float(np.median(errs) * HARTREE_MEV) if errs else None
     res["prediction_within_10meV"] = int(sum(e <= FALLBACK_HA for e in errs))

@@ -35,6 +35,7 @@ SIGMA_DIAG_SELF = 2
 
 FOCK_FULL_JK = 0
 OPT_GRAPH = 1
+OPT_REFINE = 2
 REPORT_MAX_ITERS = 64
 MLP_NPARAMS = 18817
 MLP_NFEAT = 16
@@ -44,7 +45,7 @@ EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_err
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
            "qsgw_residues", "qsgw_sigma", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
-           "qsgw_mlp_train_step", "qsgw_warm_start")
+           "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles")
 
 
 class QsgwError(RuntimeError):
@@ -114,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_mlp_forward": ([P, P, I64, P, P], I),
         "qsgw_mlp_train_step": ([P, P, P, P, I64, D, I64, P, P, P, P], I),
         "qsgw_warm_start": ([P, I64, P, P, P, P, P], I),
+        "qsgw_set_tiles": ([P, ct.c_char_p], I),
+        "qsgw_get_tiles": ([P, ct.c_char_p, I64], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -173,6 +176,15 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    def set_tiles(self, spec: str | None):
+        """Tile table of the context (see qsgw_set_tiles); None restores defaults."""
+        self.check(lib().qsgw_set_tiles(self.handle, spec.encode() if spec else None))
+
+    def get_tiles(self) -> str:
+        buf = ct.create_string_buffer(512)
+        self.check(lib().qsgw_get_tiles(self.handle, buf, 512))
+        return buf.value.decode()
 
     def check(self, rc, allow=(OK,)):
         if rc in allow:
@@ -306,7 +318,7 @@ def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
 
 
 def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
-                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None):
+                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None, refine=False):
     """Runs qsGW iterations in place on (eps, C).  Returns (status, report dict, iteration)."""
     naux, nbf, _ = B_ao.shape
     prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
@@ -315,7 +327,7 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
                _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration,
                _ptr(diag, (nbf, 4), name="diag") if diag is not None else None)
     opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
-                  int(s_block), 0)
+                  int(s_block), OPT_REFINE if refine else 0)
     rep = Report()
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))

@@ -1,0 +1,157 @@
+"""Tile-shape autotuner for the products of one qsGW iteration.
+
+For a workload it times each tunable product (libqsgw's tile table, see
+qsgw_set_tiles) under every shape the product allows, and the K-split targets
+of the split products, by coordinate descent from the default table: one key
+at a time, every candidate value with the other keys at their best so far,
+the median of `reps` iterations of that product's own HIP-event time.  The
+fastest table per workload goes to tiles.json next to this file, which
+bench.py applies to its workload.
+
+    python -m paper_2210_17093_amd.tune cfg2 cfg4 [--reps 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import qsgw as q
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tiles.json")
+
+# key -> (candidate values, kernels whose time decides)
+CANDIDATES = {
+    "mo1": (["128x64", "64x64", "128x128"], ["mo_transform_1"]),
+    "mo2": (["64x64", "128x128"], ["mo_transform_2"]),
+    "casida": (["128x128", "64x64"], ["casida"]),
+    "rho": (["128x128", "128x64", "64x64"], ["residue_rho"]),
+    "rho_target": ([2048, 1024, 4096], ["residue_rho"]),
+    "sigma": (["64x64", "128x64", "128x128"], ["sigma_qs_gemm", "sigma_qs_reduce"]),
+    "sigma_target": ([4096, 2048, 8192], ["sigma_qs_gemm", "sigma_qs_reduce"]),
+    "exchange": (["64x64", "128x128"], ["fock"]),
+}
+DEFAULTS = {"mo1": "128x64", "mo2": "64x64", "casida": "128x128", "rho": "128x128",
+            "rho_target": 2048, "sigma": "64x64", "sigma_target": 4096, "exchange": "64x64"}
+
+
+def spec_of(table):
+    return ",".join(f"{k}={v}" for k, v in table.items())
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def single_timer(name):
+    """Per-kernel times of one plain iteration of a single-instance workload."""
+    from qsgw_inputs import CONFIGS, make_config
+    p = make_config(name)
+    eta = CONFIGS[name]["eta"]
+    dev = torch.device("cuda:0")
+    ctx = q.Context()
+    B = torch.from_numpy(p.B_ao).to(dev)
+    C0 = torch.from_numpy(p.C0.copy()).to(dev)
+    e0 = torch.from_numpy(p.eps0.copy()).to(dev)
+    h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
+    e, C = torch.empty_like(e0), torch.empty_like(C0)
+
+    def run(spec):
+        ctx.set_tiles(spec)
+        e.copy_(e0)
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        _, rep, _ = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1)
+        return rep["kernel_ms"]
+    return ctx, run
+
+
+def batched_timer(name):
+    """Per-kernel times of one eager batched iteration (the 256-molecule
+    workload of bench.py --config cfg4)."""
+    from qsgw_inputs import batch_shapes, make_problem
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    ctx = q.Context(stream)
+    mols = []
+    with torch.cuda.stream(stream):
+        for s in batch_shapes():
+            p = make_problem(s["nbf"], s["naux"], s["nocc"], s["rank"], s["decay"], s["seed"])
+            B = torch.from_numpy(p.B_ao).to(dev)
+            C0 = torch.from_numpy(p.C0.copy()).to(dev)
+            e0 = torch.from_numpy(p.eps0.copy()).to(dev)
+            mols.append(dict(B=B, C0=C0, e0=e0, nocc=p.nocc, h=q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)))
+    stream.synchronize()
+
+    def run(spec):
+        ctx.set_tiles(spec)
+        with torch.cuda.stream(stream):
+            runs = [dict(B_ao=m["B"], h=m["h"], nocc=m["nocc"], eps=m["e0"].clone(),
+                         C=m["C0"].clone()) for m in mols]
+        stream.synchronize()
+        with torch.cuda.stream(stream):
+            _, reps = q.qsgw_iterate_batched(ctx, runs, 1e-3, tol=0.0, max_iter=1,
+                                             precision=q.PREC_FP32)
+        stream.synchronize()
+        return reps[0]["kernel_ms"]
+    return ctx, run
+
+
+def tune(name, reps=3):
+    ctx, run = batched_timer(name) if name == "cfg4" else single_timer(name)
+    best = dict(DEFAULTS)
+    run(spec_of(best))  # warm-up
+    trials = []
+    for key, (values, kernels) in CANDIDATES.items():
+        scores = {}
+        for v in values:
+            table = dict(best)
+            table[key] = v
+            try:
+                ts = [sum(run(spec_of(table))[k] for k in kernels) for _ in range(reps)]
+            except q.QsgwError as err:
+                log(f"[tune] {name} {key}={v}: {err}")
+                continue
+            scores[v] = float(np.median(ts))
+            trials.append(dict(key=key, value=v, ms=scores[v]))
+            log(f"[tune] {name} {key}={v}: {scores[v]:.3f} ms")
+        best[key] = min(scores, key=scores.get)
+    kd = [run(spec_of(DEFAULTS)) for _ in range(reps)]
+    kb = [run(spec_of(best)) for _ in range(reps)]
+    default_ms = {k: float(np.median([x[k] for x in kd])) for k in kd[0]}
+    best_ms = {k: float(np.median([x[k] for x in kb])) for k in kb[0]}
+    ctx.close()
+    return dict(spec=spec_of(best), kernel_ms=best_ms, default_kernel_ms=default_ms,
+                trials=trials)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workloads", nargs="+", choices=("cfg1", "cfg2", "cfg4"))
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args()
+    table = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            table = json.load(f)
+    for name in args.workloads:
+        t0 = time.time()
+        res = tune(name, args.reps)
+        res["seconds"] = round(time.time() - t0, 1)
+        res["command"] = "python -m paper_2210_17093_amd.tune " + " ".join(sys.argv[1:])
+        table[name] = res
+        log(f"[tune] {name}: {res['spec']}")
+        with open(args.out, "w") as f:
+            json.dump(table, f, indent=1)
+    print(json.dumps({k: v["spec"] for k, v in table.items()}))
+
+
+if __name__ == "__main__":
+    main()

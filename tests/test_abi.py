@@ -41,7 +41,8 @@ def test_binding_matches_header():
     assert sorted(q.EXPORTS) == declared()
     for n in declared():
         py = n if n.startswith("qsgw_") else None
-        if n in ("qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error", "qsgw_last_stage_ms"):
+        if n in ("qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error", "qsgw_last_stage_ms",
+                 "qsgw_set_tiles", "qsgw_get_tiles"):
             continue  # wrapped by the Context class
         if n == "qsgw_sigma":
             assert hasattr(q, "qsgw_sigma_qs") and hasattr(q, "qsgw_sigma_diag")

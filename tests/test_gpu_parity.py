@@ -388,3 +388,41 @@ def test_fp32_iteration_qp_error(q, ctx, shape):
     log(f"  FP32 per-state QP error: max {err.max() * 27211.386:.4f} meV, "
         f"median {np.median(err) * 27211.386:.5f} meV")
     assert err.max() <= FP32_QP_TOL
+
+
+def test_fp32_refinement_pass():
+    """Reduced-precision iterations to convergence, then one FP64 iteration
+    (refinement pass): the per-state error against the FP64 fixed point stays
+    within 1 meV before and does not grow after the FP64 step."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2210_17093_amd.qsgw as q
+    from qsgw_inputs import make_problem
+    p = make_problem(21, 84, 4, 42, 0.99, 100001)
+    dev = torch.device("cuda:0")
+    B = torch.from_numpy(p.B_ao).to(dev)
+    C0 = torch.from_numpy(p.C0.copy()).to(dev)
+    e0 = torch.from_numpy(p.eps0.copy()).to(dev)
+    with q.Context() as ctx:
+        h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
+        out = {}
+        # the FP32 products leave rounding noise of ~1e-8 Ha in the energies,
+        # so the reduced-precision iterations stop at 1e-6 Ha
+        for name, prec, refine, tol in (("fp64", q.PREC_FP64, False, 1e-10),
+                                        ("fp32", q.PREC_FP32, False, 1e-6),
+                                        ("fp32+refine", q.PREC_FP32, True, 1e-6)):
+            e, C = e0.clone(), C0.clone()
+            Vc = torch.zeros((p.nbf, p.nbf), dtype=torch.float64, device=dev)
+            rc, rep, it = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, 1e-3, tol=tol, max_iter=80,
+                                         mix=0.5, Vc=Vc, precision=prec, refine=refine)
+            print(name, rc, rep["iterations"], rep["max_deps"][-3:], flush=True)
+            out[name] = (rc, rep, e.cpu().numpy())
+    assert out["fp64"][0] == q.OK
+    assert out["fp32"][0] == q.OK
+    before = np.max(np.abs(out["fp32"][2] - out["fp64"][2]))
+    after = np.max(np.abs(out["fp32+refine"][2] - out["fp64"][2]))
+    rep = out["fp32+refine"][1]
+    print(f"refinement: {before:.3e} -> {after:.3e} Ha after {rep['iterations']} iterations", flush=True)
+    assert rep["iterations"] == out["fp32"][1]["iterations"] + 1
+    assert before <= 1.0 / 27211.386
+    assert after <= before + 1e-9
