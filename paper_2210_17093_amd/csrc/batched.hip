@@ -45,7 +45,8 @@ struct Mol {
   int* flag;
 };
 
-enum Seg { S_NTR = 0, S_NAUXNTR, S_NN, S_NBM2, S_NBF2, S_NAUX, S_NBF, S_COUNT };
+enum Seg { S_NTR = 0, S_NAUXNTR, S_NN, S_NBM2, S_NBF2, S_NAUX, S_NBF, S_CHM, S_CHF, S_COUNT };
+constexpr int64_t kGerCols = 256;  // columns per Gershgorin workgroup
 
 __device__ __forceinline__ int64_t seg_find(const int64_t* pre, int64_t n, int64_t idx) {
   int64_t lo = 0, hi = n - 1;
@@ -85,20 +86,26 @@ __global__ void kb_gather_bia(const Mol* mols, const int64_t* pre, int64_t nmol,
   m.Bt[li] = m.Bmo[(P * m.nbf + i) * m.nbf + a] * m.sqd[t];
 }
 
-// One workgroup per molecule: padding diagonal = 1 + max_t sum_u |A[u][t]|
-// over the matrix's own n x n block (ld = nb).  A is symmetric, so column
-// sums are row sums; consecutive threads read consecutive columns.
-// which = 0 Casida, 1 Fock.
-__global__ void kb_gershgorin(const Mol* mols, int which) {
+// Padding diagonal = 1 + max_t sum_u |A[u][t]| over the matrix's own n x n
+// block (ld = nb), the Gershgorin bound of its spectrum.  A is symmetric, so
+// column sums are row sums: workgroup g of a molecule takes columns
+// [256 g, 256 g + 256), one per thread (consecutive threads read consecutive
+// addresses), and writes the largest sum to part[g]; kb_gershgorin_max then
+// takes the largest over the molecule's workgroups.  which = 0 Casida, 1 Fock.
+__global__ void kb_gershgorin(const Mol* mols, const int64_t* pre, int64_t nmol, int which,
+                              double* part) {
   __shared__ double red[4];
-  const Mol& m = mols[blockIdx.x];
+  const int64_t g = blockIdx.x;
+  const int64_t mi = seg_find(pre, nmol, g);
+  const Mol& m = mols[mi];
   const double* A = which == 0 ? m.M : m.F;
   const int64_t n = which == 0 ? m.ntr : m.nbf, nb = which == 0 ? m.nbM : m.nbF;
+  const int64_t t = (g - pre[mi]) * kGerCols + threadIdx.x;
   double best = 0.0;
-  for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+  if (t < n) {
     double s = 0.0;
     for (int64_t u = 0; u < n; ++u) s += fabs(A[u * nb + t]);
-    best = fmax(best, s);
+    best = s;
   }
   for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_down(best, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
@@ -106,8 +113,18 @@ __global__ void kb_gershgorin(const Mol* mols, int which) {
   if (threadIdx.x == 0) {
     double r = red[0];
     for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, red[k]);
-    m.pad[which] = 1.0 + r;
+    part[g] = r;
   }
+}
+
+__global__ void kb_gershgorin_max(const Mol* mols, const int64_t* pre, int64_t nmol, int64_t total,
+                                  int which, const double* part) {
+  const int64_t mi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mi >= nmol) return;
+  const int64_t g1 = mi + 1 < nmol ? pre[mi + 1] : total;
+  double r = 0.0;
+  for (int64_t g = pre[mi]; g < g1; ++g) r = fmax(r, part[g]);
+  mols[mi].pad[which] = 1.0 + r;
 }
 
 // Padding of the nb x nb storage outside the matrix's own n x n block.
@@ -285,6 +302,7 @@ struct Plan {
   int64_t* exc_nz = nullptr;   // device, per molecule
   std::vector<Bucket> bM, bF;
   double* deps = nullptr;      // device [nmol]
+  double* gpart = nullptr;     // device, Gershgorin partial maxima (one per workgroup)
   double mix = 1.0;
 };
 
@@ -398,7 +416,10 @@ int segment_a(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   CHECK((launch_shape<true, CT>(c, c->tiles.shape[TU_CASIDA], "batched casida", J.cas, J.n,
                                 J.cas_wg)));
   SPAN_CLOSE(sp);
-  hipLaunchKernelGGL(kb_gershgorin, dim3((unsigned)nmol), dim3(256), 0, c->stream, P.dmols, 0);
+  hipLaunchKernelGGL(kb_gershgorin, dim3((unsigned)P.total[S_CHM]), dim3(kGerCols), 0, c->stream,
+                     P.dmols, P.dpre[S_CHM], nmol, 0, P.gpart);
+  hipLaunchKernelGGL(kb_gershgorin_max, dim3(blocks_for(nmol)), dim3(256), 0, c->stream, P.dmols,
+                     P.dpre[S_CHM], nmol, P.total[S_CHM], 0, P.gpart);
   hipLaunchKernelGGL(kb_pad, dim3(blocks_for(P.total[S_NBM2])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NBM2], nmol, P.total[S_NBM2], 0);
   return launch_check(c, "batched segment A");
@@ -456,7 +477,10 @@ int segment_b2(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   hipLaunchKernelGGL(kb_reduce_nn, dim3(blocks_for(P.total[S_NN])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NN], nmol, P.total[S_NN], P.exc_nz, 1);
   SPAN_CLOSE(sp);
-  hipLaunchKernelGGL(kb_gershgorin, dim3((unsigned)nmol), dim3(256), 0, c->stream, P.dmols, 1);
+  hipLaunchKernelGGL(kb_gershgorin, dim3((unsigned)P.total[S_CHF]), dim3(kGerCols), 0, c->stream,
+                     P.dmols, P.dpre[S_CHF], nmol, 1, P.gpart);
+  hipLaunchKernelGGL(kb_gershgorin_max, dim3(blocks_for(nmol)), dim3(256), 0, c->stream, P.dmols,
+                     P.dpre[S_CHF], nmol, P.total[S_CHF], 1, P.gpart);
   hipLaunchKernelGGL(kb_pad, dim3(blocks_for(P.total[S_NBF2])), dim3(256), 0, c->stream, P.dmols,
                      P.dpre[S_NBF2], nmol, P.total[S_NBF2], 1);
   return launch_check(c, "batched segment B2");
@@ -473,15 +497,53 @@ int segment_c(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   return launch_check(c, "batched segment C");
 }
 
+int aux_streams(qsgw_ctx* c) {
+  if (c->aux_ready) return QSGW_OK;
+  for (int i = 0; i < qsgw_ctx::kAux; ++i) {
+    if (!c->aux[i]) HIP_TRY(c, hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
+    if (!c->join[i]) HIP_TRY(c, hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming));
+    if (!c->aux_blas[i]) {
+      if (rocblas_create_handle(&c->aux_blas[i]) != rocblas_status_success) {
+        c->aux_blas[i] = nullptr;
+        return fail(c, QSGW_ERR_SOLVER, "rocblas_create_handle failed");
+      }
+      if (rocblas_set_stream(c->aux_blas[i], c->aux[i]) != rocblas_status_success)
+        return fail(c, QSGW_ERR_SOLVER, "rocblas_set_stream failed");
+    }
+  }
+  if (!c->fork) HIP_TRY(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+  c->aux_ready = true;
+  return QSGW_OK;
+}
+
+// Strided-batched dsyevd per bucket; the buckets (largest first) go
+// round-robin over the context stream and the auxiliary streams, which fork
+// from and join back into the context stream.
 int eig_buckets(qsgw_ctx* c, std::vector<Bucket>& bs) {
-  for (auto& b : bs) {
+  CHECK(aux_streams(c));
+  std::vector<Bucket*> order;
+  for (auto& b : bs) order.push_back(&b);
+  std::sort(order.begin(), order.end(), [](const Bucket* a, const Bucket* b) {
+    return a->nb * a->nb * (int64_t)a->mols.size() > b->nb * b->nb * (int64_t)b->mols.size();
+  });
+  const int lanes = 1 + qsgw_ctx::kAux;
+  HIP_TRY(c, hipEventRecord(c->fork, c->stream));
+  for (int i = 0; i < qsgw_ctx::kAux; ++i) HIP_TRY(c, hipStreamWaitEvent(c->aux[i], c->fork, 0));
+  for (size_t j = 0; j < order.size(); ++j) {
+    Bucket& b = *order[j];
+    const int lane = (int)(j % lanes);
+    rocblas_handle h = lane == 0 ? c->blas : c->aux_blas[lane - 1];
     const rocblas_stride sA = (rocblas_stride)(b.nb * b.nb), sD = (rocblas_stride)b.nb;
     rocblas_status st = rocsolver_dsyevd_strided_batched(
-        c->blas, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)b.nb, b.A,
-        (rocblas_int)b.nb, sA, b.ev, sD, b.E, sD, (rocblas_int*)b.info, (rocblas_int)b.mols.size());
+        h, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)b.nb, b.A, (rocblas_int)b.nb,
+        sA, b.ev, sD, b.E, sD, (rocblas_int*)b.info, (rocblas_int)b.mols.size());
     if (st != rocblas_status_success)
       return fail(c, QSGW_ERR_SOLVER, "rocsolver_dsyevd_strided_batched status %d (n = %lld)",
                   (int)st, (long long)b.nb);
+  }
+  for (int i = 0; i < qsgw_ctx::kAux; ++i) {
+    HIP_TRY(c, hipEventRecord(c->join[i], c->aux[i]));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join[i], 0));
   }
   return QSGW_OK;
 }
@@ -566,6 +628,10 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   for (auto& kv : bucketM) nd += kv.second.size() * (kv.first * kv.first + 2 * kv.first);
   for (auto& kv : bucketF) nd += kv.second.size() * (kv.first * kv.first + 2 * kv.first);
   nd += nmol + 2 * nmol;  // deps, pads
+  int64_t nger = 0;        // Gershgorin workgroups, Casida and Fock
+  for (int64_t i = 0; i < nmol; ++i)
+    nger += (P.mols[i].ntr + kGerCols - 1) / kGerCols + (P.mols[i].nbf + kGerCols - 1) / kGerCols;
+  nd += nger;
 
   double* D = nullptr;
   int32_t* I = nullptr;
@@ -580,6 +646,7 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   int32_t* icur = I;
   P.deps = take(nmol);
   double* pads = take(2 * nmol);
+  P.gpart = take(nger);
   int* flags = reinterpret_cast<int*>(icur);
   icur += nmol;
   for (int64_t i = 0; i < nmol; ++i) {
@@ -646,7 +713,8 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
       const Mol& m = P.mols[i];
       pre[s * nmol + i] = acc;
       const int64_t cnt[S_COUNT] = {m.ntr, m.naux * m.ntr, m.nn, m.nbM * m.nbM, m.nbF * m.nbF,
-                                    m.naux, m.nbf};
+                                    m.naux, m.nbf, (m.ntr + kGerCols - 1) / kGerCols,
+                                    (m.nbf + kGerCols - 1) / kGerCols};
       acc += cnt[s];
     }
     P.total[s] = acc;

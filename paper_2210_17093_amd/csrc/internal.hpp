@@ -93,6 +93,14 @@ struct qsgw_ctx {
   // cached residue pair-block table
   int64_t rowtab_nbf = -1, rowtab_n = 0;
   Tiles tiles;
+  // auxiliary streams (default priority) with their own rocBLAS handles, so
+  // the bucketed eigensolves of the batched iteration overlap; created on
+  // first use
+  static constexpr int kAux = 3;
+  hipStream_t aux[kAux] = {};
+  rocblas_handle aux_blas[kAux] = {};
+  hipEvent_t fork = nullptr, join[kAux] = {};
+  bool aux_ready = false;
 };
 
 namespace {

@@ -282,6 +282,13 @@ int qsgw_ctx_create(qsgw_ctx** out, void* hip_stream) {
 int qsgw_ctx_destroy(qsgw_ctx* c) {
   if (!c) return QSGW_OK;
   (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < qsgw_ctx::kAux; ++i) {
+    if (c->aux[i]) (void)hipStreamSynchronize(c->aux[i]);
+    if (c->aux_blas[i]) rocblas_destroy_handle(c->aux_blas[i]);
+    if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
+    if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
   for (auto& b : c->ws)
     if (b.p) (void)hipFree(b.p);
   for (auto e : c->events) (void)hipEventDestroy(e);
