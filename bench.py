@@ -49,10 +49,12 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of a kernel at the cfg2 workload, from the rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes scaled by the plain-copy calibration
-# (profiles/residue_w_cfg2_hbm_counters.md).  Only valid for the kernel build
+# (profiles/residue_w_cfg2_hbm_counters.md, residue_w_cfg2_fp32_hbm_counters.md).
+# Only valid for the kernel build
 # the counters were taken on: set an entry to None whenever that kernel changes.
 MEASURED_TRAFFIC_BYTES = {
     ("cfg2", "fp64", "residue_w"): 49.83e9,
+    ("cfg2", "fp32", "residue_w"): 53.71e9,
 }
 
 
@@ -312,7 +314,8 @@ def main():
                     help="for rocprofv3 --pmc passes only: run the hot-path entry points once "
                          "each (MO transform, Casida build, residues with the pole-weighted copy, "
                          "qsGW matrix) with Z = I and Omega = Delta in place of the eigensolve, "
-                         "which is not run under counter collection; prints no timing")
+                         "which is not run under counter collection, with the benchmark's tile "
+                         "table and --precision (fp64 unless fp32); prints no timing")
     ap.add_argument("--train-molecules", type=int, default=1024,
                     help="cfg5: training molecules (the full protocol names 20,000)")
     ap.add_argument("--test-molecules", type=int, default=256,
@@ -345,14 +348,16 @@ def main():
         B = torch.from_numpy(p.B_ao).to(dev)
         C0 = torch.from_numpy(p.C0).to(dev)
         e0 = torch.from_numpy(p.eps0).to(dev)
+        prec = q.PREC_FP32 if args.precision == "fp32" else q.PREC_FP64
         with q.Context() as ctx:
-            B_mo = q.qsgw_mo_transform(ctx, B, C0)
-            M, sq = q.qsgw_rpa_build(ctx, B_mo, e0, p.nocc)
+            ctx.set_tiles(tuned_tiles(args.config))
+            B_mo = q.qsgw_mo_transform(ctx, B, C0, precision=prec)
+            M, sq = q.qsgw_rpa_build(ctx, B_mo, e0, p.nocc, precision=prec)
             # an orthogonal eigenvector matrix and positive energies of the right shape
             Z = torch.eye(p.ntr, dtype=torch.float64, device=dev)
             Om = (sq * sq).contiguous()
             w, wh = q.qsgw_residues(ctx, B_mo, sq, Z, Om, p.nocc, weighted=True, eps=e0,
-                                    eta=cfg["eta"])
+                                    eta=cfg["eta"], precision=prec)
             q.qsgw_sigma_qs(ctx, w, e0, Om, p.nocc, cfg["eta"], wh=wh)
             torch.cuda.synchronize()
         print(json.dumps({"counter_probe": args.config}), flush=True)
