@@ -207,6 +207,9 @@ typedef struct {
   int fock_mode;    /* QSGW_FOCK_FULL_JK */
   int64_t s_block;  /* excitations per streamed residue block; 0 = automatic */
   int64_t flags;    /* QSGW_OPT_* bits */
+  double near_pole; /* QSGW_PREC_FP32, qsgw_iterate: terms of the qsGW product (Eq. 19) with
+                       |eps_m - eps_k +- Omega_s| below this (Ha) are summed in FP64, the rest on
+                       FP32 matrix cores; 0 = 0.05 Ha */
 } qsgw_options;
 
 /* qsgw_options.flags, qsgw_iterate_batched only: run the kernel segments

@@ -57,6 +57,8 @@ enum Slot {
   W_MLP_F32,     // warm-start network: activations, gradients
   W_MLP_F64,     // warm-start network: partial sums, squared errors
   W_MLP_PERM,    // warm start: state permutation
+  W_NEAR,        // FP32 qsGW product: near-pole ranges, offsets  [3 ntiles nbf + 2 ntiles]
+  W_NEARTAB,     // FP32 qsGW product: compacted (k, s) columns   [2][columns] int32
   W_NSLOTS
 };
 
@@ -222,6 +224,27 @@ inline int64_t tiles_of(int shape, int64_t M, int64_t N) {
 inline SplitPlan sigma_split(const Tiles& tl, int64_t nbf, int64_t ns) {
   const int64_t t = tiles_of(tl.shape[TU_SIGMA], nbf, nbf);
   return split_plan(nbf * ns, splits_for(t, nbf * ns, tl.sigma_target));
+}
+
+// FP32 qsGW product: far-from-pole part on FP32 matrix cores (each split's
+// K <= kFp32MaxK), near-pole part in FP64 over compacted columns, one 64-row
+// tile of m at a time, in `near` extra partial slices.
+constexpr double kNearPoleDefault = 0.05;  // Ha
+inline SplitPlan sigma_split32(const Tiles& tl, int64_t nbf, int64_t ns) {
+  const int64_t K = nbf * ns;
+  const int64_t t = tiles_of(tl.shape[TU_SIGMA], nbf, nbf);
+  int64_t want = splits_for(t, K, tl.sigma_target);
+  const int64_t need = (K + kFp32MaxK - 1) / kFp32MaxK;
+  if (want < need) want = need;
+  return split_plan(K, want);
+}
+inline int64_t near_slices_max(int64_t nbf) {
+  const int64_t t = (nbf + 63) / 64;
+  const int64_t z = (2048 + t * t - 1) / (t * t);
+  return z < 1 ? 1 : z;
+}
+inline int64_t sigma_slices(const Tiles& tl, int64_t nbf, int64_t ns, bool fp32) {
+  return fp32 ? sigma_split32(tl, nbf, ns).nz + near_slices_max(nbf) : sigma_split(tl, nbf, ns).nz;
 }
 
 // rho product: tiles of the naux x ns output, K = ntr; split only when the

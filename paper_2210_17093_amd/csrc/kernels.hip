@@ -277,4 +277,83 @@ __global__ void k_exchange_diag(const double* bmo, int64_t naux, int64_t nbf, in
   if (threadIdx.x == 0) out[m * ld] = v[0];
 }
 
+namespace {
+// first index s in [0, n) with a[s] > x (a ascending), n if none
+__device__ __forceinline__ int64_t first_above(const double* a, int64_t n, double x) {
+  int64_t l = 0, h = n;
+  while (l < h) {
+    const int64_t mid = (l + h) >> 1;
+    if (a[mid] > x) h = mid; else l = mid + 1;
+  }
+  return l;
+}
+// first index s with a[s] >= x
+__device__ __forceinline__ int64_t first_at_least(const double* a, int64_t n, double x) {
+  int64_t l = 0, h = n;
+  while (l < h) {
+    const int64_t mid = (l + h) >> 1;
+    if (a[mid] >= x) h = mid; else l = mid + 1;
+  }
+  return l;
+}
+}  // namespace
+
+__global__ void k_near_ranges(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                              int64_t ns, double thr, int64_t ntiles, int64_t* lo, int64_t* cnt) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ntiles * nbf) return;
+  const int64_t t = idx / nbf, k = idx - t * nbf;
+  const int64_t m0 = t * 64, m1 = (m0 + 64 < nbf ? m0 + 64 : nbf) - 1;
+  const double elo = eps[m0], ehi = eps[m1], ek = eps[k];
+  // occupied k: |eps_m - eps_k + Omega| < thr  <=>  Omega in (eps_k - eps_m - thr, eps_k - eps_m + thr)
+  // empty k:    |eps_m - eps_k - Omega| < thr  <=>  Omega in (eps_m - eps_k - thr, eps_m - eps_k + thr)
+  double a, b;
+  if (k < nocc) {
+    a = ek - ehi - thr;
+    b = ek - elo + thr;
+  } else {
+    a = elo - ek - thr;
+    b = ehi - ek + thr;
+  }
+  const double slack = 1e-12 * (1.0 + fabs(a) + fabs(b));
+  const int64_t s0 = first_at_least(Omega, ns, a - slack);
+  const int64_t s1 = first_above(Omega, ns, b + slack);
+  lo[idx] = s0;
+  cnt[idx] = s1 > s0 ? s1 - s0 : 0;
+}
+
+__global__ void k_near_offsets(const int64_t* cnt, int64_t nbf, int64_t ntiles, int64_t* off,
+                               int64_t* total, int64_t* base) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t start = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    int64_t acc = 0;
+    for (int64_t k = 0; k < nbf; ++k) {
+      off[t * nbf + k] = acc;
+      acc += cnt[t * nbf + k];
+    }
+    total[t] = acc;
+    base[t] = start;
+    start += acc;
+  }
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_near_fill(const int64_t* lo, const int64_t* cnt, const int64_t* off,
+                            const int64_t* base, int64_t nbf, int64_t ntiles, int32_t* ktab,
+                            int32_t* stab) {
+  const int64_t idx = blockIdx.x;  // one workgroup per (tile, k)
+  if (idx >= ntiles * nbf) return;
+  const int64_t t = idx / nbf, k = idx - t * nbf;
+  const int64_t n = cnt[idx], s0 = lo[idx], o = base[t] + off[idx];
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    ktab[o + j] = (int32_t)k;
+    stab[o + j] = (int32_t)(s0 + j);
+  }
+}
+
 }  // namespace qsgw

@@ -90,23 +90,69 @@ struct EpiPairResidue {
   const double* Omega;    // the block's excitations
   int64_t nbf, nocc, ns;
   double eta;
-  __device__ __forceinline__ double weight(int64_t a, int64_t b, double om) const {
-    const double x = eps[a] - eps[b] + (b < nocc ? om : -om);
-    return x / (x * x + eta * eta);
+  // FP32 variant of the qsGW product (both null otherwise): wh32 = the
+  // pole-weighted copy with every near-pole term (|x| < thr) set to zero,
+  // w32 = w rounded to FP32.  The near-pole terms are summed in FP64 apart.
+  float* wh32 = nullptr;
+  float* w32 = nullptr;
+  double thr = 0.0;
+  __device__ __forceinline__ double xval(int64_t a, int64_t b, double om) const {
+    return eps[a] - eps[b] + (b < nocc ? om : -om);
+  }
+  __device__ __forceinline__ void store(int64_t a, int64_t b, int64_t s, double v) const {
+    const int64_t i = (a * nbf + b) * ns + s;
+    w[i] = v;
+    if (wh || wh32) {
+      const double x = xval(a, b, Omega[s]);
+      const double g = x / (x * x + eta * eta);
+      if (wh) wh[i] = v * g;
+      if (wh32) {
+        wh32[i] = fabs(x) >= thr ? (float)(v * g) : 0.0f;
+        w32[i] = (float)v;
+      }
+    }
   }
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
                                              bool) const {
     int64_t m, k;
     pair_of<8, 16>(blocks, r >> 7, (int)(r & 127), m, k);
     if (m >= nbf || k >= nbf || m > k) return;
-    const int64_t r1 = m * nbf + k, r2 = k * nbf + m;
-    w[r1 * ns + s] = v;
-    if (m != k) w[r2 * ns + s] = v;
-    if (wh) {
-      const double om = Omega[s];
-      wh[r1 * ns + s] = v * weight(m, k, om);
-      if (m != k) wh[r2 * ns + s] = v * weight(k, m, om);
-    }
+    store(m, k, s, v);
+    if (m != k) store(k, m, s, v);
+  }
+};
+
+// Near-pole terms of the qsGW product for one 64-row tile of m, over a
+// compacted list of (k, s) columns (ktab, stab) that holds every pair with
+// some m of the tile within thr of a pole:
+//   A(r, j) = w[m][k][s] x / (x^2 + eta^2) if |x| < thr else 0,  m = m0 + r,
+//   B(n, j) = w[n][k][s],   (k, s) = (ktab[j], stab[j]).
+struct NearRowsOp {
+  static constexpr bool kContig = true;
+  const double* w;
+  const double* eps;
+  const double* Omega;
+  const int32_t* ktab;
+  const int32_t* stab;
+  int64_t m0, rows, nbf, nocc, ns;
+  double eta, thr;
+  __device__ __forceinline__ double get(int64_t, int64_t r, int64_t j) const {
+    if (r >= rows) return 0.0;
+    const int64_t m = m0 + r, k = ktab[j], s = stab[j];
+    const double x = eps[m] - eps[k] + (k < nocc ? Omega[s] : -Omega[s]);
+    if (!(fabs(x) < thr)) return 0.0;
+    return w[(m * nbf + k) * ns + s] * (x / (x * x + eta * eta));
+  }
+};
+struct NearColsOp {
+  static constexpr bool kContig = true;
+  const double* w;
+  const int32_t* ktab;
+  const int32_t* stab;
+  int64_t nbf, ns;
+  __device__ __forceinline__ double get(int64_t, int64_t n, int64_t j) const {
+    if (n >= nbf) return 0.0;
+    return w[(n * nbf + ktab[j]) * ns + stab[j]];
   }
 };
 
@@ -188,6 +234,28 @@ __device__ __forceinline__ double exchange_diag_partial(const double* bmo, int64
   }
   return acc;
 }
+
+// p[i] = v for i < n (a fill that graph capture records as a kernel node).
+__global__ void k_fill(double* p, int64_t n, double v);
+
+// Near-pole column ranges of the FP32 qsGW product.  For row tile t (rows
+// [64 t, 64 t + 64) of m, energies ascending) and state k, the excitations s
+// with |eps_m - eps_k +- Omega_s| < thr for some m of the tile form one
+// contiguous range (Omega ascending): lo[t][k], cnt[t][k].  The range is
+// widened by a relative 1e-12 so no near-pole term is missed; extra columns
+// contribute zeros.
+__global__ void k_near_ranges(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                              int64_t ns, double thr, int64_t ntiles, int64_t* lo, int64_t* cnt);
+
+// Offsets of the (k, s) lists in order of k within each tile, each tile's
+// total and the tiles' starts base[t] in one table (one thread, in order).
+__global__ void k_near_offsets(const int64_t* cnt, int64_t nbf, int64_t ntiles, int64_t* off,
+                               int64_t* total, int64_t* base);
+
+// Fill the compacted (k, s) lists: tile t's list starts at base[t].
+__global__ void k_near_fill(const int64_t* lo, const int64_t* cnt, const int64_t* off,
+                            const int64_t* base, int64_t nbf, int64_t ntiles, int32_t* ktab,
+                            int32_t* stab);
 
 __global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, double* delta,
                               double* sqrt_delta, int* bad);

@@ -86,7 +86,7 @@ template <class CT>
 int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
                      const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
-                     double eta) {
+                     double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0) {
   {
     Strided<true> A{Bt, ntr, 1, 0, naux};
     Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
@@ -117,6 +117,9 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     PairRows<8, 16> A{B_mo, nn, 0, nbf, blocks};
     Strided<false> B{rho, 1, ns, 0, ns};
     EpiPairResidue E{w, wh, blocks, eps, Omega + s0, nbf, nocc, ns, eta};
+    E.wh32 = wh32;
+    E.w32 = w32;
+    E.thr = thr;
     SPAN_OPEN(sp, kKW);
     CHECK((gemm_t<CT, 128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
     SPAN_CLOSE(sp);
@@ -128,12 +131,87 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
                    double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
                    const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
-                   int prec = QSGW_PREC_FP64) {
+                   int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
+                   double thr = 0.0) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                   eps, nocc, eta);
+                                   eps, nocc, eta, wh32, w32, thr);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta);
+}
+
+// FP32 variant of Eq. (19) for one excitation block.  G = G_far + G_near:
+// G_far = Wh32 W32^T over every term with |x| >= thr (FP32 matrix cores,
+// FP64 split-K reduction); G_near over the near-pole terms (|x| < thr) in
+// FP64, for each 64-row tile of m over the compacted (k, s) columns in
+// which some m of the tile is near a pole.  V (+)= 1/2 (G + G^T).
+int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
+                     const float* wh32, const float* w32, const double* eps, const double* Omega,
+                     double eta, double thr, double* V, int accumulate, Spans* spn) {
+  const int64_t nn = nbf * nbf, K = nbf * ns, nt = (nbf + 63) / 64;
+  if (K >= (int64_t)1 << 31) return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^31");
+  const SplitPlan spf = sigma_split32(c->tiles, nbf, ns);
+  int64_t* nearws = nullptr;
+  CHECK(ws_get(c, W_NEAR, (size_t)(3 * nt * nbf + 2 * nt), &nearws));
+  int64_t *lo = nearws, *cnt = lo + nt * nbf, *off = cnt + nt * nbf, *tot = off + nt * nbf,
+          *base = tot + nt;
+  SPAN_OPEN(spn, kKSigma);
+  hipLaunchKernelGGL(k_near_ranges, dim3(blocks_for(nt * nbf)), dim3(256), 0, c->stream, eps, Omega,
+                     nbf, nocc, ns, thr, nt, lo, cnt);
+  hipLaunchKernelGGL(k_near_offsets, dim3(1), dim3(64), 0, c->stream, cnt, nbf, nt, off, tot, base);
+  CHECK(launch_check(c, "near-pole ranges"));
+  std::vector<int64_t> tot_h(nt), base_h(nt);
+  HIP_TRY(c, hipMemcpyAsync(tot_h.data(), tot, nt * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(base_h.data(), base, nt * sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int64_t lmax = 0, ltot = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    lmax = tot_h[t] > lmax ? tot_h[t] : lmax;
+    ltot += tot_h[t];
+  }
+  int32_t* tab = nullptr;
+  CHECK(ws_get(c, W_NEARTAB, (size_t)(2 * ltot + 2), &tab));
+  int32_t *ktab = tab, *stab = tab + ltot + 1;
+  if (ltot > 0) {
+    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)(nt * nbf)), dim3(256), 0, c->stream, lo, cnt,
+                       off, base, nbf, nt, ktab, stab);
+    CHECK(launch_check(c, "k_near_fill"));
+  }
+  int64_t zn = near_slices_max(nbf);
+  const int64_t zcap = (lmax + 255) / 256;
+  if (zn > zcap) zn = zcap < 1 ? 1 : zcap;
+  double* part = nullptr;
+  CHECK(ws_get(c, W_PART, (size_t)((spf.nz + zn) * nn), &part));
+  double* npart = part + spf.nz * nn;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(zn * nn)), dim3(256), 0, c->stream, npart, zn * nn, 0.0);
+  CHECK(launch_check(c, "k_fill"));
+  {
+    Strided<true, float> A{wh32, K, 1, 0, nbf};
+    Strided<true, float> B{w32, K, 1, 0, nbf};
+    EpiStore E{part, nbf, 0, nn, 1.0};
+    CHECK((gemm_shape<float, false>(c, c->tiles.shape[TU_SIGMA], "sigma_qs/far", A, B, E, nbf, nbf,
+                                    K, 1, spf)));
+  }
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t L = tot_h[t];
+    if (L == 0) continue;
+    const int64_t m0 = t * 64, rows = (m0 + 64 < nbf ? 64 : nbf - m0);
+    int64_t kchunk = (L + zn - 1) / zn;
+    kchunk = ((kchunk + 15) / 16) * 16;
+    NearRowsOp A{w, eps, Omega, ktab + base_h[t], stab + base_h[t], m0, rows, nbf, nocc, ns, eta, thr};
+    NearColsOp B{w, ktab + base_h[t], stab + base_h[t], nbf, ns};
+    EpiStore E{npart + m0 * nbf, nbf, 0, nn, 1.0};
+    CHECK((gemm_t<double, 64, 64, false>(c, "sigma_qs/near", A, B, E, rows, nbf, L, 1,
+                                         SplitPlan{kchunk, zn})));
+  }
+  SPAN_CLOSE(spn);
+  SPAN_OPEN(spn, kKSigmaRed);
+  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nn)), dim3(256), 0, c->stream, part,
+                     spf.nz + zn, nbf, V, accumulate);
+  CHECK(launch_check(c, "k_reduce_sym"));
+  SPAN_CLOSE(spn);
+  return QSGW_OK;
 }
 
 // Eq. (19) contribution of one excitation block: V (+)= 1/2 (G + G^T).
@@ -479,6 +557,10 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   if (o->fock_mode != QSGW_FOCK_FULL_JK)
     return fail(c, QSGW_ERR_UNSUPPORTED, "fock_mode %d is not available", o->fock_mode);
   if (o->s_block < 0) return fail(c, QSGW_ERR_INVALID_ARG, "need s_block >= 0");
+  if (!(o->near_pole >= 0.0) || !isfinite(o->near_pole))
+    return fail(c, QSGW_ERR_INVALID_ARG, "need a finite near_pole >= 0");
+  const bool fp32 = o->precision == QSGW_PREC_FP32;
+  const double near = o->near_pole > 0.0 ? o->near_pole : kNearPoleDefault;
 
   const int64_t nv = nbf - nocc, ntr = nocc * nv, nn = nbf * nbf;
   int64_t sb = o->s_block;
@@ -518,7 +600,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     double* part = nullptr;
     int64_t nz = exchange_split(c->tiles, nbf, naux, nocc).nz;
     for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
-      const int64_t z = sigma_split(c->tiles, nbf, (ntr - s0) < sb ? (ntr - s0) : sb).nz;
+      const int64_t z = sigma_slices(c->tiles, nbf, (ntr - s0) < sb ? (ntr - s0) : sb, fp32);
       nz = z > nz ? z : nz;
     }
     CHECK(ws_get(c, W_PART, (size_t)(nz * nn), &part));
@@ -590,12 +672,24 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
       const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
       CHECK(sp.open(kStageRes));
-      CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps, nocc,
-                           o->eta, o->precision));
-      CHECK(sp.close());
-      CHECK(sp.open(kStageSigma));
-      CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
-                           wh));
+      if (fp32) {
+        // FP32 products: the pole-weighted copy and w in FP32 share the wh buffer
+        float* wh32 = reinterpret_cast<float*>(wh);
+        float* w32 = wh32 + nn * ns;
+        CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, nullptr,
+                             eps, nocc, o->eta, o->precision, wh32, w32, near));
+        CHECK(sp.close());
+        CHECK(sp.open(kStageSigma));
+        CHECK(stage_sigma_qs32(c, nbf, nocc, ns, w, wh32, w32, eps, Omega + s0, o->eta, near, V,
+                               s0 > 0 ? 1 : 0, &sp));
+      } else {
+        CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps,
+                             nocc, o->eta, o->precision));
+        CHECK(sp.close());
+        CHECK(sp.open(kStageSigma));
+        CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
+                             wh));
+      }
       CHECK(sp.close());
       if (it == 0 && st->diag) {
         hipLaunchKernelGGL(k_sigma_diag_self, dim3((unsigned)nbf), dim3(256), 0, c->stream, w, eps,

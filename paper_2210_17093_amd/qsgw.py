@@ -67,7 +67,7 @@ class State(ct.Structure):
 class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("eta", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int64), ("mix", ct.c_double), ("fock_mode", ct.c_int),
-                ("s_block", ct.c_int64), ("flags", ct.c_int64)]
+                ("s_block", ct.c_int64), ("flags", ct.c_int64), ("near_pole", ct.c_double)]
 
 
 KERNELS = ("mo_transform_1", "mo_transform_2", "casida", "residue_rho", "residue_w",
@@ -318,7 +318,8 @@ def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
 
 
 def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
-                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None, refine=False):
+                 Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None, refine=False,
+                 near_pole=0.0):
     """Runs qsGW iterations in place on (eps, C).  Returns (status, report dict, iteration)."""
     naux, nbf, _ = B_ao.shape
     prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
@@ -327,7 +328,7 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
                _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration,
                _ptr(diag, (nbf, 4), name="diag") if diag is not None else None)
     opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
-                  int(s_block), OPT_REFINE if refine else 0)
+                  int(s_block), OPT_REFINE if refine else 0, float(near_pole))
     rep = Report()
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))

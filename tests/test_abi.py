@@ -70,5 +70,5 @@ def test_struct_layouts_match_header():
     import paper_2210_17093_amd.qsgw as q
     assert ctypes.sizeof(q.Problem) == 5 * 8
     assert ctypes.sizeof(q.State) == 5 * 8
-    assert ctypes.sizeof(q.Options) == 8 * 8
+    assert ctypes.sizeof(q.Options) == 9 * 8
     assert ctypes.sizeof(q.Report) == 8 + 8 + 64 * 8 + 7 * 8 + 8 + 3 * 8 * 8

@@ -373,17 +373,21 @@ def test_fp32_products(q, ctx, shape):
     np.testing.assert_array_equal(Mh, Mh.T)
 
 
+@pytest.mark.parametrize("near_pole,s_block", [(0.0, 0), (1e-9, 0), (1e6, 0), (0.05, 40)])
 @pytest.mark.parametrize("shape", [(24, 96, 5), (70, 200, 11)])
-def test_fp32_iteration_qp_error(q, ctx, shape):
-    """One iteration in FP32 against the FP64 oracle: per-state QP error <= 1 meV."""
-    log("fp32 iteration", shape)
+def test_fp32_iteration_qp_error(q, ctx, shape, near_pole, s_block):
+    """One iteration in FP32 against the FP64 oracle: per-state QP error <= 1 meV,
+    with the default near-pole threshold (0.05 Ha), with every qsGW term on
+    FP32 matrix cores (1e-9), with every term in the FP64 near-pole part (1e6),
+    and with streamed excitation blocks."""
+    log("fp32 iteration", shape, near_pole, s_block)
     p = make_config("cfg1") if shape == (24, 96, 5) else problem(*shape)
     eta = 1e-3
     h_ref = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
     st = O.qsgw_step(p.B_ao, h_ref, p.C0, p.eps0, p.nocc, eta)
     dB, h, dC, de = _gpu_start(q, ctx, p)
     rc, rep, it = q.qsgw_iterate(ctx, dB, h, p.nocc, de, dC, eta, tol=0.0, max_iter=1,
-                                 precision=q.PREC_FP32)
+                                 precision=q.PREC_FP32, near_pole=near_pole, s_block=s_block)
     err = np.abs(host(de) - st["eps"])
     log(f"  FP32 per-state QP error: max {err.max() * 27211.386:.4f} meV, "
         f"median {np.median(err) * 27211.386:.5f} meV")
