@@ -92,12 +92,14 @@ struct is_strided_op<OP, decltype((void)OP::kStrided, void())> {
 // m = PM mb + i / PK, k = PK kb + i % PK, i = 0..PM*PK-1.  Element (row, kk)
 // sits at p[b*sb + kk*sk + m*N + k].  Only blocks holding some m <= k are
 // listed, so a symmetric product in (m, k) runs about half the pair space.
-template <int PM, int PK>
+// Storage type S: double, or float for a rounded copy.
+template <int PM, int PK, class S = double>
 struct PairRows {
   static constexpr bool kContig = false;
   static constexpr bool kPairRows = true;
   static constexpr int kPM = PM, kPK = PK;
-  const double* p;
+  typedef S storage_t;
+  const S* p;
   int64_t sk, sb;
   int64_t n;              // N, the range of m and k
   const int32_t* blocks;  // one entry per row tile
@@ -110,6 +112,17 @@ struct is_pair_rows_op {
 template <class OP>
 struct is_pair_rows_op<OP, decltype((void)OP::kPairRows, void())> {
   static constexpr bool value = OP::kPairRows;
+};
+
+// Register type of an operand's prefetched elements: its storage type for
+// strided and pair-row operands (float copies stay float), double otherwise.
+template <class OP, class = void>
+struct reg_type {
+  typedef double type;
+};
+template <class OP>
+struct reg_type<OP, decltype((void)sizeof(typename OP::storage_t), void())> {
+  typedef typename OP::storage_t type;
 };
 
 // Pair (m, k) of row i of pair-row tile t (blocks as in PairRows).
@@ -126,9 +139,9 @@ __device__ __forceinline__ void pair_of(const int32_t* blocks, int64_t t, int i,
 //   k-contiguous operand:  r = e*(256/BK) + tid/BK,  kk = tid % BK
 //   r-contiguous operand:  r = tid % BR,             kk = e*(256/BR) + tid/BR
 // so consecutive lanes read consecutive addresses either way.
-template <int BR, int BK, class OP>
+template <int BR, int BK, class OP, class R>
 __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
-                                          int64_t kend, int tid, double* v) {
+                                          int64_t kend, int tid, R* v) {
   constexpr int E = BR * BK / 256;
   if constexpr (is_pair_rows_op<OP>::value) {
     static_assert(OP::kPM * OP::kPK == BR && 256 % BR == 0, "pair block must fill the row tile");
@@ -138,16 +151,17 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
     int64_t m, k;
     pair_of<OP::kPM, OP::kPK>(op.blocks, r0 / BR, i, m, k);
     const bool rok = (m < op.n) && (k < op.n);
-    const uint32_t toff = rok ? (uint32_t)((m * op.n + k) * 8) : 0u;
+    typedef typename OP::storage_t S;
+    const uint32_t toff = rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u;
     const int64_t estride = (int64_t)(256 / BR) * op.sk;
-    const double* origin = op.p + b * op.sb + (kbase + kl) * op.sk;
+    const S* origin = op.p + b * op.sb + (kbase + kl) * op.sk;
     const bool kfull = kbase + BK <= kend;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const bool ok = rok && (kfull || kbase + kl + e * (256 / BR) < kend);
       const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : op.p);
-      const double x = *reinterpret_cast<const double*>(sb + (ok ? toff : 0u));
-      v[e] = ok ? x : 0.0;
+      const S x = *reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
+      v[e] = ok ? (R)x : (R)0;
     }
   } else if constexpr (is_strided_op<OP>::value) {
     static_assert(OP::kContig ? (256 % BK == 0) : (256 % BR == 0),
@@ -165,7 +179,7 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const char* sb = reinterpret_cast<const char*>(origin + e * estride);
-        v[e] = (double)*reinterpret_cast<const S*>(sb + toff);
+        v[e] = (R)*reinterpret_cast<const S*>(sb + toff);
       }
     } else {
 #pragma unroll
@@ -175,8 +189,8 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
         const bool ok = (r0 + r < op.rows) && (kbase + k < kend);
         // masked elements read the tile origin, which is always a valid element
         const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : origin);
-        const double x = (double)*reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
-        v[e] = ok ? x : 0.0;
+        const S x = *reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
+        v[e] = ok ? (R)x : (R)0;
       }
     }
   } else {
@@ -186,7 +200,7 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
       const int kk = OP::kContig ? (idx % BK) : (idx / BR);
       const int r = OP::kContig ? (idx / BK) : (idx % BR);
       const int64_t k = kbase + kk;
-      v[e] = (k < kend) ? op.get(b, r0 + r, k) : 0.0;
+      v[e] = (k < kend) ? (R)op.get(b, r0 + r, k) : (R)0;
     }
   }
 }
@@ -197,7 +211,7 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
 template <class OP>
 inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16) {
   if constexpr (is_pair_rows_op<OP>::value) {
-    return (uint64_t)op.n * (uint64_t)op.n * 8u < (1ull << 32);
+    return (uint64_t)op.n * (uint64_t)op.n * sizeof(typename OP::storage_t) < (1ull << 32);
   } else if constexpr (is_strided_op<OP>::value) {
     const uint64_t rl = OP::kContig ? 256 / BK - 1 : BR - 1;
     const uint64_t kl = OP::kContig ? BK - 1 : 256 / BR - 1;
@@ -318,7 +332,8 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = MM::zero();
 
-  double ra[EA], rb[EB];
+  typename reg_type<OA>::type ra[EA];
+  typename reg_type<OB>::type rb[EB];
 
   auto gload = [&](int64_t kbase) {
     load_tile<BM, BK>(A, batch, m0, kbase, kb1, tid, ra);
@@ -457,12 +472,18 @@ struct EpiStore {
   int64_t sb;       // stride per batch index
   int64_t sz;       // stride per split index (partial sums)
   double alpha;
+  float* c32 = nullptr;  // optional FP32 copy, same layout (not with split-K)
   __device__ __forceinline__ void operator()(int64_t b, int64_t z, int64_t m, int64_t n, double v,
                                              bool mirror) const {
     double* cb = c + b * sb + z * sz;
     const double x = alpha * v;
     cb[m * ldc + n] = x;
     if (mirror) cb[n * ldc + m] = x;
+    if (c32) {
+      float* fb = c32 + b * sb;
+      fb[m * ldc + n] = (float)x;
+      if (mirror) fb[n * ldc + m] = (float)x;
+    }
   }
 };
 

@@ -59,6 +59,8 @@ enum Slot {
   W_MLP_PERM,    // warm start: state permutation
   W_NEAR,        // FP32 qsGW product: near-pole ranges, offsets  [3 ntiles nbf + 2 ntiles]
   W_NEARTAB,     // FP32 qsGW product: compacted (k, s) columns   [2][columns] int32
+  W_BMO32,       // FP32 products: B_mo rounded to FP32           [naux][nbf][nbf] float
+  W_RHO32,       // FP32 products: rho' rounded to FP32           [naux][sb] float
   W_NSLOTS
 };
 
@@ -179,7 +181,8 @@ inline SplitPlan split_plan(int64_t K, int64_t want) {
 
 // Launch the FP64 GEMM engine.  TRI requires M == N.  `sp` is the K-split plan
 // (partial-sum buffers must hold sp.nz slices).
-template <class T, int BM, int BN, bool TRI, class OA, class OB, class EPI, class FILT = AllTiles>
+template <class T, int BM, int BN, bool TRI, int BK = 16, class OA, class OB, class EPI,
+          class FILT = AllTiles>
 int gemm_t(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K,
            int64_t batch, SplitPlan sp = {0, 1}, FILT f = FILT()) {
   const int64_t tm = (M + BM - 1) / BM;
@@ -190,9 +193,11 @@ int gemm_t(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t 
   if (ntiles <= 0 || batch <= 0 || K <= 0) return QSGW_OK;
   const int64_t total = ntiles * batch * splits;
   if (total > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
-  if (!loader_offsets_fit(a, BM) || !loader_offsets_fit(b, BN))
+  if (!loader_offsets_fit(a, BM, BK) || !loader_offsets_fit(b, BN, BK))
     return fail(c, QSGW_ERR_UNSUPPORTED, "%s: operand strides too large for the tile loader", what);
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT, 16, T>), dim3((unsigned)total),
+  if (sp.nz > 1 && sp.kchunk % BK != 0)
+    return fail(c, QSGW_ERR_INVALID_ARG, "%s: K chunk not a multiple of the k tile", what);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, OA, OB, EPI, TRI, FILT, BK, T>), dim3((unsigned)total),
                      dim3(256), 0, c->stream, a, b, e, M, N, K, kchunk, tm, tn, batch, f);
   return launch_check(c, what);
 }

@@ -74,13 +74,20 @@ __global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* 
 }
 
 __global__ void k_rho_reduce(const double* part, int64_t nz, int64_t rows, int64_t ns,
-                             const double* Omega, double* rho) {
+                             const double* Omega, double* rho, float* rho32) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t len = rows * ns;
   if (idx >= len) return;
   double v = 0.0;
   for (int64_t z = 0; z < nz; ++z) v += part[z * len + idx];
-  rho[idx] = v * sqrt(2.0 / Omega[idx % ns]);
+  const double r = v * sqrt(2.0 / Omega[idx % ns]);
+  rho[idx] = r;
+  if (rho32) rho32[idx] = (float)r;
+}
+
+__global__ void k_to_f32(const double* in, int64_t n, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
 }
 
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc,

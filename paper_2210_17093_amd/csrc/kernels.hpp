@@ -69,9 +69,12 @@ struct EpiRho {
   double* rho;
   const double* Omega;  // already offset to the block's first excitation
   int64_t ld;
+  float* rho32 = nullptr;  // optional FP32 copy
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t m, int64_t n, double v,
                                              bool) const {
-    rho[m * ld + n] = v * sqrt(2.0 / Omega[n]);
+    const double r = v * sqrt(2.0 / Omega[n]);
+    rho[m * ld + n] = r;
+    if (rho32) rho32[m * ld + n] = (float)r;
   }
 };
 
@@ -267,7 +270,10 @@ __global__ void k_omega_from_eigs(const double* lam, int64_t n, double* Omega, i
 __global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* out, int accumulate);
 // rho'[P][s] = sqrt(2 / Omega_s) sum_z part[z][P][s]  (split-K reduce of the rho product)
 __global__ void k_rho_reduce(const double* part, int64_t nz, int64_t rows, int64_t ns,
-                             const double* Omega, double* rho);
+                             const double* Omega, double* rho, float* rho32);
+
+// out[i] = (float) in[i]
+__global__ void k_to_f32(const double* in, int64_t n, float* out);
 // c_P = sum_{i<nocc} B_mo[P][i][i]
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc, double* c);
 // J_mn = 2 sum_P c_P B_mo[P][m][n]

@@ -12,7 +12,8 @@ namespace {
 // over P, upper tiles only, mirrored).  CT is the matrix-core type.
 template <class CT>
 int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
-                         const double* C, double* T, double* B_mo, Spans* sp) {
+                         const double* C, double* T, double* B_mo, Spans* sp,
+                         float* B_mo32 = nullptr) {
   const int64_t nn = nbf * nbf;
   {
     Strided<true> A{B_ao, nbf, 1, 0, naux * nbf};
@@ -27,6 +28,7 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
     Strided<false> A{C, 1, nbf, 0, nbf};
     Strided<false> B{T, 1, nbf, nn, nbf};
     EpiStore E{B_mo, nbf, nn, 0, 1.0};
+    E.c32 = B_mo32;  // FP32 copy for the residue product of the FP32 variant
     SPAN_OPEN(sp, kKMo2);
     CHECK((gemm_shape<CT, true>(c, c->tiles.shape[TU_MO2], "mo_transform/2", A, B, E, nbf, nbf, nbf,
                                 naux)));
@@ -37,8 +39,9 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
 
 int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
                        const double* C, double* T, double* B_mo, Spans* sp = nullptr,
-                       int prec = QSGW_PREC_FP64) {
-  if (prec == QSGW_PREC_FP32) return stage_mo_transform_t<float>(c, nbf, naux, B_ao, C, T, B_mo, sp);
+                       int prec = QSGW_PREC_FP64, float* B_mo32 = nullptr) {
+  if (prec == QSGW_PREC_FP32)
+    return stage_mo_transform_t<float>(c, nbf, naux, B_ao, C, T, B_mo, sp, B_mo32);
   return stage_mo_transform_t<double>(c, nbf, naux, B_ao, C, T, B_mo, sp);
 }
 
@@ -86,7 +89,23 @@ template <class CT>
 int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
                      const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
-                     double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0) {
+                     double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
+                     const float* B_mo32 = nullptr) {
+  // The FP32 variant reads FP32 copies of B_mo and rho' in the residue product
+  // (half the operand bytes); rounding them is what its matrix cores do anyway.
+  constexpr bool f32 = sizeof(CT) == sizeof(float);
+  float* rho32 = nullptr;
+  if (f32) {
+    CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
+    if (!B_mo32) {
+      float* b32 = nullptr;
+      CHECK(ws_get(c, W_BMO32, (size_t)(naux * nbf * nbf), &b32));
+      hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * nbf * nbf)), dim3(256), 0, c->stream, B_mo,
+                         naux * nbf * nbf, b32);
+      CHECK(launch_check(c, "k_to_f32"));
+      B_mo32 = b32;
+    }
+  }
   {
     Strided<true> A{Bt, ntr, 1, 0, naux};
     Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
@@ -100,10 +119,11 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns, ntr,
                                    1, spl)));
       hipLaunchKernelGGL(k_rho_reduce, dim3(blocks_for(naux * ns)), dim3(256), 0, c->stream, part,
-                         spl.nz, naux, ns, Omega + s0, rho);
+                         spl.nz, naux, ns, Omega + s0, rho, rho32);
       CHECK(launch_check(c, "k_rho_reduce"));
     } else {
       EpiRho E{rho, Omega + s0, ns};
+      E.rho32 = rho32;
       CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns, ntr,
                                    1)));
     }
@@ -114,14 +134,21 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     const int32_t* blocks = nullptr;
     int64_t nblk = 0;
     CHECK(pair_blocks(c, nbf, &blocks, &nblk));
-    PairRows<8, 16> A{B_mo, nn, 0, nbf, blocks};
-    Strided<false> B{rho, 1, ns, 0, ns};
     EpiPairResidue E{w, wh, blocks, eps, Omega + s0, nbf, nocc, ns, eta};
     E.wh32 = wh32;
     E.w32 = w32;
     E.thr = thr;
     SPAN_OPEN(sp, kKW);
-    CHECK((gemm_t<CT, 128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
+    if constexpr (f32) {
+      // k tiles of 32: twice the matrix-core work per barrier and per prefetch
+      PairRows<8, 16, float> A{B_mo32, nn, 0, nbf, blocks};
+      Strided<false, float> B{rho32, 1, ns, 0, ns};
+      CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
+    } else {
+      PairRows<8, 16> A{B_mo, nn, 0, nbf, blocks};
+      Strided<false> B{rho, 1, ns, 0, ns};
+      CHECK((gemm_t<CT, 128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
+    }
     SPAN_CLOSE(sp);
   }
   return QSGW_OK;
@@ -132,10 +159,10 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
                    const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
                    int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
-                   double thr = 0.0) {
+                   double thr = 0.0, const float* B_mo32 = nullptr) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                   eps, nocc, eta, wh32, w32, thr);
+                                   eps, nocc, eta, wh32, w32, thr, B_mo32);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta);
 }
@@ -595,6 +622,12 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   CHECK(ws_get(c, W_CNEW, (size_t)nn, &Cn));
   CHECK(ws_get(c, W_SCAL, 8, &scal));
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  float* Bmo32 = nullptr;
+  if (fp32) {
+    CHECK(ws_get(c, W_BMO32, (size_t)(naux * nn), &Bmo32));
+    float* r32 = nullptr;
+    CHECK(ws_get(c, W_RHO32, (size_t)(naux * sb), &r32));
+  }
   // The partial-sum slot is sized by its largest user before any pointer into it is taken.
   {
     double* part = nullptr;
@@ -654,7 +687,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     Spans sp;
     sp.c = c;
     CHECK(sp.open(kStageMo));
-    CHECK(stage_mo_transform(c, nbf, naux, p->B_ao, C, T, Bmo, &sp, o->precision));
+    CHECK(stage_mo_transform(c, nbf, naux, p->B_ao, C, T, Bmo, &sp, o->precision, Bmo32));
     CHECK(sp.close());
     HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
     CHECK(sp.open(kStageRpa));
@@ -677,7 +710,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
         float* wh32 = reinterpret_cast<float*>(wh);
         float* w32 = wh32 + nn * ns;
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, nullptr,
-                             eps, nocc, o->eta, o->precision, wh32, w32, near));
+                             eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32));
         CHECK(sp.close());
         CHECK(sp.open(kStageSigma));
         CHECK(stage_sigma_qs32(c, nbf, nocc, ns, w, wh32, w32, eps, Omega + s0, o->eta, near, V,
