@@ -86,7 +86,7 @@ struct EpiRho {
 //   x = eps_m - eps_k + Omega_s (occupied k) or eps_m - eps_k - Omega_s (empty k);
 // the mirrored entry (k, m) gets its own weight.
 struct EpiPairResidue {
-  double* w;
+  double* w;              // nullptr: not written (the FP32 variant keeps w32 only)
   double* wh;             // nullptr: residues only
   const int32_t* blocks;
   const double* eps;
@@ -104,7 +104,7 @@ struct EpiPairResidue {
   }
   __device__ __forceinline__ void store(int64_t a, int64_t b, int64_t s, double v) const {
     const int64_t i = (a * nbf + b) * ns + s;
-    w[i] = v;
+    if (w) w[i] = v;
     if (wh || wh32) {
       const double x = xval(a, b, Omega[s]);
       const double g = x / (x * x + eta * eta);
@@ -132,7 +132,7 @@ struct EpiPairResidue {
 //   B(n, j) = w[n][k][s],   (k, s) = (ktab[j], stab[j]).
 struct NearRowsOp {
   static constexpr bool kContig = true;
-  const double* w;
+  const float* w;  // the FP32 copy of the residues (their accuracy is FP32 already)
   const double* eps;
   const double* Omega;
   const int32_t* ktab;
@@ -144,18 +144,18 @@ struct NearRowsOp {
     const int64_t m = m0 + r, k = ktab[j], s = stab[j];
     const double x = eps[m] - eps[k] + (k < nocc ? Omega[s] : -Omega[s]);
     if (!(fabs(x) < thr)) return 0.0;
-    return w[(m * nbf + k) * ns + s] * (x / (x * x + eta * eta));
+    return (double)w[(m * nbf + k) * ns + s] * (x / (x * x + eta * eta));
   }
 };
 struct NearColsOp {
   static constexpr bool kContig = true;
-  const double* w;
+  const float* w;
   const int32_t* ktab;
   const int32_t* stab;
   int64_t nbf, ns;
   __device__ __forceinline__ double get(int64_t, int64_t n, int64_t j) const {
     if (n >= nbf) return 0.0;
-    return w[(n * nbf + ktab[j]) * ns + stab[j]];
+    return (double)w[(n * nbf + ktab[j]) * ns + stab[j]];
   }
 };
 

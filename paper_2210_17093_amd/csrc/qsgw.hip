@@ -172,9 +172,9 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
 // FP64 split-K reduction); G_near over the near-pole terms (|x| < thr) in
 // FP64, for each 64-row tile of m over the compacted (k, s) columns in
 // which some m of the tile is near a pole.  V (+)= 1/2 (G + G^T).
-int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
-                     const float* wh32, const float* w32, const double* eps, const double* Omega,
-                     double eta, double thr, double* V, int accumulate, Spans* spn) {
+int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const float* wh32,
+                     const float* w32, const double* eps, const double* Omega, double eta,
+                     double thr, double* V, int accumulate, Spans* spn) {
   const int64_t nn = nbf * nbf, K = nbf * ns, nt = (nbf + 63) / 64;
   if (K >= (int64_t)1 << 31) return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^31");
   const SplitPlan spf = sigma_split32(c->tiles, nbf, ns);
@@ -226,8 +226,9 @@ int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const d
     const int64_t m0 = t * 64, rows = (m0 + 64 < nbf ? 64 : nbf - m0);
     int64_t kchunk = (L + zn - 1) / zn;
     kchunk = ((kchunk + 15) / 16) * 16;
-    NearRowsOp A{w, eps, Omega, ktab + base_h[t], stab + base_h[t], m0, rows, nbf, nocc, ns, eta, thr};
-    NearColsOp B{w, ktab + base_h[t], stab + base_h[t], nbf, ns};
+    NearRowsOp A{w32, eps, Omega, ktab + base_h[t], stab + base_h[t], m0, rows, nbf, nocc, ns, eta,
+                 thr};
+    NearColsOp B{w32, ktab + base_h[t], stab + base_h[t], nbf, ns};
     EpiStore E{npart + m0 * nbf, nbf, 0, nn, 1.0};
     CHECK((gemm_t<double, 64, 64, false>(c, "sigma_qs/near", A, B, E, rows, nbf, L, 1,
                                          SplitPlan{kchunk, zn})));
@@ -707,13 +708,15 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       CHECK(sp.open(kStageRes));
       if (fp32) {
         // FP32 products: the pole-weighted copy and w in FP32 share the wh buffer
+        // (the FP64 residues are written only for the diagonal outputs)
         float* wh32 = reinterpret_cast<float*>(wh);
         float* w32 = wh32 + nn * ns;
-        CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, nullptr,
+        double* w64 = (it == 0 && st->diag) ? w : nullptr;
+        CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
                              eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32));
         CHECK(sp.close());
         CHECK(sp.open(kStageSigma));
-        CHECK(stage_sigma_qs32(c, nbf, nocc, ns, w, wh32, w32, eps, Omega + s0, o->eta, near, V,
+        CHECK(stage_sigma_qs32(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta, near, V,
                                s0 > 0 ? 1 : 0, &sp));
       } else {
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps,
