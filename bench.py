@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # the counters were taken on: set an entry to None whenever that kernel changes.
 MEASURED_TRAFFIC_BYTES = {
     ("cfg2", "fp64", "residue_w"): 49.83e9,
-    ("cfg2", "fp32", "residue_w"): 53.71e9,
+    ("cfg2", "fp32", "residue_w"): None,  # kernel changed since its counters were taken
 }
 
 
