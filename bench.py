@@ -62,14 +62,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def tuned_tiles(workload):
+def tuned_tiles(workload, variant=None):
     """Tile table the autotuner (paper_2210_17093_amd/tune.py) chose for this
-    workload, or None (library defaults)."""
+    workload and variant ("fp32"), else for the workload, else None (library
+    defaults)."""
     path = os.path.join(ROOT, "paper_2210_17093_amd", "tiles.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        return json.load(f).get(workload, {}).get("spec")
+        table = json.load(f)
+    if variant and f"{workload}:{variant}" in table:
+        return table[f"{workload}:{variant}"]["spec"]
+    return table.get(workload, {}).get("spec")
 
 
 def workload_name(p, eta):
@@ -350,7 +354,7 @@ def main():
         e0 = torch.from_numpy(p.eps0).to(dev)
         prec = q.PREC_FP32 if args.precision == "fp32" else q.PREC_FP64
         with q.Context() as ctx:
-            ctx.set_tiles(tuned_tiles(args.config))
+            ctx.set_tiles(tuned_tiles(args.config, "fp32" if prec == q.PREC_FP32 else None))
             B_mo = q.qsgw_mo_transform(ctx, B, C0, precision=prec)
             M, sq = q.qsgw_rpa_build(ctx, B_mo, e0, p.nocc, precision=prec)
             # an orthogonal eigenvector matrix and positive energies of the right shape
@@ -380,12 +384,12 @@ def main():
     C = torch.empty_like(C0)
     e = torch.empty_like(e0)
     ctx = q.Context()
-    tiles = tuned_tiles(args.config)
-    ctx.set_tiles(tiles)
+    tiles = {"fp64": tuned_tiles(args.config), "fp32": tuned_tiles(args.config, "fp32")}
     h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
     torch.cuda.synchronize()
 
     def step(prec):
+        ctx.set_tiles(tiles["fp32" if prec == q.PREC_FP32 else "fp64"])
         C.copy_(C0)
         e.copy_(e0)
         return q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1, precision=prec)
@@ -457,7 +461,8 @@ def main():
         "dtype": "f32+f64" if pick == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": workload_name(p, eta), "precision": pick,
-                   "tiles": ctx.get_tiles(), "tiles_from": "tune.py" if tiles else "defaults"},
+                   "tiles": tiles[pick] or "defaults",
+                   "tiles_from": "tune.py" if tiles[pick] else "defaults"},
         "hot_path_ms": round(S["hot_ms"], 3),
         "eig_rpa_ms": round(S["eig_rpa"], 3),
         "eig_fock_ms": round(S["eig_fock"], 3),

@@ -340,13 +340,18 @@ GemmJob<OA, OB, EPI> job(OA a, OB b, EPI e, int64_t M, int64_t N, int64_t K, int
   return j;
 }
 
+constexpr int64_t kComputeUnits = 256;
+
 template <int BM, int BN, bool TRI, class CT, class OA, class OB, class EPI>
 int launch_grouped(qsgw_ctx* c, const char* what, const GemmJob<OA, OB, EPI>* jobs, int64_t njobs,
                    int64_t nwg) {
   if (nwg <= 0) return QSGW_OK;
   if (nwg > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch too large", what);
-  hipLaunchKernelGGL((gemm_grouped_kernel<BM, BN, OA, OB, EPI, TRI, 16, CT>), dim3((unsigned)nwg),
-                     dim3(256), 0, c->stream, jobs, njobs);
+  int64_t grid = nwg;
+  if (c->tiles.persistent > 0 && grid > c->tiles.persistent * kComputeUnits)
+    grid = c->tiles.persistent * kComputeUnits;
+  hipLaunchKernelGGL((gemm_grouped_kernel<BM, BN, OA, OB, EPI, TRI, 16, CT>), dim3((unsigned)grid),
+                     dim3(256), 0, c->stream, jobs, njobs, nwg);
   return launch_check(c, what);
 }
 

@@ -446,22 +446,29 @@ struct GemmJob {
 };
 
 // Grouped launch: many independent problems of different sizes (one per
-// molecule of a batch) in one dispatch.  Each workgroup finds its job by
-// binary search over the jobs' first workgroup ids, then runs the same tile
+// molecule of a batch) in one dispatch.  The `total` workgroup tiles of all
+// jobs are split into gridDim.x contiguous ranges, one per workgroup (one
+// tile each when the grid covers them all; a persistent grid of a few
+// workgroups per compute unit walks longer ranges).  Each tile finds its job
+// by binary search over the jobs' first tile ids, then runs the same tile
 // body as the single-problem kernel.
 template <int BM, int BN, class OA, class OB, class EPI, bool TRI, int BK = 16, class T = double>
 __global__ __launch_bounds__(256, 2) void gemm_grouped_kernel(const GemmJob<OA, OB, EPI>* jobs,
-                                                              int64_t njobs) {
-  const int64_t g = xcd_logical_id((int64_t)blockIdx.x, (int64_t)gridDim.x);
-  int64_t lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].wg_begin <= g) lo = mid; else hi = mid - 1;
+                                                              int64_t njobs, int64_t total) {
+  const int64_t lid = xcd_logical_id((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int64_t G = gridDim.x;
+  const int64_t t0 = lid * total / G, t1 = (lid + 1) * total / G;
+  for (int64_t g = t0; g < t1; ++g) {
+    int64_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].wg_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    const GemmJob<OA, OB, EPI>& j = jobs[lo];
+    gemm_body<BM, BN, OA, OB, EPI, TRI, AllTiles, BK, T>(j.a, j.b, j.e, j.M, j.N, j.K, j.kchunk,
+                                                         j.tiles_m, j.tiles_n, j.nbatch, AllTiles(),
+                                                         g - j.wg_begin);
   }
-  const GemmJob<OA, OB, EPI>& j = jobs[lo];
-  gemm_body<BM, BN, OA, OB, EPI, TRI, AllTiles, BK, T>(j.a, j.b, j.e, j.M, j.N, j.K, j.kchunk,
-                                                       j.tiles_m, j.tiles_n, j.nbatch, AllTiles(),
-                                                       g - j.wg_begin);
 }
 
 // ---------------------------------------------------------------- epilogues

@@ -893,13 +893,19 @@ int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {
         done = true;
       }
       if (done) continue;
+      char* e = nullptr;
+      const long long v = strtoll(val.c_str(), &e, 10);
+      if (key == "persistent") {
+        if (!e || *e || v < 0 || v > 8)
+          return fail(c, QSGW_ERR_INVALID_ARG, "tiles: persistent needs an integer in [0, 8]");
+        t.persistent = v;
+        continue;
+      }
       int64_t* target = key == "sigma_target" ? &t.sigma_target
                         : key == "rho_target" ? &t.rho_target
                         : key == "exchange_target" ? &t.exchange_target
                                                     : nullptr;
       if (!target) return fail(c, QSGW_ERR_INVALID_ARG, "tiles: unknown key '%s'", key.c_str());
-      char* e = nullptr;
-      const long long v = strtoll(val.c_str(), &e, 10);
       if (!e || *e || v < 64 || v > (1 << 20))
         return fail(c, QSGW_ERR_INVALID_ARG, "tiles: %s needs an integer in [64, 2^20]", key.c_str());
       *target = v;
@@ -924,6 +930,7 @@ int qsgw_get_tiles(qsgw_ctx* c, char* buf, int64_t size) {
   out += "sigma_target=" + std::to_string(c->tiles.sigma_target);
   out += ",rho_target=" + std::to_string(c->tiles.rho_target);
   out += ",exchange_target=" + std::to_string(c->tiles.exchange_target);
+  out += ",persistent=" + std::to_string(c->tiles.persistent);
   if ((int64_t)out.size() + 1 > size) return fail(c, QSGW_ERR_INVALID_ARG, "buffer too small");
   memcpy(buf, out.c_str(), out.size() + 1);
   return QSGW_OK;

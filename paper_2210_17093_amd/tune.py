@@ -8,7 +8,10 @@ the median of `reps` iterations of that product's own HIP-event time.  The
 fastest table per workload goes to tiles.json next to this file, which
 bench.py applies to its workload.
 
-    python -m paper_2210_17093_amd.tune cfg2 cfg4 [--reps 3]
+    python -m paper_2210_17093_amd.tune cfg2 cfg2:fp32 cfg4 [--reps 3]
+
+A workload name may carry the variant (":fp32" for the FP32 matrix-core
+products); the batched workload is tuned in its FP32 variant.
 """
 from __future__ import annotations
 
@@ -36,9 +39,12 @@ CANDIDATES = {
     "sigma": (["64x64", "128x64", "128x128"], ["sigma_qs_gemm", "sigma_qs_reduce"]),
     "sigma_target": ([4096, 2048, 8192], ["sigma_qs_gemm", "sigma_qs_reduce"]),
     "exchange": (["64x64", "128x128"], ["fock"]),
+    "persistent": ([0, 2, 4], ["mo_transform_1", "mo_transform_2", "casida", "residue_rho",
+                               "residue_w", "sigma_qs_gemm", "fock"]),
 }
 DEFAULTS = {"mo1": "128x64", "mo2": "64x64", "casida": "128x128", "rho": "128x128",
-            "rho_target": 2048, "sigma": "64x64", "sigma_target": 4096, "exchange": "64x64"}
+            "rho_target": 2048, "sigma": "64x64", "sigma_target": 4096, "exchange": "64x64",
+            "persistent": 0}
 
 
 def spec_of(table):
@@ -49,8 +55,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def single_timer(name):
-    """Per-kernel times of one plain iteration of a single-instance workload."""
+def single_timer(name, precision):
+    """Per-kernel times of one iteration of a single-instance workload."""
     from qsgw_inputs import CONFIGS, make_config
     p = make_config(name)
     eta = CONFIGS[name]["eta"]
@@ -67,7 +73,8 @@ def single_timer(name):
         e.copy_(e0)
         C.copy_(C0)
         torch.cuda.synchronize()
-        _, rep, _ = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1)
+        _, rep, _ = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1,
+                                   precision=precision)
         return rep["kernel_ms"]
     return ctx, run
 
@@ -104,11 +111,15 @@ def batched_timer(name):
 
 
 def tune(name, reps=3):
-    ctx, run = batched_timer(name) if name == "cfg4" else single_timer(name)
+    base, _, variant = name.partition(":")
+    prec = q.PREC_FP32 if variant == "fp32" else q.PREC_FP64
+    ctx, run = batched_timer(base) if base == "cfg4" else single_timer(base, prec)
     best = dict(DEFAULTS)
     run(spec_of(best))  # warm-up
     trials = []
     for key, (values, kernels) in CANDIDATES.items():
+        if key == "persistent" and base != "cfg4":
+            continue  # grouped (batched) products only
         scores = {}
         for v in values:
             table = dict(best)
@@ -133,7 +144,8 @@ def tune(name, reps=3):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("workloads", nargs="+", choices=("cfg1", "cfg2", "cfg4"))
+    ap.add_argument("workloads", nargs="+",
+                    choices=("cfg1", "cfg2", "cfg1:fp32", "cfg2:fp32", "cfg4"))
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args()

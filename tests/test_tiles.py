@@ -11,6 +11,7 @@ TABLES = [
     "mo1=64x64,mo2=128x128,casida=64x64,rho=64x64,sigma=128x128,exchange=128x128,"
     "sigma_target=2048,rho_target=1024",
     "mo1=128x128,rho=128x64,sigma=128x64,sigma_target=8192,rho_target=4096,exchange_target=512",
+    "persistent=1,mo1=64x64,sigma_target=1024",
 ]
 
 
@@ -45,7 +46,8 @@ def test_table_roundtrip_and_errors(env):
     ctx.set_tiles(TABLES[0])
     got = dict(kv.split("=") for kv in ctx.get_tiles().split(","))
     assert got["sigma"] == "128x128" and got["rho_target"] == "1024" and got["mo2"] == "128x128"
-    for bad in ("casida=128x64", "sigma=32x32", "nope=64x64", "sigma_target=7", "mo1"):
+    for bad in ("casida=128x64", "sigma=32x32", "nope=64x64", "sigma_target=7", "mo1",
+                "persistent=9"):
         with pytest.raises(q.QsgwError):
             ctx.set_tiles(bad)
     ctx.set_tiles("")
