@@ -331,17 +331,38 @@ __global__ void k_near_ranges(const double* eps, const double* Omega, int64_t nb
 
 __global__ void k_near_offsets(const int64_t* cnt, int64_t nbf, int64_t ntiles, int64_t* off,
                                int64_t* total, int64_t* base) {
+  // one workgroup per tile: exclusive prefix over k in chunks of blockDim.x
+  __shared__ int64_t sh[1024];
+  __shared__ int64_t carry;
+  const int64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < nbf; k0 += blockDim.x) {
+    const int64_t k = k0 + threadIdx.x;
+    const int64_t v = k < nbf ? cnt[t * nbf + k] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (unsigned d = 1; d < blockDim.x; d <<= 1) {  // inclusive scan (Hillis-Steele)
+      const int64_t add = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (k < nbf) off[t * nbf + k] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) carry += sh[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) total[t] = carry;
+}
+
+__global__ void k_near_bases(const int64_t* total, int64_t ntiles, int64_t* base) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   int64_t start = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
-    int64_t acc = 0;
-    for (int64_t k = 0; k < nbf; ++k) {
-      off[t * nbf + k] = acc;
-      acc += cnt[t * nbf + k];
-    }
-    total[t] = acc;
     base[t] = start;
-    start += acc;
+    start += total[t];
   }
 }
 

@@ -250,10 +250,12 @@ __global__ void k_fill(double* p, int64_t n, double v);
 __global__ void k_near_ranges(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
                               int64_t ns, double thr, int64_t ntiles, int64_t* lo, int64_t* cnt);
 
-// Offsets of the (k, s) lists in order of k within each tile, each tile's
-// total and the tiles' starts base[t] in one table (one thread, in order).
+// Offsets of the (k, s) lists in order of k within each tile and each
+// tile's total (one workgroup of at most 1024 threads per tile), then the
+// tiles' starts base[t] in one table (k_near_bases, one thread, in order).
 __global__ void k_near_offsets(const int64_t* cnt, int64_t nbf, int64_t ntiles, int64_t* off,
                                int64_t* total, int64_t* base);
+__global__ void k_near_bases(const int64_t* total, int64_t ntiles, int64_t* base);
 
 // Fill the compacted (k, s) lists: tile t's list starts at base[t].
 __global__ void k_near_fill(const int64_t* lo, const int64_t* cnt, const int64_t* off,

@@ -177,7 +177,11 @@ int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const f
                      double thr, double* V, int accumulate, Spans* spn) {
   const int64_t nn = nbf * nbf, K = nbf * ns, nt = (nbf + 63) / 64;
   if (K >= (int64_t)1 << 31) return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^31");
-  const SplitPlan spf = sigma_split32(c->tiles, nbf, ns);
+  SplitPlan spf = sigma_split32(c->tiles, nbf, ns);
+  if (spf.nz > 1) {  // the far product runs k tiles of 32: chunks are multiples of 32
+    spf.kchunk = ((spf.kchunk + 31) / 32) * 32;
+    spf.nz = (K + spf.kchunk - 1) / spf.kchunk;
+  }
   int64_t* nearws = nullptr;
   CHECK(ws_get(c, W_NEAR, (size_t)(3 * nt * nbf + 2 * nt), &nearws));
   int64_t *lo = nearws, *cnt = lo + nt * nbf, *off = cnt + nt * nbf, *tot = off + nt * nbf,
@@ -185,7 +189,9 @@ int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const f
   SPAN_OPEN(spn, kKSigma);
   hipLaunchKernelGGL(k_near_ranges, dim3(blocks_for(nt * nbf)), dim3(256), 0, c->stream, eps, Omega,
                      nbf, nocc, ns, thr, nt, lo, cnt);
-  hipLaunchKernelGGL(k_near_offsets, dim3(1), dim3(64), 0, c->stream, cnt, nbf, nt, off, tot, base);
+  hipLaunchKernelGGL(k_near_offsets, dim3((unsigned)nt), dim3(256), 0, c->stream, cnt, nbf, nt, off,
+                     tot, base);
+  hipLaunchKernelGGL(k_near_bases, dim3(1), dim3(64), 0, c->stream, tot, nt, base);
   CHECK(launch_check(c, "near-pole ranges"));
   std::vector<int64_t> tot_h(nt), base_h(nt);
   HIP_TRY(c, hipMemcpyAsync(tot_h.data(), tot, nt * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
@@ -217,8 +223,17 @@ int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const f
     Strided<true, float> A{wh32, K, 1, 0, nbf};
     Strided<true, float> B{w32, K, 1, 0, nbf};
     EpiStore E{part, nbf, 0, nn, 1.0};
-    CHECK((gemm_shape<float, false>(c, c->tiles.shape[TU_SIGMA], "sigma_qs/far", A, B, E, nbf, nbf,
-                                    K, 1, spf)));
+    const SplitPlan sp32 = spf;  // chunks are multiples of 32 (see above)
+    switch (c->tiles.shape[TU_SIGMA]) {
+      case SH_64x64:
+        CHECK((gemm_t<float, 64, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
+        break;
+      case SH_128x128:
+        CHECK((gemm_t<float, 128, 128, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
+        break;
+      default:
+        CHECK((gemm_t<float, 128, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
+    }
   }
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t L = tot_h[t];
