@@ -61,6 +61,8 @@ enum Slot {
   W_NEARTAB,     // FP32 qsGW product: compacted (k, s) columns   [2][columns] int32
   W_BMO32,       // FP32 products: B_mo rounded to FP32           [naux][nbf][nbf] float
   W_RHO32,       // FP32 products: rho' rounded to FP32           [naux][sb] float
+  W_BT32,        // FP32 products: Bt rounded to FP32             [naux][ntr] float
+  W_Z32,         // FP32 products: eigenvectors of a block, FP32  [sb][ntr] float
   W_NSLOTS
 };
 
@@ -271,22 +273,30 @@ inline SplitPlan exchange_split(const Tiles& tl, int64_t nbf, int64_t naux, int6
   return split_plan(naux * nocc, splits_for(t * (t + 1) / 2, naux * nocc, tl.exchange_target));
 }
 
-// GEMM with the tile shape chosen at run time.
-template <class T, bool TRI, class OA, class OB, class EPI>
+// GEMM with the tile shape chosen at run time (BK: k-tile depth).
+template <class T, bool TRI, int BK = 16, class OA, class OB, class EPI>
 int gemm_shape(qsgw_ctx* c, int shape, const char* what, OA a, OB b, EPI e, int64_t M, int64_t N,
                int64_t K, int64_t batch, SplitPlan sp = {0, 1}) {
   switch (shape) {
     case SH_64x64:
-      return gemm_t<T, 64, 64, TRI>(c, what, a, b, e, M, N, K, batch, sp);
+      return gemm_t<T, 64, 64, TRI, BK>(c, what, a, b, e, M, N, K, batch, sp);
     case SH_128x128:
-      return gemm_t<T, 128, 128, TRI>(c, what, a, b, e, M, N, K, batch, sp);
+      return gemm_t<T, 128, 128, TRI, BK>(c, what, a, b, e, M, N, K, batch, sp);
     default:
       if constexpr (TRI) {
         return fail(c, QSGW_ERR_INVALID_ARG, "%s: symmetric products take square tiles", what);
       } else {
-        return gemm_t<T, 128, 64, false>(c, what, a, b, e, M, N, K, batch, sp);
+        return gemm_t<T, 128, 64, false, BK>(c, what, a, b, e, M, N, K, batch, sp);
       }
   }
+}
+
+// A K-split plan with chunks rounded up to a multiple of `bk`.
+inline SplitPlan round_chunks(SplitPlan sp, int64_t K, int64_t bk) {
+  if (sp.nz <= 1) return sp;
+  sp.kchunk = ((sp.kchunk + bk - 1) / bk) * bk;
+  sp.nz = (K + sp.kchunk - 1) / sp.kchunk;
+  return sp;
 }
 
 int record(qsgw_ctx* c, size_t idx) {

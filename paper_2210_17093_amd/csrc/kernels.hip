@@ -36,7 +36,7 @@ __global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, doubl
 }
 
 __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_t naux,
-                             int64_t nbf, int64_t nocc, double* bt) {
+                             int64_t nbf, int64_t nocc, double* bt, float* bt32) {
   const int64_t nv = nbf - nocc;
   const int64_t ntr = nocc * nv;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,7 +45,9 @@ __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_
   const int64_t t = idx - P * ntr;
   const int64_t i = t / nv;
   const int64_t a = nocc + (t - i * nv);
-  bt[idx] = bmo[(P * nbf + i) * nbf + a] * sqrt_delta[t];
+  const double v = bmo[(P * nbf + i) * nbf + a] * sqrt_delta[t];
+  bt[idx] = v;
+  if (bt32) bt32[idx] = (float)v;
 }
 
 __global__ void k_omega_from_eigs(const double* lam, int64_t n, double* Omega, int* bad) {

@@ -265,7 +265,7 @@ __global__ void k_near_fill(const int64_t* lo, const int64_t* cnt, const int64_t
 __global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, double* delta,
                               double* sqrt_delta, int* bad);
 __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_t naux,
-                             int64_t nbf, int64_t nocc, double* bt);
+                             int64_t nbf, int64_t nocc, double* bt, float* bt32);
 // Omega = sqrt(lambda); flags lambda <= 0 or non-finite.
 __global__ void k_omega_from_eigs(const double* lam, int64_t n, double* Omega, int* bad);
 // out[m][n] (+)= 1/2 (sum_z part[z][m][n] + sum_z part[z][n][m])

@@ -50,22 +50,30 @@ int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_a
 int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                     const double* eps, double* M, double* sqrt_delta, double* delta, double* Bt,
                     int* flags, Spans* sp = nullptr, int prec = QSGW_PREC_FP64) {
+  // The FP32 variant also keeps Bt rounded to FP32 (W_BT32) for its products.
+  float* Bt32 = nullptr;
+  if (prec == QSGW_PREC_FP32) {
+    const int64_t n32 = naux * nocc * (nbf - nocc);
+    CHECK(ws_get(c, W_BT32, (size_t)n32, &Bt32));
+  }
   const int64_t nv = nbf - nocc, ntr = nocc * nv;
   SPAN_OPEN(sp, kKCasida);
   hipLaunchKernelGGL(k_transitions, dim3(blocks_for(ntr)), dim3(256), 0, c->stream, eps, nocc, nv,
                      delta, sqrt_delta, flags);
   CHECK(launch_check(c, "k_transitions"));
   hipLaunchKernelGGL(k_gather_bia, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, B_mo,
-                     sqrt_delta, naux, nbf, nocc, Bt);
+                     sqrt_delta, naux, nbf, nocc, Bt, Bt32);
   CHECK(launch_check(c, "k_gather_bia"));
-  Strided<false> A{Bt, 1, ntr, 0, ntr};
   EpiCasida E{M, delta, ntr};
-  if (prec == QSGW_PREC_FP32)
-    CHECK((gemm_shape<float, true>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr, ntr,
-                                   naux, 1)));
-  else
+  if (prec == QSGW_PREC_FP32) {
+    Strided<false, float> A{Bt32, 1, ntr, 0, ntr};
+    CHECK((gemm_shape<float, true, 32>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr,
+                                       ntr, naux, 1)));
+  } else {
+    Strided<false> A{Bt, 1, ntr, 0, ntr};
     CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr, ntr,
                                     naux, 1)));
+  }
   SPAN_CLOSE(sp);
   return QSGW_OK;
 }
@@ -90,12 +98,26 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
                      const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
                      double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
-                     const float* B_mo32 = nullptr) {
+                     const float* B_mo32 = nullptr, const float* Bt32_in = nullptr) {
   // The FP32 variant reads FP32 copies of B_mo and rho' in the residue product
   // (half the operand bytes); rounding them is what its matrix cores do anyway.
   constexpr bool f32 = sizeof(CT) == sizeof(float);
   float* rho32 = nullptr;
+  const float* Bt32 = Bt32_in;
+  float* Z32 = nullptr;
   if (f32) {
+    if (!Bt32) {
+      float* b = nullptr;
+      CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &b));
+      hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, Bt,
+                         naux * ntr, b);
+      CHECK(launch_check(c, "k_to_f32"));
+      Bt32 = b;
+    }
+    CHECK(ws_get(c, W_Z32, (size_t)(ns * ntr), &Z32));
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(ns * ntr)), dim3(256), 0, c->stream, Z + s0 * ntr,
+                       ns * ntr, Z32);
+    CHECK(launch_check(c, "k_to_f32"));
     CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
     if (!B_mo32) {
       float* b32 = nullptr;
@@ -107,25 +129,35 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     }
   }
   {
-    Strided<true> A{Bt, ntr, 1, 0, naux};
-    Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
-    const int64_t maxk = sizeof(CT) == sizeof(float) ? kFp32MaxK : ntr;
-    const SplitPlan spl = rho_split(c->tiles, naux, ns, ntr, maxk);
+    const int64_t maxk = f32 ? kFp32MaxK : ntr;
+    SplitPlan spl = rho_split(c->tiles, naux, ns, ntr, maxk);
+    if (f32) spl = round_chunks(spl, ntr, 32);
+    auto rho_gemm = [&](auto E, SplitPlan p) -> int {
+      if constexpr (f32) {
+        Strided<true, float> A{Bt32, ntr, 1, 0, naux};
+        Strided<true, float> B{Z32, ntr, 1, 0, ns};
+        return gemm_shape<CT, false, 32>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux,
+                                         ns, ntr, 1, p);
+      } else {
+        Strided<true> A{Bt, ntr, 1, 0, naux};
+        Strided<true> B{Z + s0 * ntr, ntr, 1, 0, ns};
+        return gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns,
+                                     ntr, 1, p);
+      }
+    };
     SPAN_OPEN(sp, kKRho);
     if (spl.nz > 1) {
       double* part = nullptr;
       CHECK(ws_get(c, W_RHOPART, (size_t)(spl.nz * naux * ns), &part));
       EpiStore E{part, ns, 0, naux * ns, 1.0};
-      CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns, ntr,
-                                   1, spl)));
+      CHECK(rho_gemm(E, spl));
       hipLaunchKernelGGL(k_rho_reduce, dim3(blocks_for(naux * ns)), dim3(256), 0, c->stream, part,
                          spl.nz, naux, ns, Omega + s0, rho, rho32);
       CHECK(launch_check(c, "k_rho_reduce"));
     } else {
       EpiRho E{rho, Omega + s0, ns};
       E.rho32 = rho32;
-      CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux, ns, ntr,
-                                   1)));
+      CHECK(rho_gemm(E, SplitPlan{0, 1}));
     }
     SPAN_CLOSE(sp);
   }
@@ -159,10 +191,10 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
                    const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
                    int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
-                   double thr = 0.0, const float* B_mo32 = nullptr) {
+                   double thr = 0.0, const float* B_mo32 = nullptr, const float* Bt32 = nullptr) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                   eps, nocc, eta, wh32, w32, thr, B_mo32);
+                                   eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta);
 }
@@ -491,14 +523,16 @@ int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const do
   if (wh && (!eps || !(eta > 0.0) || !isfinite(eta)))
     return fail(c, QSGW_ERR_INVALID_ARG, "the pole-weighted copy needs eps and a finite eta > 0");
   double *Bt = nullptr, *rho = nullptr;
+  float* Bt32 = nullptr;
   CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
   CHECK(ws_get(c, W_RHO, (size_t)(naux * s_count), &rho));
+  if (precision == QSGW_PREC_FP32) CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &Bt32));
   CHECK(single_begin(c, kStageRes));
   hipLaunchKernelGGL(k_gather_bia, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, B_mo,
-                     sqrt_delta, naux, nbf, nocc, Bt);
+                     sqrt_delta, naux, nbf, nocc, Bt, Bt32);
   CHECK(launch_check(c, "k_gather_bia"));
   CHECK(stage_residues(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s_begin, s_count, rho, w, nullptr,
-                       wh, eps, nocc, eta, precision));
+                       wh, eps, nocc, eta, precision, nullptr, nullptr, 0.0, nullptr, Bt32));
   return single_end(c);
 }
 
@@ -728,7 +762,8 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
         float* w32 = wh32 + nn * ns;
         double* w64 = (it == 0 && st->diag) ? w : nullptr;
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
-                             eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32));
+                             eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
+                             static_cast<const float*>(c->ws[W_BT32].p)));
         CHECK(sp.close());
         CHECK(sp.open(kStageSigma));
         CHECK(stage_sigma_qs32(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta, near, V,

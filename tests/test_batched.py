@@ -21,6 +21,7 @@ ETA = 1e-3
 # amplify that (weights up to 1/(2 eta), slopes up to 1/eta^2), so the two
 # are held to the same 1e-8 Ha gate as any FP64 evaluation of the method.
 QP_TOL = 1e-8      # Ha
+FP32_TOL = 1.0 / 27211.386  # 1 meV, the gate of the FP32 variants
 
 
 def shapes():
@@ -149,14 +150,22 @@ def test_graph_replays_match_eager(env):
             np.testing.assert_allclose(ra["max_deps"], rb["max_deps"], rtol=0, atol=1e-12)
 
 
-def test_batched_fp32_matches_single_fp32(env):
+def test_batched_fp32_within_the_fp32_gate(env):
+    """The batched FP32 variant (FP32 matrix-core MO transform, Casida and
+    residue products; FP64 qsGW product) and the single-instance FP32 variant
+    (which also runs the far-from-pole qsGW terms in FP32) are two reduced-
+    precision evaluations: each is held to 1 meV per state against FP64."""
     q, ctx, stream, probs = env
     rc, reps, mols = run_batch(q, ctx, stream, probs, 1, precision=q.PREC_FP32)
     for x, m in zip(probs, mols):
-        e1, _, _ = single(q, ctx, stream, x, 1, precision=q.PREC_FP32)
-        err = np.max(np.abs(m["eps"].cpu().numpy() - e1))
-        print(f"FP32 nbf={x['p'].nbf}: max|eps batched - single| = {err:.2e}", flush=True)
-        assert err <= QP_TOL, (x["p"].nbf, err)
+        e64, _, _ = single(q, ctx, stream, x, 1)
+        e32, _, _ = single(q, ctx, stream, x, 1, precision=q.PREC_FP32)
+        eb = m["eps"].cpu().numpy()
+        err_b = np.max(np.abs(eb - e64))
+        err_s = np.max(np.abs(e32 - e64))
+        print(f"FP32 nbf={x['p'].nbf}: batched {err_b:.2e}, single {err_s:.2e}, "
+              f"batched - single {np.max(np.abs(eb - e32)):.2e} Ha", flush=True)
+        assert err_b <= FP32_TOL and err_s <= FP32_TOL, (x["p"].nbf, err_b, err_s)
 
 
 def test_single_molecule_batch(env):
