@@ -49,11 +49,12 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of a kernel at the cfg2 workload, from the rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes scaled by the plain-copy calibration
-# (profiles/residue_w_cfg2_hbm_counters.md, residue_w_cfg2_fp32_hbm_counters.md).
+# (profiles/residue_w_cfg2_hbm_counters.md).  The FP32 variant's residue kernel writes
+# FP32 residues that the C-ABI counter probe cannot reproduce without an eigensolve.
 # Only valid for the kernel build
 # the counters were taken on: set an entry to None whenever that kernel changes.
 MEASURED_TRAFFIC_BYTES = {
-    ("cfg2", "fp64", "residue_w"): 49.83e9,
+    ("cfg2", "fp64", "residue_w"): 58.00e9,
     ("cfg2", "fp32", "residue_w"): None,  # kernel changed since its counters were taken
 }
 
