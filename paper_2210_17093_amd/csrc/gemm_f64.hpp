@@ -139,10 +139,15 @@ __device__ __forceinline__ void pair_of(const int32_t* blocks, int64_t t, int i,
 //   k-contiguous operand:  r = e*(256/BK) + tid/BK,  kk = tid % BK
 //   r-contiguous operand:  r = tid % BR,             kk = e*(256/BR) + tid/BR
 // so consecutive lanes read consecutive addresses either way.
+// `keep` returns whether this thread's elements are kept (false: they are
+// zeros and the caller stores 0): full pair-row tiles load unconditionally
+// and leave the masking to the LDS store, so that the loads of a tile are all
+// in flight together instead of each waiting for its own select.
 template <int BR, int BK, class OP, class R>
 __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
-                                          int64_t kend, int tid, R* v) {
+                                          int64_t kend, int tid, R* v, bool& keep) {
   constexpr int E = BR * BK / 256;
+  keep = true;
   if constexpr (is_pair_rows_op<OP>::value) {
     static_assert(OP::kPM * OP::kPK == BR && 256 % BR == 0, "pair block must fill the row tile");
     // rows are unit-stride within a block row: thread owns one row i = tid % BR
@@ -152,16 +157,31 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
     pair_of<OP::kPM, OP::kPK>(op.blocks, r0 / BR, i, m, k);
     const bool rok = (m < op.n) && (k < op.n);
     typedef typename OP::storage_t S;
-    const uint32_t toff = rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u;
     const int64_t estride = (int64_t)(256 / BR) * op.sk;
-    const S* origin = op.p + b * op.sb + (kbase + kl) * op.sk;
     const bool kfull = kbase + BK <= kend;
+    if (kfull) {
+      // Full k tile: one uniform base per element (scalar registers) and one
+      // 32-bit per-lane offset; a lane outside the pair range reads element
+      // (0, 0) of its k slab, which exists, and discards it.
+      const S* origin = op.p + b * op.sb + kbase * op.sk;
+      const uint32_t kofs = (uint32_t)((int64_t)kl * op.sk * (int64_t)sizeof(S));
+      const uint32_t toff = kofs + (rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const bool ok = rok && (kfull || kbase + kl + e * (256 / BR) < kend);
-      const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : op.p);
-      const S x = *reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
-      v[e] = ok ? (R)x : (R)0;
+      for (int e = 0; e < E; ++e) {
+        const char* sb = reinterpret_cast<const char*>(origin + e * estride);
+        v[e] = (R)*reinterpret_cast<const S*>(sb + toff);
+      }
+      keep = rok;
+    } else {
+      const uint32_t toff = rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u;
+      const S* origin = op.p + b * op.sb + (kbase + kl) * op.sk;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool ok = rok && kbase + kl + e * (256 / BR) < kend;
+        const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : op.p);
+        const S x = *reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
+        v[e] = ok ? (R)x : (R)0;
+      }
     }
   } else if constexpr (is_strided_op<OP>::value) {
     static_assert(OP::kContig ? (256 % BK == 0) : (256 % BR == 0),
@@ -211,7 +231,10 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
 template <class OP>
 inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16) {
   if constexpr (is_pair_rows_op<OP>::value) {
-    return (uint64_t)op.n * (uint64_t)op.n * sizeof(typename OP::storage_t) < (1ull << 32);
+    // pair offset plus the lane's k-slab offset (kl < 256 / BR)
+    const uint64_t kl = 256 / BR - 1;
+    return ((uint64_t)op.n * (uint64_t)op.n + kl * (uint64_t)op.sk) *
+               sizeof(typename OP::storage_t) < (1ull << 32);
   } else if constexpr (is_strided_op<OP>::value) {
     const uint64_t rl = OP::kContig ? 256 / BK - 1 : BR - 1;
     const uint64_t kl = OP::kContig ? BK - 1 : 256 / BR - 1;
@@ -334,10 +357,11 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
 
   typename reg_type<OA>::type ra[EA];
   typename reg_type<OB>::type rb[EB];
+  bool keep_a = true, keep_b = true;
 
   auto gload = [&](int64_t kbase) {
-    load_tile<BM, BK>(A, batch, m0, kbase, kb1, tid, ra);
-    load_tile<BN, BK>(B, batch, n0, kbase, kb1, tid, rb);
+    load_tile<BM, BK>(A, batch, m0, kbase, kb1, tid, ra, keep_a);
+    load_tile<BN, BK>(B, batch, n0, kbase, kb1, tid, rb, keep_b);
   };
   auto sstore = [&](int buf) {
 #pragma unroll
@@ -345,14 +369,14 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
       const int idx = e * 256 + tid;
       const int kk = OA::kContig ? (idx % BK) : (idx / BM);
       const int r = OA::kContig ? (idx / BK) : (idx % BM);
-      As[buf][a_at(r, kk)] = (T)ra[e];
+      As[buf][a_at(r, kk)] = keep_a ? (T)ra[e] : (T)0;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = e * 256 + tid;
       const int kk = OB::kContig ? (idx % BK) : (idx / BN);
       const int r = OB::kContig ? (idx / BK) : (idx % BN);
-      Bs[buf][b_at(r, kk)] = (T)rb[e];
+      Bs[buf][b_at(r, kk)] = keep_b ? (T)rb[e] : (T)0;
     }
   };
 
