@@ -2,10 +2,12 @@
 """Benchmark of one RI qsGW iteration on one MI355X.
 
 A step is one qsGW iteration through the C-ABI (qsgw_iterate, max_iter = 1)
-from the same starting orbitals, run twice per step: the plain FP64 path and
-the FP32 matrix-core variant (MO transform, Casida build and residue products
-in FP32 with FP64 outputs; eigensolves, sqrt(Delta), the self-energy product
-and the Fock update in FP64).  Each run does the AO->MO transform, Casida
+from the same starting orbitals, run once per precision variant: the plain
+FP64 path, the FP32 matrix-core variant (MO transform, Casida build, residue
+and far-from-pole self-energy products in FP32 with FP64 outputs;
+eigensolves, sqrt(Delta), near-pole terms and the Fock update in FP64) and
+the split-BF16 variant (the same with the Casida, residue and far self-energy
+products as three BF16 products of hi/lo halves).  Each run does the AO->MO transform, Casida
 build, rocSOLVER eigensolve of the Casida matrix, residues, qsGW self-energy
 matrix, Fock build and rocSOLVER eigensolve of the Fock matrix.
 
@@ -14,9 +16,9 @@ algorithmic FLOP rate (FP64-equivalent FLOPs counted from the contraction
 sizes, symmetric products at half cost) of the hot path of the fastest
 variant whose per-state quasiparticle energies stay within 1 meV of the FP64 step from the same start, from HIP events recorded
 inside the library on its stream; ms_per_step is the wall time of one step
-(both variants, eigensolves included).
+(all variants, eigensolves included).
 
-    python bench.py [--steps K] [--warmup W] [--config cfg2] [--precision both|fp64|fp32]
+    python bench.py [--steps K] [--warmup W] [--config cfg2] [--precision all|fp64|fp32|bf16x3]
                     [--no-cpu-baseline]
 
 With --config cfg4 a step is instead one call of the batched entry point
@@ -44,6 +46,7 @@ sys.path.insert(0, ROOT)
 METRIC = "qsGW iteration time & sustained TFLOP/s vs FP64 plain path at ≤1 meV QP error"
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+X3_PEAK_TFLOPS = round(2500.0 / 3, 1)  # dense BF16 matrix, 3 products per split product
 HARTREE_MEV = 27211.386
 HBM_PEAK_GBS = 8000.0
 
@@ -65,15 +68,17 @@ def log(*a):
 
 def tuned_tiles(workload, variant=None):
     """Tile table the autotuner (paper_2210_17093_amd/tune.py) chose for this
-    workload and variant ("fp32"), else for the workload, else None (library
-    defaults)."""
+    workload and variant ("fp32", "bf16x3"; the split-BF16 variant falls back
+    to the FP32 table), else for the workload, else None (library defaults)."""
     path = os.path.join(ROOT, "paper_2210_17093_amd", "tiles.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         table = json.load(f)
-    if variant and f"{workload}:{variant}" in table:
-        return table[f"{workload}:{variant}"]["spec"]
+    chain = [variant] + (["fp32"] if variant == "bf16x3" else []) if variant else []
+    for v in chain:
+        if f"{workload}:{v}" in table:
+            return table[f"{workload}:{v}"]["spec"]
     return table.get(workload, {}).get("spec")
 
 
@@ -160,6 +165,8 @@ def batch_cpu_baseline(probs, eta, iters, total_flops):
 
 def bench_batched(args, q, torch):
     from qsgw_inputs import batch_shapes, make_problem
+    if args.precision == "bf16x3":
+        raise SystemExit("the batched workload runs the FP64 and FP32 variants only")
     eta, iters = 1e-3, 5
     shapes = batch_shapes()
     log(f"[bench] generating {len(shapes)} molecules")
@@ -192,7 +199,7 @@ def bench_batched(args, q, torch):
         return time.perf_counter() - t0, reps, mols
 
     variants = {"fp64": q.PREC_FP64, "fp32": q.PREC_FP32}
-    if args.precision != "both":
+    if args.precision != "all":
         variants = {args.precision: variants[args.precision]}
     for i in range(args.warmup):
         log(f"[bench] warmup {i + 1}/{args.warmup}")
@@ -312,15 +319,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both",
-                    help="both: time the FP64 plain step and the FP32 matrix-core step from the "
-                         "same start and report their per-state QP difference")
+    ap.add_argument("--precision", choices=("all", "fp64", "fp32", "bf16x3"), default="all",
+                    help="all: time the FP64 plain step and the reduced-precision steps from the "
+                         "same start and report their per-state QP differences (cfg4: FP64 "
+                         "and FP32)")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for rocprofv3 --pmc passes only: run the hot-path entry points once "
                          "each (MO transform, Casida build, residues with the pole-weighted copy, "
                          "qsGW matrix) with Z = I and Omega = Delta in place of the eigensolve, "
                          "which is not run under counter collection, with the benchmark's tile "
-                         "table and --precision (fp64 unless fp32); prints no timing")
+                         "table and --precision (fp64 unless fp32 or bf16x3); prints no timing")
     ap.add_argument("--train-molecules", type=int, default=1024,
                     help="cfg5: training molecules (the full protocol names 20,000)")
     ap.add_argument("--test-molecules", type=int, default=256,
@@ -353,9 +361,9 @@ def main():
         B = torch.from_numpy(p.B_ao).to(dev)
         C0 = torch.from_numpy(p.C0).to(dev)
         e0 = torch.from_numpy(p.eps0).to(dev)
-        prec = q.PREC_FP32 if args.precision == "fp32" else q.PREC_FP64
+        prec = {"fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}.get(args.precision, q.PREC_FP64)
         with q.Context() as ctx:
-            ctx.set_tiles(tuned_tiles(args.config, "fp32" if prec == q.PREC_FP32 else None))
+            ctx.set_tiles(tuned_tiles(args.config, args.precision if prec != q.PREC_FP64 else None))
             B_mo = q.qsgw_mo_transform(ctx, B, C0, precision=prec)
             M, sq = q.qsgw_rpa_build(ctx, B_mo, e0, p.nocc, precision=prec)
             # an orthogonal eigenvector matrix and positive energies of the right shape
@@ -385,30 +393,33 @@ def main():
     C = torch.empty_like(C0)
     e = torch.empty_like(e0)
     ctx = q.Context()
-    tiles = {"fp64": tuned_tiles(args.config), "fp32": tuned_tiles(args.config, "fp32")}
+    tiles = {"fp64": tuned_tiles(args.config), "fp32": tuned_tiles(args.config, "fp32"),
+             "bf16x3": tuned_tiles(args.config, "bf16x3")}
     h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
     torch.cuda.synchronize()
 
-    def step(prec):
-        ctx.set_tiles(tiles["fp32" if prec == q.PREC_FP32 else "fp64"])
+    variants = {"fp64": q.PREC_FP64, "fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}
+    if args.precision != "all":
+        variants = {args.precision: variants[args.precision]}
+
+    def step(name):
+        ctx.set_tiles(tiles[name])
         C.copy_(C0)
         e.copy_(e0)
-        return q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1, precision=prec)
+        return q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1,
+                              precision=variants[name])
 
-    variants = {"fp64": q.PREC_FP64, "fp32": q.PREC_FP32}
-    if args.precision != "both":
-        variants = {args.precision: variants[args.precision]}
     for i in range(args.warmup):
         log(f"[bench] warmup {i + 1}/{args.warmup}")
-        for v in variants.values():
-            step(v)
+        for name in variants:
+            step(name)
     torch.cuda.synchronize()
     reps = {k: [] for k in variants}
     eps_out = {}
     t0 = time.perf_counter()
     for i in range(args.steps):
-        for name, v in variants.items():
-            rc, rep, _ = step(v)
+        for name in variants:
+            rc, rep, _ = step(name)
             reps[name].append(rep)
             eps_out[name] = e.cpu().numpy()
             log(f"[bench] step {i + 1}/{args.steps} {name}: hot "
@@ -432,20 +443,21 @@ def main():
                     eig_fock=float(np.mean([r["ms"]["eig_fock"] for r in rs])),
                     stage_ms={k: float(np.mean([r["ms"][k] for r in rs])) for k in rs[0]["ms"]})
 
-    peaks = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS}
+    peaks = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16x3": X3_PEAK_TFLOPS}
     sums = {k: summary(reps[k], peaks[k]) for k in reps}
     hot_flops = next(iter(reps.values()))[0]["hot_flops"]
-    qp = None
-    if "fp64" in eps_out and "fp32" in eps_out:
-        err = np.abs(eps_out["fp32"] - eps_out["fp64"]) * HARTREE_MEV
-        qp = dict(max_meV=float(err.max()), median_meV=float(np.median(err)),
-                  states_over_1meV=int((err > 1.0).sum()), states=int(err.size))
+    qps = {}
+    if "fp64" in eps_out:
+        for k in eps_out:
+            if k == "fp64":
+                continue
+            err = np.abs(eps_out[k] - eps_out["fp64"]) * HARTREE_MEV
+            qps[k] = dict(max_meV=float(err.max()), median_meV=float(np.median(err)),
+                          states_over_1meV=int((err > 1.0).sum()), states=int(err.size))
     # headline: the fastest variant whose per-state QP error against FP64 is <= 1 meV
-    pick = "fp64"
-    if "fp32" in sums and (qp is None and args.precision == "fp32" or qp and qp["max_meV"] <= 1.0):
-        pick = "fp32"
-    if args.precision == "fp32" and "fp64" not in sums:
-        pick = "fp32"
+    # (a single reduced variant run alone has no FP64 reference and stands as is)
+    ok = [k for k in sums if k == "fp64" or "fp64" not in sums or qps[k]["max_meV"] <= 1.0]
+    pick = min(ok, key=lambda k: sums[k]["hot_ms"])
     S = sums[pick]
     value = hot_flops / (S["hot_ms"] * 1e-3) / 1e12
     out = {
@@ -459,7 +471,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if pick == "fp32" else "f64",
+        "dtype": {"fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}.get(pick, "f64"),
         "data": "synthetic",
         "config": {"workload": workload_name(p, eta), "precision": pick,
                    "tiles": tiles[pick] or "defaults",
@@ -480,9 +492,12 @@ def main():
                          "dominant_kernel": v["dom"], "dominant_frac": round(v["achieved"] / v["peak"], 4)}
                      for k, v in sums.items()},
     }
-    if qp is not None:
-        out["qp_error_fp32_vs_fp64"] = qp
-        out["speedup_fp32_vs_fp64"] = round(sums["fp64"]["hot_ms"] / sums["fp32"]["hot_ms"], 3)
+    if pick == "bf16x3":
+        out["roofline"]["peak_note"] = ("BF16 dense matrix peak 2500 TFLOP/s over the 3 BF16 "
+                                        "products of one split product (algorithmic FLOPs)")
+    for k, v in qps.items():
+        out[f"qp_error_{k}_vs_fp64"] = v
+        out[f"speedup_{k}_vs_fp64"] = round(sums["fp64"]["hot_ms"] / sums[k]["hot_ms"], 3)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, eta, hot_flops)

@@ -58,7 +58,14 @@ extern "C" {
 /* Arithmetic of the contractions (MO transform, RPA build, residues). */
 #define QSGW_PREC_FP64 0
 #define QSGW_PREC_FP32 1       /* FP32 matrix-core products, FP64 accumulation across K chunks */
-#define QSGW_PREC_SPLIT_BF16 2 /* not in this version: QSGW_ERR_UNSUPPORTED */
+/* Split-BF16 products: every FP32 operand x is split into x = hi + lo (hi =
+   bf16(x), lo = bf16(x - hi)) and a*b is taken as hi*hi + hi*lo + lo*hi on
+   BF16 matrix cores with FP32 accumulation (relative error about 2^-16 per
+   product term), FP64 across K chunks.  It applies to the Casida build, the
+   residue products and the far-from-pole part of the qsGW matrix; the MO
+   transform runs on the FP32 matrix cores.  Not available in
+   qsgw_iterate_batched (QSGW_ERR_UNSUPPORTED). */
+#define QSGW_PREC_SPLIT_BF16 2
 
 /* qsgw_sigma modes. */
 #define QSGW_SIGMA_QS_MATRIX 0
@@ -92,7 +99,9 @@ int qsgw_last_stage_ms(const qsgw_ctx* ctx, double* ms, int n);
  * B_ao: [naux][nbf][nbf], symmetric in its last two indices.
  * C:    [nbf][nbf], column m holds MO m.
  * B_mo: [naux][nbf][nbf] out; written exactly symmetric in (m, n).
- * Errors: nbf < 1, naux < 1, NULL pointers, precision other than FP64.
+ * precision: QSGW_PREC_FP64, or FP32 products (QSGW_PREC_FP32 and
+ *   QSGW_PREC_SPLIT_BF16).
+ * Errors: nbf < 1, naux < 1, NULL pointers, an unknown precision.
  */
 int qsgw_mo_transform(qsgw_ctx* ctx, int64_t nbf, int64_t naux, const double* B_ao,
                       const double* C, double* B_mo, int precision);
@@ -103,7 +112,8 @@ int qsgw_mo_transform(qsgw_ctx* ctx, int64_t nbf, int64_t naux, const double* B_
  *   M[t][u] = delta_tu Delta_t^2 + 4 sqrt_delta[t] (sum_P B_mo[P][i][a] B_mo[P][j][b]) sqrt_delta[u]
  * for t = (i, a), u = (j, b).  M is [ntr][ntr], written exactly symmetric.
  * B_mo: [naux][nbf][nbf]; eps: [nbf] ascending (eps[a] > eps[i] required).
- * Errors: 0 < nocc < nbf violated; precision other than FP64.
+ * precision: any QSGW_PREC_*; sqrt_delta and the diagonal stay FP64.
+ * Errors: 0 < nocc < nbf violated; an unknown precision.
  */
 int qsgw_rpa_build(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                    const double* eps, double* M, double* sqrt_delta, int precision);
@@ -132,7 +142,9 @@ int qsgw_rpa_solve(qsgw_ctx* ctx, int64_t ntr, double* M_to_Z, double* Omega);
  *   wh[m][n][s] = w[m][n][s] Re 1/(eps_m - eps_n +- (Omega_s - i eta))
  *   ("+" for occupied n, "-" for empty n); then eps ([nbf]) and eta > 0 are
  *   required, otherwise they are ignored.
- * Errors: s range outside [0, ntr); precision other than FP64; wh without
+ * precision: any QSGW_PREC_* (reduced precisions round B_mo, Bt, Z and rho
+ *   to FP32 before their products; w and wh are still written in FP64).
+ * Errors: s range outside [0, ntr); an unknown precision; wh without
  * eps or with eta <= 0.
  */
 int qsgw_residues(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
@@ -199,7 +211,7 @@ typedef struct {
 } qsgw_state;
 
 typedef struct {
-  int precision;    /* QSGW_PREC_FP64 */
+  int precision;    /* QSGW_PREC_* */
   double eta;       /* > 0, Ha */
   double tol;       /* converged when max_m |eps'_m - eps_m| < tol */
   int64_t max_iter; /* iterations in this call, >= 1 */
@@ -207,9 +219,9 @@ typedef struct {
   int fock_mode;    /* QSGW_FOCK_FULL_JK */
   int64_t s_block;  /* excitations per streamed residue block; 0 = automatic */
   int64_t flags;    /* QSGW_OPT_* bits */
-  double near_pole; /* QSGW_PREC_FP32, qsgw_iterate: terms of the qsGW product (Eq. 19) with
-                       |eps_m - eps_k +- Omega_s| below this (Ha) are summed in FP64, the rest on
-                       FP32 matrix cores; 0 = 0.05 Ha */
+  double near_pole; /* reduced precisions, qsgw_iterate: terms of the qsGW product (Eq. 19)
+                       with |eps_m - eps_k +- Omega_s| below this (Ha) are summed in FP64, the
+                       rest on FP32 (or split-BF16) matrix cores; 0 = 0.05 Ha */
 } qsgw_options;
 
 /* qsgw_options.flags, qsgw_iterate_batched only: run the kernel segments

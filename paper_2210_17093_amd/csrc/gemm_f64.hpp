@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace qsgw {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -57,6 +59,41 @@ struct Mfma<float> {
   }
   __device__ __forceinline__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
+
+// Split-BF16 products: each FP32 operand x is split as x = hi + lo with
+// hi = bf16(x) and lo = bf16(x - hi) (both round to nearest even), and
+// a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation.  The dropped lo_a lo_b and the rounding of lo leave a
+// relative error of about 2^-16 per product; the three BF16 products run at
+// several times the FP32 matrix-core rate.  Fragments: lane l holds the 8
+// consecutive k = 8 (l / 16) .. 8 (l / 16) + 7 of row l % 16 of A (column
+// l % 16 of B); D as in the FP32 16x16x4 instruction.
+struct Bf16x3 {};
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+template <>
+struct Mfma<Bf16x3> {
+  typedef f32x4 acc_t;
+  __device__ __forceinline__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ __forceinline__ static acc_t mma(bf16x8 a, bf16x8 b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+template <class T>
+struct is_bf16x3 {
+  static constexpr bool value = false;
+};
+template <>
+struct is_bf16x3<Bf16x3> {
+  static constexpr bool value = true;
+};
+
+// hi and lo halves of a split value (see Bf16x3)
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
 
 // Element (r, k) at p[b*sb + r*sr + k*sk] (strides in elements of the
 // storage type S, double or float); rows >= `rows` or k >= K read 0.
@@ -134,81 +171,114 @@ __device__ __forceinline__ void pair_of(const int32_t* blocks, int64_t t, int i,
   k = (int64_t)(bk & 0xffff) * PK + i % PK;
 }
 
-// Load this thread's E = BR*BK/256 elements of a BR x BK operand tile
-// (rows r0.., k = kbase..) into v[].  Element e of thread tid sits at
-//   k-contiguous operand:  r = e*(256/BK) + tid/BK,  kk = tid % BK
-//   r-contiguous operand:  r = tid % BR,             kk = e*(256/BR) + tid/BR
-// so consecutive lanes read consecutive addresses either way.
+// Which elements of a BR x BK operand tile each of the 256 threads holds.
+// Element e of thread tid sits at row rl(tid) + dr(e), k kl(tid) + dk(e): a
+// per-thread origin plus a uniform step, so a thread addresses all its
+// elements from one 32-bit offset.  Consecutive lanes read consecutive
+// addresses in both orientations.
+//   KB = false (FP64 / FP32 products, one element per lane and k step):
+//     k-contiguous:  r = e*(256/BK) + tid/BK,  k = tid % BK
+//     r-contiguous:  r = tid % BR,             k = e*(256/BR) + tid/BR
+//   KB = true (split-BF16 products, whose fragments hold 8 consecutive k):
+//     k-contiguous:  r = (e/4)*(1024/BK) + tid/(BK/4),  k = 4 (tid % (BK/4)) + e % 4
+//     r-contiguous:  r = tid % BR,                      k = E (tid / BR) + e
+template <int BR, int BK, bool KC, bool KB>
+struct TileMap {
+  static constexpr int E = BR * BK / 256;
+  static constexpr int TK = BK / 4;  // KB, k-contiguous: threads along k
+  __host__ __device__ static constexpr int rl(int tid) {
+    return KC ? (KB ? tid / TK : tid / BK) : tid % BR;
+  }
+  __host__ __device__ static constexpr int kl(int tid) {
+    return KC ? (KB ? 4 * (tid % TK) : tid % BK) : (KB ? E * (tid / BR) : tid / BR);
+  }
+  __host__ __device__ static constexpr int dr(int e) {
+    return KC ? (KB ? (e / 4) * (256 / TK) : e * (256 / BK)) : 0;
+  }
+  __host__ __device__ static constexpr int dk(int e) {
+    return KC ? (KB ? e % 4 : 0) : (KB ? e : e * (256 / BR));
+  }
+};
+
+// Element map of a split-BF16 operand tile, as a tag for the LDS store.
+template <int BR, int BK, bool KC>
+struct X3Map {
+  typedef TileMap<BR, BK, KC, true> M;
+  static constexpr int E = M::E;
+  static constexpr bool kc = KC;
+};
+
+// Load this thread's E = BR*BK/256 elements of a BR x BK operand tile (rows
+// r0.., k = kbase..) into v[], in the order of TileMap.
 // `keep` returns whether this thread's elements are kept (false: they are
 // zeros and the caller stores 0): full pair-row tiles load unconditionally
 // and leave the masking to the LDS store, so that the loads of a tile are all
 // in flight together instead of each waiting for its own select.
-template <int BR, int BK, class OP, class R>
+template <int BR, int BK, bool KB, class OP, class R>
 __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
                                           int64_t kend, int tid, R* v, bool& keep) {
-  constexpr int E = BR * BK / 256;
+  typedef TileMap<BR, BK, OP::kContig, KB> TM;
+  constexpr int E = TM::E;
   keep = true;
   if constexpr (is_pair_rows_op<OP>::value) {
     static_assert(OP::kPM * OP::kPK == BR && 256 % BR == 0, "pair block must fill the row tile");
     // rows are unit-stride within a block row: thread owns one row i = tid % BR
-    const int i = tid % BR;
-    const int kl = tid / BR;
+    const int i = TM::rl(tid);
+    const int kl = TM::kl(tid);
     int64_t m, k;
     pair_of<OP::kPM, OP::kPK>(op.blocks, r0 / BR, i, m, k);
     const bool rok = (m < op.n) && (k < op.n);
     typedef typename OP::storage_t S;
-    const int64_t estride = (int64_t)(256 / BR) * op.sk;
     const bool kfull = kbase + BK <= kend;
+    const S* origin = op.p + b * op.sb + kbase * op.sk;
+    const uint32_t pofs = rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u;
     if (kfull) {
       // Full k tile: one uniform base per element (scalar registers) and one
       // 32-bit per-lane offset; a lane outside the pair range reads element
       // (0, 0) of its k slab, which exists, and discards it.
-      const S* origin = op.p + b * op.sb + kbase * op.sk;
-      const uint32_t kofs = (uint32_t)((int64_t)kl * op.sk * (int64_t)sizeof(S));
-      const uint32_t toff = kofs + (rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u);
+      const uint32_t toff = (uint32_t)((int64_t)kl * op.sk * (int64_t)sizeof(S)) + pofs;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const char* sb = reinterpret_cast<const char*>(origin + e * estride);
+        const char* sb = reinterpret_cast<const char*>(origin + TM::dk(e) * op.sk);
         v[e] = (R)*reinterpret_cast<const S*>(sb + toff);
       }
       keep = rok;
     } else {
-      const uint32_t toff = rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u;
-      const S* origin = op.p + b * op.sb + (kbase + kl) * op.sk;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const bool ok = rok && kbase + kl + e * (256 / BR) < kend;
-        const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : op.p);
-        const S x = *reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
+        const int64_t kk = kl + TM::dk(e);
+        const bool ok = rok && kbase + kk < kend;
+        const char* sb = reinterpret_cast<const char*>(ok ? origin + kk * op.sk : op.p);
+        const S x = *reinterpret_cast<const S*>(sb + (ok ? pofs : 0u));
         v[e] = ok ? (R)x : (R)0;
       }
     }
   } else if constexpr (is_strided_op<OP>::value) {
-    static_assert(OP::kContig ? (256 % BK == 0) : (256 % BR == 0),
+    static_assert(OP::kContig ? (256 % (KB ? BK / 4 : BK) == 0) : (256 % BR == 0),
                   "tile shape must divide the block");
     // Uniform part (scalar registers): the tile origin and the element step.
     // Per-thread part: one 32-bit byte offset shared by all E elements.
-    const int rl = OP::kContig ? (tid / BK) : (tid % BR);
-    const int kl = OP::kContig ? (tid % BK) : (tid / BR);
+    const int rl = TM::rl(tid);
+    const int kl = TM::kl(tid);
     typedef typename OP::storage_t S;
-    const int64_t estride = OP::kContig ? (int64_t)(256 / BK) * op.sr : (int64_t)(256 / BR) * op.sk;
     const S* origin = op.p + b * op.sb + r0 * op.sr + kbase * op.sk;
     const uint32_t toff = (uint32_t)(((int64_t)rl * op.sr + (int64_t)kl * op.sk) * (int64_t)sizeof(S));
     const bool full = (r0 + BR <= op.rows) && (kbase + BK <= kend);
     if (full) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const char* sb = reinterpret_cast<const char*>(origin + e * estride);
+        const char* sb = reinterpret_cast<const char*>(origin + TM::dr(e) * op.sr + TM::dk(e) * op.sk);
         v[e] = (R)*reinterpret_cast<const S*>(sb + toff);
       }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int r = OP::kContig ? rl + e * (256 / BK) : rl;
-        const int k = OP::kContig ? kl : kl + e * (256 / BR);
+        const int r = rl + TM::dr(e);
+        const int k = kl + TM::dk(e);
         const bool ok = (r0 + r < op.rows) && (kbase + k < kend);
         // masked elements read the tile origin, which is always a valid element
-        const char* sb = reinterpret_cast<const char*>(ok ? origin + e * estride : origin);
+        const char* sb = reinterpret_cast<const char*>(
+            ok ? origin + TM::dr(e) * op.sr + TM::dk(e) * op.sk : origin);
         const S x = *reinterpret_cast<const S*>(sb + (ok ? toff : 0u));
         v[e] = ok ? (R)x : (R)0;
       }
@@ -216,9 +286,8 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int idx = e * 256 + tid;
-      const int kk = OP::kContig ? (idx % BK) : (idx / BR);
-      const int r = OP::kContig ? (idx / BK) : (idx % BR);
+      const int kk = TM::kl(tid) + TM::dk(e);
+      const int r = TM::rl(tid) + TM::dr(e);
       const int64_t k = kbase + kk;
       v[e] = (k < kend) ? (R)op.get(b, r0 + r, k) : (R)0;
     }
@@ -227,17 +296,24 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
 
 // Host check: the tile loaders address a thread's elements with one 32-bit
 // byte offset from a uniform origin; it must fit for the operand's strides
-// (BR rows x BK k per tile, 256 threads).
+// (BR rows x BK k per tile, 256 threads, element map KB).
 template <class OP>
-inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16) {
+inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16, bool KB = false) {
+  const uint64_t E = (uint64_t)BR * BK / 256;
   if constexpr (is_pair_rows_op<OP>::value) {
-    // pair offset plus the lane's k-slab offset (kl < 256 / BR)
-    const uint64_t kl = 256 / BR - 1;
+    // pair offset plus the lane's k offset
+    const uint64_t kl = KB ? BK - E : 256 / BR - 1;
     return ((uint64_t)op.n * (uint64_t)op.n + kl * (uint64_t)op.sk) *
                sizeof(typename OP::storage_t) < (1ull << 32);
   } else if constexpr (is_strided_op<OP>::value) {
-    const uint64_t rl = OP::kContig ? 256 / BK - 1 : BR - 1;
-    const uint64_t kl = OP::kContig ? BK - 1 : 256 / BR - 1;
+    uint64_t rl, kl;
+    if (OP::kContig) {
+      rl = KB ? 1024 / BK - 1 : 256 / BK - 1;
+      kl = KB ? BK - 4 : BK - 1;
+    } else {
+      rl = BR - 1;
+      kl = KB ? BK - E : 256 / BR - 1;
+    }
     return (rl * (uint64_t)op.sr + kl * (uint64_t)op.sk) * sizeof(typename OP::storage_t) <
            (1ull << 32);
   } else {
@@ -293,38 +369,49 @@ struct AllTiles {
 
 // TRI: only tiles with tm <= tn run, elements with m > n are dropped and the
 // epilogue is asked to mirror (m, n) -> (n, m) (symmetric results).
+// T: double or float (v_mfma_*_16x16x4), or Bf16x3 (split-BF16 products).
 template <int BM, int BN, class OA, class OB, class EPI, bool TRI, class FILT, int BK, class T>
 __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& epi, int64_t M,
                                           int64_t N, int64_t K, int64_t kchunk, int64_t tiles_m,
                                           int64_t tiles_n, int64_t nbatch, const FILT& filt,
                                           int64_t lid) {
-  static_assert(BK % 4 == 0, "BK is a multiple of the MFMA depth");
-  // LDS layout per operand: a k-contiguous operand is kept [r][k] (pitch BK+1)
-  // so global rows land in LDS rows without a transpose; an r-contiguous one
-  // is kept [k][r] (pitch BR+1).  Both pitches are odd, which keeps the 16
-  // lanes of an MFMA fragment read on distinct banks.
+  constexpr bool X3 = is_bf16x3<T>::value;
+  static_assert(BK % (X3 ? 32 : 4) == 0, "BK is a multiple of the MFMA depth");
+  // LDS layout per operand.  FP64 / FP32: a k-contiguous operand is kept
+  // [r][k] (pitch BK+1) so global rows land in LDS rows without a transpose;
+  // an r-contiguous one is kept [k][r] (pitch BR+1).  Both pitches are odd,
+  // which keeps the 16 lanes of an MFMA fragment read on distinct banks.
+  // Split-BF16: hi and lo tiles, both [r][k] whatever the global orientation
+  // (a fragment is 8 consecutive k of one row, one 16-byte read), pitch BK+8
+  // (16-byte aligned rows; 8 consecutive rows of a fragment read cover all
+  // banks once).
   constexpr bool AK = OA::kContig, BKC = OB::kContig;
-  constexpr int SZA = AK ? BM * (BK + 1) : BK * (BM + 1);
-  constexpr int SZB = BKC ? BN * (BK + 1) : BK * (BN + 1);
+  constexpr int PX = BK + 8;
+  constexpr int SZA = X3 ? BM * PX : (AK ? BM * (BK + 1) : BK * (BM + 1));
+  constexpr int SZB = X3 ? BN * PX : (BKC ? BN * (BK + 1) : BK * (BN + 1));
   constexpr int EA = BM * BK / 256;
   constexpr int EB = BN * BK / 256;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   static_assert(BM % 32 == 0 && BN % 32 == 0, "tile must split into 2x2 waves of 16x16 MFMA tiles");
   static_assert(EA >= 1 && EB >= 1, "tile too small for 256 threads");
+  static_assert(!X3 || ((AK || EA % 8 == 0) && (BKC || EB % 8 == 0)),
+                "split-BF16 r-contiguous tiles store 8 consecutive k per thread");
+  typedef typename std::conditional<X3, __bf16, T>::type LT;  // LDS element type
+  constexpr int NPL = X3 ? 2 : 1;                               // planes (hi, lo)
 
-  // One LDS block: the double-buffered operand tiles (compute type T) during
-  // the K loop, then the FP64 staging area of the epilogue (WM rows of the C
-  // tile at a time).
+  // One LDS block: the double-buffered operand tiles during the K loop, then
+  // the FP64 staging area of the epilogue (WM rows of the C tile at a time).
   constexpr int LDC = BN + 1;
-  constexpr size_t OPER_BYTES = 2 * (size_t)(SZA + SZB) * sizeof(T);
+  constexpr size_t OPER_BYTES = 2 * NPL * (size_t)(SZA + SZB) * sizeof(LT);
   constexpr size_t STAGE_BYTES = (size_t)WM * LDC * sizeof(double);
   constexpr size_t SMEM_BYTES = OPER_BYTES > STAGE_BYTES ? OPER_BYTES : STAGE_BYTES;
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
-  T (*As)[SZA] = reinterpret_cast<T (*)[SZA]>(smem);
-  T (*Bs)[SZB] = reinterpret_cast<T (*)[SZB]>(smem + 2 * (size_t)SZA * sizeof(T));
+  // plane p of buffer u: As[u * NPL + p]
+  LT (*As)[SZA] = reinterpret_cast<LT (*)[SZA]>(smem);
+  LT (*Bs)[SZB] = reinterpret_cast<LT (*)[SZB]>(smem + 2 * NPL * (size_t)SZA * sizeof(LT));
   typedef Mfma<T> MM;
-  // element (r, k) of the staged tiles
+  // element (r, k) of the staged FP64 / FP32 tiles
   auto a_at = [](int r, int k) { return AK ? r * (BK + 1) + k : k * (BM + 1) + r; };
   auto b_at = [](int r, int k) { return BKC ? r * (BK + 1) + k : k * (BN + 1) + r; };
 
@@ -360,23 +447,52 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   bool keep_a = true, keep_b = true;
 
   auto gload = [&](int64_t kbase) {
-    load_tile<BM, BK>(A, batch, m0, kbase, kb1, tid, ra, keep_a);
-    load_tile<BN, BK>(B, batch, n0, kbase, kb1, tid, rb, keep_b);
+    load_tile<BM, BK, X3>(A, batch, m0, kbase, kb1, tid, ra, keep_a);
+    load_tile<BN, BK, X3>(B, batch, n0, kbase, kb1, tid, rb, keep_b);
+  };
+  // Split-BF16 store of one operand's elements (TileMap<.., KB = true>
+  // order): runs of consecutive k of one row go out as 16-byte (r-contiguous:
+  // 8 k) or 8-byte (k-contiguous: 4 k) writes to the hi and lo planes.
+  auto sstore_x3 = [&](auto* v, bool keep, LT* hi, LT* lo, auto map_tag) {
+    typedef decltype(map_tag) MP;
+    constexpr int E = MP::E;
+    constexpr int RUN = MP::kc ? 4 : 8;
+#pragma unroll
+    for (int g = 0; g < E / RUN; ++g) {
+      const int r = MP::M::rl(tid) + MP::M::dr(g * RUN);
+      const int k = MP::M::kl(tid) + MP::M::dk(g * RUN);
+      typedef typename std::conditional<MP::kc, bf16x4, bf16x8>::type V;
+      V h, l;
+#pragma unroll
+      for (int u = 0; u < RUN; ++u) {
+        __bf16 a, c;
+        split_bf16(keep ? (float)v[g * RUN + u] : 0.f, a, c);
+        h[u] = a;
+        l[u] = c;
+      }
+      *reinterpret_cast<V*>(hi + r * PX + k) = h;
+      *reinterpret_cast<V*>(lo + r * PX + k) = l;
+    }
   };
   auto sstore = [&](int buf) {
+    if constexpr (X3) {
+      sstore_x3(ra, keep_a, As[2 * buf], As[2 * buf + 1], X3Map<BM, BK, AK>());
+      sstore_x3(rb, keep_b, Bs[2 * buf], Bs[2 * buf + 1], X3Map<BN, BK, BKC>());
+    } else {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = e * 256 + tid;
-      const int kk = OA::kContig ? (idx % BK) : (idx / BM);
-      const int r = OA::kContig ? (idx / BK) : (idx % BM);
-      As[buf][a_at(r, kk)] = keep_a ? (T)ra[e] : (T)0;
-    }
+      for (int e = 0; e < EA; ++e) {
+        const int idx = e * 256 + tid;
+        const int kk = OA::kContig ? (idx % BK) : (idx / BM);
+        const int r = OA::kContig ? (idx / BK) : (idx % BM);
+        As[buf][a_at(r, kk)] = keep_a ? (T)ra[e] : (T)0;
+      }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int idx = e * 256 + tid;
-      const int kk = OB::kContig ? (idx % BK) : (idx / BN);
-      const int r = OB::kContig ? (idx / BK) : (idx % BN);
-      Bs[buf][b_at(r, kk)] = keep_b ? (T)rb[e] : (T)0;
+      for (int e = 0; e < EB; ++e) {
+        const int idx = e * 256 + tid;
+        const int kk = OB::kContig ? (idx % BK) : (idx / BN);
+        const int r = OB::kContig ? (idx / BK) : (idx % BN);
+        Bs[buf][b_at(r, kk)] = keep_b ? (T)rb[e] : (T)0;
+      }
     }
   };
 
@@ -389,21 +505,58 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   for (int64_t it = 0; it < nk; ++it) {
     const int cur = (int)(it & 1);
     if (it + 1 < nk) gload(kb0 + (it + 1) * BK);
-    const T* as = As[cur];
-    const T* bs = Bs[cur];
+    if constexpr (X3) {
+      const LT* ah_s = As[2 * cur];
+      const LT* al_s = As[2 * cur + 1];
+      const LT* bh_s = Bs[2 * cur];
+      const LT* bl_s = Bs[2 * cur + 1];
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int krow = ks * 4 + (lane >> 4);
-      T a[TM], b[TN];
+      for (int ks = 0; ks < BK / 32; ++ks) {
+        const int kofs = ks * 32 + 8 * (lane >> 4);
+        bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = as[a_at(wm + i * 16 + (lane & 15), krow)];
+        for (int i = 0; i < TM; ++i) {
+          const int o = (wm + i * 16 + (lane & 15)) * PX + kofs;
+          ah[i] = *reinterpret_cast<const bf16x8*>(ah_s + o);
+          al[i] = *reinterpret_cast<const bf16x8*>(al_s + o);
+        }
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = bs[b_at(wn + j * 16 + (lane & 15), krow)];
+        for (int j = 0; j < TN; ++j) {
+          const int o = (wn + j * 16 + (lane & 15)) * PX + kofs;
+          bh[j] = *reinterpret_cast<const bf16x8*>(bh_s + o);
+          bl[j] = *reinterpret_cast<const bf16x8*>(bl_s + o);
+        }
+        // small cross terms first, then hi * hi
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(al[i], bh[j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah[i], bl[j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah[i], bh[j], acc[i][j]);
+      }
+    } else {
+      const T* as = As[cur];
+      const T* bs = Bs[cur];
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int krow = ks * 4 + (lane >> 4);
+        T a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = as[a_at(wm + i * 16 + (lane & 15), krow)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = bs[b_at(wn + j * 16 + (lane & 15), krow)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
+      }
     }
     if (it + 1 < nk) sstore(cur ^ 1);
     __syncthreads();

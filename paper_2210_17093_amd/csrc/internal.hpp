@@ -198,7 +198,8 @@ int gemm_t(qsgw_ctx* c, const char* what, OA a, OB b, EPI e, int64_t M, int64_t 
   if (ntiles <= 0 || batch <= 0 || K <= 0) return QSGW_OK;
   const int64_t total = ntiles * batch * splits;
   if (total > 0x7fffffffLL) return fail(c, QSGW_ERR_INVALID_ARG, "%s: launch grid too large", what);
-  if (!loader_offsets_fit(a, BM, BK) || !loader_offsets_fit(b, BN, BK))
+  constexpr bool kb = is_bf16x3<T>::value;
+  if (!loader_offsets_fit(a, BM, BK, kb) || !loader_offsets_fit(b, BN, BK, kb))
     return fail(c, QSGW_ERR_UNSUPPORTED, "%s: operand strides too large for the tile loader", what);
   if (sp.nz > 1 && sp.kchunk % BK != 0)
     return fail(c, QSGW_ERR_INVALID_ARG, "%s: K chunk not a multiple of the k tile", what);

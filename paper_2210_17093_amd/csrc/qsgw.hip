@@ -40,7 +40,8 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
 int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
                        const double* C, double* T, double* B_mo, Spans* sp = nullptr,
                        int prec = QSGW_PREC_FP64, float* B_mo32 = nullptr) {
-  if (prec == QSGW_PREC_FP32)
+  // (the split-BF16 variant transforms on the FP32 matrix cores)
+  if (prec != QSGW_PREC_FP64)
     return stage_mo_transform_t<float>(c, nbf, naux, B_ao, C, T, B_mo, sp, B_mo32);
   return stage_mo_transform_t<double>(c, nbf, naux, B_ao, C, T, B_mo, sp);
 }
@@ -50,9 +51,10 @@ int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_a
 int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                     const double* eps, double* M, double* sqrt_delta, double* delta, double* Bt,
                     int* flags, Spans* sp = nullptr, int prec = QSGW_PREC_FP64) {
-  // The FP32 variant also keeps Bt rounded to FP32 (W_BT32) for its products.
+  // The reduced-precision variants also keep Bt rounded to FP32 (W_BT32) for
+  // their products.
   float* Bt32 = nullptr;
-  if (prec == QSGW_PREC_FP32) {
+  if (prec != QSGW_PREC_FP64) {
     const int64_t n32 = naux * nocc * (nbf - nocc);
     CHECK(ws_get(c, W_BT32, (size_t)n32, &Bt32));
   }
@@ -69,6 +71,10 @@ int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const 
     Strided<false, float> A{Bt32, 1, ntr, 0, ntr};
     CHECK((gemm_shape<float, true, 32>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr,
                                        ntr, naux, 1)));
+  } else if (prec == QSGW_PREC_SPLIT_BF16) {
+    Strided<false, float> A{Bt32, 1, ntr, 0, ntr};
+    CHECK((gemm_shape<Bf16x3, true, 32>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr,
+                                        ntr, naux, 1)));
   } else {
     Strided<false> A{Bt, 1, ntr, 0, ntr};
     CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr, ntr,
@@ -99,9 +105,10 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
                      double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
                      const float* B_mo32 = nullptr, const float* Bt32_in = nullptr) {
-  // The FP32 variant reads FP32 copies of B_mo and rho' in the residue product
-  // (half the operand bytes); rounding them is what its matrix cores do anyway.
-  constexpr bool f32 = sizeof(CT) == sizeof(float);
+  // The FP32 and split-BF16 variants read FP32 copies of B_mo and rho' in the
+  // residue product (half the operand bytes); rounding them is what their
+  // matrix cores do anyway.
+  constexpr bool f32 = !std::is_same<CT, double>::value;
   float* rho32 = nullptr;
   const float* Bt32 = Bt32_in;
   float* Z32 = nullptr;
@@ -195,18 +202,23 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
+  if (prec == QSGW_PREC_SPLIT_BF16)
+    return stage_residues_t<Bf16x3>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
+                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta);
 }
 
-// FP32 variant of Eq. (19) for one excitation block.  G = G_far + G_near:
+// Reduced-precision variant of Eq. (19) for one excitation block (PT: float
+// for FP32 matrix-core products, Bf16x3 for split-BF16).  G = G_far + G_near:
 // G_far = Wh32 W32^T over every term with |x| >= thr (FP32 matrix cores,
 // FP64 split-K reduction); G_near over the near-pole terms (|x| < thr) in
 // FP64, for each 64-row tile of m over the compacted (k, s) columns in
 // which some m of the tile is near a pole.  V (+)= 1/2 (G + G^T).
-int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const float* wh32,
-                     const float* w32, const double* eps, const double* Omega, double eta,
-                     double thr, double* V, int accumulate, Spans* spn) {
+template <class PT>
+int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const float* wh32,
+                       const float* w32, const double* eps, const double* Omega, double eta,
+                       double thr, double* V, int accumulate, Spans* spn) {
   const int64_t nn = nbf * nbf, K = nbf * ns, nt = (nbf + 63) / 64;
   if (K >= (int64_t)1 << 31) return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^31");
   SplitPlan spf = sigma_split32(c->tiles, nbf, ns);
@@ -258,13 +270,13 @@ int stage_sigma_qs32(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const f
     const SplitPlan sp32 = spf;  // chunks are multiples of 32 (see above)
     switch (c->tiles.shape[TU_SIGMA]) {
       case SH_64x64:
-        CHECK((gemm_t<float, 64, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
+        CHECK((gemm_t<PT, 64, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
         break;
       case SH_128x128:
-        CHECK((gemm_t<float, 128, 128, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
+        CHECK((gemm_t<PT, 128, 128, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
         break;
       default:
-        CHECK((gemm_t<float, 128, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
+        CHECK((gemm_t<PT, 128, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
     }
   }
   for (int64_t t = 0; t < nt; ++t) {
@@ -389,10 +401,9 @@ int check_common(qsgw_ctx* c, int64_t nbf, int64_t naux) {
 }
 
 int check_prec(qsgw_ctx* c, int precision) {
-  if (precision == QSGW_PREC_FP64 || precision == QSGW_PREC_FP32) return QSGW_OK;
-  if (precision == QSGW_PREC_SPLIT_BF16)
-    return fail(c, QSGW_ERR_UNSUPPORTED, "precision %d is not available in this version",
-                precision);
+  if (precision == QSGW_PREC_FP64 || precision == QSGW_PREC_FP32 ||
+      precision == QSGW_PREC_SPLIT_BF16)
+    return QSGW_OK;
   return fail(c, QSGW_ERR_INVALID_ARG, "unknown precision %d", precision);
 }
 
@@ -526,7 +537,7 @@ int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const do
   float* Bt32 = nullptr;
   CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
   CHECK(ws_get(c, W_RHO, (size_t)(naux * s_count), &rho));
-  if (precision == QSGW_PREC_FP32) CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &Bt32));
+  if (precision != QSGW_PREC_FP64) CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &Bt32));
   CHECK(single_begin(c, kStageRes));
   hipLaunchKernelGGL(k_gather_bia, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, B_mo,
                      sqrt_delta, naux, nbf, nocc, Bt, Bt32);
@@ -636,7 +647,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   if (o->s_block < 0) return fail(c, QSGW_ERR_INVALID_ARG, "need s_block >= 0");
   if (!(o->near_pole >= 0.0) || !isfinite(o->near_pole))
     return fail(c, QSGW_ERR_INVALID_ARG, "need a finite near_pole >= 0");
-  const bool fp32 = o->precision == QSGW_PREC_FP32;
+  const bool fp32 = o->precision != QSGW_PREC_FP64;  // FP32 or split-BF16 products
   const double near = o->near_pole > 0.0 ? o->near_pole : kNearPoleDefault;
 
   const int64_t nv = nbf - nocc, ntr = nocc * nv, nn = nbf * nbf;
@@ -766,8 +777,12 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
                              static_cast<const float*>(c->ws[W_BT32].p)));
         CHECK(sp.close());
         CHECK(sp.open(kStageSigma));
-        CHECK(stage_sigma_qs32(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta, near, V,
-                               s0 > 0 ? 1 : 0, &sp));
+        if (o->precision == QSGW_PREC_SPLIT_BF16)
+          CHECK(stage_sigma_qs32_t<Bf16x3>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
+                                           near, V, s0 > 0 ? 1 : 0, &sp));
+        else
+          CHECK(stage_sigma_qs32_t<float>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
+                                          near, V, s0 > 0 ? 1 : 0, &sp));
       } else {
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps,
                              nocc, o->eta, o->precision));

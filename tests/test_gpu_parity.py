@@ -317,8 +317,8 @@ def test_error_paths(q, ctx):
     p = problem(10, 12, 3)
     dB, dC, de = dev(p.B_ao), dev(p.C0), dev(p.eps0)
     with pytest.raises(q.QsgwError) as e:
-        q.qsgw_mo_transform(ctx, dB, dC, precision=q.PREC_SPLIT_BF16)
-    assert e.value.code == q.ERR_UNSUPPORTED
+        q.qsgw_mo_transform(ctx, dB, dC, precision=7)
+    assert e.value.code == q.ERR_INVALID_ARG
     B_mo = q.qsgw_mo_transform(ctx, dB, dC)
     with pytest.raises(q.QsgwError) as e:
         q.qsgw_rpa_build(ctx, B_mo, de, 10)
@@ -373,28 +373,74 @@ def test_fp32_products(q, ctx, shape):
     np.testing.assert_array_equal(Mh, Mh.T)
 
 
+# Split-BF16 products (hi + lo halves, three BF16 products, FP32 accumulation):
+# each operand keeps 16 significant bits, |x - hi - lo| <= 2^-18 |x|, and the
+# dropped lo*lo term is <= 2^-18 |a b|, so one product term is within
+# 3 * 2^-18 of |a b| on top of the FP32 rounding of the inputs and sums.
+X3_UNIT = 3 * 2.0 ** -18
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 2), (37, 53, 9), (130, 260, 17)])
+def test_split_bf16_products(q, ctx, shape):
+    """Casida build and residue product in split-BF16 against FP64, element by
+    element within the split's error bound (sums of absolute terms)."""
+    nbf, naux, nocc = shape
+    log("split-bf16 products", shape)
+    p = problem(*shape)
+    u = 2.0 ** -24
+    ref = O.mo_transform(p.B_ao, p.C0)
+    M_ref, sq_ref = O.rpa_hermitian(ref, p.eps0, nocc)
+    dB, de = dev(ref), dev(p.eps0)
+    M, sq = q.qsgw_rpa_build(ctx, dB, de, nocc, precision=q.PREC_SPLIT_BF16)
+    Mh = host(M)
+    Bt = np.abs(ref[:, :nocc, nocc:].reshape(naux, -1)) * sq_ref[None, :]
+    bound = 4 * (X3_UNIT + (naux + 2) * u) * (Bt.T @ Bt)
+    assert np.all(np.abs(Mh - M_ref) <= 2 * bound + 1e-12 * np.abs(M_ref).max())
+    np.testing.assert_array_equal(Mh, Mh.T)
+    # residues from the FP64 eigenvectors: rho' and w both in split-BF16
+    M64, sq64 = q.qsgw_rpa_build(ctx, dB, de, nocc)
+    Z, Om = q.qsgw_rpa_solve(ctx, M64)
+    w64 = host(q.qsgw_residues(ctx, dB, sq64, Z, Om, nocc))
+    w3 = host(q.qsgw_residues(ctx, dB, sq64, Z, Om, nocc, precision=q.PREC_SPLIT_BF16))
+    np.testing.assert_array_equal(w3, w3.transpose(1, 0, 2))
+    Zh, Omh = host(Z), host(Om)
+    ntr = Omh.size
+    Bt64 = ref[:, :nocc, nocc:].reshape(naux, -1) * sq_ref[None, :]
+    scale = np.sqrt(2.0 / Omh)
+    rho_abs = (np.abs(Bt64) @ np.abs(Zh.reshape(ntr, ntr)).T) * scale[None, :]
+    e_rho = (X3_UNIT + (ntr + 2) * u) * rho_abs
+    absB = np.abs(ref).reshape(naux, nbf * nbf)
+    bound_w = np.sqrt(2.0) * (absB.T @ ((X3_UNIT + (naux + 2) * u) * rho_abs + e_rho))
+    err = np.abs(w3 - w64).reshape(nbf * nbf, ntr)
+    assert np.all(err <= 2 * bound_w + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
 @pytest.mark.parametrize("near_pole,s_block", [(0.0, 0), (1e-9, 0), (1e6, 0), (0.05, 40)])
 @pytest.mark.parametrize("shape", [(24, 96, 5), (70, 200, 11)])
-def test_fp32_iteration_qp_error(q, ctx, shape, near_pole, s_block):
-    """One iteration in FP32 against the FP64 oracle: per-state QP error <= 1 meV,
-    with the default near-pole threshold (0.05 Ha), with every qsGW term on
-    FP32 matrix cores (1e-9), with every term in the FP64 near-pole part (1e6),
-    and with streamed excitation blocks."""
-    log("fp32 iteration", shape, near_pole, s_block)
+def test_fp32_iteration_qp_error(q, ctx, shape, near_pole, s_block, prec):
+    """One iteration in FP32 (or split-BF16) against the FP64 oracle: per-state
+    QP error <= 1 meV, with the default near-pole threshold (0.05 Ha), with
+    every qsGW term on the reduced-precision matrix cores (1e-9), with every
+    term in the FP64 near-pole part (1e6), and with streamed excitation
+    blocks."""
+    log(f"{prec} iteration", shape, near_pole, s_block)
+    precision = q.PREC_FP32 if prec == "fp32" else q.PREC_SPLIT_BF16
     p = make_config("cfg1") if shape == (24, 96, 5) else problem(*shape)
     eta = 1e-3
     h_ref = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
     st = O.qsgw_step(p.B_ao, h_ref, p.C0, p.eps0, p.nocc, eta)
     dB, h, dC, de = _gpu_start(q, ctx, p)
     rc, rep, it = q.qsgw_iterate(ctx, dB, h, p.nocc, de, dC, eta, tol=0.0, max_iter=1,
-                                 precision=q.PREC_FP32, near_pole=near_pole, s_block=s_block)
+                                 precision=precision, near_pole=near_pole, s_block=s_block)
     err = np.abs(host(de) - st["eps"])
-    log(f"  FP32 per-state QP error: max {err.max() * 27211.386:.4f} meV, "
+    log(f"  {prec} per-state QP error: max {err.max() * 27211.386:.4f} meV, "
         f"median {np.median(err) * 27211.386:.5f} meV")
     assert err.max() <= FP32_QP_TOL
 
 
-def test_fp32_refinement_pass():
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_fp32_refinement_pass(prec):
     """Reduced-precision iterations to convergence, then one FP64 iteration
     (refinement pass): the per-state error against the FP64 fixed point stays
     within 1 meV before and does not grow after the FP64 step."""
@@ -410,15 +456,16 @@ def test_fp32_refinement_pass():
     with q.Context() as ctx:
         h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
         out = {}
-        # the FP32 products leave rounding noise of ~1e-8 Ha in the energies,
-        # so the reduced-precision iterations stop at 1e-6 Ha
-        for name, prec, refine, tol in (("fp64", q.PREC_FP64, False, 1e-10),
-                                        ("fp32", q.PREC_FP32, False, 1e-6),
-                                        ("fp32+refine", q.PREC_FP32, True, 1e-6)):
+        # the FP32 products leave rounding noise of ~1e-8 Ha in the energies
+        # (split-BF16 ~1e-7), so the reduced-precision iterations stop at 1e-6 Ha
+        low = q.PREC_FP32 if prec == "fp32" else q.PREC_SPLIT_BF16
+        for name, pr, refine, tol in (("fp64", q.PREC_FP64, False, 1e-10),
+                                      ("fp32", low, False, 1e-6),
+                                      ("fp32+refine", low, True, 1e-6)):
             e, C = e0.clone(), C0.clone()
             Vc = torch.zeros((p.nbf, p.nbf), dtype=torch.float64, device=dev)
             rc, rep, it = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, 1e-3, tol=tol, max_iter=80,
-                                         mix=0.5, Vc=Vc, precision=prec, refine=refine)
+                                         mix=0.5, Vc=Vc, precision=pr, refine=refine)
             print(name, rc, rep["iterations"], rep["max_deps"][-3:], flush=True)
             out[name] = (rc, rep, e.cpu().numpy())
     assert out["fp64"][0] == q.OK
