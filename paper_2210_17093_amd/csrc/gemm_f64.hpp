@@ -89,10 +89,27 @@ struct is_bf16x3<Bf16x3> {
   static constexpr bool value = true;
 };
 
-// hi and lo halves of a split value (see Bf16x3)
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+// hi and lo halves of two split values (see Bf16x3), each pair packed in one
+// 32-bit word (element 0 in the low half): two packed conversions, and hi is
+// widened back to FP32 by placing its bits in the upper half of a word.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16x2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x0, x1}, bf16x2));
+  const float h0 = __builtin_bit_cast(float, hi << 16);
+  const float h1 = __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x0 - h0, x1 - h1}, bf16x2));
+}
+
+// Split-BF16 LDS tiles are [r][k] with unpadded rows of BK values; the
+// 16-byte chunk c (8 k) of row r sits at chunk c ^ x3_swizzle(r).  The
+// swizzle spreads 8 consecutive rows of one chunk (a 16-byte access of 8
+// lanes) over distinct 32-bank groups, and 16 consecutive rows over distinct
+// 64-bank groups; two consecutive rows of one row run also share no bank.
+__device__ __forceinline__ constexpr int x3_swizzle(int r) { return ((r >> 1) + (r >> 3)) & 3; }
+template <int BK>
+__device__ __forceinline__ constexpr int x3_at(int r, int k) {
+  return r * BK + ((((k >> 3) ^ x3_swizzle(r)) << 3) | (k & 7));
 }
 
 // Element (r, k) at p[b*sb + r*sr + k*sk] (strides in elements of the
@@ -214,9 +231,102 @@ struct X3Map {
 // zeros and the caller stores 0): full pair-row tiles load unconditionally
 // and leave the masking to the LDS store, so that the loads of a tile are all
 // in flight together instead of each waiting for its own select.
+// Split-BF16 element map (KB = true): no element is zeroed here.  Loads of
+// rows outside the operand read a clamped, valid element (their products only
+// reach output rows the epilogue drops); k beyond the end of the range is
+// clamped the same way and zeroed by the LDS store of the last k tile.
+template <int BR, int BK, class OP, class R>
+__device__ __forceinline__ void load_tile_kb(const OP& op, int64_t b, int64_t r0, int64_t kbase,
+                                             int64_t kend, int tid, R* v) {
+  typedef TileMap<BR, BK, OP::kContig, true> TM;
+  constexpr int E = TM::E;
+  const int rl = TM::rl(tid);
+  const int kl = TM::kl(tid);
+  const bool kfull = kbase + BK <= kend;
+  const int kv = kfull ? BK : (int)(kend - kbase);  // valid k of the tile (uniform)
+  if constexpr (is_pair_rows_op<OP>::value) {
+    static_assert(OP::kPM * OP::kPK == BR && 256 % BR == 0, "pair block must fill the row tile");
+    typedef typename OP::storage_t S;
+    int64_t m, k;
+    pair_of<OP::kPM, OP::kPK>(op.blocks, r0 / BR, rl, m, k);
+    const bool rok = (m < op.n) && (k < op.n);
+    // a lane outside the pair range reads element (0, 0) of its k slab
+    const uint32_t pofs = rok ? (uint32_t)((m * op.n + k) * (int64_t)sizeof(S)) : 0u;
+    const S* origin = op.p + b * op.sb + kbase * op.sk;
+    if (kfull) {
+      const uint32_t toff = (uint32_t)((int64_t)kl * op.sk * (int64_t)sizeof(S)) + pofs;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const char* sb = reinterpret_cast<const char*>(origin + TM::dk(e) * op.sk);
+        v[e] = (R)*reinterpret_cast<const S*>(sb + toff);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int kk = kl + TM::dk(e);
+        const int kc = kk < kv ? kk : kv - 1;
+        const char* sb = reinterpret_cast<const char*>(origin + (int64_t)kc * op.sk);
+        v[e] = (R)*reinterpret_cast<const S*>(sb + pofs);
+      }
+    }
+  } else if constexpr (is_strided_op<OP>::value) {
+    static_assert(OP::kContig ? (256 % (BK / 4) == 0) : (256 % BR == 0),
+                  "tile shape must divide the block");
+    typedef typename OP::storage_t S;
+    const S* origin = op.p + b * op.sb + r0 * op.sr + kbase * op.sk;
+    const bool full = kfull && (r0 + BR <= op.rows);
+    const uint32_t toff = (uint32_t)(((int64_t)rl * op.sr + (int64_t)kl * op.sk) * (int64_t)sizeof(S));
+    if constexpr (OP::kContig && sizeof(S) == 4 && sizeof(R) == 4) {
+      // Unit-stride FP32 rows whose 4-element runs are 16-byte aligned (uniform
+      // test): one 16-byte load per run of 4 k, a wave covering whole rows.
+      const bool vec = full && op.sk == 1 && (op.sr & 3) == 0 && (op.sb & 3) == 0 &&
+                       (reinterpret_cast<uintptr_t>(op.p) & 15) == 0 && (kbase & 3) == 0;
+      if (vec) {
+#pragma unroll
+        for (int g = 0; g < E / 4; ++g) {
+          const char* sb = reinterpret_cast<const char*>(origin + TM::dr(4 * g) * op.sr);
+          const f32x4 x = *reinterpret_cast<const f32x4*>(sb + toff);
+          v[4 * g] = x[0];
+          v[4 * g + 1] = x[1];
+          v[4 * g + 2] = x[2];
+          v[4 * g + 3] = x[3];
+        }
+        return;
+      }
+    }
+    if (full) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const char* sb = reinterpret_cast<const char*>(origin + TM::dr(e) * op.sr + TM::dk(e) * op.sk);
+        v[e] = (R)*reinterpret_cast<const S*>(sb + toff);
+      }
+    } else {
+      const int rv = (r0 + BR <= op.rows) ? BR : (int)(op.rows - r0);  // valid rows (uniform)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = rl + TM::dr(e), kk = kl + TM::dk(e);
+        const int rc = r < rv ? r : rv - 1, kc = kk < kv ? kk : kv - 1;
+        v[e] = (R)origin[(int64_t)rc * op.sr + (int64_t)kc * op.sk];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kk = kl + TM::dk(e);
+      const int r = rl + TM::dr(e);
+      v[e] = (R)op.get(b, r0 + r, kbase + (kk < kv ? kk : kv - 1));
+    }
+  }
+}
+
 template <int BR, int BK, bool KB, class OP, class R>
 __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
                                           int64_t kend, int tid, R* v, bool& keep) {
+  if constexpr (KB) {
+    keep = true;
+    load_tile_kb<BR, BK>(op, b, r0, kbase, kend, tid, v);
+    return;
+  }
   typedef TileMap<BR, BK, OP::kContig, KB> TM;
   constexpr int E = TM::E;
   keep = true;
@@ -382,13 +492,11 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   // an r-contiguous one is kept [k][r] (pitch BR+1).  Both pitches are odd,
   // which keeps the 16 lanes of an MFMA fragment read on distinct banks.
   // Split-BF16: hi and lo tiles, both [r][k] whatever the global orientation
-  // (a fragment is 8 consecutive k of one row, one 16-byte read), pitch BK+8
-  // (16-byte aligned rows; 8 consecutive rows of a fragment read cover all
-  // banks once).
+  // (a fragment is 8 consecutive k of one row, one 16-byte read), in the
+  // chunk-swizzled layout of x3_at.
   constexpr bool AK = OA::kContig, BKC = OB::kContig;
-  constexpr int PX = BK + 8;
-  constexpr int SZA = X3 ? BM * PX : (AK ? BM * (BK + 1) : BK * (BM + 1));
-  constexpr int SZB = X3 ? BN * PX : (BKC ? BN * (BK + 1) : BK * (BN + 1));
+  constexpr int SZA = X3 ? BM * BK : (AK ? BM * (BK + 1) : BK * (BM + 1));
+  constexpr int SZB = X3 ? BN * BK : (BKC ? BN * (BK + 1) : BK * (BN + 1));
   constexpr int EA = BM * BK / 256;
   constexpr int EB = BN * BK / 256;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -445,39 +553,53 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   typename reg_type<OA>::type ra[EA];
   typename reg_type<OB>::type rb[EB];
   bool keep_a = true, keep_b = true;
+  int kv_next = BK;  // split-BF16: valid k of the k tile held in the prefetch registers
 
   auto gload = [&](int64_t kbase) {
     load_tile<BM, BK, X3>(A, batch, m0, kbase, kb1, tid, ra, keep_a);
     load_tile<BN, BK, X3>(B, batch, n0, kbase, kb1, tid, rb, keep_b);
+    if constexpr (X3) kv_next = kbase + BK <= kb1 ? BK : (int)(kb1 - kbase);
   };
   // Split-BF16 store of one operand's elements (TileMap<.., KB = true>
   // order): runs of consecutive k of one row go out as 16-byte (r-contiguous:
-  // 8 k) or 8-byte (k-contiguous: 4 k) writes to the hi and lo planes.
-  auto sstore_x3 = [&](auto* v, bool keep, LT* hi, LT* lo, auto map_tag) {
+  // 8 k) or 8-byte (k-contiguous: 4 k) writes to the hi and lo planes.  In
+  // the last, partial k tile (kv < BK valid k, uniform) the k beyond the range
+  // are stored as zeros.
+  auto sstore_x3 = [&](auto* v, int kv, LT* hi, LT* lo, auto map_tag) {
     typedef decltype(map_tag) MP;
     constexpr int E = MP::E;
     constexpr int RUN = MP::kc ? 4 : 8;
+    if (kv < BK) {
+      // (the empty asm makes the bound opaque, so that the compares stay in
+      // this rarely taken branch instead of being hoisted into every k tile)
+      int kvo = kv;
+      asm volatile("" : "+s"(kvo));
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (MP::M::kl(tid) + MP::M::dk(e) >= kvo) v[e] = 0;
+    }
 #pragma unroll
     for (int g = 0; g < E / RUN; ++g) {
       const int r = MP::M::rl(tid) + MP::M::dr(g * RUN);
       const int k = MP::M::kl(tid) + MP::M::dk(g * RUN);
-      typedef typename std::conditional<MP::kc, bf16x4, bf16x8>::type V;
-      V h, l;
+      uint32_t h[RUN / 2], l[RUN / 2];
 #pragma unroll
-      for (int u = 0; u < RUN; ++u) {
-        __bf16 a, c;
-        split_bf16(keep ? (float)v[g * RUN + u] : 0.f, a, c);
-        h[u] = a;
-        l[u] = c;
+      for (int u = 0; u < RUN / 2; ++u)
+        split_bf16x2((float)v[g * RUN + 2 * u], (float)v[g * RUN + 2 * u + 1], h[u], l[u]);
+      const int o = x3_at<BK>(r, k);
+      if constexpr (RUN == 8) {
+        *reinterpret_cast<uint4*>(hi + o) = uint4{h[0], h[1], h[2], h[3]};
+        *reinterpret_cast<uint4*>(lo + o) = uint4{l[0], l[1], l[2], l[3]};
+      } else {
+        *reinterpret_cast<uint2*>(hi + o) = uint2{h[0], h[1]};
+        *reinterpret_cast<uint2*>(lo + o) = uint2{l[0], l[1]};
       }
-      *reinterpret_cast<V*>(hi + r * PX + k) = h;
-      *reinterpret_cast<V*>(lo + r * PX + k) = l;
     }
   };
   auto sstore = [&](int buf) {
     if constexpr (X3) {
-      sstore_x3(ra, keep_a, As[2 * buf], As[2 * buf + 1], X3Map<BM, BK, AK>());
-      sstore_x3(rb, keep_b, Bs[2 * buf], Bs[2 * buf + 1], X3Map<BN, BK, BKC>());
+      sstore_x3(ra, kv_next, As[2 * buf], As[2 * buf + 1], X3Map<BM, BK, AK>());
+      sstore_x3(rb, kv_next, Bs[2 * buf], Bs[2 * buf + 1], X3Map<BN, BK, BKC>());
     } else {
 #pragma unroll
       for (int e = 0; e < EA; ++e) {
@@ -513,32 +635,28 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
 #pragma unroll
       for (int ks = 0; ks < BK / 32; ++ks) {
         const int kofs = ks * 32 + 8 * (lane >> 4);
-        bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int o = (wm + i * 16 + (lane & 15)) * PX + kofs;
-          ah[i] = *reinterpret_cast<const bf16x8*>(ah_s + o);
-          al[i] = *reinterpret_cast<const bf16x8*>(al_s + o);
-        }
+        bf16x8 bh[TN], bl[TN];
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          const int o = (wn + j * 16 + (lane & 15)) * PX + kofs;
+          const int o = x3_at<BK>(wn + j * 16 + (lane & 15), kofs);
           bh[j] = *reinterpret_cast<const bf16x8*>(bh_s + o);
           bl[j] = *reinterpret_cast<const bf16x8*>(bl_s + o);
         }
-        // small cross terms first, then hi * hi
+        // one row block of A at a time (fewer live fragments); the TN
+        // accumulators of a row block interleave, so consecutive products
+        // never wait on each other: small cross terms first, then hi * hi
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i) {
+          const int o = x3_at<BK>(wm + i * 16 + (lane & 15), kofs);
+          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ah_s + o);
+          const bf16x8 al = *reinterpret_cast<const bf16x8*>(al_s + o);
 #pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(al[i], bh[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(al, bh[j], acc[i][j]);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah, bl[j], acc[i][j]);
 #pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah[i], bl[j], acc[i][j]);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah[i], bh[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah, bh[j], acc[i][j]);
+        }
       }
     } else {
       const T* as = As[cur];

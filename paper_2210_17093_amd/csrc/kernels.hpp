@@ -105,21 +105,37 @@ struct EpiPairResidue {
   __device__ __forceinline__ void store(int64_t a, int64_t b, int64_t s, double v) const {
     const int64_t i = (a * nbf + b) * ns + s;
     if (w) w[i] = v;
-    if (wh || wh32) {
+    if (wh) {
       const double x = xval(a, b, Omega[s]);
-      const double g = x / (x * x + eta * eta);
-      if (wh) wh[i] = v * g;
-      if (wh32) {
-        wh32[i] = fabs(x) >= thr ? (float)(v * g) : 0.0f;
-        w32[i] = (float)v;
-      }
+      wh[i] = v * (x / (x * x + eta * eta));
     }
+  }
+  // Reduced-precision variants: the FP32 copies, with the pole weight of the
+  // far terms in FP32 (x is formed in FP64, so the weight carries only the
+  // FP32 rounding that its product is rounded to anyway).
+  __device__ __forceinline__ void store32(int64_t a, int64_t b, int64_t s, double v, double om,
+                                          float eta2) const {
+    const int64_t i = (a * nbf + b) * ns + s;
+    const double x = xval(a, b, om);
+    const float xf = (float)x;
+    const float vf = (float)v;
+    const float g = xf * __builtin_amdgcn_rcpf(fmaf(xf, xf, eta2));
+    if (w) w[i] = v;
+    wh32[i] = fabs(x) >= thr ? vf * g : 0.0f;
+    w32[i] = vf;
   }
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
                                              bool) const {
     int64_t m, k;
     pair_of<8, 16>(blocks, r >> 7, (int)(r & 127), m, k);
     if (m >= nbf || k >= nbf || m > k) return;
+    if (wh32) {
+      const double om = Omega[s];
+      const float eta2 = (float)(eta * eta);
+      store32(m, k, s, v, om, eta2);
+      if (m != k) store32(k, m, s, v, om, eta2);
+      return;
+    }
     store(m, k, s, v);
     if (m != k) store(k, m, s, v);
   }
