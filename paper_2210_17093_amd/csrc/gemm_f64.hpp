@@ -168,6 +168,43 @@ struct is_pair_rows_op<OP, decltype((void)OP::kPairRows, void())> {
   static constexpr bool value = OP::kPairRows;
 };
 
+// Operand already split into BF16 halves (the split-BF16 products only), in
+// k-blocks of 8: the 16-byte chunk (r, kb) of plane q (0 = hi, 1 = lo) holds
+// k = 8 kb .. 8 kb + 7 of row r at p + q * ps + (kb * cs + r) * 8 (elements).
+// Every tile is full: the producer pads K to a multiple of the k tile and
+// the rows to cs >= the rows the launch covers, with zeros.
+struct Split8 {
+  static constexpr bool kContig = true;
+  static constexpr bool kSplit8 = true;
+  typedef uint32_t storage_t;  // registers hold the chunks' 32-bit words
+  const uint16_t* p;
+  int64_t cs;  // rows of a k-block slab
+  int64_t ps;  // plane stride (elements)
+  int64_t sb;  // batch stride (elements)
+};
+
+template <class OP, class = void>
+struct is_split8_op {
+  static constexpr bool value = false;
+};
+template <class OP>
+struct is_split8_op<OP, decltype((void)OP::kSplit8, void())> {
+  static constexpr bool value = OP::kSplit8;
+};
+
+// Chunks of a BR x BK split tile held by one of the 256 threads: chunk c is
+// number q = c * 256 + tid, row q % BR, then (k-block, plane) from q / BR,
+// k-block fastest.  With 256 / BR <= BK / 8 the plane is uniform per c.
+template <int BR, int BK>
+struct ChunkMap {
+  static constexpr int C = BR * BK / 1024;  // chunks per thread (two planes)
+  static constexpr int NKB = BK / 8;
+  static_assert(256 % BR == 0 && 256 / BR <= NKB, "split tile shape");
+  __device__ static constexpr int r(int tid) { return tid % BR; }
+  __device__ static constexpr int kb(int tid, int c) { return (c * (256 / BR) + tid / BR) % NKB; }
+  __device__ static constexpr int plane(int c) { return (c * (256 / BR)) / NKB; }
+};
+
 // Register type of an operand's prefetched elements: its storage type for
 // strided and pair-row operands (float copies stay float), double otherwise.
 template <class OP, class = void>
@@ -244,7 +281,20 @@ __device__ __forceinline__ void load_tile_kb(const OP& op, int64_t b, int64_t r0
   const int kl = TM::kl(tid);
   const bool kfull = kbase + BK <= kend;
   const int kv = kfull ? BK : (int)(kend - kbase);  // valid k of the tile (uniform)
-  if constexpr (is_pair_rows_op<OP>::value) {
+  if constexpr (is_split8_op<OP>::value) {
+    typedef ChunkMap<BR, BK> CM;
+    const uint16_t* origin = op.p + b * op.sb + ((kbase >> 3) * op.cs + r0) * 8;
+#pragma unroll
+    for (int c = 0; c < CM::C; ++c) {
+      const char* sb = reinterpret_cast<const char*>(origin + CM::plane(c) * op.ps);
+      const uint32_t off = (uint32_t)(((int64_t)CM::kb(tid, c) * op.cs + CM::r(tid)) * 16);
+      const uint4 x = *reinterpret_cast<const uint4*>(sb + off);
+      v[4 * c] = x.x;
+      v[4 * c + 1] = x.y;
+      v[4 * c + 2] = x.z;
+      v[4 * c + 3] = x.w;
+    }
+  } else if constexpr (is_pair_rows_op<OP>::value) {
     static_assert(OP::kPM * OP::kPK == BR && 256 % BR == 0, "pair block must fill the row tile");
     typedef typename OP::storage_t S;
     int64_t m, k;
@@ -319,14 +369,10 @@ __device__ __forceinline__ void load_tile_kb(const OP& op, int64_t b, int64_t r0
   }
 }
 
-template <int BR, int BK, bool KB, class OP, class R>
-__device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
-                                          int64_t kend, int tid, R* v, bool& keep) {
-  if constexpr (KB) {
-    keep = true;
-    load_tile_kb<BR, BK>(op, b, r0, kbase, kend, tid, v);
-    return;
-  }
+template <int BR, int BK, class OP, class R>
+__device__ __forceinline__ void load_tile_std(const OP& op, int64_t b, int64_t r0, int64_t kbase,
+                                              int64_t kend, int tid, R* v, bool& keep) {
+  constexpr bool KB = false;
   typedef TileMap<BR, BK, OP::kContig, KB> TM;
   constexpr int E = TM::E;
   keep = true;
@@ -404,13 +450,26 @@ __device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, i
   }
 }
 
+template <int BR, int BK, bool KB, class OP, class R>
+__device__ __forceinline__ void load_tile(const OP& op, int64_t b, int64_t r0, int64_t kbase,
+                                          int64_t kend, int tid, R* v, bool& keep) {
+  if constexpr (KB) {
+    keep = true;
+    load_tile_kb<BR, BK>(op, b, r0, kbase, kend, tid, v);
+  } else {
+    load_tile_std<BR, BK>(op, b, r0, kbase, kend, tid, v, keep);
+  }
+}
+
 // Host check: the tile loaders address a thread's elements with one 32-bit
 // byte offset from a uniform origin; it must fit for the operand's strides
 // (BR rows x BK k per tile, 256 threads, element map KB).
 template <class OP>
 inline bool loader_offsets_fit(const OP& op, int BR, int BK = 16, bool KB = false) {
   const uint64_t E = (uint64_t)BR * BK / 256;
-  if constexpr (is_pair_rows_op<OP>::value) {
+  if constexpr (is_split8_op<OP>::value) {
+    return KB && ((uint64_t)(BK / 8 - 1) * (uint64_t)op.cs + BR) * 16 < (1ull << 32);
+  } else if constexpr (is_pair_rows_op<OP>::value) {
     // pair offset plus the lane's k offset
     const uint64_t kl = KB ? BK - E : 256 / BR - 1;
     return ((uint64_t)op.n * (uint64_t)op.n + kl * (uint64_t)op.sk) *
@@ -565,6 +624,16 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   // 8 k) or 8-byte (k-contiguous: 4 k) writes to the hi and lo planes.  In
   // the last, partial k tile (kv < BK valid k, uniform) the k beyond the range
   // are stored as zeros.
+  // Pre-split operands: each chunk goes to its plane as one 16-byte write.
+  auto sstore_split = [&](const uint32_t* v, LT* hi, LT* lo, auto map_tag) {
+    typedef decltype(map_tag) CM;
+#pragma unroll
+    for (int c = 0; c < CM::C; ++c) {
+      LT* dst = CM::plane(c) ? lo : hi;
+      *reinterpret_cast<uint4*>(dst + x3_at<BK>(CM::r(tid), 8 * CM::kb(tid, c))) =
+          uint4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+    }
+  };
   auto sstore_x3 = [&](auto* v, int kv, LT* hi, LT* lo, auto map_tag) {
     typedef decltype(map_tag) MP;
     constexpr int E = MP::E;
@@ -598,8 +667,14 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   };
   auto sstore = [&](int buf) {
     if constexpr (X3) {
-      sstore_x3(ra, kv_next, As[2 * buf], As[2 * buf + 1], X3Map<BM, BK, AK>());
-      sstore_x3(rb, kv_next, Bs[2 * buf], Bs[2 * buf + 1], X3Map<BN, BK, BKC>());
+      if constexpr (is_split8_op<OA>::value)
+        sstore_split(ra, As[2 * buf], As[2 * buf + 1], ChunkMap<BM, BK>());
+      else
+        sstore_x3(ra, kv_next, As[2 * buf], As[2 * buf + 1], X3Map<BM, BK, AK>());
+      if constexpr (is_split8_op<OB>::value)
+        sstore_split(rb, Bs[2 * buf], Bs[2 * buf + 1], ChunkMap<BN, BK>());
+      else
+        sstore_x3(rb, kv_next, Bs[2 * buf], Bs[2 * buf + 1], X3Map<BN, BK, BKC>());
     } else {
 #pragma unroll
       for (int e = 0; e < EA; ++e) {

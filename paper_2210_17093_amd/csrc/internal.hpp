@@ -63,6 +63,8 @@ enum Slot {
   W_RHO32,       // FP32 products: rho' rounded to FP32           [naux][sb] float
   W_BT32,        // FP32 products: Bt rounded to FP32             [naux][ntr] float
   W_Z32,         // FP32 products: eigenvectors of a block, FP32  [sb][ntr] float
+  W_SPLIT_A,     // split-BF16 residue product: B_mo pair rows    [2][kpad/8][pair rows][8] bf16
+  W_SPLIT_B,     // split-BF16 residue product: rho' of a block   [2][kpad/8][sb padded][8] bf16
   W_NSLOTS
 };
 

@@ -92,6 +92,52 @@ __global__ void k_to_f32(const double* in, int64_t n, float* out) {
   if (i < n) out[i] = (float)in[i];
 }
 
+// One thread per chunk (row, k-block): 8 FP64 values rounded to FP32 and
+// split into hi and lo BF16 halves (x = hi + lo to 16 significant bits).
+__device__ __forceinline__ void split_chunk(const double (&x)[8], uint16_t* hi, uint16_t* lo) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_bf16x2((float)x[2 * u], (float)x[2 * u + 1], h[u], l[u]);
+  *reinterpret_cast<uint4*>(hi) = uint4{h[0], h[1], h[2], h[3]};
+  *reinterpret_cast<uint4*>(lo) = uint4{l[0], l[1], l[2], l[3]};
+}
+
+__global__ void k_split_pairs(const double* bmo, const int32_t* blocks, int64_t nblk, int64_t nbf,
+                              int64_t naux, int64_t kpad, uint16_t* out) {
+  const int64_t rows = nblk * 128, nkb = kpad / 8;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * nkb) return;
+  const int64_t r = idx % rows, kb = idx / rows;
+  int64_t m, k;
+  pair_of<8, 16>(blocks, r >> 7, (int)(r & 127), m, k);
+  const bool ok = m < nbf && k < nbf;
+  const int64_t nn = nbf * nbf;
+  double x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t P = kb * 8 + j;
+    x[j] = (ok && P < naux) ? bmo[P * nn + m * nbf + k] : 0.0;
+  }
+  const int64_t o = (kb * rows + r) * 8;
+  split_chunk(x, out + o, out + nkb * rows * 8 + o);
+}
+
+__global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,
+                             int64_t rows_pad, int64_t kpad, uint16_t* out) {
+  const int64_t nkb = kpad / 8;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows_pad * nkb) return;
+  const int64_t r = idx % rows_pad, kb = idx / rows_pad;
+  double x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t k = kb * 8 + j;
+    x[j] = (r < rows && k < K) ? in[k * ld + r] : 0.0;
+  }
+  const int64_t o = (kb * rows_pad + r) * 8;
+  split_chunk(x, out + o, out + nkb * rows_pad * 8 + o);
+}
+
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc,
                             double* c) {
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -292,6 +292,18 @@ __global__ void k_rho_reduce(const double* part, int64_t nz, int64_t rows, int64
 
 // out[i] = (float) in[i]
 __global__ void k_to_f32(const double* in, int64_t n, float* out);
+
+// Split-BF16 operands (Split8 layout, planes hi and lo, k-blocks of 8, K
+// padded with zeros to kpad):
+// rows of the residue product, one per pair (m, k) of the pair blocks
+// (row t * 128 + i of block t), k = the auxiliary index P of B_mo[P][m][k];
+// pairs outside the N x N range are zero.
+__global__ void k_split_pairs(const double* bmo, const int32_t* blocks, int64_t nblk, int64_t nbf,
+                              int64_t naux, int64_t kpad, uint16_t* out);
+// rows r < rows_pad of a [K][ld] matrix read as (r, k) = in[k * ld + r]
+// (r < rows, k < K; zero elsewhere).
+__global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,
+                             int64_t rows_pad, int64_t kpad, uint16_t* out);
 // c_P = sum_{i<nocc} B_mo[P][i][i]
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc, double* c);
 // J_mn = 2 sum_P c_P B_mo[P][m][n]

@@ -104,14 +104,34 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
                      const double* Bt, const double* Z, const double* Omega, int64_t s0, int64_t ns,
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
                      double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
-                     const float* B_mo32 = nullptr, const float* Bt32_in = nullptr) {
-  // The FP32 and split-BF16 variants read FP32 copies of B_mo and rho' in the
-  // residue product (half the operand bytes); rounding them is what their
-  // matrix cores do anyway.
+                     const float* B_mo32 = nullptr, const float* Bt32_in = nullptr,
+                     bool reuse_split = false) {
+  // The FP32 variant reads FP32 copies of B_mo and rho' in the residue
+  // product (half the operand bytes); rounding them is what its matrix cores
+  // do anyway.  The split-BF16 variant reads them split into BF16 halves in
+  // k-blocks of 8 (the same bytes), made once per B_mo (reuse_split: the
+  // split of B_mo made for an earlier block of the same iteration is current).
   constexpr bool f32 = !std::is_same<CT, double>::value;
+  constexpr bool x3 = std::is_same<CT, Bf16x3>::value;
   float* rho32 = nullptr;
   const float* Bt32 = Bt32_in;
   float* Z32 = nullptr;
+  const int64_t kpad = ((naux + 31) / 32) * 32, ns_pad = ((ns + 127) / 128) * 128;
+  const int32_t* blocks = nullptr;
+  int64_t nblk = 0;
+  CHECK(pair_blocks(c, nbf, &blocks, &nblk));
+  uint16_t *splitA = nullptr, *splitB = nullptr;
+  if (x3) {
+    CHECK(ws_get(c, W_SPLIT_A, (size_t)(2 * kpad * nblk * 128), &splitA));
+    CHECK(ws_get(c, W_SPLIT_B, (size_t)(2 * kpad * ns_pad), &splitB));
+    if (!reuse_split) {
+      SPAN_OPEN(sp, kKW);
+      hipLaunchKernelGGL(k_split_pairs, dim3(blocks_for(nblk * 128 * (kpad / 8))), dim3(256), 0,
+                         c->stream, B_mo, blocks, nblk, nbf, naux, kpad, splitA);
+      CHECK(launch_check(c, "k_split_pairs"));
+      SPAN_CLOSE(sp);
+    }
+  }
   if (f32) {
     if (!Bt32) {
       float* b = nullptr;
@@ -125,8 +145,8 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(ns * ntr)), dim3(256), 0, c->stream, Z + s0 * ntr,
                        ns * ntr, Z32);
     CHECK(launch_check(c, "k_to_f32"));
-    CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
-    if (!B_mo32) {
+    if (!x3) CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
+    if (!B_mo32 && !x3) {
       float* b32 = nullptr;
       CHECK(ws_get(c, W_BMO32, (size_t)(naux * nbf * nbf), &b32));
       hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * nbf * nbf)), dim3(256), 0, c->stream, B_mo,
@@ -166,19 +186,26 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       E.rho32 = rho32;
       CHECK(rho_gemm(E, SplitPlan{0, 1}));
     }
+    if (x3) {
+      hipLaunchKernelGGL(k_split_cols, dim3(blocks_for(ns_pad * (kpad / 8))), dim3(256), 0,
+                         c->stream, rho, ns, ns, naux, ns_pad, kpad, splitB);
+      CHECK(launch_check(c, "k_split_cols"));
+    }
     SPAN_CLOSE(sp);
   }
   {
     const int64_t nn = nbf * nbf;
-    const int32_t* blocks = nullptr;
-    int64_t nblk = 0;
-    CHECK(pair_blocks(c, nbf, &blocks, &nblk));
     EpiPairResidue E{w, wh, blocks, eps, Omega + s0, nbf, nocc, ns, eta};
     E.wh32 = wh32;
     E.w32 = w32;
     E.thr = thr;
     SPAN_OPEN(sp, kKW);
-    if constexpr (f32) {
+    if constexpr (x3) {
+      const int64_t rows = nblk * 128;
+      Split8 A{splitA, rows, kpad * rows, 0};
+      Split8 B{splitB, ns_pad, kpad * ns_pad, 0};
+      CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E, rows, ns, kpad, 1)));
+    } else if constexpr (f32) {
       // k tiles of 32: twice the matrix-core work per barrier and per prefetch
       PairRows<8, 16, float> A{B_mo32, nn, 0, nbf, blocks};
       Strided<false, float> B{rho32, 1, ns, 0, ns};
@@ -198,13 +225,14 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    double* rho, double* w, Spans* sp = nullptr, double* wh = nullptr,
                    const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
                    int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
-                   double thr = 0.0, const float* B_mo32 = nullptr, const float* Bt32 = nullptr) {
+                   double thr = 0.0, const float* B_mo32 = nullptr, const float* Bt32 = nullptr,
+                   bool reuse_split = false) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
   if (prec == QSGW_PREC_SPLIT_BF16)
     return stage_residues_t<Bf16x3>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
+                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, reuse_split);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta);
 }
@@ -684,7 +712,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   CHECK(ws_get(c, W_SCAL, 8, &scal));
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
   float* Bmo32 = nullptr;
-  if (fp32) {
+  if (o->precision == QSGW_PREC_FP32) {  // (the split-BF16 residue product reads split copies)
     CHECK(ws_get(c, W_BMO32, (size_t)(naux * nn), &Bmo32));
     float* r32 = nullptr;
     CHECK(ws_get(c, W_RHO32, (size_t)(naux * sb), &r32));
@@ -774,7 +802,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
         double* w64 = (it == 0 && st->diag) ? w : nullptr;
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
                              eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
-                             static_cast<const float*>(c->ws[W_BT32].p)));
+                             static_cast<const float*>(c->ws[W_BT32].p), s0 > 0));
         CHECK(sp.close());
         CHECK(sp.open(kStageSigma));
         if (o->precision == QSGW_PREC_SPLIT_BF16)

@@ -8,10 +8,11 @@ the median of `reps` iterations of that product's own HIP-event time.  The
 fastest table per workload goes to tiles.json next to this file, which
 bench.py applies to its workload.
 
-    python -m paper_2210_17093_amd.tune cfg2 cfg2:fp32 cfg4 [--reps 3]
+    python -m paper_2210_17093_amd.tune cfg2 cfg2:fp32 cfg2:bf16x3 cfg4 [--reps 3]
 
 A workload name may carry the variant (":fp32" for the FP32 matrix-core
-products); the batched workload is tuned in its FP32 variant.
+products, ":bf16x3" for the split-BF16 ones); the batched workload is tuned
+in its FP32 variant.
 """
 from __future__ import annotations
 
@@ -112,7 +113,7 @@ def batched_timer(name):
 
 def tune(name, reps=3):
     base, _, variant = name.partition(":")
-    prec = q.PREC_FP32 if variant == "fp32" else q.PREC_FP64
+    prec = {"fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}.get(variant, q.PREC_FP64)
     ctx, run = batched_timer(base) if base == "cfg4" else single_timer(base, prec)
     best = dict(DEFAULTS)
     run(spec_of(best))  # warm-up
@@ -145,7 +146,7 @@ def tune(name, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workloads", nargs="+",
-                    choices=("cfg1", "cfg2", "cfg1:fp32", "cfg2:fp32", "cfg4"))
+                    choices=("cfg1", "cfg2", "cfg1:fp32", "cfg2:fp32", "cfg2:bf16x3", "cfg4"))
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args()
