@@ -254,6 +254,17 @@ struct TileMap {
   }
 };
 
+// Epilogues with a pass<ROWS, BN>(r0, n0, Cs, ldc, tid) member that takes one
+// staged pass of the tile at a time.
+template <class E, class = void>
+struct has_pass_hook {
+  static constexpr bool value = false;
+};
+template <class E>
+struct has_pass_hook<E, decltype((void)E::kPassHook, void())> {
+  static constexpr bool value = E::kPassHook;
+};
+
 // Element map of a split-BF16 operand tile, as a tag for the LDS store.
 template <int BR, int BK, bool KC>
 struct X3Map {
@@ -775,16 +786,23 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
             Cs[(i * 16 + MM::row(lane, q)) * LDC + wn + j * 16 + (lane & 15)] = (double)acc[i][j][q];
     }
     __syncthreads();
-    for (int idx = tid; idx < WM * BN; idx += 256) {
-      const int row = idx / BN, col = idx - (idx / BN) * BN;
-      const int64_t m = m0 + pass * WM + row;
-      const int64_t n = n0 + col;
-      if (m < M && n < N) {
-        const double v = Cs[row * LDC + col];
-        if (TRI) {
-          if (m <= n) epi(batch, split, m, n, v, m != n);
-        } else {
-          epi(batch, split, m, n, v, false);
+    if constexpr (has_pass_hook<EPI>::value) {
+      // epilogues that take a whole staged pass (rows m0 + pass WM .., all
+      // columns of the tile; they check their own ranges)
+      static_assert(!TRI, "pass epilogues of full tiles");
+      epi.template pass<WM, BN>(m0 + pass * WM, n0, Cs, LDC, tid);
+    } else {
+      for (int idx = tid; idx < WM * BN; idx += 256) {
+        const int row = idx / BN, col = idx - (idx / BN) * BN;
+        const int64_t m = m0 + pass * WM + row;
+        const int64_t n = n0 + col;
+        if (m < M && n < N) {
+          const double v = Cs[row * LDC + col];
+          if (TRI) {
+            if (m <= n) epi(batch, split, m, n, v, m != n);
+          } else {
+            epi(batch, split, m, n, v, false);
+          }
         }
       }
     }

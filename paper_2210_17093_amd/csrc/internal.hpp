@@ -65,6 +65,8 @@ enum Slot {
   W_Z32,         // FP32 products: eigenvectors of a block, FP32  [sb][ntr] float
   W_SPLIT_A,     // split-BF16 residue product: B_mo pair rows    [2][kpad/8][pair rows][8] bf16
   W_SPLIT_B,     // split-BF16 residue product: rho' of a block   [2][kpad/8][sb padded][8] bf16
+  W_SPLIT_W,     // split-BF16 qsGW product: w and wh of a block  [2][2][kfar/8][nbf padded][8] bf16
+  W_NEARMASK,    // split-BF16 qsGW product: near-pole (k, s)     [nbf][sb padded to 8] byte
   W_NSLOTS
 };
 
@@ -243,8 +245,8 @@ inline SplitPlan sigma_split(const Tiles& tl, int64_t nbf, int64_t ns) {
 // K <= kFp32MaxK), near-pole part in FP64 over compacted columns, one 64-row
 // tile of m at a time, in `near` extra partial slices.
 constexpr double kNearPoleDefault = 0.05;  // Ha
-inline SplitPlan sigma_split32(const Tiles& tl, int64_t nbf, int64_t ns) {
-  const int64_t K = nbf * ns;
+// (K = the product's k length: nbf * ns, or x3_kfar for split operands)
+inline SplitPlan sigma_split32(const Tiles& tl, int64_t nbf, int64_t K) {
   const int64_t t = tiles_of(tl.shape[TU_SIGMA], nbf, nbf);
   int64_t want = splits_for(t, K, tl.sigma_target);
   const int64_t need = (K + kFp32MaxK - 1) / kFp32MaxK;
@@ -256,8 +258,15 @@ inline int64_t near_slices_max(int64_t nbf) {
   const int64_t z = (2048 + t * t - 1) / (t * t);
   return z < 1 ? 1 : z;
 }
-inline int64_t sigma_slices(const Tiles& tl, int64_t nbf, int64_t ns, bool fp32) {
-  return fp32 ? sigma_split32(tl, nbf, ns).nz + near_slices_max(nbf) : sigma_split(tl, nbf, ns).nz;
+// k length of the split-BF16 qsGW product: k index j = k * nsp + s with ns
+// padded to nsp (a multiple of 8), then to a multiple of the k tile (32).
+inline int64_t x3_kfar(int64_t nbf, int64_t ns) {
+  const int64_t nsp = (ns + 7) / 8 * 8;
+  return (nbf * nsp + 31) / 32 * 32;
+}
+inline int64_t sigma_slices(const Tiles& tl, int64_t nbf, int64_t ns, bool fp32, bool x3 = false) {
+  if (!fp32) return sigma_split(tl, nbf, ns).nz;
+  return sigma_split32(tl, nbf, x3 ? x3_kfar(nbf, ns) : nbf * ns).nz + near_slices_max(nbf);
 }
 
 // rho product: tiles of the naux x ns output, K = ntr; split only when the

@@ -122,6 +122,24 @@ __global__ void k_split_pairs(const double* bmo, const int32_t* blocks, int64_t 
   split_chunk(x, out + o, out + nkb * rows * 8 + o);
 }
 
+__global__ void k_zero_u16(uint16_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_near_mask(const int64_t* lo, const int64_t* cnt, int64_t ntiles, int64_t nbf,
+                            int64_t nsp, uint8_t* mask) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * nsp) return;
+  const int64_t k = idx / nsp, s = idx - k * nsp;
+  uint8_t near = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t a = lo[t * nbf + k];
+    near |= (s >= a && s < a + cnt[t * nbf + k]) ? 1 : 0;
+  }
+  mask[idx] = near;
+}
+
 __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,
                              int64_t rows_pad, int64_t kpad, uint16_t* out) {
   const int64_t nkb = kpad / 8;

@@ -141,6 +141,97 @@ struct EpiPairResidue {
   }
 };
 
+// Split-BF16 variant of the residue epilogue.  For each pair (a, b) in
+// {(m, k), (k, m)} and excitation s it writes
+//   w[a][b][s] = w in FP64 if w is set,
+//   w32[a][b][s] = w in FP32 where nearmask[b][s] is set (the near-pole part
+//                  of the qsGW product reads these entries only),
+// and the qsGW product's operands in the Split8 layout (rows a, k index
+// j = b * nsp + s, nsp = ns rounded up to 8, s >= ns stored as zero):
+//   ws  = w split into BF16 halves,
+//   whs = w Re 1/(x -+ i eta) split the same way, zero where |x| < thr (those
+//         terms are summed in FP64 apart), x = eps_a - eps_b +- Omega_s.
+// It runs on whole staged passes (kPassHook): 64 pair rows (4 values of m x
+// 16 of k of one pair block) by the tile's columns, eight excitations (one
+// 16-byte chunk per plane) per work item, with the items ordered so that the
+// chunks of consecutive threads are adjacent in memory (consecutive a).
+struct EpiPairResidueX3 {
+  static constexpr bool kPassHook = true;
+  double* w;  // nullptr: not written
+  float* w32;
+  const uint8_t* nearmask;  // [nbf][nsp]
+  uint16_t* ws;
+  uint16_t* whs;
+  int64_t cs, ps, nsp;  // Split8 rows per k-block slab, plane stride, padded ns
+  const int32_t* blocks;
+  const double* eps;
+  const double* Omega;  // the block's excitations
+  int64_t nbf, nocc, ns;
+  double eta, thr;
+  __device__ __forceinline__ void put(int64_t a, int64_t b, int64_t s0, const double* v) const {
+    const double ea = eps[a] - eps[b];
+    const double sg = b < nocc ? 1.0 : -1.0;
+    const float eta2 = (float)(eta * eta);
+    const uint64_t near8 = *reinterpret_cast<const uint64_t*>(nearmask + b * nsp + s0);
+    float wv[8], hv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t s = s0 + u;
+      const bool ok = s < ns;
+      const double x = ok ? ea + sg * Omega[s] : 1.0;
+      const float xf = (float)x;
+      const float vf = ok ? (float)v[u] : 0.0f;
+      const float g = xf * __builtin_amdgcn_rcpf(fmaf(xf, xf, eta2));
+      wv[u] = vf;
+      hv[u] = fabs(x) >= thr ? vf * g : 0.0f;
+      if (ok) {
+        const int64_t i = (a * nbf + b) * ns + s;
+        if ((near8 >> (8 * u)) & 0xff) w32[i] = vf;
+        if (w) w[i] = v[u];
+      }
+    }
+    const int64_t o = ((b * nsp + s0) / 8 * cs + a) * 8;
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) split_bf16x2(wv[2 * u], wv[2 * u + 1], h[u], l[u]);
+    *reinterpret_cast<uint4*>(ws + o) = uint4{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<uint4*>(ws + ps + o) = uint4{l[0], l[1], l[2], l[3]};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) split_bf16x2(hv[2 * u], hv[2 * u + 1], h[u], l[u]);
+    *reinterpret_cast<uint4*>(whs + o) = uint4{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<uint4*>(whs + ps + o) = uint4{l[0], l[1], l[2], l[3]};
+  }
+  // pair rows r0 .. r0 + ROWS - 1, columns n0 .. n0 + BN - 1 at Cs[row * ldc + col]
+  template <int ROWS, int BN>
+  __device__ __forceinline__ void pass(int64_t r0, int64_t n0, const double* Cs, int ldc,
+                                       int tid) const {
+    static_assert(ROWS == 64 && BN % 8 == 0, "pair-block passes of 4 x 16 pairs");
+    const int32_t bk = blocks[r0 >> 7];
+    const int64_t mbase = (int64_t)(bk >> 16) * 8 + (r0 & 127) / 16, kbase = (int64_t)(bk & 0xffff) * 16;
+    constexpr int NSC = BN / 8, ITEMS = 64 * NSC;
+    // (m, k): four consecutive m per (k, chunk)
+    for (int q = tid; q < ITEMS; q += 256) {
+      const int mo = q & 3, ko = (q >> 2) & 15, sc = q >> 6;
+      const int64_t m = mbase + mo, k = kbase + ko, s0 = n0 + 8 * sc;
+      if (m >= nbf || k >= nbf || m > k || s0 >= ns) continue;
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Cs[(mo * 16 + ko) * ldc + 8 * sc + u];
+      put(m, k, s0, v);
+    }
+    // (k, m), m < k: sixteen consecutive k per (m, chunk)
+    for (int q = tid; q < ITEMS; q += 256) {
+      const int ko = q & 15, mo = (q >> 4) & 3, sc = q >> 6;
+      const int64_t m = mbase + mo, k = kbase + ko, s0 = n0 + 8 * sc;
+      if (m >= nbf || k >= nbf || m >= k || s0 >= ns) continue;
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Cs[(mo * 16 + ko) * ldc + 8 * sc + u];
+      put(k, m, s0, v);
+    }
+  }
+};
+
 // Near-pole terms of the qsGW product for one 64-row tile of m, over a
 // compacted list of (k, s) columns (ktab, stab) that holds every pair with
 // some m of the tile within thr of a pole:
@@ -300,6 +391,11 @@ __global__ void k_to_f32(const double* in, int64_t n, float* out);
 // pairs outside the N x N range are zero.
 __global__ void k_split_pairs(const double* bmo, const int32_t* blocks, int64_t nblk, int64_t nbf,
                               int64_t naux, int64_t kpad, uint16_t* out);
+__global__ void k_zero_u16(uint16_t* p, int64_t n);
+// mask[k][s] (s < nsp) = 1 where (k, s) is in the near-pole list of some
+// 64-row tile (s in [lo, lo + cnt) of k_near_ranges), else 0.
+__global__ void k_near_mask(const int64_t* lo, const int64_t* cnt, int64_t ntiles, int64_t nbf,
+                            int64_t nsp, uint8_t* mask);
 // rows r < rows_pad of a [K][ld] matrix read as (r, k) = in[k * ld + r]
 // (r < rows, k < K; zero elsewhere).
 __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,

@@ -6,6 +6,69 @@
 
 namespace {
 
+// Near-pole columns of the reduced-precision qsGW product for one excitation
+// block: for each 64-row tile t of m, the (k, s) with Omega_s inside the
+// window where some m of the tile may be within thr of a pole (k_near_ranges),
+// compacted into ktab / stab at base_h[t] (tot_h[t] columns).
+struct NearLists {
+  int64_t *lo = nullptr, *cnt = nullptr;  // device [ntiles][nbf]: the s range of (t, k)
+  const int32_t *ktab = nullptr, *stab = nullptr;
+  std::vector<int64_t> tot_h, base_h;
+  int64_t lmax = 0, ltot = 0, nt = 0;
+};
+
+int near_lists(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* eps,
+               const double* Omega, double thr, NearLists* nl) {
+  const int64_t nt = (nbf + 63) / 64;
+  int64_t* nearws = nullptr;
+  CHECK(ws_get(c, W_NEAR, (size_t)(3 * nt * nbf + 2 * nt), &nearws));
+  int64_t *lo = nearws, *cnt = lo + nt * nbf, *off = cnt + nt * nbf, *tot = off + nt * nbf,
+          *base = tot + nt;
+  hipLaunchKernelGGL(k_near_ranges, dim3(blocks_for(nt * nbf)), dim3(256), 0, c->stream, eps, Omega,
+                     nbf, nocc, ns, thr, nt, lo, cnt);
+  hipLaunchKernelGGL(k_near_offsets, dim3((unsigned)nt), dim3(256), 0, c->stream, cnt, nbf, nt, off,
+                     tot, base);
+  hipLaunchKernelGGL(k_near_bases, dim3(1), dim3(64), 0, c->stream, tot, nt, base);
+  CHECK(launch_check(c, "near-pole ranges"));
+  nl->tot_h.assign(nt, 0);
+  nl->base_h.assign(nt, 0);
+  HIP_TRY(c, hipMemcpyAsync(nl->tot_h.data(), tot, nt * sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(nl->base_h.data(), base, nt * sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  nl->lmax = nl->ltot = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    nl->lmax = nl->tot_h[t] > nl->lmax ? nl->tot_h[t] : nl->lmax;
+    nl->ltot += nl->tot_h[t];
+  }
+  int32_t* tab = nullptr;
+  CHECK(ws_get(c, W_NEARTAB, (size_t)(2 * nl->ltot + 2), &tab));
+  if (nl->ltot > 0) {
+    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)(nt * nbf)), dim3(256), 0, c->stream, lo, cnt,
+                       off, base, nbf, nt, tab, tab + nl->ltot + 1);
+    CHECK(launch_check(c, "k_near_fill"));
+  }
+  nl->lo = lo;
+  nl->cnt = cnt;
+  nl->ktab = tab;
+  nl->stab = tab + nl->ltot + 1;
+  nl->nt = nt;
+  return QSGW_OK;
+}
+
+// Split-BF16 operands of the qsGW product for one excitation block, written by
+// the residue epilogue (EpiPairResidueX3): w and its pole-weighted copy in the
+// Split8 layout, rows m < nbf of cs, k index j = k * nsp + s, K padded with
+// zero chunks to kfar (a multiple of 32).
+struct X3Out {
+  uint16_t* ws;
+  uint16_t* whs;
+  const uint8_t* nearmask;  // [nbf][nsp]: where the FP32 residues are needed
+  int64_t cs, nsp, kfar;
+  int64_t plane() const { return kfar * cs; }
+};
+
 // ------------------------------------------------------------- stages ----
 
 // Eq. (16): T = B_ao C (one GEMM over all P), B_mo[P] = C^T T[P] (batched
@@ -105,7 +168,7 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
                      double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
                      const float* B_mo32 = nullptr, const float* Bt32_in = nullptr,
-                     bool reuse_split = false) {
+                     bool reuse_split = false, const X3Out* x3o = nullptr) {
   // The FP32 variant reads FP32 copies of B_mo and rho' in the residue
   // product (half the operand bytes); rounding them is what its matrix cores
   // do anyway.  The split-BF16 variant reads them split into BF16 halves in
@@ -204,7 +267,14 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       const int64_t rows = nblk * 128;
       Split8 A{splitA, rows, kpad * rows, 0};
       Split8 B{splitB, ns_pad, kpad * ns_pad, 0};
-      CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E, rows, ns, kpad, 1)));
+      if (x3o) {
+        EpiPairResidueX3 E3{w,      w32,     x3o->nearmask, x3o->ws, x3o->whs,   x3o->cs,
+                            x3o->plane(), x3o->nsp, blocks,  eps,     Omega + s0, nbf,
+                            nocc,   ns,      eta,     thr};
+        CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E3, rows, ns, kpad, 1)));
+      } else {
+        CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E, rows, ns, kpad, 1)));
+      }
     } else if constexpr (f32) {
       // k tiles of 32: twice the matrix-core work per barrier and per prefetch
       PairRows<8, 16, float> A{B_mo32, nn, 0, nbf, blocks};
@@ -226,13 +296,13 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
                    int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
                    double thr = 0.0, const float* B_mo32 = nullptr, const float* Bt32 = nullptr,
-                   bool reuse_split = false) {
+                   bool reuse_split = false, const X3Out* x3o = nullptr) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
   if (prec == QSGW_PREC_SPLIT_BF16)
     return stage_residues_t<Bf16x3>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, reuse_split);
+                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, reuse_split, x3o);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta);
 }
@@ -246,43 +316,27 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
 template <class PT>
 int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const float* wh32,
                        const float* w32, const double* eps, const double* Omega, double eta,
-                       double thr, double* V, int accumulate, Spans* spn) {
-  const int64_t nn = nbf * nbf, K = nbf * ns, nt = (nbf + 63) / 64;
+                       double thr, double* V, int accumulate, Spans* spn,
+                       const X3Out* x3o = nullptr, const NearLists* nl = nullptr) {
+  // (split-BF16 with split operands: the far product runs over the padded k
+  // index of the Split8 layout, kfar >= nbf * ns)
+  const int64_t nn = nbf * nbf, K = x3o ? x3o->kfar : nbf * ns, nt = (nbf + 63) / 64;
   if (K >= (int64_t)1 << 31) return fail(c, QSGW_ERR_INVALID_ARG, "sigma: nbf * ns must stay below 2^31");
-  SplitPlan spf = sigma_split32(c->tiles, nbf, ns);
+  SplitPlan spf = sigma_split32(c->tiles, nbf, K);
   if (spf.nz > 1) {  // the far product runs k tiles of 32: chunks are multiples of 32
     spf.kchunk = ((spf.kchunk + 31) / 32) * 32;
     spf.nz = (K + spf.kchunk - 1) / spf.kchunk;
   }
-  int64_t* nearws = nullptr;
-  CHECK(ws_get(c, W_NEAR, (size_t)(3 * nt * nbf + 2 * nt), &nearws));
-  int64_t *lo = nearws, *cnt = lo + nt * nbf, *off = cnt + nt * nbf, *tot = off + nt * nbf,
-          *base = tot + nt;
+  NearLists own;
   SPAN_OPEN(spn, kKSigma);
-  hipLaunchKernelGGL(k_near_ranges, dim3(blocks_for(nt * nbf)), dim3(256), 0, c->stream, eps, Omega,
-                     nbf, nocc, ns, thr, nt, lo, cnt);
-  hipLaunchKernelGGL(k_near_offsets, dim3((unsigned)nt), dim3(256), 0, c->stream, cnt, nbf, nt, off,
-                     tot, base);
-  hipLaunchKernelGGL(k_near_bases, dim3(1), dim3(64), 0, c->stream, tot, nt, base);
-  CHECK(launch_check(c, "near-pole ranges"));
-  std::vector<int64_t> tot_h(nt), base_h(nt);
-  HIP_TRY(c, hipMemcpyAsync(tot_h.data(), tot, nt * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(base_h.data(), base, nt * sizeof(int64_t), hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  int64_t lmax = 0, ltot = 0;
-  for (int64_t t = 0; t < nt; ++t) {
-    lmax = tot_h[t] > lmax ? tot_h[t] : lmax;
-    ltot += tot_h[t];
+  if (!nl) {
+    CHECK(near_lists(c, nbf, nocc, ns, eps, Omega, thr, &own));
+    nl = &own;
   }
-  int32_t* tab = nullptr;
-  CHECK(ws_get(c, W_NEARTAB, (size_t)(2 * ltot + 2), &tab));
-  int32_t *ktab = tab, *stab = tab + ltot + 1;
-  if (ltot > 0) {
-    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)(nt * nbf)), dim3(256), 0, c->stream, lo, cnt,
-                       off, base, nbf, nt, ktab, stab);
-    CHECK(launch_check(c, "k_near_fill"));
-  }
+  const std::vector<int64_t>& tot_h = nl->tot_h;
+  const std::vector<int64_t>& base_h = nl->base_h;
+  const int64_t lmax = nl->lmax;
+  const int32_t *ktab = nl->ktab, *stab = nl->stab;
   int64_t zn = near_slices_max(nbf);
   const int64_t zcap = (lmax + 255) / 256;
   if (zn > zcap) zn = zcap < 1 ? 1 : zcap;
@@ -291,7 +345,34 @@ int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const
   double* npart = part + spf.nz * nn;
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(zn * nn)), dim3(256), 0, c->stream, npart, zn * nn, 0.0);
   CHECK(launch_check(c, "k_fill"));
-  {
+  if constexpr (std::is_same<PT, Bf16x3>::value) {
+    if (x3o) {
+      // zero k chunks beyond nbf * nsp (the residue epilogue writes the rest)
+      const int64_t kb0 = nbf * x3o->nsp / 8, tail = (x3o->kfar / 8 - kb0) * x3o->cs * 8;
+      if (tail > 0) {
+        uint16_t* t[4] = {x3o->ws, x3o->ws + x3o->plane(), x3o->whs, x3o->whs + x3o->plane()};
+        for (uint16_t* q : t) {
+          hipLaunchKernelGGL(k_zero_u16, dim3(blocks_for(tail)), dim3(256), 0, c->stream,
+                             q + kb0 * x3o->cs * 8, tail);
+        }
+        CHECK(launch_check(c, "k_zero_u16"));
+      }
+      Split8 A{x3o->whs, x3o->cs, x3o->plane(), 0};
+      Split8 B{x3o->ws, x3o->cs, x3o->plane(), 0};
+      EpiStore E{part, nbf, 0, nn, 1.0};
+      switch (c->tiles.shape[TU_SIGMA]) {
+        case SH_64x64:
+          CHECK((gemm_t<PT, 64, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, spf)));
+          break;
+        case SH_128x128:
+          CHECK((gemm_t<PT, 128, 128, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, spf)));
+          break;
+        default:
+          CHECK((gemm_t<PT, 128, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, spf)));
+      }
+    }
+  }
+  if (!x3o) {
     Strided<true, float> A{wh32, K, 1, 0, nbf};
     Strided<true, float> B{w32, K, 1, 0, nbf};
     EpiStore E{part, nbf, 0, nn, 1.0};
@@ -722,10 +803,17 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     double* part = nullptr;
     int64_t nz = exchange_split(c->tiles, nbf, naux, nocc).nz;
     for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
-      const int64_t z = sigma_slices(c->tiles, nbf, (ntr - s0) < sb ? (ntr - s0) : sb, fp32);
+      const int64_t z = sigma_slices(c->tiles, nbf, (ntr - s0) < sb ? (ntr - s0) : sb, fp32,
+                                     o->precision == QSGW_PREC_SPLIT_BF16);
       nz = z > nz ? z : nz;
     }
     CHECK(ws_get(c, W_PART, (size_t)(nz * nn), &part));
+    if (o->precision == QSGW_PREC_SPLIT_BF16) {
+      uint16_t* u = nullptr;  // the qsGW product's split operands, sized for the largest block
+      CHECK(ws_get(c, W_SPLIT_W, (size_t)(4 * x3_kfar(nbf, sb) * ((nbf + 127) / 128 * 128)), &u));
+      uint8_t* mk = nullptr;  // near-pole mask of a block
+      CHECK(ws_get(c, W_NEARMASK, (size_t)(nbf * ((sb + 7) / 8 * 8)), &mk));
+    }
     double* dummy = nullptr;
     CHECK(ws_get(c, W_J, (size_t)nn, &dummy));
     CHECK(ws_get(c, W_CP, (size_t)naux, &dummy));
@@ -800,14 +888,34 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
         float* wh32 = reinterpret_cast<float*>(wh);
         float* w32 = wh32 + nn * ns;
         double* w64 = (it == 0 && st->diag) ? w : nullptr;
+        // split-BF16: the residue epilogue also writes the qsGW product's split operands
+        X3Out x3o{};
+        NearLists nl;
+        const bool x3 = o->precision == QSGW_PREC_SPLIT_BF16;
+        if (x3) {
+          x3o.cs = (nbf + 127) / 128 * 128;
+          x3o.nsp = (ns + 7) / 8 * 8;
+          x3o.kfar = x3_kfar(nbf, ns);
+          x3o.ws = static_cast<uint16_t*>(c->ws[W_SPLIT_W].p);
+          x3o.whs = x3o.ws + 2 * x3o.plane();
+          // the near-pole columns first: the residue epilogue keeps FP32
+          // residues only where the near-pole part will read them
+          uint8_t* mk = static_cast<uint8_t*>(c->ws[W_NEARMASK].p);
+          CHECK(near_lists(c, nbf, nocc, ns, eps, Omega + s0, near, &nl));
+          hipLaunchKernelGGL(k_near_mask, dim3(blocks_for(nbf * x3o.nsp)), dim3(256), 0, c->stream,
+                             nl.lo, nl.cnt, nl.nt, nbf, x3o.nsp, mk);
+          CHECK(launch_check(c, "k_near_mask"));
+          x3o.nearmask = mk;
+        }
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
                              eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
-                             static_cast<const float*>(c->ws[W_BT32].p), s0 > 0));
+                             static_cast<const float*>(c->ws[W_BT32].p), s0 > 0,
+                             x3 ? &x3o : nullptr));
         CHECK(sp.close());
         CHECK(sp.open(kStageSigma));
-        if (o->precision == QSGW_PREC_SPLIT_BF16)
+        if (x3)
           CHECK(stage_sigma_qs32_t<Bf16x3>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
-                                           near, V, s0 > 0 ? 1 : 0, &sp));
+                                           near, V, s0 > 0 ? 1 : 0, &sp, &x3o, &nl));
         else
           CHECK(stage_sigma_qs32_t<float>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
                                           near, V, s0 > 0 ? 1 : 0, &sp));
