@@ -67,6 +67,7 @@ enum Slot {
   W_SPLIT_B,     // split-BF16 residue product: rho' of a block   [2][kpad/8][sb padded][8] bf16
   W_SPLIT_W,     // split-BF16 qsGW product: w and wh of a block  [2][2][kfar/8][nbf padded][8] bf16
   W_NEARMASK,    // split-BF16 qsGW product: near-pole (k, s)     [nbf][sb padded to 8] byte
+  W_REDPART,     // first level of a long split-K reduction       [ceil(nz / 32)][nbf][nbf]
   W_NSLOTS
 };
 

@@ -75,6 +75,18 @@ __global__ void k_reduce_sym(const double* part, int64_t nz, int64_t n, double* 
   out[idx] = accumulate ? out[idx] + v : v;
 }
 
+__global__ void k_sum_slices(const double* part, int64_t nz, int64_t len, int64_t zg,
+                             double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ng = (nz + zg - 1) / zg;
+  if (idx >= ng * len) return;
+  const int64_t g = idx / len, e = idx - g * len;
+  const int64_t z1 = (g + 1) * zg < nz ? (g + 1) * zg : nz;
+  double a = 0.0;
+  for (int64_t z = g * zg; z < z1; ++z) a += part[z * len + e];
+  out[idx] = a;
+}
+
 __global__ void k_rho_reduce(const double* part, int64_t nz, int64_t rows, int64_t ns,
                              const double* Omega, double* rho, float* rho32) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -165,13 +177,16 @@ __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_
   c[P] = s;
 }
 
-__global__ void k_hartree_mo(const double* bmo, const double* c, int64_t naux, int64_t nn,
-                             double* J) {
+__global__ void k_hartree_part(const double* bmo, const double* c, int64_t naux, int64_t nn,
+                               int64_t pg, double* out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn) return;
+  const int64_t ng = (naux + pg - 1) / pg;
+  if (idx >= ng * nn) return;
+  const int64_t g = idx / nn, e = idx - g * nn;
+  const int64_t p1 = (g + 1) * pg < naux ? (g + 1) * pg : naux;
   double s = 0.0;
-  for (int64_t P = 0; P < naux; ++P) s += c[P] * bmo[P * nn + idx];
-  J[idx] = 2.0 * s;
+  for (int64_t P = g * pg; P < p1; ++P) s += c[P] * bmo[P * nn + e];
+  out[idx] = 2.0 * s;
 }
 
 __global__ void k_fock_assemble(const double* hmo, const double* J, const double* Kpart,

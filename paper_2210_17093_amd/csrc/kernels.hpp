@@ -392,6 +392,10 @@ __global__ void k_to_f32(const double* in, int64_t n, float* out);
 __global__ void k_split_pairs(const double* bmo, const int32_t* blocks, int64_t nblk, int64_t nbf,
                               int64_t naux, int64_t kpad, uint16_t* out);
 __global__ void k_zero_u16(uint16_t* p, int64_t n);
+// out[g][e] = sum over slices z in [g zg, (g + 1) zg) of part[z][e] (e < len),
+// g < ceil(nz / zg): the first, coalesced level of a long slice reduction.
+__global__ void k_sum_slices(const double* part, int64_t nz, int64_t len, int64_t zg,
+                             double* out);
 // mask[k][s] (s < nsp) = 1 where (k, s) is in the near-pole list of some
 // 64-row tile (s in [lo, lo + cnt) of k_near_ranges), else 0.
 __global__ void k_near_mask(const int64_t* lo, const int64_t* cnt, int64_t ntiles, int64_t nbf,
@@ -402,9 +406,10 @@ __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t
                              int64_t rows_pad, int64_t kpad, uint16_t* out);
 // c_P = sum_{i<nocc} B_mo[P][i][i]
 __global__ void k_occ_trace(const double* bmo, int64_t naux, int64_t nbf, int64_t nocc, double* c);
-// J_mn = 2 sum_P c_P B_mo[P][m][n]
-__global__ void k_hartree_mo(const double* bmo, const double* c, int64_t naux, int64_t nn,
-                             double* J);
+// J_mn = 2 sum_P c_P B_mo[P][m][n] in two levels: out[g][e] = 2 sum over
+// P in [g pg, (g + 1) pg) of c_P bmo[P][e], then k_sum_slices over g.
+__global__ void k_hartree_part(const double* bmo, const double* c, int64_t naux, int64_t nn,
+                               int64_t pg, double* out);
 // F[m][n] = sym(hmo)[m][n] + J[m][n] - sum_z Kpart[z][m][n] + V[m][n]
 __global__ void k_fock_assemble(const double* hmo, const double* J, const double* Kpart, int64_t nz,
                                 const double* V, int64_t n, double* F);

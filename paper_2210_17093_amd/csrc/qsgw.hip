@@ -6,6 +6,27 @@
 
 namespace {
 
+// V (+)= 1/2 (G + G^T), G = sum of the nz partial slices of part.  Long sums
+// go through a first level of 32 slices per group (coalesced reads, many
+// threads), then the symmetric sum over the group results.
+int reduce_sym(qsgw_ctx* c, const double* part, int64_t nz, int64_t n, double* V, int accumulate) {
+  const int64_t nn = n * n;
+  constexpr int64_t zg = 32;
+  if (nz > 2 * zg) {
+    const int64_t ng = (nz + zg - 1) / zg;
+    double* red = nullptr;
+    CHECK(ws_get(c, W_REDPART, (size_t)(ng * nn), &red));
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(ng * nn)), dim3(256), 0, c->stream, part, nz,
+                       nn, zg, red);
+    CHECK(launch_check(c, "k_sum_slices"));
+    part = red;
+    nz = ng;
+  }
+  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nn)), dim3(256), 0, c->stream, part, nz, n, V,
+                     accumulate);
+  return launch_check(c, "k_reduce_sym");
+}
+
 // Near-pole columns of the reduced-precision qsGW product for one excitation
 // block: for each 64-row tile t of m, the (k, s) with Omega_s inside the
 // window where some m of the tile may be within thr of a pole (k_near_ranges),
@@ -403,9 +424,7 @@ int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const
   }
   SPAN_CLOSE(spn);
   SPAN_OPEN(spn, kKSigmaRed);
-  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nn)), dim3(256), 0, c->stream, part,
-                     spf.nz + zn, nbf, V, accumulate);
-  CHECK(launch_check(c, "k_reduce_sym"));
+  CHECK(reduce_sym(c, part, spf.nz + zn, nbf, V, accumulate));
   SPAN_CLOSE(spn);
   return QSGW_OK;
 }
@@ -434,9 +453,7 @@ int stage_sigma_qs(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const dou
   }
   SPAN_CLOSE(spn);
   SPAN_OPEN(spn, kKSigmaRed);
-  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nbf * nbf)), dim3(256), 0, c->stream, part,
-                     sp.nz, nbf, V, accumulate);
-  CHECK(launch_check(c, "k_reduce_sym"));
+  CHECK(reduce_sym(c, part, sp.nz, nbf, V, accumulate));
   SPAN_CLOSE(spn);
   return QSGW_OK;
 }
@@ -453,9 +470,19 @@ int stage_jk_mo(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const doub
   hipLaunchKernelGGL(k_occ_trace, dim3(blocks_for(naux)), dim3(256), 0, c->stream, B_mo, naux, nbf,
                      nocc, cp);
   CHECK(launch_check(c, "k_occ_trace"));
-  hipLaunchKernelGGL(k_hartree_mo, dim3(blocks_for(nn)), dim3(256), 0, c->stream, B_mo, cp, naux,
-                     nn, *J);
-  CHECK(launch_check(c, "k_hartree_mo"));
+  {
+    // J over groups of 32 auxiliary functions (many threads, coalesced), then
+    // the sum of the groups
+    constexpr int64_t pg = 32;
+    const int64_t ng = (naux + pg - 1) / pg;
+    double* jp = nullptr;
+    CHECK(ws_get(c, W_REDPART, (size_t)(ng * nn), &jp));
+    hipLaunchKernelGGL(k_hartree_part, dim3(blocks_for(ng * nn)), dim3(256), 0, c->stream, B_mo,
+                       cp, naux, nn, pg, jp);
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(nn)), dim3(256), 0, c->stream, jp, ng, nn, ng,
+                       *J);
+    CHECK(launch_check(c, "k_hartree_part"));
+  }
   const SplitPlan sp = exchange_split(c->tiles, nbf, naux, nocc);
   CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nn), Kpart));
   OccRowsOp A{B_mo, nbf, nocc};
