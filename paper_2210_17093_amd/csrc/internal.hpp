@@ -57,8 +57,8 @@ enum Slot {
   W_MLP_F32,     // warm-start network: activations, gradients
   W_MLP_F64,     // warm-start network: partial sums, squared errors
   W_MLP_PERM,    // warm start: state permutation
-  W_NEAR,        // FP32 qsGW product: near-pole ranges, offsets  [3 ntiles nbf + 2 ntiles]
-  W_NEARTAB,     // FP32 qsGW product: compacted (k, s) columns   [2][columns] int32
+  W_NEAR,        // reduced-precision qsGW product: near-pole ranges, offsets, flags (int64)
+  W_NEARTAB,     // reduced-precision qsGW product: near-pole column tables (int32)
   W_BMO32,       // FP32 products: B_mo rounded to FP32           [naux][nbf][nbf] float
   W_RHO32,       // FP32 products: rho' rounded to FP32           [naux][sb] float
   W_BT32,        // FP32 products: Bt rounded to FP32             [naux][ntr] float
@@ -66,7 +66,7 @@ enum Slot {
   W_SPLIT_A,     // split-BF16 residue product: B_mo pair rows    [2][kpad/8][pair rows][8] bf16
   W_SPLIT_B,     // split-BF16 residue product: rho' of a block   [2][kpad/8][sb padded][8] bf16
   W_SPLIT_W,     // split-BF16 qsGW product: w and wh of a block  [2][2][kfar/8][nbf padded][8] bf16
-  W_NEARMASK,    // split-BF16 qsGW product: near-pole (k, s)     [nbf][sb padded to 8] byte
+  W_NEARW,       // split-BF16 qsGW product: near-pole columns    [columns][nbf] float
   W_REDPART,     // first level of a long split-K reduction       [ceil(nz / 32)][nbf][nbf]
   W_NSLOTS
 };

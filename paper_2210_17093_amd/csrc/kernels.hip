@@ -139,19 +139,6 @@ __global__ void k_zero_u16(uint16_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-__global__ void k_near_mask(const int64_t* lo, const int64_t* cnt, int64_t ntiles, int64_t nbf,
-                            int64_t nsp, uint8_t* mask) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nbf * nsp) return;
-  const int64_t k = idx / nsp, s = idx - k * nsp;
-  uint8_t near = 0;
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const int64_t a = lo[t * nbf + k];
-    near |= (s >= a && s < a + cnt[t * nbf + k]) ? 1 : 0;
-  }
-  mask[idx] = near;
-}
-
 __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,
                              int64_t rows_pad, int64_t kpad, uint16_t* out) {
   const int64_t nkb = kpad / 8;
@@ -408,6 +395,87 @@ __global__ void k_near_ranges(const double* eps, const double* Omega, int64_t nb
   const int64_t s1 = first_above(Omega, ns, b + slack);
   lo[idx] = s0;
   cnt[idx] = s1 > s0 ? s1 - s0 : 0;
+}
+
+// x of the pole term (m, k, s), formed exactly as the residue epilogue forms it
+__device__ __forceinline__ double pole_x(const double* eps, const double* Omega, int64_t nocc,
+                                         int64_t m, int64_t k, int64_t s) {
+  return (eps[m] - eps[k]) + (k < nocc ? 1.0 : -1.0) * Omega[s];
+}
+
+__global__ void k_near_colflags(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                                int64_t ns, int64_t nsp, double thr, int64_t* flag) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * nsp) return;
+  const int64_t k = idx / nsp, s = idx - k * nsp;
+  int64_t f = 0;
+  if (s < ns) {
+    // x = eps_m - c with c = eps_k -+ Omega_s: candidates m with eps_m near c
+    const double c = eps[k] - (k < nocc ? 1.0 : -1.0) * Omega[s];
+    const double slack = 1e-12 * (1.0 + fabs(c) + thr);
+    const int64_t m0 = first_at_least(eps, nbf, c - thr - slack);
+    const int64_t m1 = first_above(eps, nbf, c + thr + slack);
+    for (int64_t m = m0; m < m1 && !f; ++m) f = fabs(pole_x(eps, Omega, nocc, m, k, s)) < thr;
+  }
+  flag[idx] = f;
+}
+
+__global__ void k_near_colidx(const int64_t* flag, const int64_t* off, const int64_t* base,
+                              int64_t nbf, int64_t nsp, int32_t* colidx) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * nsp) return;
+  colidx[idx] = flag[idx] ? (int32_t)(base[idx / nsp] + off[idx]) : -1;
+}
+
+__global__ void k_near_mk(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                          int64_t ns, int64_t nsp, double thr, const int32_t* colidx,
+                          int32_t* c0, int32_t* slo, int32_t* len) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * nbf) return;
+  const int64_t m = idx / nbf, k = idx - m * nbf;
+  // |ea + sg Omega_s| < thr, ea = eps_m - eps_k: Omega_s in (-sg ea - thr, -sg ea + thr)
+  const double ea = eps[m] - eps[k];
+  const double ctr = k < nocc ? -ea : ea;
+  const double slack = 1e-12 * (1.0 + fabs(ctr) + thr);
+  int64_t a = first_at_least(Omega, ns, ctr - thr - slack);
+  int64_t b = first_above(Omega, ns, ctr + thr + slack);
+  while (a < b && !(fabs(pole_x(eps, Omega, nocc, m, k, a)) < thr)) ++a;
+  while (b > a && !(fabs(pole_x(eps, Omega, nocc, m, k, b - 1)) < thr)) --b;
+  len[idx] = (int32_t)(b - a);
+  slo[idx] = (int32_t)a;
+  c0[idx] = b > a ? colidx[k * nsp + a] : 0;
+}
+
+__global__ void k_near_product(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                               double eta, const int32_t* c0, const int32_t* slo,
+                               const int32_t* len, const float* wN, int64_t kc, double* npart) {
+  const int64_t m = blockIdx.x, z = blockIdx.y;
+  const int64_t k0 = z * kc, k1 = (k0 + kc) < nbf ? (k0 + kc) : nbf;
+  constexpr int NJ = 8;  // n = threadIdx.x + 256 j, nbf <= 2048
+  double acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = 0.0;
+  for (int64_t k = k0; k < k1; ++k) {
+    const int64_t e = m * nbf + k;
+    const int64_t L = len[e];
+    for (int64_t i = 0; i < L; ++i) {
+      const int64_t c = c0[e] + i, s = slo[e] + i;
+      const double x = pole_x(eps, Omega, nocc, m, k, s);
+      const double coef = (double)wN[c * nbf + m] * (x / (x * x + eta * eta));
+      const float* col = wN + c * nbf;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int64_t n = threadIdx.x + 256 * j;
+        if (n < nbf) acc[j] += coef * (double)col[n];
+      }
+    }
+  }
+  double* out = npart + (z * nbf + m) * nbf;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t n = threadIdx.x + 256 * j;
+    if (n < nbf) out[n] = acc[j];
+  }
 }
 
 __global__ void k_near_offsets(const int64_t* cnt, int64_t nbf, int64_t ntiles, int64_t* off,

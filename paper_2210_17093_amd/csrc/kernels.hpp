@@ -144,8 +144,8 @@ struct EpiPairResidue {
 // Split-BF16 variant of the residue epilogue.  For each pair (a, b) in
 // {(m, k), (k, m)} and excitation s it writes
 //   w[a][b][s] = w in FP64 if w is set,
-//   w32[a][b][s] = w in FP32 where nearmask[b][s] is set (the near-pole part
-//                  of the qsGW product reads these entries only),
+//   wN[colidx[b][s]][a] = w in FP32 where colidx[b][s] >= 0 (the compacted
+//                  near-pole columns the near-pole part reads),
 // and the qsGW product's operands in the Split8 layout (rows a, k index
 // j = b * nsp + s, nsp = ns rounded up to 8, s >= ns stored as zero):
 //   ws  = w split into BF16 halves,
@@ -158,8 +158,8 @@ struct EpiPairResidue {
 struct EpiPairResidueX3 {
   static constexpr bool kPassHook = true;
   double* w;  // nullptr: not written
-  float* w32;
-  const uint8_t* nearmask;  // [nbf][nsp]
+  float* wN;
+  const int32_t* colidx;  // [nbf][nsp]
   uint16_t* ws;
   uint16_t* whs;
   int64_t cs, ps, nsp;  // Split8 rows per k-block slab, plane stride, padded ns
@@ -172,7 +172,9 @@ struct EpiPairResidueX3 {
     const double ea = eps[a] - eps[b];
     const double sg = b < nocc ? 1.0 : -1.0;
     const float eta2 = (float)(eta * eta);
-    const uint64_t near8 = *reinterpret_cast<const uint64_t*>(nearmask + b * nsp + s0);
+    const int4 ci0 = *reinterpret_cast<const int4*>(colidx + b * nsp + s0);
+    const int4 ci1 = *reinterpret_cast<const int4*>(colidx + b * nsp + s0 + 4);
+    const int ci[8] = {ci0.x, ci0.y, ci0.z, ci0.w, ci1.x, ci1.y, ci1.z, ci1.w};
     float wv[8], hv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -185,9 +187,8 @@ struct EpiPairResidueX3 {
       wv[u] = vf;
       hv[u] = fabs(x) >= thr ? vf * g : 0.0f;
       if (ok) {
-        const int64_t i = (a * nbf + b) * ns + s;
-        if ((near8 >> (8 * u)) & 0xff) w32[i] = vf;
-        if (w) w[i] = v[u];
+        if (ci[u] >= 0) wN[(int64_t)ci[u] * nbf + a] = vf;
+        if (w) w[(a * nbf + b) * ns + s] = v[u];
       }
     }
     const int64_t o = ((b * nsp + s0) / 8 * cs + a) * 8;
@@ -392,14 +393,32 @@ __global__ void k_to_f32(const double* in, int64_t n, float* out);
 __global__ void k_split_pairs(const double* bmo, const int32_t* blocks, int64_t nblk, int64_t nbf,
                               int64_t naux, int64_t kpad, uint16_t* out);
 __global__ void k_zero_u16(uint16_t* p, int64_t n);
+
+// Exact near-pole terms of the split-BF16 qsGW product (|x_mks| < thr with
+// x_mks = (eps_m - eps_k) +- Omega_s, the residue epilogue's own formula).
+// flag[k][s] (s < nsp) = 1 where some m has a near-pole term at (k, s).
+__global__ void k_near_colflags(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                                int64_t ns, int64_t nsp, double thr, int64_t* flag);
+// colidx[k][s] = base[k] + off[k][s] where flagged (the compacted column of
+// (k, s), columns in (k, s) order), else -1.
+__global__ void k_near_colidx(const int64_t* flag, const int64_t* off, const int64_t* base,
+                              int64_t nbf, int64_t nsp, int32_t* colidx);
+// For each (m, k): the near-pole excitations of (m, k) are s = slo .. slo + len - 1
+// (contiguous, Omega ascending), their compacted columns c0 .. c0 + len - 1.
+__global__ void k_near_mk(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                          int64_t ns, int64_t nsp, double thr, const int32_t* colidx,
+                          int32_t* c0, int32_t* slo, int32_t* len);
+// npart[z][m][n] = sum over k in [z kc, (z + 1) kc) and the near-pole s of
+// (m, k) of w_mks Re 1/(x -+ i eta) w_nks, with w_nks = wN[column][n] (FP32
+// columns the residue epilogue writes).  Grid (nbf, ceil(nbf / kc)),
+// 256 threads, nbf <= 2048.
+__global__ void k_near_product(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
+                               double eta, const int32_t* c0, const int32_t* slo,
+                               const int32_t* len, const float* wN, int64_t kc, double* npart);
 // out[g][e] = sum over slices z in [g zg, (g + 1) zg) of part[z][e] (e < len),
 // g < ceil(nz / zg): the first, coalesced level of a long slice reduction.
 __global__ void k_sum_slices(const double* part, int64_t nz, int64_t len, int64_t zg,
                              double* out);
-// mask[k][s] (s < nsp) = 1 where (k, s) is in the near-pole list of some
-// 64-row tile (s in [lo, lo + cnt) of k_near_ranges), else 0.
-__global__ void k_near_mask(const int64_t* lo, const int64_t* cnt, int64_t ntiles, int64_t nbf,
-                            int64_t nsp, uint8_t* mask);
 // rows r < rows_pad of a [K][ld] matrix read as (r, k) = in[k * ld + r]
 // (r < rows, k < K; zero elsewhere).
 __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,

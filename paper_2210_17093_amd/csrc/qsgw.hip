@@ -85,10 +85,54 @@ int near_lists(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double*
 struct X3Out {
   uint16_t* ws;
   uint16_t* whs;
-  const uint8_t* nearmask;  // [nbf][nsp]: where the FP32 residues are needed
   int64_t cs, nsp, kfar;
   int64_t plane() const { return kfar * cs; }
+  // exact near-pole terms (near_x3): compacted (k, s) columns and, per (m, k),
+  // the near-pole excitations slo .. slo + len - 1 at columns c0 ..
+  const int32_t* colidx;  // [nbf][nsp], -1 where not near any m
+  const int32_t *c0, *slo, *len;  // [nbf][nbf]
+  float* wN;  // [ncols][nbf] FP32 residues of the columns
+  int64_t ncols;
 };
+
+// The exact near-pole terms of one excitation block (|x_mks| < thr), listed
+// before the residue product so that its epilogue can keep the FP32 residues
+// of those (k, s) columns, compacted.
+int near_x3(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const double* eps,
+            const double* Omega, double thr, X3Out* x) {
+  const int64_t nsp = x->nsp, nn = nbf * nbf;
+  int64_t* iw = nullptr;
+  CHECK(ws_get(c, W_NEAR, (size_t)(2 * nbf * nsp + 2 * nbf), &iw));
+  int64_t *flag = iw, *off = flag + nbf * nsp, *total = off + nbf * nsp, *base = total + nbf;
+  int32_t* tw = nullptr;
+  CHECK(ws_get(c, W_NEARTAB, (size_t)(nbf * nsp + 3 * nn), &tw));
+  int32_t *colidx = tw, *c0 = tw + nbf * nsp, *slo = c0 + nn, *len = slo + nn;
+  hipLaunchKernelGGL(k_near_colflags, dim3(blocks_for(nbf * nsp)), dim3(256), 0, c->stream, eps,
+                     Omega, nbf, nocc, ns, nsp, thr, flag);
+  hipLaunchKernelGGL(k_near_offsets, dim3((unsigned)nbf), dim3(256), 0, c->stream, flag, nsp, nbf,
+                     off, total, base);
+  hipLaunchKernelGGL(k_near_bases, dim3(1), dim3(64), 0, c->stream, total, nbf, base);
+  CHECK(launch_check(c, "near-pole columns"));
+  int64_t tail[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(&tail[0], base + nbf - 1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&tail[1], total + nbf - 1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  x->ncols = tail[0] + tail[1];
+  if (x->ncols >= ((int64_t)1 << 31)) return fail(c, QSGW_ERR_UNSUPPORTED, "too many near-pole columns");
+  hipLaunchKernelGGL(k_near_colidx, dim3(blocks_for(nbf * nsp)), dim3(256), 0, c->stream, flag, off,
+                     base, nbf, nsp, colidx);
+  hipLaunchKernelGGL(k_near_mk, dim3(blocks_for(nn)), dim3(256), 0, c->stream, eps, Omega, nbf, nocc,
+                     ns, nsp, thr, colidx, c0, slo, len);
+  CHECK(launch_check(c, "near-pole terms"));
+  CHECK(ws_get(c, W_NEARW, (size_t)(x->ncols * nbf), &x->wN));
+  x->colidx = colidx;
+  x->c0 = c0;
+  x->slo = slo;
+  x->len = len;
+  return QSGW_OK;
+}
 
 // ------------------------------------------------------------- stages ----
 
@@ -289,9 +333,10 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       Split8 A{splitA, rows, kpad * rows, 0};
       Split8 B{splitB, ns_pad, kpad * ns_pad, 0};
       if (x3o) {
-        EpiPairResidueX3 E3{w,      w32,     x3o->nearmask, x3o->ws, x3o->whs,   x3o->cs,
-                            x3o->plane(), x3o->nsp, blocks,  eps,     Omega + s0, nbf,
-                            nocc,   ns,      eta,     thr};
+        EpiPairResidueX3 E3{w,      x3o->wN,      x3o->colidx, x3o->ws, x3o->whs,
+                            x3o->cs, x3o->plane(), x3o->nsp,   blocks,  eps,
+                            Omega + s0, nbf,       nocc,        ns,      eta,
+                            thr};
         CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E3, rows, ns, kpad, 1)));
       } else {
         CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E, rows, ns, kpad, 1)));
@@ -338,7 +383,7 @@ template <class PT>
 int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const float* wh32,
                        const float* w32, const double* eps, const double* Omega, double eta,
                        double thr, double* V, int accumulate, Spans* spn,
-                       const X3Out* x3o = nullptr, const NearLists* nl = nullptr) {
+                       const X3Out* x3o = nullptr) {
   // (split-BF16 with split operands: the far product runs over the padded k
   // index of the Split8 layout, kfar >= nbf * ns)
   const int64_t nn = nbf * nbf, K = x3o ? x3o->kfar : nbf * ns, nt = (nbf + 63) / 64;
@@ -348,24 +393,35 @@ int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const
     spf.kchunk = ((spf.kchunk + 31) / 32) * 32;
     spf.nz = (K + spf.kchunk - 1) / spf.kchunk;
   }
-  NearLists own;
+  NearLists nl;
   SPAN_OPEN(spn, kKSigma);
-  if (!nl) {
-    CHECK(near_lists(c, nbf, nocc, ns, eps, Omega, thr, &own));
-    nl = &own;
-  }
-  const std::vector<int64_t>& tot_h = nl->tot_h;
-  const std::vector<int64_t>& base_h = nl->base_h;
-  const int64_t lmax = nl->lmax;
-  const int32_t *ktab = nl->ktab, *stab = nl->stab;
   int64_t zn = near_slices_max(nbf);
-  const int64_t zcap = (lmax + 255) / 256;
-  if (zn > zcap) zn = zcap < 1 ? 1 : zcap;
   double* part = nullptr;
-  CHECK(ws_get(c, W_PART, (size_t)((spf.nz + zn) * nn), &part));
-  double* npart = part + spf.nz * nn;
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for(zn * nn)), dim3(256), 0, c->stream, npart, zn * nn, 0.0);
-  CHECK(launch_check(c, "k_fill"));
+  double* npart = nullptr;
+  if (x3o) {
+    // exact near-pole terms from the compacted FP32 columns, k in slices of kc
+    const int64_t kc = std::max<int64_t>(32, (nbf + zn - 1) / zn);
+    zn = (nbf + kc - 1) / kc;
+    if (nbf > 2048) return fail(c, QSGW_ERR_UNSUPPORTED, "split-BF16 near-pole part: nbf > 2048");
+    CHECK(ws_get(c, W_PART, (size_t)((spf.nz + zn) * nn), &part));
+    npart = part + spf.nz * nn;
+    hipLaunchKernelGGL(k_near_product, dim3((unsigned)nbf, (unsigned)zn), dim3(256), 0, c->stream,
+                       eps, Omega, nbf, nocc, eta, x3o->c0, x3o->slo, x3o->len, x3o->wN, kc,
+                       npart);
+    CHECK(launch_check(c, "k_near_product"));
+  } else {
+    CHECK(near_lists(c, nbf, nocc, ns, eps, Omega, thr, &nl));
+    const int64_t zcap = (nl.lmax + 255) / 256;
+    if (zn > zcap) zn = zcap < 1 ? 1 : zcap;
+    CHECK(ws_get(c, W_PART, (size_t)((spf.nz + zn) * nn), &part));
+    npart = part + spf.nz * nn;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(zn * nn)), dim3(256), 0, c->stream, npart, zn * nn,
+                       0.0);
+    CHECK(launch_check(c, "k_fill"));
+  }
+  const std::vector<int64_t>& tot_h = nl.tot_h;
+  const std::vector<int64_t>& base_h = nl.base_h;
+  const int32_t *ktab = nl.ktab, *stab = nl.stab;
   if constexpr (std::is_same<PT, Bf16x3>::value) {
     if (x3o) {
       // zero k chunks beyond nbf * nsp (the residue epilogue writes the rest)
@@ -409,7 +465,7 @@ int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const
         CHECK((gemm_t<PT, 128, 64, false, 32>(c, "sigma_qs/far", A, B, E, nbf, nbf, K, 1, sp32)));
     }
   }
-  for (int64_t t = 0; t < nt; ++t) {
+  for (int64_t t = 0; t < (x3o ? 0 : nt); ++t) {
     const int64_t L = tot_h[t];
     if (L == 0) continue;
     const int64_t m0 = t * 64, rows = (m0 + 64 < nbf ? 64 : nbf - m0);
@@ -838,8 +894,6 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     if (o->precision == QSGW_PREC_SPLIT_BF16) {
       uint16_t* u = nullptr;  // the qsGW product's split operands, sized for the largest block
       CHECK(ws_get(c, W_SPLIT_W, (size_t)(4 * x3_kfar(nbf, sb) * ((nbf + 127) / 128 * 128)), &u));
-      uint8_t* mk = nullptr;  // near-pole mask of a block
-      CHECK(ws_get(c, W_NEARMASK, (size_t)(nbf * ((sb + 7) / 8 * 8)), &mk));
     }
     double* dummy = nullptr;
     CHECK(ws_get(c, W_J, (size_t)nn, &dummy));
@@ -917,7 +971,6 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
         double* w64 = (it == 0 && st->diag) ? w : nullptr;
         // split-BF16: the residue epilogue also writes the qsGW product's split operands
         X3Out x3o{};
-        NearLists nl;
         const bool x3 = o->precision == QSGW_PREC_SPLIT_BF16;
         if (x3) {
           x3o.cs = (nbf + 127) / 128 * 128;
@@ -925,14 +978,9 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
           x3o.kfar = x3_kfar(nbf, ns);
           x3o.ws = static_cast<uint16_t*>(c->ws[W_SPLIT_W].p);
           x3o.whs = x3o.ws + 2 * x3o.plane();
-          // the near-pole columns first: the residue epilogue keeps FP32
-          // residues only where the near-pole part will read them
-          uint8_t* mk = static_cast<uint8_t*>(c->ws[W_NEARMASK].p);
-          CHECK(near_lists(c, nbf, nocc, ns, eps, Omega + s0, near, &nl));
-          hipLaunchKernelGGL(k_near_mask, dim3(blocks_for(nbf * x3o.nsp)), dim3(256), 0, c->stream,
-                             nl.lo, nl.cnt, nl.nt, nbf, x3o.nsp, mk);
-          CHECK(launch_check(c, "k_near_mask"));
-          x3o.nearmask = mk;
+          // the near-pole terms first: the residue epilogue keeps FP32
+          // residues only in the columns the near-pole part reads
+          CHECK(near_x3(c, nbf, nocc, ns, eps, Omega + s0, near, &x3o));
         }
         CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
                              eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
@@ -942,7 +990,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
         CHECK(sp.open(kStageSigma));
         if (x3)
           CHECK(stage_sigma_qs32_t<Bf16x3>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
-                                           near, V, s0 > 0 ? 1 : 0, &sp, &x3o, &nl));
+                                           near, V, s0 > 0 ? 1 : 0, &sp, &x3o));
         else
           CHECK(stage_sigma_qs32_t<float>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
                                           near, V, s0 > 0 ? 1 : 0, &sp));
