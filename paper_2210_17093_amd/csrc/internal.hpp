@@ -265,9 +265,13 @@ inline int64_t x3_kfar(int64_t nbf, int64_t ns) {
   const int64_t nsp = (ns + 7) / 8 * 8;
   return (nbf * nsp + 31) / 32 * 32;
 }
+// split-BF16 near-pole part: k in slices of kX3NearK, one partial slice each
+constexpr int64_t kX3NearK = 32;
+inline int64_t x3_near_slices(int64_t nbf) { return (nbf + kX3NearK - 1) / kX3NearK; }
 inline int64_t sigma_slices(const Tiles& tl, int64_t nbf, int64_t ns, bool fp32, bool x3 = false) {
   if (!fp32) return sigma_split(tl, nbf, ns).nz;
-  return sigma_split32(tl, nbf, x3 ? x3_kfar(nbf, ns) : nbf * ns).nz + near_slices_max(nbf);
+  if (x3) return sigma_split32(tl, nbf, x3_kfar(nbf, ns)).nz + x3_near_slices(nbf);
+  return sigma_split32(tl, nbf, nbf * ns).nz + near_slices_max(nbf);
 }
 
 // rho product: tiles of the naux x ns output, K = ntr; split only when the

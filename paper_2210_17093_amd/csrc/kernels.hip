@@ -449,26 +449,53 @@ __global__ void k_near_mk(const double* eps, const double* Omega, int64_t nbf, i
 __global__ void k_near_product(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
                                double eta, const int32_t* c0, const int32_t* slo,
                                const int32_t* len, const float* wN, int64_t kc, double* npart) {
+  // The slice's terms are enumerated into LDS in batches (coefficient and
+  // column), then every thread runs over the batch for its n: independent
+  // coalesced loads, no per-term latency chain.
+  constexpr int KCMAX = 64, BATCH = 1024, NJ = 8;  // nbf <= 256 NJ
+  __shared__ int64_t start[KCMAX + 1];
+  __shared__ double scoef[BATCH];
+  __shared__ int32_t scol[BATCH];
   const int64_t m = blockIdx.x, z = blockIdx.y;
   const int64_t k0 = z * kc, k1 = (k0 + kc) < nbf ? (k0 + kc) : nbf;
-  constexpr int NJ = 8;  // n = threadIdx.x + 256 j, nbf <= 2048
+  const int nk = (int)(k1 - k0);
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int i = 0; i < nk; ++i) {
+      start[i] = t;
+      t += len[m * nbf + k0 + i];
+    }
+    start[nk] = t;
+  }
+  __syncthreads();
+  const int64_t total = start[nk];
   double acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = 0.0;
-  for (int64_t k = k0; k < k1; ++k) {
-    const int64_t e = m * nbf + k;
-    const int64_t L = len[e];
-    for (int64_t i = 0; i < L; ++i) {
-      const int64_t c = c0[e] + i, s = slo[e] + i;
-      const double x = pole_x(eps, Omega, nocc, m, k, s);
-      const double coef = (double)wN[c * nbf + m] * (x / (x * x + eta * eta));
-      const float* col = wN + c * nbf;
+  for (int64_t b0 = 0; b0 < total; b0 += BATCH) {
+    const int64_t nb = (total - b0) < BATCH ? (total - b0) : BATCH;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) {
+      const int64_t t = b0 + q;
+      int i = 0;
+      while (start[i + 1] <= t) ++i;  // the k of term t
+      const int64_t k = k0 + i, e = m * nbf + k, r = t - start[i];
+      const int64_t c = c0[e] + r, sidx = slo[e] + r;
+      const double x = pole_x(eps, Omega, nocc, m, k, sidx);
+      scoef[q] = (double)wN[c * nbf + m] * (x / (x * x + eta * eta));
+      scol[q] = (int32_t)c;
+    }
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int64_t n = threadIdx.x + 256 * j;
-        if (n < nbf) acc[j] += coef * (double)col[n];
+    for (int j = 0; j < NJ; ++j) {
+      const int64_t n = threadIdx.x + 256 * j;
+      if (n < nbf) {
+        double a = acc[j];
+#pragma unroll 8
+        for (int64_t q = 0; q < nb; ++q) a += scoef[q] * (double)wN[(int64_t)scol[q] * nbf + n];
+        acc[j] = a;
       }
     }
+    __syncthreads();
   }
   double* out = npart + (z * nbf + m) * nbf;
 #pragma unroll

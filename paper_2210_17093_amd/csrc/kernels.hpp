@@ -411,7 +411,7 @@ __global__ void k_near_mk(const double* eps, const double* Omega, int64_t nbf, i
 // npart[z][m][n] = sum over k in [z kc, (z + 1) kc) and the near-pole s of
 // (m, k) of w_mks Re 1/(x -+ i eta) w_nks, with w_nks = wN[column][n] (FP32
 // columns the residue epilogue writes).  Grid (nbf, ceil(nbf / kc)),
-// 256 threads, nbf <= 2048.
+// 256 threads, kc <= 64, nbf <= 2048.
 __global__ void k_near_product(const double* eps, const double* Omega, int64_t nbf, int64_t nocc,
                                double eta, const int32_t* c0, const int32_t* slo,
                                const int32_t* len, const float* wN, int64_t kc, double* npart);

@@ -400,8 +400,8 @@ int stage_sigma_qs32_t(qsgw_ctx* c, int64_t nbf, int64_t nocc, int64_t ns, const
   double* npart = nullptr;
   if (x3o) {
     // exact near-pole terms from the compacted FP32 columns, k in slices of kc
-    const int64_t kc = std::max<int64_t>(32, (nbf + zn - 1) / zn);
-    zn = (nbf + kc - 1) / kc;
+    const int64_t kc = kX3NearK;
+    zn = x3_near_slices(nbf);
     if (nbf > 2048) return fail(c, QSGW_ERR_UNSUPPORTED, "split-BF16 near-pole part: nbf > 2048");
     CHECK(ws_get(c, W_PART, (size_t)((spf.nz + zn) * nn), &part));
     npart = part + spf.nz * nn;
