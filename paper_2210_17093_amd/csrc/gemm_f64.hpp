@@ -704,66 +704,108 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
     }
   };
 
-  const int64_t nk = kb1 > kb0 ? (kb1 - kb0 + BK - 1) / BK : 0;
-  if (nk > 0) {
-    gload(kb0);
-    sstore(0);
-    __syncthreads();
-  }
-  for (int64_t it = 0; it < nk; ++it) {
-    const int cur = (int)(it & 1);
-    if (it + 1 < nk) gload(kb0 + (it + 1) * BK);
+  // Split-BF16 products of one staged k tile (buffer cur).
+  auto mma_x3 = [&](int cur) {
     if constexpr (X3) {
-      const LT* ah_s = As[2 * cur];
-      const LT* al_s = As[2 * cur + 1];
-      const LT* bh_s = Bs[2 * cur];
-      const LT* bl_s = Bs[2 * cur + 1];
+    const LT* ah_s = As[2 * cur];
+    const LT* al_s = As[2 * cur + 1];
+    const LT* bh_s = Bs[2 * cur];
+    const LT* bl_s = Bs[2 * cur + 1];
 #pragma unroll
-      for (int ks = 0; ks < BK / 32; ++ks) {
-        const int kofs = ks * 32 + 8 * (lane >> 4);
-        bf16x8 bh[TN], bl[TN];
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      const int kofs = ks * 32 + 8 * (lane >> 4);
+      bf16x8 bh[TN], bl[TN];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int o = x3_at<BK>(wn + j * 16 + (lane & 15), kofs);
-          bh[j] = *reinterpret_cast<const bf16x8*>(bh_s + o);
-          bl[j] = *reinterpret_cast<const bf16x8*>(bl_s + o);
-        }
-        // one row block of A at a time (fewer live fragments); the TN
-        // accumulators of a row block interleave, so consecutive products
-        // never wait on each other: small cross terms first, then hi * hi
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int o = x3_at<BK>(wm + i * 16 + (lane & 15), kofs);
-          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ah_s + o);
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(al_s + o);
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(al, bh[j], acc[i][j]);
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah, bl[j], acc[i][j]);
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah, bh[j], acc[i][j]);
-        }
+      for (int j = 0; j < TN; ++j) {
+        const int o = x3_at<BK>(wn + j * 16 + (lane & 15), kofs);
+        bh[j] = *reinterpret_cast<const bf16x8*>(bh_s + o);
+        bl[j] = *reinterpret_cast<const bf16x8*>(bl_s + o);
       }
-    } else {
-      const T* as = As[cur];
-      const T* bs = Bs[cur];
+      // one row block of A at a time (fewer live fragments); the TN
+      // accumulators of a row block interleave, so consecutive products
+      // never wait on each other: small cross terms first, then hi * hi
 #pragma unroll
-      for (int ks = 0; ks < BK / 4; ++ks) {
-        const int krow = ks * 4 + (lane >> 4);
-        T a[TM], b[TN];
+      for (int i = 0; i < TM; ++i) {
+        const int o = x3_at<BK>(wm + i * 16 + (lane & 15), kofs);
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ah_s + o);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(al_s + o);
 #pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = as[a_at(wm + i * 16 + (lane & 15), krow)];
+        for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(al, bh[j], acc[i][j]);
 #pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = bs[b_at(wn + j * 16 + (lane & 15), krow)];
+        for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah, bl[j], acc[i][j]);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = MM::mma(ah, bh[j], acc[i][j]);
       }
     }
-    if (it + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
+    }
+  };
+
+  const int64_t nk = kb1 > kb0 ? (kb1 - kb0 + BK - 1) / BK : 0;
+  if constexpr (X3 && is_split8_op<OA>::value && is_split8_op<OB>::value) {
+    // Both operands pre-split (every tile full): loads run two k tiles ahead
+    // through two register sets, so a load has two tiles of products to land.
+    uint32_t xa[2][EA], xb[2][EB];
+    auto ld = [&](int64_t kbase, int u) {
+      load_tile_kb<BM, BK>(A, batch, m0, kbase, kb1, tid, xa[u]);
+      load_tile_kb<BN, BK>(B, batch, n0, kbase, kb1, tid, xb[u]);
+    };
+    auto st = [&](int buf, int u) {
+      sstore_split(xa[u], As[2 * buf], As[2 * buf + 1], ChunkMap<BM, BK>());
+      sstore_split(xb[u], Bs[2 * buf], Bs[2 * buf + 1], ChunkMap<BN, BK>());
+    };
+    if (nk > 0) {
+      ld(kb0, 0);
+      st(0, 0);
+      if (nk > 1) ld(kb0 + BK, 1);
+      __syncthreads();
+    }
+    // Step it computes buffer it % 2, holds tile it + 1 in registers
+    // (1 - it % 2), loads tile it + 2 into registers it % 2 (their tile it
+    // went to LDS one step earlier) and stores tile it + 1 into the other
+    // buffer (its tile it - 1 was consumed before the previous barrier).
+    for (int64_t it = 0; it < nk; it += 2) {
+      if (it + 2 < nk) ld(kb0 + (it + 2) * BK, 0);
+      mma_x3(0);
+      if (it + 1 < nk) st(1, 1);
+      __syncthreads();
+      if (it + 1 >= nk) break;
+      if (it + 3 < nk) ld(kb0 + (it + 3) * BK, 1);
+      mma_x3(1);
+      if (it + 2 < nk) st(0, 0);
+      __syncthreads();
+    }
+  } else {
+    if (nk > 0) {
+      gload(kb0);
+      sstore(0);
+      __syncthreads();
+    }
+    for (int64_t it = 0; it < nk; ++it) {
+      const int cur = (int)(it & 1);
+      if (it + 1 < nk) gload(kb0 + (it + 1) * BK);
+      if constexpr (X3) {
+        mma_x3(cur);
+      } else {
+        const T* as = As[cur];
+        const T* bs = Bs[cur];
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+          const int krow = ks * 4 + (lane >> 4);
+          T a[TM], b[TN];
+#pragma unroll
+          for (int i = 0; i < TM; ++i) a[i] = as[a_at(wm + i * 16 + (lane & 15), krow)];
+#pragma unroll
+          for (int j = 0; j < TN; ++j) b[j] = bs[b_at(wn + j * 16 + (lane & 15), krow)];
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
+        }
+      }
+      if (it + 1 < nk) sstore(cur ^ 1);
+      __syncthreads();
+    }
   }
 
   // Epilogue through LDS, one wave-row (WM rows of the tile) per pass: the
