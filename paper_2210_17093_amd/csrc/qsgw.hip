@@ -252,12 +252,10 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
   if (x3) {
     CHECK(ws_get(c, W_SPLIT_A, (size_t)(2 * kpad * nblk * 128), &splitA));
     CHECK(ws_get(c, W_SPLIT_B, (size_t)(2 * kpad * ns_pad), &splitB));
-    if (!reuse_split) {
-      SPAN_OPEN(sp, kKW);
+    if (!reuse_split) {  // (stage time; the kernel spans time the products alone)
       hipLaunchKernelGGL(k_split_pairs, dim3(blocks_for(nblk * 128 * (kpad / 8))), dim3(256), 0,
                          c->stream, B_mo, blocks, nblk, nbf, naux, kpad, splitA);
       CHECK(launch_check(c, "k_split_pairs"));
-      SPAN_CLOSE(sp);
     }
   }
   if (f32) {
