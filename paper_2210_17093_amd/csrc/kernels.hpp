@@ -168,6 +168,10 @@ struct EpiPairResidueX3 {
   const double* Omega;  // the block's excitations
   int64_t nbf, nocc, ns;
   double eta, thr;
+  // (HAS_W: the FP64 residues are written too; without them no store of this
+  // epilogue has the type of its FP64 loads, so loads of the next chunk can
+  // move ahead of the stores of this one)
+  template <bool HAS_W>
   __device__ __forceinline__ void put(int64_t a, int64_t b, int64_t s0, const double* v) const {
     const double ea = eps[a] - eps[b];
     const double sg = b < nocc ? 1.0 : -1.0;
@@ -175,12 +179,15 @@ struct EpiPairResidueX3 {
     const int4 ci0 = *reinterpret_cast<const int4*>(colidx + b * nsp + s0);
     const int4 ci1 = *reinterpret_cast<const int4*>(colidx + b * nsp + s0 + 4);
     const int ci[8] = {ci0.x, ci0.y, ci0.z, ci0.w, ci1.x, ci1.y, ci1.z, ci1.w};
+    double om[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) om[u] = s0 + u < ns ? Omega[s0 + u] : 0.0;
     float wv[8], hv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t s = s0 + u;
       const bool ok = s < ns;
-      const double x = ok ? ea + sg * Omega[s] : 1.0;
+      const double x = ok ? ea + sg * om[u] : 1.0;
       const float xf = (float)x;
       const float vf = ok ? (float)v[u] : 0.0f;
       const float g = xf * __builtin_amdgcn_rcpf(fmaf(xf, xf, eta2));
@@ -188,7 +195,7 @@ struct EpiPairResidueX3 {
       hv[u] = fabs(x) >= thr ? vf * g : 0.0f;
       if (ok) {
         if (ci[u] >= 0) wN[(int64_t)ci[u] * nbf + a] = vf;
-        if (w) w[(a * nbf + b) * ns + s] = v[u];
+        if (HAS_W) w[(a * nbf + b) * ns + s] = v[u];
       }
     }
     const int64_t o = ((b * nsp + s0) / 8 * cs + a) * 8;
@@ -206,6 +213,14 @@ struct EpiPairResidueX3 {
   template <int ROWS, int BN>
   __device__ __forceinline__ void pass(int64_t r0, int64_t n0, const double* Cs, int ldc,
                                        int tid) const {
+    if (w)
+      pass_t<ROWS, BN, true>(r0, n0, Cs, ldc, tid);
+    else
+      pass_t<ROWS, BN, false>(r0, n0, Cs, ldc, tid);
+  }
+  template <int ROWS, int BN, bool HAS_W>
+  __device__ __forceinline__ void pass_t(int64_t r0, int64_t n0, const double* Cs, int ldc,
+                                         int tid) const {
     static_assert(ROWS == 64 && BN % 8 == 0, "pair-block passes of 4 x 16 pairs");
     const int32_t bk = blocks[r0 >> 7];
     const int64_t mbase = (int64_t)(bk >> 16) * 8 + (r0 & 127) / 16, kbase = (int64_t)(bk & 0xffff) * 16;
@@ -218,7 +233,7 @@ struct EpiPairResidueX3 {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = Cs[(mo * 16 + ko) * ldc + 8 * sc + u];
-      put(m, k, s0, v);
+      put<HAS_W>(m, k, s0, v);
     }
     // (k, m), m < k: sixteen consecutive k per (m, chunk)
     for (int q = tid; q < ITEMS; q += 256) {
@@ -228,7 +243,7 @@ struct EpiPairResidueX3 {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = Cs[(mo * 16 + ko) * ldc + 8 * sc + u];
-      put(k, m, s0, v);
+      put<HAS_W>(k, m, s0, v);
     }
   }
 };
