@@ -265,6 +265,16 @@ struct has_pass_hook<E, decltype((void)E::kPassHook, void())> {
   static constexpr bool value = E::kPassHook;
 };
 
+// Offset of element (r, k) of a split-BF16 LDS plane with br rows: swizzled
+// [r][k] rows, or k-block-major [k/8][r][8] (KBM).
+template <bool KBM, int BK>
+__device__ __forceinline__ int x3_off(int br, int r, int k) {
+  if constexpr (KBM)
+    return ((k >> 3) * br + r) * 8 + (k & 7);
+  else
+    return x3_at<BK>(r, k);
+}
+
 // Element map of a split-BF16 operand tile, as a tag for the LDS store.
 template <int BR, int BK, bool KC>
 struct X3Map {
@@ -704,9 +714,13 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
     }
   };
 
-  // Split-BF16 products of one staged k tile (buffer cur).
-  auto mma_x3 = [&](int cur) {
+  // Split-BF16 products of one staged k tile (buffer cur).  KBM: tiles held
+  // k-block-major ([k/8][r][8] per plane, as direct-to-LDS loads write them)
+  // instead of the swizzled [r][k] rows.
+  auto mma_x3 = [&](int cur, auto kbm_tag) {
     if constexpr (X3) {
+    constexpr bool KBM = decltype(kbm_tag)::value;
+    auto at = [&](int br, int r, int k) { return x3_off<KBM, BK>(br, r, k); };
     const LT* ah_s = As[2 * cur];
     const LT* al_s = As[2 * cur + 1];
     const LT* bh_s = Bs[2 * cur];
@@ -717,7 +731,7 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
       bf16x8 bh[TN], bl[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const int o = x3_at<BK>(wn + j * 16 + (lane & 15), kofs);
+        const int o = at(BN, wn + j * 16 + (lane & 15), kofs);
         bh[j] = *reinterpret_cast<const bf16x8*>(bh_s + o);
         bl[j] = *reinterpret_cast<const bf16x8*>(bl_s + o);
       }
@@ -726,7 +740,7 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
       // never wait on each other: small cross terms first, then hi * hi
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int o = x3_at<BK>(wm + i * 16 + (lane & 15), kofs);
+        const int o = at(BM, wm + i * 16 + (lane & 15), kofs);
         const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ah_s + o);
         const bf16x8 al = *reinterpret_cast<const bf16x8*>(al_s + o);
 #pragma unroll
@@ -742,6 +756,45 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
 
   const int64_t nk = kb1 > kb0 ? (kb1 - kb0 + BK - 1) / BK : 0;
   if constexpr (X3 && is_split8_op<OA>::value && is_split8_op<OB>::value) {
+    // Both operands pre-split (every tile full): the chunks go from global
+    // memory straight into LDS (global_load_lds_dwordx4: each lane's 16 bytes
+    // land at the wave's LDS base + 16 x lane), one k tile ahead, in the
+    // k-block-major layout that a wave's 64 consecutive rows of one k-block
+    // and plane fill contiguously.
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef __attribute__((address_space(1))) void glob_void;
+    auto issue = [&](const auto& op, int64_t r0, int64_t kbase, LT* hi, LT* lo, auto br_tag) {
+      constexpr int BR = decltype(br_tag)::value;
+      typedef ChunkMap<BR, BK> CM;
+      const uint16_t* origin = op.p + batch * op.sb + ((kbase >> 3) * op.cs + r0) * 8;
+#pragma unroll
+      for (int c = 0; c < CM::C; ++c) {
+        const int q0 = c * 256 + wave * 64;  // chunk of lane 0: rows r_w .. r_w + 63
+        const int rw = q0 % BR, rest = q0 / BR;
+        const int kb = rest % CM::NKB, pl = rest / CM::NKB;
+        const uint16_t* src = origin + pl * op.ps + ((int64_t)kb * op.cs + rw + lane) * 8;
+        LT* dst = (pl ? lo : hi) + (kb * BR + rw) * 8;
+        __builtin_amdgcn_global_load_lds((glob_void*)src, (lds_void*)dst, 16, 0, 0);
+      }
+    };
+    auto issue_tile = [&](int64_t kbase, int buf) {
+      issue(A, m0, kbase, As[2 * buf], As[2 * buf + 1], std::integral_constant<int, BM>());
+      issue(B, n0, kbase, Bs[2 * buf], Bs[2 * buf + 1], std::integral_constant<int, BN>());
+    };
+    if (nk > 0) {
+      issue_tile(kb0, 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+    for (int64_t it = 0; it < nk; ++it) {
+      const int cur = (int)(it & 1);
+      // (the other buffer's tile was consumed before the previous barrier)
+      if (it + 1 < nk) issue_tile(kb0 + (it + 1) * BK, cur ^ 1);
+      mma_x3(cur, std::true_type());
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+  } else if constexpr (false) {
     // Both operands pre-split (every tile full): loads run two k tiles ahead
     // through two register sets, so a load has two tiles of products to land.
     uint32_t xa[2][EA], xb[2][EB];
@@ -765,12 +818,12 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
     // buffer (its tile it - 1 was consumed before the previous barrier).
     for (int64_t it = 0; it < nk; it += 2) {
       if (it + 2 < nk) ld(kb0 + (it + 2) * BK, 0);
-      mma_x3(0);
+      mma_x3(0, std::false_type());
       if (it + 1 < nk) st(1, 1);
       __syncthreads();
       if (it + 1 >= nk) break;
       if (it + 3 < nk) ld(kb0 + (it + 3) * BK, 1);
-      mma_x3(1);
+      mma_x3(1, std::false_type());
       if (it + 2 < nk) st(0, 0);
       __syncthreads();
     }
@@ -784,7 +837,7 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
       const int cur = (int)(it & 1);
       if (it + 1 < nk) gload(kb0 + (it + 1) * BK);
       if constexpr (X3) {
-        mma_x3(cur);
+        mma_x3(cur, std::false_type());
       } else {
         const T* as = As[cur];
         const T* bs = Bs[cur];
