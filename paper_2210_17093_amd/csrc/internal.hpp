@@ -66,6 +66,9 @@ enum Slot {
   W_SPLIT_A,     // split-BF16 residue product: B_mo pair rows    [2][kpad/8][pair rows][8] bf16
   W_SPLIT_B,     // split-BF16 residue product: rho' of a block   [2][kpad/8][sb padded][8] bf16
   W_SPLIT_W,     // split-BF16 qsGW product: w and wh of a block  [2][2][kfar/8][nbf padded][8] bf16
+  W_SPLIT_CAS,   // split-BF16 Casida build: Bt, rows t, k = P     [2][naux/8][ntr padded][8] bf16
+  W_SPLIT_RA,    // split-BF16 rho' product: Bt, rows P, k = t     [2][ntr/8][naux padded][8] bf16
+  W_SPLIT_Z,     // split-BF16 rho' product: Z of a block, rows s  [2][ntr/8][sb padded][8] bf16
   W_NEARW,       // split-BF16 qsGW product: near-pole columns    [columns][nbf] float
   W_REDPART,     // first level of a long split-K reduction       [ceil(nz / 32)][nbf][nbf]
   W_NSLOTS

@@ -139,6 +139,34 @@ __global__ void k_zero_u16(uint16_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+__global__ void k_split_rows(const double* in, int64_t ld, int64_t rows, int64_t K,
+                             int64_t rows_pad, int64_t kpad, uint16_t* out) {
+  // 32 rows x 256 k per workgroup through LDS: rows are read along k
+  // (coalesced), chunks are written along r (adjacent rows adjacent).
+  constexpr int TR = 32, TK = 256, PITCH = TK + 4;
+  __shared__ __attribute__((aligned(16))) float t[TR * PITCH];
+  const int64_t r0 = (int64_t)blockIdx.x * TR, k0 = (int64_t)blockIdx.y * TK;
+  const int tid = threadIdx.x;
+  for (int rr = 0; rr < TR; ++rr) {
+    const int64_t r = r0 + rr, k = k0 + tid;
+    t[rr * PITCH + tid] = (r < rows && k < K) ? (float)in[r * ld + k] : 0.0f;
+  }
+  __syncthreads();
+  const int64_t nkb = kpad / 8;
+  for (int q = tid; q < TR * (TK / 8); q += blockDim.x) {
+    const int rr = q % TR, kbl = q / TR;
+    const int64_t kb = k0 / 8 + kbl;
+    if (kb >= nkb) continue;
+    const float* x = t + rr * PITCH + 8 * kbl;
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) split_bf16x2(x[2 * u], x[2 * u + 1], h[u], l[u]);
+    const int64_t o = (kb * rows_pad + r0 + rr) * 8;
+    *reinterpret_cast<uint4*>(out + o) = uint4{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<uint4*>(out + nkb * rows_pad * 8 + o) = uint4{l[0], l[1], l[2], l[3]};
+  }
+}
+
 __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,
                              int64_t rows_pad, int64_t kpad, uint16_t* out) {
   const int64_t nkb = kpad / 8;

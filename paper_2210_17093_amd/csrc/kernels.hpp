@@ -434,6 +434,11 @@ __global__ void k_near_product(const double* eps, const double* Omega, int64_t n
 // g < ceil(nz / zg): the first, coalesced level of a long slice reduction.
 __global__ void k_sum_slices(const double* part, int64_t nz, int64_t len, int64_t zg,
                              double* out);
+// rows r < rows_pad of a [rows][ld] matrix read as (r, k) = in[r * ld + k]
+// (r < rows, k < K; zero elsewhere).  Grid (rows_pad / 32, ceil(kpad / 256)),
+// 256 threads; rows_pad a multiple of 32.
+__global__ void k_split_rows(const double* in, int64_t ld, int64_t rows, int64_t K,
+                             int64_t rows_pad, int64_t kpad, uint16_t* out);
 // rows r < rows_pad of a [K][ld] matrix read as (r, k) = in[k * ld + r]
 // (r < rows, k < K; zero elsewhere).
 __global__ void k_split_cols(const double* in, int64_t ld, int64_t rows, int64_t K,

@@ -182,7 +182,7 @@ int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const 
   // The reduced-precision variants also keep Bt rounded to FP32 (W_BT32) for
   // their products.
   float* Bt32 = nullptr;
-  if (prec != QSGW_PREC_FP64) {
+  if (prec == QSGW_PREC_FP32) {
     const int64_t n32 = naux * nocc * (nbf - nocc);
     CHECK(ws_get(c, W_BT32, (size_t)n32, &Bt32));
   }
@@ -200,9 +200,16 @@ int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const 
     CHECK((gemm_shape<float, true, 32>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr,
                                        ntr, naux, 1)));
   } else if (prec == QSGW_PREC_SPLIT_BF16) {
-    Strided<false, float> A{Bt32, 1, ntr, 0, ntr};
+    // Bt split once into BF16 halves in k-blocks of 8 (rows t, k = P)
+    const int64_t kpad = (naux + 31) / 32 * 32, rp = (ntr + 127) / 128 * 128;
+    uint16_t* bs = nullptr;
+    CHECK(ws_get(c, W_SPLIT_CAS, (size_t)(2 * kpad * rp), &bs));
+    hipLaunchKernelGGL(k_split_cols, dim3(blocks_for(rp * (kpad / 8))), dim3(256), 0, c->stream, Bt,
+                       ntr, ntr, naux, rp, kpad, bs);
+    CHECK(launch_check(c, "k_split_cols"));
+    Split8 A{bs, rp, kpad * rp, 0};
     CHECK((gemm_shape<Bf16x3, true, 32>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr,
-                                        ntr, naux, 1)));
+                                        ntr, kpad, 1)));
   } else {
     Strided<false> A{Bt, 1, ntr, 0, ntr};
     CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_CASIDA], "rpa_build", A, A, E, ntr, ntr,
@@ -258,7 +265,22 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       CHECK(launch_check(c, "k_split_pairs"));
     }
   }
-  if (f32) {
+  uint16_t *splitRA = nullptr, *splitZ = nullptr;
+  const int64_t kpt = ((ntr + 31) / 32) * 32, naux_pad = ((naux + 127) / 128) * 128;
+  if (x3) {
+    // rho' = Bt Z^T from split copies: Bt with rows P (once per B_mo, as the
+    // pair rows), the block's eigenvectors with rows s; k = t, padded to 32
+    CHECK(ws_get(c, W_SPLIT_RA, (size_t)(2 * kpt * naux_pad), &splitRA));
+    CHECK(ws_get(c, W_SPLIT_Z, (size_t)(2 * kpt * ns_pad), &splitZ));
+    if (!reuse_split) {
+      hipLaunchKernelGGL(k_split_rows, dim3((unsigned)(naux_pad / 32), (unsigned)((kpt + 255) / 256)),
+                         dim3(256), 0, c->stream, Bt, ntr, naux, ntr, naux_pad, kpt, splitRA);
+      CHECK(launch_check(c, "k_split_rows"));
+    }
+    hipLaunchKernelGGL(k_split_rows, dim3((unsigned)(ns_pad / 32), (unsigned)((kpt + 255) / 256)),
+                       dim3(256), 0, c->stream, Z + s0 * ntr, ntr, ns, ntr, ns_pad, kpt, splitZ);
+    CHECK(launch_check(c, "k_split_rows"));
+  } else if (f32) {
     if (!Bt32) {
       float* b = nullptr;
       CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &b));
@@ -271,8 +293,8 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(ns * ntr)), dim3(256), 0, c->stream, Z + s0 * ntr,
                        ns * ntr, Z32);
     CHECK(launch_check(c, "k_to_f32"));
-    if (!x3) CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
-    if (!B_mo32 && !x3) {
+    CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
+    if (!B_mo32) {
       float* b32 = nullptr;
       CHECK(ws_get(c, W_BMO32, (size_t)(naux * nbf * nbf), &b32));
       hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * nbf * nbf)), dim3(256), 0, c->stream, B_mo,
@@ -283,10 +305,16 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
   }
   {
     const int64_t maxk = f32 ? kFp32MaxK : ntr;
-    SplitPlan spl = rho_split(c->tiles, naux, ns, ntr, maxk);
-    if (f32) spl = round_chunks(spl, ntr, 32);
+    const int64_t kr = x3 ? kpt : ntr;  // (k length of the product)
+    SplitPlan spl = rho_split(c->tiles, naux, ns, kr, maxk);
+    if (f32) spl = round_chunks(spl, kr, 32);
     auto rho_gemm = [&](auto E, SplitPlan p) -> int {
-      if constexpr (f32) {
+      if constexpr (x3) {
+        Split8 A{splitRA, naux_pad, kpt * naux_pad, 0};
+        Split8 B{splitZ, ns_pad, kpt * ns_pad, 0};
+        return gemm_shape<CT, false, 32>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux,
+                                         ns, kpt, 1, p);
+      } else if constexpr (f32) {
         Strided<true, float> A{Bt32, ntr, 1, 0, naux};
         Strided<true, float> B{Z32, ntr, 1, 0, ns};
         return gemm_shape<CT, false, 32>(c, c->tiles.shape[TU_RHO], "residues/rho", A, B, E, naux,
