@@ -143,12 +143,13 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
                          const double* C, double* T, double* B_mo, Spans* sp,
                          float* B_mo32 = nullptr) {
   const int64_t nn = nbf * nbf;
+  constexpr int BKm = std::is_same<CT, Bf16x3>::value ? 32 : 16;  // (k tile of the instruction)
   {
     Strided<true> A{B_ao, nbf, 1, 0, naux * nbf};
     Strided<false> B{C, 1, nbf, 0, nbf};
     EpiStore E{T, nbf, 0, 0, 1.0};
     SPAN_OPEN(sp, kKMo1);
-    CHECK((gemm_shape<CT, false>(c, c->tiles.shape[TU_MO1], "mo_transform/1", A, B, E, naux * nbf,
+    CHECK((gemm_shape<CT, false, BKm>(c, c->tiles.shape[TU_MO1], "mo_transform/1", A, B, E, naux * nbf,
                                  nbf, nbf, 1)));
     SPAN_CLOSE(sp);
   }
@@ -158,7 +159,7 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
     EpiStore E{B_mo, nbf, nn, 0, 1.0};
     E.c32 = B_mo32;  // FP32 copy for the residue product of the FP32 variant
     SPAN_OPEN(sp, kKMo2);
-    CHECK((gemm_shape<CT, true>(c, c->tiles.shape[TU_MO2], "mo_transform/2", A, B, E, nbf, nbf, nbf,
+    CHECK((gemm_shape<CT, true, BKm>(c, c->tiles.shape[TU_MO2], "mo_transform/2", A, B, E, nbf, nbf, nbf,
                                 naux)));
     SPAN_CLOSE(sp);
   }
@@ -168,9 +169,10 @@ int stage_mo_transform_t(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B
 int stage_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao,
                        const double* C, double* T, double* B_mo, Spans* sp = nullptr,
                        int prec = QSGW_PREC_FP64, float* B_mo32 = nullptr) {
-  // (the split-BF16 variant transforms on the FP32 matrix cores)
-  if (prec != QSGW_PREC_FP64)
+  if (prec == QSGW_PREC_FP32)
     return stage_mo_transform_t<float>(c, nbf, naux, B_ao, C, T, B_mo, sp, B_mo32);
+  if (prec == QSGW_PREC_SPLIT_BF16)
+    return stage_mo_transform_t<Bf16x3>(c, nbf, naux, B_ao, C, T, B_mo, sp, B_mo32);
   return stage_mo_transform_t<double>(c, nbf, naux, B_ao, C, T, B_mo, sp);
 }
 

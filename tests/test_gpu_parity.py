@@ -382,13 +382,19 @@ X3_UNIT = 3 * 2.0 ** -18
 
 @pytest.mark.parametrize("shape", [(5, 7, 2), (37, 53, 9), (130, 260, 17)])
 def test_split_bf16_products(q, ctx, shape):
-    """Casida build and residue product in split-BF16 against FP64, element by
-    element within the split's error bound (sums of absolute terms)."""
+    """MO transform, Casida build and residue product in split-BF16 against
+    FP64, element by element within the split's error bound (sums of absolute
+    terms)."""
     nbf, naux, nocc = shape
     log("split-bf16 products", shape)
     p = problem(*shape)
     u = 2.0 ** -24
     ref = O.mo_transform(p.B_ao, p.C0)
+    got = host(q.qsgw_mo_transform(ctx, dev(p.B_ao), dev(p.C0), precision=q.PREC_SPLIT_BF16))
+    absb = O.mo_transform(np.abs(p.B_ao), np.abs(p.C0))
+    # two products, each within (3 2^-18 + (nbf + 2) 2^-24) of its absolute terms
+    assert np.all(np.abs(got - ref) <= 4 * (X3_UNIT + (nbf + 2) * u) * absb + 1e-300)
+    np.testing.assert_array_equal(got, got.transpose(0, 2, 1))
     M_ref, sq_ref = O.rpa_hermitian(ref, p.eps0, nocc)
     dB, de = dev(ref), dev(p.eps0)
     M, sq = q.qsgw_rpa_build(ctx, dB, de, nocc, precision=q.PREC_SPLIT_BF16)
