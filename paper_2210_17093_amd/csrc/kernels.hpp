@@ -179,6 +179,7 @@ struct EpiPairResidueX3 {
     const int4 ci0 = *reinterpret_cast<const int4*>(colidx + b * nsp + s0);
     const int4 ci1 = *reinterpret_cast<const int4*>(colidx + b * nsp + s0 + 4);
     const int ci[8] = {ci0.x, ci0.y, ci0.z, ci0.w, ci1.x, ci1.y, ci1.z, ci1.w};
+    // (s0 is the same across each wave's work items: loaded as scalars)
     double om[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) om[u] = s0 + u < ns ? Omega[s0 + u] : 0.0;
@@ -227,7 +228,8 @@ struct EpiPairResidueX3 {
     constexpr int NSC = BN / 8, ITEMS = 64 * NSC;
     // (m, k): four consecutive m per (k, chunk)
     for (int q = tid; q < ITEMS; q += 256) {
-      const int mo = q & 3, ko = (q >> 2) & 15, sc = q >> 6;
+      const int mo = q & 3, ko = (q >> 2) & 15;
+      const int sc = __builtin_amdgcn_readfirstlane(q >> 6);  // one chunk per wave
       const int64_t m = mbase + mo, k = kbase + ko, s0 = n0 + 8 * sc;
       if (m >= nbf || k >= nbf || m > k || s0 >= ns) continue;
       double v[8];
@@ -237,7 +239,8 @@ struct EpiPairResidueX3 {
     }
     // (k, m), m < k: sixteen consecutive k per (m, chunk)
     for (int q = tid; q < ITEMS; q += 256) {
-      const int ko = q & 15, mo = (q >> 4) & 3, sc = q >> 6;
+      const int ko = q & 15, mo = (q >> 4) & 3;
+      const int sc = __builtin_amdgcn_readfirstlane(q >> 6);  // one chunk per wave
       const int64_t m = mbase + mo, k = kbase + ko, s0 = n0 + 8 * sc;
       if (m >= nbf || k >= nbf || m >= k || s0 >= ns) continue;
       double v[8];
