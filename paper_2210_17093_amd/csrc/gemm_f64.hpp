@@ -868,6 +868,23 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
   // of the accumulator registers stops the compiler from copying all of them
   // to VGPRs at once, which would halve the occupancy of the K loop.
   if (nk > 0) __syncthreads();  // operand buffers are free once every wave is done
+  if constexpr (has_pass_hook<EPI>::value && X3) {
+    // FP32 accumulators: the whole tile is staged at once as FP32 (the size of
+    // half the tile in FP64) and handed to the epilogue in one pass
+    static_assert(!TRI, "pass epilogues of full tiles");
+    static_assert((size_t)BM * LDC * sizeof(float) <= SMEM_BYTES, "FP32 staging fits");
+    float* Cf = reinterpret_cast<float*>(smem);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          Cf[(wm + i * 16 + MM::row(lane, q)) * LDC + wn + j * 16 + (lane & 15)] = acc[i][j][q];
+    __syncthreads();
+    epi.template pass<BM, BN>(m0, n0, Cf, LDC, tid);
+    __syncthreads();  // (a persistent caller reuses the LDS for its next tile)
+  } else {
   double* Cs = reinterpret_cast<double*>(smem);
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
@@ -902,6 +919,7 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
       }
     }
     __syncthreads();
+  }
   }
 }
 

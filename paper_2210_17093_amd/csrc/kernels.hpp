@@ -151,10 +151,10 @@ struct EpiPairResidue {
 //   ws  = w split into BF16 halves,
 //   whs = w Re 1/(x -+ i eta) split the same way, zero where |x| < thr (those
 //         terms are summed in FP64 apart), x = eps_a - eps_b +- Omega_s.
-// It runs on whole staged passes (kPassHook): 64 pair rows (4 values of m x
-// 16 of k of one pair block) by the tile's columns, eight excitations (one
-// 16-byte chunk per plane) per work item, with the items ordered so that the
-// chunks of consecutive threads are adjacent in memory (consecutive a).
+// It runs on the whole staged tile (kPassHook, FP32 staging): 128 pair rows
+// (one pair block) by the tile's columns, eight excitations (one 16-byte
+// chunk per plane) per work item, with the items ordered so that the chunks
+// of consecutive threads are adjacent in memory (consecutive a).
 struct EpiPairResidueX3 {
   static constexpr bool kPassHook = true;
   double* w;  // nullptr: not written
@@ -210,9 +210,10 @@ struct EpiPairResidueX3 {
     *reinterpret_cast<uint4*>(whs + o) = uint4{h[0], h[1], h[2], h[3]};
     *reinterpret_cast<uint4*>(whs + ps + o) = uint4{l[0], l[1], l[2], l[3]};
   }
-  // pair rows r0 .. r0 + ROWS - 1, columns n0 .. n0 + BN - 1 at Cs[row * ldc + col]
+  // the whole tile: pair rows r0 .. r0 + 127 (one pair block: 8 values of m x
+  // 16 of k), columns n0 .. n0 + BN - 1 at Cs[row * ldc + col]
   template <int ROWS, int BN>
-  __device__ __forceinline__ void pass(int64_t r0, int64_t n0, const double* Cs, int ldc,
+  __device__ __forceinline__ void pass(int64_t r0, int64_t n0, const float* Cs, int ldc,
                                        int tid) const {
     if (w)
       pass_t<ROWS, BN, true>(r0, n0, Cs, ldc, tid);
@@ -220,16 +221,16 @@ struct EpiPairResidueX3 {
       pass_t<ROWS, BN, false>(r0, n0, Cs, ldc, tid);
   }
   template <int ROWS, int BN, bool HAS_W>
-  __device__ __forceinline__ void pass_t(int64_t r0, int64_t n0, const double* Cs, int ldc,
+  __device__ __forceinline__ void pass_t(int64_t r0, int64_t n0, const float* Cs, int ldc,
                                          int tid) const {
-    static_assert(ROWS == 64 && BN % 8 == 0, "pair-block passes of 4 x 16 pairs");
+    static_assert(ROWS == 128 && BN % 8 == 0, "one pair block of 8 x 16 pairs per tile");
     const int32_t bk = blocks[r0 >> 7];
-    const int64_t mbase = (int64_t)(bk >> 16) * 8 + (r0 & 127) / 16, kbase = (int64_t)(bk & 0xffff) * 16;
-    constexpr int NSC = BN / 8, ITEMS = 64 * NSC;
-    // (m, k): four consecutive m per (k, chunk)
+    const int64_t mbase = (int64_t)(bk >> 16) * 8, kbase = (int64_t)(bk & 0xffff) * 16;
+    constexpr int NSC = BN / 8, ITEMS = 128 * NSC;
+    // (m, k): the eight m of one (k, chunk) fill one 128-byte line
     for (int q = tid; q < ITEMS; q += 256) {
-      const int mo = q & 3, ko = (q >> 2) & 15;
-      const int sc = __builtin_amdgcn_readfirstlane(q >> 6);  // one chunk per wave
+      const int mo = q & 7, ko = (q >> 3) & 15;
+      const int sc = __builtin_amdgcn_readfirstlane(q >> 7);  // one chunk per wave
       const int64_t m = mbase + mo, k = kbase + ko, s0 = n0 + 8 * sc;
       if (m >= nbf || k >= nbf || m > k || s0 >= ns) continue;
       double v[8];
@@ -237,10 +238,10 @@ struct EpiPairResidueX3 {
       for (int u = 0; u < 8; ++u) v[u] = Cs[(mo * 16 + ko) * ldc + 8 * sc + u];
       put<HAS_W>(m, k, s0, v);
     }
-    // (k, m), m < k: sixteen consecutive k per (m, chunk)
+    // (k, m), m < k: the sixteen k of one (m, chunk) fill two lines
     for (int q = tid; q < ITEMS; q += 256) {
-      const int ko = q & 15, mo = (q >> 4) & 3;
-      const int sc = __builtin_amdgcn_readfirstlane(q >> 6);  // one chunk per wave
+      const int ko = q & 15, mo = (q >> 4) & 7;
+      const int sc = __builtin_amdgcn_readfirstlane(q >> 7);  // one chunk per wave
       const int64_t m = mbase + mo, k = kbase + ko, s0 = n0 + 8 * sc;
       if (m >= nbf || k >= nbf || m >= k || s0 >= ns) continue;
       double v[8];
