@@ -186,18 +186,27 @@ struct EpiPairResidueX3 {
     float wv[8], hv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int64_t s = s0 + u;
-      const bool ok = s < ns;
+      const bool ok = s0 + u < ns;
       const double x = ok ? ea + sg * om[u] : 1.0;
       const float xf = (float)x;
       const float vf = ok ? (float)v[u] : 0.0f;
       const float g = xf * __builtin_amdgcn_rcpf(fmaf(xf, xf, eta2));
       wv[u] = vf;
       hv[u] = fabs(x) >= thr ? vf * g : 0.0f;
-      if (ok) {
-        if (ci[u] >= 0) wN[(int64_t)ci[u] * nbf + a] = vf;
-        if (HAS_W) w[(a * nbf + b) * ns + s] = v[u];
-      }
+    }
+    // near-pole columns are rare: one wave-wide test skips the eight
+    // conditional stores when no lane has any (columns past ns are never near)
+    // (the AND keeps the sign bit only if every index is -1)
+    const bool near = (ci[0] & ci[1] & ci[2] & ci[3] & ci[4] & ci[5] & ci[6] & ci[7]) >= 0;
+    if (__any(near)) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (ci[u] >= 0) wN[(int64_t)ci[u] * nbf + a] = wv[u];
+    }
+    if (HAS_W) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (s0 + u < ns) w[(a * nbf + b) * ns + s0 + u] = v[u];
     }
     const int64_t o = ((b * nsp + s0) / 8 * cs + a) * 8;
     uint32_t h[4], l[4];
