@@ -794,39 +794,6 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
-  } else if constexpr (false) {
-    // Both operands pre-split (every tile full): loads run two k tiles ahead
-    // through two register sets, so a load has two tiles of products to land.
-    uint32_t xa[2][EA], xb[2][EB];
-    auto ld = [&](int64_t kbase, int u) {
-      load_tile_kb<BM, BK>(A, batch, m0, kbase, kb1, tid, xa[u]);
-      load_tile_kb<BN, BK>(B, batch, n0, kbase, kb1, tid, xb[u]);
-    };
-    auto st = [&](int buf, int u) {
-      sstore_split(xa[u], As[2 * buf], As[2 * buf + 1], ChunkMap<BM, BK>());
-      sstore_split(xb[u], Bs[2 * buf], Bs[2 * buf + 1], ChunkMap<BN, BK>());
-    };
-    if (nk > 0) {
-      ld(kb0, 0);
-      st(0, 0);
-      if (nk > 1) ld(kb0 + BK, 1);
-      __syncthreads();
-    }
-    // Step it computes buffer it % 2, holds tile it + 1 in registers
-    // (1 - it % 2), loads tile it + 2 into registers it % 2 (their tile it
-    // went to LDS one step earlier) and stores tile it + 1 into the other
-    // buffer (its tile it - 1 was consumed before the previous barrier).
-    for (int64_t it = 0; it < nk; it += 2) {
-      if (it + 2 < nk) ld(kb0 + (it + 2) * BK, 0);
-      mma_x3(0, std::false_type());
-      if (it + 1 < nk) st(1, 1);
-      __syncthreads();
-      if (it + 1 >= nk) break;
-      if (it + 3 < nk) ld(kb0 + (it + 3) * BK, 1);
-      mma_x3(1, std::false_type());
-      if (it + 2 < nk) st(0, 0);
-      __syncthreads();
-    }
   } else {
     if (nk > 0) {
       gload(kb0);
