@@ -329,6 +329,10 @@ def main():
                          "qsGW matrix) with Z = I and Omega = Delta in place of the eigensolve, "
                          "which is not run under counter collection, with the benchmark's tile "
                          "table and --precision (fp64 unless fp32 or bf16x3); prints no timing")
+    ap.add_argument("--iterate-probe", action="store_true",
+                    help="for rocprofv3 --pmc passes restricted to one kernel "
+                         "(--kernel-include-regex): run one qsgw_iterate of --config in "
+                         "--precision with the benchmark's tile table; prints no timing")
     ap.add_argument("--train-molecules", type=int, default=1024,
                     help="cfg5: training molecules (the full protocol names 20,000)")
     ap.add_argument("--test-molecules", type=int, default=256,
@@ -374,6 +378,22 @@ def main():
             q.qsgw_sigma_qs(ctx, w, e0, Om, p.nocc, cfg["eta"], wh=wh)
             torch.cuda.synchronize()
         print(json.dumps({"counter_probe": args.config}), flush=True)
+        return
+
+    if args.iterate_probe:
+        cfg = CONFIGS[args.config]
+        p = make_config(args.config)
+        dev = torch.device("cuda:0")
+        B = torch.from_numpy(p.B_ao).to(dev)
+        C = torch.from_numpy(p.C0.copy()).to(dev)
+        e = torch.from_numpy(p.eps0.copy()).to(dev)
+        prec = {"fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}.get(args.precision, q.PREC_FP64)
+        with q.Context() as ctx:
+            ctx.set_tiles(tuned_tiles(args.config, args.precision if prec != q.PREC_FP64 else None))
+            h = q.qsgw_hf_core(ctx, B, C, e, p.nocc)
+            q.qsgw_iterate(ctx, B, h, p.nocc, e, C, cfg["eta"], tol=0.0, max_iter=1, precision=prec)
+            torch.cuda.synchronize()
+        print(json.dumps({"iterate_probe": args.config, "precision": args.precision}), flush=True)
         return
 
     if args.config == "cfg4":

@@ -61,9 +61,10 @@ extern "C" {
 /* Split-BF16 products: every FP32 operand x is split into x = hi + lo (hi =
    bf16(x), lo = bf16(x - hi)) and a*b is taken as hi*hi + hi*lo + lo*hi on
    BF16 matrix cores with FP32 accumulation (relative error about 2^-16 per
-   product term), FP64 across K chunks.  It applies to the MO transform, the
-   Casida build, the residue products and the far-from-pole part of the qsGW
-   matrix.  Not available in qsgw_iterate_batched (QSGW_ERR_UNSUPPORTED). */
+   product term), FP64 across K chunks.  It applies to the Casida build, the
+   residue products and the far-from-pole part of the qsGW matrix; the MO
+   transform runs on the FP32 matrix cores.  Not available in
+   qsgw_iterate_batched (QSGW_ERR_UNSUPPORTED). */
 #define QSGW_PREC_SPLIT_BF16 2
 
 /* qsgw_sigma modes. */
@@ -98,7 +99,7 @@ int qsgw_last_stage_ms(const qsgw_ctx* ctx, double* ms, int n);
  * B_ao: [naux][nbf][nbf], symmetric in its last two indices.
  * C:    [nbf][nbf], column m holds MO m.
  * B_mo: [naux][nbf][nbf] out; written exactly symmetric in (m, n).
- * precision: any QSGW_PREC_*.
+ * precision: any QSGW_PREC_*; QSGW_PREC_SPLIT_BF16 runs FP32 products here.
  * Errors: nbf < 1, naux < 1, NULL pointers, an unknown precision.
  */
 int qsgw_mo_transform(qsgw_ctx* ctx, int64_t nbf, int64_t naux, const double* B_ao,

@@ -948,16 +948,30 @@ struct EpiStore {
   int64_t sz;       // stride per split index (partial sums)
   double alpha;
   float* c32 = nullptr;  // optional FP32 copy, same layout (not with split-K)
+  bool nt = false;  // non-temporal stores: large outputs read by a later kernel, whole lines
+                    // (partly written lines of a non-temporal store reach HBM unmerged)
+  __device__ __forceinline__ void put(double* p, double x) const {
+    if (nt)
+      __builtin_nontemporal_store(x, p);
+    else
+      *p = x;
+  }
+  __device__ __forceinline__ void put(float* p, float x) const {
+    if (nt)
+      __builtin_nontemporal_store(x, p);
+    else
+      *p = x;
+  }
   __device__ __forceinline__ void operator()(int64_t b, int64_t z, int64_t m, int64_t n, double v,
                                              bool mirror) const {
     double* cb = c + b * sb + z * sz;
     const double x = alpha * v;
-    cb[m * ldc + n] = x;
-    if (mirror) cb[n * ldc + m] = x;
+    put(&cb[m * ldc + n], x);
+    if (mirror) put(&cb[n * ldc + m], x);
     if (c32) {
       float* fb = c32 + b * sb;
-      fb[m * ldc + n] = (float)x;
-      if (mirror) fb[n * ldc + m] = (float)x;
+      put(&fb[m * ldc + n], (float)x);
+      if (mirror) put(&fb[n * ldc + m], (float)x);
     }
   }
 };

@@ -102,12 +102,14 @@ struct EpiPairResidue {
   __device__ __forceinline__ double xval(int64_t a, int64_t b, double om) const {
     return eps[a] - eps[b] + (b < nocc ? om : -om);
   }
+  // (the residues are written once and read by later kernels: non-temporal
+  // stores keep them from evicting the product's operand panels from L2)
   __device__ __forceinline__ void store(int64_t a, int64_t b, int64_t s, double v) const {
     const int64_t i = (a * nbf + b) * ns + s;
-    if (w) w[i] = v;
+    if (w) __builtin_nontemporal_store(v, &w[i]);
     if (wh) {
       const double x = xval(a, b, Omega[s]);
-      wh[i] = v * (x / (x * x + eta * eta));
+      __builtin_nontemporal_store(v * (x / (x * x + eta * eta)), &wh[i]);
     }
   }
   // Reduced-precision variants: the FP32 copies, with the pole weight of the
@@ -120,9 +122,9 @@ struct EpiPairResidue {
     const float xf = (float)x;
     const float vf = (float)v;
     const float g = xf * __builtin_amdgcn_rcpf(fmaf(xf, xf, eta2));
-    if (w) w[i] = v;
-    wh32[i] = fabs(x) >= thr ? vf * g : 0.0f;
-    w32[i] = vf;
+    if (w) __builtin_nontemporal_store(v, &w[i]);
+    __builtin_nontemporal_store(fabs(x) >= thr ? vf * g : 0.0f, &wh32[i]);
+    __builtin_nontemporal_store(vf, &w32[i]);
   }
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t r, int64_t s, double v,
                                              bool) const {
@@ -208,16 +210,20 @@ struct EpiPairResidueX3 {
       for (int u = 0; u < 8; ++u)
         if (s0 + u < ns) w[(a * nbf + b) * ns + s0 + u] = v[u];
     }
+    // The split operands (7.5 GB at N_b = 300) are written once and read by a
+    // later kernel: non-temporal stores keep them from evicting the product's
+    // own operand panels from L2.
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const int64_t o = ((b * nsp + s0) / 8 * cs + a) * 8;
     uint32_t h[4], l[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) split_bf16x2(wv[2 * u], wv[2 * u + 1], h[u], l[u]);
-    *reinterpret_cast<uint4*>(ws + o) = uint4{h[0], h[1], h[2], h[3]};
-    *reinterpret_cast<uint4*>(ws + ps + o) = uint4{l[0], l[1], l[2], l[3]};
+    __builtin_nontemporal_store(u32x4{h[0], h[1], h[2], h[3]}, reinterpret_cast<u32x4*>(ws + o));
+    __builtin_nontemporal_store(u32x4{l[0], l[1], l[2], l[3]}, reinterpret_cast<u32x4*>(ws + ps + o));
 #pragma unroll
     for (int u = 0; u < 4; ++u) split_bf16x2(hv[2 * u], hv[2 * u + 1], h[u], l[u]);
-    *reinterpret_cast<uint4*>(whs + o) = uint4{h[0], h[1], h[2], h[3]};
-    *reinterpret_cast<uint4*>(whs + ps + o) = uint4{l[0], l[1], l[2], l[3]};
+    __builtin_nontemporal_store(u32x4{h[0], h[1], h[2], h[3]}, reinterpret_cast<u32x4*>(whs + o));
+    __builtin_nontemporal_store(u32x4{l[0], l[1], l[2], l[3]}, reinterpret_cast<u32x4*>(whs + ps + o));
   }
   // the whole tile: pair rows r0 .. r0 + 127 (one pair block: 8 values of m x
   // 16 of k), columns n0 .. n0 + BN - 1 at Cs[row * ldc + col]

@@ -392,6 +392,7 @@ def test_split_bf16_products(q, ctx, shape):
     ref = O.mo_transform(p.B_ao, p.C0)
     got = host(q.qsgw_mo_transform(ctx, dev(p.B_ao), dev(p.C0), precision=q.PREC_SPLIT_BF16))
     absb = O.mo_transform(np.abs(p.B_ao), np.abs(p.C0))
+    # (FP32 products for this variant; held to the split bound, which they meet)
     # two products, each within (3 2^-18 + (nbf + 2) 2^-24) of its absolute terms
     assert np.all(np.abs(got - ref) <= 4 * (X3_UNIT + (nbf + 2) * u) * absb + 1e-300)
     np.testing.assert_array_equal(got, got.transpose(0, 2, 1))
