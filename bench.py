@@ -50,15 +50,15 @@ X3_PEAK_TFLOPS = round(2500.0 / 3, 1)  # dense BF16 matrix, 3 products per split
 HARTREE_MEV = 27211.386
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of a kernel at the cfg2 workload, from the rocprofv3
+# HBM bytes per launch of the dominant kernel at the cfg2 workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes scaled by the plain-copy calibration
-# (profiles/residue_w_cfg2_hbm_counters.md).  The FP32 variant's residue kernel writes
-# FP32 residues that the C-ABI counter probe cannot reproduce without an eigensolve.
-# Only valid for the kernel build
-# the counters were taken on: set an entry to None whenever that kernel changes.
+# (profiles/residue_w_split_bf16_cfg2_hbm_counters.md, profiles/residue_w_cfg2_hbm_counters.md).
+# Only valid for the kernel build the counters were taken on: set an entry to None
+# whenever that kernel changes.
 MEASURED_TRAFFIC_BYTES = {
-    ("cfg2", "fp64", "residue_w"): 58.00e9,
-    ("cfg2", "fp32", "residue_w"): None,  # kernel changed since its counters were taken
+    ("cfg2", "bf16x3", "residue_w"): 19.86e9,
+    ("cfg2", "fp64", "residue_w"): 66.05e9,
+    ("cfg2", "fp32", "residue_w"): 23.46e9,
 }
 
 
