@@ -34,6 +34,16 @@ its reason in the design notes of the repository):
   * The one-body part of Eq. (6), T + V_ext, is a synthetic matrix h built so
     that the starting (eps0, C0) is an exact Hartree-Fock fixed point.
   * No mixing by default; convergence when max_m |eps_m' - eps_m| < tol.
+  * Eq. (20), second-order exchange with p occupied: the printed integral
+    (pi|an) is read as (pa|in).  The printed form matches the second-order
+    self-energy of antisymmetrised spin-orbital integrals for virtual p only;
+    for occupied p it breaks the m <-> n symmetry that self-energy has for
+    real orbitals, while (pa|in) restores both.
+  * Eq. (21) takes the real part, as Eq. (19): V_mn = 1/2 Re[Sigma_mn(eps_n)
+    + Sigma_nm(eps_m)].
+
+Also here, beyond the qsGW iteration: the MP2 self-energy, Eq. (20), and the
+qsMP2 potential, Eq. (21).
 """
 from __future__ import annotations
 
@@ -273,3 +283,82 @@ def sigma_diag_derivative(w, eps, Omega, nocc, eta, m, omega) -> complex:
     """d Sigma_mm / d omega of Eq. (17): -sum_{k s} w_mks^2 / d_ks^2."""
     d = _pole_denominators(omega, eps, Omega, nocc, eta)
     return complex(-np.sum(w[m] ** 2 / d ** 2))
+
+
+# ------------------------------------------------------------ qsMP2 -------
+def _mp2_integrals(B_mo: np.ndarray, nocc: int, m_rows=None, n_rows=None):
+    """RI integrals of Eq. (20) over (p, i, a), p any state, i occupied, a virtual.
+
+    L[m, p, i, a] = (mp|ia)              for m in m_rows
+    R[n, p, i, a] = (pn|ai)              (direct, for n in n_rows)
+    X[n, p, i, a] = (pi|an), p virtual;  (pa|in), p occupied  (exchange)
+    every (kl|rs) = sum_P B^P_{kl} B^P_{rs}.
+    """
+    nb = B_mo.shape[1]
+    occ, vir = slice(0, nocc), slice(nocc, nb)
+    m_rows = np.arange(nb) if m_rows is None else np.asarray(m_rows)
+    n_rows = np.arange(nb) if n_rows is None else np.asarray(n_rows)
+    Bia = B_mo[:, occ, vir]                                   # [P][i][a]
+    L = np.einsum("Pmp,Pia->mpia", B_mo[:, m_rows, :], Bia)
+    R = np.einsum("Ppn,Pai->npia", B_mo[:, :, n_rows], B_mo[:, vir, occ])
+    X = np.empty_like(R)
+    # p virtual: (pi|an) = sum_P B^P_{pi} B^P_{an}
+    X[:, nocc:] = np.einsum("Ppi,Pan->npia", B_mo[:, vir, occ], B_mo[:, vir][:, :, n_rows])
+    # p occupied: (pa|in) = sum_P B^P_{pa} B^P_{in}
+    X[:, :nocc] = np.einsum("Ppa,Pin->npia", B_mo[:, occ, vir], B_mo[:, occ][:, :, n_rows])
+    return L, R, X
+
+
+def _mp2_denominators(omega, eps: np.ndarray, nocc: int, eta: float) -> np.ndarray:
+    """Bracket of Eq. (20) for one frequency, as an array over (p, i, a):
+    f_p / (omega + eps_a - eps_i - eps_p - i eta) for occupied p,
+    (1 - f_p) / (omega + eps_i - eps_a - eps_p + i eta) for virtual p."""
+    ep = eps[:, None, None]
+    ei = eps[None, :nocc, None]
+    ea = eps[None, None, nocc:]
+    occ_p = (np.arange(eps.size) < nocc)[:, None, None]
+    return np.where(occ_p, 1.0 / (omega + ea - ei - ep - 1j * eta),
+                    1.0 / (omega + ei - ea - ep + 1j * eta))
+
+
+def sigma_mp2(B_mo: np.ndarray, eps: np.ndarray, nocc: int, eta: float, omegas,
+              terms: str = "both") -> np.ndarray:
+    """MP2 correlation self-energy, Eq. (20), closed shell, real orbitals.
+
+    Returns the complex matrix S[m, n] = Sigma_mn(omegas[n]): column n is taken
+    at its own frequency (a scalar omegas gives Sigma(omega) itself).  The sum
+    over sigma' of the direct term gives its factor 2; the exchange term has
+    no spin sum.  terms = "direct" or "sox" keeps one of the two sums.
+    """
+    nb = eps.size
+    om = np.broadcast_to(np.asarray(omegas, dtype=np.float64), (nb,))
+    L, R, X = _mp2_integrals(B_mo, nocc)
+    fd = {"both": 1.0, "direct": 1.0, "sox": 0.0}[terms]
+    fx = {"both": 1.0, "direct": 0.0, "sox": 1.0}[terms]
+    S = np.empty((nb, nb), dtype=np.complex128)
+    for n in range(nb):
+        g = _mp2_denominators(om[n], eps, nocc, eta)
+        S[:, n] = np.einsum("mpia,pia->m", L, (2.0 * fd * R[n] - fx * X[n]) * g)
+    return S
+
+
+def sigma_mp2_entry(B_mo: np.ndarray, eps: np.ndarray, nocc: int, eta: float, omega: float,
+                    m: int, n: int) -> complex:
+    """One element Sigma_mn(omega) of Eq. (20), from B_mo without the four-index
+    tensor (for sampled checks at sizes where the full matrix is too costly)."""
+    L, R, X = _mp2_integrals(B_mo, nocc, [m], [n])
+    g = _mp2_denominators(omega, eps, nocc, eta)
+    return complex(np.sum(L[0] * (2.0 * R[0] - X[0]) * g))
+
+
+def qsmp2_potential(B_mo: np.ndarray, eps: np.ndarray, nocc: int, eta: float) -> np.ndarray:
+    """Eq. (21): V_mn = 1/2 Re[Sigma_mn(eps_n) + Sigma_nm(eps_m)]."""
+    S = sigma_mp2(B_mo, eps, nocc, eta, eps)   # S[m, n] = Sigma_mn(eps_n)
+    return 0.5 * np.real(S + S.T)
+
+
+def qsmp2_entry(B_mo: np.ndarray, eps: np.ndarray, nocc: int, eta: float, m: int, n: int) -> float:
+    """One element of Eq. (21) from two elements of Eq. (20)."""
+    a = sigma_mp2_entry(B_mo, eps, nocc, eta, eps[n], m, n)
+    b = sigma_mp2_entry(B_mo, eps, nocc, eta, eps[m], n, m)
+    return 0.5 * (a + b).real

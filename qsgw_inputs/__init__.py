@@ -12,5 +12,6 @@ from .generator import (  # noqa: F401
     batch_shapes,
     cfg1_omega_grid,
     make_config,
+    make_mo_tensor,
     make_problem,
 )

@@ -15,7 +15,18 @@ module synthesises inputs with the same shapes and structure instead:
   sign(diag R)), so the synthetic AO basis is orthonormal (S = I).
 
 Draw order from ``numpy.random.default_rng(seed)``: U, the Gaussian behind L,
-eps_occ, eps_virt, the Gaussian behind C.  Nothing here evaluates any
+eps_occ, eps_virt, the Gaussian behind C.
+
+Because Q has orthonormal columns, sum_P B^P_{ab} B^P_{cd} = sum_r s_r^2 U_ra
+U_rb U_rc U_rd is symmetric under every permutation of (a, b, c, d): more
+symmetry than molecular integrals have (those are symmetric within each pair
+and under the exchange of the two pairs only).  ``make_mo_tensor`` draws a
+general symmetric RI tensor instead, for the terms whose index pairing that
+extra symmetry would hide (the exchange term of the MP2 self-energy):
+
+* B^P_{mn} = g (G^P_{mn} + G^P_{nm}) / 2 with G ~ N(0, 1), g fixed so that
+  the mean (m m|m m) = sum_P (B^P_{mm})^2 is 0.5 Ha times the coupling scale;
+  orbital energies drawn as above.  Draw order: G, eps_occ, eps_virt.  Nothing here evaluates any
 equation of the method; the core Hamiltonian that makes (eps, C) a
 Hartree-Fock fixed point is built by each implementation on its own.
 """
@@ -91,6 +102,23 @@ def make_problem(nbf: int, naux: int, nocc: int, rank: int, decay: float,
     return Problem(nbf, naux, nocc, np.ascontiguousarray(B),
                    np.ascontiguousarray(C), eps, meta)
 
+
+
+def make_mo_tensor(nbf: int, naux: int, nocc: int, seed: int,
+                   coupling: float = COUPLING):
+    """General symmetric RI tensor in the MO basis and sorted orbital energies.
+
+    Returns (B_mo [naux][nbf][nbf], eps [nbf]); see the module docstring.
+    """
+    if not (0 < nocc < nbf) or naux < 1:
+        raise ValueError("need 0 < nocc < nbf and naux >= 1")
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((naux, nbf, nbf))
+    eps_occ = np.sort(rng.uniform(-30.0, -0.3, nocc))
+    eps_virt = np.sort(rng.uniform(0.05, 20.0, nbf - nocc))
+    g = np.sqrt(coupling * 0.5 / naux)
+    B = g * 0.5 * (G + G.transpose(0, 2, 1))
+    return np.ascontiguousarray(B), np.concatenate([eps_occ, eps_virt])
 
 
 # The workloads of the benchmark configurations.  cfg1..cfg3 are single

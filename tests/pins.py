@@ -198,3 +198,50 @@ def jk_four_index(B_ao, D):
     J = np.einsum("mnlt,lt->mn", eri, 2.0 * D)
     K = np.einsum("lt,mltn->mn", D, eri)
     return J, K
+
+
+# ------------------------------------------------------------ P12 --------
+def sigma2_spin_orbital(B_mo, eps, nocc, eta, omega):
+    """Second-order (MP2) self-energy from antisymmetrised spin-orbital integrals.
+
+    Spin orbital q = 2 k + spin has energy eps_k; <pq||rs> = <pq|rs> - <pq|sr>
+    with <pq|rs> = (pr|qs) delta(spin p, spin r) delta(spin q, spin s).  With
+    i, j occupied and a, b virtual spin orbitals:
+      Sigma_pq(omega) = 1/2 sum_{ija} <pa||ij><ij||qa> / (omega + e_a - e_i - e_j - i eta)
+                      + 1/2 sum_{iab} <pi||ab><ab||qi> / (omega + e_i - e_a - e_b + i eta).
+    Returns the spatial matrix (spin-up block) at one frequency.
+    """
+    nb = eps.size
+    eri = mo_eri(B_mo)                          # chemist (kl|rs)
+    ns = 2 * nb
+    orb = np.arange(ns) // 2
+    spin = np.arange(ns) % 2
+    # <pq|rs> = (pr|qs) with spin deltas
+    chem = eri[np.ix_(orb, orb, orb, orb)]      # (pr|qs) indexed [p][r][q][s]
+    same_pr = spin[:, None] == spin[None, :]
+    phys = np.einsum("prqs->pqrs", chem) * same_pr[:, None, :, None] * same_pr[None, :, None, :]
+    anti = phys - np.swapaxes(phys, 2, 3)
+    e = eps[orb]
+    O_ = np.where(orb < nocc)[0]
+    V_ = np.where(orb >= nocc)[0]
+    d2h = omega + e[V_][None, None, :] - e[O_][:, None, None] - e[O_][None, :, None] - 1j * eta
+    d2p = omega + e[O_][:, None, None] - e[V_][None, :, None] - e[V_][None, None, :] + 1j * eta
+    up = np.arange(0, ns, 2)
+    t1 = 0.5 * np.einsum("pAij,ijqA,ijA->pq", anti[np.ix_(up, V_, O_, O_)],
+                         anti[np.ix_(O_, O_, up, V_)], 1.0 / d2h)
+    t2 = 0.5 * np.einsum("piab,abqi,iab->pq", anti[np.ix_(up, O_, V_, V_)],
+                         anti[np.ix_(V_, V_, up, O_)], 1.0 / d2p)
+    return t1 + t2
+
+
+# ------------------------------------------------------------ P13 --------
+def mp2_two_level_closed_form(B, eps0, eps1, eta, omega):
+    """N_b = 2, n_occ = 1, N_aux = 1 with B = [[B00, b], [b, B11]]: every
+    integral is (mk|rs) = B_mk B_rs and the direct and exchange terms of the
+    second-order self-energy combine to
+      Sigma_mn = b^2 [B_m0 B_n0 / (omega + eps1 - 2 eps0 - i eta)
+                      + B_m1 B_n1 / (omega + eps0 - 2 eps1 + i eta)].
+    """
+    b = B[0, 1]
+    return b * b * (np.outer(B[:, 0], B[:, 0]) / (omega + eps1 - 2 * eps0 - 1j * eta)
+                    + np.outer(B[:, 1], B[:, 1]) / (omega + eps0 - 2 * eps1 + 1j * eta))

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import pins
-from qsgw_inputs import cfg1_omega_grid, make_config, make_problem
+from qsgw_inputs import cfg1_omega_grid, make_config, make_mo_tensor, make_problem
 
 
 def tiny(nbf=6, naux=14, nocc=2, seed=3, coupling=1.0):
@@ -287,6 +287,85 @@ def test_mutant_sigma_sign_caught_by_closed_form(monkeypatch):
     _, _, sig_ref = pins.one_transition_closed_form(eps[0], eps[1], 0.3, 0.7, -0.2, 1e-3, grid)
     sig = O.sigma_element(w, eps, Om, 1, 1e-3, 0, 0, grid)
     assert not np.allclose(sig, sig_ref[0], rtol=1e-8)
+
+
+# ------------------------------------------------------- P12-P14: qsMP2 --
+@pytest.mark.parametrize("nbf,naux,nocc,seed", [(5, 9, 2, 1), (6, 4, 3, 2), (4, 6, 1, 7)])
+def test_p12_mp2_is_spin_orbital_second_order(nbf, naux, nocc, seed):
+    """Eq. (20) with the exchange reading equals the second-order self-energy
+    of antisymmetrised spin-orbital integrals, complex, every (m, n)."""
+    # a general RI tensor: the generator's B has fully symmetric integrals,
+    # which would hide the index pairing of the exchange term
+    B_mo, eps = make_mo_tensor(nbf, naux, nocc, seed, coupling=1.0)
+    for om, eta in ((0.37, 0.05), (-1.3, 1e-3), (eps[0], 0.02)):
+        S = O.sigma_mp2(B_mo, eps, nocc, eta, om)
+        T = pins.sigma2_spin_orbital(B_mo, eps, nocc, eta, om)
+        np.testing.assert_allclose(S, T, rtol=0, atol=1e-12 * np.abs(T).max())
+        np.testing.assert_allclose(S, S.T, rtol=0, atol=1e-12 * np.abs(T).max())
+
+
+@pytest.mark.parametrize("B00,b,B11", [(0.7, 0.3, -0.2), (-0.1, 0.8, 0.5)])
+def test_p13_mp2_two_level_closed_form(B00, b, B11):
+    B_mo = np.array([[[B00, b], [b, B11]]])
+    eps = np.array([-0.6, 0.35])
+    for om in (-0.9, 0.1, 1.7):
+        S = O.sigma_mp2(B_mo, eps, 1, 1e-3, om)
+        ref = pins.mp2_two_level_closed_form(B_mo[0], eps[0], eps[1], 1e-3, om)
+        np.testing.assert_allclose(S, ref, rtol=1e-13, atol=1e-16)
+
+
+def test_p14_qsmp2_potential_and_direct_limit():
+    """Eq. (21) from elements of Eq. (20); the direct sum is the weak-coupling
+    limit of the GW self-energy (Sigma^GW - Sigma^MP2,direct ~ lambda^6)."""
+    B_mo, eps = make_mo_tensor(7, 12, 3, 11, coupling=1.0)
+    V = O.qsmp2_potential(B_mo, eps, 3, 0.01)
+    np.testing.assert_array_equal(V, V.T)
+    for m, n in ((0, 0), (1, 5), (6, 2)):
+        a = pins.sigma2_spin_orbital(B_mo, eps, 3, 0.01, eps[n])[m, n]
+        b = pins.sigma2_spin_orbital(B_mo, eps, 3, 0.01, eps[m])[n, m]
+        assert abs(V[m, n] - 0.5 * (a + b).real) < 1e-12 * abs(V).max()
+        assert abs(O.qsmp2_entry(B_mo, eps, 3, 0.01, m, n) - V[m, n]) < 1e-12 * abs(V).max()
+    q = tiny(nbf=5, naux=10, nocc=2, seed=5)
+    diffs = []
+    for lam in (0.01, 0.02):
+        Bl = O.mo_transform(q.B_ao * lam, q.C0)
+        M, sq = O.rpa_hermitian(Bl, q.eps0, q.nocc)
+        Om, XpY = O.rpa_solve(M, sq)
+        w = O.residues(Bl, XpY, q.nocc)
+        gw = O.sigma_element(w, q.eps0, Om, q.nocc, 0.05, 1, 2, [0.37])[0]
+        d = O.sigma_mp2(Bl, q.eps0, q.nocc, 0.05, 0.37, terms="direct")[1, 2]
+        x = O.sigma_mp2(Bl, q.eps0, q.nocc, 0.05, 0.37, terms="sox")[1, 2]
+        full = O.sigma_mp2(Bl, q.eps0, q.nocc, 0.05, 0.37)[1, 2]
+        assert abs(full - d - x) < 1e-14 * abs(full) + 1e-300
+        diffs.append(abs(gw - d))
+    assert 54.0 < diffs[1] / diffs[0] < 74.0
+
+
+def test_mutant_mp2_printed_exchange_caught(monkeypatch):
+    """The exchange integral of Eq. (20) exactly as printed for occupied p,
+    (pi|an), fails the spin-orbital pin; so does dropping the spin factor 2."""
+    import oracle.qsgw_oracle as OM
+    orig = OM._mp2_integrals
+
+    def printed(B_mo, nocc, m_rows=None, n_rows=None):
+        L, R, X = orig(B_mo, nocc, m_rows, n_rows)
+        n_rows_ = np.arange(B_mo.shape[1]) if n_rows is None else np.asarray(n_rows)
+        X = X.copy()
+        X[:, :nocc] = np.einsum("Ppi,Pan->npia", B_mo[:, :nocc, :nocc],
+                                B_mo[:, nocc:][:, :, n_rows_])
+        return L, R, X
+
+    def no_spin(B_mo, nocc, m_rows=None, n_rows=None):
+        L, R, X = orig(B_mo, nocc, m_rows, n_rows)
+        return L, 0.5 * R, X
+
+    B_mo, eps = make_mo_tensor(5, 9, 2, 1, coupling=1.0)
+    T = pins.sigma2_spin_orbital(B_mo, eps, 2, 0.05, 0.37)
+    for mutant in (printed, no_spin):
+        monkeypatch.setattr(OM, "_mp2_integrals", mutant)
+        S = O.sigma_mp2(B_mo, eps, 2, 0.05, 0.37)
+        assert np.abs(S - T).max() > 1e-6 * np.abs(T).max()
+    monkeypatch.setattr(OM, "_mp2_integrals", orig)
 
 
 # ------------------------------------------------------------ generator ---
