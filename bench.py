@@ -132,6 +132,60 @@ def cpu_baseline(p, eta, hot_flops):
                 stage_s=t)
 
 
+def mp2_flops(nbf, naux, nocc):
+    """Algorithmic FLOPs of one qsMP2 potential: the integrals (mp|ia) on pairs
+    m <= p (symmetric) and the contraction G = D Rh^T over k = (p, i, a)."""
+    ntr = nocc * (nbf - nocc)
+    return nbf * (nbf + 1) * ntr * naux + 2 * nbf ** 3 * ntr
+
+
+def mp2_cpu_baseline(B_mo, eps, nocc, eta, flops):
+    """Time the oracle's element route (Eq. 21 from two elements of Eq. 20)
+    on two sampled elements and scale to the nbf (nbf + 1) / 2 independent ones."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    nbf = eps.size
+    pairs = [(0, nbf - 1), (nocc - 1, nocc)]
+    t0 = time.perf_counter()
+    for m, n in pairs:
+        O.qsmp2_entry(B_mo, eps, nocc, eta, m, n)
+    per = (time.perf_counter() - t0) / len(pairs)
+    est = per * nbf * (nbf + 1) / 2
+    return dict(value=flops / est / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
+                sample=(f"oracle qsmp2_entry on {len(pairs)} elements, scaled to the "
+                        f"{nbf * (nbf + 1) // 2} independent elements; est. s/potential = {est:.1f}"))
+
+
+def bench_mp2(args, q, torch, ctx, B, C0, e0, p, eta):
+    """qsMP2 potential (Eqs. 20-21) from the starting orbitals, FP64."""
+    B_mo = q.qsgw_mo_transform(ctx, B, C0)
+    V = torch.empty((p.nbf, p.nbf), dtype=torch.float64, device=B.device)
+    for _ in range(max(1, args.warmup)):
+        q.qsgw_mp2_sigma(ctx, B_mo, e0, p.nocc, eta, out=V)
+    torch.cuda.synchronize()
+    ms = []
+    for i in range(args.steps):
+        q.qsgw_mp2_sigma(ctx, B_mo, e0, p.nocc, eta, out=V)
+        ms.append(ctx.last_stage_ms()["sigma"])
+        log(f"[bench] qsMP2 potential {i + 1}/{args.steps}: {ms[-1]:.2f} ms")
+    t = float(np.mean(ms))
+    flops = mp2_flops(p.nbf, p.naux, p.nocc)
+    achieved = flops / (t * 1e-3) / 1e12
+    out = {"ms": round(t, 3), "tflops": round(achieved, 3), "flops": flops, "precision": "fp64",
+           "roofline": {"bound": "mfma", "scope": "whole call (integrals, weights, contraction)",
+                        "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the qsMP2 oracle on sampled elements")
+        out["cpu_baseline"] = mp2_cpu_baseline(B_mo.cpu().numpy(), p.eps0, p.nocc, eta, flops)
+    del B_mo, V
+    return out
+
+
 BATCH_METRIC = "batched qsGW throughput, 5 iterations per molecule"
 
 
@@ -337,6 +391,10 @@ def main():
                     help="cfg5: training molecules (the full protocol names 20,000)")
     ap.add_argument("--test-molecules", type=int, default=256,
                     help="cfg5: held-out molecules (the full protocol names 2,000)")
+    ap.add_argument("--no-mp2", action="store_true",
+                    help="skip the qsMP2 potential leg (Eqs. 20-21, FP64)")
+    ap.add_argument("--mp2-probe", action="store_true",
+                    help="only build the qsMP2 potential of the workload twice (for profilers)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (HBM counter "
                          "calibration: 1 GiB read + 1 GiB written per copy)")
@@ -378,6 +436,23 @@ def main():
             q.qsgw_sigma_qs(ctx, w, e0, Om, p.nocc, cfg["eta"], wh=wh)
             torch.cuda.synchronize()
         print(json.dumps({"counter_probe": args.config}), flush=True)
+        return
+
+    if args.mp2_probe:
+        cfg = CONFIGS[args.config]
+        p = make_config(args.config)
+        dev = torch.device("cuda:0")
+        B = torch.from_numpy(p.B_ao).to(dev)
+        C0 = torch.from_numpy(p.C0).to(dev)
+        e0 = torch.from_numpy(p.eps0).to(dev)
+        with q.Context() as ctx:
+            ctx.set_tiles(tuned_tiles(args.config))
+            B_mo = q.qsgw_mo_transform(ctx, B, C0)
+            for _ in range(2):
+                q.qsgw_mp2_sigma(ctx, B_mo, e0, p.nocc, cfg["eta"])
+            torch.cuda.synchronize()
+            ms = ctx.last_stage_ms()["sigma"]
+        print(json.dumps({"mp2_probe": args.config, "ms": ms}), flush=True)
         return
 
     if args.iterate_probe:
@@ -518,6 +593,9 @@ def main():
     for k, v in qps.items():
         out[f"qp_error_{k}_vs_fp64"] = v
         out[f"speedup_{k}_vs_fp64"] = round(sums["fp64"]["hot_ms"] / sums[k]["hot_ms"], 3)
+    if not args.no_mp2:
+        ctx.set_tiles(tiles["fp64"])
+        out["qsmp2"] = bench_mp2(args, q, torch, ctx, B, C0, e0, p, eta)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, eta, hot_flops)

@@ -180,6 +180,37 @@ int qsgw_sigma(qsgw_ctx* ctx, int mode, int64_t nbf, int64_t nocc, int64_t ns, c
                double* out, int accumulate);
 
 /*
+ * qsMP2 potential: the correlation part of the MP2 self-energy, Eq. (20),
+ * made Hermitian as in Eq. (21); closed shell, real orbitals:
+ *   V[m][n] (+)= 1/2 Re[Sigma_mn(eps_n) + Sigma_nm(eps_m)],
+ *   Sigma_mn(w) = sum_{p, i, a} (mp|ia) [2 (pn|ai) - X_pian] g_pia(w),
+ *   X = (pi|an) for empty p, (pa|in) for occupied p,
+ *   g = 1 / (w + eps_a - eps_i - eps_p - i eta) for occupied p,
+ *       1 / (w + eps_i - eps_a - eps_p + i eta) for empty p,
+ * i occupied, a empty, p any state, (kl|rs) = sum_P B_mo[P][k][l] B_mo[P][r][s].
+ * The second-order exchange term for occupied p pairs the indices as (pa|in),
+ * the form the antisymmetrised spin-orbital second-order self-energy gives.
+ * B_mo: [naux][nbf][nbf] device, symmetric in (k, l) (as qsgw_mo_transform
+ *       writes it); eps: [nbf] device; V: [nbf][nbf] device out, written
+ *       exactly symmetric.
+ * occ_block: occupied states i per block of transitions (i, a); 0 picks the
+ *       largest block whose two [nbf][nbf][block transitions] FP64 work
+ *       arrays fit in 16 GiB.  More than one block also keeps (ni|pa) for
+ *       every occupied i ([nocc][nbf][ntr] FP64).  The workspace is owned by
+ *       the context and kept for later calls.
+ * accumulate = 1 adds into V, 0 overwrites.
+ * precision: QSGW_PREC_FP64 only (others return QSGW_ERR_UNSUPPORTED).
+ * Errors: 0 < nocc < nbf violated, naux < 1, eta <= 0 or not finite, NULL
+ * pointers, occ_block < 0, nbf * (transitions of a block) >= 2^32,
+ * QSGW_ERR_ALLOC when the workspace cannot be allocated.  Asynchronous on the
+ * context stream; the time of the call is reported as the sigma stage of
+ * qsgw_last_stage_ms.
+ */
+int qsgw_mp2_sigma(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                   const double* eps, double eta, double* V, int64_t occ_block, int accumulate,
+                   int precision);
+
+/*
  * One-body matrix that makes (eps0, C0) a Hartree-Fock fixed point of
  * Eq. (6) with Sigma_c = 0:  h = C0 diag(eps0) C0^T - J[D0] + K[D0],
  * D0 = C0[:, :nocc] C0[:, :nocc]^T (Eq. (9)), J and K from Eqs. (7), (10).

@@ -299,13 +299,13 @@ def _mp2_integrals(B_mo: np.ndarray, nocc: int, m_rows=None, n_rows=None):
     m_rows = np.arange(nb) if m_rows is None else np.asarray(m_rows)
     n_rows = np.arange(nb) if n_rows is None else np.asarray(n_rows)
     Bia = B_mo[:, occ, vir]                                   # [P][i][a]
-    L = np.einsum("Pmp,Pia->mpia", B_mo[:, m_rows, :], Bia)
-    R = np.einsum("Ppn,Pai->npia", B_mo[:, :, n_rows], B_mo[:, vir, occ])
+    L = np.einsum("Pmp,Pia->mpia", B_mo[:, m_rows, :], Bia, optimize=True)
+    R = np.einsum("Ppn,Pai->npia", B_mo[:, :, n_rows], B_mo[:, vir, occ], optimize=True)
     X = np.empty_like(R)
     # p virtual: (pi|an) = sum_P B^P_{pi} B^P_{an}
-    X[:, nocc:] = np.einsum("Ppi,Pan->npia", B_mo[:, vir, occ], B_mo[:, vir][:, :, n_rows])
+    X[:, nocc:] = np.einsum("Ppi,Pan->npia", B_mo[:, vir, occ], B_mo[:, vir][:, :, n_rows], optimize=True)
     # p occupied: (pa|in) = sum_P B^P_{pa} B^P_{in}
-    X[:, :nocc] = np.einsum("Ppa,Pin->npia", B_mo[:, occ, vir], B_mo[:, occ][:, :, n_rows])
+    X[:, :nocc] = np.einsum("Ppa,Pin->npia", B_mo[:, occ, vir], B_mo[:, occ][:, :, n_rows], optimize=True)
     return L, R, X
 
 

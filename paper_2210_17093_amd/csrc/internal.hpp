@@ -71,6 +71,10 @@ enum Slot {
   W_SPLIT_Z,     // split-BF16 rho' product: Z of a block, rows s  [2][ntr/8][sb padded][8] bf16
   W_NEARW,       // split-BF16 qsGW product: near-pole columns    [columns][nbf] float
   W_REDPART,     // first level of a long split-K reduction       [ceil(nz / 32)][nbf][nbf]
+  W_MP2_BIA,     // qsMP2: B_mo[P][i][a], unscaled                [naux][ntr]
+  W_MP2_D,       // qsMP2: (mp|ia) of a block of transitions     [nbf][nbf][block]
+  W_MP2_R,       // qsMP2: pole-weighted right operand            [nbf][nbf][block]
+  W_MP2_E,       // qsMP2, several blocks: (ni|pa), i occupied    [nocc][nbf][ntr]
   W_NSLOTS
 };
 
@@ -425,5 +429,39 @@ int syevd(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what) {
   return QSGW_OK;
 }
 
+
+// V (+)= 1/2 (G + G^T), G = sum of the nz partial slices of part.  Long sums
+// go through a first level of 32 slices per group (coalesced reads, many
+// threads), then the symmetric sum over the group results.
+inline int reduce_sym(qsgw_ctx* c, const double* part, int64_t nz, int64_t n, double* V, int accumulate) {
+  const int64_t nn = n * n;
+  constexpr int64_t zg = 32;
+  if (nz > 2 * zg) {
+    const int64_t ng = (nz + zg - 1) / zg;
+    double* red = nullptr;
+    CHECK(ws_get(c, W_REDPART, (size_t)(ng * nn), &red));
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(ng * nn)), dim3(256), 0, c->stream, part, nz,
+                       nn, zg, red);
+    CHECK(launch_check(c, "k_sum_slices"));
+    part = red;
+    nz = ng;
+  }
+  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nn)), dim3(256), 0, c->stream, part, nz, n, V,
+                     accumulate);
+  return launch_check(c, "k_reduce_sym");
+}
+
+inline int check_common(qsgw_ctx* c, int64_t nbf, int64_t naux) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  if (nbf < 1 || naux < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need nbf >= 1 and naux >= 1");
+  if (nbf > 46340) return fail(c, QSGW_ERR_INVALID_ARG, "nbf too large");
+  return QSGW_OK;
+}
+
+inline int single_begin(qsgw_ctx* c, int stage) {
+  c->last_stage = stage;
+  return record(c, 0);
+}
+inline int single_end(qsgw_ctx* c) { return record(c, 1); }
 
 }  // namespace

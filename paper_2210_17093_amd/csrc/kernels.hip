@@ -45,7 +45,7 @@ __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_
   const int64_t t = idx - P * ntr;
   const int64_t i = t / nv;
   const int64_t a = nocc + (t - i * nv);
-  const double v = bmo[(P * nbf + i) * nbf + a] * sqrt_delta[t];
+  const double v = bmo[(P * nbf + i) * nbf + a] * (sqrt_delta ? sqrt_delta[t] : 1.0);
   bt[idx] = v;
   if (bt32) bt32[idx] = (float)v;
 }
@@ -585,6 +585,64 @@ __global__ void k_near_fill(const int64_t* lo, const int64_t* cnt, const int64_t
   for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
     ktab[o + j] = (int32_t)k;
     stab[o + j] = (int32_t)(s0 + j);
+  }
+}
+
+// ------------------------------------------------------------------ qsMP2 --
+// Right operand of the MP2 product for occupied p.  Element (n, p, ii, a') of
+// the block: tb = ii nv + a', i = i0 + ii, a = nocc + a',
+//   Rh[n][p][tb] = (2 (np|ia) - (pa|in)) x / (x^2 + eta^2),
+//   x = eps_n + eps_a - eps_i - eps_p,
+// with (np|ia) = D[n][p][tb] and (pa|in) = (ni|pa) read at
+// xo + n xsn + i xsi + p nv + a'.
+__global__ void k_mp2_rhs_occ(const double* D, const double* xo, int64_t xsn, int64_t xsi,
+                              const double* eps, int64_t nbf, int64_t nocc, int64_t i0,
+                              int64_t ni, double eta, double* R) {
+  const int64_t nv = nbf - nocc, ntb = ni * nv;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbf * nocc * ntb) return;
+  const int64_t ap = idx % nv;
+  int64_t r = idx / nv;
+  const int64_t ii = r % ni;
+  r /= ni;
+  const int64_t p = r % nocc;
+  const int64_t n = r / nocc;
+  const int64_t i = i0 + ii;
+  const int64_t o = (n * nbf + p) * ntb + ii * nv + ap;
+  const double x = eps[n] + eps[nocc + ap] - eps[i] - eps[p];
+  const double X = xo[n * xsn + i * xsi + p * nv + ap];
+  R[o] = (2.0 * D[o] - X) * (x / (x * x + eta * eta));
+}
+
+// Right operand for empty p, p' = p - nocc: the exchange integral
+// (pi|an) = (na|ip) = D[n][a][ii nv + p'] is the transpose, in (a', p'), of
+// the direct block, so each workgroup moves one 32 x 32 tile of it through LDS:
+//   Rh[n][p][tb] = (2 (np|ia) - (pi|an)) x / (x^2 + eta^2),
+//   x = eps_n + eps_i - eps_a - eps_p.
+// Grid: (tiles of (p', a'), ii, n); 256 threads.
+__global__ void k_mp2_rhs_vir(const double* D, const double* eps, int64_t nbf, int64_t nocc,
+                              int64_t i0, int64_t ni, double eta, double* R) {
+  __shared__ double X[32][33];
+  const int64_t nv = nbf - nocc, ntb = ni * nv;
+  const int64_t nvt = (nv + 31) / 32;
+  const int64_t pt = blockIdx.x / nvt, at = blockIdx.x - pt * nvt;
+  const int64_t ii = blockIdx.y, n = blockIdx.z;
+  const int64_t p0 = pt * 32, a0 = at * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double* Dn = D + n * nbf * ntb + ii * nv;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t a = a0 + r, pp = p0 + tx;
+    if (a < nv && pp < nv) X[r][tx] = Dn[(nocc + a) * ntb + pp];
+  }
+  __syncthreads();
+  const double en = eps[n], ei = eps[i0 + ii];
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t pp = p0 + r, a = a0 + tx;
+    if (pp < nv && a < nv) {
+      const int64_t o = (nocc + pp) * ntb + a;
+      const double x = en + ei - eps[nocc + a] - eps[nocc + pp];
+      R[n * nbf * ntb + ii * nv + o] = (2.0 * Dn[o] - X[tx][r]) * (x / (x * x + eta * eta));
+    }
   }
 }
 

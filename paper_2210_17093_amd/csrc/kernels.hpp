@@ -406,6 +406,7 @@ __global__ void k_near_fill(const int64_t* lo, const int64_t* cnt, const int64_t
 
 __global__ void k_transitions(const double* eps, int64_t nocc, int64_t nv, double* delta,
                               double* sqrt_delta, int* bad);
+// bt[P][t] = B_mo[P][i][a] sqrt_delta[t] for t = (i, a) (sqrt_delta NULL: unscaled)
 __global__ void k_gather_bia(const double* bmo, const double* sqrt_delta, int64_t naux,
                              int64_t nbf, int64_t nocc, double* bt, float* bt32);
 // Omega = sqrt(lambda); flags lambda <= 0 or non-finite.
@@ -490,5 +491,13 @@ __global__ void k_sigma_diag_grid(const double* w, const double* eps, const doub
                                   int64_t nbf, int64_t nocc, int64_t ns, double eta,
                                   const double* omega, int64_t nomega, const int64_t* states,
                                   int64_t nstates, double* out, int accumulate, int* bad);
+
+// qsMP2 right operand of one block of transitions (i in [i0, i0 + ni)):
+// occupied p (flat grid over n, p, i, a) and empty p (32 x 32 LDS tiles).
+__global__ void k_mp2_rhs_occ(const double* D, const double* xo, int64_t xsn, int64_t xsi,
+                              const double* eps, int64_t nbf, int64_t nocc, int64_t i0,
+                              int64_t ni, double eta, double* R);
+__global__ void k_mp2_rhs_vir(const double* D, const double* eps, int64_t nbf, int64_t nocc,
+                              int64_t i0, int64_t ni, double eta, double* R);
 
 }  // namespace qsgw

@@ -6,26 +6,6 @@
 
 namespace {
 
-// V (+)= 1/2 (G + G^T), G = sum of the nz partial slices of part.  Long sums
-// go through a first level of 32 slices per group (coalesced reads, many
-// threads), then the symmetric sum over the group results.
-int reduce_sym(qsgw_ctx* c, const double* part, int64_t nz, int64_t n, double* V, int accumulate) {
-  const int64_t nn = n * n;
-  constexpr int64_t zg = 32;
-  if (nz > 2 * zg) {
-    const int64_t ng = (nz + zg - 1) / zg;
-    double* red = nullptr;
-    CHECK(ws_get(c, W_REDPART, (size_t)(ng * nn), &red));
-    hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(ng * nn)), dim3(256), 0, c->stream, part, nz,
-                       nn, zg, red);
-    CHECK(launch_check(c, "k_sum_slices"));
-    part = red;
-    nz = ng;
-  }
-  hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nn)), dim3(256), 0, c->stream, part, nz, n, V,
-                     accumulate);
-  return launch_check(c, "k_reduce_sym");
-}
 
 // Near-pole columns of the reduced-precision qsGW product for one excitation
 // block: for each 64-row tile t of m, the (k, s) with Omega_s inside the
@@ -616,13 +596,6 @@ int congruence(qsgw_ctx* c, int64_t n, const double* X, const double* Y, double*
   return QSGW_OK;
 }
 
-int check_common(qsgw_ctx* c, int64_t nbf, int64_t naux) {
-  if (!c) return QSGW_ERR_INVALID_ARG;
-  if (nbf < 1 || naux < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need nbf >= 1 and naux >= 1");
-  if (nbf > 46340) return fail(c, QSGW_ERR_INVALID_ARG, "nbf too large");
-  return QSGW_OK;
-}
-
 int check_prec(qsgw_ctx* c, int precision) {
   if (precision == QSGW_PREC_FP64 || precision == QSGW_PREC_FP32 ||
       precision == QSGW_PREC_SPLIT_BF16)
@@ -630,11 +603,6 @@ int check_prec(qsgw_ctx* c, int precision) {
   return fail(c, QSGW_ERR_INVALID_ARG, "unknown precision %d", precision);
 }
 
-int single_begin(qsgw_ctx* c, int stage) {
-  c->last_stage = stage;
-  return record(c, 0);
-}
-int single_end(qsgw_ctx* c) { return record(c, 1); }
 
 }  // namespace
 

@@ -43,7 +43,7 @@ STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "
 
 EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
-           "qsgw_residues", "qsgw_sigma", "qsgw_hf_core", "qsgw_iterate",
+           "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
            "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles")
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_residues": ([P, I64, I64, I64, P, P, P, P, I64, I64, P, P, P, D, I], I),
         "qsgw_sigma": ([P, I, I64, I64, I64, P, P, P, P, D, P, I64, P, I64, P, I], I),
         "qsgw_hf_core": ([P, I64, I64, I64, P, P, P, P], I),
+        "qsgw_mp2_sigma": ([P, I64, I64, I64, P, P, D, P, I64, I, I], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
         "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
@@ -304,6 +305,19 @@ def qsgw_sigma_diag_self(ctx: Context, w, eps, Omega_block, nocc, eta, states, o
                                _ptr(Omega_block, (ns,), name="Omega"), float(eta), None, 0,
                                _ptr(states, (nstates,), torch.int64, name="states"), nstates,
                                _ptr(out, (nstates, 3), name="out"), int(bool(accumulate))))
+    return out
+
+
+def qsgw_mp2_sigma(ctx: Context, B_mo, eps, nocc, eta, out=None, occ_block=0, accumulate=False,
+                   precision=PREC_FP64):
+    naux, nbf, _ = B_mo.shape
+    if out is None:
+        out = torch.empty((nbf, nbf), dtype=torch.float64, device=B_mo.device)
+    ctx.check(lib().qsgw_mp2_sigma(ctx.handle, nbf, naux, nocc,
+                                   _ptr(B_mo, (naux, nbf, nbf), name="B_mo"),
+                                   _ptr(eps, (nbf,), name="eps"), float(eta),
+                                   _ptr(out, (nbf, nbf), name="out"), int(occ_block),
+                                   int(bool(accumulate)), int(precision)))
     return out
 
 
