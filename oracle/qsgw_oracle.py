@@ -42,8 +42,9 @@ its reason in the design notes of the repository):
   * Eq. (21) takes the real part, as Eq. (19): V_mn = 1/2 Re[Sigma_mn(eps_n)
     + Sigma_nm(eps_m)].
 
-Also here, beyond the qsGW iteration: the MP2 self-energy, Eq. (20), and the
-qsMP2 potential, Eq. (21).
+Also here, beyond the qsGW iteration: the MP2 self-energy, Eq. (20), the
+qsMP2 potential, Eq. (21), and the four-index AO->MO transform of Eq. (16)
+without the RI factorisation.
 """
 from __future__ import annotations
 
@@ -362,3 +363,15 @@ def qsmp2_entry(B_mo: np.ndarray, eps: np.ndarray, nocc: int, eta: float, m: int
     a = sigma_mp2_entry(B_mo, eps, nocc, eta, eps[n], m, n)
     b = sigma_mp2_entry(B_mo, eps, nocc, eta, eps[m], n, m)
     return 0.5 * (a + b).real
+
+
+# ------------------------------------------------------ four-index AO->MO --
+def ao2mo_4center(eri_ao: np.ndarray, C: np.ndarray, m_rows=None) -> np.ndarray:
+    """Eq. (16) on explicit four-index integrals:
+    (mn|kl) = sum_{mu nu lambda tau} C_{mu m} C_{nu n} C_{lambda k} C_{tau l} (mu nu|lambda tau).
+
+    eri_ao is [mu][nu][lambda][tau]; C is [mu][m].  m_rows selects the first MO
+    index (default: all).  Returns [len(m_rows)][nbf][nbf][nbf].
+    """
+    Cm = C if m_rows is None else C[:, np.asarray(m_rows)]
+    return np.einsum("abcd,am,bn,ck,dl->mnkl", eri_ao, Cm, C, C, C, optimize=True)

@@ -245,3 +245,34 @@ def mp2_two_level_closed_form(B, eps0, eps1, eta, omega):
     b = B[0, 1]
     return b * b * (np.outer(B[:, 0], B[:, 0]) / (omega + eps1 - 2 * eps0 - 1j * eta)
                     + np.outer(B[:, 1], B[:, 1]) / (omega + eps0 - 2 * eps1 + 1j * eta))
+
+
+# ------------------------------------------------------------ P15 --------
+def ao2mo_brute_force(eri_ao, C):
+    """Eq. (16) as the literal eight-fold sum (tiny N only)."""
+    n = C.shape[0]
+    out = np.zeros((n, n, n, n))
+    for m in range(n):
+        for q in range(n):
+            for k in range(n):
+                for l in range(n):
+                    acc = 0.0
+                    for a in range(n):
+                        for b in range(n):
+                            for c in range(n):
+                                for d in range(n):
+                                    acc += C[a, m] * C[b, q] * C[c, k] * C[d, l] * eri_ao[a, b, c, d]
+                    out[m, q, k, l] = acc
+    return out
+
+
+def ri_four_index(B, C):
+    """(mn|kl) of an RI tensor: transform each B^P to the MO basis with explicit
+    loops over the AO pair, then sum_P B^P_mn B^P_kl."""
+    naux, n, _ = B.shape
+    Bm = np.zeros((naux, n, n))
+    for P in range(naux):
+        for a in range(n):
+            for b in range(n):
+                Bm[P] += B[P, a, b] * np.outer(C[a], C[b])
+    return np.einsum("Pmn,Pkl->mnkl", Bm, Bm)

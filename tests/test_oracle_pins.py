@@ -368,6 +368,39 @@ def test_mutant_mp2_printed_exchange_caught(monkeypatch):
     monkeypatch.setattr(OM, "_mp2_integrals", orig)
 
 
+# ------------------------------------------------- P15: four-index AO->MO --
+def test_p15_ao2mo_4center():
+    """Eq. (16) on explicit integrals: the literal eight-fold sum (N = 4), the
+    RI route (mn|kl) = sum_P B^P_mn B^P_kl with its own MO transform, slabs of
+    the first index, and the identity / permutation special cases."""
+    p = tiny(nbf=4, naux=5, nocc=1, seed=2)
+    B = make_mo_tensor(4, 5, 1, 8)[0]          # general symmetric RI factors
+    eri = pins.mo_eri(B)
+    C = p.C0
+    ref = pins.ao2mo_brute_force(eri, C)
+    np.testing.assert_allclose(O.ao2mo_4center(eri, C), ref, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(O.ao2mo_4center(eri, C, [2, 3]), ref[2:], rtol=0, atol=1e-14)
+    q = tiny(nbf=9, naux=7, nocc=2, seed=4)
+    B9 = make_mo_tensor(9, 7, 2, 5)[0]
+    np.testing.assert_allclose(O.ao2mo_4center(pins.mo_eri(B9), q.C0), pins.ri_four_index(B9, q.C0),
+                               rtol=0, atol=1e-13)
+    np.testing.assert_allclose(O.ao2mo_4center(eri, np.eye(4)), eri, rtol=0, atol=0)
+    perm = np.eye(4)[:, [2, 0, 3, 1]]
+    np.testing.assert_array_equal(O.ao2mo_4center(eri, perm), eri[np.ix_([2, 0, 3, 1], [2, 0, 3, 1],
+                                                                        [2, 0, 3, 1], [2, 0, 3, 1])])
+
+
+def test_mutant_ao2mo_caught():
+    """A transposed C in one slot of Eq. (16), or a dropped slot, fails P15."""
+    p = tiny(nbf=4, naux=5, nocc=1, seed=2)
+    eri = pins.mo_eri(make_mo_tensor(4, 5, 1, 8)[0])
+    ref = pins.ao2mo_brute_force(eri, p.C0)
+    bad1 = np.einsum("abcd,am,bn,kc,dl->mnkl", eri, p.C0, p.C0, p.C0, p.C0)
+    bad2 = np.einsum("abcd,am,bn,ck->mnkd", eri, p.C0, p.C0, p.C0)
+    for bad in (bad1, bad2):
+        assert np.abs(bad - ref).max() > 1e-6 * np.abs(ref).max()
+
+
 # ------------------------------------------------------------ generator ---
 def test_generator_determinism_and_structure():
     a = make_problem(10, 30, 3, 15, 0.9, 42)
