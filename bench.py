@@ -186,6 +186,70 @@ def bench_mp2(args, q, torch, ctx, B, C0, e0, p, eta):
     return out
 
 
+AO2MO_SLAB = 64
+
+
+def ao2mo_eri(torch, B):
+    """Synthetic explicit AO integrals (mu nu|lambda tau) = sum_P B^P B^P of the
+    workload's RI tensor, built on the device (input preparation)."""
+    naux, n, _ = B.shape
+    flat = B.reshape(naux, n * n)
+    return (flat.T @ flat).reshape(n, n, n, n)
+
+
+def ao2mo_cpu_baseline(nbf, slab, flops):
+    """Time the oracle's four-index transform at a reduced basis (the full
+    [nbf]^4 tensor does not fit the host sample budget) and scale by nbf^5."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    ns = 90
+    ms = max(1, round(slab * ns / nbf))
+    rng = np.random.default_rng(3)
+    eri = rng.standard_normal((ns, ns, ns, ns))
+    C = np.linalg.qr(rng.standard_normal((ns, ns)))[0]
+    t0 = time.perf_counter()
+    O.ao2mo_4center(eri, C, np.arange(ms))
+    t = time.perf_counter() - t0
+    est = t * (slab / ms) * (nbf / ns) ** 4
+    return dict(value=flops / est / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
+                sample=(f"oracle ao2mo_4center at N_b = {ns}, slab of {ms}, scaled by slab and "
+                        f"N_b^4 to N_b = {nbf}, slab {slab}; est. s/slab = {est:.1f}"))
+
+
+def bench_ao2mo(args, q, torch, ctx, B, C):
+    """Four-index AO->MO transform (Eq. 16, no RI) of a slab of AO2MO_SLAB MOs
+    with the workload's starting orbitals."""
+    nbf = B.shape[1]
+    eri = ao2mo_eri(torch, B)
+    out = torch.empty((AO2MO_SLAB, nbf, nbf, nbf), dtype=torch.float64, device=B.device)
+    for _ in range(max(1, args.warmup)):
+        q.qsgw_ao2mo_4center(ctx, eri, C, 0, AO2MO_SLAB, out=out)
+    torch.cuda.synchronize()
+    ms = []
+    for i in range(args.steps):
+        q.qsgw_ao2mo_4center(ctx, eri, C, 0, AO2MO_SLAB, out=out)
+        ms.append(ctx.last_stage_ms()["mo_transform"])
+        log(f"[bench] four-index AO->MO slab {i + 1}/{args.steps}: {ms[-1]:.2f} ms")
+    t = float(np.mean(ms))
+    flops = 8 * AO2MO_SLAB * nbf ** 4
+    achieved = flops / (t * 1e-3) / 1e12
+    res = {"ms": round(t, 3), "tflops": round(achieved, 3), "flops": flops, "slab": AO2MO_SLAB,
+           "precision": "fp64",
+           "roofline": {"bound": "mfma", "scope": "whole call (four quarter transforms)",
+                        "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}}
+    del eri, out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the four-index oracle on a reduced basis")
+        res["cpu_baseline"] = ao2mo_cpu_baseline(nbf, AO2MO_SLAB, flops)
+    return res
+
+
 BATCH_METRIC = "batched qsGW throughput, 5 iterations per molecule"
 
 
@@ -393,6 +457,10 @@ def main():
                     help="cfg5: held-out molecules (the full protocol names 2,000)")
     ap.add_argument("--no-mp2", action="store_true",
                     help="skip the qsMP2 potential leg (Eqs. 20-21, FP64)")
+    ap.add_argument("--no-ao2mo", action="store_true",
+                    help="skip the four-index AO->MO transform leg (Eq. 16 without RI)")
+    ap.add_argument("--ao2mo-probe", action="store_true",
+                    help="only run the four-index AO->MO slab twice (for profilers)")
     ap.add_argument("--mp2-probe", action="store_true",
                     help="only build the qsMP2 potential of the workload twice (for profilers)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -436,6 +504,17 @@ def main():
             q.qsgw_sigma_qs(ctx, w, e0, Om, p.nocc, cfg["eta"], wh=wh)
             torch.cuda.synchronize()
         print(json.dumps({"counter_probe": args.config}), flush=True)
+        return
+
+    if args.ao2mo_probe:
+        p = make_config(args.config)
+        B = torch.from_numpy(p.B_ao).to(torch.device("cuda:0"))
+        C0 = torch.from_numpy(p.C0).to(torch.device("cuda:0"))
+        with q.Context() as ctx:
+            ctx.set_tiles(tuned_tiles(args.config))
+            args.steps, args.warmup, args.no_cpu_baseline = 1, 1, True
+            res = bench_ao2mo(args, q, torch, ctx, B, C0)
+        print(json.dumps({"ao2mo_probe": args.config, **res}), flush=True)
         return
 
     if args.mp2_probe:
@@ -596,6 +675,9 @@ def main():
     if not args.no_mp2:
         ctx.set_tiles(tiles["fp64"])
         out["qsmp2"] = bench_mp2(args, q, torch, ctx, B, C0, e0, p, eta)
+    if not args.no_ao2mo:
+        ctx.set_tiles(tiles["fp64"])
+        out["ao2mo_4center"] = bench_ao2mo(args, q, torch, ctx, B, C0)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, eta, hot_flops)

@@ -211,6 +211,28 @@ int qsgw_mp2_sigma(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const
                    int precision);
 
 /*
+ * Four-index AO->MO transform, Eq. (16), on explicit integrals (the route
+ * without the RI factorisation), for a slab of the first MO index:
+ *   eri_mo[m - m_begin][n][k][l] = sum_{mu nu lambda tau} C[mu][m] C[nu][n] C[lambda][k]
+ *                                  C[tau][l] eri_ao[mu][nu][lambda][tau],
+ *   m in [m_begin, m_begin + m_count), n, k, l in [0, nbf).
+ * Four quarter transforms, one GEMM each (8 m_count nbf^4 FLOPs); a smaller
+ * slab lowers the memory of the intermediates and the arithmetic intensity
+ * of the first quarter (it reads the whole AO tensor once per call).
+ * eri_ao: [nbf][nbf][nbf][nbf] device; C: [nbf][nbf] device, column m = MO m;
+ * eri_mo: [m_count][nbf][nbf][nbf] device out, also used as scratch for the
+ *   second quarter (must not overlap eri_ao or C).  The context keeps one
+ *   [m_count][nbf][nbf][nbf] FP64 workspace.
+ * precision: QSGW_PREC_FP64 only (others return QSGW_ERR_UNSUPPORTED).
+ * Errors: nbf < 1, NULL pointers, a slab outside [0, nbf), QSGW_ERR_UNSUPPORTED
+ * when nbf^3 strides exceed the tile loader's 32-bit offsets (nbf above about
+ * 560), QSGW_ERR_ALLOC.  Asynchronous; timed as the MO stage of
+ * qsgw_last_stage_ms.
+ */
+int qsgw_ao2mo_4center(qsgw_ctx* ctx, int64_t nbf, const double* eri_ao, const double* C,
+                       int64_t m_begin, int64_t m_count, double* eri_mo, int precision);
+
+/*
  * One-body matrix that makes (eps0, C0) a Hartree-Fock fixed point of
  * Eq. (6) with Sigma_c = 0:  h = C0 diag(eps0) C0^T - J[D0] + K[D0],
  * D0 = C0[:, :nocc] C0[:, :nocc]^T (Eq. (9)), J and K from Eqs. (7), (10).

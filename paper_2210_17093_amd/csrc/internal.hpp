@@ -75,6 +75,7 @@ enum Slot {
   W_MP2_D,       // qsMP2: (mp|ia) of a block of transitions     [nbf][nbf][block]
   W_MP2_R,       // qsMP2: pole-weighted right operand            [nbf][nbf][block]
   W_MP2_E,       // qsMP2, several blocks: (ni|pa), i occupied    [nocc][nbf][ntr]
+  W_AO2MO,       // four-index AO->MO: quarter-transformed slab   [m_count][nbf][nbf][nbf]
   W_NSLOTS
 };
 

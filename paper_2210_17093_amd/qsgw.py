@@ -43,7 +43,7 @@ STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "
 
 EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
-           "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_hf_core", "qsgw_iterate",
+           "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_ao2mo_4center", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
            "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles")
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_sigma": ([P, I, I64, I64, I64, P, P, P, P, D, P, I64, P, I64, P, I], I),
         "qsgw_hf_core": ([P, I64, I64, I64, P, P, P, P], I),
         "qsgw_mp2_sigma": ([P, I64, I64, I64, P, P, D, P, I64, I, I], I),
+        "qsgw_ao2mo_4center": ([P, I64, P, P, I64, I64, P, I], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
         "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
@@ -318,6 +319,19 @@ def qsgw_mp2_sigma(ctx: Context, B_mo, eps, nocc, eta, out=None, occ_block=0, ac
                                    _ptr(eps, (nbf,), name="eps"), float(eta),
                                    _ptr(out, (nbf, nbf), name="out"), int(occ_block),
                                    int(bool(accumulate)), int(precision)))
+    return out
+
+
+def qsgw_ao2mo_4center(ctx: Context, eri_ao, C, m_begin=0, m_count=None, out=None,
+                       precision=PREC_FP64):
+    nbf = C.shape[0]
+    m_count = nbf - m_begin if m_count is None else m_count
+    if out is None:
+        out = torch.empty((m_count, nbf, nbf, nbf), dtype=torch.float64, device=C.device)
+    ctx.check(lib().qsgw_ao2mo_4center(ctx.handle, nbf, _ptr(eri_ao, (nbf,) * 4, name="eri_ao"),
+                                       _ptr(C, (nbf, nbf), name="C"), int(m_begin), int(m_count),
+                                       _ptr(out, (m_count, nbf, nbf, nbf), name="out"),
+                                       int(precision)))
     return out
 
 
