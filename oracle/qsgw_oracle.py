@@ -43,8 +43,10 @@ its reason in the design notes of the repository):
     + Sigma_nm(eps_m)].
 
 Also here, beyond the qsGW iteration: the MP2 self-energy, Eq. (20), the
-qsMP2 potential, Eq. (21), and the four-index AO->MO transform of Eq. (16)
-without the RI factorisation.
+qsMP2 potential, Eq. (21), the four-index AO->MO transform of Eq. (16)
+without the RI factorisation, and the open-shell (spin-unrestricted) GW
+potential: Eqs. (12)-(19) with the spin labels kept, each spin with its own
+orbitals, energies and occupation.
 """
 from __future__ import annotations
 
@@ -375,3 +377,43 @@ def ao2mo_4center(eri_ao: np.ndarray, C: np.ndarray, m_rows=None) -> np.ndarray:
     """
     Cm = C if m_rows is None else C[:, np.asarray(m_rows)]
     return np.einsum("abcd,am,bn,ck,dl->mnkl", eri_ao, Cm, C, C, C, optimize=True)
+
+
+# ------------------------------------------------------ open shell (UHF) --
+def rpa_hermitian_unrestricted(B_mo_s, eps_s, nocc_s):
+    """Eqs. (12)-(14) with explicit spins, direct RPA ("+" reading): transitions
+    t = (i, a, sigma) of both spins, spin alpha first, each in the order of
+    ``transition_energies``;  A = diag(Delta) + K, B = K with
+    K_{t u} = (i a sigma | j b sigma') = sum_P B^{sigma P}_{ia} B^{sigma' P}_{jb}.
+    Returns (M, sqrt_delta, Bt) with M = (A-B)^{1/2} (A+B) (A-B)^{1/2} and
+    Bt[P][t] = B^{sigma P}_{ia} (unscaled, [naux][ntr_alpha + ntr_beta]).
+    """
+    naux = B_mo_s[0].shape[0]
+    Bt = np.concatenate([B[:, :no, no:].reshape(naux, -1) for B, no in zip(B_mo_s, nocc_s)],
+                        axis=1)
+    delta = np.concatenate([transition_energies(e, no) for e, no in zip(eps_s, nocc_s)])
+    K = Bt.T @ Bt
+    A = np.diag(delta) + K
+    B = K
+    sqrt_delta = np.sqrt(delta)
+    M = sqrt_delta[:, None] * (A + B) * sqrt_delta[None, :]
+    return M, sqrt_delta, Bt
+
+
+def residues_unrestricted(B_mo: np.ndarray, Bt: np.ndarray, XpY: np.ndarray) -> np.ndarray:
+    """Eq. (18) for one spin sigma: w^s_{mn sigma} = sum_{t sigma'} (mn sigma|t) (X+Y)^s_t
+    = sum_P B^{sigma P}_{mn} rho_{P s}, rho = Bt (X+Y) over both spins' transitions."""
+    naux, n, _ = B_mo.shape
+    rho = Bt @ XpY
+    return (B_mo.reshape(naux, n * n).T @ rho).reshape(n, n, -1)
+
+
+def gw_unrestricted(B_mo_s, eps_s, nocc_s, eta):
+    """Open-shell qsGW potential of each spin, Eqs. (12)-(19):
+    returns ([V_alpha, V_beta], Omega) with V_sigma from Eq. (19) on the residues
+    and energies of that spin (occupied k < nocc_sigma)."""
+    M, sq, Bt = rpa_hermitian_unrestricted(B_mo_s, eps_s, nocc_s)
+    Om, XpY = rpa_solve(M, sq)
+    V = [sigma_qs(residues_unrestricted(B, Bt, XpY), e, Om, no, eta)
+         for B, e, no in zip(B_mo_s, eps_s, nocc_s)]
+    return V, Om

@@ -276,3 +276,55 @@ def ri_four_index(B, C):
             for b in range(n):
                 Bm[P] += B[P, a, b] * np.outer(C[a], C[b])
     return np.einsum("Pmn,Pkl->mnkl", Bm, Bm)
+
+
+# ------------------------------------------------------------ P17 --------
+def casida_spin_blocks_eig(B_mo_s, eps_s, nocc_s):
+    """Open-shell direct RPA from the full non-Hermitian problem
+    [[A, B], [-B, -A]] (X, Y) = Omega (X, Y) over transitions (i, a, sigma),
+    with (ia sigma|jb sigma') built element by element from the two spins' RI
+    factors.  Returns (positive Omega ascending, X+Y normalised so that
+    X^T X - Y^T Y = 1, columns in the order of Omega)."""
+    pr = []
+    for s, (e, no) in enumerate(zip(eps_s, nocc_s)):
+        pr += [(i, a, s) for i in range(no) for a in range(no, e.size)]
+    n = len(pr)
+    A = np.zeros((n, n))
+    B = np.zeros((n, n))
+    for t, (i, a, s) in enumerate(pr):
+        for u, (j, b, s2) in enumerate(pr):
+            v = float(np.dot(B_mo_s[s][:, i, a], B_mo_s[s2][:, j, b]))
+            A[t, u] = (eps_s[s][a] - eps_s[s][i]) * (t == u) + v
+            B[t, u] = float(np.dot(B_mo_s[s][:, i, a], B_mo_s[s2][:, b, j]))
+    H = np.block([[A, B], [-B, -A]])
+    lam, vec = np.linalg.eig(H)
+    keep = np.where(lam.real > 0)[0]
+    order = keep[np.argsort(lam.real[keep])]
+    Om = lam.real[order]
+    X = vec[:n, order].real
+    Y = vec[n:, order].real
+    norm = np.sqrt(np.einsum("ts,ts->s", X, X) - np.einsum("ts,ts->s", Y, Y))
+    return Om, (X + Y) / norm[None, :], pr
+
+
+def gw_unrestricted_spin_sums(B_mo_s, eps_s, nocc_s, eta, spin):
+    """Eqs. (17)-(19) for one spin from P17's excitations: residues
+    w^s_{mk} = sum_{(i, a, sigma')} (mk sigma|ia sigma') (X+Y)^s, summed term by
+    term, and V = 1/2 Re[Sigma(eps_m) + Sigma(eps_n)] element by element."""
+    Om, XpY, pr = casida_spin_blocks_eig(B_mo_s, eps_s, nocc_s)
+    Bs, es, no = B_mo_s[spin], eps_s[spin], nocc_s[spin]
+    nb = es.size
+    w = np.zeros((nb, nb, Om.size))
+    for t, (i, a, s2) in enumerate(pr):
+        integ = np.einsum("P,Pmk->mk", B_mo_s[s2][:, i, a], Bs)
+        w += integ[:, :, None] * XpY[t][None, None, :]
+    V = np.zeros((nb, nb))
+    for m in range(nb):
+        for q in range(nb):
+            tot = 0.0
+            for om in (es[m], es[q]):
+                for k in range(nb):
+                    den = (om - es[k] + Om - 1j * eta) if k < no else (om - es[k] - Om + 1j * eta)
+                    tot += np.sum(w[m, k] * w[q, k] / den).real
+            V[m, q] = 0.5 * tot
+    return V, Om

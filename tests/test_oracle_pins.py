@@ -401,6 +401,62 @@ def test_mutant_ao2mo_caught():
         assert np.abs(bad - ref).max() > 1e-6 * np.abs(ref).max()
 
 
+# --------------------------------------------- P16-P17: open shell (UHF) --
+def _two_spins(nbf, naux, nocc_a, nocc_b, seed):
+    pa = make_problem(nbf, naux, nocc_a, naux, 0.9, seed, coupling=1.0)
+    pb = make_problem(nbf, naux, nocc_b, naux, 0.9, seed + 100, coupling=1.0)
+    B_a = O.mo_transform(pa.B_ao, pa.C0)
+    B_b = O.mo_transform(pa.B_ao, pb.C0)          # same AO integrals, other orbitals
+    return [B_a, B_b], [pa.eps0, pb.eps0], [nocc_a, nocc_b]
+
+
+def test_p16_unrestricted_closed_shell_reduces_to_restricted():
+    """Equal spins: V_alpha = V_beta = the restricted V of Eq. (19), and the
+    excitations are the singlets plus triplets at Omega = Delta."""
+    p = tiny(nbf=7, naux=11, nocc=3, seed=6)
+    B_mo = O.mo_transform(p.B_ao, p.C0)
+    V, Om = O.gw_unrestricted([B_mo, B_mo], [p.eps0, p.eps0], [3, 3], 0.02)
+    M, sq = O.rpa_hermitian(B_mo, p.eps0, 3)
+    Om_r, XpY = O.rpa_solve(M, sq)
+    Vr = O.sigma_qs(O.residues(B_mo, XpY, 3), p.eps0, Om_r, 3, 0.02)
+    scale = np.abs(Vr).max()
+    np.testing.assert_allclose(V[0], Vr, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(V[1], Vr, rtol=0, atol=1e-12 * scale)
+    both = np.sort(np.concatenate([Om_r, O.transition_energies(p.eps0, 3)]))
+    np.testing.assert_allclose(Om, both, rtol=1e-12)
+
+
+@pytest.mark.parametrize("nocc_a,nocc_b", [(3, 2), (2, 2), (1, 3)])
+def test_p17_unrestricted_spin_sums(nocc_a, nocc_b):
+    """Open shell with different orbitals per spin: the Hermitian form, the
+    concatenated RI sums and Eq. (19) agree with the non-Hermitian spin-block
+    problem and term-by-term sums over (i, a, sigma')."""
+    B_s, e_s, n_s = _two_spins(6, 9, nocc_a, nocc_b, 12)
+    V, Om = O.gw_unrestricted(B_s, e_s, n_s, 0.03)
+    for spin in (0, 1):
+        Vp, Omp = pins.gw_unrestricted_spin_sums(B_s, e_s, n_s, 0.03, spin)
+        np.testing.assert_allclose(Om, Omp, rtol=1e-10)
+        np.testing.assert_allclose(V[spin], Vp, rtol=0, atol=1e-10 * np.abs(Vp).max())
+
+
+def test_mutant_unrestricted_spin_factor_caught(monkeypatch):
+    """The closed-shell factor 2 of the Casida coupling left in the open-shell
+    build fails P17."""
+    import oracle.qsgw_oracle as OM
+    orig = OM.rpa_hermitian_unrestricted
+
+    def doubled(B_mo_s, eps_s, nocc_s):
+        M, sq, Bt = orig(B_mo_s, eps_s, nocc_s)
+        d = sq * sq
+        return 2.0 * M - np.diag(d * d), sq, Bt
+
+    B_s, e_s, n_s = _two_spins(6, 9, 3, 2, 12)
+    Vp, Omp = pins.gw_unrestricted_spin_sums(B_s, e_s, n_s, 0.03, 0)
+    monkeypatch.setattr(OM, "rpa_hermitian_unrestricted", doubled)
+    V, Om = O.gw_unrestricted(B_s, e_s, n_s, 0.03)
+    assert np.abs(Om - Omp).max() > 1e-6 * Omp.max()
+
+
 # ------------------------------------------------------------ generator ---
 def test_generator_determinism_and_structure():
     a = make_problem(10, 30, 3, 15, 0.9, 42)
