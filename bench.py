@@ -186,6 +186,75 @@ def bench_mp2(args, q, torch, ctx, B, C0, e0, p, eta):
     return out
 
 
+def uhf_flops(nbf, naux, ntr):
+    """Algorithmic FLOPs of one open-shell GW potential (eigensolve excluded):
+    symmetric Casida product, rho' once, residues on pairs m <= n and the qsGW
+    product for each of the two spins."""
+    return (ntr * (ntr + 1) * naux + 2 * naux * ntr * ntr
+            + 2 * (nbf * (nbf + 1) * naux * ntr + 2 * nbf ** 3 * ntr))
+
+
+def uhf_cpu_baseline(B_mo, eps, nocc_s, eta, flops):
+    """Oracle stages of the open-shell potential on a bounded sample, scaled by
+    work ratio: the Casida product on 1/8 of the auxiliary functions, residues
+    and Eq. (19) of one spin on 1/40 of the excitations (random X+Y)."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    naux, nbf, _ = B_mo.shape
+    ps = max(1, naux // 8)
+    t0 = time.perf_counter()
+    M, sq, Bt = O.rpa_hermitian_unrestricted([B_mo[:ps], B_mo[:ps]], [eps, eps], nocc_s)
+    t_cas = (time.perf_counter() - t0) * naux / ps
+    ntr = sq.size
+    ss = max(1, ntr // 40)
+    rng = np.random.default_rng(7)
+    Bt = np.concatenate([B_mo[:, :no, no:].reshape(naux, -1) for no in nocc_s], axis=1)
+    XpY = rng.standard_normal((ntr, ss))
+    Om = np.sort(rng.uniform(0.5, 50.0, ss))
+    t0 = time.perf_counter()
+    w = O.residues_unrestricted(B_mo, Bt, XpY)
+    O.sigma_qs(w, eps, Om, nocc_s[0], eta)
+    t_spin = (time.perf_counter() - t0) * ntr / ss
+    est = t_cas + 2 * t_spin
+    return dict(value=flops / est / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
+                sample=(f"oracle open-shell stages: Casida on 1/8 of the auxiliary functions, "
+                        f"residues + Eq. (19) of one spin on 1/40 of the excitations, scaled by "
+                        f"work ratio (two spins); est. s/potential without eigensolve = {est:.1f}"))
+
+
+def bench_uhf(args, q, torch, ctx, B, C0, e0, p, eta):
+    """Open-shell GW potential of a doublet on the workload: both spins on the
+    starting orbitals, n_occ electrons alpha and n_occ - 1 beta (Eqs. 12-19 with
+    explicit spins); one warm-up and one timed call."""
+    B_mo = q.qsgw_mo_transform(ctx, B, C0)
+    na, nb = p.nocc, p.nocc - 1
+    q.qsgw_gw_unrestricted(ctx, B_mo, B_mo, e0, e0, na, nb, eta)
+    torch.cuda.synchronize()
+    q.qsgw_gw_unrestricted(ctx, B_mo, B_mo, e0, e0, na, nb, eta)
+    st = ctx.last_stage_ms()
+    hot = st["rpa_build"] + st["residues"] + st["sigma"]
+    ntr = na * (p.nbf - na) + nb * (p.nbf - nb)
+    flops = uhf_flops(p.nbf, p.naux, ntr)
+    achieved = flops / (hot * 1e-3) / 1e12
+    log(f"[bench] open-shell GW potential: {hot:.2f} ms without the eigensolve "
+        f"({st['eig_rpa']:.0f} ms, n = {ntr})")
+    res = {"nocc": [na, nb], "transitions": ntr, "hot_ms": round(hot, 3),
+           "stage_ms": {k: round(st[k], 3) for k in ("rpa_build", "eig_rpa", "residues", "sigma")},
+           "tflops": round(achieved, 3), "flops": flops, "precision": "fp64",
+           "roofline": {"bound": "mfma", "scope": "Casida product, residues and qsGW products of both spins",
+                        "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the open-shell oracle stages on a bounded sample")
+        res["cpu_baseline"] = uhf_cpu_baseline(B_mo.cpu().numpy(), p.eps0, [na, nb], eta, flops)
+    del B_mo
+    return res
+
+
 AO2MO_SLAB = 64
 
 
@@ -457,6 +526,10 @@ def main():
                     help="cfg5: held-out molecules (the full protocol names 2,000)")
     ap.add_argument("--no-mp2", action="store_true",
                     help="skip the qsMP2 potential leg (Eqs. 20-21, FP64)")
+    ap.add_argument("--no-uhf", action="store_true",
+                    help="skip the open-shell GW potential leg (doublet on the workload)")
+    ap.add_argument("--uhf-probe", action="store_true",
+                    help="only run the open-shell GW potential leg (for profilers)")
     ap.add_argument("--no-ao2mo", action="store_true",
                     help="skip the four-index AO->MO transform leg (Eq. 16 without RI)")
     ap.add_argument("--ao2mo-probe", action="store_true",
@@ -504,6 +577,20 @@ def main():
             q.qsgw_sigma_qs(ctx, w, e0, Om, p.nocc, cfg["eta"], wh=wh)
             torch.cuda.synchronize()
         print(json.dumps({"counter_probe": args.config}), flush=True)
+        return
+
+    if args.uhf_probe:
+        cfg = CONFIGS[args.config]
+        p = make_config(args.config)
+        dev = torch.device("cuda:0")
+        B = torch.from_numpy(p.B_ao).to(dev)
+        C0 = torch.from_numpy(p.C0).to(dev)
+        e0 = torch.from_numpy(p.eps0).to(dev)
+        with q.Context() as ctx:
+            ctx.set_tiles(tuned_tiles(args.config))
+            args.no_cpu_baseline = True
+            res = bench_uhf(args, q, torch, ctx, B, C0, e0, p, cfg["eta"])
+        print(json.dumps({"uhf_probe": args.config, **res}), flush=True)
         return
 
     if args.ao2mo_probe:
@@ -675,6 +762,9 @@ def main():
     if not args.no_mp2:
         ctx.set_tiles(tiles["fp64"])
         out["qsmp2"] = bench_mp2(args, q, torch, ctx, B, C0, e0, p, eta)
+    if not args.no_uhf:
+        ctx.set_tiles(tiles["fp64"])
+        out["open_shell_gw"] = bench_uhf(args, q, torch, ctx, B, C0, e0, p, eta)
     if not args.no_ao2mo:
         ctx.set_tiles(tiles["fp64"])
         out["ao2mo_4center"] = bench_ao2mo(args, q, torch, ctx, B, C0)

@@ -233,6 +233,34 @@ int qsgw_ao2mo_4center(qsgw_ctx* ctx, int64_t nbf, const double* eri_ao, const d
                        int64_t m_begin, int64_t m_count, double* eri_mo, int precision);
 
 /*
+ * Open-shell (spin-unrestricted) GW potential, Eqs. (12)-(19) with the spin
+ * labels sigma, sigma' kept: each spin has its own MO tensor, energies and
+ * occupation.  Transitions t = (i, a, sigma) of both spins (alpha first, each
+ * i-major) share one direct-RPA Casida problem,
+ *   M = Delta^2 + 2 sqrt(Delta) K sqrt(Delta),  K[t][u] = sum_P B^{sigma P}_{ia} B^{sigma' P}_{jb},
+ * solved by rocSOLVER dsyevd inside the call; then for each spin sigma
+ *   w[m][n][s] = sum_P B^{sigma P}_{mn} rho_{P s},  rho = sum_t B_t sqrt(Delta_t) Z[s][t] / sqrt(Omega_s),
+ *   V_sigma[m][n] = 1/2 (G[m][n] + G[n][m]),
+ *   G[m][n] = sum_{k,s} w[m][k][s] w[n][k][s] Re 1/(eps_m - eps_k +- (Omega_s - i eta))
+ * with eps, the occupied range and "+" for k < nocc of that spin.
+ * B_mo_a, B_mo_b: [naux][nbf][nbf] device (each spin's MO tensor, as
+ *   qsgw_mo_transform writes it); eps_a, eps_b: [nbf] device, ascending.
+ * V_a, V_b: [nbf][nbf] device out, written exactly symmetric.
+ * Omega_out: NULL, or [nocc_a (nbf - nocc_a) + nocc_b (nbf - nocc_b)] device
+ *   out, the excitation energies ascending.
+ * precision: QSGW_PREC_FP64 only (others return QSGW_ERR_UNSUPPORTED).
+ * Errors: 0 < nocc_a, nocc_b < nbf violated, naux < 1, eta <= 0, NULL
+ * pointers, more than 46340 transitions, an empty transition energy
+ * (INVALID_ARG), QSGW_ERR_SOLVER on an RPA instability.  Synchronizes the
+ * context stream; qsgw_last_stage_ms then reports the rpa_build (transitions,
+ * gather, Casida product), eig_rpa, residues and sigma stages of the call.
+ */
+int qsgw_gw_unrestricted(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc_a, int64_t nocc_b,
+                         const double* B_mo_a, const double* B_mo_b, const double* eps_a,
+                         const double* eps_b, double eta, double* V_a, double* V_b,
+                         double* Omega_out, int precision);
+
+/*
  * One-body matrix that makes (eps0, C0) a Hartree-Fock fixed point of
  * Eq. (6) with Sigma_c = 0:  h = C0 diag(eps0) C0^T - J[D0] + K[D0],
  * D0 = C0[:, :nocc] C0[:, :nocc]^T (Eq. (9)), J and K from Eqs. (7), (10).

@@ -646,4 +646,19 @@ __global__ void k_mp2_rhs_vir(const double* D, const double* eps, int64_t nbf, i
   }
 }
 
+// Open shell: one spin's block of the concatenated transition tensor,
+// bt[P * ld + t] = B_mo[P][i][a] sqrt_delta[t] scale, t = (i, a) of that spin.
+__global__ void k_gather_bia_ld(const double* bmo, const double* sqrt_delta, double scale,
+                                int64_t naux, int64_t nbf, int64_t nocc, int64_t ld, double* bt) {
+  const int64_t nv = nbf - nocc;
+  const int64_t ntr = nocc * nv;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= naux * ntr) return;
+  const int64_t P = idx / ntr;
+  const int64_t t = idx - P * ntr;
+  const int64_t i = t / nv;
+  const int64_t a = nocc + (t - i * nv);
+  bt[P * ld + t] = bmo[(P * nbf + i) * nbf + a] * sqrt_delta[t] * scale;
+}
+
 }  // namespace qsgw

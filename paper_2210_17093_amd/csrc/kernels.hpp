@@ -500,4 +500,8 @@ __global__ void k_mp2_rhs_occ(const double* D, const double* xo, int64_t xsn, in
 __global__ void k_mp2_rhs_vir(const double* D, const double* eps, int64_t nbf, int64_t nocc,
                               int64_t i0, int64_t ni, double eta, double* R);
 
+// Open shell: one spin's transitions into the concatenated [naux][ld] tensor.
+__global__ void k_gather_bia_ld(const double* bmo, const double* sqrt_delta, double scale,
+                                int64_t naux, int64_t nbf, int64_t nocc, int64_t ld, double* bt);
+
 }  // namespace qsgw

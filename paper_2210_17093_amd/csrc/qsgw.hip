@@ -1137,6 +1137,95 @@ int qsgw_iterate(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   return rc2;
 }
 
+// Open-shell GW potential, FP64.  Transitions of both spins share one Casida
+// problem (spin alpha first); the concatenated Bt carries sqrt(Delta) / sqrt(2),
+// so the closed-shell kernels give the open-shell factors: the Casida epilogue's
+// 4 Bt^T Bt becomes 2 K sqrt(Delta)..sqrt(Delta), and rho' = sqrt(2 / Omega) Bt Z^T
+// becomes the spin-resolved sqrt(1 / Omega) B_ia (X+Y) sum without the singlet sqrt(2).
+int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a, int64_t nocc_b,
+                         const double* B_mo_a, const double* B_mo_b, const double* eps_a,
+                         const double* eps_b, double eta, double* V_a, double* V_b,
+                         double* Omega_out, int precision) {
+  CHECK(check_common(c, nbf, naux));
+  if (!(nocc_a > 0 && nocc_a < nbf && nocc_b > 0 && nocc_b < nbf))
+    return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc_a, nocc_b < nbf");
+  if (!(eta > 0.0) || !isfinite(eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need finite eta > 0");
+  if (!B_mo_a || !B_mo_b || !eps_a || !eps_b || !V_a || !V_b)
+    return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  if (precision != QSGW_PREC_FP64)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "qsgw_gw_unrestricted: FP64 only (precision %d)", precision);
+  const int64_t nn = nbf * nbf;
+  const int64_t no[2] = {nocc_a, nocc_b};
+  const int64_t nt[2] = {nocc_a * (nbf - nocc_a), nocc_b * (nbf - nocc_b)};
+  const int64_t ntr = nt[0] + nt[1];
+  const double* Bs[2] = {B_mo_a, B_mo_b};
+  const double* es[2] = {eps_a, eps_b};
+  double* Vs[2] = {V_a, V_b};
+  if (ntr > 46340) return fail(c, QSGW_ERR_INVALID_ARG, "too many transitions for one Casida matrix");
+  double *Bt, *delta, *sqd, *M, *Omega, *rho, *w, *wh;
+  int* flags;
+  CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
+  CHECK(ws_get(c, W_DELTA, (size_t)ntr, &delta));
+  CHECK(ws_get(c, W_SQD, (size_t)ntr, &sqd));
+  CHECK(ws_get(c, W_M, (size_t)(ntr * ntr), &M));
+  CHECK(ws_get(c, W_OMEGA, (size_t)ntr, &Omega));
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  const int64_t cap = (int64_t)((8ull << 30) / (sizeof(double) * (uint64_t)nn));
+  const int64_t sb = ntr < cap ? ntr : (cap < 64 ? 64 : cap);
+  CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
+  CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
+  CHECK(ws_get(c, W_WH, (size_t)(nn * sb), &wh));
+  Spans spn;
+  spn.c = c;
+  HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+  CHECK(spn.open(kStageRpa));
+  int64_t off = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t nv = nbf - no[sp];
+    hipLaunchKernelGGL(k_transitions, dim3(blocks_for(nt[sp])), dim3(256), 0, c->stream, es[sp],
+                       no[sp], nv, delta + off, sqd + off, flags);
+    CHECK(launch_check(c, "k_transitions"));
+    hipLaunchKernelGGL(k_gather_bia_ld, dim3(blocks_for(naux * nt[sp])), dim3(256), 0, c->stream,
+                       Bs[sp], sqd + off, 1.0 / sqrt(2.0), naux, nbf, no[sp], ntr, Bt + off);
+    CHECK(launch_check(c, "k_gather_bia_ld"));
+    off += nt[sp];
+  }
+  int bad = 0;
+  CHECK(read_flag(c, flags, &bad));
+  if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "need eps[a] > eps[i] for every transition");
+  {
+    EpiCasida E{M, delta, ntr};
+    Strided<false> A{Bt, 1, ntr, 0, ntr};
+    CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_CASIDA], "gw_unrestricted/casida", A, A,
+                                    E, ntr, ntr, naux, 1)));
+  }
+  CHECK(spn.close());
+  CHECK(spn.open(kStageEigRpa));
+  CHECK(stage_rpa_solve(c, ntr, M, Omega));
+  CHECK(spn.close());
+  for (int sp = 0; sp < 2; ++sp) {
+    for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
+      const int64_t ns = ntr - s0 < sb ? ntr - s0 : sb;
+      CHECK(spn.open(kStageRes));
+      CHECK(stage_residues(c, nbf, naux, ntr, Bs[sp], Bt, M, Omega, s0, ns, rho, w, nullptr, wh,
+                           es[sp], no[sp], eta));
+      CHECK(spn.close());
+      CHECK(spn.open(kStageSigma));
+      CHECK(stage_sigma_qs(c, nbf, no[sp], ns, w, es[sp], Omega + s0, eta, Vs[sp],
+                           s0 > 0 ? 1 : 0, nullptr, wh));
+      CHECK(spn.close());
+    }
+  }
+  if (Omega_out)
+    HIP_TRY(c, hipMemcpyAsync(Omega_out, Omega, (size_t)ntr * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 7; ++i) c->stage_ms[i] = 0.0;
+  for (const auto& span : spn.v) c->stage_ms[span.id] += elapsed(c, span.e0, span.e1);
+  c->last_stage = -1;  // qsgw_last_stage_ms reports stage_ms as set here
+  return QSGW_OK;
+}
+
 int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {
   if (!c) return QSGW_ERR_INVALID_ARG;
   Tiles t;  // defaults

@@ -43,7 +43,8 @@ STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "
 
 EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
-           "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_ao2mo_4center", "qsgw_hf_core", "qsgw_iterate",
+           "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_ao2mo_4center",
+           "qsgw_gw_unrestricted", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
            "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles")
 
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_hf_core": ([P, I64, I64, I64, P, P, P, P], I),
         "qsgw_mp2_sigma": ([P, I64, I64, I64, P, P, D, P, I64, I, I], I),
         "qsgw_ao2mo_4center": ([P, I64, P, P, I64, I64, P, I], I),
+        "qsgw_gw_unrestricted": ([P, I64, I64, I64, I64, P, P, P, P, D, P, P, P, I], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
         "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
@@ -333,6 +335,25 @@ def qsgw_ao2mo_4center(ctx: Context, eri_ao, C, m_begin=0, m_count=None, out=Non
                                        _ptr(out, (m_count, nbf, nbf, nbf), name="out"),
                                        int(precision)))
     return out
+
+
+def qsgw_gw_unrestricted(ctx: Context, B_mo_a, B_mo_b, eps_a, eps_b, nocc_a, nocc_b, eta,
+                         precision=PREC_FP64):
+    """Open-shell GW potential of each spin; returns (V_a, V_b, Omega)."""
+    naux, nbf, _ = B_mo_a.shape
+    ntr = nocc_a * (nbf - nocc_a) + nocc_b * (nbf - nocc_b)
+    V_a = torch.empty((nbf, nbf), dtype=torch.float64, device=B_mo_a.device)
+    V_b = torch.empty_like(V_a)
+    Om = torch.empty((ntr,), dtype=torch.float64, device=B_mo_a.device)
+    ctx.check(lib().qsgw_gw_unrestricted(ctx.handle, nbf, naux, int(nocc_a), int(nocc_b),
+                                         _ptr(B_mo_a, (naux, nbf, nbf), name="B_mo_a"),
+                                         _ptr(B_mo_b, (naux, nbf, nbf), name="B_mo_b"),
+                                         _ptr(eps_a, (nbf,), name="eps_a"),
+                                         _ptr(eps_b, (nbf,), name="eps_b"), float(eta),
+                                         _ptr(V_a, (nbf, nbf), name="V_a"),
+                                         _ptr(V_b, (nbf, nbf), name="V_b"),
+                                         _ptr(Om, (ntr,), name="Omega"), int(precision)))
+    return V_a, V_b, Om
 
 
 def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):

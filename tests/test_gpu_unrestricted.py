@@ -1,0 +1,101 @@
+"""Parity of the open-shell (spin-unrestricted) GW potential on the GPU.
+
+Each spin has its own orbitals (two seeded orthogonal matrices applied to one
+synthetic AO tensor), energies and occupation.  The GPU call builds and solves
+the shared Casida problem and the potential of each spin; it is compared with
+the FP64 oracle element by element, and with the restricted GPU chain when
+both spins are equal.  The eigensolvers differ (rocSOLVER dsyevd, LAPACK
+dsyevr), so V is compared at 1e-10 of its largest element (eta well above the
+level spacing of the poles it weights); Omega at 1e-11 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from qsgw_inputs import make_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2210_17093_amd.qsgw as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context()
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def two_spins(nbf, naux, nocc_a, nocc_b, seed):
+    pa = make_problem(nbf, naux, nocc_a, max(1, naux // 2), 0.99, seed, coupling=0.1)
+    pb = make_problem(nbf, naux, nocc_b, max(1, naux // 2), 0.99, seed + 100, coupling=0.1)
+    return ([O.mo_transform(pa.B_ao, pa.C0), O.mo_transform(pa.B_ao, pb.C0)],
+            [pa.eps0, pb.eps0], [nocc_a, nocc_b])
+
+
+CASES = [  # nbf, naux, nocc_a, nocc_b, eta
+    (2, 1, 1, 1, 0.05),
+    (6, 9, 3, 2, 0.05),
+    (5, 7, 1, 3, 0.02),
+    (24, 96, 5, 4, 0.05),
+    (37, 53, 9, 8, 0.02),
+    (70, 150, 11, 10, 0.05),
+]
+
+
+@pytest.mark.parametrize("nbf,naux,na,nb,eta", CASES)
+def test_unrestricted_matches_oracle(q, ctx, nbf, naux, na, nb, eta):
+    print(f"[uhf] nbf={nbf} naux={naux} nocc=({na}, {nb}) eta={eta}", flush=True)
+    B_s, e_s, n_s = two_spins(nbf, naux, na, nb, nbf)
+    V_ref, Om_ref = O.gw_unrestricted(B_s, e_s, n_s, eta)
+    Va, Vb, Om = q.qsgw_gw_unrestricted(ctx, dev(B_s[0]), dev(B_s[1]), dev(e_s[0]), dev(e_s[1]),
+                                        na, nb, eta)
+    np.testing.assert_allclose(host(Om), Om_ref, rtol=1e-11)
+    for V, R in ((host(Va), V_ref[0]), (host(Vb), V_ref[1])):
+        np.testing.assert_array_equal(V, V.T)
+        assert np.abs(V - R).max() <= 1e-10 * np.abs(R).max() + 1e-15
+
+
+def test_unrestricted_equal_spins_is_restricted_chain(q, ctx):
+    p = make_problem(30, 80, 6, 40, 0.99, 4, coupling=0.1)
+    eta = 0.05
+    B_mo = q.qsgw_mo_transform(ctx, dev(p.B_ao), dev(p.C0))
+    e = dev(p.eps0)
+    M, sq = q.qsgw_rpa_build(ctx, B_mo, e, 6)
+    Z, Om_r = q.qsgw_rpa_solve(ctx, M)
+    w, wh = q.qsgw_residues(ctx, B_mo, sq, Z, Om_r, 6, weighted=True, eps=e, eta=eta)
+    Vr = host(q.qsgw_sigma_qs(ctx, w, e, Om_r, 6, eta, wh=wh))
+    Va, Vb, Om = q.qsgw_gw_unrestricted(ctx, B_mo, B_mo, e, e, 6, 6, eta)
+    scale = np.abs(Vr).max()
+    assert np.abs(host(Va) - Vr).max() <= 1e-10 * scale
+    np.testing.assert_array_equal(host(Va), host(Vb))
+    both = np.sort(np.concatenate([host(Om_r), O.transition_energies(p.eps0, 6)]))
+    np.testing.assert_allclose(host(Om), both, rtol=1e-11)
+
+
+def test_unrestricted_errors(q, ctx):
+    B_s, e_s, n_s = two_spins(6, 5, 2, 2, 0)
+    args = [dev(B_s[0]), dev(B_s[1]), dev(e_s[0]), dev(e_s[1])]
+    with pytest.raises(q.QsgwError) as x:
+        q.qsgw_gw_unrestricted(ctx, *args, 2, 2, 0.05, precision=q.PREC_FP32)
+    assert x.value.code == q.ERR_UNSUPPORTED
+    for na, nb, eta in ((0, 2, 0.05), (2, 6, 0.05), (2, 2, 0.0)):
+        with pytest.raises(q.QsgwError) as x:
+            q.qsgw_gw_unrestricted(ctx, *args, na, nb, eta)
+        assert x.value.code == q.ERR_INVALID_ARG
