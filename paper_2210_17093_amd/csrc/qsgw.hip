@@ -225,7 +225,10 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
                      double* rho, double* w, Spans* sp, double* wh, const double* eps, int64_t nocc,
                      double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
                      const float* B_mo32 = nullptr, const float* Bt32_in = nullptr,
-                     bool reuse_split = false, const X3Out* x3o = nullptr) {
+                     bool reuse_split = false, const X3Out* x3o = nullptr,
+                     bool rho_ready = false) {
+  // rho_ready (FP64 only): rho already holds rho' of this block (computed for
+  // another MO tensor with the same Bt and Z), so only the w product runs.
   // The FP32 variant reads FP32 copies of B_mo and rho' in the residue
   // product (half the operand bytes); rounding them is what its matrix cores
   // do anyway.  The split-BF16 variant reads them split into BF16 halves in
@@ -288,7 +291,7 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       B_mo32 = b32;
     }
   }
-  {
+  if (!(rho_ready && !f32)) {
     const int64_t maxk = f32 ? kFp32MaxK : ntr;
     const int64_t kr = x3 ? kpt : ntr;  // (k length of the product)
     SplitPlan spl = rho_split(c->tiles, naux, ns, kr, maxk);
@@ -373,7 +376,8 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    const double* eps = nullptr, int64_t nocc = 0, double eta = 0.0,
                    int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
                    double thr = 0.0, const float* B_mo32 = nullptr, const float* Bt32 = nullptr,
-                   bool reuse_split = false, const X3Out* x3o = nullptr) {
+                   bool reuse_split = false, const X3Out* x3o = nullptr,
+                   bool rho_ready = false) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
@@ -381,7 +385,8 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
     return stage_residues_t<Bf16x3>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                     eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, reuse_split, x3o);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                  eps, nocc, eta);
+                                  eps, nocc, eta, nullptr, nullptr, 0.0, nullptr, nullptr, false,
+                                  nullptr, rho_ready);
 }
 
 // Reduced-precision variant of Eq. (19) for one excitation block (PT: float
@@ -1203,12 +1208,14 @@ int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a,
   CHECK(spn.open(kStageEigRpa));
   CHECK(stage_rpa_solve(c, ntr, M, Omega));
   CHECK(spn.close());
-  for (int sp = 0; sp < 2; ++sp) {
-    for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
-      const int64_t ns = ntr - s0 < sb ? ntr - s0 : sb;
+  for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
+    const int64_t ns = ntr - s0 < sb ? ntr - s0 : sb;
+    for (int sp = 0; sp < 2; ++sp) {
+      // rho' of the block is shared by both spins
       CHECK(spn.open(kStageRes));
       CHECK(stage_residues(c, nbf, naux, ntr, Bs[sp], Bt, M, Omega, s0, ns, rho, w, nullptr, wh,
-                           es[sp], no[sp], eta));
+                           es[sp], no[sp], eta, QSGW_PREC_FP64, nullptr, nullptr, 0.0, nullptr,
+                           nullptr, false, nullptr, sp > 0));
       CHECK(spn.close());
       CHECK(spn.open(kStageSigma));
       CHECK(stage_sigma_qs(c, nbf, no[sp], ns, w, es[sp], Omega + s0, eta, Vs[sp],
