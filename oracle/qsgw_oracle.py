@@ -417,3 +417,23 @@ def gw_unrestricted(B_mo_s, eps_s, nocc_s, eta):
     V = [sigma_qs(residues_unrestricted(B, Bt, XpY), e, Om, no, eta)
          for B, e, no in zip(B_mo_s, eps_s, nocc_s)]
     return V, Om
+
+
+def fock_unrestricted(h, B_ao, C_s, nocc_s, V_s):
+    """Eq. (6) per spin with explicit spins: F^sigma = h + J[D^alpha + D^beta] - K[D^sigma]
+    + C^sigma V^sigma C^sigma^T, D^sigma from Eq. (9) with that spin's occupied
+    orbitals, J[D] = sum_P B^P (B^P . D) (Eq. 7), K[D] = sum_P B^P D B^P (Eq. 10)."""
+    D = [density(C, no) for C, no in zip(C_s, nocc_s)]
+    Dt = D[0] + D[1]
+    J = np.einsum("p,pmn->mn", np.einsum("plt,lt->p", B_ao, Dt), B_ao)
+    return [h + J - exchange(B_ao, Ds) + C @ V @ C.T for Ds, C, V in zip(D, C_s, V_s)]
+
+
+def unrestricted_step(B_ao, h, C_s, eps_s, nocc_s, eta):
+    """One open-shell qsGW step: MO transform per spin, the open-shell GW
+    potential, the Fock matrix of each spin and its eigenproblem (Eq. 4, S = I).
+    Returns ([eps'_alpha, eps'_beta], [C'_alpha, C'_beta])."""
+    B_mo_s = [mo_transform(B_ao, C) for C in C_s]
+    V_s, _ = gw_unrestricted(B_mo_s, eps_s, nocc_s, eta)
+    out = [diagonalize(F) for F in fock_unrestricted(h, B_ao, C_s, nocc_s, V_s)]
+    return [e for e, _ in out], [C for _, C in out]

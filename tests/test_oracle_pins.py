@@ -439,6 +439,39 @@ def test_p17_unrestricted_spin_sums(nocc_a, nocc_b):
         np.testing.assert_allclose(V[spin], Vp, rtol=0, atol=1e-10 * np.abs(Vp).max())
 
 
+def test_p18_unrestricted_fock():
+    """Open-shell Fock matrices: explicit four-index J[D_alpha + D_beta] and
+    K[D_sigma] (P9's route), and equal spins reduce to the closed-shell Fock."""
+    p = tiny(nbf=6, naux=10, nocc=3, seed=14)
+    q2 = make_problem(6, 10, 2, 10, 0.9, 15, coupling=1.0)
+    C_s, n_s = [p.C0, q2.C0], [3, 2]
+    rng = np.random.default_rng(3)
+    V_s = [(lambda a: a + a.T)(rng.standard_normal((6, 6))) for _ in range(2)]
+    h = O.hf_core(p.B_ao, p.C0, p.eps0, 3)
+    F = O.fock_unrestricted(h, p.B_ao, C_s, n_s, V_s)
+    D = [O.density(C, no) for C, no in zip(C_s, n_s)]
+    Jt = pins.jk_four_index(p.B_ao, 0.5 * (D[0] + D[1]))[0]
+    for s_ in (0, 1):
+        K = pins.jk_four_index(p.B_ao, D[s_])[1]
+        ref = h + Jt - K + C_s[s_] @ V_s[s_] @ C_s[s_].T
+        np.testing.assert_allclose(F[s_], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    Fr = O.fock(h, p.B_ao, p.C0, 3, V_s[0])
+    Fe = O.fock_unrestricted(h, p.B_ao, [p.C0, p.C0], [3, 3], [V_s[0], V_s[0]])
+    np.testing.assert_allclose(Fe[0], Fr, rtol=0, atol=1e-12 * np.abs(Fr).max())
+    np.testing.assert_allclose(Fe[1], Fr, rtol=0, atol=1e-12 * np.abs(Fr).max())
+
+
+def test_unrestricted_step_equal_spins_is_qsgw_step():
+    p = tiny(nbf=7, naux=11, nocc=3, seed=6, coupling=0.1)
+    h = O.hf_core(p.B_ao, p.C0, p.eps0, 3)
+    r = O.qsgw_step(p.B_ao, h, p.C0, p.eps0, 3, 0.02)
+    e_r, C_r = r["eps"], r["C"]
+    e_u, C_u = O.unrestricted_step(p.B_ao, h, [p.C0, p.C0], [p.eps0, p.eps0], [3, 3], 0.02)
+    for s_ in (0, 1):
+        np.testing.assert_allclose(e_u[s_], e_r, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(C_u[s_], C_r, rtol=0, atol=1e-10)
+
+
 def test_mutant_unrestricted_spin_factor_caught(monkeypatch):
     """The closed-shell factor 2 of the Casida coupling left in the open-shell
     build fails P17."""
