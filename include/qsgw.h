@@ -261,6 +261,27 @@ int qsgw_gw_unrestricted(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc_
                          double* Omega_out, int precision);
 
 /*
+ * Open-shell Fock update of both spins, Eqs. (4), (6), (7), (9), (10) with
+ * explicit spins, in the MO basis of each spin's current orbitals C_sigma:
+ *   F_sigma = C_sigma^T h C_sigma + J - K_sigma + V_sigma,
+ *   J[m][n] = sum_P B^{sigma P}_mn (t^alpha_P + t^beta_P),  t^s_P = sum_{i < nocc_s} B^{s P}_ii,
+ *   K_sigma[m][n] = sum_P sum_{i < nocc_sigma} B^{sigma P}_mi B^{sigma P}_ni,
+ * then F_sigma = U diag(eps') U^T and C_sigma <- C_sigma U, each column's
+ * largest-magnitude entry made positive.
+ * B_mo_a, B_mo_b: [naux][nbf][nbf] device, the MO tensors of the current C_a, C_b;
+ * h: [nbf][nbf] device (AO basis, orthonormal); V_a, V_b: [nbf][nbf] device, the
+ *   spins' correlation potentials in their current MO bases (qsgw_gw_unrestricted);
+ * eps_a, eps_b: [nbf] device out; C_a, C_b: [nbf][nbf] device in/out.
+ * Errors: 0 < nocc_a, nocc_b < nbf violated, naux < 1, NULL pointers,
+ * QSGW_ERR_SOLVER if dsyevd fails.  Synchronizes the context stream; timed as
+ * the fock stage of qsgw_last_stage_ms.
+ */
+int qsgw_fock_unrestricted(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc_a, int64_t nocc_b,
+                           const double* B_mo_a, const double* B_mo_b, const double* h,
+                           const double* V_a, const double* V_b, double* eps_a, double* eps_b,
+                           double* C_a, double* C_b);
+
+/*
  * One-body matrix that makes (eps0, C0) a Hartree-Fock fixed point of
  * Eq. (6) with Sigma_c = 0:  h = C0 diag(eps0) C0^T - J[D0] + K[D0],
  * D0 = C0[:, :nocc] C0[:, :nocc]^T (Eq. (9)), J and K from Eqs. (7), (10).

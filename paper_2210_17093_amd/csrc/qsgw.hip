@@ -1233,6 +1233,82 @@ int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a,
   return QSGW_OK;
 }
 
+// Open-shell Fock update in the MO basis of each spin's current orbitals:
+// F = C^T h C + J - K + V with J from both spins' densities (the Hartree kernel
+// doubles its trace vector, so it gets half the summed traces) and K from that
+// spin's occupied orbitals; then eigenvectors U, C' = C U, signs fixed.
+int qsgw_fock_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a, int64_t nocc_b,
+                           const double* B_mo_a, const double* B_mo_b, const double* h,
+                           const double* V_a, const double* V_b, double* eps_a, double* eps_b,
+                           double* C_a, double* C_b) {
+  CHECK(check_common(c, nbf, naux));
+  if (!(nocc_a > 0 && nocc_a < nbf && nocc_b > 0 && nocc_b < nbf))
+    return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc_a, nocc_b < nbf");
+  if (!B_mo_a || !B_mo_b || !h || !V_a || !V_b || !eps_a || !eps_b || !C_a || !C_b)
+    return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  const int64_t nn = nbf * nbf;
+  const int64_t no[2] = {nocc_a, nocc_b};
+  const double* Bs[2] = {B_mo_a, B_mo_b};
+  const double* Vs[2] = {V_a, V_b};
+  double* es[2] = {eps_a, eps_b};
+  double* Cs[2] = {C_a, C_b};
+  double *cp, *J, *hmo, *F, *tmp, *epsn, *Cn;
+  CHECK(ws_get(c, W_CP, (size_t)(3 * naux), &cp));
+  CHECK(ws_get(c, W_J, (size_t)nn, &J));
+  CHECK(ws_get(c, W_HMO, (size_t)nn, &hmo));
+  CHECK(ws_get(c, W_F, (size_t)nn, &F));
+  CHECK(ws_get(c, W_TMP, (size_t)nn, &tmp));
+  CHECK(ws_get(c, W_EPSN, (size_t)nbf, &epsn));
+  CHECK(ws_get(c, W_CNEW, (size_t)nn, &Cn));
+  CHECK(single_begin(c, kStageFock));
+  for (int sp = 0; sp < 2; ++sp) {
+    hipLaunchKernelGGL(k_occ_trace, dim3(blocks_for(naux)), dim3(256), 0, c->stream, Bs[sp], naux,
+                       nbf, no[sp], cp + sp * naux);
+    CHECK(launch_check(c, "k_occ_trace"));
+  }
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(naux)), dim3(256), 0, c->stream, cp, cp + naux, 0.5,
+                     0.5, naux, cp + 2 * naux);
+  CHECK(launch_check(c, "k_axpby"));
+  for (int sp = 0; sp < 2; ++sp) {
+    constexpr int64_t pg = 32;
+    const int64_t ng = (naux + pg - 1) / pg;
+    double* jp = nullptr;
+    CHECK(ws_get(c, W_REDPART, (size_t)(ng * nn), &jp));
+    hipLaunchKernelGGL(k_hartree_part, dim3(blocks_for(ng * nn)), dim3(256), 0, c->stream, Bs[sp],
+                       cp + 2 * naux, naux, nn, pg, jp);
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(nn)), dim3(256), 0, c->stream, jp, ng, nn, ng,
+                       J);
+    CHECK(launch_check(c, "k_hartree_part"));
+    const SplitPlan spl = exchange_split(c->tiles, nbf, naux, no[sp]);
+    double* Kpart = nullptr;
+    CHECK(ws_get(c, W_PART, (size_t)(spl.nz * nn), &Kpart));
+    {
+      OccRowsOp A{Bs[sp], nbf, no[sp]};
+      EpiStore E{Kpart, nbf, 0, nn, 1.0};
+      CHECK((gemm_shape<double, true>(c, c->tiles.shape[TU_EXCHANGE], "fock_u/exchange", A, A, E,
+                                      nbf, nbf, naux * no[sp], 1, spl)));
+    }
+    CHECK(congruence_t(c, nbf, Cs[sp], h, tmp, hmo));
+    hipLaunchKernelGGL(k_fock_assemble, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hmo, J,
+                       Kpart, spl.nz, Vs[sp], nbf, F);
+    CHECK(launch_check(c, "k_fock_assemble"));
+    CHECK(syevd(c, nbf, F, epsn, "fock_u/eig"));
+    {  // C' = C U (U column-major in F)
+      Strided<true> A{Cs[sp], nbf, 1, 0, nbf};
+      Strided<true> B{F, nbf, 1, 0, nbf};
+      EpiStore E{Cn, nbf, 0, 0, 1.0};
+      CHECK((gemm<64, 64, false>(c, "fock_u/rotate", A, B, E, nbf, nbf, nbf, 1)));
+    }
+    hipLaunchKernelGGL(k_fix_column_signs, dim3(blocks_for(nbf)), dim3(256), 0, c->stream, Cn, nbf);
+    CHECK(launch_check(c, "k_fix_column_signs"));
+    HIP_TRY(c, hipMemcpyAsync(es[sp], epsn, nbf * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(Cs[sp], Cn, nn * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+  }
+  return single_end(c);
+}
+
 int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {
   if (!c) return QSGW_ERR_INVALID_ARG;
   Tiles t;  // defaults

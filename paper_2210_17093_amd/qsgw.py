@@ -44,7 +44,7 @@ STAGES = ("mo_transform", "rpa_build", "eig_rpa", "residues", "sigma", "fock", "
 EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error",
            "qsgw_last_stage_ms", "qsgw_mo_transform", "qsgw_rpa_build", "qsgw_rpa_solve",
            "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_ao2mo_4center",
-           "qsgw_gw_unrestricted", "qsgw_hf_core", "qsgw_iterate",
+           "qsgw_gw_unrestricted", "qsgw_fock_unrestricted", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
            "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles")
 
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_mp2_sigma": ([P, I64, I64, I64, P, P, D, P, I64, I, I], I),
         "qsgw_ao2mo_4center": ([P, I64, P, P, I64, I64, P, I], I),
         "qsgw_gw_unrestricted": ([P, I64, I64, I64, I64, P, P, P, P, D, P, P, P, I], I),
+        "qsgw_fock_unrestricted": ([P, I64, I64, I64, I64, P, P, P, P, P, P, P, P, P], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
         "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
@@ -354,6 +355,22 @@ def qsgw_gw_unrestricted(ctx: Context, B_mo_a, B_mo_b, eps_a, eps_b, nocc_a, noc
                                          _ptr(V_b, (nbf, nbf), name="V_b"),
                                          _ptr(Om, (ntr,), name="Omega"), int(precision)))
     return V_a, V_b, Om
+
+
+def qsgw_fock_unrestricted(ctx: Context, B_mo_a, B_mo_b, h, V_a, V_b, nocc_a, nocc_b, eps_a, eps_b,
+                           C_a, C_b):
+    """Open-shell Fock update: eps_a, eps_b (out) and C_a, C_b (in/out) in place."""
+    naux, nbf, _ = B_mo_a.shape
+    sq = (nbf, nbf)
+    ctx.check(lib().qsgw_fock_unrestricted(ctx.handle, nbf, naux, int(nocc_a), int(nocc_b),
+                                           _ptr(B_mo_a, (naux, nbf, nbf), name="B_mo_a"),
+                                           _ptr(B_mo_b, (naux, nbf, nbf), name="B_mo_b"),
+                                           _ptr(h, sq, name="h"), _ptr(V_a, sq, name="V_a"),
+                                           _ptr(V_b, sq, name="V_b"),
+                                           _ptr(eps_a, (nbf,), name="eps_a"),
+                                           _ptr(eps_b, (nbf,), name="eps_b"),
+                                           _ptr(C_a, sq, name="C_a"), _ptr(C_b, sq, name="C_b")))
+    return eps_a, eps_b, C_a, C_b
 
 
 def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):

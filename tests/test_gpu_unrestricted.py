@@ -99,3 +99,48 @@ def test_unrestricted_errors(q, ctx):
         with pytest.raises(q.QsgwError) as x:
             q.qsgw_gw_unrestricted(ctx, *args, na, nb, eta)
         assert x.value.code == q.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("nbf,naux,na,nb", [(6, 9, 3, 2), (24, 96, 5, 4), (37, 53, 9, 8)])
+def test_unrestricted_step_matches_oracle(q, ctx, nbf, naux, na, nb):
+    """One open-shell step through the C-ABI (MO transform of each spin, the
+    open-shell GW potential, the open-shell Fock update) against the oracle's."""
+    print(f"[uhf-step] nbf={nbf} naux={naux} nocc=({na}, {nb})", flush=True)
+    eta = 0.05
+    pa = make_problem(nbf, naux, na, max(1, naux // 2), 0.99, nbf, coupling=0.1)
+    pb = make_problem(nbf, naux, nb, max(1, naux // 2), 0.99, nbf + 100, coupling=0.1)
+    h = O.hf_core(pa.B_ao, pa.C0, pa.eps0, na)
+    e_ref, C_ref = O.unrestricted_step(pa.B_ao, h, [pa.C0, pb.C0], [pa.eps0, pb.eps0], [na, nb],
+                                       eta)
+    Bd = dev(pa.B_ao)
+    Ca, Cb = dev(pa.C0), dev(pb.C0)
+    ea, eb = dev(pa.eps0), dev(pb.eps0)
+    Ba = q.qsgw_mo_transform(ctx, Bd, Ca)
+    Bb = q.qsgw_mo_transform(ctx, Bd, Cb)
+    Va, Vb, _ = q.qsgw_gw_unrestricted(ctx, Ba, Bb, ea, eb, na, nb, eta)
+    ea2, eb2 = torch.empty_like(ea), torch.empty_like(eb)
+    q.qsgw_fock_unrestricted(ctx, Ba, Bb, dev(h), Va, Vb, na, nb, ea2, eb2, Ca, Cb)
+    V_ref, _ = O.gw_unrestricted([O.mo_transform(pa.B_ao, pa.C0), O.mo_transform(pa.B_ao, pb.C0)],
+                                 [pa.eps0, pb.eps0], [na, nb], eta)
+    F_ref = O.fock_unrestricted(h, pa.B_ao, [pa.C0, pb.C0], [na, nb], V_ref)
+    for e, C, er, F in ((ea2, Ca, e_ref[0], F_ref[0]), (eb2, Cb, e_ref[1], F_ref[1])):
+        e, C = host(e), host(C)
+        np.testing.assert_allclose(e, er, rtol=0, atol=1e-8)
+        np.testing.assert_allclose(C.T @ C, np.eye(nbf), rtol=0, atol=1e-11)
+        np.testing.assert_allclose(C.T @ F @ C, np.diag(er), rtol=0, atol=1e-8)
+
+
+def test_unrestricted_step_equal_spins_is_iterate(q, ctx):
+    p = make_problem(30, 80, 6, 40, 0.99, 4, coupling=0.1)
+    eta = 0.05
+    Bd, e0, C0 = dev(p.B_ao), dev(p.eps0), dev(p.C0)
+    h = q.qsgw_hf_core(ctx, Bd, C0, e0, 6)
+    e_it, C_it = e0.clone(), C0.clone()
+    q.qsgw_iterate(ctx, Bd, h, 6, e_it, C_it, eta, tol=0.0, max_iter=1)
+    B_mo = q.qsgw_mo_transform(ctx, Bd, C0)
+    Va, Vb, _ = q.qsgw_gw_unrestricted(ctx, B_mo, B_mo, e0, e0, 6, 6, eta)
+    Ca, Cb = C0.clone(), C0.clone()
+    ea, eb = torch.empty_like(e0), torch.empty_like(e0)
+    q.qsgw_fock_unrestricted(ctx, B_mo, B_mo, h, Va, Vb, 6, 6, ea, eb, Ca, Cb)
+    np.testing.assert_allclose(host(ea), host(e_it), rtol=0, atol=1e-10)
+    np.testing.assert_array_equal(host(ea), host(eb))
