@@ -68,6 +68,7 @@ SHAPES = [  # nbf, naux, nocc, seed
     (24, 96, 5, 2),
     (37, 53, 9, 3),
     (70, 150, 11, 4),
+    (6, 8, 5, 5),  # one empty state
 ]
 
 

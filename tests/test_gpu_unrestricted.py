@@ -56,6 +56,7 @@ CASES = [  # nbf, naux, nocc_a, nocc_b, eta
     (24, 96, 5, 4, 0.05),
     (37, 53, 9, 8, 0.02),
     (70, 150, 11, 10, 0.05),
+    (6, 8, 5, 4, 0.05),  # one empty alpha state
 ]
 
 
