@@ -334,6 +334,12 @@ typedef struct {
  * counts it: its last max_deps entry is the FP64 iteration's, and converged
  * and the return code are that iteration's. */
 #define QSGW_OPT_REFINE 2
+/* qsgw_options.flags, qsgw_iterate only: each iteration's correlation
+ * potential is the qsMP2 potential of Eqs. (20)-(21) (as qsgw_mp2_sigma,
+ * automatic blocks) instead of the qsGW one; the Casida problem is not built.
+ * Needs precision QSGW_PREC_FP64 and state.diag NULL (QSGW_ERR_UNSUPPORTED
+ * otherwise); its time is reported as the sigma stage. */
+#define QSGW_OPT_QSMP2 4
 
 typedef struct {
   int64_t iterations; /* iterations done in this call */

@@ -437,3 +437,12 @@ def unrestricted_step(B_ao, h, C_s, eps_s, nocc_s, eta):
     V_s, _ = gw_unrestricted(B_mo_s, eps_s, nocc_s, eta)
     out = [diagonalize(F) for F in fock_unrestricted(h, B_ao, C_s, nocc_s, V_s)]
     return [e for e, _ in out], [C for _, C in out]
+
+
+def qsmp2_step(B_ao, h, C, eps, nocc, eta):
+    """One qsMP2 iteration: MO transform (Eq. 16), the qsMP2 potential (Eqs. 20-21)
+    in place of the qsGW one, Fock matrix (Eq. 6) and its eigenproblem.
+    Returns (eps', C')."""
+    B_mo = mo_transform(B_ao, C)
+    V = qsmp2_potential(B_mo, eps, nocc, eta)
+    return diagonalize(fock(h, B_ao, C, nocc, V))

@@ -125,6 +125,11 @@ struct qsgw_ctx {
   bool aux_ready = false;
 };
 
+// qsMP2 potential of Eqs. (20)-(21) in the MO basis (mp2.hip), for the
+// iteration driver: V (+)= the potential; occ_block 0 = automatic blocks.
+int qsgw_mp2_stage(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                   const double* eps, double eta, double* V, int64_t occ_block, int accumulate);
+
 namespace {
 
 constexpr int kStageMo = 0, kStageRpa = 1, kStageEigRpa = 2, kStageRes = 3, kStageSigma = 4,

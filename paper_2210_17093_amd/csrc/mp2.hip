@@ -87,6 +87,11 @@ int stage_mp2(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double
 
 }  // namespace
 
+int qsgw_mp2_stage(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
+                   const double* eps, double eta, double* V, int64_t occ_block, int accumulate) {
+  return stage_mp2(c, nbf, naux, nocc, B_mo, eps, eta, V, occ_block, accumulate);
+}
+
 extern "C" {
 
 int qsgw_mp2_sigma(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,

@@ -843,6 +843,11 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   if (o->s_block < 0) return fail(c, QSGW_ERR_INVALID_ARG, "need s_block >= 0");
   if (!(o->near_pole >= 0.0) || !isfinite(o->near_pole))
     return fail(c, QSGW_ERR_INVALID_ARG, "need a finite near_pole >= 0");
+  const bool qsmp2 = (o->flags & QSGW_OPT_QSMP2) != 0;
+  if (qsmp2 && o->precision != QSGW_PREC_FP64)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "QSGW_OPT_QSMP2 runs in FP64 only");
+  if (qsmp2 && st->diag)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "QSGW_OPT_QSMP2 writes no diagonal self-energy");
   const bool fp32 = o->precision != QSGW_PREC_FP64;  // FP32 or split-BF16 products
   const double near = o->near_pole > 0.0 ? o->near_pole : kNearPoleDefault;
 
@@ -931,6 +936,11 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
                       + 2.0 * a * b * b              // Hartree
                       + 8.0 * b * b * b;             // C^T h C, C V C^T, C U
   }
+  if (qsmp2) {  // the qsMP2 potential replaces Casida, residues and the qsGW product
+    const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
+    local.hot_flops = 4.0 * b * b * b * a + b * (b + 1.0) * t * a + 2.0 * b * b * b * t +
+                      b * (b + 1.0) * a * oc + 2.0 * a * b * b + 8.0 * b * b * b;
+  }
   {
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
     local.kernel_flops[kKMo1 - kKernelBase] = 2.0 * b * b * b * a;
@@ -951,73 +961,79 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     CHECK(sp.open(kStageMo));
     CHECK(stage_mo_transform(c, nbf, naux, p->B_ao, C, T, Bmo, &sp, o->precision, Bmo32));
     CHECK(sp.close());
-    HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
-    CHECK(sp.open(kStageRpa));
-    CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, M, sqd, delta, Bt, flags, &sp,
-                          o->precision));
-    CHECK(sp.close());
-    {
-      int bad = 0;
-      CHECK(read_flag(c, flags, &bad));
-      if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "orbital energies are not in aufbau order");
-    }
-    CHECK(sp.open(kStageEigRpa));
-    CHECK(stage_rpa_solve(c, ntr, M, Omega));
-    CHECK(sp.close());
-    for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
-      const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
-      CHECK(sp.open(kStageRes));
-      if (fp32) {
-        // FP32 products: the pole-weighted copy and w in FP32 share the wh buffer
-        // (the FP64 residues are written only for the diagonal outputs)
-        float* wh32 = reinterpret_cast<float*>(wh);
-        float* w32 = wh32 + nn * ns;
-        double* w64 = (it == 0 && st->diag) ? w : nullptr;
-        // split-BF16: the residue epilogue also writes the qsGW product's split operands
-        X3Out x3o{};
-        const bool x3 = o->precision == QSGW_PREC_SPLIT_BF16;
-        if (x3) {
-          x3o.cs = (nbf + 127) / 128 * 128;
-          x3o.nsp = (ns + 7) / 8 * 8;
-          x3o.kfar = x3_kfar(nbf, ns);
-          x3o.ws = static_cast<uint16_t*>(c->ws[W_SPLIT_W].p);
-          x3o.whs = x3o.ws + 2 * x3o.plane();
-          // the near-pole terms first: the residue epilogue keeps FP32
-          // residues only in the columns the near-pole part reads
-          CHECK(near_x3(c, nbf, nocc, ns, eps, Omega + s0, near, &x3o));
-        }
-        CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
-                             eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
-                             static_cast<const float*>(c->ws[W_BT32].p), s0 > 0,
-                             x3 ? &x3o : nullptr));
-        CHECK(sp.close());
-        CHECK(sp.open(kStageSigma));
-        if (x3)
-          CHECK(stage_sigma_qs32_t<Bf16x3>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
-                                           near, V, s0 > 0 ? 1 : 0, &sp, &x3o));
-        else
-          CHECK(stage_sigma_qs32_t<float>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
-                                          near, V, s0 > 0 ? 1 : 0, &sp));
-      } else {
-        CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps,
-                             nocc, o->eta, o->precision));
-        CHECK(sp.close());
-        CHECK(sp.open(kStageSigma));
-        CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
-                             wh));
-      }
+    if (qsmp2) {
+      CHECK(sp.open(kStageSigma));
+      CHECK(qsgw_mp2_stage(c, nbf, naux, nocc, Bmo, eps, o->eta, V, 0, 0));
       CHECK(sp.close());
-      if (it == 0 && st->diag) {
-        hipLaunchKernelGGL(k_sigma_diag_self, dim3((unsigned)nbf), dim3(256), 0, c->stream, w, eps,
-                           Omega + s0, nbf, nocc, ns, o->eta, (const int64_t*)nullptr, nbf,
-                           st->diag, (int64_t)4, s0 > 0 ? 1 : 0, flags + 3);
-        CHECK(launch_check(c, "k_sigma_diag_self"));
+    } else {
+      HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+      CHECK(sp.open(kStageRpa));
+      CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, M, sqd, delta, Bt, flags, &sp,
+                            o->precision));
+      CHECK(sp.close());
+      {
+        int bad = 0;
+        CHECK(read_flag(c, flags, &bad));
+        if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "orbital energies are not in aufbau order");
       }
-    }
-    if (it == 0 && st->diag) {
-      hipLaunchKernelGGL(k_exchange_diag, dim3((unsigned)nbf), dim3(256), 0, c->stream, Bmo, naux,
-                         nbf, nocc, st->diag + 3, (int64_t)4);
-      CHECK(launch_check(c, "k_exchange_diag"));
+      CHECK(sp.open(kStageEigRpa));
+      CHECK(stage_rpa_solve(c, ntr, M, Omega));
+      CHECK(sp.close());
+      for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
+        const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
+        CHECK(sp.open(kStageRes));
+        if (fp32) {
+          // FP32 products: the pole-weighted copy and w in FP32 share the wh buffer
+          // (the FP64 residues are written only for the diagonal outputs)
+          float* wh32 = reinterpret_cast<float*>(wh);
+          float* w32 = wh32 + nn * ns;
+          double* w64 = (it == 0 && st->diag) ? w : nullptr;
+          // split-BF16: the residue epilogue also writes the qsGW product's split operands
+          X3Out x3o{};
+          const bool x3 = o->precision == QSGW_PREC_SPLIT_BF16;
+          if (x3) {
+            x3o.cs = (nbf + 127) / 128 * 128;
+            x3o.nsp = (ns + 7) / 8 * 8;
+            x3o.kfar = x3_kfar(nbf, ns);
+            x3o.ws = static_cast<uint16_t*>(c->ws[W_SPLIT_W].p);
+            x3o.whs = x3o.ws + 2 * x3o.plane();
+            // the near-pole terms first: the residue epilogue keeps FP32
+            // residues only in the columns the near-pole part reads
+            CHECK(near_x3(c, nbf, nocc, ns, eps, Omega + s0, near, &x3o));
+          }
+          CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
+                               eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
+                               static_cast<const float*>(c->ws[W_BT32].p), s0 > 0,
+                               x3 ? &x3o : nullptr));
+          CHECK(sp.close());
+          CHECK(sp.open(kStageSigma));
+          if (x3)
+            CHECK(stage_sigma_qs32_t<Bf16x3>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
+                                             near, V, s0 > 0 ? 1 : 0, &sp, &x3o));
+          else
+            CHECK(stage_sigma_qs32_t<float>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
+                                            near, V, s0 > 0 ? 1 : 0, &sp));
+        } else {
+          CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps,
+                               nocc, o->eta, o->precision));
+          CHECK(sp.close());
+          CHECK(sp.open(kStageSigma));
+          CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
+                               wh));
+        }
+        CHECK(sp.close());
+        if (it == 0 && st->diag) {
+          hipLaunchKernelGGL(k_sigma_diag_self, dim3((unsigned)nbf), dim3(256), 0, c->stream, w, eps,
+                             Omega + s0, nbf, nocc, ns, o->eta, (const int64_t*)nullptr, nbf,
+                             st->diag, (int64_t)4, s0 > 0 ? 1 : 0, flags + 3);
+          CHECK(launch_check(c, "k_sigma_diag_self"));
+        }
+      }
+      if (it == 0 && st->diag) {
+        hipLaunchKernelGGL(k_exchange_diag, dim3((unsigned)nbf), dim3(256), 0, c->stream, Bmo, naux,
+                           nbf, nocc, st->diag + 3, (int64_t)4);
+        CHECK(launch_check(c, "k_exchange_diag"));
+      }
     }
     CHECK(sp.open(kStageFock));
     CHECK(sp.open(kKFock));

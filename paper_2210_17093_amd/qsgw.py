@@ -36,6 +36,7 @@ SIGMA_DIAG_SELF = 2
 FOCK_FULL_JK = 0
 OPT_GRAPH = 1
 OPT_REFINE = 2
+OPT_QSMP2 = 4
 REPORT_MAX_ITERS = 64
 MLP_NPARAMS = 18817
 MLP_NFEAT = 16
@@ -385,8 +386,9 @@ def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
 
 def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
                  Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None, refine=False,
-                 near_pole=0.0):
-    """Runs qsGW iterations in place on (eps, C).  Returns (status, report dict, iteration)."""
+                 near_pole=0.0, qsmp2=False):
+    """Runs qsGW iterations (qsMP2 iterations with qsmp2=True) in place on (eps, C).
+    Returns (status, report dict, iteration)."""
     naux, nbf, _ = B_ao.shape
     prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
                    _ptr(h, (nbf, nbf), name="h"))
@@ -394,7 +396,8 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
                _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration,
                _ptr(diag, (nbf, 4), name="diag") if diag is not None else None)
     opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
-                  int(s_block), OPT_REFINE if refine else 0, float(near_pole))
+                  int(s_block), (OPT_REFINE if refine else 0) | (OPT_QSMP2 if qsmp2 else 0),
+                  float(near_pole))
     rep = Report()
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))

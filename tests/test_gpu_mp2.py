@@ -14,7 +14,7 @@ import pytest
 
 import oracle as O
 import oracle.qsgw_oracle as OM
-from qsgw_inputs import make_mo_tensor
+from qsgw_inputs import make_mo_tensor, make_problem
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -127,3 +127,25 @@ def test_mp2_errors(q, ctx):
         with pytest.raises(q.QsgwError) as e:
             q.qsgw_mp2_sigma(ctx, Bd, ed, **kw)
         assert e.value.code == q.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("nbf,naux,nocc", [(7, 9, 3), (24, 60, 5), (37, 53, 9)])
+def test_qsmp2_iteration_matches_oracle(q, ctx, nbf, naux, nocc):
+    """Two qsMP2 iterations through qsgw_iterate (QSGW_OPT_QSMP2) against the
+    oracle's steps, on general RI factors in the AO basis."""
+    log(f"[qsmp2-iter] nbf={nbf} naux={naux} nocc={nocc}")
+    B_ao, eps0 = make_mo_tensor(nbf, naux, nocc, nbf)
+    C0 = make_problem(nbf, 2, nocc, 1, 0.5, nbf).C0
+    h = O.hf_core(B_ao, C0, eps0, nocc)
+    e_ref, C_ref = eps0, C0
+    for _ in range(2):
+        e_ref, C_ref = O.qsmp2_step(B_ao, h, C_ref, e_ref, nocc, ETA)
+    e, C = dev(eps0), dev(C0)
+    rc, rep, it = q.qsgw_iterate(ctx, dev(B_ao), dev(h), nocc, e, C, ETA, tol=0.0, max_iter=2,
+                                 qsmp2=True)
+    assert it == 2 and rep["iterations"] == 2
+    np.testing.assert_allclose(host(e), e_ref, rtol=0, atol=1e-8)
+    with pytest.raises(q.QsgwError) as x:
+        q.qsgw_iterate(ctx, dev(B_ao), dev(h), nocc, dev(eps0), dev(C0), ETA, tol=0.0,
+                       max_iter=1, qsmp2=True, precision=q.PREC_FP32)
+    assert x.value.code == q.ERR_UNSUPPORTED
