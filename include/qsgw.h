@@ -405,14 +405,16 @@ int qsgw_iterate_batched(qsgw_ctx* ctx, int64_t nmol, const qsgw_problem* probs,
  * Tile table of the context (written by the autotuner, tune.py).  spec is a
  * comma-separated list of key=value: mo1, rho, sigma take 64x64, 128x64 or
  * 128x128; mo2, casida, exchange (symmetric products) 64x64 or 128x128;
- * sigma_target, rho_target, exchange_target (integers in [64, 2^20]) are the
- * workgroup counts a K-split aims for when a product has few output tiles;
+ * sigma_target, rho_target, exchange_target, mp2_target (integers in
+ * [64, 2^20]) are the workgroup counts a K-split aims for when a product has
+ * few output tiles (mp2_target: the contraction of qsgw_mp2_sigma, whose
+ * tile shape is sigma's);
  * persistent (integer in [0, 8]): for the grouped products of
  * qsgw_iterate_batched, 0 launches one workgroup per tile, n > 0 a
  * persistent grid of n workgroups per compute unit that walk contiguous
  * tile ranges.  Keys not given keep their defaults (mo1=128x64, mo2=64x64,
  * casida=128x128, rho=128x128, sigma=64x64, exchange=64x64, 4096, 2048,
- * 2048, persistent=0); NULL or "" restores all defaults.  Every later product and
+ * 2048, mp2_target=32768, persistent=0); NULL or "" restores all defaults.  Every later product and
  * iteration on the context uses the table (results change only by rounding
  * order).  qsgw_get_tiles writes the current table in the same format.
  */

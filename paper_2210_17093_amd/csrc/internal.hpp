@@ -92,6 +92,8 @@ struct Tiles {
   int shape[TU_COUNT] = {SH_128x64, SH_64x64, SH_128x128, SH_128x128, SH_64x64, SH_64x64};
   // workgroups a K-split aims for when the output tiles alone are few
   int64_t sigma_target = 4096, rho_target = 2048, exchange_target = 2048;
+  // the qsMP2 contraction (K = nbf * block transitions) wants more splits
+  int64_t mp2_target = 32768;
   // batched grouped products: 0 = one workgroup per tile, n > 0 = a
   // persistent grid of n workgroups per compute unit walking tile ranges
   int64_t persistent = 0;

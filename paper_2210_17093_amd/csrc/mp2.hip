@@ -71,7 +71,9 @@ int stage_mp2(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double
       CHECK(launch_check(c, "k_mp2_rhs_vir"));
     }
     {  // G = D Rh^T over k = (p, tb), split over k; V (+)= 1/2 (G + G^T)
-      const SplitPlan sp = sigma_split(c->tiles, nbf, ntb);
+      const SplitPlan sp = split_plan(
+          nbf * ntb, splits_for(tiles_of(c->tiles.shape[TU_SIGMA], nbf, nbf), nbf * ntb,
+                                c->tiles.mp2_target));
       double* part = nullptr;
       CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nn), &part));
       Strided<true> A{D, nbf * ntb, 1, 0, nbf};

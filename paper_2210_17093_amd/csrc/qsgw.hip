@@ -1367,6 +1367,7 @@ int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {
       int64_t* target = key == "sigma_target" ? &t.sigma_target
                         : key == "rho_target" ? &t.rho_target
                         : key == "exchange_target" ? &t.exchange_target
+                        : key == "mp2_target"      ? &t.mp2_target
                                                     : nullptr;
       if (!target) return fail(c, QSGW_ERR_INVALID_ARG, "tiles: unknown key '%s'", key.c_str());
       if (!e || *e || v < 64 || v > (1 << 20))
@@ -1394,6 +1395,7 @@ int qsgw_get_tiles(qsgw_ctx* c, char* buf, int64_t size) {
   out += ",rho_target=" + std::to_string(c->tiles.rho_target);
   out += ",exchange_target=" + std::to_string(c->tiles.exchange_target);
   out += ",persistent=" + std::to_string(c->tiles.persistent);
+  out += ",mp2_target=" + std::to_string(c->tiles.mp2_target);
   if ((int64_t)out.size() + 1 > size) return fail(c, QSGW_ERR_INVALID_ARG, "buffer too small");
   memcpy(buf, out.c_str(), out.size() + 1);
   return QSGW_OK;
