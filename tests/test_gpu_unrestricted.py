@@ -145,3 +145,29 @@ def test_unrestricted_step_equal_spins_is_iterate(q, ctx):
     q.qsgw_fock_unrestricted(ctx, B_mo, B_mo, h, Va, Vb, 6, 6, ea, eb, Ca, Cb)
     np.testing.assert_allclose(host(ea), host(e_it), rtol=0, atol=1e-10)
     np.testing.assert_array_equal(host(ea), host(eb))
+
+
+def test_unrestricted_full_size_equal_spins(q, ctx):
+    """N_b = 300, N_aux = 1200, 40 + 40 electrons on the workload's orbitals:
+    20,800 transitions, so the residues run in two excitation blocks as in the
+    benchmark's doublet.  Equal spins must give the restricted chain's V for
+    both spins and Omega = singlets plus triplets at Delta."""
+    from qsgw_inputs import make_config
+    p = make_config("cfg2")
+    eta = 0.05
+    print("[uhf] full size, equal spins", flush=True)
+    B_mo = q.qsgw_mo_transform(ctx, dev(p.B_ao), dev(p.C0))
+    e = dev(p.eps0)
+    M, sq = q.qsgw_rpa_build(ctx, B_mo, e, p.nocc)
+    Z, Om_r = q.qsgw_rpa_solve(ctx, M)
+    w, wh = q.qsgw_residues(ctx, B_mo, sq, Z, Om_r, p.nocc, weighted=True, eps=e, eta=eta)
+    Vr = host(q.qsgw_sigma_qs(ctx, w, e, Om_r, p.nocc, eta, wh=wh))
+    om_r = host(Om_r)
+    del M, Z, w, wh
+    torch.cuda.empty_cache()
+    Va, Vb, Om = q.qsgw_gw_unrestricted(ctx, B_mo, B_mo, e, e, p.nocc, p.nocc, eta)
+    Va, Vb = host(Va), host(Vb)
+    np.testing.assert_array_equal(Va, Vb)
+    assert np.abs(Va - Vr).max() <= 1e-9 * np.abs(Vr).max()
+    both = np.sort(np.concatenate([om_r, O.transition_energies(p.eps0, p.nocc)]))
+    np.testing.assert_allclose(host(Om), both, rtol=1e-10)
