@@ -244,19 +244,40 @@ __global__ void k_axpby(const double* a, const double* b, double alpha, double b
   out[idx] = alpha * a[idx] + beta * b[idx];
 }
 
+// One workgroup (256 threads) per column j: the first row of largest |C[r][j]|
+// decides the sign (larger magnitude wins, ties go to the smaller row).
 __global__ void k_fix_column_signs(double* C, int64_t n) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sm[256];
+  __shared__ int64_t sr[256];
+  const int64_t j = blockIdx.x;
   if (j >= n) return;
-  double best = -1.0, val = 1.0;
-  for (int64_t r = 0; r < n; ++r) {
-    const double x = C[r * n + j];
-    if (fabs(x) > best) {
-      best = fabs(x);
-      val = x;
+  double best = -1.0;
+  int64_t br = n;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const double a = fabs(C[r * n + j]);
+    if (a > best) {  // rows ascend per thread: the first maximum is kept
+      best = a;
+      br = r;
     }
   }
-  if (val < 0.0)
-    for (int64_t r = 0; r < n; ++r) C[r * n + j] = -C[r * n + j];
+  sm[threadIdx.x] = best;
+  sr[threadIdx.x] = br;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double o = sm[threadIdx.x + w];
+      const int64_t orow = sr[threadIdx.x + w];
+      if (o > sm[threadIdx.x] || (o == sm[threadIdx.x] && orow < sr[threadIdx.x])) {
+        sm[threadIdx.x] = o;
+        sr[threadIdx.x] = orow;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = sr[0] < n && C[sr[0] * n + j] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) C[r * n + j] = -C[r * n + j];
 }
 
 __global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, double* out) {

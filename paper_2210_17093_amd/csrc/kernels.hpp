@@ -481,6 +481,7 @@ __global__ void k_symmetrize(const double* a, int64_t n, double* out);
 __global__ void k_axpby(const double* a, const double* b, double alpha, double beta, int64_t len,
                         double* out);
 // Sign convention of eigenvector columns: the largest-|.| entry is positive.
+// Sign convention of eigenvector columns; launch one 256-thread workgroup per column.
 __global__ void k_fix_column_signs(double* C, int64_t n);
 // max_m |a_m - b_m| (one workgroup), and a finiteness flag.
 __global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, double* out);

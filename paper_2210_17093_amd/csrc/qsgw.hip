@@ -1078,7 +1078,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       EpiStore E{Cn, nbf, 0, 0, 1.0};
       CHECK((gemm<64, 64, false>(c, "rotate_orbitals", A, B, E, nbf, nbf, nbf, 1)));
     }
-    hipLaunchKernelGGL(k_fix_column_signs, dim3(blocks_for(nbf)), dim3(256), 0, c->stream, Cn, nbf);
+    hipLaunchKernelGGL(k_fix_column_signs, dim3((unsigned)nbf), dim3(256), 0, c->stream, Cn, nbf);
     hipLaunchKernelGGL(k_max_abs_diff, dim3(1), dim3(256), 0, c->stream, epsn, st->eps, nbf, scal);
     CHECK(launch_check(c, "k_max_abs_diff"));
     HIP_TRY(c, hipMemcpyAsync(st->eps, epsn, nbf * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1315,7 +1315,7 @@ int qsgw_fock_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_
       EpiStore E{Cn, nbf, 0, 0, 1.0};
       CHECK((gemm<64, 64, false>(c, "fock_u/rotate", A, B, E, nbf, nbf, nbf, 1)));
     }
-    hipLaunchKernelGGL(k_fix_column_signs, dim3(blocks_for(nbf)), dim3(256), 0, c->stream, Cn, nbf);
+    hipLaunchKernelGGL(k_fix_column_signs, dim3((unsigned)nbf), dim3(256), 0, c->stream, Cn, nbf);
     CHECK(launch_check(c, "k_fix_column_signs"));
     HIP_TRY(c, hipMemcpyAsync(es[sp], epsn, nbf * sizeof(double), hipMemcpyDeviceToDevice,
                               c->stream));
