@@ -38,7 +38,7 @@ CANDIDATES = {
     "rho": (["128x128", "128x64", "64x64"], ["residue_rho"]),
     "rho_target": ([2048, 1024, 4096], ["residue_rho"]),
     "sigma": (["64x64", "128x64", "128x128"], ["sigma_qs_gemm", "sigma_qs_reduce"]),
-    "sigma_target": ([4096, 2048, 8192], ["sigma_qs_gemm", "sigma_qs_reduce"]),
+    "sigma_target": ([4096, 2048, 8192, 16384, 32768], ["sigma_qs_gemm", "sigma_qs_reduce"]),
     "exchange": (["64x64", "128x128"], ["fock"]),
     "persistent": ([0, 2, 4], ["mo_transform_1", "mo_transform_2", "casida", "residue_rho",
                                "residue_w", "sigma_qs_gemm", "fock"]),
