@@ -1,7 +1,13 @@
-"""Plain FP64 NumPy reference of the warm-start network (16 -> 128 -> 128 -> 1,
+"""Plain FP64 NumPy oracle of the warm-start network (16 -> 128 -> 128 -> 1,
 exact GELU), its mean-squared-error gradient and one Adam step, written from
-the textbook definitions.  Test infrastructure: pinned by finite differences
-in tests/test_mlp_ref.py, used to check the HIP kernels."""
+the textbook definitions (GELU as z * Phi(z) with Phi the normal CDF; Adam with
+bias-corrected first and second moments).
+
+TEST INFRASTRUCTURE, like the rest of this package: only the tests may import
+it.  Pinned on the CPU by central finite differences of the loss (every
+parameter block), the GELU limits and derivative, and the first Adam step.
+The trained network's values are parity unpinned: their quality is judged by
+the plain qsGW iteration they warm-start."""
 import math
 
 import numpy as np

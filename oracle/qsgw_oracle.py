@@ -157,13 +157,6 @@ def sigma_element(w: np.ndarray, eps: np.ndarray, Omega: np.ndarray, nocc: int,
     return out
 
 
-def sigma_row(w: np.ndarray, eps: np.ndarray, Omega: np.ndarray, nocc: int,
-              eta: float, m: int, omega: float) -> np.ndarray:
-    """Eq. (17) for row m at one frequency: Sigma_{mn}(omega) for all n (complex)."""
-    inv_d = 1.0 / _pole_denominators(omega, eps, Omega, nocc, eta)
-    return np.tensordot(w, w[m] * inv_d, axes=([1, 2], [0, 1]))
-
-
 # ---------------------------------------------------------------- O6 ------
 def sigma_qs(w: np.ndarray, eps: np.ndarray, Omega: np.ndarray, nocc: int,
              eta: float) -> np.ndarray:
@@ -278,12 +271,15 @@ def qsgw_iterate(B_ao, h, C0, eps0, nocc, eta, tol, max_iter, mix=1.0,
 
 # ------------------------------------------------- per-state features -----
 def exchange_diagonal_mo(B_mo: np.ndarray, nocc: int) -> np.ndarray:
-    """Sigma_x,mm = -sum_{i occ} (mi|im) = -sum_i sum_P (B^P_{mi})^2."""
+    """Diagonal of the exchange operator of Eq. (10) in the MO basis, closed
+    shell: Sigma_x,mm = -(C^T K[D] C)_mm = -sum_{i occ} (mi|im)
+    = -sum_i sum_P (B^P_{mi})^2."""
     return -np.einsum("pmi,pmi->m", B_mo[:, :, :nocc], B_mo[:, :, :nocc])
 
 
 def sigma_diag_derivative(w, eps, Omega, nocc, eta, m, omega) -> complex:
-    """d Sigma_mm / d omega of Eq. (17): -sum_{k s} w_mks^2 / d_ks^2."""
+    """d Sigma_mm / d omega of Eq. (17): omega enters every denominator d_ks
+    with coefficient 1, so the derivative is -sum_{k s} w_mks^2 / d_ks^2."""
     d = _pole_denominators(omega, eps, Omega, nocc, eta)
     return complex(-np.sum(w[m] ** 2 / d ** 2))
 

@@ -36,6 +36,19 @@ def one_transition_closed_form(eps0, eps1, b, B00, B11, eta, omegas):
     return Omega, w, sig
 
 
+def one_transition_sigma_derivative(eps0, eps1, b, B00, B11, eta, omegas):
+    """d Sigma_mm / d omega of the one-transition closed form above, term by
+    term: d/dw [c / (w - e + Om - i eta)] = -c / (w - e + Om - i eta)^2 and the
+    same for the virtual pole.  Returns [2][len(omegas)] complex."""
+    Omega, w, _ = one_transition_closed_form(eps0, eps1, b, B00, B11, eta, [0.0])
+    omegas = np.asarray(omegas, dtype=np.complex128)
+    out = np.zeros((2, omegas.size), dtype=np.complex128)
+    for m in range(2):
+        out[m] = (-w[m, 0] ** 2 / (omegas - eps0 + Omega - 1j * eta) ** 2
+                  - w[m, 1] ** 2 / (omegas - eps1 - Omega + 1j * eta) ** 2)
+    return out
+
+
 # ------------------------------------------------------------ helpers ----
 def mo_eri(B_mo):
     n = B_mo.shape[1]

@@ -1,10 +1,10 @@
 """HIP kernels of the learned warm start against the NumPy reference
-(tests/mlp_ref.py, pinned by finite differences) and the feature and
+(oracle/mlp_oracle.py, pinned by finite differences) and the feature and
 warm-start definitions of include/qsgw.h."""
 import numpy as np
 import pytest
 
-import mlp_ref as R
+from oracle import mlp_oracle as R
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu

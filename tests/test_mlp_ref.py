@@ -4,7 +4,7 @@ import math
 
 import numpy as np
 
-import mlp_ref as R
+from oracle import mlp_oracle as R
 
 
 def test_parameter_count():

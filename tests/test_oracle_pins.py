@@ -203,9 +203,6 @@ def test_sigma_real_symmetric_and_cfg1_grid():
     assert grid.size == 201 and grid[0] == -2.0 and abs(grid[-1] - 2.0) < 1e-15
     homo = p.nocc - 1
     sig = O.sigma_element(w, p.eps0, Om, p.nocc, 1e-3, homo, homo, grid)
-    # Sigma(omega) at the grid equals the row form at each omega
-    row = O.sigma_row(w, p.eps0, Om, p.nocc, 1e-3, homo, grid[37])
-    assert abs(row[homo] - sig[37]) < 1e-12 * abs(sig[37])
     # Sigma(conj z) = conj Sigma(z) with eta -> 0 (real residues)
     z = 0.1 + 0.4j
     a = O.sigma_element(w, p.eps0, Om, p.nocc, 0.0, homo, homo + 1, [z, np.conj(z)])
@@ -224,6 +221,74 @@ def test_iterate_records_and_mixing():
     # linear mixing reaches the same fixed point
     eps2, _, _ = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, 1e-2, 1e-11, 200, mix=0.6)
     np.testing.assert_allclose(eps2, eps, atol=1e-9)
+
+
+# ------------------------------------------- P19, P20: per-state features --
+@pytest.mark.parametrize("eta", [1e-2, 1e-3])
+def test_p19_sigma_derivative_is_finite_difference_of_eq17(eta):
+    """d Sigma_mm / d omega against a central difference of Eq. (17) itself
+    (sigma_element), at several states and frequencies between the poles."""
+    p = make_config("cfg1")
+    B_mo, M, sq, Om, XpY, w = chain(p)
+    for m in (0, p.nocc - 2, p.nocc - 1, p.nocc, p.nocc + 3, p.nbf - 1):
+        for om in (p.eps0[m], p.eps0[m] + 0.013, -0.71):
+            der = O.sigma_diag_derivative(w, p.eps0, Om, p.nocc, eta, m, om)
+            # Richardson-extrapolated central difference, step << eta
+            h = eta * 1e-3
+            d1 = (O.sigma_element(w, p.eps0, Om, p.nocc, eta, m, m, [om + h, om - h]))
+            d2 = (O.sigma_element(w, p.eps0, Om, p.nocc, eta, m, m, [om + 2 * h, om - 2 * h]))
+            f1 = (d1[0] - d1[1]) / (2 * h)
+            f2 = (d2[0] - d2[1]) / (4 * h)
+            fd = (4 * f1 - f2) / 3
+            assert abs(der - fd) <= 1e-6 * abs(fd) + 1e-9, (m, om, der, fd)
+
+
+@pytest.mark.parametrize("b,B00,B11", [(0.3, 0.7, -0.2), (1.1, 0.0, 0.4)])
+def test_p19_sigma_derivative_two_level_closed_form(b, B00, B11):
+    """The one-transition case: the derivative of the closed-form Sigma_mm(omega)."""
+    eps = np.array([-0.8, 0.45])
+    B_mo = np.array([[[B00, b], [b, B11]]])
+    M, sq = O.rpa_hermitian(B_mo, eps, 1)
+    Om, XpY = O.rpa_solve(M, sq)
+    w = O.residues(B_mo, XpY, 1)
+    grid = [-1.3, -0.8, 0.0, 0.45, 1.7]
+    for eta in (1e-2, 1e-3):
+        ref = pins.one_transition_sigma_derivative(eps[0], eps[1], b, B00, B11, eta, grid)
+        for m in range(2):
+            der = np.array([O.sigma_diag_derivative(w, eps, Om, 1, eta, m, x) for x in grid])
+            np.testing.assert_allclose(der, ref[m], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("nbf,naux,nocc,seed", [(6, 14, 2, 3), (7, 9, 3, 5), (5, 20, 1, 8)])
+def test_p20_exchange_diagonal_is_four_index_exchange(nbf, naux, nocc, seed):
+    """Sigma_x,mm against -(C^T K[D] C)_mm with K[D] of Eq. (10) built from
+    explicit four-index integrals (mu nu|lambda tau) = sum_P B B."""
+    p = tiny(nbf=nbf, naux=naux, nocc=nocc, seed=seed)
+    # a general orthogonal C, not the generator's, so occupied columns mix
+    C = np.linalg.qr(np.random.default_rng(seed + 100).standard_normal((nbf, nbf)))[0]
+    D = C[:, :nocc] @ C[:, :nocc].T
+    _, K = pins.jk_four_index(p.B_ao, D)
+    ref = -np.diag(C.T @ K @ C)
+    got = O.exchange_diagonal_mo(O.mo_transform(p.B_ao, C), nocc)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_mutant_sigma_derivative_sign_caught(monkeypatch):
+    """A sign slip in d Sigma / d omega fails the finite-difference pin."""
+    orig = O.sigma_diag_derivative
+    monkeypatch.setattr(O, "sigma_diag_derivative", lambda *a: -orig(*a))
+    with pytest.raises(AssertionError):
+        test_p19_sigma_derivative_is_finite_difference_of_eq17(1e-2)
+
+
+def test_mutant_exchange_diagonal_over_virtuals_caught(monkeypatch):
+    """Summing the exchange diagonal over virtual instead of occupied states
+    fails the four-index pin."""
+    def over_virtuals(B_mo, nocc):
+        return -np.einsum("pmi,pmi->m", B_mo[:, :, nocc:], B_mo[:, :, nocc:])
+    monkeypatch.setattr(O, "exchange_diagonal_mo", over_virtuals)
+    with pytest.raises(AssertionError):
+        test_p20_exchange_diagonal_is_four_index_exchange(6, 14, 2, 3)
 
 
 # ------------------------------------------------------------- mutations --
