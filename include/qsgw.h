@@ -32,6 +32,11 @@
  *     hipMalloc, released by qsgw_ctx_destroy).
  *   - Return value: QSGW_OK, QSGW_NOT_CONVERGED (results valid), or a
  *     negative error; qsgw_last_error() returns a message for the context.
+ *   - Every entry point that reads floating-point input arrays checks them
+ *     for NaN and infinity on the device (one pass over each input, then one
+ *     read-back, so the call synchronizes its stream once before its work
+ *     is queued) and returns QSGW_ERR_NONFINITE naming the array; nothing
+ *     else runs then.
  *   - One context per host thread.  Calls on one context must not overlap.
  */
 #ifndef QSGW_H
@@ -72,8 +77,14 @@ extern "C" {
 #define QSGW_SIGMA_DIAG_GRID 1
 #define QSGW_SIGMA_DIAG_SELF 2
 
-/* Fock update modes of qsgw_iterate. */
+/* Fock update modes of qsgw_iterate, Eq. (6). */
 #define QSGW_FOCK_FULL_JK 0 /* F = h + J[D] - K[D] + Vc, D from the current orbitals */
+/* F = h + Vc: the mean field is frozen.  h is then the whole frozen mean-field
+ * Hamiltonian F0 = T + V_ext + J[D0] - K[D0] of a reference density D0 (for
+ * example the Hartree-Fock Fock matrix of the start); J and K are not rebuilt.
+ * From a start whose density is D0 the first iteration equals that of
+ * QSGW_FOCK_FULL_JK with the matching one-body h. */
+#define QSGW_FOCK_FROZEN 1
 
 #define QSGW_REPORT_MAX_ITERS 64
 
@@ -323,6 +334,10 @@ typedef struct {
   double near_pole; /* reduced precisions, qsgw_iterate: terms of the qsGW product (Eq. 19)
                        with |eps_m - eps_k +- Omega_s| below this (Ha) are summed in FP64, the
                        rest on FP32 (or split-BF16) matrix cores; 0 = 0.05 Ha */
+  const float* warm_start; /* qsgw_iterate only: NULL, or device [nbf] FP32 predicted shifts
+                       delta_m (the learned warm start); the call first replaces the state's
+                       (eps, C) by the warm start of qsgw_warm_start built from them, then
+                       iterates.  qsgw_iterate_batched requires NULL. */
 } qsgw_options;
 
 /* qsgw_options.flags, qsgw_iterate_batched only: run the kernel segments
@@ -340,6 +355,15 @@ typedef struct {
  * Needs precision QSGW_PREC_FP64 and state.diag NULL (QSGW_ERR_UNSUPPORTED
  * otherwise); its time is reported as the sigma stage. */
 #define QSGW_OPT_QSMP2 4
+/* qsgw_options.flags, qsgw_iterate only, for timing the hot path apart from
+ * the Casida eigensolve: each iteration still builds its Casida matrix (into
+ * a separate buffer) but, instead of solving it, takes the eigenpairs the
+ * context kept from its last solved Casida matrix.  The library checks that
+ * the new matrix is bitwise the solved one (an order-independent fingerprint
+ * of its bit patterns) and returns QSGW_ERR_INVALID_ARG otherwise, so the
+ * results are those of a full iteration.  The eig_rpa stage then reports
+ * 0 ms.  Not combinable with QSGW_OPT_QSMP2. */
+#define QSGW_OPT_REPLAY_EIG 8
 
 typedef struct {
   int64_t iterations; /* iterations done in this call */

@@ -201,8 +201,16 @@ def hf_core(B_ao: np.ndarray, C0: np.ndarray, eps0: np.ndarray, nocc: int) -> np
 
 
 def fock(h: np.ndarray, B_ao: np.ndarray, C: np.ndarray, nocc: int,
-         V: np.ndarray) -> np.ndarray:
-    """Eq. (6): H = h + J - K + Sigma_c, with Sigma_c in the AO basis = C V C^T."""
+         V: np.ndarray, fock_mode: str = "full") -> np.ndarray:
+    """Eq. (6): H = h + J - K + Sigma_c, with Sigma_c in the AO basis = C V C^T.
+
+    fock_mode "frozen" keeps the mean field of a reference density fixed: h is
+    then the whole frozen mean-field matrix F0 = T + V_ext + J[D0] - K[D0] and
+    H = F0 + C V C^T (J and K are not rebuilt)."""
+    if fock_mode == "frozen":
+        return h + C @ V @ C.T
+    if fock_mode != "full":
+        raise ValueError(f"unknown fock_mode {fock_mode!r}")
     D = density(C, nocc)
     return h + hartree(B_ao, D) - exchange(B_ao, D) + C @ V @ C.T
 
@@ -218,25 +226,27 @@ def diagonalize(F: np.ndarray):
 
 
 # ---------------------------------------------------------------- O1-O8 ---
-def qsgw_step(B_ao, h, C, eps, nocc, eta):
-    """One qsGW iteration from (eps, C).  Returns a dict of every intermediate."""
+def qsgw_step(B_ao, h, C, eps, nocc, eta, fock_mode="full"):
+    """One qsGW iteration from (eps, C).  Returns a dict of every intermediate.
+    fock_mode as in ``fock``."""
     B_mo = mo_transform(B_ao, C)
     M, sqrt_delta = rpa_hermitian(B_mo, eps, nocc)
     Omega, XpY = rpa_solve(M, sqrt_delta)
     w = residues(B_mo, XpY, nocc)
     V = sigma_qs(w, eps, Omega, nocc, eta)
-    F = fock(h, B_ao, C, nocc, V)
+    F = fock(h, B_ao, C, nocc, V, fock_mode)
     eps_new, C_new = diagonalize(F)
     return dict(B_mo=B_mo, M=M, sqrt_delta=sqrt_delta, Omega=Omega, XpY=XpY,
                 w=w, V=V, F=F, eps=eps_new, C=C_new)
 
 
 def qsgw_iterate(B_ao, h, C0, eps0, nocc, eta, tol, max_iter, mix=1.0,
-                 keep=("eps", "Omega")):
+                 keep=("eps", "Omega"), fock_mode="full"):
     """Repeat the qsGW step until max|eps' - eps| < tol or max_iter.
 
     With mix < 1 the AO-basis correlation potential is mixed linearly with the
     previous one: Sigma_ao <- mix * Sigma_ao + (1 - mix) * Sigma_ao_prev.
+    fock_mode "frozen": h is the frozen mean-field matrix F0 (see ``fock``).
     Returns (eps, C, history) where history[j] holds the ``keep`` entries and
     max|d eps| of iteration j + 1.
     """
@@ -253,8 +263,11 @@ def qsgw_iterate(B_ao, h, C0, eps0, nocc, eta, tol, max_iter, mix=1.0,
         if Vao_prev is not None and mix != 1.0:
             Vao = mix * Vao + (1.0 - mix) * Vao_prev
         Vao_prev = Vao
-        D = density(C, nocc)
-        F = h + hartree(B_ao, D) - exchange(B_ao, D) + Vao
+        if fock_mode == "frozen":
+            F = h + Vao
+        else:
+            D = density(C, nocc)
+            F = h + hartree(B_ao, D) - exchange(B_ao, D) + Vao
         eps_new, C_new = diagonalize(F)
         d = float(np.max(np.abs(eps_new - eps)))
         rec = {"max_deps": d}

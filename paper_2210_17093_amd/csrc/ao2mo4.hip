@@ -20,6 +20,7 @@ int qsgw_ao2mo_4center(qsgw_ctx* c, int64_t nbf, const double* eri_ao, const dou
     return fail(c, QSGW_ERR_UNSUPPORTED, "qsgw_ao2mo_4center: FP64 only (precision %d)", precision);
   const int64_t n = nbf, n2 = n * n, n3 = n2 * n;
   if (n > 2000) return fail(c, QSGW_ERR_INVALID_ARG, "nbf too large for the four-index tensor");
+  CHECK(check_finite(c, "qsgw_ao2mo_4center", {fin(eri_ao, n3 * n, "eri_ao"), fin(C, n2, "C")}));
   double* T = nullptr;
   CHECK(ws_get(c, W_AO2MO, (size_t)(m_count * n3), &T));
   CHECK(single_begin(c, kStageMo));

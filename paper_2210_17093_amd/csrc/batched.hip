@@ -579,6 +579,10 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     return fail(c, QSGW_ERR_UNSUPPORTED, "the batched iteration keeps every excitation resident");
   if (o->fock_mode != QSGW_FOCK_FULL_JK)
     return fail(c, QSGW_ERR_UNSUPPORTED, "fock_mode %d is not available", o->fock_mode);
+  if (o->warm_start)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "warm_start: apply qsgw_warm_start to each molecule");
+  if (o->flags & ~(int64_t)QSGW_OPT_GRAPH)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "flags other than QSGW_OPT_GRAPH");
   const bool fp32 = o->precision == QSGW_PREC_FP32;
 
   // ------------------------------------------------------------ layout --
@@ -629,6 +633,34 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
       for (int64_t kb = 0; kb < nkb; ++kb)
         if (8 * mb <= 16 * kb + 15) tables[i].push_back((int32_t)((mb << 16) | kb));
     ni += tables[i].size();
+  }
+  {
+    // finite inputs of every molecule: one pass each, one read-back
+    int* flags = nullptr;
+    CHECK(ws_get(c, W_FLAGS, 8, &flags));
+    HIP_TRY(c, hipMemsetAsync(flags + 5, 0, sizeof(int), c->stream));
+    for (int64_t i = 0; i < nmol; ++i) {
+      const Mol& m = P.mols[i];
+      const double* arr[4] = {m.B_ao, m.h, m.C, m.eps};
+      const int64_t len[4] = {m.naux * m.nn, m.nn, m.nn, m.nbf};
+      for (int k = 0; k < 4; ++k) {
+        const int64_t nb = (len[k] + 255) / 256;
+        hipLaunchKernelGGL(k_check_finite, dim3((unsigned)(nb < 512 ? nb : 512)), dim3(256), 0,
+                           c->stream, arr[k], len[k], flags + 5, 1 << k);
+      }
+    }
+    CHECK(launch_check(c, "k_check_finite"));
+    int bad = 0;
+    CHECK(read_flag(c, flags + 5, &bad));
+    if (bad) {
+      for (int64_t i = 0; i < nmol; ++i) {
+        const Mol& m = P.mols[i];
+        char what[64];
+        snprintf(what, sizeof(what), "qsgw_iterate_batched, molecule %lld", (long long)i);
+        CHECK(check_finite(c, what, {fin(m.B_ao, m.naux * m.nn, "B_ao"), fin(m.h, m.nn, "h"),
+                                     fin(m.C, m.nn, "C"), fin(m.eps, m.nbf, "eps")}));
+      }
+    }
   }
   for (auto& kv : bucketM) nd += kv.second.size() * (kv.first * kv.first + 2 * kv.first);
   for (auto& kv : bucketF) nd += kv.second.size() * (kv.first * kv.first + 2 * kv.first);

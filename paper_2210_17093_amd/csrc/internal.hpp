@@ -12,6 +12,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -76,6 +77,8 @@ enum Slot {
   W_MP2_R,       // qsMP2: pole-weighted right operand            [nbf][nbf][block]
   W_MP2_E,       // qsMP2, several blocks: (ni|pa), i occupied    [nocc][nbf][ntr]
   W_AO2MO,       // four-index AO->MO: quarter-transformed slab   [m_count][nbf][nbf][nbf]
+  W_M2,          // replayed iteration: Casida matrix, checked against the solved one [ntr][ntr]
+  W_FPRINT,      // bit fingerprints of Casida matrices           [2] u64
   W_NSLOTS
 };
 
@@ -125,6 +128,11 @@ struct qsgw_ctx {
   rocblas_handle aux_blas[kAux] = {};
   hipEvent_t fork = nullptr, join[kAux] = {};
   bool aux_ready = false;
+  // The last Casida matrix qsgw_iterate solved: its size (-1: none kept) and
+  // bit fingerprint; W_M then holds its eigenvectors and W_OMEGA its
+  // excitation energies (QSGW_OPT_REPLAY_EIG reads them).
+  int64_t eig_ntr = -1;
+  unsigned long long eig_fp = 0;
 };
 
 // qsMP2 potential of Eqs. (20)-(21) in the MO basis (mp2.hip), for the
@@ -287,6 +295,23 @@ inline int64_t sigma_slices(const Tiles& tl, int64_t nbf, int64_t ns, bool fp32,
   if (!fp32) return sigma_split(tl, nbf, ns).nz;
   if (x3) return sigma_split32(tl, nbf, x3_kfar(nbf, ns)).nz + x3_near_slices(nbf);
   return sigma_split32(tl, nbf, nbf * ns).nz + near_slices_max(nbf);
+}
+
+// qsMP2 potential: occupied states per block of transitions (occ_block 0:
+// the largest block whose two [nbf][nbf][block transitions] FP64 work arrays
+// fit in 16 GiB) and the K-split of its contraction (K = nbf * block transitions).
+inline int64_t mp2_block(int64_t nbf, int64_t nocc, int64_t occ_block) {
+  constexpr double kMp2BlockBytes = 16.0 * 1024 * 1024 * 1024;
+  int64_t ib = occ_block;
+  if (ib <= 0) {
+    ib = (int64_t)(kMp2BlockBytes / (2.0 * 8.0 * (double)(nbf * nbf) * (double)(nbf - nocc)));
+    if (ib < 1) ib = 1;
+  }
+  return ib > nocc ? nocc : ib;
+}
+inline SplitPlan mp2_split(const Tiles& tl, int64_t nbf, int64_t ntb) {
+  return split_plan(nbf * ntb, splits_for(tiles_of(tl.shape[TU_SIGMA], nbf, nbf), nbf * ntb,
+                                          tl.mp2_target));
 }
 
 // rho product: tiles of the naux x ns output, K = ntr; split only when the
@@ -457,6 +482,49 @@ inline int reduce_sym(qsgw_ctx* c, const double* part, int64_t nz, int64_t n, do
   hipLaunchKernelGGL(k_reduce_sym, dim3(blocks_for(nn)), dim3(256), 0, c->stream, part, nz, n, V,
                      accumulate);
   return launch_check(c, "k_reduce_sym");
+}
+
+// Finite-input check of an entry point: one pass over each input array on
+// the device (a NaN or infinity sets that array's bit), then one read-back.
+struct FiniteArg {
+  const void* p;
+  int64_t n;
+  const char* name;
+  bool f32;
+};
+inline FiniteArg fin(const double* p, int64_t n, const char* name) { return {p, n, name, false}; }
+inline FiniteArg fin32(const float* p, int64_t n, const char* name) { return {p, n, name, true}; }
+
+inline int check_finite(qsgw_ctx* c, const char* what, std::initializer_list<FiniteArg> args) {
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  int* bad = flags + 5;
+  HIP_TRY(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream));
+  int bit = 0;
+  for (const FiniteArg& a : args) {
+    if (a.p && a.n > 0) {
+      int64_t nb = (a.n + 255) / 256;
+      const unsigned grid = (unsigned)(nb < 2048 ? nb : 2048);
+      if (a.f32)
+        hipLaunchKernelGGL(k_check_finite_f32, dim3(grid), dim3(256), 0, c->stream,
+                           static_cast<const float*>(a.p), a.n, bad, 1 << bit);
+      else
+        hipLaunchKernelGGL(k_check_finite, dim3(grid), dim3(256), 0, c->stream,
+                           static_cast<const double*>(a.p), a.n, bad, 1 << bit);
+    }
+    ++bit;
+  }
+  CHECK(launch_check(c, "k_check_finite"));
+  int mask = 0;
+  CHECK(read_flag(c, bad, &mask));
+  if (mask) {
+    int i = 0;
+    for (const FiniteArg& a : args) {
+      if (mask & (1 << i)) return fail(c, QSGW_ERR_NONFINITE, "%s: non-finite value in %s", what, a.name);
+      ++i;
+    }
+  }
+  return QSGW_OK;
 }
 
 inline int check_common(qsgw_ctx* c, int64_t nbf, int64_t naux) {

@@ -300,12 +300,40 @@ __global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, doub
   }
 }
 
-__global__ void k_check_finite(const double* x, int64_t len, int* bad) {
+template <class T>
+__device__ __forceinline__ void check_finite_body(const T* x, int64_t len, int* bad, int mask) {
   bool ok = true;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * blockDim.x)
-    ok = ok && finite(x[i]);
-  if (!ok) atomicOr(bad, 1);
+    ok = ok && isfinite(x[i]);
+  if (!ok) atomicOr(bad, mask);
+}
+__global__ void k_check_finite(const double* x, int64_t len, int* bad, int mask) {
+  check_finite_body(x, len, bad, mask);
+}
+__global__ void k_check_finite_f32(const float* x, int64_t len, int* bad, int mask) {
+  check_finite_body(x, len, bad, mask);
+}
+
+// Order-independent fingerprint of an array's bit patterns:
+// sum_i bits(x_i) * (2 i + 1) mod 2^64.  Integer sums wrap and commute, so
+// the result does not depend on the reduction order.
+__global__ void k_bits_fingerprint(const double* x, int64_t len, unsigned long long* out) {
+  unsigned long long acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += (unsigned long long)__double_as_longlong(x[i]) * (unsigned long long)(2 * i + 1);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+// Fock matrix with a frozen mean field, MO basis: F = (hmo + hmo^T) / 2 + V.
+__global__ void k_fock_frozen(const double* hmo, const double* V, int64_t n, double* F) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t m = idx / n;
+  const int64_t c = idx - m * n;
+  F[idx] = 0.5 * (hmo[m * n + c] + hmo[c * n + m]) + V[idx];
 }
 
 // One workgroup per (state, block of OT frequencies).  Threads stride over the

@@ -486,7 +486,10 @@ __global__ void k_fix_column_signs(double* C, int64_t n);
 // max_m |a_m - b_m| (one workgroup), and a finiteness flag.
 __global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, double* out);
 // Non-finite scan: flags any NaN/Inf in x[0..len).
-__global__ void k_check_finite(const double* x, int64_t len, int* bad);
+__global__ void k_check_finite(const double* x, int64_t len, int* bad, int mask);
+__global__ void k_check_finite_f32(const float* x, int64_t len, int* bad, int mask);
+__global__ void k_bits_fingerprint(const double* x, int64_t len, unsigned long long* out);
+__global__ void k_fock_frozen(const double* hmo, const double* V, int64_t n, double* F);
 // Diagonal pole sum Sigma_mm(omega_l), Eq. (17), complex128 interleaved.
 __global__ void k_sigma_diag_grid(const double* w, const double* eps, const double* Omega,
                                   int64_t nbf, int64_t nocc, int64_t ns, double eta,

@@ -234,6 +234,8 @@ int qsgw_mlp_forward(qsgw_ctx* c, const float* params, int64_t n, const float* X
   if (!c) return QSGW_ERR_INVALID_ARG;
   CHECK(check_n(c, n));
   if (!params || !X || !y) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_mlp_forward",
+                     {fin32(params, kNParams, "params"), fin32(X, n * kIn, "X")}));
   MlpBuffers b;
   CHECK(mlp_buffers(c, n, 1, 1, &b));
   CHECK(mlp_hidden(c, params, n, X, b, false));
@@ -252,6 +254,10 @@ int qsgw_mlp_train_step(qsgw_ctx* c, float* params, float* adam_m, float* adam_v
     return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
   if (step < 1) return fail(c, QSGW_ERR_INVALID_ARG, "Adam steps count from 1");
   if (!(lr >= 0.0) || !isfinite(lr)) return fail(c, QSGW_ERR_INVALID_ARG, "need a finite lr >= 0");
+  CHECK(check_finite(c, "qsgw_mlp_train_step",
+                     {fin32(params, kNParams, "params"), fin32(adam_m, kNParams, "adam_m"),
+                      fin32(adam_v, kNParams, "adam_v"), fin32(X, n * kIn, "X"),
+                      fin32(target, n, "target")}));
   // weight gradients reduce over the batch: split K = n in chunks of 512
   const SplitPlan sp = split_plan(n, (n + 511) / 512);
   const int64_t R = 1024, ngroups = (n + R - 1) / R;
@@ -322,6 +328,9 @@ int qsgw_mlp_features(qsgw_ctx* c, int64_t nbf, int64_t nocc, const double* eps,
   if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
   if (!eps || !diag || !X || (!mean) != (!scale))
     return fail(c, QSGW_ERR_INVALID_ARG, "null pointer (mean and scale go together)");
+  CHECK(check_finite(c, "qsgw_mlp_features",
+                     {fin(eps, nbf, "eps"), fin(diag, 4 * nbf, "diag"), fin32(mean, kIn, "mean"),
+                      fin32(scale, kIn, "scale")}));
   hipLaunchKernelGGL(k_mlp_features, dim3(blocks_for(nbf)), dim3(256), 0, c->stream, nbf, nocc, eps,
                      diag, mean, scale, X);
   return launch_check(c, "k_mlp_features");
@@ -333,6 +342,8 @@ int qsgw_warm_start(qsgw_ctx* c, int64_t nbf, const double* eps0, const double* 
   if (nbf < 1 || nbf > 46340) return fail(c, QSGW_ERR_INVALID_ARG, "bad nbf");
   if (!eps0 || !C0 || !delta || !eps || !C) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
   if (eps == eps0 || C == C0) return fail(c, QSGW_ERR_INVALID_ARG, "outputs must not alias inputs");
+  CHECK(check_finite(c, "qsgw_warm_start", {fin(eps0, nbf, "eps0"), fin(C0, nbf * nbf, "C0"),
+                                            fin32(delta, nbf, "delta")}));
   int64_t* perm = nullptr;
   CHECK(ws_get(c, W_MLP_PERM, (size_t)nbf, &perm));
   hipLaunchKernelGGL(k_warm_rank, dim3(1), dim3(1024), 0, c->stream, nbf, eps0, delta, eps, perm);

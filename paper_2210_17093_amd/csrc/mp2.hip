@@ -14,18 +14,10 @@
 
 namespace {
 
-// Two [nbf][nbf][block] FP64 work arrays at most this large (automatic block).
-constexpr double kMp2BlockBytes = 16.0 * 1024 * 1024 * 1024;
-
 int stage_mp2(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
               const double* eps, double eta, double* V, int64_t occ_block, int accumulate) {
   const int64_t nv = nbf - nocc, ntr = nocc * nv, nn = nbf * nbf;
-  int64_t ib = occ_block;
-  if (ib <= 0) {
-    ib = (int64_t)(kMp2BlockBytes / (2.0 * 8.0 * (double)nn * (double)nv));
-    if (ib < 1) ib = 1;
-  }
-  if (ib > nocc) ib = nocc;
+  const int64_t ib = mp2_block(nbf, nocc, occ_block);
   const int64_t nblocks = (nocc + ib - 1) / ib;
   const int64_t ntb_max = ib * nv;
   if (nbf * ntb_max >= (int64_t)1 << 32)
@@ -71,9 +63,7 @@ int stage_mp2(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const double
       CHECK(launch_check(c, "k_mp2_rhs_vir"));
     }
     {  // G = D Rh^T over k = (p, tb), split over k; V (+)= 1/2 (G + G^T)
-      const SplitPlan sp = split_plan(
-          nbf * ntb, splits_for(tiles_of(c->tiles.shape[TU_SIGMA], nbf, nbf), nbf * ntb,
-                                c->tiles.mp2_target));
+      const SplitPlan sp = mp2_split(c->tiles, nbf, ntb);
       double* part = nullptr;
       CHECK(ws_get(c, W_PART, (size_t)(sp.nz * nn), &part));
       Strided<true> A{D, nbf * ntb, 1, 0, nbf};
@@ -108,6 +98,7 @@ int qsgw_mp2_sigma(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const d
     return fail(c, QSGW_ERR_UNSUPPORTED, "qsgw_mp2_sigma: FP64 only (precision %d)", precision);
   if (nocc * (nbf - nocc) > 0x7fffffffLL)
     return fail(c, QSGW_ERR_INVALID_ARG, "mp2: too many transitions");
+  CHECK(check_finite(c, "qsgw_mp2_sigma", {fin(B_mo, naux * nbf * nbf, "B_mo"), fin(eps, nbf, "eps")}));
   CHECK(single_begin(c, kStageSigma));
   CHECK(stage_mp2(c, nbf, naux, nocc, B_mo, eps, eta, V, occ_block, accumulate ? 1 : 0));
   return single_end(c);

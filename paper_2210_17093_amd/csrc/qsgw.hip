@@ -676,6 +676,7 @@ int qsgw_mo_transform(qsgw_ctx* c, int64_t nbf, int64_t naux, const double* B_ao
   CHECK(check_common(c, nbf, naux));
   CHECK(check_prec(c, precision));
   if (!B_ao || !C || !B_mo) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_mo_transform", {fin(B_ao, naux * nbf * nbf, "B_ao"), fin(C, nbf * nbf, "C")}));
   double* T = nullptr;
   CHECK(ws_get(c, W_T, (size_t)(naux * nbf * nbf), &T));
   CHECK(single_begin(c, kStageMo));
@@ -689,6 +690,7 @@ int qsgw_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const d
   CHECK(check_prec(c, precision));
   if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
   if (!B_mo || !eps || !M || !sqrt_delta) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_rpa_build", {fin(B_mo, naux * nbf * nbf, "B_mo"), fin(eps, nbf, "eps")}));
   const int64_t ntr = nocc * (nbf - nocc);
   double *delta = nullptr, *Bt = nullptr;
   int* flags = nullptr;
@@ -709,6 +711,7 @@ int qsgw_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const d
 int qsgw_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M_to_Z, double* Omega) {
   if (!c) return QSGW_ERR_INVALID_ARG;
   if (ntr < 1 || !M_to_Z || !Omega) return fail(c, QSGW_ERR_INVALID_ARG, "bad arguments");
+  CHECK(check_finite(c, "qsgw_rpa_solve", {fin(M_to_Z, ntr * ntr, "M")}));
   CHECK(single_begin(c, kStageEigRpa));
   CHECK(stage_rpa_solve(c, ntr, M_to_Z, Omega));
   return single_end(c);
@@ -729,6 +732,10 @@ int qsgw_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const do
     return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
   if (wh && (!eps || !(eta > 0.0) || !isfinite(eta)))
     return fail(c, QSGW_ERR_INVALID_ARG, "the pole-weighted copy needs eps and a finite eta > 0");
+  CHECK(check_finite(c, "qsgw_residues",
+                     {fin(B_mo, naux * nbf * nbf, "B_mo"), fin(sqrt_delta, ntr, "sqrt_delta"),
+                      fin(Z, ntr * ntr, "Z"), fin(Omega, ntr, "Omega"),
+                      fin(wh ? eps : nullptr, nbf, "eps")}));
   double *Bt = nullptr, *rho = nullptr;
   float* Bt32 = nullptr;
   CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
@@ -752,6 +759,11 @@ int qsgw_sigma(qsgw_ctx* c, int mode, int64_t nbf, int64_t nocc, int64_t ns, con
   if (ns < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need ns >= 1");
   if (!(eta > 0.0) || !isfinite(eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need finite eta > 0");
   if (!w || !eps || !Omega || !out) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_sigma",
+                     {fin(w, nbf * nbf * ns, "w"),
+                      fin(mode == QSGW_SIGMA_QS_MATRIX ? wh : nullptr, nbf * nbf * ns, "wh"),
+                      fin(eps, nbf, "eps"), fin(Omega, ns, "Omega"),
+                      fin(mode == QSGW_SIGMA_DIAG_GRID ? omega : nullptr, nomega, "omega")}));
   if (mode == QSGW_SIGMA_QS_MATRIX) {
     CHECK(single_begin(c, kStageSigma));
     CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega, eta, out, accumulate ? 1 : 0, nullptr,
@@ -800,6 +812,8 @@ int qsgw_hf_core(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const dou
   CHECK(check_common(c, nbf, naux));
   if (!(nocc > 0 && nocc < nbf)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc < nbf");
   if (!B_ao || !C0 || !eps0 || !h) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_hf_core", {fin(B_ao, naux * nbf * nbf, "B_ao"), fin(C0, nbf * nbf, "C0"),
+                                         fin(eps0, nbf, "eps0")}));
   const int64_t nn = nbf * nbf;
   double *T = nullptr, *Bmo = nullptr, *X = nullptr, *tmp = nullptr, *tmp2 = nullptr;
   CHECK(ws_get(c, W_T, (size_t)(naux * nn), &T));
@@ -838,8 +852,9 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   if (!(o->mix > 0.0 && o->mix <= 1.0)) return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < mix <= 1");
   if (o->mix != 1.0 && !st->Vc)
     return fail(c, QSGW_ERR_INVALID_ARG, "mixing needs a Vc buffer in the state");
-  if (o->fock_mode != QSGW_FOCK_FULL_JK)
-    return fail(c, QSGW_ERR_UNSUPPORTED, "fock_mode %d is not available", o->fock_mode);
+  if (o->fock_mode != QSGW_FOCK_FULL_JK && o->fock_mode != QSGW_FOCK_FROZEN)
+    return fail(c, QSGW_ERR_INVALID_ARG, "unknown fock_mode %d", o->fock_mode);
+  const bool frozen = o->fock_mode == QSGW_FOCK_FROZEN;
   if (o->s_block < 0) return fail(c, QSGW_ERR_INVALID_ARG, "need s_block >= 0");
   if (!(o->near_pole >= 0.0) || !isfinite(o->near_pole))
     return fail(c, QSGW_ERR_INVALID_ARG, "need a finite near_pole >= 0");
@@ -848,6 +863,9 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     return fail(c, QSGW_ERR_UNSUPPORTED, "QSGW_OPT_QSMP2 runs in FP64 only");
   if (qsmp2 && st->diag)
     return fail(c, QSGW_ERR_UNSUPPORTED, "QSGW_OPT_QSMP2 writes no diagonal self-energy");
+  const bool replay = (o->flags & QSGW_OPT_REPLAY_EIG) != 0;
+  if (replay && qsmp2)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "QSGW_OPT_REPLAY_EIG does not apply to qsMP2 iterations");
   const bool fp32 = o->precision != QSGW_PREC_FP64;  // FP32 or split-BF16 products
   const double near = o->near_pole > 0.0 ? o->near_pole : kNearPoleDefault;
 
@@ -861,20 +879,32 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   }
   if (sb > ntr) sb = ntr;
 
-  double *T, *Bmo, *Bt, *delta, *sqd, *M, *Omega, *rho, *w, *V, *hmo, *F, *tmp, *tmp2, *epsn, *Cn,
-      *scal;
+  double *T, *Bmo, *V, *hmo, *F, *tmp, *tmp2, *epsn, *Cn, *scal;
+  double *Bt = nullptr, *delta = nullptr, *sqd = nullptr, *M = nullptr, *Omega = nullptr,
+         *rho = nullptr, *w = nullptr;
   int* flags;
   CHECK(ws_get(c, W_T, (size_t)(naux * nn), &T));
   CHECK(ws_get(c, W_BMO, (size_t)(naux * nn), &Bmo));
-  CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
-  CHECK(ws_get(c, W_DELTA, (size_t)ntr, &delta));
-  CHECK(ws_get(c, W_SQD, (size_t)ntr, &sqd));
-  CHECK(ws_get(c, W_M, (size_t)(ntr * ntr), &M));
-  CHECK(ws_get(c, W_OMEGA, (size_t)ntr, &Omega));
-  CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
-  CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
-  double* wh = nullptr;
-  CHECK(ws_get(c, W_WH, (size_t)(nn * sb), &wh));
+  if (!qsmp2) {
+    CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
+    CHECK(ws_get(c, W_DELTA, (size_t)ntr, &delta));
+    CHECK(ws_get(c, W_SQD, (size_t)ntr, &sqd));
+  }
+  double *M2 = nullptr, *wh = nullptr;
+  unsigned long long* fprint = nullptr;
+  if (!qsmp2) {  // (the qsMP2 potential replaces Casida, residues and the qsGW product)
+    if (replay && c->eig_ntr != ntr)
+      return fail(c, QSGW_ERR_INVALID_ARG,
+                  "QSGW_OPT_REPLAY_EIG: the context keeps no solved Casida matrix of %lld transitions",
+                  (long long)ntr);
+    CHECK(ws_get(c, W_M, (size_t)(ntr * ntr), &M));
+    CHECK(ws_get(c, W_OMEGA, (size_t)ntr, &Omega));
+    if (replay) CHECK(ws_get(c, W_M2, (size_t)(ntr * ntr), &M2));
+    CHECK(ws_get(c, W_FPRINT, 2, &fprint));
+    CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
+    CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
+    CHECK(ws_get(c, W_WH, (size_t)(nn * sb), &wh));
+  }
   CHECK(ws_get(c, W_V, (size_t)nn, &V));
   CHECK(ws_get(c, W_HMO, (size_t)nn, &hmo));
   CHECK(ws_get(c, W_F, (size_t)nn, &F));
@@ -885,7 +915,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   CHECK(ws_get(c, W_SCAL, 8, &scal));
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
   float* Bmo32 = nullptr;
-  if (o->precision == QSGW_PREC_FP32) {  // (the split-BF16 residue product reads split copies)
+  if (o->precision == QSGW_PREC_FP32 && !qsmp2) {  // (the split-BF16 residue product reads split copies)
     CHECK(ws_get(c, W_BMO32, (size_t)(naux * nn), &Bmo32));
     float* r32 = nullptr;
     CHECK(ws_get(c, W_RHO32, (size_t)(naux * sb), &r32));
@@ -894,33 +924,39 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   {
     double* part = nullptr;
     int64_t nz = exchange_split(c->tiles, nbf, naux, nocc).nz;
-    for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
+    if (qsmp2) {
+      const int64_t z = mp2_split(c->tiles, nbf, mp2_block(nbf, nocc, 0) * nv).nz;
+      nz = z > nz ? z : nz;
+    }
+    for (int64_t s0 = 0; s0 < (qsmp2 ? 0 : ntr); s0 += sb) {
       const int64_t z = sigma_slices(c->tiles, nbf, (ntr - s0) < sb ? (ntr - s0) : sb, fp32,
                                      o->precision == QSGW_PREC_SPLIT_BF16);
       nz = z > nz ? z : nz;
     }
     CHECK(ws_get(c, W_PART, (size_t)(nz * nn), &part));
-    if (o->precision == QSGW_PREC_SPLIT_BF16) {
+    if (o->precision == QSGW_PREC_SPLIT_BF16 && !qsmp2) {
       uint16_t* u = nullptr;  // the qsGW product's split operands, sized for the largest block
       CHECK(ws_get(c, W_SPLIT_W, (size_t)(4 * x3_kfar(nbf, sb) * ((nbf + 127) / 128 * 128)), &u));
     }
     double* dummy = nullptr;
     CHECK(ws_get(c, W_J, (size_t)nn, &dummy));
     CHECK(ws_get(c, W_CP, (size_t)naux, &dummy));
-    CHECK(ws_get(c, W_EIGE, (size_t)(ntr > nbf ? ntr : nbf), &dummy));
+    CHECK(ws_get(c, W_EIGE, (size_t)(!qsmp2 && ntr > nbf ? ntr : nbf), &dummy));
   }
 
   // Finite inputs (one pass over each input array).
+  CHECK(check_finite(c, "qsgw_iterate",
+                     {fin(p->B_ao, naux * nn, "B_ao"), fin(p->h, nn, "h"), fin(st->C, nn, "C"),
+                      fin(st->eps, nbf, "eps"),
+                      fin(o->mix != 1.0 && st->iteration > 0 ? st->Vc : nullptr, nn, "Vc"),
+                      fin32(o->warm_start, nbf, "warm_start")}));
   HIP_TRY(c, hipMemsetAsync(flags, 0, 8 * sizeof(int), c->stream));
-  hipLaunchKernelGGL(k_check_finite, dim3(2048), dim3(256), 0, c->stream, p->B_ao, naux * nn, flags);
-  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, p->h, nn, flags);
-  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, st->C, nn, flags);
-  hipLaunchKernelGGL(k_check_finite, dim3(1), dim3(256), 0, c->stream, st->eps, nbf, flags);
-  CHECK(launch_check(c, "k_check_finite"));
-  {
-    int bad = 0;
-    CHECK(read_flag(c, flags, &bad));
-    if (bad) return fail(c, QSGW_ERR_NONFINITE, "non-finite value in B_ao, h, C or eps");
+  if (o->warm_start) {
+    // the learned warm start replaces the state's orbitals before the first iteration
+    HIP_TRY(c, hipMemcpyAsync(epsn, st->eps, nbf * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(Cn, st->C, nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    CHECK(qsgw_warm_start(c, nbf, epsn, Cn, o->warm_start, st->eps, st->C));
   }
 
   qsgw_report local;
@@ -932,14 +968,14 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
                       + 2.0 * a * t * t              // rho
                       + b * (b + 1.0) * a * t        // residues (symmetric in m, k)
                       + 2.0 * b * b * b * t          // qsGW matrix
-                      + b * (b + 1.0) * a * oc       // exchange (symmetric)
-                      + 2.0 * a * b * b              // Hartree
+                      + (frozen ? 0.0 : b * (b + 1.0) * a * oc  // exchange (symmetric)
+                                          + 2.0 * a * b * b)         // Hartree
                       + 8.0 * b * b * b;             // C^T h C, C V C^T, C U
   }
   if (qsmp2) {  // the qsMP2 potential replaces Casida, residues and the qsGW product
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
     local.hot_flops = 4.0 * b * b * b * a + b * (b + 1.0) * t * a + 2.0 * b * b * b * t +
-                      b * (b + 1.0) * a * oc + 2.0 * a * b * b + 8.0 * b * b * b;
+                      (frozen ? 0.0 : b * (b + 1.0) * a * oc + 2.0 * a * b * b) + 8.0 * b * b * b;
   }
   {
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
@@ -950,7 +986,8 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     local.kernel_flops[kKW - kKernelBase] = b * (b + 1.0) * a * t;
     local.kernel_flops[kKSigma - kKernelBase] = 2.0 * b * b * b * t;
     local.kernel_flops[kKSigmaRed - kKernelBase] = 0.0;
-    local.kernel_flops[kKFock - kKernelBase] = b * (b + 1.0) * a * oc + 2.0 * a * b * b + 8.0 * b * b * b;
+    local.kernel_flops[kKFock - kKernelBase] =
+        (frozen ? 0.0 : b * (b + 1.0) * a * oc + 2.0 * a * b * b) + 8.0 * b * b * b;
   }
   int status = QSGW_NOT_CONVERGED;
   for (int64_t it = 0; it < o->max_iter; ++it) {
@@ -967,18 +1004,36 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       CHECK(sp.close());
     } else {
       HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+      // a replayed iteration builds its Casida matrix apart and keeps the solved eigenpairs
+      double* Mb = replay ? M2 : M;
+      if (!replay) c->eig_ntr = -1;  // W_M is about to be overwritten
       CHECK(sp.open(kStageRpa));
-      CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, M, sqd, delta, Bt, flags, &sp,
+      CHECK(stage_rpa_build(c, nbf, naux, nocc, Bmo, eps, Mb, sqd, delta, Bt, flags, &sp,
                             o->precision));
       CHECK(sp.close());
+      // bit fingerprint of the matrix (outside the timed stages)
+      HIP_TRY(c, hipMemsetAsync(fprint, 0, sizeof(unsigned long long), c->stream));
+      hipLaunchKernelGGL(k_bits_fingerprint, dim3(2048), dim3(256), 0, c->stream, Mb, ntr * ntr,
+                         fprint);
+      CHECK(launch_check(c, "k_bits_fingerprint"));
+      unsigned long long fp = 0;
+      HIP_TRY(c, hipMemcpyAsync(&fp, fprint, sizeof(fp), hipMemcpyDeviceToHost, c->stream));
       {
         int bad = 0;
-        CHECK(read_flag(c, flags, &bad));
+        CHECK(read_flag(c, flags, &bad));  // (synchronizes: fp is read too)
         if (bad) return fail(c, QSGW_ERR_INVALID_ARG, "orbital energies are not in aufbau order");
       }
-      CHECK(sp.open(kStageEigRpa));
-      CHECK(stage_rpa_solve(c, ntr, M, Omega));
-      CHECK(sp.close());
+      if (replay) {
+        if (fp != c->eig_fp)
+          return fail(c, QSGW_ERR_INVALID_ARG,
+                      "QSGW_OPT_REPLAY_EIG: the Casida matrix differs from the one last solved");
+      } else {
+        CHECK(sp.open(kStageEigRpa));
+        CHECK(stage_rpa_solve(c, ntr, M, Omega));
+        CHECK(sp.close());
+        c->eig_ntr = ntr;
+        c->eig_fp = fp;
+      }
       for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
         const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
         CHECK(sp.open(kStageRes));
@@ -1059,13 +1114,20 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       }
     }
     // Eq. (6) in the MO basis of the current orbitals: C^T h C + J - K + V
+    // (frozen mean field: C^T h C + V)
     CHECK(congruence_t(c, nbf, C, p->h, tmp, hmo));
-    double *J = nullptr, *Kpart = nullptr;
-    int64_t nz = 0;
-    CHECK(stage_jk_mo(c, nbf, naux, nocc, Bmo, &J, &Kpart, &nz));
-    hipLaunchKernelGGL(k_fock_assemble, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hmo, J, Kpart,
-                       nz, V, nbf, F);
-    CHECK(launch_check(c, "k_fock_assemble"));
+    if (frozen) {
+      hipLaunchKernelGGL(k_fock_frozen, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hmo, V, nbf,
+                         F);
+      CHECK(launch_check(c, "k_fock_frozen"));
+    } else {
+      double *J = nullptr, *Kpart = nullptr;
+      int64_t nz = 0;
+      CHECK(stage_jk_mo(c, nbf, naux, nocc, Bmo, &J, &Kpart, &nz));
+      hipLaunchKernelGGL(k_fock_assemble, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hmo, J,
+                         Kpart, nz, V, nbf, F);
+      CHECK(launch_check(c, "k_fock_assemble"));
+    }
     CHECK(sp.close());
     CHECK(sp.close());
     CHECK(sp.open(kStageEigFock));
@@ -1175,6 +1237,9 @@ int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a,
     return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
   if (precision != QSGW_PREC_FP64)
     return fail(c, QSGW_ERR_UNSUPPORTED, "qsgw_gw_unrestricted: FP64 only (precision %d)", precision);
+  CHECK(check_finite(c, "qsgw_gw_unrestricted",
+                     {fin(B_mo_a, naux * nbf * nbf, "B_mo_a"), fin(B_mo_b, naux * nbf * nbf, "B_mo_b"),
+                      fin(eps_a, nbf, "eps_a"), fin(eps_b, nbf, "eps_b")}));
   const int64_t nn = nbf * nbf;
   const int64_t no[2] = {nocc_a, nocc_b};
   const int64_t nt[2] = {nocc_a * (nbf - nocc_a), nocc_b * (nbf - nocc_b)};
@@ -1183,6 +1248,7 @@ int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a,
   const double* es[2] = {eps_a, eps_b};
   double* Vs[2] = {V_a, V_b};
   if (ntr > 46340) return fail(c, QSGW_ERR_INVALID_ARG, "too many transitions for one Casida matrix");
+  c->eig_ntr = -1;  // W_M and W_OMEGA are reused here
   double *Bt, *delta, *sqd, *M, *Omega, *rho, *w, *wh;
   int* flags;
   CHECK(ws_get(c, W_BT, (size_t)(naux * ntr), &Bt));
@@ -1262,6 +1328,10 @@ int qsgw_fock_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_
     return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc_a, nocc_b < nbf");
   if (!B_mo_a || !B_mo_b || !h || !V_a || !V_b || !eps_a || !eps_b || !C_a || !C_b)
     return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_fock_unrestricted",
+                     {fin(B_mo_a, naux * nbf * nbf, "B_mo_a"), fin(B_mo_b, naux * nbf * nbf, "B_mo_b"),
+                      fin(h, nbf * nbf, "h"), fin(V_a, nbf * nbf, "V_a"), fin(V_b, nbf * nbf, "V_b"),
+                      fin(C_a, nbf * nbf, "C_a"), fin(C_b, nbf * nbf, "C_b")}));
   const int64_t nn = nbf * nbf;
   const int64_t no[2] = {nocc_a, nocc_b};
   const double* Bs[2] = {B_mo_a, B_mo_b};

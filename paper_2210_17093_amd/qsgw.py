@@ -34,9 +34,11 @@ SIGMA_DIAG_GRID = 1
 SIGMA_DIAG_SELF = 2
 
 FOCK_FULL_JK = 0
+FOCK_FROZEN = 1
 OPT_GRAPH = 1
 OPT_REFINE = 2
 OPT_QSMP2 = 4
+OPT_REPLAY_EIG = 8
 REPORT_MAX_ITERS = 64
 MLP_NPARAMS = 18817
 MLP_NFEAT = 16
@@ -69,7 +71,8 @@ class State(ct.Structure):
 class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("eta", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int64), ("mix", ct.c_double), ("fock_mode", ct.c_int),
-                ("s_block", ct.c_int64), ("flags", ct.c_int64), ("near_pole", ct.c_double)]
+                ("s_block", ct.c_int64), ("flags", ct.c_int64), ("near_pole", ct.c_double),
+                ("warm_start", ct.c_void_p)]
 
 
 KERNELS = ("mo_transform_1", "mo_transform_2", "casida", "residue_rho", "residue_w",
@@ -386,8 +389,11 @@ def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
 
 def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
                  Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None, refine=False,
-                 near_pole=0.0, qsmp2=False):
+                 near_pole=0.0, qsmp2=False, fock_mode=FOCK_FULL_JK, warm_start=None,
+                 replay_eig=False):
     """Runs qsGW iterations (qsMP2 iterations with qsmp2=True) in place on (eps, C).
+    warm_start: None or a float32 [nbf] device tensor of predicted shifts.
+    replay_eig: reuse the context's last Casida eigenpairs (QSGW_OPT_REPLAY_EIG).
     Returns (status, report dict, iteration)."""
     naux, nbf, _ = B_ao.shape
     prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
@@ -395,9 +401,12 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
     st = State(_ptr(eps, (nbf,), name="eps"), _ptr(C, (nbf, nbf), name="C"),
                _ptr(Vc, (nbf, nbf), name="Vc") if Vc is not None else None, iteration,
                _ptr(diag, (nbf, 4), name="diag") if diag is not None else None)
-    opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), FOCK_FULL_JK,
-                  int(s_block), (OPT_REFINE if refine else 0) | (OPT_QSMP2 if qsmp2 else 0),
-                  float(near_pole))
+    flags = ((OPT_REFINE if refine else 0) | (OPT_QSMP2 if qsmp2 else 0)
+             | (OPT_REPLAY_EIG if replay_eig else 0))
+    opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), int(fock_mode),
+                  int(s_block), flags, float(near_pole),
+                  _ptr(warm_start, (nbf,), torch.float32, "warm_start")
+                  if warm_start is not None else None)
     rep = Report()
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))

@@ -4,9 +4,11 @@ For a workload it times each tunable product (libqsgw's tile table, see
 qsgw_set_tiles) under every shape the product allows, and the K-split targets
 of the split products, by coordinate descent from the default table: one key
 at a time, every candidate value with the other keys at their best so far,
-the median of `reps` iterations of that product's own HIP-event time.  The
-fastest table per workload goes to tiles.json next to this file, which
-bench.py applies to its workload.
+the median of `reps` iterations of that product's own HIP-event time.  A
+candidate whose orbital energies leave those of the default table by more
+than a rounding-order difference (1e-10 Ha for FP64, a tenth of the 1 meV
+gate for the reduced precisions) is dropped.  The fastest table per workload
+goes to tiles.json next to this file, which bench.py applies to its workload.
 
     python -m paper_2210_17093_amd.tune cfg2 cfg2:fp32 cfg2:bf16x3 cfg4 [--reps 3]
 
@@ -76,7 +78,7 @@ def single_timer(name, precision):
         torch.cuda.synchronize()
         _, rep, _ = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1,
                                    precision=precision)
-        return rep["kernel_ms"]
+        return rep["kernel_ms"], e.cpu().numpy()
     return ctx, run
 
 
@@ -107,7 +109,7 @@ def batched_timer(name):
             _, reps = q.qsgw_iterate_batched(ctx, runs, 1e-3, tol=0.0, max_iter=1,
                                              precision=q.PREC_FP32)
         stream.synchronize()
-        return reps[0]["kernel_ms"]
+        return reps[0]["kernel_ms"], np.concatenate([r["eps"].cpu().numpy() for r in runs])
     return ctx, run
 
 
@@ -116,7 +118,9 @@ def tune(name, reps=3):
     prec = {"fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}.get(variant, q.PREC_FP64)
     ctx, run = batched_timer(base) if base == "cfg4" else single_timer(base, prec)
     best = dict(DEFAULTS)
-    run(spec_of(best))  # warm-up
+    _, eps_ref = run(spec_of(best))  # warm-up, and the default table's energies
+    # a tile table changes only the rounding order of the products
+    max_dev = 1e-10 if prec == q.PREC_FP64 and base != "cfg4" else 0.1 / 27211.386
     trials = []
     for key, (values, kernels) in CANDIDATES.items():
         if key == "persistent" and base != "cfg4":
@@ -126,16 +130,21 @@ def tune(name, reps=3):
             table = dict(best)
             table[key] = v
             try:
-                ts = [sum(run(spec_of(table))[k] for k in kernels) for _ in range(reps)]
+                outs = [run(spec_of(table)) for _ in range(reps)]
             except q.QsgwError as err:
                 log(f"[tune] {name} {key}={v}: {err}")
                 continue
+            dev = max(float(np.max(np.abs(e - eps_ref))) for _, e in outs)
+            if dev > max_dev:
+                log(f"[tune] {name} {key}={v}: dropped, energies moved by {dev:.2e} Ha")
+                continue
+            ts = [sum(km[k] for k in kernels) for km, _ in outs]
             scores[v] = float(np.median(ts))
             trials.append(dict(key=key, value=v, ms=scores[v]))
             log(f"[tune] {name} {key}={v}: {scores[v]:.3f} ms")
         best[key] = min(scores, key=scores.get)
-    kd = [run(spec_of(DEFAULTS)) for _ in range(reps)]
-    kb = [run(spec_of(best)) for _ in range(reps)]
+    kd = [run(spec_of(DEFAULTS))[0] for _ in range(reps)]
+    kb = [run(spec_of(best))[0] for _ in range(reps)]
     default_ms = {k: float(np.median([x[k] for x in kd])) for k in kd[0]}
     best_ms = {k: float(np.median([x[k] for x in kb])) for k in kb[0]}
     ctx.close()

@@ -65,10 +65,31 @@ def test_product_never_imports_the_oracle():
                 assert "qsgw_oracle" not in src, f
 
 
-def test_struct_layouts_match_header():
-    """ctypes mirrors of the C structs: sizes follow the header's field order."""
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the C structs: every field's offset and each struct's
+    size as the C compiler lays out the header (gcc on the host)."""
+    import shutil
+    import subprocess
+
     import paper_2210_17093_amd.qsgw as q
-    assert ctypes.sizeof(q.Problem) == 5 * 8
-    assert ctypes.sizeof(q.State) == 5 * 8
-    assert ctypes.sizeof(q.Options) == 9 * 8
-    assert ctypes.sizeof(q.Report) == 8 + 8 + 64 * 8 + 7 * 8 + 8 + 3 * 8 * 8
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    mirrors = {"qsgw_problem": q.Problem, "qsgw_state": q.State, "qsgw_options": q.Options,
+               "qsgw_report": q.Report}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qsgw.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -291,6 +291,34 @@ def test_mutant_exchange_diagonal_over_virtuals_caught(monkeypatch):
         test_p20_exchange_diagonal_is_four_index_exchange(6, 14, 2, 3)
 
 
+# ------------------------------------------- P21: frozen mean field ------
+def test_p21_frozen_mean_field():
+    """Eq. (6) with the mean field frozen at the start's density: with F0 the
+    start's Hartree-Fock matrix, the first step equals the full step (same
+    density); the converged frozen iteration is self-consistent for F0 + V."""
+    p = tiny(nbf=8, naux=16, nocc=3, seed=21, coupling=0.1)
+    h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+    D0 = p.C0[:, :p.nocc] @ p.C0[:, :p.nocc].T
+    J0, K0 = pins.jk_four_index(p.B_ao, D0)
+    F0 = h + J0 - K0
+    # the synthetic start is an exact Hartree-Fock fixed point: F0 = C0 diag(eps0) C0^T
+    np.testing.assert_allclose(F0, (p.C0 * p.eps0) @ p.C0.T, atol=1e-12)
+    eta = 1e-2
+    full = O.qsgw_step(p.B_ao, h, p.C0, p.eps0, p.nocc, eta)
+    frz = O.qsgw_step(p.B_ao, F0, p.C0, p.eps0, p.nocc, eta, fock_mode="frozen")
+    np.testing.assert_allclose(frz["eps"], full["eps"], atol=1e-12)
+    eps, C, hist = O.qsgw_iterate(p.B_ao, F0, p.C0, p.eps0, p.nocc, eta, 1e-11, 200, mix=0.6,
+                                  keep=("Vao",), fock_mode="frozen")
+    assert hist[-1]["max_deps"] < 1e-11
+    # at the fixed point (F0 + V[eps, C]) C = C diag(eps); V from the converged orbitals
+    st = O.qsgw_step(p.B_ao, F0, C, eps, p.nocc, eta, fock_mode="frozen")
+    Fc = F0 + C @ st["V"] @ C.T
+    np.testing.assert_allclose(Fc @ C, C * eps[None, :], atol=1e-9)
+    # and the frozen and full fixed points differ once the density has moved
+    eps_f, _, _ = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, eta, 1e-11, 200, mix=0.6)
+    assert np.max(np.abs(eps_f - eps)) > 1e-6
+
+
 # ------------------------------------------------------------- mutations --
 _residues = O.residues
 
