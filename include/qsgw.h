@@ -128,13 +128,33 @@ int qsgw_mo_transform(qsgw_ctx* ctx, int64_t nbf, int64_t naux, const double* B_
 int qsgw_rpa_build(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const double* B_mo,
                    const double* eps, double* M, double* sqrt_delta, int precision);
 
+/* Solvers of the Casida eigenproblem M Z = Z Omega^2 (Eq. (12)), chosen per
+ * context with qsgw_set_eigensolver.  They apply to qsgw_rpa_solve and to the
+ * Casida eigensolves inside qsgw_iterate and qsgw_gw_unrestricted (the Fock
+ * eigensolves and the batched path always use rocSOLVER dsyevd). */
+#define QSGW_EIG_AUTO 0      /* the two-stage solver for n >= 2048, dsyevd below (default) */
+#define QSGW_EIG_ROCSOLVER 1 /* rocSOLVER dsyevd (one-stage tridiagonal reduction) */
+/* Two-stage reduction, all FP64: dense -> band of half-width 64 by blocked
+ * Householder panels whose two-sided updates are matrix products, band ->
+ * tridiagonal by bulge chasing, rocSOLVER divide and conquer (dstedc) on the
+ * tridiagonal matrix, then both back-transformations (the bulge-chasing
+ * reflectors in blocks of 64 sweeps, the panel reflectors as block
+ * reflectors).  Below n = 256 it calls dsyevd. */
+#define QSGW_EIG_TWO_STAGE 2
+
+/* Selects the Casida eigensolver of the context (QSGW_EIG_*).  Eigenvectors
+ * of equal quality either way; signs, and rotations inside degenerate
+ * eigenspaces, may differ between solvers.
+ * Errors: an unknown solver. */
+int qsgw_set_eigensolver(qsgw_ctx* ctx, int solver);
+
 /*
- * Dense symmetric eigensolve of the Casida matrix (rocSOLVER dsyevd), kept
- * apart from the hot path: M Z = Z Omega^2.
+ * Dense symmetric eigensolve of the Casida matrix (the context's solver,
+ * qsgw_set_eigensolver), kept apart from the hot path: M Z = Z Omega^2.
  * M_to_Z: [ntr][ntr] in; on return holds Z column-major, i.e. row s of the
  *         row-major view is the eigenvector of Omega[s].
  * Omega:  [ntr] out, ascending, Omega_s = sqrt of the eigenvalue.
- * Errors: QSGW_ERR_SOLVER if dsyevd fails or an eigenvalue is <= 0 (RPA
+ * Errors: QSGW_ERR_SOLVER if the solver fails or an eigenvalue is <= 0 (RPA
  * instability).  Synchronizes the context stream.
  */
 int qsgw_rpa_solve(qsgw_ctx* ctx, int64_t ntr, double* M_to_Z, double* Omega);
@@ -249,7 +269,8 @@ int qsgw_ao2mo_4center(qsgw_ctx* ctx, int64_t nbf, const double* eri_ao, const d
  * occupation.  Transitions t = (i, a, sigma) of both spins (alpha first, each
  * i-major) share one direct-RPA Casida problem,
  *   M = Delta^2 + 2 sqrt(Delta) K sqrt(Delta),  K[t][u] = sum_P B^{sigma P}_{ia} B^{sigma' P}_{jb},
- * solved by rocSOLVER dsyevd inside the call; then for each spin sigma
+ * solved inside the call by the context's Casida eigensolver
+ * (qsgw_set_eigensolver); then for each spin sigma
  *   w[m][n][s] = sum_P B^{sigma P}_{mn} rho_{P s},  rho = sum_t B_t sqrt(Delta_t) Z[s][t] / sqrt(Omega_s),
  *   V_sigma[m][n] = 1/2 (G[m][n] + G[n][m]),
  *   G[m][n] = sum_{k,s} w[m][k][s] w[n][k][s] Re 1/(eps_m - eps_k +- (Omega_s - i eta))
@@ -389,6 +410,32 @@ typedef struct {
  */
 int qsgw_iterate(qsgw_ctx* ctx, const qsgw_problem* prob, qsgw_state* st, const qsgw_options* opt,
                  qsgw_report* rep);
+
+/*
+ * Open-shell (spin-unrestricted) qsGW iterations, Eqs. (4), (6), (12)-(19)
+ * with explicit spins, all on the device: per iteration the MO transform of
+ * each spin's orbitals (Eq. 16), the open-shell GW potential of both spins
+ * from one Casida problem over the transitions of both spins
+ * (qsgw_gw_unrestricted), and the open-shell Fock update with its
+ * eigensolve (qsgw_fock_unrestricted).  Converged when the largest change
+ * of any orbital energy of either spin, max_m |eps'_m - eps_m|, is below
+ * opt->tol.
+ * prob: nbf, naux, B_ao, h as in qsgw_iterate, with prob->nocc the number of
+ *   alpha electrons; nocc_b: the number of beta electrons.
+ * st_a, st_b: each spin's eps and C (in/out) and iteration count (advanced);
+ *   Vc and diag must be NULL.
+ * opt: eta, tol, max_iter are used; precision must be QSGW_PREC_FP64, mix 1,
+ *   fock_mode QSGW_FOCK_FULL_JK, flags 0, s_block 0, warm_start NULL
+ *   (QSGW_ERR_UNSUPPORTED otherwise).
+ * rep: NULL or the report (iterations, converged, max_deps per iteration,
+ *   ms_stage summed over the call, hot_flops of one iteration; the per-kernel
+ *   fields are zero).
+ * Returns QSGW_OK if converged, QSGW_NOT_CONVERGED otherwise, or an error of
+ * the entry points it calls.  Synchronizes several times per iteration.
+ */
+int qsgw_iterate_unrestricted(qsgw_ctx* ctx, const qsgw_problem* prob, int64_t nocc_b,
+                              qsgw_state* st_a, qsgw_state* st_b, const qsgw_options* opt,
+                              qsgw_report* rep);
 
 /*
  * Batched qsGW iterations for nmol independent molecules of different sizes

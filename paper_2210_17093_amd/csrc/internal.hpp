@@ -79,6 +79,22 @@ enum Slot {
   W_AO2MO,       // four-index AO->MO: quarter-transformed slab   [m_count][nbf][nbf][nbf]
   W_M2,          // replayed iteration: Casida matrix, checked against the solved one [ntr][ntr]
   W_FPRINT,      // bit fingerprints of Casida matrices           [2] u64
+  W_EIG_V1,      // two-stage eigensolver: panel reflectors V    [sum of panel rows * b]
+  W_EIG_T1,      // two-stage eigensolver: panel factors T       [panels][b][b]
+  W_EIG_TAU1,    // two-stage eigensolver: panel tau             [panels][b]
+  W_EIG_U,       // two-stage eigensolver: [V W], [W V]          [2][n][2b]
+  W_EIG_XY,      // two-stage eigensolver: X, Y, small products   [2 n b + 2 b b]
+  W_EIG_BAND,    // two-stage eigensolver: lower band + bulge     [n][2b+1]
+  W_EIG_V2,      // two-stage eigensolver: bulge reflectors       [steps][b]
+  W_EIG_TAU2,    // two-stage eigensolver: bulge tau              [steps]
+  W_EIG_OFF,     // two-stage eigensolver: first step of a sweep  [n] int64
+  W_EIG_DE,      // two-stage eigensolver: tridiagonal d, e       [2 n]
+  W_EIG_TB,      // two-stage eigensolver: WY factors of the bulge reflector blocks [blocks][64][64]
+  W_EIG_PX,      // two-stage projection: Q2^T Q1^T Bt^T          [naux][ntr]
+  W_RHOFULL,     // iteration through the projection: rho' of every excitation [naux][ntr]
+  W_RHOFULL32,   // ... and its FP32 copy (FP32 products)          [naux][ntr] float
+  W_BMO_B,       // open-shell iteration: beta-spin MO tensor     [naux][nbf][nbf]
+  W_VB,          // open-shell iteration: beta-spin potential     [nbf][nbf]
   W_NSLOTS
 };
 
@@ -133,7 +149,21 @@ struct qsgw_ctx {
   // excitation energies (QSGW_OPT_REPLAY_EIG reads them).
   int64_t eig_ntr = -1;
   unsigned long long eig_fp = 0;
+  // the kept eigenpairs are (Omega, rho' of every excitation in W_RHOFULL)
+  // from the two-stage projection instead of (Omega, Z in W_M)
+  bool eig_fold = false;
+  // solver of the Casida eigenproblems (QSGW_EIG_*)
+  int eig_solver = QSGW_EIG_AUTO;
 };
+
+
+// Two-stage dense symmetric eigensolver (eig2s.hip): A [n][n] in, its
+// eigenvectors column-major out, eigenvalues ascending.
+int eig_two_stage(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what);
+// Eigenvalues of A and R[P][s] = sum_t Bt[P][t] Z[t][s] without forming Z
+// (eig2s.hip); A is destroyed, X is an [naux][n] work array.
+int eig_two_stage_project(qsgw_ctx* c, int64_t n, double* A, double* evals, int64_t naux,
+                          const double* Bt, double* X, double* R, const char* what);
 
 // qsMP2 potential of Eqs. (20)-(21) in the MO basis (mp2.hip), for the
 // iteration driver: V (+)= the potential; occ_block 0 = automatic blocks.
@@ -462,6 +492,16 @@ int syevd(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what) {
   return QSGW_OK;
 }
 
+// Casida eigenproblems: the two-stage solver from this size on (QSGW_EIG_AUTO).
+constexpr int64_t kEigTwoStageMin = (int64_t)1 << 40;
+inline bool eig_two_stage_for(const qsgw_ctx* c, int64_t n) {
+  return c->eig_solver == QSGW_EIG_TWO_STAGE ||
+         (c->eig_solver == QSGW_EIG_AUTO && n >= kEigTwoStageMin);
+}
+inline int eig_casida(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what) {
+  if (eig_two_stage_for(c, n)) return eig_two_stage(c, n, A, evals, what);
+  return syevd(c, n, A, evals, what);
+}
 
 // V (+)= 1/2 (G + G^T), G = sum of the nz partial slices of part.  Long sums
 // go through a first level of 32 slices per group (coalesced reads, many

@@ -308,6 +308,12 @@ __device__ __forceinline__ void check_finite_body(const T* x, int64_t len, int* 
     ok = ok && isfinite(x[i]);
   if (!ok) atomicOr(bad, mask);
 }
+__global__ void k_scale_rho(double* rho, int64_t naux, int64_t ntr, const double* Omega) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= naux * ntr) return;
+  rho[idx] *= sqrt(2.0 / Omega[idx % ntr]);
+}
+
 __global__ void k_check_finite(const double* x, int64_t len, int* bad, int mask) {
   check_finite_body(x, len, bad, mask);
 }

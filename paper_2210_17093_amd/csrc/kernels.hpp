@@ -487,6 +487,9 @@ __global__ void k_fix_column_signs(double* C, int64_t n);
 __global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, double* out);
 // Non-finite scan: flags any NaN/Inf in x[0..len).
 __global__ void k_check_finite(const double* x, int64_t len, int* bad, int mask);
+// rho[P][s] *= sqrt(2 / Omega[s]) over a row-major [naux][ntr] array (the
+// factor of Eq. (18) with the normalisation (X+Y)^s = sqrt(Delta) Z^s / sqrt(Omega_s))
+__global__ void k_scale_rho(double* rho, int64_t naux, int64_t ntr, const double* Omega);
 __global__ void k_check_finite_f32(const float* x, int64_t len, int* bad, int mask);
 __global__ void k_bits_fingerprint(const double* x, int64_t len, unsigned long long* out);
 __global__ void k_fock_frozen(const double* hmo, const double* V, int64_t n, double* F);

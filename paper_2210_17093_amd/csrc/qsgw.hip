@@ -205,7 +205,7 @@ int stage_rpa_build(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc, const 
 }
 
 int stage_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M, double* Omega) {
-  CHECK(syevd(c, ntr, M, Omega, "rpa_solve"));
+  CHECK(eig_casida(c, ntr, M, Omega, "rpa_solve"));
   int* flags = nullptr;
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
   HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
@@ -218,6 +218,27 @@ int stage_rpa_solve(qsgw_ctx* c, int64_t ntr, double* M, double* Omega) {
   return QSGW_OK;
 }
 
+// Casida eigensolve through the two-stage projection (Eq. (12)): Omega and
+// rho'[P][s] = sqrt(2/Omega_s) sum_t Bt[P][t] Z[t][s] for every excitation
+// (row-major [naux][ntr]), the rho' of Eq. (18), without forming Z.  M is
+// destroyed; X is an [naux][ntr] work array.
+int stage_rpa_solve_project(qsgw_ctx* c, int64_t ntr, int64_t naux, double* M, double* Omega,
+                            const double* Bt, double* X, double* rho) {
+  CHECK(eig_two_stage_project(c, ntr, M, Omega, naux, Bt, X, rho, "rpa_solve"));
+  int* flags = nullptr;
+  CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_omega_from_eigs, dim3(blocks_for(ntr)), dim3(256), 0, c->stream, Omega, ntr,
+                     Omega, flags);
+  CHECK(launch_check(c, "k_omega_from_eigs"));
+  int bad = 0;
+  CHECK(read_flag(c, flags, &bad));
+  if (bad) return fail(c, QSGW_ERR_SOLVER, "RPA instability: a Casida eigenvalue Omega^2 <= 0");
+  hipLaunchKernelGGL(k_scale_rho, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, rho, naux,
+                     ntr, Omega);
+  return launch_check(c, "k_scale_rho");
+}
+
 // Eq. (18) for excitations [s0, s0 + ns): rho' = sqrt(2/Omega) Bt Z^T, w = B_mo^T rho'.
 template <class CT>
 int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const double* B_mo,
@@ -226,9 +247,13 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
                      double eta, float* wh32 = nullptr, float* w32 = nullptr, double thr = 0.0,
                      const float* B_mo32 = nullptr, const float* Bt32_in = nullptr,
                      bool reuse_split = false, const X3Out* x3o = nullptr,
-                     bool rho_ready = false) {
-  // rho_ready (FP64 only): rho already holds rho' of this block (computed for
-  // another MO tensor with the same Bt and Z), so only the w product runs.
+                     bool rho_ready = false, int64_t rho_ld = 0,
+                     const float* rho32_in = nullptr) {
+  // rho_ready: rho already holds rho' of this block (computed for another MO
+  // tensor with the same Bt and Z, or by the eigensolver's projection), row P
+  // at rho + P * rho_ld (rho_ld 0: ns), so only the w product runs; the FP32
+  // variant then reads rho32_in (same layout) and the split-BF16 variant
+  // splits rho.  Z is not read.
   // The FP32 variant reads FP32 copies of B_mo and rho' in the residue
   // product (half the operand bytes); rounding them is what its matrix cores
   // do anyway.  The split-BF16 variant reads them split into BF16 halves in
@@ -255,7 +280,8 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
   }
   uint16_t *splitRA = nullptr, *splitZ = nullptr;
   const int64_t kpt = ((ntr + 31) / 32) * 32, naux_pad = ((naux + 127) / 128) * 128;
-  if (x3) {
+  const int64_t ldr = rho_ld > 0 ? rho_ld : ns;
+  if (x3 && !rho_ready) {
     // rho' = Bt Z^T from split copies: Bt with rows P (once per B_mo, as the
     // pair rows), the block's eigenvectors with rows s; k = t, padded to 32
     CHECK(ws_get(c, W_SPLIT_RA, (size_t)(2 * kpt * naux_pad), &splitRA));
@@ -268,20 +294,25 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     hipLaunchKernelGGL(k_split_rows, dim3((unsigned)(ns_pad / 32), (unsigned)((kpt + 255) / 256)),
                        dim3(256), 0, c->stream, Z + s0 * ntr, ntr, ns, ntr, ns_pad, kpt, splitZ);
     CHECK(launch_check(c, "k_split_rows"));
-  } else if (f32) {
-    if (!Bt32) {
-      float* b = nullptr;
-      CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &b));
-      hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, Bt,
-                         naux * ntr, b);
+  } else if (f32 && !x3) {
+    if (!rho_ready) {
+      if (!Bt32) {
+        float* b = nullptr;
+        CHECK(ws_get(c, W_BT32, (size_t)(naux * ntr), &b));
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, Bt,
+                           naux * ntr, b);
+        CHECK(launch_check(c, "k_to_f32"));
+        Bt32 = b;
+      }
+      CHECK(ws_get(c, W_Z32, (size_t)(ns * ntr), &Z32));
+      hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(ns * ntr)), dim3(256), 0, c->stream,
+                         Z + s0 * ntr, ns * ntr, Z32);
       CHECK(launch_check(c, "k_to_f32"));
-      Bt32 = b;
+      CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
+    } else {
+      if (!rho32_in) return fail(c, QSGW_ERR_INVALID_ARG, "residues: no FP32 copy of rho'");
+      rho32 = const_cast<float*>(rho32_in);
     }
-    CHECK(ws_get(c, W_Z32, (size_t)(ns * ntr), &Z32));
-    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(ns * ntr)), dim3(256), 0, c->stream, Z + s0 * ntr,
-                       ns * ntr, Z32);
-    CHECK(launch_check(c, "k_to_f32"));
-    CHECK(ws_get(c, W_RHO32, (size_t)(naux * ns), &rho32));
     if (!B_mo32) {
       float* b32 = nullptr;
       CHECK(ws_get(c, W_BMO32, (size_t)(naux * nbf * nbf), &b32));
@@ -291,7 +322,7 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       B_mo32 = b32;
     }
   }
-  if (!(rho_ready && !f32)) {
+  if (!rho_ready) {
     const int64_t maxk = f32 ? kFp32MaxK : ntr;
     const int64_t kr = x3 ? kpt : ntr;  // (k length of the product)
     SplitPlan spl = rho_split(c->tiles, naux, ns, kr, maxk);
@@ -328,12 +359,12 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
       E.rho32 = rho32;
       CHECK(rho_gemm(E, SplitPlan{0, 1}));
     }
-    if (x3) {
-      hipLaunchKernelGGL(k_split_cols, dim3(blocks_for(ns_pad * (kpad / 8))), dim3(256), 0,
-                         c->stream, rho, ns, ns, naux, ns_pad, kpad, splitB);
-      CHECK(launch_check(c, "k_split_cols"));
-    }
     SPAN_CLOSE(sp);
+  }
+  if (x3) {
+    hipLaunchKernelGGL(k_split_cols, dim3(blocks_for(ns_pad * (kpad / 8))), dim3(256), 0, c->stream,
+                       rho, ldr, ns, naux, ns_pad, kpad, splitB);
+    CHECK(launch_check(c, "k_split_cols"));
   }
   {
     const int64_t nn = nbf * nbf;
@@ -358,11 +389,11 @@ int stage_residues_t(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const 
     } else if constexpr (f32) {
       // k tiles of 32: twice the matrix-core work per barrier and per prefetch
       PairRows<8, 16, float> A{B_mo32, nn, 0, nbf, blocks};
-      Strided<false, float> B{rho32, 1, ns, 0, ns};
+      Strided<false, float> B{rho32, 1, ldr, 0, ns};
       CHECK((gemm_t<CT, 128, 128, false, 32>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
     } else {
       PairRows<8, 16> A{B_mo, nn, 0, nbf, blocks};
-      Strided<false> B{rho, 1, ns, 0, ns};
+      Strided<false> B{rho, 1, ldr, 0, ns};
       CHECK((gemm_t<CT, 128, 128, false>(c, "residues/w", A, B, E, nblk * 128, ns, naux, 1)));
     }
     SPAN_CLOSE(sp);
@@ -377,16 +408,18 @@ int stage_residues(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t ntr, const do
                    int prec = QSGW_PREC_FP64, float* wh32 = nullptr, float* w32 = nullptr,
                    double thr = 0.0, const float* B_mo32 = nullptr, const float* Bt32 = nullptr,
                    bool reuse_split = false, const X3Out* x3o = nullptr,
-                   bool rho_ready = false) {
+                   bool rho_ready = false, int64_t rho_ld = 0, const float* rho32 = nullptr) {
   if (prec == QSGW_PREC_FP32)
     return stage_residues_t<float>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                   eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32);
+                                   eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, false, nullptr,
+                                   rho_ready, rho_ld, rho32);
   if (prec == QSGW_PREC_SPLIT_BF16)
     return stage_residues_t<Bf16x3>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
-                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, reuse_split, x3o);
+                                    eps, nocc, eta, wh32, w32, thr, B_mo32, Bt32, reuse_split, x3o,
+                                    rho_ready, rho_ld);
   return stage_residues_t<double>(c, nbf, naux, ntr, B_mo, Bt, Z, Omega, s0, ns, rho, w, sp, wh,
                                   eps, nocc, eta, nullptr, nullptr, 0.0, nullptr, nullptr, false,
-                                  nullptr, rho_ready);
+                                  nullptr, rho_ready, rho_ld);
 }
 
 // Reduced-precision variant of Eq. (19) for one excitation block (PT: float
@@ -890,16 +923,27 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     CHECK(ws_get(c, W_DELTA, (size_t)ntr, &delta));
     CHECK(ws_get(c, W_SQD, (size_t)ntr, &sqd));
   }
-  double *M2 = nullptr, *wh = nullptr;
+  double *M2 = nullptr, *wh = nullptr, *rhoF = nullptr, *PX = nullptr;
+  float* rhoF32 = nullptr;
   unsigned long long* fprint = nullptr;
+  // the two-stage solver hands the residues rho' of every excitation
+  // directly (projection), the rocSOLVER path the eigenvectors Z
+  const bool fold = !qsmp2 && eig_two_stage_for(c, ntr);
   if (!qsmp2) {  // (the qsMP2 potential replaces Casida, residues and the qsGW product)
-    if (replay && c->eig_ntr != ntr)
+    if (replay && (c->eig_ntr != ntr || c->eig_fold != fold))
       return fail(c, QSGW_ERR_INVALID_ARG,
-                  "QSGW_OPT_REPLAY_EIG: the context keeps no solved Casida matrix of %lld transitions",
+                  "QSGW_OPT_REPLAY_EIG: the context keeps no Casida solution of %lld transitions "
+                  "from the current eigensolver",
                   (long long)ntr);
     CHECK(ws_get(c, W_M, (size_t)(ntr * ntr), &M));
     CHECK(ws_get(c, W_OMEGA, (size_t)ntr, &Omega));
     if (replay) CHECK(ws_get(c, W_M2, (size_t)(ntr * ntr), &M2));
+    if (fold) {
+      CHECK(ws_get(c, W_RHOFULL, (size_t)(naux * ntr), &rhoF));
+      if (!replay) CHECK(ws_get(c, W_EIG_PX, (size_t)(naux * ntr), &PX));
+      if (o->precision == QSGW_PREC_FP32)
+        CHECK(ws_get(c, W_RHOFULL32, (size_t)(naux * ntr), &rhoF32));
+    }
     CHECK(ws_get(c, W_FPRINT, 2, &fprint));
     CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
     CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
@@ -965,7 +1009,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
     local.hot_flops = 4.0 * b * b * b * a            // Eq. (16)
                       + t * (t + 1.0) * a            // Casida build (symmetric)
-                      + 2.0 * a * t * t              // rho
+                      + (fold ? 0.0 : 2.0 * a * t * t)  // rho' (inside the eigensolve when projected)
                       + b * (b + 1.0) * a * t        // residues (symmetric in m, k)
                       + 2.0 * b * b * b * t          // qsGW matrix
                       + (frozen ? 0.0 : b * (b + 1.0) * a * oc  // exchange (symmetric)
@@ -982,7 +1026,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
     local.kernel_flops[kKMo1 - kKernelBase] = 2.0 * b * b * b * a;
     local.kernel_flops[kKMo2 - kKernelBase] = 2.0 * b * b * b * a;
     local.kernel_flops[kKCasida - kKernelBase] = t * (t + 1.0) * a;
-    local.kernel_flops[kKRho - kKernelBase] = 2.0 * a * t * t;
+    local.kernel_flops[kKRho - kKernelBase] = fold ? 0.0 : 2.0 * a * t * t;
     local.kernel_flops[kKW - kKernelBase] = b * (b + 1.0) * a * t;
     local.kernel_flops[kKSigma - kKernelBase] = 2.0 * b * b * b * t;
     local.kernel_flops[kKSigmaRed - kKernelBase] = 0.0;
@@ -1029,10 +1073,19 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
                       "QSGW_OPT_REPLAY_EIG: the Casida matrix differs from the one last solved");
       } else {
         CHECK(sp.open(kStageEigRpa));
-        CHECK(stage_rpa_solve(c, ntr, M, Omega));
+        if (fold)
+          CHECK(stage_rpa_solve_project(c, ntr, naux, M, Omega, Bt, PX, rhoF));
+        else
+          CHECK(stage_rpa_solve(c, ntr, M, Omega));
         CHECK(sp.close());
         c->eig_ntr = ntr;
         c->eig_fp = fp;
+        c->eig_fold = fold;
+      }
+      if (fold && rhoF32) {
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(naux * ntr)), dim3(256), 0, c->stream, rhoF,
+                           naux * ntr, rhoF32);
+        CHECK(launch_check(c, "k_to_f32"));
       }
       for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
         const int64_t ns = (ntr - s0) < sb ? (ntr - s0) : sb;
@@ -1056,10 +1109,12 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
             // residues only in the columns the near-pole part reads
             CHECK(near_x3(c, nbf, nocc, ns, eps, Omega + s0, near, &x3o));
           }
-          CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w64, &sp, nullptr,
-                               eps, nocc, o->eta, o->precision, wh32, w32, near, Bmo32,
+          CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns,
+                               fold ? rhoF + s0 : rho, w64, &sp, nullptr, eps, nocc, o->eta,
+                               o->precision, wh32, w32, near, Bmo32,
                                static_cast<const float*>(c->ws[W_BT32].p), s0 > 0,
-                               x3 ? &x3o : nullptr));
+                               x3 ? &x3o : nullptr, fold, fold ? ntr : 0,
+                               rhoF32 ? rhoF32 + s0 : nullptr));
           CHECK(sp.close());
           CHECK(sp.open(kStageSigma));
           if (x3)
@@ -1069,8 +1124,10 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
             CHECK(stage_sigma_qs32_t<float>(c, nbf, nocc, ns, wh32, w32, eps, Omega + s0, o->eta,
                                             near, V, s0 > 0 ? 1 : 0, &sp));
         } else {
-          CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns, rho, w, &sp, wh, eps,
-                               nocc, o->eta, o->precision));
+          CHECK(stage_residues(c, nbf, naux, ntr, Bmo, Bt, M, Omega, s0, ns,
+                               fold ? rhoF + s0 : rho, w, &sp, wh, eps, nocc, o->eta,
+                               o->precision, nullptr, nullptr, 0.0, nullptr, nullptr, false,
+                               nullptr, fold, fold ? ntr : 0));
           CHECK(sp.close());
           CHECK(sp.open(kStageSigma));
           CHECK(stage_sigma_qs(c, nbf, nocc, ns, w, eps, Omega + s0, o->eta, V, s0 > 0 ? 1 : 0, &sp,
@@ -1393,6 +1450,95 @@ int qsgw_fock_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_
                               c->stream));
   }
   return single_end(c);
+}
+
+int qsgw_iterate_unrestricted(qsgw_ctx* c, const qsgw_problem* p, int64_t nocc_b,
+                              qsgw_state* st_a, qsgw_state* st_b, const qsgw_options* o,
+                              qsgw_report* rep) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  if (!p || !st_a || !st_b || !o) return fail(c, QSGW_ERR_INVALID_ARG, "null argument struct");
+  const int64_t nbf = p->nbf, naux = p->naux, na = p->nocc, nb = nocc_b, nn = nbf * nbf;
+  CHECK(check_common(c, nbf, naux));
+  if (!(na > 0 && na < nbf && nb > 0 && nb < nbf))
+    return fail(c, QSGW_ERR_INVALID_ARG, "need 0 < nocc_a, nocc_b < nbf");
+  if (!p->B_ao || !p->h || !st_a->eps || !st_a->C || !st_b->eps || !st_b->C)
+    return fail(c, QSGW_ERR_INVALID_ARG, "null problem/state pointer");
+  if (!(o->eta > 0.0) || !isfinite(o->eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need eta > 0");
+  if (o->max_iter < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need max_iter >= 1");
+  if (o->precision != QSGW_PREC_FP64 || o->mix != 1.0 || o->fock_mode != QSGW_FOCK_FULL_JK ||
+      o->flags != 0 || o->s_block != 0 || o->warm_start || st_a->Vc || st_b->Vc || st_a->diag ||
+      st_b->diag)
+    return fail(c, QSGW_ERR_UNSUPPORTED,
+                "qsgw_iterate_unrestricted: FP64, mix 1, QSGW_FOCK_FULL_JK, no flags, automatic "
+                "blocks, no warm start and no Vc/diag outputs only");
+  double *Bma, *Bmb, *Va, *Vb, *old;
+  CHECK(ws_get(c, W_BMO, (size_t)(naux * nn), &Bma));
+  CHECK(ws_get(c, W_BMO_B, (size_t)(naux * nn), &Bmb));
+  CHECK(ws_get(c, W_V, (size_t)nn, &Va));
+  CHECK(ws_get(c, W_VB, (size_t)nn, &Vb));
+  CHECK(ws_get(c, W_TMP2, (size_t)(nn > 2 * nbf ? nn : 2 * nbf), &old));
+  qsgw_report local;
+  memset(&local, 0, sizeof(local));
+  {
+    const double b = (double)nbf, a = (double)naux;
+    const double t = (double)(na * (nbf - na) + nb * (nbf - nb));
+    local.hot_flops = 2.0 * 4.0 * b * b * b * a            // Eq. (16), both spins
+                      + t * (t + 1.0) * a + 2.0 * a * t * t  // Casida build and rho' (shared)
+                      + 2.0 * (b * (b + 1.0) * a * t + 2.0 * b * b * b * t)  // residues + Eq. (19)
+                      + b * (b + 1.0) * a * (double)(na + nb) + 2.0 * a * b * b + 16.0 * b * b * b;
+  }
+  auto add_ms = [&](void) -> int {
+    double ms[7];
+    CHECK(qsgw_last_stage_ms(c, ms, 7));
+    for (int i = 0; i < 7; ++i) local.ms_stage[i] += ms[i];
+    return QSGW_OK;
+  };
+  std::vector<double> h_old((size_t)(2 * nbf)), h_new((size_t)(2 * nbf));
+  int status = QSGW_NOT_CONVERGED;
+  for (int64_t it = 0; it < o->max_iter; ++it) {
+    CHECK(qsgw_mo_transform(c, nbf, naux, p->B_ao, st_a->C, Bma, QSGW_PREC_FP64));
+    CHECK(add_ms());
+    CHECK(qsgw_mo_transform(c, nbf, naux, p->B_ao, st_b->C, Bmb, QSGW_PREC_FP64));
+    CHECK(add_ms());
+    CHECK(qsgw_gw_unrestricted(c, nbf, naux, na, nb, Bma, Bmb, st_a->eps, st_b->eps, o->eta, Va,
+                               Vb, nullptr, QSGW_PREC_FP64));
+    CHECK(add_ms());
+    HIP_TRY(c, hipMemcpyAsync(old, st_a->eps, nbf * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(old + nbf, st_b->eps, nbf * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    CHECK(qsgw_fock_unrestricted(c, nbf, naux, na, nb, Bma, Bmb, p->h, Va, Vb, st_a->eps,
+                                 st_b->eps, st_a->C, st_b->C));
+    CHECK(add_ms());
+    HIP_TRY(c, hipMemcpyAsync(h_old.data(), old, 2 * nbf * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(h_new.data(), st_a->eps, nbf * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(h_new.data() + nbf, st_b->eps, nbf * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double d = 0.0;
+    for (int64_t m = 0; m < 2 * nbf; ++m) d = fmax(d, fabs(h_new[(size_t)m] - h_old[(size_t)m]));
+    if (it < QSGW_REPORT_MAX_ITERS) local.max_deps[it] = d;
+    local.iterations = it + 1;
+    ++st_a->iteration;
+    ++st_b->iteration;
+    if (d < o->tol) {
+      status = QSGW_OK;
+      local.converged = 1;
+      break;
+    }
+  }
+  if (rep) *rep = local;
+  return status;
+}
+
+int qsgw_set_eigensolver(qsgw_ctx* c, int solver) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  if (solver != QSGW_EIG_AUTO && solver != QSGW_EIG_ROCSOLVER && solver != QSGW_EIG_TWO_STAGE)
+    return fail(c, QSGW_ERR_INVALID_ARG, "unknown eigensolver %d", solver);
+  c->eig_solver = solver;
+  return QSGW_OK;
 }
 
 int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {

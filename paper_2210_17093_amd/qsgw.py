@@ -39,6 +39,9 @@ OPT_GRAPH = 1
 OPT_REFINE = 2
 OPT_QSMP2 = 4
 OPT_REPLAY_EIG = 8
+EIG_AUTO = 0
+EIG_ROCSOLVER = 1
+EIG_TWO_STAGE = 2
 REPORT_MAX_ITERS = 64
 MLP_NPARAMS = 18817
 MLP_NFEAT = 16
@@ -49,7 +52,8 @@ EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_err
            "qsgw_residues", "qsgw_sigma", "qsgw_mp2_sigma", "qsgw_ao2mo_4center",
            "qsgw_gw_unrestricted", "qsgw_fock_unrestricted", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
-           "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles")
+           "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles",
+           "qsgw_set_eigensolver", "qsgw_iterate_unrestricted")
 
 
 class QsgwError(RuntimeError):
@@ -118,6 +122,8 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_fock_unrestricted": ([P, I64, I64, I64, I64, P, P, P, P, P, P, P, P, P], I),
         "qsgw_iterate": ([P, ct.POINTER(Problem), ct.POINTER(State), ct.POINTER(Options),
                           ct.POINTER(Report)], I),
+        "qsgw_iterate_unrestricted": ([P, ct.POINTER(Problem), I64, ct.POINTER(State),
+                                       ct.POINTER(State), ct.POINTER(Options), ct.POINTER(Report)], I),
         "qsgw_iterate_batched": ([P, I64, ct.POINTER(Problem), ct.POINTER(State),
                                   ct.POINTER(Options), ct.POINTER(Report)], I),
         "qsgw_mlp_features": ([P, I64, I64, P, P, P, P, P], I),
@@ -126,6 +132,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_warm_start": ([P, I64, P, P, P, P, P], I),
         "qsgw_set_tiles": ([P, ct.c_char_p], I),
         "qsgw_get_tiles": ([P, ct.c_char_p, I64], I),
+        "qsgw_set_eigensolver": ([P, I], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -189,6 +196,10 @@ class Context:
     def set_tiles(self, spec: str | None):
         """Tile table of the context (see qsgw_set_tiles); None restores defaults."""
         self.check(lib().qsgw_set_tiles(self.handle, spec.encode() if spec else None))
+
+    def set_eigensolver(self, solver: int):
+        """Casida eigensolver of the context (EIG_AUTO, EIG_ROCSOLVER, EIG_TWO_STAGE)."""
+        self.check(lib().qsgw_set_eigensolver(self.handle, int(solver)))
 
     def get_tiles(self) -> str:
         buf = ct.create_string_buffer(512)
@@ -411,6 +422,26 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))
     return rc, rep.as_dict(), int(st.iteration)
+
+
+def qsgw_iterate_unrestricted(ctx: Context, B_ao, h, nocc_a, nocc_b, eps_a, C_a, eps_b, C_b, eta,
+                              tol=1e-6, max_iter=1, iteration=0):
+    """Open-shell qsGW iterations in place on (eps_a, C_a) and (eps_b, C_b).
+    Returns (status, report dict, iteration)."""
+    naux, nbf, _ = B_ao.shape
+    prob = Problem(nbf, naux, nocc_a, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
+                   _ptr(h, (nbf, nbf), name="h"))
+    sa = State(_ptr(eps_a, (nbf,), name="eps_a"), _ptr(C_a, (nbf, nbf), name="C_a"), None,
+               iteration, None)
+    sb = State(_ptr(eps_b, (nbf,), name="eps_b"), _ptr(C_b, (nbf, nbf), name="C_b"), None,
+               iteration, None)
+    opt = Options(PREC_FP64, float(eta), float(tol), int(max_iter), 1.0, FOCK_FULL_JK, 0, 0, 0.0,
+                  None)
+    rep = Report()
+    rc = ctx.check(lib().qsgw_iterate_unrestricted(ctx.handle, ct.byref(prob), int(nocc_b),
+                                                   ct.byref(sa), ct.byref(sb), ct.byref(opt),
+                                                   ct.byref(rep)), allow=(OK, NOT_CONVERGED))
+    return rc, rep.as_dict(), int(sa.iteration)
 
 
 def qsgw_iterate_batched(ctx: Context, mols, eta, tol=1e-6, max_iter=1, graph=False,

@@ -42,7 +42,7 @@ def test_binding_matches_header():
     for n in declared():
         py = n if n.startswith("qsgw_") else None
         if n in ("qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_error", "qsgw_last_stage_ms",
-                 "qsgw_set_tiles", "qsgw_get_tiles"):
+                 "qsgw_set_tiles", "qsgw_get_tiles", "qsgw_set_eigensolver"):
             continue  # wrapped by the Context class
         if n == "qsgw_sigma":
             assert hasattr(q, "qsgw_sigma_qs") and hasattr(q, "qsgw_sigma_diag")

@@ -171,3 +171,48 @@ def test_unrestricted_full_size_equal_spins(q, ctx):
     assert np.abs(Va - Vr).max() <= 1e-9 * np.abs(Vr).max()
     both = np.sort(np.concatenate([om_r, O.transition_energies(p.eps0, p.nocc)]))
     np.testing.assert_allclose(host(Om), both, rtol=1e-10)
+
+
+@pytest.mark.parametrize("nbf,naux,na,nb", [(24, 96, 5, 4), (37, 53, 9, 8), (30, 80, 3, 1)])
+def test_unrestricted_iterations_match_oracle(q, ctx, nbf, naux, na, nb):
+    """Open-shell iterations through qsgw_iterate_unrestricted against the
+    oracle's open-shell steps chained: every iteration's orbital energies of
+    both spins to 1e-8 Ha, max|d eps| as the oracle's, one call of three
+    iterations equal to three calls of one, and the convergence exit."""
+    print(f"[uhf-iterate] nbf={nbf} naux={naux} nocc=({na}, {nb})", flush=True)
+    eta, iters = 0.05, 3
+    pa = make_problem(nbf, naux, na, max(1, naux // 2), 0.99, nbf, coupling=0.1)
+    pb = make_problem(nbf, naux, nb, max(1, naux // 2), 0.99, nbf + 100, coupling=0.1)
+    h = O.hf_core(pa.B_ao, pa.C0, pa.eps0, na)
+    es, Cs = [pa.eps0, pb.eps0], [pa.C0, pb.C0]
+    refs, deps = [], []
+    for _ in range(iters):
+        new_e, Cs = O.unrestricted_step(pa.B_ao, h, Cs, es, [na, nb], eta)
+        deps.append(max(np.max(np.abs(a - b)) for a, b in zip(new_e, es)))
+        es = new_e
+        refs.append([e.copy() for e in es])
+    Bd, hd = dev(pa.B_ao), dev(h)
+    ea, eb, Ca, Cb = dev(pa.eps0), dev(pb.eps0), dev(pa.C0), dev(pb.C0)
+    it = 0
+    for j in range(iters):
+        rc, rep, it = q.qsgw_iterate_unrestricted(ctx, Bd, hd, na, nb, ea, Ca, eb, Cb, eta,
+                                                  tol=0.0, max_iter=1, iteration=it)
+        assert rc == q.NOT_CONVERGED and rep["iterations"] == 1 and it == j + 1
+        np.testing.assert_allclose(host(ea), refs[j][0], rtol=0, atol=1e-8)
+        np.testing.assert_allclose(host(eb), refs[j][1], rtol=0, atol=1e-8)
+        assert abs(rep["max_deps"][0] - deps[j]) <= 1e-8
+    ea3, eb3, Ca3, Cb3 = dev(pa.eps0), dev(pb.eps0), dev(pa.C0), dev(pb.C0)
+    rc, rep, it = q.qsgw_iterate_unrestricted(ctx, Bd, hd, na, nb, ea3, Ca3, eb3, Cb3, eta,
+                                              tol=0.0, max_iter=iters)
+    assert rep["iterations"] == iters and it == iters
+    np.testing.assert_array_equal(host(ea3), host(ea))
+    np.testing.assert_array_equal(host(eb3), host(eb))
+    np.testing.assert_allclose(rep["max_deps"][:iters], deps, rtol=0, atol=1e-8)
+    # a tolerance above the first change stops after one iteration
+    ea4, eb4, Ca4, Cb4 = dev(pa.eps0), dev(pb.eps0), dev(pa.C0), dev(pb.C0)
+    rc, rep, it = q.qsgw_iterate_unrestricted(ctx, Bd, hd, na, nb, ea4, Ca4, eb4, Cb4, eta,
+                                              tol=deps[0] * 1.5 + 1e-12, max_iter=iters)
+    assert rc == q.OK and rep["converged"] == 1 and rep["iterations"] == 1
+    with pytest.raises(q.QsgwError) as x:
+        q.qsgw_iterate_unrestricted(ctx, Bd, hd, na, nbf, ea4, Ca4, eb4, Cb4, eta)
+    assert x.value.code == q.ERR_INVALID_ARG
