@@ -211,6 +211,23 @@ int qsgw_sigma(qsgw_ctx* ctx, int mode, int64_t nbf, int64_t nocc, int64_t ns, c
                double* out, int accumulate);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * QSGW_SIGMA_QS_MATRIX mode of qsgw_sigma (same arguments, same result up to
+ * the rounding order of its K-split) without any allocation.  Its split-K
+ * partial sums and its finite-input flag live in one static device array of
+ * 64 MiB that the library holds on every device it runs on until the process
+ * ends; the K-split is capped at what it holds (at most 64 slices), so nbf is
+ * limited to 2896 (QSGW_ERR_INVALID_ARG above).  The call still synchronizes
+ * once to read the finite-input flag, and records no stage times.  All calls
+ * on one device share that array: calls that overlap on one device (two
+ * contexts or streams at once) race and must be serialized by the caller.
+ */
+int qsgw_sigma_qs_noalloc(qsgw_ctx* ctx, int64_t nbf, int64_t nocc, int64_t ns, const double* w,
+                          const double* wh, const double* eps, const double* Omega, double eta,
+                          double* out, int accumulate);
+
+/*
  * qsMP2 potential: the correlation part of the MP2 self-energy, Eq. (20),
  * made Hermitian as in Eq. (21); closed shell, real orbitals:
  *   V[m][n] (+)= 1/2 Re[Sigma_mn(eps_n) + Sigma_nm(eps_m)],

@@ -154,8 +154,14 @@ struct qsgw_ctx {
   bool eig_fold = false;
   // solver of the Casida eigenproblems (QSGW_EIG_*)
   int eig_solver = QSGW_EIG_AUTO;
+  // this device's copy of the allocation-free entry point's static scratch
+  // array (noalloc.hip), null if the lookup failed
+  double* scratch = nullptr;
 };
 
+// Looks up the device address of the static scratch array of the
+// allocation-free entry point for the context's device (noalloc.hip).
+int noalloc_setup(qsgw_ctx* c);
 
 // Two-stage dense symmetric eigensolver (eig2s.hip): A [n][n] in, its
 // eigenvectors column-major out, eigenvalues ascending.

@@ -668,6 +668,9 @@ int qsgw_ctx_create(qsgw_ctx** out, void* hip_stream) {
     delete c;
     return QSGW_ERR_SOLVER;
   }
+  // the allocation-free entry point reports a failed lookup itself
+  if (noalloc_setup(c) != QSGW_OK) c->scratch = nullptr;
+  c->err.clear();
   *out = c;
   return QSGW_OK;
 }

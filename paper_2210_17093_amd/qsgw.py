@@ -53,7 +53,7 @@ EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_err
            "qsgw_gw_unrestricted", "qsgw_fock_unrestricted", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
            "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles",
-           "qsgw_set_eigensolver", "qsgw_iterate_unrestricted")
+           "qsgw_set_eigensolver", "qsgw_sigma_qs_noalloc", "qsgw_iterate_unrestricted")
 
 
 class QsgwError(RuntimeError):
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "qsgw_set_tiles": ([P, ct.c_char_p], I),
         "qsgw_get_tiles": ([P, ct.c_char_p, I64], I),
         "qsgw_set_eigensolver": ([P, I], I),
+        "qsgw_sigma_qs_noalloc": ([P, I64, I64, I64, P, P, P, P, D, P, I], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -290,6 +291,20 @@ def qsgw_sigma_qs(ctx: Context, w, eps, Omega_block, nocc, eta, out=None, accumu
                                _ptr(eps, (nbf,), name="eps"),
                                _ptr(Omega_block, (ns,), name="Omega"), float(eta), None, 0, None, 0,
                                _ptr(out, (nbf, nbf), name="out"), int(bool(accumulate))))
+    return out
+
+
+def qsgw_sigma_qs_noalloc(ctx: Context, w, eps, Omega_block, nocc, eta, out, accumulate=False,
+                          wh=None):
+    """qsGW matrix (QSGW_SIGMA_QS_MATRIX) through the allocation-free entry
+    point: `out` must be given (the call allocates nothing)."""
+    nbf, _, ns = w.shape
+    ctx.check(lib().qsgw_sigma_qs_noalloc(ctx.handle, nbf, nocc, ns,
+                                          _ptr(w, (nbf, nbf, ns), name="w"),
+                                          _ptr(wh, (nbf, nbf, ns), name="wh") if wh is not None else None,
+                                          _ptr(eps, (nbf,), name="eps"),
+                                          _ptr(Omega_block, (ns,), name="Omega"), float(eta),
+                                          _ptr(out, (nbf, nbf), name="out"), int(bool(accumulate))))
     return out
 
 
