@@ -132,7 +132,7 @@ int qsgw_rpa_build(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const
  * context with qsgw_set_eigensolver.  They apply to qsgw_rpa_solve and to the
  * Casida eigensolves inside qsgw_iterate and qsgw_gw_unrestricted (the Fock
  * eigensolves and the batched path always use rocSOLVER dsyevd). */
-#define QSGW_EIG_AUTO 0      /* the two-stage solver for n >= 2048, dsyevd below (default) */
+#define QSGW_EIG_AUTO 0      /* the two-stage solver for n >= 8192, dsyevd below (default) */
 #define QSGW_EIG_ROCSOLVER 1 /* rocSOLVER dsyevd (one-stage tridiagonal reduction) */
 /* Two-stage reduction, all FP64: dense -> band of half-width 64 by blocked
  * Householder panels whose two-sided updates are matrix products, band ->

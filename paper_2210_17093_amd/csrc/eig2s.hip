@@ -45,6 +45,216 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Householder QR of one panel (m x b, column-major, ld lda), one launch per
+// column j with a partition of the rows over the workgroups (kPanelRows
+// rows each).  Column j's reflector needs dots[c] = sum_{r > j} P[r][j] P[r][c]
+// (c >= j) of the current panel: the launch for column j - 1 leaves one
+// partial sum per workgroup (part_in[g][c]) and every workgroup of the launch
+// for column j adds them up in a fixed order.  Then, with the LAPACK dlarfg
+// convention (v_j = 1, beta = -sign(alpha) |x|, tau = (beta - alpha) / beta),
+//   w_c = P[j][c] + dots[c] / (alpha - beta)      (w = v^T P[:, c]),
+//   P[r][j] <- v_r = P[r][j] / (alpha - beta),  P[r][c] -= tau v_r w_c  (r > j, c > j),
+// and row j of R goes to Rbuf (P's row j is left as it was: every workgroup
+// reads it).  Each workgroup then leaves its partial dots for column j + 1.
+// j = -1 only computes the partial dots of column 0.
+constexpr int kPanelRows = 512;
+__global__ __launch_bounds__(256) void k_panel_col(double* __restrict__ P, int64_t lda, int64_t m,
+                                                   int b, int j, const double* __restrict__ part_in,
+                                                   double* __restrict__ part_out, int G,
+                                                   double* __restrict__ Rbuf,
+                                                   double* __restrict__ tau) {
+  __shared__ double wv[kBand];
+  __shared__ double sc[3];
+  __shared__ double red[4][kBand];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x;
+  const int64_t rbase = (int64_t)g * kPanelRows;
+  constexpr int RPT = kPanelRows / 256;
+  if (j >= 0) {
+    // column j's dots from the previous launch's partial sums
+    if (tid < kBand) {
+      double s2 = 0.0;
+      if (tid >= j && tid < b)
+        for (int h = 0; h < G; ++h) s2 += part_in[(int64_t)h * kBand + tid];
+      wv[tid] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double alpha = P[(int64_t)j * lda + j];
+      const double sig = wv[j];
+      if (sig == 0.0) {
+        sc[0] = 0.0;
+        sc[1] = alpha;
+        sc[2] = 0.0;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+        sc[0] = (beta - alpha) / beta;
+        sc[1] = beta;
+        sc[2] = 1.0 / (alpha - beta);
+      }
+    }
+    __syncthreads();
+    const double t = sc[0], scale = sc[2];
+    double wc = 0.0;
+    if (tid > j && tid < b) wc = P[(int64_t)tid * lda + j] + scale * wv[tid];
+    __syncthreads();
+    if (tid < kBand) wv[tid] = wc;
+    __syncthreads();
+    if (g == 0 && tid < kBand) {  // row j of R, and tau
+      if (tid == j) Rbuf[(int64_t)j * kBand + j] = sc[1];
+      if (tid > j && tid < b) Rbuf[(int64_t)j * kBand + tid] = P[(int64_t)tid * lda + j] - t * wv[tid];
+      if (tid == 0) tau[j] = t;
+    }
+    // rows r > j of this workgroup: v_r into column j, the other columns updated
+    double v[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int64_t r = rbase + tid + 256 * u;
+      v[u] = 0.0;
+      if (r > j && r < m) {
+        v[u] = P[(int64_t)j * lda + r] * scale;
+        P[(int64_t)j * lda + r] = v[u];
+      }
+    }
+    if (t != 0.0) {
+      // columns in chunks of 8: all loads of a chunk first, then the stores
+      for (int c0 = j + 1; c0 < b; c0 += 8) {
+        double x[8][RPT];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int64_t r = rbase + tid + 256 * u;
+            x[cc][u] = (c0 + cc < b && r > j && r < m) ? P[(int64_t)(c0 + cc) * lda + r] : 0.0;
+          }
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          if (c0 + cc >= b) break;
+          const double tw = t * wv[c0 + cc];
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) {
+            const int64_t r = rbase + tid + 256 * u;
+            if (r > j && r < m) P[(int64_t)(c0 + cc) * lda + r] = x[cc][u] - tw * v[u];
+          }
+        }
+      }
+    }
+  }
+  // partial dots of column j + 1 over this workgroup's rows r > j + 1
+  const int jn = j + 1;
+  if (jn >= b || jn >= m - 1) return;  // (uniform) no further column to factor here
+  double pj[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int64_t r = rbase + tid + 256 * u;
+    pj[u] = (r > jn && r < m) ? P[(int64_t)jn * lda + r] : 0.0;
+  }
+  for (int c0 = jn; c0 < b; c0 += 8) {
+    double x[8][RPT];
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int64_t r = rbase + tid + 256 * u;
+        x[cc][u] = (c0 + cc < b && r > jn && r < m) ? P[(int64_t)(c0 + cc) * lda + r] : 0.0;
+      }
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) s2 += pj[u] * x[cc][u];
+      s2 = wave_sum(s2);
+      if (lane == 0 && c0 + cc < b) red[wave][c0 + cc] = s2;
+    }
+  }
+  __syncthreads();
+  if (tid < kBand)
+    part_out[(int64_t)g * kBand + tid] =
+        (tid >= jn && tid < b) ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
+}
+
+// R (rows q < b of the panel, columns c >= q) from Rbuf into the panel's upper triangle.
+__global__ void k_panel_r(double* __restrict__ P, int64_t lda, int b, const double* __restrict__ Rbuf) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= b * b) return;
+  const int q = idx / b, c = idx - q * b;
+  if (c >= q) P[(int64_t)c * lda + q] = Rbuf[(int64_t)q * kBand + c];
+}
+
+// T factor of a panel's k reflectors from their Gram matrix G[i][j] = v_i . v_j
+// (row-major, ld k) and tau, one workgroup: T[j][j] = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j] (the forward, column-wise
+// convention: H_0 H_1 ... H_{k-1} = I - V T V^T); T column-major, ld ldt.
+__global__ __launch_bounds__(256) void k_panel_t(const double* __restrict__ G, int k,
+                                                 const double* __restrict__ tau,
+                                                 double* __restrict__ T, int ldt) {
+  __shared__ double Ts[kBand][kBand + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kBand * kBand; e += 256) Ts[e / kBand][e % kBand] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid < j) {
+      double sum = 0.0;
+      for (int l = tid; l < j; ++l) sum += Ts[tid][l] * G[l * k + j];
+      Ts[tid][j] = -tau[j] * sum;
+    } else if (tid == j) {
+      Ts[j][j] = tau[j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < ldt * ldt; e += 256) {
+    const int col = e / ldt, row = e - col * ldt;
+    T[e] = (row < kBand && col < kBand) ? Ts[row][col] : 0.0;
+  }
+}
+
+// W = X - 1/2 V Z2 for the panel update, written straight into the second
+// half of U1 = [V W] and the first half of U2 = [W V] (both column-major,
+// ld m): the element (c, r) of the product W^T handed by the GEMM engine.
+struct EpiPanelW {
+  const double* X;
+  double* U1w;
+  double* U2w;
+  int64_t m;
+  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t c, int64_t r, double v,
+                                             bool) const {
+    const double w = X[c * m + r] - 0.5 * v;
+    U1w[c * m + r] = w;
+    U2w[c * m + r] = w;
+  }
+};
+
+// A product C[i][c] = sum_r A(i, r) B(c, r) with a long k = r and a small
+// output, split over k (partials summed in a fixed order) when that fills
+// the chip better; C row-major, ld N.
+template <class OA, class OB>
+static int gemm_long_k(qsgw_ctx* c, const char* what, OA A, OB B, double* C, int64_t M, int64_t N,
+                       int64_t K) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  const SplitPlan sp = split_plan(K, splits_for(tiles, K, 2048));
+  if (sp.nz > 1) {
+    double* part = nullptr;
+    CHECK(ws_get(c, W_EIG_XP, (size_t)(sp.nz * M * N), &part));
+    EpiStore E{part, N, 0, M * N, 1.0};
+    CHECK((gemm_shape<double, false>(c, SH_64x64, what, A, B, E, M, N, K, 1, sp)));
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(M * N)), dim3(256), 0, c->stream, part, sp.nz,
+                       M * N, sp.nz, C);
+    return launch_check(c, "k_sum_slices");
+  }
+  EpiStore E{C, N, 0, 0, 1.0};
+  return gemm_shape<double, false>(c, SH_64x64, what, A, B, E, M, N, K, 1);
+}
+
+// X[m][n] -= v (a plain product subtracted from its output).
+struct EpiSub {
+  double* X;
+  int64_t ld;
+  __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t m, int64_t n, double v,
+                                             bool) const {
+    X[m * ld + n] -= v;
+  }
+};
+
 // Copies the panel's Householder vectors (below the diagonal of the geqrf
 // output, unit diagonal implied) into V [m][kk] column-major (ld m) with an
 // explicit unit diagonal and zeros above it, and into the concatenated
@@ -106,95 +316,120 @@ __device__ void householder(const double* x, int L, double* v, double* sc) {
   __syncthreads();
 }
 
-// One bulge-chasing step (i, k) with k = t - 3 i, one workgroup each.
+// Shared memory of one bulge-chasing step.
+struct BulgeSmem {
+  double O[kBand][kBand + 1];
+  double D[kBand][kBand + 1];
+  double v[kBand], vp[kBand], y[kBand], z[kBand], x[kBand];
+  double sc[4];
+};
+
+// One bulge-chasing step (i, k), the whole workgroup (256 threads).
 // AB: lower band storage, AB[c * ldab + d] = A[c + d][c], ldab >= 2b.
 // V2/tau2: the reflector of step (i, k) at V2[(off[i] + k) * b], tau2[off[i] + k].
-__global__ __launch_bounds__(256) void k_bulge(double* __restrict__ AB, int64_t ldab, int64_t n,
-                                               int b, double* __restrict__ V2,
-                                               double* __restrict__ tau2,
-                                               const int64_t* __restrict__ off, int64_t t,
-                                               int64_t i_lo) {
-  const int64_t i = i_lo + blockIdx.x;
-  const int64_t k = t - 3 * i;
-  if (i > n - 3 || k < 0) return;
-  const int64_t K = (n - 1 - i + b - 1) / b;
-  if (k >= K) return;
-  __shared__ double O[kBand][kBand + 1];
-  __shared__ double D[kBand][kBand + 1];
-  __shared__ double v[kBand], vp[kBand], y[kBand], x[kBand];
-  __shared__ double sc[4];
+// Both blocks (the bulge O in the band columns of the previous window, the
+// diagonal block D in the columns of this one) are loaded at once: they are
+// disjoint.  Global loads and stores run with consecutive threads on
+// consecutive rows of a band column.
+__device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int b,
+                           double* __restrict__ V2, double* __restrict__ tau2,
+                           const int64_t* __restrict__ off, int64_t i, int64_t k, BulgeSmem& sm) {
+  double (*O)[kBand + 1] = sm.O;
+  double (*D)[kBand + 1] = sm.D;
+  double *v = sm.v, *vp = sm.vp, *y = sm.y, *z = sm.z, *x = sm.x, *sc = sm.sc;
   const int tid = threadIdx.x;
   const int q = tid & 3, rr = tid >> 2;  // 4 lanes per row (or column) rr
   const int64_t r0 = i + 1 + k * b;
   const int64_t r1 = min(i + (k + 1) * b, n - 1);
   const int L = (int)(r1 - r0 + 1);
+  const int64_t p0 = i + 1 + (k - 1) * b;  // previous window (k >= 1; always b long)
 
+  // ---- loads (all issued before any LDS store) ----
+  constexpr int EPT = kBand * kBand / 256;  // elements per thread
+  {
+    double dv[EPT], ov[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
+      dv[u] = (a >= c && a < L) ? AB[(r0 + c) * ldab + (a - c)] : 0.0;
+      ov[u] = (k > 0 && a < L && c < b) ? AB[(p0 + c) * ldab + (b + a - c)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
+      if (a >= c) D[a][c] = dv[u];
+      O[a][c] = ov[u];
+    }
+  }
   if (k == 0) {
     if (tid < kBand) x[tid] = tid < L ? AB[i * ldab + 1 + tid] : 0.0;
-    __syncthreads();
-    householder(x, L, v, sc);
-    if (tid < L) AB[i * ldab + 1 + tid] = tid == 0 ? sc[1] : 0.0;
   } else {
-    const int64_t p0 = i + 1 + (k - 1) * b;  // the previous window (always b long)
-    for (int e = tid; e < kBand * kBand; e += 256) {
-      const int c = e / kBand, a = e - c * kBand;  // consecutive threads: consecutive rows
-      O[a][c] = (a < L && c < b) ? AB[(p0 + c) * ldab + (b + a - c)] : 0.0;
-    }
     if (tid < kBand) vp[tid] = tid < b ? V2[(off[i] + k - 1) * b + tid] : 0.0;
     if (tid == 0) sc[3] = tau2[off[i] + k - 1];
-    __syncthreads();
-    // O <- O (I - taup vp vp^T)
-    {
-      double s = 0.0;
-      for (int c = q; c < kBand; c += 4) s += O[rr][c] * vp[c];
-      s = quad_sum(s);
-      if (q == 0) y[rr] = s;
+  }
+  __syncthreads();
+  {
+    double mv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
+      mv[u] = a < c ? D[c][a] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
+      if (a < c) D[a][c] = mv[u];
+    }
+  }
+  if (k > 0) {
+    // O <- O (I - taup vp vp^T); its first column is the vector to annihilate
+    double s = 0.0;
+    for (int c = q; c < kBand; c += 4) s += O[rr][c] * vp[c];
+    s = quad_sum(s);
+    if (q == 0) y[rr] = s;
     __syncthreads();
     const double taup = sc[3];
-    for (int e = tid; e < kBand * kBand; e += 256) {
+    double ov[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
       const int a = e / kBand, c = e - a * kBand;
-      O[a][c] -= taup * y[a] * vp[c];
+      ov[u] = O[a][c] - taup * y[a] * vp[c];
     }
-    __syncthreads();
-    if (tid < kBand) x[tid] = O[tid][0];
-    __syncthreads();
-    householder(x, L, v, sc);
-    const double tau = sc[0];
-    // first column -> beta e_1; the other columns <- H O
-    {
-      double s = 0.0;
-      for (int a = q; a < kBand; a += 4) s += v[a] * O[a][rr];
-      s = quad_sum(s);
-      if (q == 0) y[rr] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < kBand * kBand; e += 256) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
       const int a = e / kBand, c = e - a * kBand;
-      if (c == 0)
-        O[a][0] = a == 0 ? sc[1] : 0.0;
-      else
-        O[a][c] -= tau * v[a] * y[c];
+      O[a][c] = ov[u];
+      if (c == 0) x[a] = ov[u];
     }
+  }
+  __syncthreads();
+  householder(x, L, v, sc);  // v, sc[0] = tau, sc[1] = beta
+  const double tau = sc[0];
+  if (k == 0) {
+    if (tid < L) AB[i * ldab + 1 + tid] = tid == 0 ? sc[1] : 0.0;
+  } else {
+    // first column -> beta e_1, the other columns <- H O; written back
+    double s = 0.0;
+    for (int a = q; a < kBand; a += 4) s += v[a] * O[a][rr];
+    s = quad_sum(s);
+    if (q == 0) z[rr] = s;
     __syncthreads();
+    const double beta = sc[1];
     for (int e = tid; e < kBand * kBand; e += 256) {
       const int c = e / kBand, a = e - c * kBand;
-      if (a < L && c < b) AB[(p0 + c) * ldab + (b + a - c)] = O[a][c];
+      if (a < L && c < b) {
+        const double val = c == 0 ? (a == 0 ? beta : 0.0) : O[a][c] - tau * v[a] * z[c];
+        AB[(p0 + c) * ldab + (b + a - c)] = val;
+      }
     }
   }
-  // diagonal block D <- H D H on rows/columns r0..r1
-  // lower triangle from the band (consecutive threads: consecutive rows), then mirrored
-  for (int e = tid; e < kBand * kBand; e += 256) {
-    const int c = e / kBand, a = e - c * kBand;
-    if (a >= c) D[a][c] = (a < L) ? AB[(r0 + c) * ldab + (a - c)] : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < kBand * kBand; e += 256) {
-    const int c = e / kBand, a = e - c * kBand;
-    if (a < c) D[a][c] = D[c][a];
-  }
-  __syncthreads();
-  const double tau = sc[0];
+  // diagonal block D <- H D H
   {
     double s = 0.0;
     for (int c = q; c < kBand; c += 4) s += D[rr][c] * v[c];
@@ -217,6 +452,21 @@ __global__ __launch_bounds__(256) void k_bulge(double* __restrict__ AB, int64_t 
   }
   if (tid < b) V2[(off[i] + k) * b + tid] = v[tid];
   if (tid == 0) tau2[off[i] + k] = tau;
+}
+
+// Step k = t - 3 i of every sweep i of time t, one workgroup each (one launch per time).
+__global__ __launch_bounds__(256) void k_bulge(double* __restrict__ AB, int64_t ldab, int64_t n,
+                                               int b, double* __restrict__ V2,
+                                               double* __restrict__ tau2,
+                                               const int64_t* __restrict__ off, int64_t t,
+                                               int64_t i_lo) {
+  const int64_t i = i_lo + blockIdx.x;
+  const int64_t k = t - 3 * i;
+  if (i > n - 3 || k < 0) return;
+  const int64_t K = (n - 1 - i + b - 1) / b;
+  if (k >= K) return;
+  __shared__ BulgeSmem sm;
+  bulge_step(AB, ldab, n, b, V2, tau2, off, i, k, sm);
 }
 
 // Compact WY factor of block (J, k) of the bulge-chasing reflectors: with V
@@ -281,9 +531,15 @@ __global__ __launch_bounds__(256) void k_q2_tfactor(const double* __restrict__ V
 //            down; anti-diagonals in ascending order give X <- Q2 X);
 //   trans 1: B = I - V T^T V^T (lowest sweep first; anti-diagonals in
 //            descending order give X <- Q2^T X).
-// The block touches rows [J g + 1 + k b, J g + g - 1 + (k + 1) b] of X.
+// The block touches rows [J g + 1 + k b, J g + g - 1 + (k + 1) b] of X.  The
+// three products W = V^T X_b, W2 = T W (or T^T W) and X_b -= V W2 run on the
+// FP64 matrix cores (v_mfma_f64_16x16x4: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16], accumulator element q is D[4 q + l / 16][l % 16]), V
+// entries generated from the compact reflector rows (zero outside a
+// reflector's b rows).
 constexpr int kSlabW = 32;
 constexpr int kRows = 2 * kBand;  // b + g - 1 rows, padded
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_t n, int64_t ncols,
                                                   int b, const double* __restrict__ V2,
                                                   const int64_t* __restrict__ off,
@@ -299,11 +555,10 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
   const int64_t c_lo = J * g;
   const int64_t c_hi = min(c_lo + g, n - 2) - 1;
   if (c_hi < c_lo || k >= (n - 1 - c_lo + b - 1) / b) return;
-  __shared__ double Eb[kRows][kSlabW + 1];
+  __shared__ double Xb[kRows][kSlabW + 1];
   __shared__ double Vb[kBand][kBand + 1];
   __shared__ double Ts[kBand][kBand + 1];
   __shared__ double W[kBand][kSlabW + 1];
-  __shared__ double W2[kBand][kSlabW + 1];
   const int tid = threadIdx.x;
   const int64_t R0 = c_lo + 1 + k * b;
   const int64_t R1 = min(c_hi + (k + 1) * b, n - 1);
@@ -312,7 +567,7 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
   const int ncol = (int)min((int64_t)kSlabW, ncols - col0);
   for (int e = tid; e < kSlabW * kRows; e += 256) {
     const int cl = e / kRows, r = e - cl * kRows;  // consecutive threads: consecutive rows
-    Eb[r][cl] = (cl < ncol && r < NR) ? X[(col0 + cl) * n + R0 + r] : 0.0;
+    Xb[r][cl] = (cl < ncol && r < NR) ? X[(col0 + cl) * n + R0 + r] : 0.0;
   }
   const double* Tg = Tb + (boff[J] + k) * (kBand * kBand);
   for (int e = tid; e < kBand * kBand; e += 256) {
@@ -323,64 +578,80 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     Ts[o][a] = Tg[e];
   }
   __syncthreads();
-  const int cl = tid & (kSlabW - 1), grp = tid / kSlabW;  // 8 groups of 8 reflectors
-  // W = V^T X_block: W[o][c] = sum_a Vb[o][a] Eb[o + a][c]
+  const int lane = tid & 63, w = tid >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
+  // V(r, o): reflector o covers block rows o .. o + b - 1
+  auto vat = [&](int r, int o) -> double {
+    const int a = r - o;
+    return (a >= 0 && a < kBand) ? Vb[o][a] : 0.0;
+  };
+  // W = V^T X_b: wave w owns rows o of tile w, both column tiles; k = r
   {
-    double acc[8], e8[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      acc[u] = 0.0;
-      e8[u] = Eb[grp * 8 + u][cl];
-    }
-    for (int a = 0; a < kBand; ++a) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += Vb[grp * 8 + u][a] * e8[u];
-#pragma unroll
-      for (int u = 0; u < 7; ++u) e8[u] = e8[u + 1];
-      e8[7] = Eb[grp * 8 + 8 + a][cl];  // row grp*8 + 7 + (a + 1) <= 127
+    f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int o = 16 * w + lm;
+    const int ks_hi = min(kRows / 4 - 1, (16 * w + 15 + kBand - 1) / 4);
+    for (int ks = 4 * w; ks <= ks_hi; ++ks) {
+      const int r = 4 * ks + lk;
+      const double av = vat(r, o);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][lm], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][16 + lm], acc1, 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) W[grp * 8 + u][cl] = acc[u];
+    for (int q = 0; q < 4; ++q) {
+      W[16 * w + 4 * q + lk][lm] = acc0[q];
+      W[16 * w + 4 * q + lk][16 + lm] = acc1[q];
+    }
   }
   __syncthreads();
-  // W2 = T W or T^T W
+  // W2 = T W or T^T W (T upper triangular), back into W
   {
-    double acc[8];
+    f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int i = 16 * w + lm;
+    const int ks_lo = trans ? 0 : 4 * w, ks_hi = trans ? 4 * w + 3 : kBand / 4 - 1;
+    for (int ks = ks_lo; ks <= ks_hi; ++ks) {
+      const int j = 4 * ks + lk;
+      const double av = trans ? Ts[j][i] : Ts[i][j];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][lm], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][16 + lm], acc1, 0, 0, 0);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    for (int j = 0; j < kBand; ++j) {
-      const double wj = W[j][cl];
+    for (int q = 0; q < 4; ++q) {
+      W[16 * w + 4 * q + lk][lm] = acc0[q];
+      W[16 * w + 4 * q + lk][16 + lm] = acc1[q];
+    }
+  }
+  __syncthreads();
+  // X_b -= V W2: wave w owns row tiles 2w, 2w + 1, both column tiles; k = o
+  {
+    f64x4_t acc[2][2];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = grp * 8 + u;
-        acc[u] += (trans ? Ts[j][i] : Ts[i][j]) * wj;
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < kBand / 4; ++ks) {
+      const int o = 4 * ks + lk;
+      const double b0 = W[o][lm], b1 = W[o][16 + lm];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double av = vat(16 * (2 * w + u) + lm, o);
+        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[u][0], 0, 0, 0);
+        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[u][1], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) W2[grp * 8 + u][cl] = acc[u];
-  }
-  __syncthreads();
-  // X_block -= V W2: row r gets sum over o with 0 <= r - o < b of Vb[o][r - o] W2[o][c]
-  {
-    double acc[16];
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    for (int o = 0; o < kBand; ++o) {
-      const double w2 = W2[o][cl];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int a = grp * 16 + u - o;
-        const double v = (a >= 0 && a < kBand) ? Vb[o][a & (kBand - 1)] : 0.0;
-        acc[u] += v * w2;
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * (2 * w + u) + 4 * q + lk;
+        Xb[r][lm] -= acc[u][0][q];
+        Xb[r][16 + lm] -= acc[u][1][q];
       }
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) Eb[grp * 16 + u][cl] -= acc[u];
   }
   __syncthreads();
   for (int e = tid; e < kSlabW * kRows; e += 256) {
     const int c2 = e / kRows, r = e - c2 * kRows;
-    if (c2 < ncol && r < NR) X[(col0 + c2) * n + R0 + r] = Eb[r][c2];
+    if (c2 < ncol && r < NR) X[(col0 + c2) * n + R0 + r] = Xb[r][c2];
   }
 }
 
@@ -431,7 +702,6 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
   Z1 = Y + n * b;
   Z2 = Z1 + b * b;
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
-  const double one = 1.0, zero = 0.0, mone = -1.0, mhalf = -0.5;
   for (int64_t p = 0; p < np; ++p) {
     const int64_t j = ts->pj[p], m = ts->pm[p], kk = m < b ? m : b;
     const int mi = (int)m, ki = (int)kk;
@@ -439,30 +709,72 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
     double* S = A + (j + b) * n + (j + b);
     double* V = V1 + ts->poff[p];
     double* T = T1 + p * b * b;
-    RB_TRY(c, rocsolver_dgeqrf(h, mi, b, P, ni, tau1 + p * b), what);
+    if (m >= 2 * b) {
+      // one launch per column (see k_panel_col)
+      const int G = (int)((m + kPanelRows - 1) / kPanelRows);
+      double *part, *Rbuf;
+      CHECK(ws_get(c, W_EIG_PANEL, (size_t)(2 * G * b + b * b), &part));
+      Rbuf = part + 2 * G * b;
+      for (int jc = -1; jc < b; ++jc)
+        hipLaunchKernelGGL(k_panel_col, dim3((unsigned)G), dim3(256), 0, c->stream, P, n, m, b, jc,
+                           part + (size_t)((jc + 2) & 1) * G * b, part + (size_t)((jc + 1) & 1) * G * b,
+                           G, Rbuf, tau1 + p * b);
+      hipLaunchKernelGGL(k_panel_r, dim3(blocks_for(b * b)), dim3(256), 0, c->stream, P, n, b, Rbuf);
+      CHECK(launch_check(c, "k_panel_col"));
+    } else {
+      RB_TRY(c, rocsolver_dgeqrf(h, mi, b, P, ni, tau1 + p * b), what);
+    }
     hipLaunchKernelGGL(k_panel_v, dim3(blocks_for(m * kk)), dim3(256), 0, c->stream, P, n, m, kk,
                        V, U1, U2);
     CHECK(launch_check(c, "k_panel_v"));
-    RB_TRY(c, rocsolver_dlarft(h, rocblas_forward_direction, rocblas_column_wise, mi, ki, V, mi,
-                               tau1 + p * b, T, b), what);
-    // Y = V T;  X = S Y;  Z1 = V^T X;  Z2 = T^T Z1;  W = X - 1/2 V Z2 (in X)
-    RB_TRY(c, rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mi, ki, ki, &one, V,
-                            mi, T, b, &zero, Y, mi), what);
-    RB_TRY(c, rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mi, ki, mi, &one, S,
-                            ni, Y, mi, &zero, X, mi), what);
-    RB_TRY(c, rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, ki, ki, mi, &one,
-                            V, mi, X, mi, &zero, Z1, b), what);
-    RB_TRY(c, rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, ki, ki, ki, &one,
-                            T, b, Z1, b, &zero, Z2, b), what);
-    RB_TRY(c, rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, mi, ki, ki, &mhalf, V,
-                            mi, Z2, b, &one, X, mi), what);
-    // S -= [V W] [W V]^T
-    HIP_TRY(c, hipMemcpyAsync(U1 + kk * m, X, (size_t)(m * kk) * sizeof(double),
-                              hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(U2, X, (size_t)(m * kk) * sizeof(double), hipMemcpyDeviceToDevice,
-                              c->stream));
-    RB_TRY(c, rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, mi, mi, 2 * ki,
-                            &mone, U1, mi, U2, mi, &one, S, ni), what);
+    // T from the reflectors' Gram matrix (V^T V, long k = m) and tau
+    {
+      Strided<true> Av{V, m, 1, 0, kk};
+      CHECK(gemm_long_k(c, "eig/sy2sb gram", Av, Av, Z1, kk, kk, m));
+      hipLaunchKernelGGL(k_panel_t, dim3(1), dim3(256), 0, c->stream, Z1, (int)kk, tau1 + p * b, T,
+                         b);
+      CHECK(launch_check(c, "k_panel_t"));
+    }
+    // Y = V T  (Y^T[c][r] = sum_l T(l, c) V(r, l))
+    {
+      Strided<true> At{T, b, 1, 0, kk};
+      Strided<false> Bv{V, 1, m, 0, m};
+      EpiStore E{Y, m, 0, 0, 1.0};
+      CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb Y", At, Bv, E, kk, m, kk, 1)));
+    }
+    // X = S Y  (X^T[c][r] = sum_k Y[k][c] S[k][r], S symmetric), split over k
+    {
+      Strided<true> Ay{Y, m, 1, 0, kk};
+      Strided<true> Bs{S, n, 1, 0, m};
+      CHECK(gemm_long_k(c, "eig/sy2sb X", Ay, Bs, X, kk, m, m));
+    }
+    // Z1 = V^T X  (Z1[i][c] = sum_r V(r, i) X(r, c)), Z2 = T^T Z1
+    {
+      Strided<true> Av{V, m, 1, 0, kk};
+      Strided<true> Bx{X, m, 1, 0, kk};
+      CHECK(gemm_long_k(c, "eig/sy2sb Z1", Av, Bx, Z1, kk, kk, m));
+      Strided<true> At{T, b, 1, 0, kk};
+      Strided<false> Bz{Z1, 1, kk, 0, kk};
+      EpiStore E{Z2, kk, 0, 0, 1.0};
+      CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb Z2", At, Bz, E, kk, kk, kk, 1)));
+    }
+    // W = X - 1/2 V Z2 into U1[:, kk:] and U2[:, :kk]  (W^T[c][r] = X - 1/2 sum_l Z2[l][c] V(r, l))
+    {
+      Strided<false> Az{Z2, 1, kk, 0, kk};
+      Strided<false> Bv{V, 1, m, 0, m};
+      EpiPanelW E{X, U1 + kk * m, U2, m};
+      CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb W", Az, Bv, E, kk, m, kk, 1)));
+    }
+    {
+      // S -= U1 U2^T over the whole square: every tile writes its own rows
+      // (mirrored writes of the upper-tile form would be transposed, uncoalesced
+      // read-modify-writes)
+      Strided<false> A1{U1, 1, m, 0, m};
+      Strided<false> A2{U2, 1, m, 0, m};
+      EpiSub E{S, n};
+      CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/sy2sb update", A1, A2, E, m, m, 2 * kk,
+                                       1)));
+    }
   }
 
   // ---- stage 2: band -> tridiagonal ----
@@ -544,13 +856,49 @@ static int ts_apply(qsgw_ctx* c, const TwoStage& ts, int64_t n, double* X, int64
                        c->stream, X, n, ncols, b, ts.V2, ts.off, ts.Tb, ts.off + n, t, ts.nJ, J_lo,
                        nslab, trans ? 1 : 0);
   };
+  double *W1 = nullptr, *W2 = nullptr, *WP = nullptr;
+  CHECK(ws_get(c, W_EIG_Q1W, (size_t)(2 * b * ncols), &W1));
+  W2 = W1 + b * ncols;
+  // X[j+b:, :] <- (I - V T V^T) X (trans false) or (I - V T^T V^T) X (trans true),
+  // as W1 = V^T X (split over the long k = rows), W2 = T W1 or T^T W1, X -= V W2
   auto q1 = [&](int64_t p) -> int {
     const int64_t j = ts.pj[(size_t)p], m = ts.pm[(size_t)p], kk = m < b ? m : b;
-    RB_TRY(c, rocsolver_dlarfb(c->blas, rocblas_side_left,
-                               trans ? rocblas_operation_transpose : rocblas_operation_none,
-                               rocblas_forward_direction, rocblas_column_wise, (int)m, nc, (int)kk,
-                               ts.V1 + ts.poff[(size_t)p], (int)m, ts.T1 + p * b * b, b,
-                               X + (j + b), ni), what);
+    const double* V = ts.V1 + ts.poff[(size_t)p];
+    double* Xs = X + (j + b);
+    {
+      Strided<true> Av{V, m, 1, 0, kk};
+      Strided<true> Bx{Xs, n, 1, 0, ncols};
+      const int64_t tiles = ((kk + 63) / 64) * ((ncols + 63) / 64);
+      const SplitPlan sp = split_plan(m, splits_for(tiles, m, 2048));
+      if (sp.nz > 1) {
+        CHECK(ws_get(c, W_EIG_XP, (size_t)(sp.nz * kk * ncols), &WP));
+        EpiStore E{WP, ncols, 0, kk * ncols, 1.0};
+        CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/q1 W", Av, Bx, E, kk, ncols, m, 1, sp)));
+        hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(kk * ncols)), dim3(256), 0, c->stream, WP,
+                           sp.nz, kk * ncols, sp.nz, W1);
+        CHECK(launch_check(c, "k_sum_slices"));
+      } else {
+        EpiStore E{W1, ncols, 0, 0, 1.0};
+        CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/q1 W", Av, Bx, E, kk, ncols, m, 1)));
+      }
+    }
+    {
+      // W2[i][c] = sum_l T(i, l) W1[l][c] (or T(l, i)): the row-major kk x ncols W1, W2 are
+      // column-major ncols x kk for rocBLAS, so W2^T = W1^T T^T (or W1^T T)
+      const double one = 1.0, zero = 0.0;
+      RB_TRY(c, rocblas_dgemm(c->blas, rocblas_operation_none,
+                              trans ? rocblas_operation_none : rocblas_operation_transpose, nc,
+                              (int)kk, (int)kk, &one, W1, nc, ts.T1 + p * b * b, b, &zero, W2, nc),
+             what);
+    }
+    {
+      // X^T[c][r] -= sum_i W2[i][c] V[r][i]
+      Strided<false> Aw{W2, 1, ncols, 0, ncols};
+      Strided<false> Bv{V, 1, m, 0, m};
+      EpiSub E{Xs, n};
+      CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/q1 update", Aw, Bv, E, ncols, m, kk,
+                                       1)));
+    }
     return QSGW_OK;
   };
   if (!trans) {

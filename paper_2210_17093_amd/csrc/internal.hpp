@@ -91,6 +91,9 @@ enum Slot {
   W_EIG_DE,      // two-stage eigensolver: tridiagonal d, e       [2 n]
   W_EIG_TB,      // two-stage eigensolver: WY factors of the bulge reflector blocks [blocks][64][64]
   W_EIG_PX,      // two-stage projection: Q2^T Q1^T Bt^T          [naux][ntr]
+  W_EIG_XP,      // two-stage eigensolver: split-K partials of X = S V T [nz][b][m]
+  W_EIG_PANEL,   // two-stage eigensolver: panel QR partial dots (two buffers) and R  [2 G b + b b]
+  W_EIG_Q1W,     // two-stage eigensolver: V^T X and T V^T X of a panel [2][b][ncols]
   W_RHOFULL,     // iteration through the projection: rho' of every excitation [naux][ntr]
   W_RHOFULL32,   // ... and its FP32 copy (FP32 products)          [naux][ntr] float
   W_BMO_B,       // open-shell iteration: beta-spin MO tensor     [naux][nbf][nbf]
@@ -499,7 +502,7 @@ int syevd(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what) {
 }
 
 // Casida eigenproblems: the two-stage solver from this size on (QSGW_EIG_AUTO).
-constexpr int64_t kEigTwoStageMin = (int64_t)1 << 40;
+constexpr int64_t kEigTwoStageMin = 8192;
 inline bool eig_two_stage_for(const qsgw_ctx* c, int64_t n) {
   return c->eig_solver == QSGW_EIG_TWO_STAGE ||
          (c->eig_solver == QSGW_EIG_AUTO && n >= kEigTwoStageMin);
