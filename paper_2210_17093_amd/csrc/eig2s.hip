@@ -189,13 +189,18 @@ __global__ __launch_bounds__(256) void k_panel_t(const double* __restrict__ G, i
                                                  const double* __restrict__ tau,
                                                  double* __restrict__ T, int ldt) {
   __shared__ double Ts[kBand][kBand + 1];
+  __shared__ double Gs[kBand][kBand + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < kBand * kBand; e += 256) Ts[e / kBand][e % kBand] = 0.0;
+  for (int e = tid; e < kBand * kBand; e += 256) {
+    const int i = e / kBand, l = e % kBand;
+    Ts[i][l] = 0.0;
+    Gs[i][l] = (i < k && l < k) ? G[i * k + l] : 0.0;
+  }
   __syncthreads();
   for (int j = 0; j < k; ++j) {
     if (tid < j) {
       double sum = 0.0;
-      for (int l = tid; l < j; ++l) sum += Ts[tid][l] * G[l * k + j];
+      for (int l = tid; l < j; ++l) sum += Ts[tid][l] * Gs[l][j];
       Ts[tid][j] = -tau[j] * sum;
     } else if (tid == j) {
       Ts[j][j] = tau[j];
@@ -215,12 +220,12 @@ struct EpiPanelW {
   const double* X;
   double* U1w;
   double* U2w;
-  int64_t m;
+  int64_t m, ldu;
   __device__ __forceinline__ void operator()(int64_t, int64_t, int64_t c, int64_t r, double v,
                                              bool) const {
     const double w = X[c * m + r] - 0.5 * v;
-    U1w[c * m + r] = w;
-    U2w[c * m + r] = w;
+    U1w[c * ldu + r] = w;
+    U2w[c * ldu + r] = w;
   }
 };
 
@@ -255,20 +260,21 @@ struct EpiSub {
   }
 };
 
-// Copies the panel's Householder vectors (below the diagonal of the geqrf
+// Copies the panel's Householder vectors (below the diagonal of the panel QR
 // output, unit diagonal implied) into V [m][kk] column-major (ld m) with an
-// explicit unit diagonal and zeros above it, and into the concatenated
-// operands U1 = [V | W] (columns 0..kk-1) and U2 = [W | V] (columns kk..2kk-1).
+// explicit unit diagonal and zeros above it, and into its two columns blocks of
+// the pending-update operands: U1v (the V half of [V W]) and U2v (the V half of
+// [W V]), both column-major with ld ldu.
 __global__ void k_panel_v(const double* __restrict__ P, int64_t lda, int64_t m, int64_t kk,
-                          double* __restrict__ V, double* __restrict__ U1,
-                          double* __restrict__ U2) {
+                          double* __restrict__ V, double* __restrict__ U1v,
+                          double* __restrict__ U2v, int64_t ldu) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * kk) return;
   const int64_t col = idx / m, r = idx - col * m;
   const double v = r > col ? P[col * lda + r] : (r == col ? 1.0 : 0.0);
   V[idx] = v;
-  U1[idx] = v;
-  U2[kk * m + idx] = v;
+  U1v[col * ldu + r] = v;
+  U2v[col * ldu + r] = v;
 }
 
 // Lower band of the reduced matrix: AB[c][d] = A[c + d][c] for d <= b, 0 for
@@ -695,20 +701,39 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
   CHECK(ws_get(c, W_EIG_V1, (size_t)vtot, &V1));
   CHECK(ws_get(c, W_EIG_T1, (size_t)(np * b * b), &T1));
   CHECK(ws_get(c, W_EIG_TAU1, (size_t)(np * b), &tau1));
-  CHECK(ws_get(c, W_EIG_U, (size_t)(4 * n * b), &U1));
-  U2 = U1 + 2 * n * b;
-  CHECK(ws_get(c, W_EIG_XY, (size_t)(2 * n * b + 2 * b * b), &X));
+  CHECK(ws_get(c, W_EIG_U, (size_t)(4 * 4 * n * b), &U1));  // 2 x [n][2 b kDelay]
+  U2 = nullptr;
+  CHECK(ws_get(c, W_EIG_XY, (size_t)(2 * n * b + 2 * b * b + 2 * 4 * b * b), &X));
   Y = X + n * b;
   Z1 = Y + n * b;
   Z2 = Z1 + b * b;
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  // The two-sided update of the trailing matrix, S <- S - U1 U2^T with
+  // U1 = [V W], U2 = [W V], is delayed over up to kDelay panels: the pending
+  // blocks sit side by side in U1a, U2a ([n][2 b kDelay], row r of the matrix
+  // at row r), the next panel's columns and its product X = S Y are corrected
+  // with them (two thin products), and the stored matrix takes all of them in
+  // one product with k = 2 b (pending panels).
+  constexpr int kDelay = 4;
+  double* U1a = U1;
+  double* U2a = U1 + 2 * kDelay * n * b;
+  int dp = 0;  // pending panels
   for (int64_t p = 0; p < np; ++p) {
     const int64_t j = ts->pj[p], m = ts->pm[p], kk = m < b ? m : b;
-    const int mi = (int)m, ki = (int)kk;
+    const int mi = (int)m;
     double* P = A + j * n + (j + b);
     double* S = A + (j + b) * n + (j + b);
     double* V = V1 + ts->poff[p];
     double* T = T1 + p * b * b;
+    const int64_t Kp = 2 * b * dp;  // k of the pending blocks
+    if (dp > 0) {
+      // columns j .. j+b-1, rows j .. n-1: A -= U1a U2a^T (the panel and the diagonal block)
+      Strided<false> A2{U2a + j, 1, n, 0, b};
+      Strided<false> B1{U1a + j, 1, n, 0, n - j};
+      EpiSub E{A + j * n + j, n};
+      CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb panel", A2, B1, E, b, n - j, Kp,
+                                       1)));
+    }
     if (m >= 2 * b) {
       // one launch per column (see k_panel_col)
       const int G = (int)((m + kPanelRows - 1) / kPanelRows);
@@ -724,8 +749,15 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
     } else {
       RB_TRY(c, rocsolver_dgeqrf(h, mi, b, P, ni, tau1 + p * b), what);
     }
+    // this panel's block of the pending operands: columns [2 b dp, 2 b (dp + 1))
+    double* U1s = U1a + 2 * b * dp * n + (j + b);
+    double* U2s = U2a + 2 * b * dp * n + (j + b);
+    if (kk < b) {
+      HIP_TRY(c, hipMemset2DAsync(U1s, n * sizeof(double), 0, m * sizeof(double), 2 * b, c->stream));
+      HIP_TRY(c, hipMemset2DAsync(U2s, n * sizeof(double), 0, m * sizeof(double), 2 * b, c->stream));
+    }
     hipLaunchKernelGGL(k_panel_v, dim3(blocks_for(m * kk)), dim3(256), 0, c->stream, P, n, m, kk,
-                       V, U1, U2);
+                       V, U1s, U2s + b * n, n);
     CHECK(launch_check(c, "k_panel_v"));
     // T from the reflectors' Gram matrix (V^T V, long k = m) and tau
     {
@@ -742,11 +774,21 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
       EpiStore E{Y, m, 0, 0, 1.0};
       CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb Y", At, Bv, E, kk, m, kk, 1)));
     }
-    // X = S Y  (X^T[c][r] = sum_k Y[k][c] S[k][r], S symmetric), split over k
+    // X = S Y  (X^T[c][r] = sum_k Y[k][c] S[k][r], S symmetric), split over k,
+    // minus the pending updates: X -= U1a (U2a^T Y) on rows j+b .. n-1
     {
       Strided<true> Ay{Y, m, 1, 0, kk};
       Strided<true> Bs{S, n, 1, 0, m};
       CHECK(gemm_long_k(c, "eig/sy2sb X", Ay, Bs, X, kk, m, m));
+      if (dp > 0) {
+        double* Gp = Z2 + b * b;  // [Kp][kk]
+        Strided<true> Au{U2a + j + b, n, 1, 0, Kp};
+        CHECK(gemm_long_k(c, "eig/sy2sb X corr", Au, Ay, Gp, Kp, kk, m));
+        Strided<false> Ag{Gp, 1, kk, 0, kk};
+        Strided<false> Bu{U1a + j + b, 1, n, 0, m};
+        EpiSub E{X, m};
+        CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb X corr", Ag, Bu, E, kk, m, Kp, 1)));
+      }
     }
     // Z1 = V^T X  (Z1[i][c] = sum_r V(r, i) X(r, c)), Z2 = T^T Z1
     {
@@ -758,22 +800,22 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
       EpiStore E{Z2, kk, 0, 0, 1.0};
       CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb Z2", At, Bz, E, kk, kk, kk, 1)));
     }
-    // W = X - 1/2 V Z2 into U1[:, kk:] and U2[:, :kk]  (W^T[c][r] = X - 1/2 sum_l Z2[l][c] V(r, l))
+    // W = X - 1/2 V Z2 into this panel's W halves of U1a and U2a
     {
       Strided<false> Az{Z2, 1, kk, 0, kk};
       Strided<false> Bv{V, 1, m, 0, m};
-      EpiPanelW E{X, U1 + kk * m, U2, m};
+      EpiPanelW E{X, U1s + b * n, U2s, m, n};
       CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb W", Az, Bv, E, kk, m, kk, 1)));
     }
-    {
-      // S -= U1 U2^T over the whole square: every tile writes its own rows
-      // (mirrored writes of the upper-tile form would be transposed, uncoalesced
-      // read-modify-writes)
-      Strided<false> A1{U1, 1, m, 0, m};
-      Strided<false> A2{U2, 1, m, 0, m};
+    ++dp;
+    if (dp == kDelay || p == np - 1) {
+      // S -= U1a U2a^T over the whole trailing square (every tile its own rows)
+      Strided<false> A2{U2a + j + b, 1, n, 0, m};
+      Strided<false> B1{U1a + j + b, 1, n, 0, m};
       EpiSub E{S, n};
-      CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/sy2sb update", A1, A2, E, m, m, 2 * kk,
-                                       1)));
+      CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/sy2sb update", A2, B1, E, m, m,
+                                       2 * b * dp, 1)));
+      dp = 0;
     }
   }
 
