@@ -60,15 +60,13 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 HARTREE_MEV = 27211.386
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel at the cfg2 workload, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes scaled by the plain-copy calibration
-# (profiles/residue_w_split_bf16_cfg2_hbm_counters.md, profiles/residue_w_cfg2_hbm_counters.md).
-# Only valid for the kernel build the counters were taken on: set an entry to None
-# whenever that kernel changes.
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes over `bench.py --counter-probe` (no eigensolver in the profiled process), scaled
+# by the plain-copy calibration and to an average launch of the timed iteration
+# (profiles/hot_path_cfg3_fp64_counters.md).  Only valid for the kernel build the
+# counters were taken on: drop an entry whenever that kernel changes.
 MEASURED_TRAFFIC_BYTES = {
-    ("cfg2", "bf16x3", "residue_w"): 19.86e9,
-    ("cfg2", "fp64", "residue_w"): 66.05e9,
-    ("cfg2", "fp32", "residue_w"): 23.46e9,
+    ("cfg3", "fp64", "residue_w"): 143.6e9,
 }
 
 

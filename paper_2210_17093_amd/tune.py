@@ -10,7 +10,7 @@ than a rounding-order difference (1e-10 Ha for FP64, a tenth of the 1 meV
 gate for the reduced precisions) is dropped.  The fastest table per workload
 goes to tiles.json next to this file, which bench.py applies to its workload.
 
-    python -m paper_2210_17093_amd.tune cfg2 cfg2:fp32 cfg2:bf16x3 cfg4 [--reps 3]
+    python -m paper_2210_17093_amd.tune cfg2 cfg2:fp32 cfg2:bf16x3 cfg3 cfg4 [--reps 3]
 
 A workload name may carry the variant (":fp32" for the FP32 matrix-core
 products, ":bf16x3" for the split-BF16 ones); the batched workload is tuned
@@ -70,14 +70,31 @@ def single_timer(name, precision):
     e0 = torch.from_numpy(p.eps0.copy()).to(dev)
     h = q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)
     e, C = torch.empty_like(e0), torch.empty_like(C0)
+    solved = [False]
 
-    def run(spec):
-        ctx.set_tiles(spec)
+    def once(replay):
         e.copy_(e0)
         C.copy_(C0)
         torch.cuda.synchronize()
         _, rep, _ = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=0.0, max_iter=1,
-                                   precision=precision)
+                                   precision=precision, replay_eig=replay)
+        return rep
+
+    def run(spec):
+        # The Casida eigensolve is not among the tuned products: after the
+        # first solve, iterations replay its eigenpairs (the library checks
+        # that the rebuilt Casida matrix is bitwise the solved one; a table
+        # whose Casida product rounds differently gets a fresh solve first).
+        ctx.set_tiles(spec)
+        if solved[0]:
+            try:
+                rep = once(True)
+                return rep["kernel_ms"], e.cpu().numpy()
+            except q.QsgwError:
+                pass
+        once(False)
+        solved[0] = True
+        rep = once(True)
         return rep["kernel_ms"], e.cpu().numpy()
     return ctx, run
 
@@ -155,7 +172,8 @@ def tune(name, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workloads", nargs="+",
-                    choices=("cfg1", "cfg2", "cfg1:fp32", "cfg2:fp32", "cfg2:bf16x3", "cfg4"))
+                    choices=("cfg1", "cfg2", "cfg3", "cfg1:fp32", "cfg2:fp32", "cfg2:bf16x3",
+                             "cfg3:fp32", "cfg3:bf16x3", "cfg4"))
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args()
