@@ -34,6 +34,11 @@ its reason in the design notes of the repository):
   * The one-body part of Eq. (6), T + V_ext, is a synthetic matrix h built so
     that the starting (eps0, C0) is an exact Hartree-Fock fixed point.
   * No mixing by default; convergence when max_m |eps_m' - eps_m| < tol.
+    Optional accelerators of the fixed point (the paper names none): linear
+    mixing of the AO-basis correlation potential, or Pulay's direct inversion
+    in the iterative subspace (DIIS) on the AO Fock matrix with the
+    commutator error F D - D F (Pulay, Chem. Phys. Lett. 73, 393 (1980);
+    J. Comput. Chem. 3, 556 (1982), with S = I).
   * Eq. (20), second-order exchange with p occupied: the printed integral
     (pi|an) is read as (pa|in).  The printed form matches the second-order
     self-energy of antisymmetrised spin-orbital integrals for virtual p only;
@@ -240,19 +245,47 @@ def qsgw_step(B_ao, h, C, eps, nocc, eta, fock_mode="full"):
                 w=w, V=V, F=F, eps=eps_new, C=C_new)
 
 
+def diis_error(F: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """DIIS error of a Fock matrix built from density D: the commutator
+    F D - D F (S = I), zero exactly when F and D share eigenvectors."""
+    return F @ D - D @ F
+
+
+def diis_coefficients(errors) -> np.ndarray:
+    """Pulay's DIIS weights: the c minimising || sum_i c_i e_i ||_F subject
+    to sum_i c_i = 1, from the bordered system
+        [ B   -1 ] [c]   [ 0 ]
+        [ -1^T 0 ] [l] = [ -1 ],   B_ij = <e_i, e_j>_F."""
+    n = len(errors)
+    Bm = np.zeros((n + 1, n + 1))
+    for i in range(n):
+        for j in range(n):
+            Bm[i, j] = float(np.sum(errors[i] * errors[j]))
+    Bm[:n, n] = -1.0
+    Bm[n, :n] = -1.0
+    rhs = np.zeros(n + 1)
+    rhs[n] = -1.0
+    return np.linalg.solve(Bm, rhs)[:n]
+
+
 def qsgw_iterate(B_ao, h, C0, eps0, nocc, eta, tol, max_iter, mix=1.0,
-                 keep=("eps", "Omega"), fock_mode="full"):
+                 keep=("eps", "Omega"), fock_mode="full", diis=0):
     """Repeat the qsGW step until max|eps' - eps| < tol or max_iter.
 
     With mix < 1 the AO-basis correlation potential is mixed linearly with the
     previous one: Sigma_ao <- mix * Sigma_ao + (1 - mix) * Sigma_ao_prev.
-    fock_mode "frozen": h is the frozen mean-field matrix F0 (see ``fock``).
-    Returns (eps, C, history) where history[j] holds the ``keep`` entries and
-    max|d eps| of iteration j + 1.
+    With diis = m >= 2 the Fock matrix of Eq. (6) built from (eps, C) is
+    stored with its error e = F D - D F (D of Eq. (9) from the same C) among
+    the last m such pairs, and the matrix diagonalised is sum_i c_i F_i with
+    the weights of ``diis_coefficients`` (the first iteration is the plain
+    step).  fock_mode "frozen": h is the frozen mean-field matrix F0 (see
+    ``fock``).  Returns (eps, C, history) where history[j] holds the ``keep``
+    entries and max|d eps| of iteration j + 1.
     """
     C, eps = C0.copy(), eps0.copy()
     hist = []
     Vao_prev = None
+    F_hist, E_hist = [], []
     for _ in range(max_iter):
         B_mo = mo_transform(B_ao, C)
         M, sqrt_delta = rpa_hermitian(B_mo, eps, nocc)
@@ -263,18 +296,28 @@ def qsgw_iterate(B_ao, h, C0, eps0, nocc, eta, tol, max_iter, mix=1.0,
         if Vao_prev is not None and mix != 1.0:
             Vao = mix * Vao + (1.0 - mix) * Vao_prev
         Vao_prev = Vao
+        D = density(C, nocc)
         if fock_mode == "frozen":
             F = h + Vao
         else:
-            D = density(C, nocc)
             F = h + hartree(B_ao, D) - exchange(B_ao, D) + Vao
+        if diis >= 2:
+            F_hist.append(F)
+            E_hist.append(diis_error(F, D))
+            F_hist, E_hist = F_hist[-diis:], E_hist[-diis:]
+            if len(F_hist) > 1:
+                c = diis_coefficients(E_hist)
+                F = sum(ci * Fi for ci, Fi in zip(c, F_hist))
         eps_new, C_new = diagonalize(F)
         d = float(np.max(np.abs(eps_new - eps)))
         rec = {"max_deps": d}
+        if diis >= 2:
+            rec["diis_err"] = float(np.linalg.norm(E_hist[-1]))
         loc = dict(B_mo=B_mo, M=M, Omega=Omega, XpY=XpY, w=w, V=V, Vao=Vao,
                    F=F, eps=eps_new, C=C_new)
         for k in keep:
-            rec[k] = loc[k]
+            if k not in rec:
+                rec[k] = loc[k]
         hist.append(rec)
         C, eps = C_new, eps_new
         if d < tol:

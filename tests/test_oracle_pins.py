@@ -319,6 +319,74 @@ def test_p21_frozen_mean_field():
     assert np.max(np.abs(eps_f - eps)) > 1e-6
 
 
+# ------------------------------------- P22: DIIS on the Fock matrix ------
+@pytest.mark.parametrize("n", [2, 3, 6])
+def test_p22_diis_weights_minimise_the_error_norm(n):
+    """Pulay's weights against an independent route: eliminate the constraint
+    (c_n = 1 - sum of the others) and solve the unconstrained least-squares
+    problem for the residual e_n + sum_i c_i (e_i - e_n) with lstsq."""
+    rng = np.random.default_rng(22 + n)
+    errs = [rng.standard_normal((7, 7)) for _ in range(n)]
+    errs = [e - e.T for e in errs]  # commutators of symmetric matrices are antisymmetric
+    c = O.diis_coefficients(errs)
+    A = np.stack([(e - errs[-1]).ravel() for e in errs[:-1]], axis=1)
+    x, *_ = np.linalg.lstsq(A, -errs[-1].ravel(), rcond=None)
+    ref = np.append(x, 1.0 - x.sum())
+    np.testing.assert_allclose(c, ref, rtol=1e-9, atol=1e-12)
+    assert abs(c.sum() - 1.0) < 1e-12
+    # no other affine combination has a smaller error norm
+    best = np.linalg.norm(sum(ci * e for ci, e in zip(c, errs)))
+    for _ in range(20):
+        d = rng.standard_normal(n)
+        d -= d.mean()
+        assert np.linalg.norm(sum((ci + 1e-3 * di) * e for ci, di, e in zip(c, d, errs))) >= best
+
+
+def test_p22_diis_reaches_the_plain_fixed_point():
+    """DIIS changes the path, not the fixed point: from the same start the
+    DIIS iteration, the mixed iteration and the plain iteration end at the
+    same energies; at the end the Fock matrix commutes with the density
+    (the DIIS error vanishes) and one plain step no longer moves anything."""
+    for seed, coupling in ((21, 0.3), (22, 0.3), (23, 0.1)):
+        p = tiny(nbf=8, naux=16, nocc=3, seed=seed, coupling=coupling)
+        h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+        eta = 0.05
+        e1, C1, h1 = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, eta, 1e-11, 60, diis=6,
+                                    keep=("eps", "diis_err"))
+        e2, _, h2 = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, eta, 1e-11, 300, mix=0.5)
+        e3, _, _ = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, eta, 1e-11, 300)
+        assert h1[-1]["max_deps"] < 1e-11 and h2[-1]["max_deps"] < 1e-11
+        np.testing.assert_allclose(e1, e2, atol=1e-9)
+        np.testing.assert_allclose(e1, e3, atol=1e-9)
+        assert len(h1) < len(h2)
+        assert h1[-1]["diis_err"] < 1e-9 < h1[0]["diis_err"]
+        st = O.qsgw_step(p.B_ao, h, C1, e1, p.nocc, eta)
+        assert np.max(np.abs(st["eps"] - e1)) < 1e-9
+        # the first DIIS iteration is the plain step
+        np.testing.assert_allclose(h1[0]["eps"], O.qsgw_step(p.B_ao, h, p.C0, p.eps0, p.nocc,
+                                                             eta)["eps"], atol=1e-13)
+
+
+def test_mutant_diis_constraint_sign_caught(monkeypatch):
+    """Weights summing to -1 (the border row's sign flipped) fail P22."""
+    good = O.diis_coefficients
+
+    def flipped(errors):
+        return -good(errors)
+    monkeypatch.setattr(O, "diis_coefficients", flipped)
+    with pytest.raises(AssertionError):
+        test_p22_diis_weights_minimise_the_error_norm(3)
+
+
+def test_mutant_diis_anticommutator_error_caught(monkeypatch):
+    """An error vector F D + D F (anticommutator) does not vanish at the
+    fixed point: P22's end-of-iteration check fails."""
+    import oracle.qsgw_oracle as OQ
+    monkeypatch.setattr(OQ, "diis_error", lambda F, D: F @ D + D @ F)
+    with pytest.raises(AssertionError):
+        test_p22_diis_reaches_the_plain_fixed_point()
+
+
 # ------------------------------------------------------------- mutations --
 _residues = O.residues
 
