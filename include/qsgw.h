@@ -376,6 +376,19 @@ typedef struct {
                        delta_m (the learned warm start); the call first replaces the state's
                        (eps, C) by the warm start of qsgw_warm_start built from them, then
                        iterates.  qsgw_iterate_batched requires NULL. */
+  int64_t diis;     /* qsgw_iterate only: 0 = off, or m in [2, 16]: Pulay's DIIS on the Fock
+                       matrix of Eq. (6) (direct inversion in the iterative subspace; Pulay,
+                       Chem. Phys. Lett. 73, 393 (1980) and J. Comput. Chem. 3, 556 (1982)),
+                       an accelerator of the fixed point the paper leaves open: each
+                       iteration's Fock matrix F (AO basis, S = I) is kept with its error
+                       e = F D - D F (D of Eq. (9) from the orbitals that built F) among the
+                       last m pairs, and the matrix diagonalised is sum_i c_i F_i with the c
+                       minimising ||sum_i c_i e_i|| subject to sum_i c_i = 1 (the first
+                       iteration of a history is the plain step; a singular system takes the
+                       newest F).  The history lives in the context and continues across
+                       calls; a state with iteration 0, another N_b or another m starts a new
+                       one, so interleaved molecules need one context each.  Needs mix 1
+                       (QSGW_ERR_INVALID_ARG otherwise). */
 } qsgw_options;
 
 /* qsgw_options.flags, qsgw_iterate_batched only: run the kernel segments

@@ -581,6 +581,8 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     return fail(c, QSGW_ERR_UNSUPPORTED, "fock_mode %d is not available", o->fock_mode);
   if (o->warm_start)
     return fail(c, QSGW_ERR_UNSUPPORTED, "warm_start: apply qsgw_warm_start to each molecule");
+  if (o->diis != 0)
+    return fail(c, QSGW_ERR_UNSUPPORTED, "diis: qsgw_iterate only");
   if (o->flags & ~(int64_t)QSGW_OPT_GRAPH)
     return fail(c, QSGW_ERR_UNSUPPORTED, "flags other than QSGW_OPT_GRAPH");
   const bool fp32 = o->precision == QSGW_PREC_FP32;
@@ -993,10 +995,10 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
       r.ms_stage[kStageMo] = ms_hot;
       r.ms_stage[kStageEigRpa] = ms_eigM;
       r.ms_stage[kStageEigFock] = ms_eigF;
-      r.hot_flops = 4.0 * b * b * b * a + t * (t + 1.0) * a + 2.0 * a * t * t + b * (b + 1.0) * a * t +
+      r.hot_flops = (3.0 * b + 1.0) * b * b * a + t * (t + 1.0) * a + 2.0 * a * t * t + b * (b + 1.0) * a * t +
                     2.0 * b * b * b * t + b * (b + 1.0) * a * oc + 2.0 * a * b * b + 6.0 * b * b * b;
       r.kernel_flops[kKMo1 - kKernelBase] = 2.0 * b * b * b * a;
-      r.kernel_flops[kKMo2 - kKernelBase] = 2.0 * b * b * b * a;
+      r.kernel_flops[kKMo2 - kKernelBase] = b * (b + 1.0) * b * a;  // symmetric output
       r.kernel_flops[kKCasida - kKernelBase] = t * (t + 1.0) * a;
       r.kernel_flops[kKRho - kKernelBase] = 2.0 * a * t * t;
       r.kernel_flops[kKW - kKernelBase] = b * (b + 1.0) * a * t;

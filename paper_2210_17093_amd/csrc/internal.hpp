@@ -48,6 +48,11 @@ enum Slot {
   W_EIGE,     // dsyevd off-diagonal workspace            [max(ntr, nbf)]
   W_SCAL,     // device scalars                           [8]
   W_FLAGS,    // device int flags                         [8]
+  W_DIIS_F,   // DIIS history: AO Fock matrices             [m][nbf][nbf]
+  W_DIIS_E,   // DIIS history: their commutator errors       [m][nbf][nbf]
+  W_DIIS_B,   // DIIS error dot products                     [16][16]
+  W_DIIS_X,   // DIIS weights, then the combined Fock matrix [nbf][nbf]
+  W_DIIS_S,   // DIIS slots in time order (int)              [16]
   W_ROWTAB,   // residue pair blocks holding some m <= k  [blocks]
   W_RHOPART,  // split-K partial sums of rho              [nz][naux][sb]
   W_BATCH_F64,   // batched iteration: every molecule's arrays
@@ -160,6 +165,10 @@ struct qsgw_ctx {
   // this device's copy of the allocation-free entry point's static scratch
   // array (noalloc.hip), null if the lookup failed
   double* scratch = nullptr;
+  // DIIS history of qsgw_iterate (W_DIIS_*): stored pairs, next slot, and
+  // the (N_b, subspace size) it belongs to; diis_slots stages the slot order
+  int64_t diis_n = 0, diis_next = 0, diis_nbf = -1, diis_m = 0;
+  int diis_slots[16] = {};
 };
 
 // Looks up the device address of the static scratch array of the

@@ -300,6 +300,93 @@ __global__ void k_max_abs_diff(const double* a, const double* b, int64_t n, doub
   }
 }
 
+__global__ void k_diis_error_mo(const double* F, int64_t n, int64_t nocc, double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t m = idx / n, k = idx - m * n;
+  const double om = m < nocc ? 1.0 : 0.0, ok = k < nocc ? 1.0 : 0.0;
+  out[idx] = F[idx] * (ok - om);
+}
+
+__global__ void k_diis_dots(const double* E, int64_t len, int64_t k, const int* slots, double* B,
+                            int64_t ld) {
+  __shared__ double red[4];
+  const int64_t j = slots[blockIdx.x];
+  const double* a = E + k * len;
+  const double* b = E + j * len;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) s += a[i] * b[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    B[k * ld + j] = t;
+    B[j * ld + k] = t;
+  }
+}
+
+__global__ void k_diis_solve(const double* B, int64_t ld, const int* slots, int nact, double* c,
+                             int* bad) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  constexpr int kMax = 17;
+  double a[kMax][kMax + 1];
+  const int n = nact + 1;
+  for (int i = 0; i < nact; ++i) {
+    for (int j = 0; j < nact; ++j) a[i][j] = B[(int64_t)slots[i] * ld + slots[j]];
+    a[i][nact] = -1.0;
+    a[i][n] = 0.0;
+  }
+  for (int j = 0; j < nact; ++j) a[nact][j] = -1.0;
+  a[nact][nact] = 0.0;
+  a[nact][n] = -1.0;
+  bool singular = false;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (a[piv][col] == 0.0) {
+      singular = true;
+      break;
+    }
+    if (piv != col)
+      for (int q = col; q <= n; ++q) {
+        const double t = a[col][q];
+        a[col][q] = a[piv][q];
+        a[piv][q] = t;
+      }
+    for (int r = col + 1; r < n; ++r) {
+      const double f = a[r][col] / a[col][col];
+      for (int q = col; q <= n; ++q) a[r][q] -= f * a[col][q];
+    }
+  }
+  double x[kMax];
+  if (!singular) {
+    for (int r = n - 1; r >= 0; --r) {
+      double t = a[r][n];
+      for (int q = r + 1; q < n; ++q) t -= a[r][q] * x[q];
+      x[r] = t / a[r][r];
+    }
+    for (int i = 0; i < nact; ++i)
+      if (!isfinite(x[i])) singular = true;
+  }
+  if (singular) {
+    *bad = 1;
+    for (int i = 0; i < nact; ++i) c[i] = i == nact - 1 ? 1.0 : 0.0;
+  } else {
+    for (int i = 0; i < nact; ++i) c[i] = x[i];
+  }
+}
+
+__global__ void k_diis_combine(const double* F, int64_t len, const int* slots, int nact,
+                               const double* c, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double s = 0.0;
+  for (int i = 0; i < nact; ++i) s += c[i] * F[(int64_t)slots[i] * len + e];
+  out[e] = s;
+}
+
 template <class T>
 __device__ __forceinline__ void check_finite_body(const T* x, int64_t len, int* bad, int mask) {
   bool ok = true;

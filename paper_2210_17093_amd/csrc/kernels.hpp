@@ -507,6 +507,26 @@ __global__ void k_mp2_rhs_occ(const double* D, const double* xo, int64_t xsn, in
 __global__ void k_mp2_rhs_vir(const double* D, const double* eps, int64_t nbf, int64_t nocc,
                               int64_t i0, int64_t ni, double eta, double* R);
 
+// Pulay DIIS on the Fock matrix (qsgw_iterate's optional accelerator of the
+// fixed point).  The commutator error F D - D F of a Fock matrix F_mo given in
+// the MO basis of the orbitals whose occupied block defines D: element
+// (m, n) is F[m][n] (occ(n) - occ(m)), nonzero only between occupied and
+// empty states.
+__global__ void k_diis_error_mo(const double* F, int64_t n, int64_t nocc, double* out);
+// B[k][j] = B[j][k] = <E_k, E_j>_F for the stored slots j (one workgroup per
+// slot j in `slots`, fixed-order reduction); E is [m][len], B is [ld][ld].
+__global__ void k_diis_dots(const double* E, int64_t len, int64_t k, const int* slots, double* B,
+                            int64_t ld);
+// Pulay weights: c minimising || sum_j c_j E_j || subject to sum_j c_j = 1,
+// from the bordered (nact + 1) system over the slots in `slots` (one thread,
+// Gaussian elimination with partial pivoting); c[i] is slot slots[i]'s weight.
+// A singular system sets *bad and leaves the weight of the newest slot 1.
+__global__ void k_diis_solve(const double* B, int64_t ld, const int* slots, int nact, double* c,
+                             int* bad);
+// out[e] = sum_i c[i] F[slots[i]][e], i in fixed order.
+__global__ void k_diis_combine(const double* F, int64_t len, const int* slots, int nact,
+                               const double* c, double* out);
+
 // Open shell: one spin's transitions into the concatenated [naux][ld] tensor.
 __global__ void k_gather_bia_ld(const double* bmo, const double* sqrt_delta, double scale,
                                 int64_t naux, int64_t nbf, int64_t nocc, int64_t ld, double* bt);

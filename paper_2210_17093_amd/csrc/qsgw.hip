@@ -891,6 +891,10 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   if (o->fock_mode != QSGW_FOCK_FULL_JK && o->fock_mode != QSGW_FOCK_FROZEN)
     return fail(c, QSGW_ERR_INVALID_ARG, "unknown fock_mode %d", o->fock_mode);
   const bool frozen = o->fock_mode == QSGW_FOCK_FROZEN;
+  if (o->diis != 0 && (o->diis < 2 || o->diis > 16))
+    return fail(c, QSGW_ERR_INVALID_ARG, "diis must be 0 or in [2, 16]");
+  if (o->diis != 0 && o->mix != 1.0)
+    return fail(c, QSGW_ERR_INVALID_ARG, "diis needs mix 1");
   if (o->s_block < 0) return fail(c, QSGW_ERR_INVALID_ARG, "need s_block >= 0");
   if (!(o->near_pole >= 0.0) || !isfinite(o->near_pole))
     return fail(c, QSGW_ERR_INVALID_ARG, "need a finite near_pole >= 0");
@@ -961,6 +965,22 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   CHECK(ws_get(c, W_CNEW, (size_t)nn, &Cn));
   CHECK(ws_get(c, W_SCAL, 8, &scal));
   CHECK(ws_get(c, W_FLAGS, 8, &flags));
+  const int64_t dm = o->diis;
+  double *dF = nullptr, *dE = nullptr, *dB = nullptr, *dX = nullptr;
+  int* dS = nullptr;
+  if (dm) {
+    CHECK(ws_get(c, W_DIIS_F, (size_t)(dm * nn), &dF));
+    CHECK(ws_get(c, W_DIIS_E, (size_t)(dm * nn), &dE));
+    CHECK(ws_get(c, W_DIIS_B, (size_t)(16 * 16), &dB));
+    CHECK(ws_get(c, W_DIIS_X, (size_t)(nn > 32 ? nn : 32), &dX));
+    CHECK(ws_get(c, W_DIIS_S, (size_t)16, &dS));
+    if (st->iteration == 0 || c->diis_nbf != nbf || c->diis_m != dm) {
+      c->diis_n = 0;
+      c->diis_next = 0;
+      c->diis_nbf = nbf;
+      c->diis_m = dm;
+    }
+  }
   float* Bmo32 = nullptr;
   if (o->precision == QSGW_PREC_FP32 && !qsmp2) {  // (the split-BF16 residue product reads split copies)
     CHECK(ws_get(c, W_BMO32, (size_t)(naux * nn), &Bmo32));
@@ -1010,7 +1030,7 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   memset(&local, 0, sizeof(local));
   {
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
-    local.hot_flops = 4.0 * b * b * b * a            // Eq. (16)
+    local.hot_flops = (3.0 * b + 1.0) * b * b * a    // Eq. (16): T = B C, upper triangle of C^T T
                       + t * (t + 1.0) * a            // Casida build (symmetric)
                       + (fold ? 0.0 : 2.0 * a * t * t)  // rho' (inside the eigensolve when projected)
                       + b * (b + 1.0) * a * t        // residues (symmetric in m, k)
@@ -1021,13 +1041,13 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
   }
   if (qsmp2) {  // the qsMP2 potential replaces Casida, residues and the qsGW product
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
-    local.hot_flops = 4.0 * b * b * b * a + b * (b + 1.0) * t * a + 2.0 * b * b * b * t +
+    local.hot_flops = (3.0 * b + 1.0) * b * b * a + b * (b + 1.0) * t * a + 2.0 * b * b * b * t +
                       (frozen ? 0.0 : b * (b + 1.0) * a * oc + 2.0 * a * b * b) + 8.0 * b * b * b;
   }
   {
     const double b = (double)nbf, a = (double)naux, t = (double)ntr, oc = (double)nocc;
     local.kernel_flops[kKMo1 - kKernelBase] = 2.0 * b * b * b * a;
-    local.kernel_flops[kKMo2 - kKernelBase] = 2.0 * b * b * b * a;
+    local.kernel_flops[kKMo2 - kKernelBase] = b * (b + 1.0) * b * a;  // symmetric output
     local.kernel_flops[kKCasida - kKernelBase] = t * (t + 1.0) * a;
     local.kernel_flops[kKRho - kKernelBase] = fold ? 0.0 : 2.0 * a * t * t;
     local.kernel_flops[kKW - kKernelBase] = b * (b + 1.0) * a * t;
@@ -1187,6 +1207,37 @@ int iterate_impl(qsgw_ctx* c, const qsgw_problem* p, qsgw_state* st, const qsgw_
       hipLaunchKernelGGL(k_fock_assemble, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hmo, J,
                          Kpart, nz, V, nbf, F);
       CHECK(launch_check(c, "k_fock_assemble"));
+    }
+    if (dm) {
+      // Pulay DIIS: keep F (AO basis) and its commutator error, then
+      // diagonalise the combination of the kept Fock matrices with the
+      // weights that minimise the combined error (first iteration: F itself)
+      const int64_t k = c->diis_next;
+      CHECK(congruence(c, nbf, C, F, tmp, dF + k * nn));
+      hipLaunchKernelGGL(k_diis_error_mo, dim3(blocks_for(nn)), dim3(256), 0, c->stream, F, nbf,
+                         nocc, tmp2);
+      CHECK(launch_check(c, "k_diis_error_mo"));
+      CHECK(congruence(c, nbf, C, tmp2, tmp, dE + k * nn));
+      const int64_t na = c->diis_n < dm ? c->diis_n + 1 : dm;
+      for (int64_t i = 0; i < na; ++i) c->diis_slots[i] = (int)((k - (na - 1) + i + dm) % dm);
+      HIP_TRY(c, hipMemcpyAsync(dS, c->diis_slots, na * sizeof(int), hipMemcpyHostToDevice,
+                                c->stream));
+      hipLaunchKernelGGL(k_diis_dots, dim3((unsigned)na), dim3(256), 0, c->stream, dE, nn, k, dS,
+                         dB, (int64_t)16);
+      CHECK(launch_check(c, "k_diis_dots"));
+      if (na > 1) {
+        hipLaunchKernelGGL(k_diis_solve, dim3(1), dim3(64), 0, c->stream, dB, (int64_t)16, dS,
+                           (int)na, dX, flags + 6);
+        hipLaunchKernelGGL(k_diis_combine, dim3(blocks_for(nn)), dim3(256), 0, c->stream, dF, nn,
+                           dS, (int)na, dX, tmp2);
+        CHECK(launch_check(c, "k_diis_combine"));
+        // back to the MO basis of the current orbitals
+        CHECK(congruence_t(c, nbf, C, tmp2, tmp, dX));
+        hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(nn)), dim3(256), 0, c->stream, dX, nbf, F);
+        CHECK(launch_check(c, "k_symmetrize"));
+      }
+      c->diis_n = na;
+      c->diis_next = (k + 1) % dm;
     }
     CHECK(sp.close());
     CHECK(sp.close());
@@ -1469,11 +1520,11 @@ int qsgw_iterate_unrestricted(qsgw_ctx* c, const qsgw_problem* p, int64_t nocc_b
   if (!(o->eta > 0.0) || !isfinite(o->eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need eta > 0");
   if (o->max_iter < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need max_iter >= 1");
   if (o->precision != QSGW_PREC_FP64 || o->mix != 1.0 || o->fock_mode != QSGW_FOCK_FULL_JK ||
-      o->flags != 0 || o->s_block != 0 || o->warm_start || st_a->Vc || st_b->Vc || st_a->diag ||
-      st_b->diag)
+      o->flags != 0 || o->s_block != 0 || o->warm_start || o->diis != 0 || st_a->Vc || st_b->Vc ||
+      st_a->diag || st_b->diag)
     return fail(c, QSGW_ERR_UNSUPPORTED,
                 "qsgw_iterate_unrestricted: FP64, mix 1, QSGW_FOCK_FULL_JK, no flags, automatic "
-                "blocks, no warm start and no Vc/diag outputs only");
+                "blocks, no warm start or DIIS and no Vc/diag outputs only");
   double *Bma, *Bmb, *Va, *Vb, *old;
   CHECK(ws_get(c, W_BMO, (size_t)(naux * nn), &Bma));
   CHECK(ws_get(c, W_BMO_B, (size_t)(naux * nn), &Bmb));
@@ -1485,7 +1536,7 @@ int qsgw_iterate_unrestricted(qsgw_ctx* c, const qsgw_problem* p, int64_t nocc_b
   {
     const double b = (double)nbf, a = (double)naux;
     const double t = (double)(na * (nbf - na) + nb * (nbf - nb));
-    local.hot_flops = 2.0 * 4.0 * b * b * b * a            // Eq. (16), both spins
+    local.hot_flops = 2.0 * (3.0 * b + 1.0) * b * b * a    // Eq. (16), both spins
                       + t * (t + 1.0) * a + 2.0 * a * t * t  // Casida build and rho' (shared)
                       + 2.0 * (b * (b + 1.0) * a * t + 2.0 * b * b * b * t)  // residues + Eq. (19)
                       + b * (b + 1.0) * a * (double)(na + nb) + 2.0 * a * b * b + 16.0 * b * b * b;

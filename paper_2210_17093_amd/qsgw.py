@@ -76,7 +76,7 @@ class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("eta", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int64), ("mix", ct.c_double), ("fock_mode", ct.c_int),
                 ("s_block", ct.c_int64), ("flags", ct.c_int64), ("near_pole", ct.c_double),
-                ("warm_start", ct.c_void_p)]
+                ("warm_start", ct.c_void_p), ("diis", ct.c_int64)]
 
 
 KERNELS = ("mo_transform_1", "mo_transform_2", "casida", "residue_rho", "residue_w",
@@ -416,10 +416,11 @@ def qsgw_hf_core(ctx: Context, B_ao, C0, eps0, nocc, h=None):
 def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1, mix=1.0,
                  Vc=None, iteration=0, s_block=0, precision=PREC_FP64, diag=None, refine=False,
                  near_pole=0.0, qsmp2=False, fock_mode=FOCK_FULL_JK, warm_start=None,
-                 replay_eig=False):
+                 replay_eig=False, diis=0):
     """Runs qsGW iterations (qsMP2 iterations with qsmp2=True) in place on (eps, C).
     warm_start: None or a float32 [nbf] device tensor of predicted shifts.
     replay_eig: reuse the context's last Casida eigenpairs (QSGW_OPT_REPLAY_EIG).
+    diis: 0, or the DIIS subspace size (2..16) of qsgw_options.diis.
     Returns (status, report dict, iteration)."""
     naux, nbf, _ = B_ao.shape
     prob = Problem(nbf, naux, nocc, _ptr(B_ao, (naux, nbf, nbf), name="B_ao"),
@@ -432,7 +433,7 @@ def qsgw_iterate(ctx: Context, B_ao, h, nocc, eps, C, eta, tol=1e-6, max_iter=1,
     opt = Options(precision, float(eta), float(tol), int(max_iter), float(mix), int(fock_mode),
                   int(s_block), flags, float(near_pole),
                   _ptr(warm_start, (nbf,), torch.float32, "warm_start")
-                  if warm_start is not None else None)
+                  if warm_start is not None else None, int(diis))
     rep = Report()
     rc = ctx.check(lib().qsgw_iterate(ctx.handle, ct.byref(prob), ct.byref(st), ct.byref(opt),
                                       ct.byref(rep)), allow=(OK, NOT_CONVERGED))
