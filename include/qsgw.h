@@ -554,6 +554,15 @@ int qsgw_mlp_features(qsgw_ctx* ctx, int64_t nbf, int64_t nocc, const double* ep
 int qsgw_mlp_forward(qsgw_ctx* ctx, const float* params, int64_t n, const float* X, float* y);
 
 /*
+ * BF16 inference of the same network (the learned warm start's inference
+ * precision): X, W1, the first hidden activations, W2, the second hidden
+ * activations and w3 are rounded to BF16 (nearest even) and multiplied on
+ * the BF16 matrix cores with FP32 accumulation; biases and GELU stay FP32.
+ * Same arguments and layout as qsgw_mlp_forward; FP32 master weights in.
+ */
+int qsgw_mlp_forward_bf16(qsgw_ctx* ctx, const float* params, int64_t n, const float* X, float* y);
+
+/*
  * One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
  * step count `step` >= 1, learning rate lr) on the mean squared error
  * L = (1/n) sum_b (network(X[b]) - target[b])^2 of a batch of n states.

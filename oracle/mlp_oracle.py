@@ -51,6 +51,28 @@ def forward(p, X):
     return y, (Z1, A1, Z2, A2)
 
 
+def to_bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64:
+    BF16 keeps the sign, the 8 exponent bits and the top 7 mantissa bits of
+    IEEE binary32, so x is first rounded to binary32, then its low 16 bits
+    are rounded off with ties going to the even upper half."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    low = b & 0xFFFF
+    up = b >> 16
+    round_up = (low > 0x8000) | ((low == 0x8000) & ((up & 1) == 1))
+    up = up + round_up.astype(np.uint64)
+    return (up << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, X):
+    """The network with BF16 operands: X, W1, the hidden activations, W2 and
+    w3 rounded by ``to_bf16``; sums, biases and GELU exact (FP64 here)."""
+    q = unpack(p)
+    A1 = to_bf16(gelu(to_bf16(X) @ to_bf16(q["W1"]).T + q["b1"]))
+    A2 = to_bf16(gelu(A1 @ to_bf16(q["W2"]).T + q["b2"]))
+    return A2 @ to_bf16(q["w3"]) + q["b3"][0], (A1, A2)
+
+
 def loss(p, X, t):
     y, _ = forward(p, X)
     return float(np.mean((y - t) ** 2))

@@ -123,6 +123,84 @@ __global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t len
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
+// BF16 inference of the whole network, one workgroup (4 waves) per 64 rows,
+// 16 rows per wave.  Every matrix operand is rounded to BF16 (nearest even):
+// X, W1, the first hidden activations, W2, the second hidden activations and
+// w3; products on v_mfma_f32_16x16x32_bf16 (layer 1's k = 16 padded to 32
+// with zeros) with FP32 accumulation; biases and GELU in FP32; the output
+// layer is an FP32 dot product of the BF16 values.  Fragments: lane l holds
+// k = 8 (l / 16) .. + 7 of row l % 16 (A) or column l % 16 (B); accumulator
+// element q of lane l is row 4 (l / 16) + q, column l % 16.
+constexpr int kBfPitch = kHid + 8;  // LDS row pitch (272 bytes: 16-byte aligned rows)
+__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const float* __restrict__ P, int64_t n,
+                                                          const float* __restrict__ X,
+                                                          float* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) __bf16 W2s[kHid * kBfPitch];
+  __shared__ __attribute__((aligned(16))) __bf16 W1s[kHid * 40];
+  __shared__ __attribute__((aligned(16))) __bf16 Hs[4][16 * kBfPitch];
+  __shared__ float w3s[kHid];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kHid * kHid; e += 256)
+    W2s[(e / kHid) * kBfPitch + (e % kHid)] = (__bf16)P[kOffW2 + e];
+  for (int e = tid; e < kHid * 32; e += 256) {
+    const int j = e / 32, k = e % 32;
+    W1s[j * 40 + k] = k < kIn ? (__bf16)P[kOffW1 + j * kIn + k] : (__bf16)0.0f;
+  }
+  if (tid < kHid) w3s[tid] = (float)(__bf16)P[kOffW3 + tid];
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int rl = lane & 15, kg = lane >> 4;
+  // layer 1: A = X rows (k 0..15, zeros beyond)
+  bf16x8 a;
+  {
+    const int64_t row = r0 + rl;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * kg + j;
+      a[j] = (row < n && k < kIn) ? (__bf16)X[row * kIn + k] : (__bf16)0.0f;
+    }
+  }
+  __bf16* H = Hs[wave];
+#pragma unroll
+  for (int jt = 0; jt < kHid / 16; ++jt) {
+    const int col = jt * 16 + rl;
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(&W1s[col * 40 + 8 * kg]);
+    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    const float bias = P[kOffB1 + col];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) H[(4 * kg + q) * kBfPitch + col] = (__bf16)gelu(acc[q] + bias);
+  }
+  __syncthreads();
+  // layer 2 and the output layer
+  float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int jt = 0; jt < kHid / 16; ++jt) {
+    const int col = jt * 16 + rl;
+    f32x4 acc{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kHid / 32; ++ks) {
+      const bf16x8 ha = *reinterpret_cast<const bf16x8*>(&H[rl * kBfPitch + ks * 32 + 8 * kg]);
+      const bf16x8 wb = *reinterpret_cast<const bf16x8*>(&W2s[col * kBfPitch + ks * 32 + 8 * kg]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha, wb, acc, 0, 0, 0);
+    }
+    const float bias = P[kOffB2 + col];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[q] += (float)(__bf16)gelu(acc[q] + bias) * w3s[col];
+  }
+  // sum over the 16 lanes of a row group (the columns), fixed pattern
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) part[q] += __shfl_xor(part[q], off, 64);
+  if (rl == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = r0 + 4 * kg + q;
+      if (row < n) y[row] = part[q] + P[kOffB3];
+    }
+  }
+}
+
 // Per-state features of the first iteration (see qsgw.h), standardized as
 // (f - mean) / scale when mean is given.
 __global__ void k_mlp_features(int64_t nbf, int64_t nocc, const double* eps, const double* diag,
@@ -243,6 +321,17 @@ int qsgw_mlp_forward(qsgw_ctx* c, const float* params, int64_t n, const float* X
                      params + kOffW3, params + kOffB3, n, (const float*)nullptr, y, (float*)nullptr,
                      (double*)nullptr);
   return launch_check(c, "k_mlp_out");
+}
+
+int qsgw_mlp_forward_bf16(qsgw_ctx* c, const float* params, int64_t n, const float* X, float* y) {
+  if (!c) return QSGW_ERR_INVALID_ARG;
+  CHECK(check_n(c, n));
+  if (!params || !X || !y) return fail(c, QSGW_ERR_INVALID_ARG, "null pointer");
+  CHECK(check_finite(c, "qsgw_mlp_forward_bf16",
+                     {fin32(params, kNParams, "params"), fin32(X, n * kIn, "X")}));
+  hipLaunchKernelGGL(k_mlp_forward_bf16, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, c->stream,
+                     params, n, X, y);
+  return launch_check(c, "k_mlp_forward_bf16");
 }
 
 int qsgw_mlp_train_step(qsgw_ctx* c, float* params, float* adam_m, float* adam_v, int64_t step,

@@ -53,7 +53,8 @@ EXPORTS = ("qsgw_version", "qsgw_ctx_create", "qsgw_ctx_destroy", "qsgw_last_err
            "qsgw_gw_unrestricted", "qsgw_fock_unrestricted", "qsgw_hf_core", "qsgw_iterate",
            "qsgw_iterate_batched", "qsgw_mlp_features", "qsgw_mlp_forward",
            "qsgw_mlp_train_step", "qsgw_warm_start", "qsgw_set_tiles", "qsgw_get_tiles",
-           "qsgw_set_eigensolver", "qsgw_sigma_qs_noalloc", "qsgw_iterate_unrestricted")
+           "qsgw_set_eigensolver", "qsgw_sigma_qs_noalloc", "qsgw_iterate_unrestricted",
+           "qsgw_mlp_forward_bf16")
 
 
 class QsgwError(RuntimeError):
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
                                   ct.POINTER(Options), ct.POINTER(Report)], I),
         "qsgw_mlp_features": ([P, I64, I64, P, P, P, P, P], I),
         "qsgw_mlp_forward": ([P, P, I64, P, P], I),
+        "qsgw_mlp_forward_bf16": ([P, P, I64, P, P], I),
         "qsgw_mlp_train_step": ([P, P, P, P, I64, D, I64, P, P, P, P], I),
         "qsgw_warm_start": ([P, I64, P, P, P, P, P], I),
         "qsgw_set_tiles": ([P, ct.c_char_p], I),
@@ -504,14 +506,21 @@ def qsgw_mlp_features(ctx: Context, eps, diag, nocc, mean=None, scale=None, out=
     return out
 
 
-def qsgw_mlp_forward(ctx: Context, params, X, out=None):
+def qsgw_mlp_forward(ctx: Context, params, X, out=None, bf16=False):
+    """Network outputs for the rows of X; bf16=True runs the BF16 inference
+    entry point (qsgw_mlp_forward_bf16)."""
     n = X.shape[0]
     if out is None:
         out = torch.empty((n,), dtype=torch.float32, device=X.device)
-    ctx.check(lib().qsgw_mlp_forward(ctx.handle, _ptr(params, (MLP_NPARAMS,), torch.float32, "params"),
-                                     n, _ptr(X, (n, MLP_NFEAT), torch.float32, "X"),
-                                     _ptr(out, (n,), torch.float32, "y")))
+    fn = lib().qsgw_mlp_forward_bf16 if bf16 else lib().qsgw_mlp_forward
+    ctx.check(fn(ctx.handle, _ptr(params, (MLP_NPARAMS,), torch.float32, "params"),
+                 n, _ptr(X, (n, MLP_NFEAT), torch.float32, "X"), _ptr(out, (n,), torch.float32, "y")))
     return out
+
+
+def qsgw_mlp_forward_bf16(ctx: Context, params, X, out=None):
+    """BF16 inference of the network (qsgw_mlp_forward_bf16)."""
+    return qsgw_mlp_forward(ctx, params, X, out, bf16=True)
 
 
 def qsgw_mlp_train_step(ctx: Context, params, adam_m, adam_v, step, lr, X, target, grad=None,
