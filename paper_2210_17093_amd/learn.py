@@ -220,6 +220,64 @@ def predict(ctx, stream, P, tscale, X, bf16=True):
     return y
 
 
+def evaluate_warm(ctx, stream, name, mols, plain, dhat, sizes, max_iter):
+    """Warm path of one reading for a batch of held-out molecules: the first
+    warm iteration judges every state's prediction (moved by more than
+    10 meV: rejected, the state follows the plain iteration from there), then
+    the warm path runs to TOL.  One row per molecule: plain and warm
+    iteration counts (the warm cost includes the feature iteration; a warm
+    path that does not converge adds the plain path), rejected states and
+    the per-state prediction error against the converged plain result."""
+    starts = []
+    with torch.cuda.stream(stream):
+        for m, r, d in zip(mols, plain, torch.split(dhat, sizes)):
+            e_base, C_base = (m["e0"], m["C0"]) if name == "hf" else (r["eps1"], r["C1"])
+            starts.append(q.qsgw_warm_start(ctx, e_base, C_base, d.contiguous()))
+    stream.synchronize()
+    runs, h1 = iterate(ctx, stream, mols, starts, 1)
+    judged = [(r["eps"] - s0[0]).abs().cpu().numpy() for r, s0 in zip(runs, starts)]
+    h2 = resume(ctx, stream, runs, max_iter - 1)
+    rows = []
+    for m, r, d, a, b, mv, s0 in zip(mols, plain, torch.split(dhat, sizes), h1, h2, judged,
+                                     starts):
+        h = list(a) + list(b)
+        true = None
+        start_gap = base_gap = None
+        if r["iters"]:
+            base = m["e0"] if name == "hf" else r["eps1"]
+            true = (r["eps"] - base).double().cpu().numpy()
+            # distance of the warm start and of the unshifted start from the fixed point
+            start_gap = (s0[0] - r["eps"]).abs().cpu().numpy()
+            base_gap = (base - r["eps"]).abs().cpu().numpy()
+        state_err = np.abs(d.double().cpu().numpy() - true) if true is not None else None
+        rejected = mv > FALLBACK_HA
+        warm = first_below(h)
+        if warm is not None:
+            cost = 1 + warm  # feature iteration + warm path
+        elif r["iters"] is not None:
+            cost = 1 + max_iter + r["iters"]  # the warm path failed: the plain path too
+        else:
+            cost = None
+        bad = state_err > FALLBACK_HA if state_err is not None else None
+        rows.append(dict(plain=r["iters"], warm=warm, cost=cost, rejected=int(rejected.sum()),
+                         states=int(mv.size), err=state_err, start_gap=start_gap,
+                         base_gap=base_gap,
+                         bad_accepted=int((bad & ~rejected).sum()) if bad is not None else 0,
+                         good_rejected=int((~bad & rejected).sum()) if bad is not None else 0))
+    return rows
+
+
+def _gap(rows, key, per_molecule):
+    """Median over held-out molecules (per_molecule = np.max: of each
+    molecule's largest state distance) or over all states (np.median), meV."""
+    vals = [x[key] for x in rows if x[key] is not None]
+    if not vals:
+        return None
+    if per_molecule is np.median:
+        return float(np.median(np.concatenate(vals)) * HARTREE_MEV)
+    return float(np.median([per_molecule(v) for v in vals]) * HARTREE_MEV)
+
+
 def run(n_train=1024, n_test=256, epochs=150, max_iter=MAX_ITER, log=print):
     """Full protocol; returns a dict of results."""
     from qsgw_inputs import batch_shapes
@@ -263,48 +321,27 @@ def run(n_train=1024, n_test=256, epochs=150, max_iter=MAX_ITER, log=print):
     res["train_seconds"] = time.perf_counter() - t1
     res["train_states"] = int(X_tr.shape[0])
     res["train_molecules_converged"] = conv_tr
-    # held-out molecules: plain, then each warm reading
-    mols = build_molecules(ctx, stream, te_shapes)
-    plain = solve_plain(ctx, stream, mols, max_iter=max_iter)
-    X = features(ctx, stream, mols, plain, mean, scale)
-    sizes = [m["nbf"] for m in mols]
-    res["test_converged_plain"] = sum(r["iters"] is not None for r in plain)
+    # held-out molecules, in batches of 256: plain, then each warm reading
+    rows_by = {name: [] for name in nets}
+    bf16_dev = {name: 0.0 for name in nets}
+    res["test_converged_plain"] = 0
+    for b0 in range(0, n_test, 256):
+        mols = build_molecules(ctx, stream, te_shapes[b0:b0 + 256])
+        plain = solve_plain(ctx, stream, mols, max_iter=max_iter)
+        X = features(ctx, stream, mols, plain, mean, scale)
+        sizes = [m["nbf"] for m in mols]
+        res["test_converged_plain"] += sum(r["iters"] is not None for r in plain)
+        for name, (P, tscale) in nets.items():
+            dhat = predict(ctx, stream, P, tscale, X)
+            d32 = predict(ctx, stream, P, tscale, X, bf16=False)
+            bf16_dev[name] = max(bf16_dev[name], float((dhat - d32).abs().max().item()))
+            rows_by[name].extend(evaluate_warm(ctx, stream, name, mols, plain, dhat, sizes,
+                                               max_iter))
+        log(f"[learn] held-out molecules {b0 + len(mols)}/{n_test} evaluated "
+            f"({time.perf_counter() - t0:.0f} s)")
+        del mols, plain, X
     res["variants"] = {}
-    for name, (P, tscale) in nets.items():
-        dhat = predict(ctx, stream, P, tscale, X)
-        d32 = predict(ctx, stream, P, tscale, X, bf16=False)
-        starts = []
-        with torch.cuda.stream(stream):
-            for m, r, d in zip(mols, plain, torch.split(dhat, sizes)):
-                e_base, C_base = (m["e0"], m["C0"]) if name == "hf" else (r["eps1"], r["C1"])
-                starts.append(q.qsgw_warm_start(ctx, e_base, C_base, d.contiguous()))
-        stream.synchronize()
-        # the first warm iteration judges every state's prediction, then the
-        # warm path runs on
-        runs, h1 = iterate(ctx, stream, mols, starts, 1)
-        judged = [(r["eps"] - s0[0]).abs().cpu().numpy() for r, s0 in zip(runs, starts)]
-        h2 = resume(ctx, stream, runs, max_iter - 1)
-        rows = []
-        for m, r, d, a, b, mv in zip(mols, plain, torch.split(dhat, sizes), h1, h2, judged):
-            h = list(a) + list(b)
-            true = None
-            if r["iters"]:
-                base = m["e0"] if name == "hf" else r["eps1"]
-                true = (r["eps"] - base).double().cpu().numpy()
-            state_err = np.abs(d.double().cpu().numpy() - true) if true is not None else None
-            rejected = mv > FALLBACK_HA
-            warm = first_below(h)
-            if warm is not None:
-                cost = 1 + warm  # feature iteration + warm path
-            elif r["iters"] is not None:
-                cost = 1 + max_iter + r["iters"]  # the warm path failed: the plain path too
-            else:
-                cost = None
-            bad = state_err > FALLBACK_HA if state_err is not None else None
-            rows.append(dict(plain=r["iters"], warm=warm, cost=cost, rejected=int(rejected.sum()),
-                             states=int(mv.size), err=state_err,
-                             bad_accepted=int((bad & ~rejected).sum()) if bad is not None else 0,
-                             good_rejected=int((~bad & rejected).sum()) if bad is not None else 0))
+    for name, rows in rows_by.items():
         both = [x for x in rows if x["plain"] is not None and x["cost"] is not None]
         errs = [x["err"] for x in rows if x["err"] is not None]
         errs = np.concatenate(errs) if errs else np.zeros(0)
@@ -322,7 +359,14 @@ def run(n_train=1024, n_test=256, epochs=150, max_iter=MAX_ITER, log=print):
             prediction_err_meV_median=float(np.median(errs) * HARTREE_MEV) if errs.size else None,
             prediction_err_meV_p90=float(np.percentile(errs, 90) * HARTREE_MEV) if errs.size else None,
             prediction_within_10meV=float(np.mean(errs <= FALLBACK_HA)) if errs.size else None,
-            bf16_vs_fp32_inference_max_meV=float((dhat - d32).abs().max().item() * HARTREE_MEV))
+            bf16_vs_fp32_inference_max_meV=bf16_dev[name] * HARTREE_MEV,
+            # distance to the converged energies of the warm start and of the
+            # unshifted start (Hartree-Fock or first iteration): per state, and
+            # the largest state of each molecule
+            start_gap_state_meV_median=_gap(rows, "start_gap", np.median),
+            unshifted_gap_state_meV_median=_gap(rows, "base_gap", np.median),
+            start_gap_molecule_max_meV_median=_gap(rows, "start_gap", np.max),
+            unshifted_gap_molecule_max_meV_median=_gap(rows, "base_gap", np.max))
         log(f"[learn] warm start '{name}': {res['variants'][name]}")
     best = "first"  # the reading reported as the result; both are listed
     res["reported"] = best
