@@ -484,8 +484,11 @@ int qsgw_iterate_unrestricted(qsgw_ctx* ctx, const qsgw_problem* prob, int64_t n
  * the kernel segments between eigensolves are captured into hipGraphs on the
  * first iteration and replayed on every iteration (this needs a context
  * created on a stream other than the legacy default stream).
- * Every molecule runs opt->max_iter iterations (opt->s_block must be 0 and
- * precision FP64 or FP32; with opt->mix != 1 every state needs a Vc buffer,
+ * Every molecule runs opt->max_iter iterations (opt->s_block must be 0;
+ * precision FP64, FP32 (MO transform, Casida, rho' and residue products on
+ * the FP32 matrix cores) or SPLIT_BF16 (Casida, rho' and residue products as
+ * split-BF16 products, the MO transform on the FP32 matrix cores); the qsGW
+ * product and the Fock update stay FP64; with opt->mix != 1 every state needs a Vc buffer,
  * mixed as in qsgw_iterate from the molecule's own iteration count; the
  * diag outputs of a state are written during the call's first iteration);
  * a report's converged field says

@@ -350,7 +350,9 @@ int launch_grouped(qsgw_ctx* c, const char* what, const GemmJob<OA, OB, EPI>* jo
   int64_t grid = nwg;
   if (c->tiles.persistent > 0 && grid > c->tiles.persistent * kComputeUnits)
     grid = c->tiles.persistent * kComputeUnits;
-  hipLaunchKernelGGL((gemm_grouped_kernel<BM, BN, OA, OB, EPI, TRI, 16, CT>), dim3((unsigned)grid),
+  // (the split-BF16 products take k tiles of 32, one BF16 instruction's depth)
+  constexpr int BK = is_bf16x3<CT>::value ? 32 : 16;
+  hipLaunchKernelGGL((gemm_grouped_kernel<BM, BN, OA, OB, EPI, TRI, BK, CT>), dim3((unsigned)grid),
                      dim3(256), 0, c->stream, jobs, njobs, nwg);
   return launch_check(c, what);
 }
@@ -403,15 +405,17 @@ struct Jobs {
   int64_t nv, nmix;
 };
 
-template <class CT>
+// CTM: arithmetic of the MO transform, CT: of the Casida build (split-BF16
+// keeps the MO transform on the FP32 matrix cores, as the single path does)
+template <class CTM, class CT>
 int segment_a(qsgw_ctx* c, Plan& P, const Jobs& J, Spans* sp) {
   const int64_t nmol = (int64_t)P.mols.size();
   hipLaunchKernelGGL(kb_zero_flags, dim3(blocks_for(nmol)), dim3(256), 0, c->stream, P.dmols, nmol);
   SPAN_OPEN(sp, kKMo1);
-  CHECK((launch_shape<false, CT>(c, c->tiles.shape[TU_MO1], "batched mo/1", J.mo1, J.n, J.mo1_wg)));
+  CHECK((launch_shape<false, CTM>(c, c->tiles.shape[TU_MO1], "batched mo/1", J.mo1, J.n, J.mo1_wg)));
   SPAN_CLOSE(sp);
   SPAN_OPEN(sp, kKMo2);
-  CHECK((launch_shape<true, CT>(c, c->tiles.shape[TU_MO2], "batched mo/2", J.mo2, J.n, J.mo2_wg)));
+  CHECK((launch_shape<true, CTM>(c, c->tiles.shape[TU_MO2], "batched mo/2", J.mo2, J.n, J.mo2_wg)));
   SPAN_CLOSE(sp);
   SPAN_OPEN(sp, kKCasida);
   hipLaunchKernelGGL(kb_transitions, dim3(blocks_for(P.total[S_NTR])), dim3(256), 0, c->stream,
@@ -570,7 +574,8 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
                                     qsgw_report* reports) {
   if (!c) return QSGW_ERR_INVALID_ARG;
   if (nmol < 1 || !probs || !states || !o) return fail(c, QSGW_ERR_INVALID_ARG, "bad arguments");
-  if (o->precision != QSGW_PREC_FP64 && o->precision != QSGW_PREC_FP32)
+  if (o->precision != QSGW_PREC_FP64 && o->precision != QSGW_PREC_FP32 &&
+      o->precision != QSGW_PREC_SPLIT_BF16)
     return fail(c, QSGW_ERR_UNSUPPORTED, "precision %d is not available", o->precision);
   if (!(o->eta > 0.0) || !isfinite(o->eta)) return fail(c, QSGW_ERR_INVALID_ARG, "need eta > 0");
   if (o->max_iter < 1) return fail(c, QSGW_ERR_INVALID_ARG, "need max_iter >= 1");
@@ -585,7 +590,10 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
     return fail(c, QSGW_ERR_UNSUPPORTED, "diis: qsgw_iterate only");
   if (o->flags & ~(int64_t)QSGW_OPT_GRAPH)
     return fail(c, QSGW_ERR_UNSUPPORTED, "flags other than QSGW_OPT_GRAPH");
-  const bool fp32 = o->precision == QSGW_PREC_FP32;
+  // reduced precision: FP32 or split-BF16 products (FP32 accumulation, each
+  // workgroup's k range bounded as in the single path)
+  const bool fp32 = o->precision != QSGW_PREC_FP64;
+  const bool x3 = o->precision == QSGW_PREC_SPLIT_BF16;
 
   // ------------------------------------------------------------ layout --
   Plan P;
@@ -886,8 +894,12 @@ extern "C" int qsgw_iterate_batched(qsgw_ctx* c, int64_t nmol, const qsgw_proble
   // follows A, the Fock eigensolve B2; the per-state diagonal outputs run
   // between B1 and B2 on the first iteration only
   auto seg = [&](int k, Spans* ks) -> int {
-    if (k == 0) return fp32 ? segment_a<float>(c, P, J, ks) : segment_a<double>(c, P, J, ks);
-    if (k == 1) return fp32 ? segment_b<float>(c, P, J, ks) : segment_b<double>(c, P, J, ks);
+    if (k == 0)
+      return x3 ? segment_a<float, Bf16x3>(c, P, J, ks)
+                : fp32 ? segment_a<float, float>(c, P, J, ks) : segment_a<double, double>(c, P, J, ks);
+    if (k == 1)
+      return x3 ? segment_b<Bf16x3>(c, P, J, ks)
+                : fp32 ? segment_b<float>(c, P, J, ks) : segment_b<double>(c, P, J, ks);
     if (k == 2) return segment_b2(c, P, J, ks);
     return segment_c(c, P, J, ks);
   };

@@ -661,8 +661,10 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
     constexpr int RUN = MP::kc ? 4 : 8;
     if (kv < BK) {
       // (the empty asm makes the bound opaque, so that the compares stay in
-      // this rarely taken branch instead of being hoisted into every k tile)
-      int kvo = kv;
+      // this rarely taken branch instead of being hoisted into every k tile;
+      // kv is uniform over the workgroup, readfirstlane puts it in a scalar
+      // register also where the compiler could not prove that)
+      int kvo = __builtin_amdgcn_readfirstlane(kv);
       asm volatile("" : "+s"(kvo));
 #pragma unroll
       for (int e = 0; e < E; ++e)

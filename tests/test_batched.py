@@ -309,3 +309,65 @@ def test_sigma_diag_self_mode_against_oracle():
         der = O.sigma_diag_derivative(w, p.eps0, Om, p.nocc, 1e-3, mm, p.eps0[mm])
         ref = np.array([sig.real, sig.imag, der.real])
         np.testing.assert_allclose(got[j], ref, rtol=1e-11, atol=1e-13)
+
+
+def test_batched_split_bf16_within_the_gate(env):
+    """The batched split-BF16 variant (Casida, rho' and residue products as
+    hi*hi + hi*lo + lo*hi BF16 products with FP32 accumulation, MO transform
+    on the FP32 matrix cores, qsGW product in FP64) against FP64: 1 meV per
+    state after one iteration; the graph-captured batch equals the eager
+    one."""
+    q, ctx, stream, probs = env
+    rc, reps, mols = run_batch(q, ctx, stream, probs, 1, precision=q.PREC_SPLIT_BF16)
+    _, _, mols_g = run_batch(q, ctx, stream, probs, 1, graph=True, precision=q.PREC_SPLIT_BF16)
+    for x, m, g in zip(probs, mols, mols_g):
+        e64, _, _ = single(q, ctx, stream, x, 1)
+        eb = m["eps"].cpu().numpy()
+        err = np.max(np.abs(eb - e64))
+        print(f"split-BF16 nbf={x['p'].nbf}: batched vs FP64 {err:.2e} Ha", flush=True)
+        assert err <= FP32_TOL, (x["p"].nbf, err)
+        assert float((m["eps"] - g["eps"]).abs().max()) <= 1e-12
+
+
+def test_full_256_molecule_batch():
+    """The batched workload's whole job table: one iteration over all 256
+    molecules of batch_shapes() (every size bucket the distribution draws, in
+    one launch per stage, graph-captured as the benchmark runs it) against
+    single-instance runs of each molecule (1e-8 Ha), and the smallest and a
+    mid-sized molecule against the oracle."""
+    import oracle as O
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2210_17093_amd.qsgw as q
+    from paper_2210_17093_amd.learn import _draw
+    shapes_all = batch_shapes(256)
+    print("256-molecule batch: drawing inputs", flush=True)
+    probs_np = _draw(shapes_all)
+    stream = torch.cuda.Stream()
+    dev = torch.device("cuda:0")
+    with q.Context(stream) as ctx:
+        probs = []
+        with torch.cuda.stream(stream):
+            for p in probs_np:
+                B = torch.from_numpy(p.B_ao).to(dev)
+                C0 = torch.from_numpy(p.C0.copy()).to(dev)
+                e0 = torch.from_numpy(p.eps0.copy()).to(dev)
+                probs.append(dict(p=p, B=B, C0=C0, e0=e0, h=q.qsgw_hf_core(ctx, B, C0, e0, p.nocc)))
+        stream.synchronize()
+        print("256-molecule batch: one batched iteration", flush=True)
+        rc, reps, mols = run_batch(q, ctx, stream, probs, 1, graph=True)
+        worst = 0.0
+        for x, m in zip(probs, mols):
+            e1, _, _ = single(q, ctx, stream, x, 1)
+            err = float(np.max(np.abs(m["eps"].cpu().numpy() - e1)))
+            worst = max(worst, err)
+            assert err <= QP_TOL, (x["p"].nbf, x["p"].meta["seed"], err)
+        print(f"256 molecules: max|eps batched - single| = {worst:.2e} Ha", flush=True)
+        nbfs = [x["p"].nbf for x in probs]
+        picks = [int(np.argmin(nbfs)), int(np.argsort(nbfs)[len(nbfs) // 4])]
+        for i in picks:
+            p = probs[i]["p"]
+            print(f"  oracle: nbf={p.nbf} naux={p.naux} nocc={p.nocc}", flush=True)
+            h = O.hf_core(p.B_ao, p.C0, p.eps0, p.nocc)
+            eps, _, _ = O.qsgw_iterate(p.B_ao, h, p.C0, p.eps0, p.nocc, ETA, 0.0, 1)
+            assert np.max(np.abs(mols[i]["eps"].cpu().numpy() - eps)) <= QP_TOL
