@@ -46,8 +46,9 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // Householder QR of one panel (m x b, column-major, ld lda), one launch per
-// column j with a partition of the rows over the workgroups (kPanelRows
-// rows each).  Column j's reflector needs dots[c] = sum_{r > j} P[r][j] P[r][c]
+// column j with a partition of the rows over the workgroups (256 RPT rows
+// each: RPT = 1 spreads a panel of up to 16,384 rows over at least 64
+// compute units, RPT = 2 halves the partial sums of taller panels).  Column j's reflector needs dots[c] = sum_{r > j} P[r][j] P[r][c]
 // (c >= j) of the current panel: the launch for column j - 1 leaves one
 // partial sum per workgroup (part_in[g][c]) and every workgroup of the launch
 // for column j adds them up in a fixed order.  Then, with the LAPACK dlarfg
@@ -57,7 +58,7 @@ __device__ __forceinline__ double wave_sum(double x) {
 // and row j of R goes to Rbuf (P's row j is left as it was: every workgroup
 // reads it).  Each workgroup then leaves its partial dots for column j + 1.
 // j = -1 only computes the partial dots of column 0.
-constexpr int kPanelRows = 512;
+template <int RPT>
 __global__ __launch_bounds__(256) void k_panel_col(double* __restrict__ P, int64_t lda, int64_t m,
                                                    int b, int j, const double* __restrict__ part_in,
                                                    double* __restrict__ part_out, int G,
@@ -68,8 +69,7 @@ __global__ __launch_bounds__(256) void k_panel_col(double* __restrict__ P, int64
   __shared__ double red[4][kBand];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
-  const int64_t rbase = (int64_t)g * kPanelRows;
-  constexpr int RPT = kPanelRows / 256;
+  const int64_t rbase = (int64_t)g * (256 * RPT);
   if (j >= 0) {
     // column j's dots from the previous launch's partial sums
     if (tid < kBand) {
@@ -736,14 +736,21 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
     }
     if (m >= 2 * b) {
       // one launch per column (see k_panel_col)
-      const int G = (int)((m + kPanelRows - 1) / kPanelRows);
+      const int rpt = m > 16384 ? 2 : 1;  // rows per thread
+      const int G = (int)((m + 256 * rpt - 1) / (256 * rpt));
       double *part, *Rbuf;
       CHECK(ws_get(c, W_EIG_PANEL, (size_t)(2 * G * b + b * b), &part));
       Rbuf = part + 2 * G * b;
-      for (int jc = -1; jc < b; ++jc)
-        hipLaunchKernelGGL(k_panel_col, dim3((unsigned)G), dim3(256), 0, c->stream, P, n, m, b, jc,
-                           part + (size_t)((jc + 2) & 1) * G * b, part + (size_t)((jc + 1) & 1) * G * b,
-                           G, Rbuf, tau1 + p * b);
+      for (int jc = -1; jc < b; ++jc) {
+        double* pin = part + (size_t)((jc + 2) & 1) * G * b;
+        double* pout = part + (size_t)((jc + 1) & 1) * G * b;
+        if (rpt == 2)
+          hipLaunchKernelGGL(k_panel_col<2>, dim3((unsigned)G), dim3(256), 0, c->stream, P, n, m, b,
+                             jc, pin, pout, G, Rbuf, tau1 + p * b);
+        else
+          hipLaunchKernelGGL(k_panel_col<1>, dim3((unsigned)G), dim3(256), 0, c->stream, P, n, m, b,
+                             jc, pin, pout, G, Rbuf, tau1 + p * b);
+      }
       hipLaunchKernelGGL(k_panel_r, dim3(blocks_for(b * b)), dim3(256), 0, c->stream, P, n, b, Rbuf);
       CHECK(launch_check(c, "k_panel_col"));
     } else {

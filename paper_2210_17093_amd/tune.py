@@ -39,8 +39,11 @@ CANDIDATES = {
     "casida": (["128x128", "64x64"], ["casida"]),
     "rho": (["128x128", "128x64", "64x64"], ["residue_rho"]),
     "rho_target": ([2048, 1024, 4096], ["residue_rho"]),
-    "sigma": (["64x64", "128x64", "128x128"], ["sigma_qs_gemm", "sigma_qs_reduce"]),
-    "sigma_target": ([4096, 2048, 8192, 16384, 32768], ["sigma_qs_gemm", "sigma_qs_reduce"]),
+    # the qsGW product's tile shape and K-split target interact (small tiles
+    # pay off only with many splits): they are searched jointly
+    "sigma+sigma_target": ([f"{sh}+{tg}" for sh in ("64x64", "128x64", "128x128")
+                            for tg in (4096, 16384, 32768, 65536, 131072)],
+                           ["sigma_qs_gemm", "sigma_qs_reduce"]),
     "exchange": (["64x64", "128x128"], ["fock"]),
     "persistent": ([0, 2, 4], ["mo_transform_1", "mo_transform_2", "casida", "residue_rho",
                                "residue_w", "sigma_qs_gemm", "fock"]),
@@ -52,6 +55,15 @@ DEFAULTS = {"mo1": "128x64", "mo2": "64x64", "casida": "128x128", "rho": "128x12
 
 def spec_of(table):
     return ",".join(f"{k}={v}" for k, v in table.items())
+
+
+def assign(table, key, value):
+    """Set one candidate: a joint key "a+b" takes a value "x+y"."""
+    if "+" in key:
+        for k, v in zip(key.split("+"), str(value).split("+")):
+            table[k] = v
+    else:
+        table[key] = value
 
 
 def log(*a):
@@ -145,7 +157,7 @@ def tune(name, reps=3):
         scores = {}
         for v in values:
             table = dict(best)
-            table[key] = v
+            assign(table, key, v)
             try:
                 outs = [run(spec_of(table)) for _ in range(reps)]
             except q.QsgwError as err:
@@ -159,7 +171,7 @@ def tune(name, reps=3):
             scores[v] = float(np.median(ts))
             trials.append(dict(key=key, value=v, ms=scores[v]))
             log(f"[tune] {name} {key}={v}: {scores[v]:.3f} ms")
-        best[key] = min(scores, key=scores.get)
+        assign(best, key, min(scores, key=scores.get))
     kd = [run(spec_of(DEFAULTS))[0] for _ in range(reps)]
     kb = [run(spec_of(best))[0] for _ in range(reps)]
     default_ms = {k: float(np.median([x[k] for x in kd])) for k in kd[0]}
