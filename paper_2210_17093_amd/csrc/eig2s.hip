@@ -13,8 +13,8 @@
 //      each step k >= 1 re-applies the previous reflector to the block of
 //      rows [i+1+kb, i+(k+1)b] it fills, annihilates that block's first
 //      column and applies the new reflector to the diagonal block.  Step k
-//      of sweep i runs at time 3i + k: the steps sharing a time touch
-//      disjoint columns of the band, so each time is one launch with one
+//      of sweep i runs at time 2i + k: the steps sharing a time touch
+//      disjoint rows of the band, so each time is one launch with one
 //      workgroup per step, and the result equals the sweep-by-sweep order;
 //   3. tridiagonal eigenproblem: rocSOLVER divide and conquer (dstedc),
 //      eigenvectors E of the tridiagonal matrix;
@@ -460,14 +460,23 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   if (tid == 0) tau2[off[i] + k] = tau;
 }
 
-// Step k = t - 3 i of every sweep i of time t, one workgroup each (one launch per time).
+// Bulge-chasing schedule: step k of sweep i runs at time kLag i + k.  Step
+// (i, k) reads and writes the band entries with rows in its window
+// [i + 1 + k b, i + (k + 1) b] (the previous window's columns for k > 0), so
+// the step (i + 1, k - 2) of the same time ends its rows before that window
+// starts, and every entry shared by two steps is reached by the lower sweep
+// first: with lag 2 the steps of one time are independent and the order of
+// the sequential reduction is kept (checked on the CPU entry by entry).
+constexpr int64_t kLag = 2;
+
+// Step k = t - kLag i of every sweep i of time t, one workgroup each (one launch per time).
 __global__ __launch_bounds__(256) void k_bulge(double* __restrict__ AB, int64_t ldab, int64_t n,
                                                int b, double* __restrict__ V2,
                                                double* __restrict__ tau2,
                                                const int64_t* __restrict__ off, int64_t t,
                                                int64_t i_lo) {
   const int64_t i = i_lo + blockIdx.x;
-  const int64_t k = t - 3 * i;
+  const int64_t k = t - kLag * i;
   if (i > n - 3 || k < 0) return;
   const int64_t K = (n - 1 - i + b - 1) / b;
   if (k >= K) return;
@@ -834,7 +843,7 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
     hoff[(size_t)i] = nref;
     const int64_t K = (n - 1 - i + b - 1) / b;
     nref += K;
-    if (3 * i + K > tmax) tmax = 3 * i + K;
+    if (kLag * i + K > tmax) tmax = kLag * i + K;
   }
   const int64_t nJ = ts->nJ = (n - 2 + b - 1) / b;  // groups of g = b sweeps
   const int64_t K0 = ts->K0 = (n - 1 + b - 1) / b;
@@ -863,9 +872,9 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
                      ldab, AB);
   CHECK(launch_check(c, "k_band_extract"));
   for (int64_t t = 0; t < tmax; ++t) {
-    int64_t i_hi = t / 3;
+    int64_t i_hi = t / kLag;
     if (i_hi > n - 3) i_hi = n - 3;
-    int64_t i_lo = t - K0 >= 0 ? (t - K0) / 3 + 1 : 0;  // 3 i > t - K0
+    int64_t i_lo = t - K0 >= 0 ? (t - K0) / kLag + 1 : 0;  // kLag i > t - K0
     if (i_lo > i_hi) continue;
     hipLaunchKernelGGL(k_bulge, dim3((unsigned)(i_hi - i_lo + 1)), dim3(256), 0, c->stream, AB,
                        ldab, n, b, V2, tau2, off, t, i_lo);
