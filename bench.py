@@ -317,6 +317,35 @@ def ao2mo_cpu_baseline(nbf, slab, flops):
                         f"N_b^4 to N_b = {nbf}, slab {slab}; est. s/slab = {est:.1f}"))
 
 
+def bench_converge(q, torch, ctx, B, C0, e0, p, h, name):
+    """The N_b = 300 workload iterated to its fixed point at the paper's
+    broadening (eta = 0.05 Ha) with Pulay DIIS on the Fock matrix (8 pairs):
+    iterations, wall time with both eigensolves, and the distance of the
+    energies to the stored oracle fixed point of the same inputs."""
+    eta, m, tol, cap = 0.05, 8, 1e-8, 40
+    C, e = C0.clone(), e0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, rep, it = q.qsgw_iterate(ctx, B, h, p.nocc, e, C, eta, tol=tol, max_iter=cap, diis=m)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res = dict(eta=eta, diis=m, tol=tol, iterations=it, converged=bool(rep["converged"]),
+               wall_s=round(wall, 3), ms_per_iteration=round(wall * 1e3 / max(it, 1), 1),
+               eig_rpa_ms_total=round(rep["ms"]["eig_rpa"], 1),
+               last_max_deps=rep["max_deps"][-1] if rep["max_deps"] else None)
+    ref = os.path.join(ROOT, "tests", "golden", f"{name}_converged_oracle.json")
+    if os.path.exists(ref):
+        with open(ref) as f:
+            gold = json.load(f)
+        fp = gold.get("fingerprint", {}).get("B_abs", 0.0)
+        if gold.get("eta") == eta and abs(fp - float(np.abs(p.B_ao).sum())) <= 1e-9 * abs(fp):
+            res["max_abs_eps_vs_oracle_fixed_point_Ha"] = float(
+                np.max(np.abs(e.cpu().numpy() - np.array(gold["eps"]))))
+            res["oracle_iterations"] = len(gold["iterations"])
+    log(f"[bench] converged qsGW (eta {eta}, DIIS {m}): {it} iterations, {wall:.1f} s")
+    return res
+
+
 def bench_ao2mo(args, q, torch, ctx, B, C):
     """Four-index AO->MO transform (Eq. 16, no RI) of a slab of AO2MO_SLAB MOs
     with the workload's starting orbitals."""
@@ -563,6 +592,8 @@ def main():
                     help="skip the open-shell GW potential leg (doublet on the workload)")
     ap.add_argument("--uhf-probe", action="store_true",
                     help="only run the open-shell GW potential leg (for profilers)")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the self-consistent run to the fixed point (DIIS, eta 0.05 Ha)")
     ap.add_argument("--no-ao2mo", action="store_true",
                     help="skip the four-index AO->MO transform leg (Eq. 16 without RI)")
     ap.add_argument("--ao2mo-probe", action="store_true",
@@ -831,7 +862,7 @@ def bench_single(args, q, torch):
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, eta, hot_flops)
     del p
-    legs = not (args.no_mp2 and args.no_uhf and args.no_ao2mo)
+    legs = not (args.no_mp2 and args.no_uhf and args.no_ao2mo and args.no_converge)
     if legs:
         lc = args.legs_config
         lcfg = CONFIGS[lc]
@@ -853,6 +884,9 @@ def bench_single(args, q, torch):
                                                                    lp, lcfg["eta"], h)}
             if not args.no_ao2mo:
                 out["ao2mo_4center"] = {"workload": wl, **bench_ao2mo(args, q, torch, ctx, B, C0)}
+            if not args.no_converge:
+                out["converged_qsgw"] = {"workload": wl, **bench_converge(q, torch, ctx, B, C0, e0,
+                                                                          lp, h, lc)}
     print(json.dumps(out), flush=True)
 
 if __name__ == "__main__":
