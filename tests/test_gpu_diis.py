@@ -130,3 +130,29 @@ def test_cfg2_converges_to_oracle_fixed_point(q):
         err = np.max(np.abs(host(e) - np.array(ref["eps"])))
         print(f"  max |eps - oracle fixed point| = {err:.2e} Ha", flush=True)
         assert err <= QP_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_diis_reduced_precision_fixed_point_within_1meV(q, prec):
+    """DIIS with the reduced-precision products (the Fock update and the DIIS
+    extrapolation stay FP64) converges, and its fixed point is within 1 meV
+    per state of the oracle's FP64 fixed point.  The iteration's own noise
+    floor is the products' rounding (about 1e-8 Ha with FP32 products), so the
+    stopping tolerance is 1e-6 Ha (0.03 meV)."""
+    nbf, naux, nocc = 70, 280, 12
+    eta = 0.05
+    p = make_problem(nbf, naux, nocc, naux // 2, 0.99, 3)
+    h_ref = O.hf_core(p.B_ao, p.C0, p.eps0, nocc)
+    eps_ref, _, hist = O.qsgw_iterate(p.B_ao, h_ref, p.C0, p.eps0, nocc, eta, 1e-11, 40, diis=6)
+    assert hist[-1]["max_deps"] < 1e-11
+    pr = {"fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}[prec]
+    with q.Context() as ctx:
+        B, C, e = dev(p.B_ao), dev(p.C0.copy()), dev(p.eps0.copy())
+        h = q.qsgw_hf_core(ctx, B, C, e, nocc)
+        rc, rep, it = q.qsgw_iterate(ctx, B, h, nocc, e, C, eta, tol=1e-6, max_iter=40, diis=6,
+                                     precision=pr)
+        assert rep["converged"] == 1, rep["max_deps"]
+        err = np.max(np.abs(host(e) - eps_ref))
+        print(f"  {prec} DIIS: {it} iterations, max |eps - FP64 fixed point| = {err * 27211.386:.4f} meV",
+              flush=True)
+        assert err <= 1.0 / 27211.386
