@@ -260,6 +260,33 @@ struct EpiSub {
   }
 };
 
+// X -= C for a symmetric product C computed on the upper tiles only (m <= n,
+// a TRI launch): each staged pass of the tile goes out twice, its rows
+// (consecutive threads on consecutive columns) for m <= n and its mirror
+// X[n][m] (consecutive threads on consecutive rows) for m < n, both coalesced.
+// The two halves are disjoint, so X stays exactly symmetric.
+struct EpiSubSym {
+  static constexpr bool kPassHook = true;
+  static constexpr bool kTriPass = true;
+  double* X;
+  int64_t ld;
+  int64_t M;  // order of the product
+  template <int ROWS, int BN>
+  __device__ __forceinline__ void pass(int64_t r0, int64_t n0, const double* Cs, int ldc,
+                                       int tid) const {
+    for (int idx = tid; idx < ROWS * BN; idx += 256) {
+      const int row = idx / BN, col = idx - (idx / BN) * BN;
+      const int64_t m = r0 + row, n = n0 + col;
+      if (n < M && m <= n) X[m * ld + n] -= Cs[row * ldc + col];
+    }
+    for (int idx = tid; idx < ROWS * BN; idx += 256) {
+      const int col = idx / ROWS, row = idx - (idx / ROWS) * ROWS;
+      const int64_t m = r0 + row, n = n0 + col;
+      if (n < M && m < n) X[n * ld + m] -= Cs[row * ldc + col];
+    }
+  }
+};
+
 // Copies the panel's Householder vectors (below the diagonal of the panel QR
 // output, unit diagonal implied) into V [m][kk] column-major (ld m) with an
 // explicit unit diagonal and zeros above it, and into its two columns blocks of
@@ -541,28 +568,33 @@ __global__ __launch_bounds__(256) void k_q2_tfactor(const double* __restrict__ V
 }
 
 // X <- B X for the blocks (J, k) of one anti-diagonal t = (nJ - 1 - J) + k on
-// a slab of kSlabW columns of X ([n][ncols] column-major, ld n):
+// a group of `spg` consecutive slabs of kSlabW columns of X ([n][ncols]
+// column-major, ld n):
 //   trans 0: B = I - V T V^T   (the block's reflectors from its highest sweep
 //            down; anti-diagonals in ascending order give X <- Q2 X);
 //   trans 1: B = I - V T^T V^T (lowest sweep first; anti-diagonals in
 //            descending order give X <- Q2^T X).
-// The block touches rows [J g + 1 + k b, J g + g - 1 + (k + 1) b] of X.  The
-// three products W = V^T X_b, W2 = T W (or T^T W) and X_b -= V W2 run on the
-// FP64 matrix cores (v_mfma_f64_16x16x4: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16], accumulator element q is D[4 q + l / 16][l % 16]), V
-// entries generated from the compact reflector rows (zero outside a
-// reflector's b rows).
+// The block touches rows [J g + 1 + k b, J g + g - 1 + (k + 1) b] of X.  V
+// (generated from the compact reflector rows, zero outside a reflector's b
+// rows) and T are staged in LDS once per workgroup; the slabs then go through
+// one at a time, the next slab's rows loading into registers while the
+// current one is multiplied.  The three products W = V^T X_b, W2 = T W (or
+// T^T W) and X_b -= V W2 run on the FP64 matrix cores (v_mfma_f64_16x16x4:
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16], accumulator element
+// q is D[4 q + l / 16][l % 16]).
 constexpr int kSlabW = 32;
 constexpr int kRows = 2 * kBand;  // b + g - 1 rows, padded
+constexpr int kSlabPre = kSlabW * kRows / 256;  // slab elements per thread
+constexpr int64_t kQ2Wgs = 1024;  // workgroups a band back-transformation launch aims for
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_t n, int64_t ncols,
                                                   int b, const double* __restrict__ V2,
                                                   const int64_t* __restrict__ off,
                                                   const double* __restrict__ Tb,
                                                   const int64_t* __restrict__ boff, int64_t t,
-                                                  int64_t nJ, int64_t J_lo, int64_t nslab,
-                                                  int trans) {
-  const int64_t jj = blockIdx.x / nslab, slab = blockIdx.x - jj * nslab;
+                                                  int64_t nJ, int64_t J_lo, int64_t ngrp,
+                                                  int64_t spg, int trans) {
+  const int64_t jj = blockIdx.x / ngrp, grp = blockIdx.x - jj * ngrp;
   const int64_t J = J_lo + jj;
   const int64_t k = t - (nJ - 1 - J);
   if (J >= nJ || k < 0) return;
@@ -570,6 +602,10 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
   const int64_t c_lo = J * g;
   const int64_t c_hi = min(c_lo + g, n - 2) - 1;
   if (c_hi < c_lo || k >= (n - 1 - c_lo + b - 1) / b) return;
+  const int64_t nslab = (ncols + kSlabW - 1) / kSlabW;
+  const int64_t s0 = grp * spg;
+  const int64_t s1 = min(s0 + spg, nslab);
+  if (s0 >= s1) return;
   __shared__ double Xb[kRows][kSlabW + 1];
   __shared__ double Vb[kBand][kBand + 1];
   __shared__ double Ts[kBand][kBand + 1];
@@ -578,12 +614,6 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
   const int64_t R0 = c_lo + 1 + k * b;
   const int64_t R1 = min(c_hi + (k + 1) * b, n - 1);
   const int NR = (int)(R1 - R0 + 1);
-  const int64_t col0 = slab * kSlabW;
-  const int ncol = (int)min((int64_t)kSlabW, ncols - col0);
-  for (int e = tid; e < kSlabW * kRows; e += 256) {
-    const int cl = e / kRows, r = e - cl * kRows;  // consecutive threads: consecutive rows
-    Xb[r][cl] = (cl < ncol && r < NR) ? X[(col0 + cl) * n + R0 + r] : 0.0;
-  }
   const double* Tg = Tb + (boff[J] + k) * (kBand * kBand);
   for (int e = tid; e < kBand * kBand; e += 256) {
     const int o = e / kBand, a = e - o * kBand;
@@ -592,7 +622,23 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     Vb[o][a] = ok ? V2[(off[c] + k) * b + a] : 0.0;
     Ts[o][a] = Tg[e];
   }
-  __syncthreads();
+  // slab element i of this thread: column cl = (tid + 256 i) / kRows, row
+  // r = tid % kRows (consecutive threads on consecutive rows); rows past the
+  // block and columns past X load a clamped, valid element and are stored to
+  // LDS as zeros, so the loads of a slab need no wait before the next use.
+  const int r_t = tid % kRows;
+  const int cl_t = tid / kRows;
+  const int64_t r_ld = R0 + (r_t < NR ? r_t : NR - 1);
+  double pre[kSlabPre];
+  auto gload = [&](int64_t col0, int ncol) {
+#pragma unroll
+    for (int i = 0; i < kSlabPre; ++i) {
+      const int cl = cl_t + i * (256 / kRows);
+      pre[i] = X[(col0 + (cl < ncol ? cl : ncol - 1)) * n + r_ld];
+    }
+  };
+  auto ncol_of = [&](int64_t sl) { return (int)min((int64_t)kSlabW, ncols - sl * kSlabW); };
+  gload(s0 * kSlabW, ncol_of(s0));
   const int lane = tid & 63, w = tid >> 6;
   const int lm = lane & 15, lk = lane >> 4;
   // V(r, o): reflector o covers block rows o .. o + b - 1
@@ -600,73 +646,88 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     const int a = r - o;
     return (a >= 0 && a < kBand) ? Vb[o][a] : 0.0;
   };
-  // W = V^T X_b: wave w owns rows o of tile w, both column tiles; k = r
-  {
-    f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    const int o = 16 * w + lm;
-    const int ks_hi = min(kRows / 4 - 1, (16 * w + 15 + kBand - 1) / 4);
-    for (int ks = 4 * w; ks <= ks_hi; ++ks) {
-      const int r = 4 * ks + lk;
-      const double av = vat(r, o);
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][lm], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][16 + lm], acc1, 0, 0, 0);
-    }
+  for (int64_t sl = s0; sl < s1; ++sl) {
+    const int64_t col0 = sl * kSlabW;
+    const int ncol = ncol_of(sl);
+    __syncthreads();  // the previous slab's write-out is done with Xb
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      W[16 * w + 4 * q + lk][lm] = acc0[q];
-      W[16 * w + 4 * q + lk][16 + lm] = acc1[q];
-    }
-  }
-  __syncthreads();
-  // W2 = T W or T^T W (T upper triangular), back into W
-  {
-    f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    const int i = 16 * w + lm;
-    const int ks_lo = trans ? 0 : 4 * w, ks_hi = trans ? 4 * w + 3 : kBand / 4 - 1;
-    for (int ks = ks_lo; ks <= ks_hi; ++ks) {
-      const int j = 4 * ks + lk;
-      const double av = trans ? Ts[j][i] : Ts[i][j];
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][lm], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][16 + lm], acc1, 0, 0, 0);
+    for (int i = 0; i < kSlabPre; ++i) {
+      const int cl = cl_t + i * (256 / kRows);
+      Xb[r_t][cl] = (cl < ncol && r_t < NR) ? pre[i] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      W[16 * w + 4 * q + lk][lm] = acc0[q];
-      W[16 * w + 4 * q + lk][16 + lm] = acc1[q];
-    }
-  }
-  __syncthreads();
-  // X_b -= V W2: wave w owns row tiles 2w, 2w + 1, both column tiles; k = o
-  {
-    f64x4_t acc[2][2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-    for (int ks = 0; ks < kBand / 4; ++ks) {
-      const int o = 4 * ks + lk;
-      const double b0 = W[o][lm], b1 = W[o][16 + lm];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const double av = vat(16 * (2 * w + u) + lm, o);
-        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[u][0], 0, 0, 0);
-        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[u][1], 0, 0, 0);
+    if (sl + 1 < s1) gload(col0 + kSlabW, ncol_of(sl + 1));
+    // W = V^T X_b: wave w owns rows o of tile w, both column tiles; k = r
+    {
+      f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      const int o = 16 * w + lm;
+      const int ks_hi = min(kRows / 4 - 1, (16 * w + 15 + kBand - 1) / 4);
+      for (int ks = 4 * w; ks <= ks_hi; ++ks) {
+        const int r = 4 * ks + lk;
+        const double av = vat(r, o);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][lm], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][16 + lm], acc1, 0, 0, 0);
       }
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = 16 * (2 * w + u) + 4 * q + lk;
-        Xb[r][lm] -= acc[u][0][q];
-        Xb[r][16 + lm] -= acc[u][1][q];
+        W[16 * w + 4 * q + lk][lm] = acc0[q];
+        W[16 * w + 4 * q + lk][16 + lm] = acc1[q];
       }
-  }
-  __syncthreads();
-  for (int e = tid; e < kSlabW * kRows; e += 256) {
-    const int c2 = e / kRows, r = e - c2 * kRows;
-    if (c2 < ncol && r < NR) X[(col0 + c2) * n + R0 + r] = Xb[r][c2];
+    }
+    __syncthreads();
+    // W2 = T W or T^T W (T upper triangular), back into W
+    {
+      f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      const int i = 16 * w + lm;
+      const int ks_lo = trans ? 0 : 4 * w, ks_hi = trans ? 4 * w + 3 : kBand / 4 - 1;
+      for (int ks = ks_lo; ks <= ks_hi; ++ks) {
+        const int j = 4 * ks + lk;
+        const double av = trans ? Ts[j][i] : Ts[i][j];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][lm], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][16 + lm], acc1, 0, 0, 0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        W[16 * w + 4 * q + lk][lm] = acc0[q];
+        W[16 * w + 4 * q + lk][16 + lm] = acc1[q];
+      }
+    }
+    __syncthreads();
+    // X_b -= V W2: wave w owns row tiles 2w, 2w + 1, both column tiles; k = o
+    // over the reflectors that reach those rows (o > r - b, o <= r)
+    {
+      f64x4_t acc[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+      const int o_lo = 32 * w - (kBand - 1) > 0 ? 32 * w - (kBand - 1) : 0;
+      const int o_hi = 32 * w + 31 < kBand - 1 ? 32 * w + 31 : kBand - 1;
+      for (int ks = o_lo / 4; ks <= o_hi / 4; ++ks) {
+        const int o = 4 * ks + lk;
+        const double b0 = W[o][lm], b1 = W[o][16 + lm];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double av = vat(16 * (2 * w + u) + lm, o);
+          acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[u][0], 0, 0, 0);
+          acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[u][1], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * (2 * w + u) + 4 * q + lk;
+          Xb[r][lm] -= acc[u][0][q];
+          Xb[r][16 + lm] -= acc[u][1][q];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kSlabW * kRows; e += 256) {
+      const int c2 = e / kRows, r = e - c2 * kRows;
+      if (c2 < ncol && r < NR) X[(col0 + c2) * n + R0 + r] = Xb[r][c2];
+    }
   }
 }
 
@@ -825,12 +886,13 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
     }
     ++dp;
     if (dp == kDelay || p == np - 1) {
-      // S -= U1a U2a^T over the whole trailing square (every tile its own rows)
+      // S -= U1a U2a^T: the sum of the pending V W^T + W V^T is symmetric, so
+      // only the upper tiles are computed and each is written to both halves
       Strided<false> A2{U2a + j + b, 1, n, 0, m};
       Strided<false> B1{U1a + j + b, 1, n, 0, m};
-      EpiSub E{S, n};
-      CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/sy2sb update", A2, B1, E, m, m,
-                                       2 * b * dp, 1)));
+      EpiSubSym E{S, n, m};
+      CHECK((gemm_shape<double, true>(c, SH_128x128, "eig/sy2sb update", A2, B1, E, m, m,
+                                      2 * b * dp, 1)));
       dp = 0;
     }
   }
@@ -910,9 +972,16 @@ static int ts_apply(qsgw_ctx* c, const TwoStage& ts, int64_t n, double* X, int64
     int64_t J_hi = ts.nJ - 1 - t + (ts.K0 - 1);
     if (J_hi > ts.nJ - 1) J_hi = ts.nJ - 1;
     if (J_hi < J_lo) return;
-    hipLaunchKernelGGL(k_q2_apply, dim3((unsigned)((J_hi - J_lo + 1) * nslab)), dim3(256), 0,
-                       c->stream, X, n, ncols, b, ts.V2, ts.off, ts.Tb, ts.off + n, t, ts.nJ, J_lo,
-                       nslab, trans ? 1 : 0);
+    // slabs per workgroup: as many as keep at least kQ2Wgs workgroups in the launch
+    // (the block's V and T are staged once per workgroup)
+    const int64_t nb = J_hi - J_lo + 1;
+    int64_t ngrp = (kQ2Wgs + nb - 1) / nb;
+    if (ngrp > nslab) ngrp = nslab;
+    const int64_t spg = (nslab + ngrp - 1) / ngrp;
+    ngrp = (nslab + spg - 1) / spg;
+    hipLaunchKernelGGL(k_q2_apply, dim3((unsigned)(nb * ngrp)), dim3(256), 0, c->stream, X, n,
+                       ncols, b, ts.V2, ts.off, ts.Tb, ts.off + n, t, ts.nJ, J_lo, ngrp, spg,
+                       trans ? 1 : 0);
   };
   double *W1 = nullptr, *W2 = nullptr, *WP = nullptr;
   CHECK(ws_get(c, W_EIG_Q1W, (size_t)(2 * b * ncols), &W1));

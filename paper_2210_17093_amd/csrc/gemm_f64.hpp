@@ -264,6 +264,17 @@ template <class E>
 struct has_pass_hook<E, decltype((void)E::kPassHook, void())> {
   static constexpr bool value = E::kPassHook;
 };
+// Pass epilogues of symmetric products (TRI): they receive every staged pass
+// of an upper tile (diagonal tiles included) and drop the m > n elements and
+// write the mirror themselves.
+template <class E, class = void>
+struct has_tri_pass {
+  static constexpr bool value = false;
+};
+template <class E>
+struct has_tri_pass<E, decltype((void)E::kTriPass, void())> {
+  static constexpr bool value = E::kTriPass;
+};
 
 // Offset of element (r, k) of a split-BF16 LDS plane with br rows: swizzled
 // [r][k] rows, or k-block-major [k/8][r][8] (KBM).
@@ -870,7 +881,8 @@ __device__ __forceinline__ void gemm_body(const OA& A, const OB& B, const EPI& e
     if constexpr (has_pass_hook<EPI>::value) {
       // epilogues that take a whole staged pass (rows m0 + pass WM .., all
       // columns of the tile; they check their own ranges)
-      static_assert(!TRI, "pass epilogues of full tiles");
+      static_assert(!TRI || has_tri_pass<EPI>::value,
+                    "pass epilogues of full tiles, or ones that handle the triangle");
       epi.template pass<WM, BN>(m0 + pass * WM, n0, Cs, LDC, tid);
     } else {
       for (int idx = tid; idx < WM * BN; idx += 256) {
