@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqsgw.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["kernels.hip", "qsgw.hip", "batched.hip", "mlp.hip", "mp2.hip", "ao2mo4.hip", "eig2s.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "qsgw.hip", "batched.hip", "mlp.hip", "mp2.hip", "ao2mo4.hip", "eig2s.hip", "eigdc.hip", "noalloc.hip"]
 HIPFLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -749,9 +749,11 @@ struct TwoStage {
 };
 
 // Stages 1-3: A [n][n] symmetric in; on return A holds the eigenvectors E of the
-// tridiagonal matrix (column-major) and evals the eigenvalues, ascending.
+// tridiagonal matrix (column-major) and evals the eigenvalues, ascending.  With
+// stage3 false the tridiagonal matrix is left in the W_EIG_DE slot (d, then e)
+// instead.
 static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what,
-                     TwoStage* ts) {
+                     TwoStage* ts, bool stage3 = true) {
   const int b = kBand;
   rocblas_handle h = c->blas;
   const int ni = (int)n;
@@ -948,6 +950,7 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
                      tau2, off, off + n, n, b, ts->Tb);
   CHECK(launch_check(c, "k_q2_tfactor"));
 
+  if (!stage3) return QSGW_OK;
   // ---- stage 3: tridiagonal eigenproblem (eigenvectors E into A) ----
   RB_TRY(c, rocsolver_dstedc(h, rocblas_evect_tridiagonal, ni, dd, ee, A, ni,
                              (rocblas_int*)(flags + 1)), what);
@@ -1056,25 +1059,27 @@ int eig_two_stage(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* 
 // matrix Bt on the eigenvectors Z, written as row-major [naux][n] (R[P][s] =
 // sum_t Bt[P][t] Z[t][s]), without forming Z: the back-transformations act on
 // the naux columns of Bt^T instead of the n columns of E,
-//   R^T = E^T (Q2^T Q1^T Bt^T).
-// A is destroyed (it holds E on return); X: [naux][n] work array.
+//   R^T = E^T (Q2^T Q1^T Bt^T),
+// and E^T is applied by the tridiagonal merge (tridiag_project_dc), which
+// never forms E either.  A is destroyed; X: [naux][n] work array.
 int eig_two_stage_project(qsgw_ctx* c, int64_t n, double* A, double* evals, int64_t naux,
                           const double* Bt, double* X, double* R, const char* what) {
   if (n > 46340) return fail(c, QSGW_ERR_UNSUPPORTED, "%s: n too large for the two-stage solver", what);
   if (naux > 0x7fffffffLL) return fail(c, QSGW_ERR_UNSUPPORTED, "%s: naux too large", what);
-  const double one = 1.0, zero = 0.0;
-  const double* Xp = Bt;
   if (n < 4 * kBand) {
     CHECK(syevd(c, n, A, evals, what));  // A = Z
-  } else {
-    TwoStage ts;
-    CHECK(ts_reduce(c, n, A, evals, what, &ts));
-    HIP_TRY(c, hipMemcpyAsync(X, Bt, (size_t)(naux * n) * sizeof(double), hipMemcpyDeviceToDevice,
-                              c->stream));
-    CHECK(ts_apply(c, ts, n, X, naux, true, what));
-    Xp = X;
+    const double one = 1.0, zero = 0.0;
+    RB_TRY(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n,
+                            (int)naux, (int)n, &one, A, (int)n, Bt, (int)n, &zero, R, (int)n),
+           what);
+    return QSGW_OK;
   }
-  RB_TRY(c, rocblas_dgemm(c->blas, rocblas_operation_transpose, rocblas_operation_none, (int)n,
-                          (int)naux, (int)n, &one, A, (int)n, Xp, (int)n, &zero, R, (int)n), what);
-  return QSGW_OK;
+  TwoStage ts;
+  CHECK(ts_reduce(c, n, A, evals, what, &ts, false));
+  HIP_TRY(c, hipMemcpyAsync(X, Bt, (size_t)(naux * n) * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
+  CHECK(ts_apply(c, ts, n, X, naux, true, what));
+  double* dd = nullptr;
+  CHECK(ws_get(c, W_EIG_DE, (size_t)(2 * n), &dd));
+  return tridiag_project_dc(c, n, dd, dd + n, A, naux, X, evals, R, what);
 }

@@ -99,6 +99,9 @@ enum Slot {
   W_EIG_XP,      // two-stage eigensolver: split-K partials of X = S V T [nz][b][m]
   W_EIG_PANEL,   // two-stage eigensolver: panel QR partial dots (two buffers) and R  [2 G b + b b]
   W_EIG_Q1W,     // two-stage eigensolver: V^T X and T V^T X of a panel [2][b][ncols]
+  W_EIG_DCG,     // tridiagonal merge (projection): Q^T X and its sorted rows [2][n][naux]
+  W_EIG_DCV,     // tridiagonal merge: poles, weights, roots, rotations [12 n + 8]
+  W_EIG_DCI,     // tridiagonal merge: row maps, positions, counts (int64) [9 n + 4]
   W_RHOFULL,     // iteration through the projection: rho' of every excitation [naux][ntr]
   W_RHOFULL32,   // ... and its FP32 copy (FP32 products)          [naux][ntr] float
   W_BMO_B,       // open-shell iteration: beta-spin MO tensor     [naux][nbf][nbf]
@@ -182,6 +185,11 @@ int eig_two_stage(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* 
 // (eig2s.hip); A is destroyed, X is an [naux][n] work array.
 int eig_two_stage_project(qsgw_ctx* c, int64_t n, double* A, double* evals, int64_t naux,
                           const double* Bt, double* X, double* R, const char* what);
+// Eigenvalues (ascending) of a tridiagonal matrix (d, e: destroyed) and
+// R[P][s] = sum_r E[r][s] X[P][r] (E its eigenvectors, X row-major [naux][n])
+// by one divide-and-conquer merge of the two halves (eigdc.hip); A: n x n work.
+int tridiag_project_dc(qsgw_ctx* c, int64_t n, double* d, double* e, double* A, int64_t naux,
+                       const double* X, double* evals, double* R, const char* what);
 
 // qsMP2 potential of Eqs. (20)-(21) in the MO basis (mp2.hip), for the
 // iteration driver: V (+)= the potential; occ_block 0 = automatic blocks.

@@ -213,3 +213,37 @@ def test_projected_iteration_matches_oracle(q, ctx, prec, s_block):
     q.qsgw_iterate(ctx, B, h, nocc, e2, C2, eta, tol=0.0, max_iter=1, precision=pr,
                    s_block=s_block, replay_eig=True)
     np.testing.assert_array_equal(host(e2), e_full)
+
+
+@pytest.mark.parametrize("case", ["degenerate", "rank_one", "uncoupled"])
+def test_projected_iteration_deflation(q, ctx, case):
+    """The projection's tridiagonal merge deflates most of its poles when the
+    Casida spectrum is degenerate (evenly spaced orbital energies: every
+    transition energy repeats), when the coupling has rank one (N_aux = 1) and
+    when there is almost none (the torn tridiagonal is nearly diagonal): one
+    qsgw_iterate step against the oracle step to 1e-8 Ha."""
+    print("projected iteration with deflation:", case, flush=True)
+    if case == "degenerate":
+        # a rank-two coupling lifts only part of each multiplet: 185 of the 320
+        # eigenvalues repeat
+        nbf, naux, nocc = 48, 2, 8
+        p = make_problem(nbf, naux, nocc, 2, 0.99, 6, coupling=0.05)
+        eps0 = np.concatenate([-1.0 - 0.5 * np.arange(nocc)[::-1],
+                               0.5 + 0.5 * np.arange(nbf - nocc)])
+    elif case == "rank_one":
+        nbf, naux, nocc = 60, 1, 9
+        p = make_problem(nbf, naux, nocc, 1, 0.99, 5, coupling=1.0)
+        eps0 = p.eps0
+    else:
+        nbf, naux, nocc = 50, 30, 8
+        p = make_problem(nbf, naux, nocc, 15, 0.99, 7, coupling=1e-7)
+        eps0 = p.eps0
+    eta = 1e-3
+    h_ref = O.hf_core(p.B_ao, p.C0, eps0, nocc)
+    st = O.qsgw_step(p.B_ao, h_ref, p.C0, eps0, nocc, eta)
+    B = dev(p.B_ao)
+    C = dev(p.C0.copy())
+    e = dev(eps0.copy())
+    h = q.qsgw_hf_core(ctx, B, C, e, nocc)
+    q.qsgw_iterate(ctx, B, h, nocc, e, C, eta, tol=0.0, max_iter=1)
+    assert np.max(np.abs(host(e) - st["eps"])) <= QP_TOL
