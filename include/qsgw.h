@@ -139,7 +139,12 @@ int qsgw_rpa_build(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const
  * tridiagonal by bulge chasing, rocSOLVER divide and conquer (dstedc) on the
  * tridiagonal matrix, then both back-transformations (the bulge-chasing
  * reflectors in blocks of 64 sweeps, the panel reflectors as block
- * reflectors).  Below n = 256 it calls dsyevd. */
+ * reflectors).  Inside qsgw_iterate only the projection of the auxiliary
+ * basis on the eigenvectors is needed: the back-transformations act on its
+ * N_aux columns and the tridiagonal eigenproblem is solved by divide and
+ * conquer whose merges act on those columns too (blocks up to the tile
+ * table's dc_leaf by dstedc), so no eigenvector matrix is formed.  Below
+ * n = 256 it calls dsyevd. */
 #define QSGW_EIG_TWO_STAGE 2
 
 /* Selects the Casida eigensolver of the context (QSGW_EIG_*).  Eigenvectors
@@ -516,9 +521,13 @@ int qsgw_iterate_batched(qsgw_ctx* ctx, int64_t nmol, const qsgw_problem* probs,
  * persistent (integer in [0, 8]): for the grouped products of
  * qsgw_iterate_batched, 0 launches one workgroup per tile, n > 0 a
  * persistent grid of n workgroups per compute unit that walk contiguous
- * tile ranges.  Keys not given keep their defaults (mo1=128x64, mo2=64x64,
- * casida=128x128, rho=128x128, sigma=64x64, exchange=64x64, 4096, 2048,
- * 2048, mp2_target=32768, persistent=0); NULL or "" restores all defaults.  Every later product and
+ * tile ranges; dc_leaf (integer in [16, 46340]): the two-stage solver's
+ * projection (inside qsgw_iterate) solves the tridiagonal eigenproblem by
+ * divide and conquer, halving blocks larger than dc_leaf and handing blocks
+ * up to that order to rocSOLVER dstedc.  Keys not given keep their defaults
+ * (mo1=128x64, mo2=64x64, casida=128x128, rho=128x128, sigma=64x64,
+ * exchange=64x64, 4096, 2048, 2048, mp2_target=32768, persistent=0,
+ * dc_leaf=6144); NULL or "" restores all defaults.  Every later product and
  * iteration on the context uses the table (results change only by rounding
  * order).  qsgw_get_tiles writes the current table in the same format.
  */

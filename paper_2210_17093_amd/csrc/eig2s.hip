@@ -231,23 +231,25 @@ struct EpiPanelW {
 
 // A product C[i][c] = sum_r A(i, r) B(c, r) with a long k = r and a small
 // output, split over k (partials summed in a fixed order) when that fills
-// the chip better; C row-major, ld N.
+// the chip better; C row-major, ld N.  The k tile is 32 deep: these products
+// stream an operand from HBM once, and the deeper tile keeps twice the bytes
+// in flight per workgroup.
 template <class OA, class OB>
 static int gemm_long_k(qsgw_ctx* c, const char* what, OA A, OB B, double* C, int64_t M, int64_t N,
                        int64_t K) {
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  const SplitPlan sp = split_plan(K, splits_for(tiles, K, 2048));
+  const SplitPlan sp = round_chunks(split_plan(K, splits_for(tiles, K, 2048)), K, 32);
   if (sp.nz > 1) {
     double* part = nullptr;
     CHECK(ws_get(c, W_EIG_XP, (size_t)(sp.nz * M * N), &part));
     EpiStore E{part, N, 0, M * N, 1.0};
-    CHECK((gemm_shape<double, false>(c, SH_64x64, what, A, B, E, M, N, K, 1, sp)));
+    CHECK((gemm_shape<double, false, 32>(c, SH_64x64, what, A, B, E, M, N, K, 1, sp)));
     hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(M * N)), dim3(256), 0, c->stream, part, sp.nz,
                        M * N, sp.nz, C);
     return launch_check(c, "k_sum_slices");
   }
   EpiStore E{C, N, 0, 0, 1.0};
-  return gemm_shape<double, false>(c, SH_64x64, what, A, B, E, M, N, K, 1);
+  return gemm_shape<double, false, 32>(c, SH_64x64, what, A, B, E, M, N, K, 1);
 }
 
 // X[m][n] -= v (a plain product subtracted from its output).
@@ -570,10 +572,10 @@ __global__ __launch_bounds__(256) void k_q2_tfactor(const double* __restrict__ V
 // X <- B X for the blocks (J, k) of one anti-diagonal t = (nJ - 1 - J) + k on
 // a group of `spg` consecutive slabs of kSlabW columns of X ([n][ncols]
 // column-major, ld n):
-//   trans 0: B = I - V T V^T   (the block's reflectors from its highest sweep
-//            down; anti-diagonals in ascending order give X <- Q2 X);
-//   trans 1: B = I - V T^T V^T (lowest sweep first; anti-diagonals in
-//            descending order give X <- Q2^T X).
+//   TRANS false: B = I - V T V^T   (the block's reflectors from its highest
+//                sweep down; anti-diagonals in ascending order give X <- Q2 X);
+//   TRANS true:  B = I - V T^T V^T (lowest sweep first; anti-diagonals in
+//                descending order give X <- Q2^T X).
 // The block touches rows [J g + 1 + k b, J g + g - 1 + (k + 1) b] of X.  V
 // (generated from the compact reflector rows, zero outside a reflector's b
 // rows) and T are staged in LDS once per workgroup; the slabs then go through
@@ -587,13 +589,14 @@ constexpr int kRows = 2 * kBand;  // b + g - 1 rows, padded
 constexpr int kSlabPre = kSlabW * kRows / 256;  // slab elements per thread
 constexpr int64_t kQ2Wgs = 1024;  // workgroups a band back-transformation launch aims for
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
+template <bool TRANS>
 __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_t n, int64_t ncols,
                                                   int b, const double* __restrict__ V2,
                                                   const int64_t* __restrict__ off,
                                                   const double* __restrict__ Tb,
                                                   const int64_t* __restrict__ boff, int64_t t,
                                                   int64_t nJ, int64_t J_lo, int64_t ngrp,
-                                                  int64_t spg, int trans) {
+                                                  int64_t spg) {
   const int64_t jj = blockIdx.x / ngrp, grp = blockIdx.x - jj * ngrp;
   const int64_t J = J_lo + jj;
   const int64_t k = t - (nJ - 1 - J);
@@ -657,13 +660,16 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     }
     __syncthreads();
     if (sl + 1 < s1) gload(col0 + kSlabW, ncol_of(sl + 1));
-    // W = V^T X_b: wave w owns rows o of tile w, both column tiles; k = r
+    // W = V^T X_b: wave w owns rows o of tile w, both column tiles; k = r over
+    // the 80 rows that reflectors 16w .. 16w + 15 reach (r = 16w .. 16w + 79;
+    // the trip counts of all three products are fixed, so the loops unroll
+    // and the LDS reads run ahead of the matrix-core instructions)
     {
       f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const int o = 16 * w + lm;
-      const int ks_hi = min(kRows / 4 - 1, (16 * w + 15 + kBand - 1) / 4);
-      for (int ks = 4 * w; ks <= ks_hi; ++ks) {
-        const int r = 4 * ks + lk;
+#pragma unroll
+      for (int u = 0; u < 20; ++u) {
+        const int r = 16 * w + 4 * u + lk;
         const double av = vat(r, o);
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][lm], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][16 + lm], acc1, 0, 0, 0);
@@ -675,14 +681,14 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
       }
     }
     __syncthreads();
-    // W2 = T W or T^T W (T upper triangular), back into W
+    // W2 = T W or T^T W (T upper triangular, stored with its zeros), back into W
     {
       f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const int i = 16 * w + lm;
-      const int ks_lo = trans ? 0 : 4 * w, ks_hi = trans ? 4 * w + 3 : kBand / 4 - 1;
-      for (int ks = ks_lo; ks <= ks_hi; ++ks) {
+#pragma unroll
+      for (int ks = 0; ks < kBand / 4; ++ks) {
         const int j = 4 * ks + lk;
-        const double av = trans ? Ts[j][i] : Ts[i][j];
+        const double av = TRANS ? Ts[j][i] : Ts[i][j];
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][lm], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][16 + lm], acc1, 0, 0, 0);
       }
@@ -695,16 +701,14 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     }
     __syncthreads();
     // X_b -= V W2: wave w owns row tiles 2w, 2w + 1, both column tiles; k = o
-    // over the reflectors that reach those rows (o > r - b, o <= r)
     {
       f64x4_t acc[2][2];
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-      const int o_lo = 32 * w - (kBand - 1) > 0 ? 32 * w - (kBand - 1) : 0;
-      const int o_hi = 32 * w + 31 < kBand - 1 ? 32 * w + 31 : kBand - 1;
-      for (int ks = o_lo / 4; ks <= o_hi / 4; ++ks) {
+#pragma unroll
+      for (int ks = 0; ks < kBand / 4; ++ks) {
         const int o = 4 * ks + lk;
         const double b0 = W[o][lm], b1 = W[o][16 + lm];
 #pragma unroll
@@ -752,6 +756,10 @@ struct TwoStage {
 // tridiagonal matrix (column-major) and evals the eigenvalues, ascending.  With
 // stage3 false the tridiagonal matrix is left in the W_EIG_DE slot (d, then e)
 // instead.
+// Panels whose two-sided update of the trailing matrix is delayed and applied
+// as one product (k = 2 b kDelay).
+constexpr int kDelay = 8;
+
 static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const char* what,
                      TwoStage* ts, bool stage3 = true) {
   const int b = kBand;
@@ -773,9 +781,9 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
   CHECK(ws_get(c, W_EIG_V1, (size_t)vtot, &V1));
   CHECK(ws_get(c, W_EIG_T1, (size_t)(np * b * b), &T1));
   CHECK(ws_get(c, W_EIG_TAU1, (size_t)(np * b), &tau1));
-  CHECK(ws_get(c, W_EIG_U, (size_t)(4 * 4 * n * b), &U1));  // 2 x [n][2 b kDelay]
+  CHECK(ws_get(c, W_EIG_U, (size_t)(4 * kDelay * n * b), &U1));  // 2 x [n][2 b kDelay]
   U2 = nullptr;
-  CHECK(ws_get(c, W_EIG_XY, (size_t)(2 * n * b + 2 * b * b + 2 * 4 * b * b), &X));
+  CHECK(ws_get(c, W_EIG_XY, (size_t)(2 * n * b + 2 * b * b + 2 * kDelay * b * b), &X));
   Y = X + n * b;
   Z1 = Y + n * b;
   Z2 = Z1 + b * b;
@@ -786,7 +794,6 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
   // at row r), the next panel's columns and its product X = S Y are corrected
   // with them (two thin products), and the stored matrix takes all of them in
   // one product with k = 2 b (pending panels).
-  constexpr int kDelay = 4;
   double* U1a = U1;
   double* U2a = U1 + 2 * kDelay * n * b;
   int dp = 0;  // pending panels
@@ -982,9 +989,13 @@ static int ts_apply(qsgw_ctx* c, const TwoStage& ts, int64_t n, double* X, int64
     if (ngrp > nslab) ngrp = nslab;
     const int64_t spg = (nslab + ngrp - 1) / ngrp;
     ngrp = (nslab + spg - 1) / spg;
-    hipLaunchKernelGGL(k_q2_apply, dim3((unsigned)(nb * ngrp)), dim3(256), 0, c->stream, X, n,
-                       ncols, b, ts.V2, ts.off, ts.Tb, ts.off + n, t, ts.nJ, J_lo, ngrp, spg,
-                       trans ? 1 : 0);
+    if (trans)
+      hipLaunchKernelGGL(k_q2_apply<true>, dim3((unsigned)(nb * ngrp)), dim3(256), 0, c->stream, X,
+                         n, ncols, b, ts.V2, ts.off, ts.Tb, ts.off + n, t, ts.nJ, J_lo, ngrp, spg);
+    else
+      hipLaunchKernelGGL(k_q2_apply<false>, dim3((unsigned)(nb * ngrp)), dim3(256), 0, c->stream,
+                         X, n, ncols, b, ts.V2, ts.off, ts.Tb, ts.off + n, t, ts.nJ, J_lo, ngrp,
+                         spg);
   };
   double *W1 = nullptr, *W2 = nullptr, *WP = nullptr;
   CHECK(ws_get(c, W_EIG_Q1W, (size_t)(2 * b * ncols), &W1));
@@ -999,17 +1010,18 @@ static int ts_apply(qsgw_ctx* c, const TwoStage& ts, int64_t n, double* X, int64
       Strided<true> Av{V, m, 1, 0, kk};
       Strided<true> Bx{Xs, n, 1, 0, ncols};
       const int64_t tiles = ((kk + 63) / 64) * ((ncols + 63) / 64);
-      const SplitPlan sp = split_plan(m, splits_for(tiles, m, 2048));
+      const SplitPlan sp = round_chunks(split_plan(m, splits_for(tiles, m, 2048)), m, 32);
       if (sp.nz > 1) {
         CHECK(ws_get(c, W_EIG_XP, (size_t)(sp.nz * kk * ncols), &WP));
         EpiStore E{WP, ncols, 0, kk * ncols, 1.0};
-        CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/q1 W", Av, Bx, E, kk, ncols, m, 1, sp)));
+        CHECK((gemm_shape<double, false, 32>(c, SH_64x64, "eig/q1 W", Av, Bx, E, kk, ncols, m, 1,
+                                             sp)));
         hipLaunchKernelGGL(k_sum_slices, dim3(blocks_for(kk * ncols)), dim3(256), 0, c->stream, WP,
                            sp.nz, kk * ncols, sp.nz, W1);
         CHECK(launch_check(c, "k_sum_slices"));
       } else {
         EpiStore E{W1, ncols, 0, 0, 1.0};
-        CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/q1 W", Av, Bx, E, kk, ncols, m, 1)));
+        CHECK((gemm_shape<double, false, 32>(c, SH_64x64, "eig/q1 W", Av, Bx, E, kk, ncols, m, 1)));
       }
     }
     {

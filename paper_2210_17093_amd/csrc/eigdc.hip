@@ -1,7 +1,9 @@
 // Tridiagonal stage of the two-stage Casida eigensolver in projection mode:
-// the top divide-and-conquer merge is done here, the two halves by rocSOLVER.
+// divide and conquer whose merges are done here, on the projected columns
+// only; the leaves (order <= the tile table's dc_leaf) are solved by rocSOLVER
+// dstedc.
 //
-// The tridiagonal T (order n, diagonal d, off-diagonal e) is torn at
+// A tridiagonal T (order n, diagonal d, off-diagonal e) is torn at
 // n1 = n / 2 (Cuppen): with beta = e[n1 - 1],
 //   T = diag(T1, T2) + |beta| v v^T,  v = e_{n1-1} + sign(beta) e_{n1},
 // where T1 and T2 are the leading and trailing blocks with |beta| taken off
@@ -24,9 +26,12 @@
 //     Newton steps on h(mu) = mu f(mu), which has no pole at mu = 0, kept
 //     inside a bisection bracket.
 // Projection mode needs R = E^T X only (E the eigenvectors of T, X an
-// n x naux matrix), so E is never formed: R = U^T (Q^T X) with the rows of
+// n x q matrix), so E is never formed: R = U^T (Q^T X) with the rows of
 // Q^T X sorted, rotated and split into deflated rows (copied to their
-// columns of R) and the K others (one product with U).  Everything in FP64.
+// columns of R) and the K others (one product with U).  Q^T X comes from the
+// two halves solved the same way, each on its rows of X plus one unit column
+// (e_{n1-1} for the first half, e_0 for the second): their projections are
+// the boundary rows of E1 and E2 that z is made of.  Everything in FP64.
 #include "internal.hpp"
 
 namespace {
@@ -67,11 +72,12 @@ __global__ void k_dc_tear(double* __restrict__ d, const double* __restrict__ e, 
   d[n1] -= fabs(beta);
 }
 
-// The halves' eigenvalues (w1 = d[0..n1), w2 = d[n1..n), each ascending) merged
-// into ds ascending (ties: the first half first), with z (unnormalised: row
-// n1 - 1 of E1, sign(beta) times row 0 of E2) and the source row of Q^T X.
-__global__ void k_dc_prep(const double* __restrict__ d, int64_t n1, int64_t n2,
-                          const double* __restrict__ E1, const double* __restrict__ E2,
+// The halves' eigenvalues (w = w1 of n1 then w2 of n2, each ascending)
+// merged into ds ascending (ties: the first half first), with z unnormalised
+// (the last row of E1 and sign(beta) times the first row of E2: row q of the
+// halves' projections Rl [q + 1][n1] and Rr [q + 1][n2]) and the source row.
+__global__ void k_dc_prep(const double* __restrict__ w, int64_t n1, int64_t n2,
+                          const double* __restrict__ Rl, const double* __restrict__ Rr, int64_t q,
                           const double* __restrict__ scal, double* __restrict__ ds,
                           double* __restrict__ zs, int64_t* __restrict__ src) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,27 +86,60 @@ __global__ void k_dc_prep(const double* __restrict__ d, int64_t n1, int64_t n2,
   int64_t pos;
   double v, z;
   if (t < n1) {
-    v = d[t];
-    pos = t + count_below(d + n1, n2, v, false);
-    z = E1[t * n1 + (n1 - 1)];
+    v = w[t];
+    pos = t + count_below(w + n1, n2, v, false);
+    z = Rl[q * n1 + t];
   } else {
     const int64_t t2 = t - n1;
-    v = d[n1 + t2];
-    pos = t2 + count_below(d, n1, v, true);
-    z = sg * E2[t2 * n2];
+    v = w[n1 + t2];
+    pos = t2 + count_below(w, n1, v, true);
+    z = sg * Rr[q * n2 + t2];
   }
   ds[pos] = v;
   zs[pos] = z;
   src[pos] = t;
 }
 
-// Gs[s][P] = G[src[s]][P] (rows of naux values).
-__global__ void k_dc_gather_rows(const double* __restrict__ G, const int64_t* __restrict__ src,
-                                 int64_t n, int64_t naux, double* __restrict__ Gs) {
-  const int64_t s = blockIdx.y;
-  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n || P >= naux) return;
-  Gs[s * naux + P] = G[src[s] * naux + P];
+// Gs[s][P] = column src[s] of the halves' projections (Rl [.][n1] for
+// src < n1, Rr [.][n2] after), P < q: a transpose through LDS in 64 x 64 tiles
+// (reads along s, writes along P).
+__global__ __launch_bounds__(256) void k_dc_gather_rows(const double* __restrict__ Rl,
+                                                        const double* __restrict__ Rr, int64_t n1,
+                                                        int64_t n2,
+                                                        const int64_t* __restrict__ src,
+                                                        int64_t q, double* __restrict__ Gs) {
+  __shared__ double tile[64][65];
+  const int64_t n = n1 + n2;
+  const int64_t s0 = (int64_t)blockIdx.x * 64, P0 = (int64_t)blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  const int sl = tid & 63, pr = tid >> 6;
+  const int64_t s = s0 + sl;
+  const int64_t t = s < n ? src[s] : 0;
+  for (int pl = pr; pl < 64; pl += 4) {
+    const int64_t P = P0 + pl;
+    double v = 0.0;
+    if (s < n && P < q) v = t < n1 ? Rl[P * n1 + t] : Rr[P * n2 + (t - n1)];
+    tile[pl][sl] = v;
+  }
+  __syncthreads();
+  for (int r = pr; r < 64; r += 4) {
+    const int64_t s2 = s0 + r, P = P0 + sl;
+    if (s2 < n && P < q) Gs[s2 * q + P] = tile[sl][r];
+  }
+}
+
+// Inputs of the two halves of a node (X row-major [q][ldx], rows of T along
+// the row): Xl [q + 1][n1] = first n1 entries of each row, then e_{n1-1};
+// Xr [q + 1][n2] = the other n2 entries, then e_0.
+__global__ void k_dc_child_inputs(const double* __restrict__ X, int64_t ldx, int64_t q, int64_t n1,
+                                  int64_t n2, double* __restrict__ Xl, double* __restrict__ Xr) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = blockIdx.y;
+  if (P > q || r >= n1 + n2) return;
+  if (r < n1)
+    Xl[P * n1 + r] = P < q ? X[P * ldx + r] : (r == n1 - 1 ? 1.0 : 0.0);
+  else
+    Xr[P * n2 + (r - n1)] = P < q ? X[P * ldx + r] : (r == n1 ? 1.0 : 0.0);
 }
 
 // Deflation, one workgroup.  z is normalised in place, rho = |beta| |z|^2 and
@@ -403,79 +442,60 @@ struct EpiScatterCols {
   }
 };
 
-}  // namespace
 
-// Eigenvalues (ascending) of the tridiagonal T (d, e: destroyed) and
-// R[P][s] = sum_r E[r][s] X[P][r] for X row-major [naux][n] (column-major
-// n x naux, ld n), without forming E.  A: n x n work array.
-int tridiag_project_dc(qsgw_ctx* c, int64_t n, double* d, double* e, double* A, int64_t naux,
-                       const double* X, double* evals, double* R, const char* what) {
-  if (n < 4) return fail(c, QSGW_ERR_INVALID_ARG, "%s: tridiagonal merge needs n >= 4", what);
-  const int64_t n1 = n / 2, n2 = n - n1;
-  double *G, *V, *scal;
+// Buffers of one recursion depth (one node of that depth is active at a time):
+// the children's inputs Xc and projections Rc ([q + 1][n] each), the sorted
+// and the non-deflated rows of Q^T X (Gs, Gnd: [n][q]), the vectors V and the
+// int64 maps I of the merge.
+struct DcLevel {
+  double *Xc, *Rc, *Gs, *Gnd, *V;
   int64_t* I;
-  int* flags;
-  CHECK(ws_get(c, W_EIG_DCG, (size_t)(2 * n * naux), &G));
-  CHECK(ws_get(c, W_EIG_DCV, (size_t)(12 * n + 8), &V));
-  CHECK(ws_get(c, W_EIG_DCI, (size_t)(9 * n + 4), &I));
-  CHECK(ws_get(c, W_FLAGS, 8, &flags));
-  double* Gs = G + n * naux;
+};
+struct DcRun {
+  std::vector<DcLevel> lv;
+  int* info;  // one dstedc status per leaf
+  int leaves = 0;
+  int64_t leaf;  // leaves up to this order go to rocSOLVER dstedc
+  const char* what;
+};
+
+// Merge of a node whose halves are solved: w (their eigenvalues, n1 then n2),
+// Rl, Rr (their projections, [q + 1][n1], [q + 1][n2]), scal[0] = beta; out:
+// evals (ascending) and R [q][n].  A: room for K x K.
+static int dc_merge(qsgw_ctx* c, int64_t n1, int64_t n2, const double* w, const double* Rl,
+                    const double* Rr, int64_t q, double* scal, const DcLevel& L, double* A,
+                    double* evals, double* R, const char* what) {
+  const int64_t n = n1 + n2;
+  double* V = L.V;
   double *ds = V, *zs = V + n, *dk = V + 2 * n, *zk = V + 3 * n, *dfv = V + 4 * n, *rc = V + 5 * n,
          *rs = V + 6 * n, *dor = V + 7 * n, *mu = V + 8 * n, *lam = V + 9 * n, *zh = V + 10 * n,
          *dfs = V + 11 * n;
-  scal = V + 12 * n;
+  int64_t* I = L.I;
   int64_t *src = I, *nd = I + n, *df = I + 2 * n, *ra = I + 3 * n, *rb = I + 4 * n,
           *dfrow = I + 5 * n, *posnd = I + 6 * n, *posdf = I + 7 * n, *cnt = I + 9 * n;
-  double* E1 = A;
-  double* E2 = A + n1 * n1;
-  rocblas_handle h = c->blas;
-
-  hipLaunchKernelGGL(k_dc_tear, dim3(1), dim3(64), 0, c->stream, d, e, n1, scal);
-  CHECK(launch_check(c, "k_dc_tear"));
-  rocblas_status st = rocsolver_dstedc(h, rocblas_evect_tridiagonal, (rocblas_int)n1, d, e, E1,
-                                       (rocblas_int)n1, (rocblas_int*)(flags + 1));
-  if (st == rocblas_status_success)
-    st = rocsolver_dstedc(h, rocblas_evect_tridiagonal, (rocblas_int)n2, d + n1, e + n1, E2,
-                          (rocblas_int)n2, (rocblas_int*)(flags + 2));
-  if (st != rocblas_status_success)
-    return fail(c, QSGW_ERR_SOLVER, "%s: rocsolver_dstedc status %d", what, (int)st);
-  // G = Q^T X: G[i][P] = sum_r E1[r][i] X[P][r] (first half), likewise E2 (second)
-  {
-    Strided<true> A1{E1, n1, 1, 0, n1};
-    Strided<true> X1{X, n, 1, 0, naux};
-    EpiStore S1{G, naux, 0, 0, 1.0};
-    CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/dc Q^T X", A1, X1, S1, n1, naux, n1, 1)));
-    Strided<true> A2{E2, n2, 1, 0, n2};
-    Strided<true> X2{X + n1, n, 1, 0, naux};
-    EpiStore S2{G + n1 * naux, naux, 0, 0, 1.0};
-    CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/dc Q^T X", A2, X2, S2, n2, naux, n2, 1)));
-  }
-  hipLaunchKernelGGL(k_dc_prep, dim3(blocks_for(n)), dim3(256), 0, c->stream, d, n1, n2, E1, E2,
+  double *Gs = L.Gs, *Gnd = L.Gnd;
+  hipLaunchKernelGGL(k_dc_prep, dim3(blocks_for(n)), dim3(256), 0, c->stream, w, n1, n2, Rl, Rr, q,
                      scal, ds, zs, src);
   CHECK(launch_check(c, "k_dc_prep"));
-  hipLaunchKernelGGL(k_dc_gather_rows, dim3(blocks_for(naux), (unsigned)n), dim3(256), 0,
-                     c->stream, G, src, n, naux, Gs);
+  hipLaunchKernelGGL(k_dc_gather_rows, dim3(blocks_for(n, 64), blocks_for(q, 64)), dim3(256), 0,
+                     c->stream, Rl, Rr, n1, n2, src, q, Gs);
   CHECK(launch_check(c, "k_dc_gather_rows"));
   hipLaunchKernelGGL(k_dc_deflate, dim3(1), dim3(256), 0, c->stream, ds, zs, n, scal, nd, dk, zk,
                      df, dfv, ra, rb, rc, rs, cnt);
   CHECK(launch_check(c, "k_dc_deflate"));
   int64_t hc[3] = {0, 0, 0};
-  int hinfo[2] = {0, 0};
   HIP_TRY(c, hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(hinfo, flags + 1, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (hinfo[0] != 0 || hinfo[1] != 0)
-    return fail(c, QSGW_ERR_SOLVER, "%s: dstedc info = %d, %d", what, hinfo[0], hinfo[1]);
   const int64_t K = hc[0], ndf = hc[1], nrot = hc[2];
   if (K < 0 || ndf < 0 || K + ndf != n || nrot < 0 || nrot > ndf)
     return fail(c, QSGW_ERR_SOLVER, "%s: deflation counts K = %lld, deflated = %lld", what,
                 (long long)K, (long long)ndf);
   if (nrot > 0) {
-    hipLaunchKernelGGL(k_dc_rotate, dim3(blocks_for(naux)), dim3(256), 0, c->stream, Gs, naux, ra,
-                       rb, rc, rs, nrot);
+    hipLaunchKernelGGL(k_dc_rotate, dim3(blocks_for(q)), dim3(256), 0, c->stream, Gs, q, ra, rb, rc,
+                       rs, nrot);
     CHECK(launch_check(c, "k_dc_rotate"));
   }
-  double* U = A;  // E1 and E2 are consumed
+  double* U = A;
   if (K > 0) {
     hipLaunchKernelGGL(k_dc_secular, dim3(blocks_for(K, 4)), dim3(256), 0, c->stream, dk, zk, K,
                        scal, dor, mu, lam);
@@ -495,16 +515,129 @@ int tridiag_project_dc(qsgw_ctx* c, int64_t n, double* d, double* e, double* A, 
   hipLaunchKernelGGL(k_dc_positions, dim3(blocks_for(n)), dim3(256), 0, c->stream, lam, K, dfs,
                      ndf, evals, posnd, posdf);
   CHECK(launch_check(c, "k_dc_positions"));
-  double* Gnd = G;  // G is consumed (Gs holds its sorted rows)
-  hipLaunchKernelGGL(k_dc_split_rows, dim3(blocks_for(naux), (unsigned)n), dim3(256), 0, c->stream,
-                     Gs, nd, K, dfrow, posdf, ndf, naux, n, Gnd, R);
+  hipLaunchKernelGGL(k_dc_split_rows, dim3(blocks_for(q), (unsigned)n), dim3(256), 0, c->stream,
+                     Gs, nd, K, dfrow, posdf, ndf, q, n, Gnd, R);
   CHECK(launch_check(c, "k_dc_split_rows"));
   if (K > 0) {
     // R[P][posnd[j]] = sum_i Gnd[i][P] U[j][i]
-    Strided<false> Ag{Gnd, 1, naux, 0, naux};
+    Strided<false> Ag{Gnd, 1, q, 0, q};
     Strided<true> Bu{U, K, 1, 0, K};
     EpiScatterCols E{R, n, posnd};
-    CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/dc merge", Ag, Bu, E, naux, K, K, 1)));
+    CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/dc merge", Ag, Bu, E, q, K, K, 1)));
   }
+  return QSGW_OK;
+}
+
+// Node of order n at recursion depth `depth`: T from d, e (destroyed), X row-major
+// [q][ldx]; out: evals (ascending), R [q][n] with R[P][s] = sum_r E[r][s] X[P][r].
+static int dc_node(qsgw_ctx* c, DcRun& run, int depth, int64_t n, double* d, double* e, double* A,
+                   const double* X, int64_t ldx, int64_t q, double* evals, double* R) {
+  if (n <= run.leaf) {
+    rocblas_status st = rocsolver_dstedc(c->blas, rocblas_evect_tridiagonal, (rocblas_int)n, d, e,
+                                         A, (rocblas_int)n, (rocblas_int*)(run.info + run.leaves));
+    ++run.leaves;
+    if (st != rocblas_status_success)
+      return fail(c, QSGW_ERR_SOLVER, "%s: rocsolver_dstedc status %d", run.what, (int)st);
+    // R[P][s] = sum_r X[P][r] E[r][s] (E column-major in A)
+    Strided<true> Ax{X, ldx, 1, 0, q};
+    Strided<true> Be{A, n, 1, 0, n};
+    EpiStore S{R, n, 0, 0, 1.0};
+    CHECK((gemm_shape<double, false>(c, SH_128x128, "eig/dc leaf", Ax, Be, S, q, n, n, 1)));
+    HIP_TRY(c, hipMemcpyAsync(evals, d, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    return QSGW_OK;
+  }
+  const DcLevel& L = run.lv[(size_t)depth];
+  const int64_t n1 = n / 2, n2 = n - n1;
+  double* scal = L.V + 13 * n;
+  double* w = L.V + 12 * n;  // the halves' eigenvalues
+  hipLaunchKernelGGL(k_dc_tear, dim3(1), dim3(64), 0, c->stream, d, e, n1, scal);
+  CHECK(launch_check(c, "k_dc_tear"));
+  double *Xl = L.Xc, *Xr = L.Xc + (q + 1) * n1;
+  double *Rl = L.Rc, *Rr = L.Rc + (q + 1) * n1;
+  hipLaunchKernelGGL(k_dc_child_inputs, dim3(blocks_for(n), (unsigned)(q + 1)), dim3(256), 0,
+                     c->stream, X, ldx, q, n1, n2, Xl, Xr);
+  CHECK(launch_check(c, "k_dc_child_inputs"));
+  CHECK(dc_node(c, run, depth + 1, n1, d, e, A, Xl, n1, q + 1, w, Rl));
+  CHECK(dc_node(c, run, depth + 1, n2, d + n1, e + n1, A, Xr, n2, q + 1, w + n1, Rr));
+  return dc_merge(c, n1, n2, w, Rl, Rr, q, scal, L, A, evals, R, run.what);
+}
+
+}  // namespace
+
+// Eigenvalues (ascending) of the tridiagonal T (d, e: destroyed) and
+// R[P][s] = sum_r E[r][s] X[P][r] for X row-major [naux][n] (column-major
+// n x naux, ld n), without forming E.  A: n x n work array.
+int tridiag_project_dc(qsgw_ctx* c, int64_t n, double* d, double* e, double* A, int64_t naux,
+                       const double* X, double* evals, double* R, const char* what) {
+  if (n < 4) return fail(c, QSGW_ERR_INVALID_ARG, "%s: tridiagonal merge needs n >= 4", what);
+  // depth of the recursion (orders at depth l are at most ceil(n / 2^l))
+  const int64_t leaf = c->tiles.dc_leaf;
+  std::vector<int64_t> nl(1, n);
+  while (nl.back() > leaf) nl.push_back(nl.back() - nl.back() / 2);
+  const int depths = (int)nl.size() - 1;  // levels with a merge
+  if (depths == 0) {
+    // one leaf: still through the merge's interface (tear once)
+    nl.push_back(n - n / 2);
+  }
+  const int nmerge = depths > 0 ? depths : 1;
+  size_t big = 0, vec = 0, ints = 0;
+  for (int l = 0; l < nmerge; ++l) {
+    const size_t m = (size_t)nl[(size_t)l], q = (size_t)(naux + l);
+    big += 2 * (q + 1) * m + 2 * m * q;
+    vec += 13 * m + 8;
+    ints += 9 * m + 4;
+  }
+  const int max_leaves = 1 << (nmerge + 1);
+  double *B, *Vv;
+  int64_t* Iv;
+  CHECK(ws_get(c, W_EIG_DCG, big, &B));
+  CHECK(ws_get(c, W_EIG_DCV, vec, &Vv));
+  CHECK(ws_get(c, W_EIG_DCI, ints + (size_t)max_leaves, &Iv));
+  DcRun run;
+  run.what = what;
+  run.leaf = leaf;
+  for (int l = 0; l < nmerge; ++l) {
+    const int64_t m = nl[(size_t)l], q = naux + l;
+    DcLevel L;
+    L.Xc = B;
+    L.Rc = B + (q + 1) * m;
+    L.Gs = B + 2 * (q + 1) * m;
+    L.Gnd = L.Gs + m * q;
+    B += 2 * (q + 1) * m + 2 * m * q;
+    L.V = Vv;
+    Vv += 13 * m + 8;
+    L.I = Iv;
+    Iv += 9 * m + 4;
+    run.lv.push_back(L);
+  }
+  run.info = reinterpret_cast<int*>(Iv);
+  HIP_TRY(c, hipMemsetAsync(run.info, 0, (size_t)max_leaves * sizeof(int64_t), c->stream));
+  if (depths == 0) {
+    // n <= dc_leaf: a single merge of two dstedc halves
+    const DcLevel& L = run.lv[0];
+    const int64_t n1 = n / 2, n2 = n - n1;
+    double* scal = L.V + 13 * n;
+    double* w = L.V + 12 * n;
+    hipLaunchKernelGGL(k_dc_tear, dim3(1), dim3(64), 0, c->stream, d, e, n1, scal);
+    CHECK(launch_check(c, "k_dc_tear"));
+    double *Xl = L.Xc, *Xr = L.Xc + (naux + 1) * n1;
+    double *Rl = L.Rc, *Rr = L.Rc + (naux + 1) * n1;
+    hipLaunchKernelGGL(k_dc_child_inputs, dim3(blocks_for(n), (unsigned)(naux + 1)), dim3(256), 0,
+                       c->stream, X, n, naux, n1, n2, Xl, Xr);
+    CHECK(launch_check(c, "k_dc_child_inputs"));
+    CHECK(dc_node(c, run, 1, n1, d, e, A, Xl, n1, naux + 1, w, Rl));
+    CHECK(dc_node(c, run, 1, n2, d + n1, e + n1, A, Xr, n2, naux + 1, w + n1, Rr));
+    CHECK(dc_merge(c, n1, n2, w, Rl, Rr, naux, scal, L, A, evals, R, what));
+  } else {
+    CHECK(dc_node(c, run, 0, n, d, e, A, X, n, naux, evals, R));
+  }
+  std::vector<int> hinfo((size_t)run.leaves, 0);
+  HIP_TRY(c, hipMemcpyAsync(hinfo.data(), run.info, hinfo.size() * sizeof(int),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < run.leaves; ++i)
+    if (hinfo[(size_t)i] != 0)
+      return fail(c, QSGW_ERR_SOLVER, "%s: dstedc info = %d (leaf %d)", what, hinfo[(size_t)i], i);
   return QSGW_OK;
 }

@@ -127,6 +127,9 @@ struct Tiles {
   // batched grouped products: 0 = one workgroup per tile, n > 0 = a
   // persistent grid of n workgroups per compute unit walking tile ranges
   int64_t persistent = 0;
+  // projected divide and conquer of the two-stage eigensolver: tridiagonal
+  // blocks up to this order are solved by rocSOLVER dstedc
+  int64_t dc_leaf = 6144;
 };
 inline int shape_m(int s) { return s == SH_64x64 ? 64 : 128; }
 inline int shape_n(int s) { return s == SH_128x128 ? 128 : 64; }

@@ -247,3 +247,39 @@ def test_projected_iteration_deflation(q, ctx, case):
     h = q.qsgw_hf_core(ctx, B, C, e, nocc)
     q.qsgw_iterate(ctx, B, h, nocc, e, C, eta, tol=0.0, max_iter=1)
     assert np.max(np.abs(host(e) - st["eps"])) <= QP_TOL
+
+
+@pytest.mark.parametrize("leaf,case", [(64, "random"), (16, "degenerate"), (40, "rank_one")])
+def test_projected_divide_and_conquer_levels(q, ctx, leaf, case):
+    """The projection's divide and conquer with small leaves (tile table key
+    dc_leaf), so that merges of merged halves run (four to five levels, each
+    half carrying the unit column whose projection is its boundary row): one
+    qsgw_iterate step against the oracle step to 1e-8 Ha."""
+    print("projected divide and conquer, leaf", leaf, case, flush=True)
+    if case == "random":
+        nbf, naux, nocc = 70, 280, 12
+        p = make_problem(nbf, naux, nocc, naux // 2, 0.99, 0)
+        eps0 = p.eps0
+    elif case == "degenerate":
+        nbf, naux, nocc = 48, 2, 8
+        p = make_problem(nbf, naux, nocc, 2, 0.99, 6, coupling=0.05)
+        eps0 = np.concatenate([-1.0 - 0.5 * np.arange(nocc)[::-1],
+                               0.5 + 0.5 * np.arange(nbf - nocc)])
+    else:
+        nbf, naux, nocc = 60, 1, 9
+        p = make_problem(nbf, naux, nocc, 1, 0.99, 5, coupling=1.0)
+        eps0 = p.eps0
+    eta = 1e-3
+    h_ref = O.hf_core(p.B_ao, p.C0, eps0, nocc)
+    st = O.qsgw_step(p.B_ao, h_ref, p.C0, eps0, nocc, eta)
+    B = dev(p.B_ao)
+    C = dev(p.C0.copy())
+    e = dev(eps0.copy())
+    h = q.qsgw_hf_core(ctx, B, C, e, nocc)
+    ctx.set_tiles(f"dc_leaf={leaf}")
+    try:
+        assert f"dc_leaf={leaf}" in ctx.get_tiles()
+        q.qsgw_iterate(ctx, B, h, nocc, e, C, eta, tol=0.0, max_iter=1)
+    finally:
+        ctx.set_tiles(None)
+    assert np.max(np.abs(host(e) - st["eps"])) <= QP_TOL

@@ -57,8 +57,11 @@ def test_table_roundtrip_and_errors(env):
     ctx.set_tiles(TABLES[0])
     got = dict(kv.split("=") for kv in ctx.get_tiles().split(","))
     assert got["sigma"] == "128x128" and got["rho_target"] == "1024" and got["mo2"] == "128x128"
+    assert got["dc_leaf"] == "6144"
+    ctx.set_tiles("dc_leaf=512")
+    assert "dc_leaf=512" in ctx.get_tiles()
     for bad in ("casida=128x64", "sigma=32x32", "nope=64x64", "sigma_target=7", "mo1",
-                "persistent=9"):
+                "persistent=9", "dc_leaf=8", "dc_leaf=50000"):
         with pytest.raises(q.QsgwError):
             ctx.set_tiles(bad)
     ctx.set_tiles("")
