@@ -26,6 +26,8 @@
 //
 // All arrays are column-major; a symmetric row-major matrix is its own
 // column-major view.  Everything runs in FP64.
+#include <hip/hip_cooperative_groups.h>
+
 #include "internal.hpp"
 
 namespace {
@@ -171,6 +173,102 @@ __global__ __launch_bounds__(256) void k_panel_col(double* __restrict__ P, int64
   if (tid < kBand)
     part_out[(int64_t)g * kBand + tid] =
         (tid >= jn && tid < b) ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
+}
+
+// The same Householder QR of one panel (b = 64 columns) in one cooperative
+// launch: workgroup g keeps rows [256 g, 256 g + 256) of the panel in LDS for
+// the whole factorisation, and the launches of the per-column kernel become
+// grid barriers.  Column j: every workgroup writes its partial dots of column
+// j (part[j % 2][g][c], c >= j) and workgroup 0 the panel's row j as updated
+// so far (rowj[j % 2][c]); after the barrier every workgroup adds the partial
+// dots in the same fixed order, forms the reflector as k_panel_col does and
+// applies it to its rows.  Two parities of the exchange buffers let a
+// workgroup publish column j + 1 while another still reads column j.  The
+// panel goes back to global memory at the end (rows < b as they stand; R
+// comes from Rbuf through k_panel_r).  Needs all G workgroups resident at
+// once, which the cooperative launch guarantees or refuses.
+__global__ __launch_bounds__(256) void k_panel_coop(double* __restrict__ P, int64_t lda, int64_t m,
+                                                    double* __restrict__ part,
+                                                    double* __restrict__ rowj, int G,
+                                                    double* __restrict__ Rbuf,
+                                                    double* __restrict__ tau) {
+  __shared__ double Ps[kBand][256];
+  __shared__ double wv[kBand];
+  __shared__ double sc[3];
+  __shared__ double red[4][kBand];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x;
+  const int64_t r = (int64_t)g * 256 + tid;
+  const bool live = r < m;
+#pragma unroll 8
+  for (int c = 0; c < kBand; ++c) Ps[c][tid] = live ? P[(int64_t)c * lda + r] : 0.0;
+  __syncthreads();
+  const int jmax = m - 1 < kBand ? (int)(m - 1) : kBand;  // columns with rows below the diagonal
+  for (int j = 0; j < jmax; ++j) {
+    const int par = j & 1;
+    // partial dots of column j over this workgroup's rows r > j
+    const double pj = (live && r > j) ? Ps[j][tid] : 0.0;
+    for (int c = j; c < kBand; ++c) {
+      const double s2 = wave_sum(pj * Ps[c][tid]);
+      if (lane == 0) red[wave][c] = s2;
+    }
+    __syncthreads();
+    if (tid < kBand) {
+      part[((int64_t)par * G + g) * kBand + tid] =
+          tid >= j ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
+      if (g == 0) rowj[par * kBand + tid] = Ps[tid][j];  // P[j][tid]: row j < 256 is here
+    }
+    grid.sync();
+    {
+      // the same fixed order in every workgroup: four strided partial sums per column
+      const int cc = tid & 63, qd = tid >> 6;
+      double s2 = 0.0;
+      if (cc >= j)
+        for (int h = qd; h < G; h += 4) s2 += part[((int64_t)par * G + h) * kBand + cc];
+      red[qd][cc] = s2;
+    }
+    __syncthreads();
+    if (tid < kBand) wv[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    __syncthreads();
+    if (tid == 0) {
+      const double alpha = rowj[par * kBand + j];
+      const double sig = wv[j];
+      if (sig == 0.0) {
+        sc[0] = 0.0;
+        sc[1] = alpha;
+        sc[2] = 0.0;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+        sc[0] = (beta - alpha) / beta;
+        sc[1] = beta;
+        sc[2] = 1.0 / (alpha - beta);
+      }
+    }
+    __syncthreads();
+    const double t = sc[0], scale = sc[2];
+    double wc = 0.0;
+    if (tid > j && tid < kBand) wc = rowj[par * kBand + tid] + scale * wv[tid];
+    __syncthreads();
+    if (tid < kBand) wv[tid] = wc;
+    __syncthreads();
+    if (g == 0 && tid < kBand) {  // row j of R, and tau
+      if (tid == j) Rbuf[(int64_t)j * kBand + j] = sc[1];
+      if (tid > j) Rbuf[(int64_t)j * kBand + tid] = rowj[par * kBand + tid] - t * wv[tid];
+      if (tid == 0) tau[j] = t;
+    }
+    if (live && r > j) {
+      const double v = Ps[j][tid] * scale;
+      Ps[j][tid] = v;
+      if (t != 0.0)
+        for (int c = j + 1; c < kBand; ++c) Ps[c][tid] -= t * wv[c] * v;
+    }
+    __syncthreads();
+  }
+  if (live) {
+#pragma unroll 8
+    for (int c = 0; c < kBand; ++c) P[(int64_t)c * lda + r] = Ps[c][tid];
+  }
 }
 
 // R (rows q < b of the panel, columns c >= q) from Rbuf into the panel's upper triangle.
@@ -813,7 +911,33 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
       CHECK((gemm_shape<double, false>(c, SH_64x64, "eig/sy2sb panel", A2, B1, E, b, n - j, Kp,
                                        1)));
     }
-    if (m >= 2 * b) {
+    bool coop_done = false;
+    if (m >= 2 * b && c->panel_coop) {
+      // the whole panel in one cooperative launch (see k_panel_coop)
+      const int G = (int)((m + 255) / 256);
+      double *part, *Rbuf;
+      CHECK(ws_get(c, W_EIG_PANEL, (size_t)(2 * G * b + 2 * b + b * b), &part));
+      double* rowj = part + 2 * G * b;
+      Rbuf = rowj + 2 * b;
+      int64_t lda = n, mm = m;
+      double* tp = tau1 + p * b;
+      void* args[] = {&P, &lda, &mm, &part, &rowj, (void*)&G, &Rbuf, &tp};
+      const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_panel_coop),
+                                                      dim3((unsigned)G), dim3(256), args, 0,
+                                                      c->stream);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_panel_r, dim3(blocks_for(b * b)), dim3(256), 0, c->stream, P, n, b,
+                           Rbuf);
+        CHECK(launch_check(c, "k_panel_coop"));
+        coop_done = true;
+      } else {
+        // not resident at once on this device: the per-column launches below
+        (void)hipGetLastError();
+        c->panel_coop = false;
+      }
+    }
+    if (coop_done) {
+    } else if (m >= 2 * b) {
       // one launch per column (see k_panel_col)
       const int rpt = m > 16384 ? 2 : 1;  // rows per thread
       const int G = (int)((m + 256 * rpt - 1) / (256 * rpt));

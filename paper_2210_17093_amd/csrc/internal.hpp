@@ -168,6 +168,9 @@ struct qsgw_ctx {
   bool eig_fold = false;
   // solver of the Casida eigenproblems (QSGW_EIG_*)
   int eig_solver = QSGW_EIG_AUTO;
+  // two-stage solver: panel QR in one cooperative launch (cleared if the
+  // device refuses it; the per-column launches take over)
+  bool panel_coop = true;
   // this device's copy of the allocation-free entry point's static scratch
   // array (noalloc.hip), null if the lookup failed
   double* scratch = nullptr;
