@@ -524,10 +524,15 @@ int qsgw_iterate_batched(qsgw_ctx* ctx, int64_t nmol, const qsgw_problem* probs,
  * tile ranges; dc_leaf (integer in [16, 46340]): the two-stage solver's
  * projection (inside qsgw_iterate) solves the tridiagonal eigenproblem by
  * divide and conquer, halving blocks larger than dc_leaf and handing blocks
- * up to that order to rocSOLVER dstedc.  Keys not given keep their defaults
- * (mo1=128x64, mo2=64x64, casida=128x128, rho=128x128, sigma=64x64,
- * exchange=64x64, 4096, 2048, 2048, mp2_target=32768, persistent=0,
- * dc_leaf=6144); NULL or "" restores all defaults.  Every later product and
+ * up to that order to rocSOLVER dstedc; panel_coop (0 or 1): 1 factors each
+ * Householder panel of the two-stage solver's dense -> band stage in one
+ * cooperative launch (the panel's rows held on chip, grid barriers between
+ * columns; where the device cannot hold every workgroup at once it falls back
+ * by itself), 0 in one launch per column.  Keys not given keep their
+ * defaults (mo1=128x64, mo2=64x64, casida=128x128, rho=128x128,
+ * sigma=64x64, exchange=64x64, 4096, 2048, 2048, mp2_target=32768,
+ * persistent=0, dc_leaf=6144, panel_coop=1); NULL or "" restores all
+ * defaults.  Every later product and
  * iteration on the context uses the table (results change only by rounding
  * order).  qsgw_get_tiles writes the current table in the same format.
  */

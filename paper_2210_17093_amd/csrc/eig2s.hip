@@ -912,7 +912,7 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
                                        1)));
     }
     bool coop_done = false;
-    if (m >= 2 * b && c->panel_coop) {
+    if (m >= 2 * b && c->tiles.panel_coop) {
       // the whole panel in one cooperative launch (see k_panel_coop)
       const int G = (int)((m + 255) / 256);
       double *part, *Rbuf;
@@ -933,7 +933,6 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
       } else {
         // not resident at once on this device: the per-column launches below
         (void)hipGetLastError();
-        c->panel_coop = false;
       }
     }
     if (coop_done) {

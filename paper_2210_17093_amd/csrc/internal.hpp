@@ -130,6 +130,9 @@ struct Tiles {
   // projected divide and conquer of the two-stage eigensolver: tridiagonal
   // blocks up to this order are solved by rocSOLVER dstedc
   int64_t dc_leaf = 6144;
+  // two-stage eigensolver: 1 = panel QR in one cooperative launch per panel
+  // (the per-column launches when the device refuses it), 0 = per-column launches
+  int64_t panel_coop = 1;
 };
 inline int shape_m(int s) { return s == SH_64x64 ? 64 : 128; }
 inline int shape_n(int s) { return s == SH_128x128 ? 128 : 64; }
@@ -168,9 +171,6 @@ struct qsgw_ctx {
   bool eig_fold = false;
   // solver of the Casida eigenproblems (QSGW_EIG_*)
   int eig_solver = QSGW_EIG_AUTO;
-  // two-stage solver: panel QR in one cooperative launch (cleared if the
-  // device refuses it; the per-column launches take over)
-  bool panel_coop = true;
   // this device's copy of the allocation-free entry point's static scratch
   // array (noalloc.hip), null if the lookup failed
   double* scratch = nullptr;

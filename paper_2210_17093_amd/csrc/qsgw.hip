@@ -1634,6 +1634,12 @@ int qsgw_set_tiles(qsgw_ctx* c, const char* spec) {
         t.persistent = v;
         continue;
       }
+      if (key == "panel_coop") {
+        if (!e || *e || v < 0 || v > 1)
+          return fail(c, QSGW_ERR_INVALID_ARG, "tiles: panel_coop needs 0 or 1");
+        t.panel_coop = v;
+        continue;
+      }
       if (key == "dc_leaf") {
         if (!e || *e || v < 16 || v > 46340)
           return fail(c, QSGW_ERR_INVALID_ARG, "tiles: dc_leaf needs an integer in [16, 46340]");
@@ -1673,6 +1679,7 @@ int qsgw_get_tiles(qsgw_ctx* c, char* buf, int64_t size) {
   out += ",persistent=" + std::to_string(c->tiles.persistent);
   out += ",mp2_target=" + std::to_string(c->tiles.mp2_target);
   out += ",dc_leaf=" + std::to_string(c->tiles.dc_leaf);
+  out += ",panel_coop=" + std::to_string(c->tiles.panel_coop);
   if ((int64_t)out.size() + 1 > size) return fail(c, QSGW_ERR_INVALID_ARG, "buffer too small");
   memcpy(buf, out.c_str(), out.size() + 1);
   return QSGW_OK;

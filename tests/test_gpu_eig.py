@@ -283,3 +283,25 @@ def test_projected_divide_and_conquer_levels(q, ctx, leaf, case):
     finally:
         ctx.set_tiles(None)
     assert np.max(np.abs(host(e) - st["eps"])) <= QP_TOL
+
+
+def test_projected_iteration_per_column_panels(q, ctx):
+    """The dense -> band stage with the per-column panel launches (tile table
+    panel_coop=0) instead of the cooperative one, and both divide-and-conquer
+    depths: one qsgw_iterate step against the oracle step to 1e-8 Ha."""
+    print("projected iteration, per-column panel QR", flush=True)
+    nbf, naux, nocc = 70, 280, 12
+    p = make_problem(nbf, naux, nocc, naux // 2, 0.99, 0)
+    h_ref = O.hf_core(p.B_ao, p.C0, p.eps0, nocc)
+    st = O.qsgw_step(p.B_ao, h_ref, p.C0, p.eps0, nocc, 1e-3)
+    B = dev(p.B_ao)
+    C = dev(p.C0.copy())
+    e = dev(p.eps0.copy())
+    h = q.qsgw_hf_core(ctx, B, C, e, nocc)
+    ctx.set_tiles("panel_coop=0,dc_leaf=100")
+    try:
+        assert "panel_coop=0" in ctx.get_tiles()
+        q.qsgw_iterate(ctx, B, h, nocc, e, C, 1e-3, tol=0.0, max_iter=1)
+    finally:
+        ctx.set_tiles(None)
+    assert np.max(np.abs(host(e) - st["eps"])) <= QP_TOL

@@ -61,7 +61,7 @@ def test_table_roundtrip_and_errors(env):
     ctx.set_tiles("dc_leaf=512")
     assert "dc_leaf=512" in ctx.get_tiles()
     for bad in ("casida=128x64", "sigma=32x32", "nope=64x64", "sigma_target=7", "mo1",
-                "persistent=9", "dc_leaf=8", "dc_leaf=50000"):
+                "persistent=9", "dc_leaf=8", "dc_leaf=50000", "panel_coop=2"):
         with pytest.raises(q.QsgwError):
             ctx.set_tiles(bad)
     ctx.set_tiles("")
