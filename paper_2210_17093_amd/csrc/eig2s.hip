@@ -26,8 +26,6 @@
 //
 // All arrays are column-major; a symmetric row-major matrix is its own
 // column-major view.  Everything runs in FP64.
-#include <hip/hip_cooperative_groups.h>
-
 #include "internal.hpp"
 
 namespace {
@@ -185,19 +183,33 @@ __global__ __launch_bounds__(256) void k_panel_col(double* __restrict__ P, int64
 // applies it to its rows.  Two parities of the exchange buffers let a
 // workgroup publish column j + 1 while another still reads column j.  The
 // panel goes back to global memory at the end (rows < b as they stand; R
-// comes from Rbuf through k_panel_r).  Needs all G workgroups resident at
-// once, which the cooperative launch guarantees or refuses.
+// comes from Rbuf through k_panel_r).
+// The barrier: each workgroup stores gen = gen0 + j + 1 into its own flag
+// (a release store at agent scope, after a workgroup barrier that has every
+// thread's exchange writes done), then threads 0..G-1 each wait for one
+// workgroup's flag to reach gen (relaxed agent-scope loads) and the workgroup
+// takes an agent-scope acquire fence; no counter is contended.  The
+// cooperative launch guarantees that all G workgroups are resident, so every
+// flag is eventually written; a wait is still bounded (kPanelSpinMax polls),
+// and a workgroup that runs out stops waiting and raises *err, which the host
+// turns into an error.  Flags only grow within a solve (gen0 = 64 p for panel
+// p) and are cleared before each solve.
+constexpr int kPanelSpinMax = 1 << 22;
 __global__ __launch_bounds__(256) void k_panel_coop(double* __restrict__ P, int64_t lda, int64_t m,
                                                     double* __restrict__ part,
                                                     double* __restrict__ rowj, int G,
                                                     double* __restrict__ Rbuf,
-                                                    double* __restrict__ tau) {
-  __shared__ double Ps[kBand][256];
+                                                    double* __restrict__ tau,
+                                                    unsigned long long* __restrict__ flags,
+                                                    unsigned long long gen0,
+                                                    int* __restrict__ err) {
+  __shared__ double Ps[kBand][257];  // [column][row of this workgroup], odd pitch
   __shared__ double wv[kBand];
   __shared__ double sc[3];
   __shared__ double red[4][kBand];
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int stalled;
+  if (threadIdx.x == 0) stalled = 0;
+  const int tid = threadIdx.x;
   const int g = blockIdx.x;
   const int64_t r = (int64_t)g * 256 + tid;
   const bool live = r < m;
@@ -207,11 +219,21 @@ __global__ __launch_bounds__(256) void k_panel_coop(double* __restrict__ P, int6
   const int jmax = m - 1 < kBand ? (int)(m - 1) : kBand;  // columns with rows below the diagonal
   for (int j = 0; j < jmax; ++j) {
     const int par = j & 1;
-    // partial dots of column j over this workgroup's rows r > j
-    const double pj = (live && r > j) ? Ps[j][tid] : 0.0;
-    for (int c = j; c < kBand; ++c) {
-      const double s2 = wave_sum(pj * Ps[c][tid]);
-      if (lane == 0) red[wave][c] = s2;
+    // partial dots of column j over this workgroup's rows r > j: thread
+    // (c = tid % 64, q = tid / 64) sums rows 64 q .. 64 q + 63 of column c in
+    // order (rows past m hold zeros; only workgroup 0 has rows r <= j)
+    {
+      const int cc = tid & 63, qd = tid >> 6;
+      double s2 = 0.0;
+      if (cc >= j) {
+#pragma unroll 8
+        for (int u = 0; u < 64; ++u) {
+          const int rl = 64 * qd + u;
+          const double a = (g > 0 || rl > j) ? Ps[j][rl] : 0.0;
+          s2 += a * Ps[cc][rl];
+        }
+      }
+      red[qd][cc] = s2;
     }
     __syncthreads();
     if (tid < kBand) {
@@ -219,7 +241,25 @@ __global__ __launch_bounds__(256) void k_panel_coop(double* __restrict__ P, int6
           tid >= j ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
       if (g == 0) rowj[par * kBand + tid] = Ps[tid][j];  // P[j][tid]: row j < 256 is here
     }
-    grid.sync();
+    {
+      // grid barrier (see above)
+      const unsigned long long gen = gen0 + (unsigned long long)(j + 1);
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_store(flags + g, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid < G && !stalled) {
+        int spins = 0;
+        while (__hip_atomic_load(flags + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+          if (++spins > kPanelSpinMax) {
+            stalled = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     {
       // the same fixed order in every workgroup: four strided partial sums per column
       const int cc = tid & 63, qd = tid >> 6;
@@ -269,6 +309,7 @@ __global__ __launch_bounds__(256) void k_panel_coop(double* __restrict__ P, int6
 #pragma unroll 8
     for (int c = 0; c < kBand; ++c) P[(int64_t)c * lda + r] = Ps[c][tid];
   }
+  if (tid == 0 && stalled) atomicOr(err, 1);
 }
 
 // R (rows q < b of the panel, columns c >= q) from Rbuf into the panel's upper triangle.
@@ -895,6 +936,14 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
   double* U1a = U1;
   double* U2a = U1 + 2 * kDelay * n * b;
   int dp = 0;  // pending panels
+  // cooperative panel QR: barrier flags (cleared for this solve) and error flag
+  unsigned long long* pflags = nullptr;
+  int* perr = nullptr;
+  if (c->tiles.panel_coop) {
+    CHECK(ws_get(c, W_EIG_PFLAG, 257, &pflags));
+    perr = reinterpret_cast<int*>(pflags + 256);
+    HIP_TRY(c, hipMemsetAsync(pflags, 0, 257 * sizeof(unsigned long long), c->stream));
+  }
   for (int64_t p = 0; p < np; ++p) {
     const int64_t j = ts->pj[p], m = ts->pm[p], kk = m < b ? m : b;
     const int mi = (int)m;
@@ -912,8 +961,8 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
                                        1)));
     }
     bool coop_done = false;
-    if (m >= 2 * b && c->tiles.panel_coop) {
-      // the whole panel in one cooperative launch (see k_panel_coop)
+    if (m >= 2 * b && pflags && (m + 255) / 256 <= 256) {
+      // the whole panel in one cooperative launch (see k_panel_coop; one flag per workgroup)
       const int G = (int)((m + 255) / 256);
       double *part, *Rbuf;
       CHECK(ws_get(c, W_EIG_PANEL, (size_t)(2 * G * b + 2 * b + b * b), &part));
@@ -921,7 +970,8 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
       Rbuf = rowj + 2 * b;
       int64_t lda = n, mm = m;
       double* tp = tau1 + p * b;
-      void* args[] = {&P, &lda, &mm, &part, &rowj, (void*)&G, &Rbuf, &tp};
+      unsigned long long gen0 = (unsigned long long)p * (unsigned long long)b;
+      void* args[] = {&P, &lda, &mm, &part, &rowj, (void*)&G, &Rbuf, &tp, &pflags, &gen0, &perr};
       const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_panel_coop),
                                                       dim3((unsigned)G), dim3(256), args, 0,
                                                       c->stream);
@@ -1027,6 +1077,12 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
                                       2 * b * dp, 1)));
       dp = 0;
     }
+  }
+
+  if (perr) {
+    int stalled = 0;
+    CHECK(read_flag(c, perr, &stalled));
+    if (stalled) return fail(c, QSGW_ERR_SOLVER, "%s: panel QR barrier wait exceeded its bound", what);
   }
 
   // ---- stage 2: band -> tridiagonal ----

@@ -99,6 +99,7 @@ enum Slot {
   W_EIG_XP,      // two-stage eigensolver: split-K partials of X = S V T [nz][b][m]
   W_EIG_PANEL,   // two-stage eigensolver: panel QR partial dots (two buffers) and R  [2 G b + b b]
   W_EIG_Q1W,     // two-stage eigensolver: V^T X and T V^T X of a panel [2][b][ncols]
+  W_EIG_PFLAG,   // two-stage eigensolver: cooperative panel QR barrier flags [256] u64, error flag
   W_EIG_DCG,     // tridiagonal merge (projection): Q^T X and its sorted rows [2][n][naux]
   W_EIG_DCV,     // tridiagonal merge: poles, weights, roots, rotations [12 n + 8]
   W_EIG_DCI,     // tridiagonal merge: row maps, positions, counts (int64) [9 n + 4]
