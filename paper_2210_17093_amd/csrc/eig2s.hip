@@ -729,13 +729,14 @@ constexpr int kSlabPre = kSlabW * kRows / 256;  // slab elements per thread
 constexpr int64_t kQ2Wgs = 1024;  // workgroups a band back-transformation launch aims for
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 template <bool TRANS>
-__global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_t n, int64_t ncols,
-                                                  int b, const double* __restrict__ V2,
-                                                  const int64_t* __restrict__ off,
-                                                  const double* __restrict__ Tb,
-                                                  const int64_t* __restrict__ boff, int64_t t,
-                                                  int64_t nJ, int64_t J_lo, int64_t ngrp,
-                                                  int64_t spg) {
+__global__ __launch_bounds__(256, 2) void k_q2_apply(double* __restrict__ X, int64_t n,
+                                                     int64_t ncols, int b,
+                                                     const double* __restrict__ V2,
+                                                     const int64_t* __restrict__ off,
+                                                     const double* __restrict__ Tb,
+                                                     const int64_t* __restrict__ boff, int64_t t,
+                                                     int64_t nJ, int64_t J_lo, int64_t ngrp,
+                                                     int64_t spg) {
   const int64_t jj = blockIdx.x / ngrp, grp = blockIdx.x - jj * ngrp;
   const int64_t J = J_lo + jj;
   const int64_t k = t - (nJ - 1 - J);
@@ -749,21 +750,12 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
   const int64_t s1 = min(s0 + spg, nslab);
   if (s0 >= s1) return;
   __shared__ double Xb[kRows][kSlabW + 1];
-  __shared__ double Vb[kBand][kBand + 1];
-  __shared__ double Ts[kBand][kBand + 1];
   __shared__ double W[kBand][kSlabW + 1];
   const int tid = threadIdx.x;
   const int64_t R0 = c_lo + 1 + k * b;
   const int64_t R1 = min(c_hi + (k + 1) * b, n - 1);
   const int NR = (int)(R1 - R0 + 1);
   const double* Tg = Tb + (boff[J] + k) * (kBand * kBand);
-  for (int e = tid; e < kBand * kBand; e += 256) {
-    const int o = e / kBand, a = e - o * kBand;
-    const int64_t c = c_lo + o;
-    const bool ok = c <= c_hi && k < (n - 1 - c + b - 1) / b && a < b;
-    Vb[o][a] = ok ? V2[(off[c] + k) * b + a] : 0.0;
-    Ts[o][a] = Tg[e];
-  }
   // slab element i of this thread: column cl = (tid + 256 i) / kRows, row
   // r = tid % kRows (consecutive threads on consecutive rows); rows past the
   // block and columns past X load a clamped, valid element and are stored to
@@ -783,11 +775,26 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
   gload(s0 * kSlabW, ncol_of(s0));
   const int lane = tid & 63, w = tid >> 6;
   const int lm = lane & 15, lk = lane >> 4;
-  // V(r, o): reflector o covers block rows o .. o + b - 1
-  auto vat = [&](int r, int o) -> double {
+  // The block's V and T entries each lane's matrix-core operands need, kept in
+  // registers for all slabs (gathered once; LDS holds only the slab and W, so
+  // two workgroups share a compute unit).  V(r, o): entry a = r - o of
+  // reflector o (zero outside 0 <= a < b, or where the reflector is missing).
+  auto vget = [&](int r, int o) -> double {
     const int a = r - o;
-    return (a >= 0 && a < kBand) ? Vb[o][a] : 0.0;
+    const int64_t c = c_lo + o;
+    if (a < 0 || a >= kBand || c > c_hi || k >= (n - 1 - c + b - 1) / b) return 0.0;
+    return V2[(off[c] + k) * b + a];
   };
+  double v1[20], t2[kBand / 4], v3[kBand / 4][2];
+#pragma unroll
+  for (int u = 0; u < 20; ++u) v1[u] = vget(16 * w + 4 * u + lk, 16 * w + lm);
+#pragma unroll
+  for (int ks = 0; ks < kBand / 4; ++ks) {
+    const int i = 16 * w + lm, j = 4 * ks + lk;
+    t2[ks] = TRANS ? Tg[j * kBand + i] : Tg[i * kBand + j];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) v3[ks][u] = vget(16 * (2 * w + u) + lm, 4 * ks + lk);
+  }
   for (int64_t sl = s0; sl < s1; ++sl) {
     const int64_t col0 = sl * kSlabW;
     const int ncol = ncol_of(sl);
@@ -805,11 +812,10 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     // and the LDS reads run ahead of the matrix-core instructions)
     {
       f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-      const int o = 16 * w + lm;
 #pragma unroll
       for (int u = 0; u < 20; ++u) {
         const int r = 16 * w + 4 * u + lk;
-        const double av = vat(r, o);
+        const double av = v1[u];
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][lm], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xb[r][16 + lm], acc1, 0, 0, 0);
       }
@@ -823,11 +829,10 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
     // W2 = T W or T^T W (T upper triangular, stored with its zeros), back into W
     {
       f64x4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-      const int i = 16 * w + lm;
 #pragma unroll
       for (int ks = 0; ks < kBand / 4; ++ks) {
         const int j = 4 * ks + lk;
-        const double av = TRANS ? Ts[j][i] : Ts[i][j];
+        const double av = t2[ks];
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][lm], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W[j][16 + lm], acc1, 0, 0, 0);
       }
@@ -852,7 +857,7 @@ __global__ __launch_bounds__(256) void k_q2_apply(double* __restrict__ X, int64_
         const double b0 = W[o][lm], b1 = W[o][16 + lm];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const double av = vat(16 * (2 * w + u) + lm, o);
+          const double av = v3[ks][u];
           acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[u][0], 0, 0, 0);
           acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[u][1], 0, 0, 0);
         }
