@@ -498,16 +498,31 @@ struct BulgeSmem {
   double sc[4];
 };
 
+// First step of sweep i in the bulge-chasing reflector arrays: the number of
+// steps of the sweeps before it, sum over i' < i of ceil((n - 1 - i') / b),
+// in closed form from S(x) = sum_{j = 1..x} ceil(j / b) = b q (q + 1) / 2 + r (q + 1)
+// (x = q b + r), so a step needs no table lookup before its reflector loads.
+__host__ __device__ __forceinline__ int64_t sweep_first_step(int64_t n, int64_t b, int64_t i) {
+  auto S = [b](int64_t x) {
+    const int64_t q = x / b, r = x - q * b;
+    return b * q * (q + 1) / 2 + r * (q + 1);
+  };
+  return S(n - 1) - S(n - 1 - i);
+}
+
 // One bulge-chasing step (i, k), the whole workgroup (256 threads).
 // AB: lower band storage, AB[c * ldab + d] = A[c + d][c], ldab >= 2b.
-// V2/tau2: the reflector of step (i, k) at V2[(off[i] + k) * b], tau2[off[i] + k].
+// V2/tau2: the reflector of step (i, k) at V2[(f + k) * b], tau2[f + k] with f
+// the sweep's first step (sweep_first_step).
 // Both blocks (the bulge O in the band columns of the previous window, the
 // diagonal block D in the columns of this one) are loaded at once: they are
-// disjoint.  Global loads and stores run with consecutive threads on
-// consecutive rows of a band column.
+// disjoint.  D is kept as its lower triangle (D[a][c], a >= c; the upper
+// entries are read through the symmetry).  All global stores come after the
+// last workgroup barrier, so no barrier waits for them.  Global loads and
+// stores run with consecutive threads on consecutive rows of a band column.
 __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int b,
-                           double* __restrict__ V2, double* __restrict__ tau2,
-                           const int64_t* __restrict__ off, int64_t i, int64_t k, BulgeSmem& sm) {
+                           double* __restrict__ V2, double* __restrict__ tau2, int64_t i,
+                           int64_t k, BulgeSmem& sm) {
   double (*O)[kBand + 1] = sm.O;
   double (*D)[kBand + 1] = sm.D;
   double *v = sm.v, *vp = sm.vp, *y = sm.y, *z = sm.z, *x = sm.x, *sc = sm.sc;
@@ -517,6 +532,7 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   const int64_t r1 = min(i + (k + 1) * b, n - 1);
   const int L = (int)(r1 - r0 + 1);
   const int64_t p0 = i + 1 + (k - 1) * b;  // previous window (k >= 1; always b long)
+  const int64_t f = sweep_first_step(n, b, i);
 
   // ---- loads (all issued before any LDS store) ----
   constexpr int EPT = kBand * kBand / 256;  // elements per thread
@@ -529,6 +545,14 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
       dv[u] = (a >= c && a < L) ? AB[(r0 + c) * ldab + (a - c)] : 0.0;
       ov[u] = (k > 0 && a < L && c < b) ? AB[(p0 + c) * ldab + (b + a - c)] : 0.0;
     }
+    double xv = 0.0;
+    if (tid < kBand) {
+      if (k == 0)
+        xv = tid < L ? AB[i * ldab + 1 + tid] : 0.0;
+      else
+        xv = tid < b ? V2[(f + k - 1) * b + tid] : 0.0;
+    }
+    const double tp = (k > 0 && tid == 0) ? tau2[f + k - 1] : 0.0;
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = tid + 256 * u;
@@ -536,29 +560,15 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
       if (a >= c) D[a][c] = dv[u];
       O[a][c] = ov[u];
     }
-  }
-  if (k == 0) {
-    if (tid < kBand) x[tid] = tid < L ? AB[i * ldab + 1 + tid] : 0.0;
-  } else {
-    if (tid < kBand) vp[tid] = tid < b ? V2[(off[i] + k - 1) * b + tid] : 0.0;
-    if (tid == 0) sc[3] = tau2[off[i] + k - 1];
+    if (tid < kBand) {
+      if (k == 0)
+        x[tid] = xv;
+      else
+        vp[tid] = xv;
+    }
+    if (k > 0 && tid == 0) sc[3] = tp;
   }
   __syncthreads();
-  {
-    double mv[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = tid + 256 * u;
-      const int c = e / kBand, a = e - c * kBand;
-      mv[u] = a < c ? D[c][a] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = tid + 256 * u;
-      const int c = e / kBand, a = e - c * kBand;
-      if (a < c) D[a][c] = mv[u];
-    }
-  }
   if (k > 0) {
     // O <- O (I - taup vp vp^T); its first column is the vector to annihilate
     double s = 0.0;
@@ -581,32 +591,21 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
       O[a][c] = ov[u];
       if (c == 0) x[a] = ov[u];
     }
+    __syncthreads();
   }
-  __syncthreads();
   householder(x, L, v, sc);  // v, sc[0] = tau, sc[1] = beta
-  const double tau = sc[0];
-  if (k == 0) {
-    if (tid < L) AB[i * ldab + 1 + tid] = tid == 0 ? sc[1] : 0.0;
-  } else {
-    // first column -> beta e_1, the other columns <- H O; written back
+  const double tau = sc[0], beta = sc[1];
+  if (k > 0) {
+    // z = O^T v: the other columns of the bulge become H O = O - tau v z^T
     double s = 0.0;
     for (int a = q; a < kBand; a += 4) s += v[a] * O[a][rr];
     s = quad_sum(s);
     if (q == 0) z[rr] = s;
-    __syncthreads();
-    const double beta = sc[1];
-    for (int e = tid; e < kBand * kBand; e += 256) {
-      const int c = e / kBand, a = e - c * kBand;
-      if (a < L && c < b) {
-        const double val = c == 0 ? (a == 0 ? beta : 0.0) : O[a][c] - tau * v[a] * z[c];
-        AB[(p0 + c) * ldab + (b + a - c)] = val;
-      }
-    }
   }
-  // diagonal block D <- H D H
+  // diagonal block D <- H D H = D - v w^T - w v^T, w = y - 1/2 tau (y . v) v, y = tau D v
   {
     double s = 0.0;
-    for (int c = q; c < kBand; c += 4) s += D[rr][c] * v[c];
+    for (int c = q; c < kBand; c += 4) s += (c <= rr ? D[rr][c] : D[c][rr]) * v[c];
     s = quad_sum(s);
     if (q == 0) y[rr] = tau * s;
   }
@@ -617,6 +616,19 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   }
   __syncthreads();
   const double al = sc[2];
+  // ---- stores ----
+  if (k == 0) {
+    if (tid < L) AB[i * ldab + 1 + tid] = tid == 0 ? beta : 0.0;
+  } else {
+    // first column -> beta e_1, the other columns <- H O
+    for (int e = tid; e < kBand * kBand; e += 256) {
+      const int c = e / kBand, a = e - c * kBand;
+      if (a < L && c < b) {
+        const double val = c == 0 ? (a == 0 ? beta : 0.0) : O[a][c] - tau * v[a] * z[c];
+        AB[(p0 + c) * ldab + (b + a - c)] = val;
+      }
+    }
+  }
   for (int e = tid; e < kBand * kBand; e += 256) {
     const int c = e / kBand, a = e - c * kBand;
     if (a < L && c <= a) {
@@ -624,8 +636,8 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
       AB[(r0 + c) * ldab + (a - c)] = D[a][c] - v[a] * wc - wa * v[c];
     }
   }
-  if (tid < b) V2[(off[i] + k) * b + tid] = v[tid];
-  if (tid == 0) tau2[off[i] + k] = tau;
+  if (tid < b) V2[(f + k) * b + tid] = v[tid];
+  if (tid == 0) tau2[f + k] = tau;
 }
 
 // Bulge-chasing schedule: step k of sweep i runs at time kLag i + k.  Step
@@ -640,8 +652,7 @@ constexpr int64_t kLag = 2;
 // Step k = t - kLag i of every sweep i of time t, one workgroup each (one launch per time).
 __global__ __launch_bounds__(256) void k_bulge(double* __restrict__ AB, int64_t ldab, int64_t n,
                                                int b, double* __restrict__ V2,
-                                               double* __restrict__ tau2,
-                                               const int64_t* __restrict__ off, int64_t t,
+                                               double* __restrict__ tau2, int64_t t,
                                                int64_t i_lo) {
   const int64_t i = i_lo + blockIdx.x;
   const int64_t k = t - kLag * i;
@@ -649,7 +660,7 @@ __global__ __launch_bounds__(256) void k_bulge(double* __restrict__ AB, int64_t 
   const int64_t K = (n - 1 - i + b - 1) / b;
   if (k >= K) return;
   __shared__ BulgeSmem sm;
-  bulge_step(AB, ldab, n, b, V2, tau2, off, i, k, sm);
+  bulge_step(AB, ldab, n, b, V2, tau2, i, k, sm);
 }
 
 // Compact WY factor of block (J, k) of the bulge-chasing reflectors: with V
@@ -1095,6 +1106,8 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
   std::vector<int64_t> hoff((size_t)n, 0);
   int64_t nref = 0, tmax = 0;
   for (int64_t i = 0; i <= n - 3; ++i) {
+    if (sweep_first_step(n, b, i) != nref)
+      return fail(c, QSGW_ERR_SOLVER, "%s: bulge step offset of sweep %lld", what, (long long)i);
     hoff[(size_t)i] = nref;
     const int64_t K = (n - 1 - i + b - 1) / b;
     nref += K;
@@ -1132,7 +1145,7 @@ static int ts_reduce(qsgw_ctx* c, int64_t n, double* A, double* evals, const cha
     int64_t i_lo = t - K0 >= 0 ? (t - K0) / kLag + 1 : 0;  // kLag i > t - K0
     if (i_lo > i_hi) continue;
     hipLaunchKernelGGL(k_bulge, dim3((unsigned)(i_hi - i_lo + 1)), dim3(256), 0, c->stream, AB,
-                       ldab, n, b, V2, tau2, off, t, i_lo);
+                       ldab, n, b, V2, tau2, t, i_lo);
   }
   CHECK(launch_check(c, "k_bulge"));
   hipLaunchKernelGGL(k_tridiag, dim3(blocks_for(n)), dim3(256), 0, c->stream, AB, n, ldab, dd, ee);

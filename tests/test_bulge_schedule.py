@@ -60,3 +60,19 @@ def test_lag1_would_conflict():
             clash = clash or bool(seen & e)
             seen |= e
     assert clash
+
+
+@pytest.mark.parametrize("n,b", [(256, 64), (350, 64), (1001, 64), (10400, 64), (41600, 64), (97, 8)])
+def test_sweep_first_step_closed_form(n, b):
+    """The first reflector of sweep i sits after the steps of all earlier
+    sweeps, sum over i' < i of ceil((n - 1 - i') / b); the kernels compute it
+    as S(n - 1) - S(n - 1 - i) with S(x) = b q (q + 1) / 2 + r (q + 1) for
+    x = q b + r (the library also checks it against the running sum before
+    every bulge chase)."""
+    def S(x):
+        q, r = divmod(x, b)
+        return b * q * (q + 1) // 2 + r * (q + 1)
+    run = 0
+    for i in range(n - 2):
+        assert S(n - 1) - S(n - 1 - i) == run
+        run += -(-(n - 1 - i) // b)
