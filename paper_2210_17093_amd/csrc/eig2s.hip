@@ -572,7 +572,8 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   if (k > 0) {
     // O <- O (I - taup vp vp^T); its first column is the vector to annihilate
     double s = 0.0;
-    for (int c = q; c < kBand; c += 4) s += O[rr][c] * vp[c];
+#pragma unroll
+    for (int u = 0; u < kBand / 4; ++u) s += O[rr][q + 4 * u] * vp[q + 4 * u];
     s = quad_sum(s);
     if (q == 0) y[rr] = s;
     __syncthreads();
@@ -598,14 +599,19 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   if (k > 0) {
     // z = O^T v: the other columns of the bulge become H O = O - tau v z^T
     double s = 0.0;
-    for (int a = q; a < kBand; a += 4) s += v[a] * O[a][rr];
+#pragma unroll
+    for (int u = 0; u < kBand / 4; ++u) s += v[q + 4 * u] * O[q + 4 * u][rr];
     s = quad_sum(s);
     if (q == 0) z[rr] = s;
   }
   // diagonal block D <- H D H = D - v w^T - w v^T, w = y - 1/2 tau (y . v) v, y = tau D v
   {
     double s = 0.0;
-    for (int c = q; c < kBand; c += 4) s += (c <= rr ? D[rr][c] : D[c][rr]) * v[c];
+#pragma unroll
+    for (int u = 0; u < kBand / 4; ++u) {
+      const int c = q + 4 * u;
+      s += (c <= rr ? D[rr][c] : D[c][rr]) * v[c];
+    }
     s = quad_sum(s);
     if (q == 0) y[rr] = tau * s;
   }
@@ -620,20 +626,35 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   if (k == 0) {
     if (tid < L) AB[i * ldab + 1 + tid] = tid == 0 ? beta : 0.0;
   } else {
-    // first column -> beta e_1, the other columns <- H O
-    for (int e = tid; e < kBand * kBand; e += 256) {
+    // first column -> beta e_1, the other columns <- H O (all values first, then the stores)
+    double ov[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
       const int c = e / kBand, a = e - c * kBand;
-      if (a < L && c < b) {
-        const double val = c == 0 ? (a == 0 ? beta : 0.0) : O[a][c] - tau * v[a] * z[c];
-        AB[(p0 + c) * ldab + (b + a - c)] = val;
-      }
+      ov[u] = c == 0 ? (a == 0 ? beta : 0.0) : O[a][c] - tau * v[a] * z[c];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
+      if (a < L && c < b) AB[(p0 + c) * ldab + (b + a - c)] = ov[u];
     }
   }
-  for (int e = tid; e < kBand * kBand; e += 256) {
-    const int c = e / kBand, a = e - c * kBand;
-    if (a < L && c <= a) {
+  {
+    double dv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
       const double wa = y[a] + al * v[a], wc = y[c] + al * v[c];
-      AB[(r0 + c) * ldab + (a - c)] = D[a][c] - v[a] * wc - wa * v[c];
+      dv[u] = c <= a ? D[a][c] - v[a] * wc - wa * v[c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / kBand, a = e - c * kBand;
+      if (a < L && c <= a) AB[(r0 + c) * ldab + (a - c)] = dv[u];
     }
   }
   if (tid < b) V2[(f + k) * b + tid] = v[tid];
