@@ -494,8 +494,8 @@ __device__ void householder(const double* x, int L, double* v, double* sc) {
 struct BulgeSmem {
   double O[kBand][kBand + 1];
   double D[kBand][kBand + 1];
-  double v[kBand], vp[kBand], y[kBand], z[kBand], x[kBand];
-  double sc[4];
+  double v[kBand], vp[kBand], y[kBand], z[kBand], x[kBand], yo[kBand];
+  double sc[5];
 };
 
 // First step of sweep i in the bulge-chasing reflector arrays: the number of
@@ -525,7 +525,7 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
                            int64_t k, BulgeSmem& sm) {
   double (*O)[kBand + 1] = sm.O;
   double (*D)[kBand + 1] = sm.D;
-  double *v = sm.v, *vp = sm.vp, *y = sm.y, *z = sm.z, *x = sm.x, *sc = sm.sc;
+  double *v = sm.v, *vp = sm.vp, *y = sm.y, *z = sm.z, *x = sm.x, *yo = sm.yo, *sc = sm.sc;
   const int tid = threadIdx.x;
   const int q = tid & 3, rr = tid >> 2;  // 4 lanes per row (or column) rr
   const int64_t r0 = i + 1 + k * b;
@@ -569,35 +569,23 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
     if (k > 0 && tid == 0) sc[3] = tp;
   }
   __syncthreads();
+  const double taup = k > 0 ? sc[3] : 0.0;
   if (k > 0) {
-    // O <- O (I - taup vp vp^T); its first column is the vector to annihilate
+    // O' = O (I - taup vp vp^T) = O - taup yo vp^T (yo = O vp) is never formed: its first
+    // column is the vector to annihilate, and the stores below apply both reflectors
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < kBand / 4; ++u) s += O[rr][q + 4 * u] * vp[q + 4 * u];
     s = quad_sum(s);
-    if (q == 0) y[rr] = s;
+    if (q == 0) yo[rr] = s;
     __syncthreads();
-    const double taup = sc[3];
-    double ov[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = tid + 256 * u;
-      const int a = e / kBand, c = e - a * kBand;
-      ov[u] = O[a][c] - taup * y[a] * vp[c];
-    }
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = tid + 256 * u;
-      const int a = e / kBand, c = e - a * kBand;
-      O[a][c] = ov[u];
-      if (c == 0) x[a] = ov[u];
-    }
-    __syncthreads();
+    // (wave 0 writes x and reduces it in householder: no barrier in between)
+    if (tid < kBand) x[tid] = O[tid][0] - taup * yo[tid] * vp[0];
   }
   householder(x, L, v, sc);  // v, sc[0] = tau, sc[1] = beta
   const double tau = sc[0], beta = sc[1];
   if (k > 0) {
-    // z = O^T v: the other columns of the bulge become H O = O - tau v z^T
+    // O^T v; the bulge becomes H O' = O' - tau v z^T with z = O'^T v = O^T v - taup vp (yo . v)
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < kBand / 4; ++u) s += v[q + 4 * u] * O[q + 4 * u][rr];
@@ -618,10 +606,14 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
   __syncthreads();
   if (tid < 64) {
     const double wv = wave_sum(y[tid] * v[tid]);
-    if (tid == 0) sc[2] = -0.5 * tau * wv;
+    const double yv = k > 0 ? wave_sum(yo[tid] * v[tid]) : 0.0;
+    if (tid == 0) {
+      sc[2] = -0.5 * tau * wv;
+      sc[4] = yv;
+    }
   }
   __syncthreads();
-  const double al = sc[2];
+  const double al = sc[2], yov = sc[4];
   // ---- stores ----
   if (k == 0) {
     if (tid < L) AB[i * ldab + 1 + tid] = tid == 0 ? beta : 0.0;
@@ -632,7 +624,8 @@ __device__ void bulge_step(double* __restrict__ AB, int64_t ldab, int64_t n, int
     for (int u = 0; u < EPT; ++u) {
       const int e = tid + 256 * u;
       const int c = e / kBand, a = e - c * kBand;
-      ov[u] = c == 0 ? (a == 0 ? beta : 0.0) : O[a][c] - tau * v[a] * z[c];
+      const double op = O[a][c] - taup * yo[a] * vp[c];  // O'
+      ov[u] = c == 0 ? (a == 0 ? beta : 0.0) : op - tau * v[a] * (z[c] - taup * vp[c] * yov);
     }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
