@@ -1373,6 +1373,14 @@ int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a,
   CHECK(ws_get(c, W_RHO, (size_t)(naux * sb), &rho));
   CHECK(ws_get(c, W_W, (size_t)(nn * sb), &w));
   CHECK(ws_get(c, W_WH, (size_t)(nn * sb), &wh));
+  // with the two-stage solver the eigensolve hands rho' of every excitation
+  // (projection of the spin-stacked Bt, the eigenvectors never formed)
+  const bool fold = eig_two_stage_for(c, ntr);
+  double *PX = nullptr, *rhoF = nullptr;
+  if (fold) {
+    CHECK(ws_get(c, W_EIG_PX, (size_t)(naux * ntr), &PX));
+    CHECK(ws_get(c, W_RHOFULL, (size_t)(naux * ntr), &rhoF));
+  }
   Spans spn;
   spn.c = c;
   HIP_TRY(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
@@ -1399,16 +1407,20 @@ int qsgw_gw_unrestricted(qsgw_ctx* c, int64_t nbf, int64_t naux, int64_t nocc_a,
   }
   CHECK(spn.close());
   CHECK(spn.open(kStageEigRpa));
-  CHECK(stage_rpa_solve(c, ntr, M, Omega));
+  if (fold)
+    CHECK(stage_rpa_solve_project(c, ntr, naux, M, Omega, Bt, PX, rhoF));
+  else
+    CHECK(stage_rpa_solve(c, ntr, M, Omega));
   CHECK(spn.close());
   for (int64_t s0 = 0; s0 < ntr; s0 += sb) {
     const int64_t ns = ntr - s0 < sb ? ntr - s0 : sb;
     for (int sp = 0; sp < 2; ++sp) {
-      // rho' of the block is shared by both spins
+      // rho' of the block is shared by both spins (from the projection, or made by the first)
       CHECK(spn.open(kStageRes));
-      CHECK(stage_residues(c, nbf, naux, ntr, Bs[sp], Bt, M, Omega, s0, ns, rho, w, nullptr, wh,
-                           es[sp], no[sp], eta, QSGW_PREC_FP64, nullptr, nullptr, 0.0, nullptr,
-                           nullptr, false, nullptr, sp > 0));
+      CHECK(stage_residues(c, nbf, naux, ntr, Bs[sp], Bt, M, Omega, s0, ns,
+                           fold ? rhoF + s0 : rho, w, nullptr, wh, es[sp], no[sp], eta,
+                           QSGW_PREC_FP64, nullptr, nullptr, 0.0, nullptr, nullptr, false, nullptr,
+                           fold || sp > 0, fold ? ntr : 0));
       CHECK(spn.close());
       CHECK(spn.open(kStageSigma));
       CHECK(stage_sigma_qs(c, nbf, no[sp], ns, w, es[sp], Omega + s0, eta, Vs[sp],

@@ -216,3 +216,22 @@ def test_unrestricted_iterations_match_oracle(q, ctx, nbf, naux, na, nb):
     with pytest.raises(q.QsgwError) as x:
         q.qsgw_iterate_unrestricted(ctx, Bd, hd, na, nbf, ea4, Ca4, eb4, Cb4, eta)
     assert x.value.code == q.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("nbf,naux,na,nb", [(24, 96, 5, 4), (70, 150, 11, 10)])
+def test_unrestricted_two_stage_projection_matches_oracle(q, nbf, naux, na, nb):
+    """With the two-stage solver the open-shell step takes rho' of every
+    excitation from the eigensolver's projection of the spin-stacked Bt (the
+    eigenvectors never formed; at 20,579 transitions this is the default):
+    V of both spins and Omega against the oracle as above."""
+    print(f"[uhf two-stage] nbf={nbf} naux={naux} nocc=({na}, {nb})", flush=True)
+    B_s, e_s, n_s = two_spins(nbf, naux, na, nb, nbf)
+    V_ref, Om_ref = O.gw_unrestricted(B_s, e_s, n_s, 0.05)
+    with q.Context() as c:
+        c.set_eigensolver(q.EIG_TWO_STAGE)
+        Va, Vb, Om = q.qsgw_gw_unrestricted(c, dev(B_s[0]), dev(B_s[1]), dev(e_s[0]), dev(e_s[1]),
+                                            na, nb, 0.05)
+        np.testing.assert_allclose(host(Om), Om_ref, rtol=1e-11)
+        for V, R in ((host(Va), V_ref[0]), (host(Vb), V_ref[1])):
+            np.testing.assert_array_equal(V, V.T)
+            assert np.abs(V - R).max() <= 1e-10 * np.abs(R).max() + 1e-15
