@@ -68,8 +68,9 @@ extern "C" {
    BF16 matrix cores with FP32 accumulation (relative error about 2^-16 per
    product term), FP64 across K chunks.  It applies to the Casida build, the
    residue products and the far-from-pole part of the qsGW matrix; the MO
-   transform runs on the FP32 matrix cores.  Not available in
-   qsgw_iterate_batched (QSGW_ERR_UNSUPPORTED). */
+   transform runs on the FP32 matrix cores.  In qsgw_iterate_batched it
+   covers the Casida, rho' and residue products (the qsGW product stays FP64
+   there). */
 #define QSGW_PREC_SPLIT_BF16 2
 
 /* qsgw_sigma modes. */
@@ -139,8 +140,9 @@ int qsgw_rpa_build(qsgw_ctx* ctx, int64_t nbf, int64_t naux, int64_t nocc, const
  * tridiagonal by bulge chasing, rocSOLVER divide and conquer (dstedc) on the
  * tridiagonal matrix, then both back-transformations (the bulge-chasing
  * reflectors in blocks of 64 sweeps, the panel reflectors as block
- * reflectors).  Inside qsgw_iterate only the projection of the auxiliary
- * basis on the eigenvectors is needed: the back-transformations act on its
+ * reflectors).  Inside qsgw_iterate and qsgw_gw_unrestricted (and so the
+ * open-shell iteration) only the projection of the auxiliary basis on the
+ * eigenvectors is needed: the back-transformations act on its
  * N_aux columns and the tridiagonal eigenproblem is solved by divide and
  * conquer whose merges act on those columns too (blocks up to the tile
  * table's dc_leaf by dstedc), so no eigenvector matrix is formed.  Below
