@@ -142,14 +142,17 @@ __global__ void k_dc_child_inputs(const double* __restrict__ X, int64_t ldx, int
     Xr[P * n2 + (r - n1)] = P < q ? X[P * ldx + r] : (r == n1 ? 1.0 : 0.0);
 }
 
-// Deflation, one workgroup.  z is normalised in place, rho = |beta| |z|^2 and
-// tol go to scal[1], scal[2]; then thread 0 walks the poles in order (staged
-// through LDS in chunks) and emits the non-deflated poles (nd, dk, zk), the
-// deflated ones (df, dfv) and the rotations (ra, rb, rc, rs) in the order
-// they are to be applied.  cnt = {K, deflated, rotations}.
+// Deflation, one workgroup.  rho = |beta| |z|^2 and tol go to scal[1],
+// scal[2]; then thread 0 walks the poles in order (staged through LDS in
+// chunks, z normalised on the way) and emits the non-deflated poles (nd, dk,
+// zk), the deflated ones (df, dfv) and the rotations (ra, rb, rc, rs) in the
+// order they are to be applied.  cnt = {K, deflated, rotations}.  The
+// non-deflated poles come out strictly increasing, every gap above 16 eps
+// max |d| (a smaller one passes the rotation test and deflates), which the
+// secular brackets rely on.
 constexpr int kDcChunk = 2048;
 __global__ __launch_bounds__(256) void k_dc_deflate(const double* __restrict__ ds,
-                                                    double* __restrict__ zs, int64_t n,
+                                                    const double* __restrict__ zs, int64_t n,
                                                     double* __restrict__ scal,
                                                     int64_t* __restrict__ nd,
                                                     double* __restrict__ dk,
