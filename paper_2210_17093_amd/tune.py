@@ -142,10 +142,15 @@ def batched_timer(name):
     return ctx, run
 
 
-def tune(name, reps=3):
+def tune(name, reps=3, timer=None):
+    """Coordinate search over CANDIDATES from DEFAULTS for workload `name`
+    ("cfg3", "cfg3:fp32", ...).  timer: None (time on the device), or a pair
+    (ctx, run) with run(spec) -> (kernel_ms dict, energies) and ctx.close()."""
     base, _, variant = name.partition(":")
     prec = {"fp32": q.PREC_FP32, "bf16x3": q.PREC_SPLIT_BF16}.get(variant, q.PREC_FP64)
-    ctx, run = batched_timer(base) if base == "cfg4" else single_timer(base, prec)
+    if timer is None:
+        timer = batched_timer(base) if base == "cfg4" else single_timer(base, prec)
+    ctx, run = timer
     best = dict(DEFAULTS)
     _, eps_ref = run(spec_of(best))  # warm-up, and the default table's energies
     # a tile table changes only the rounding order of the products
